@@ -1,0 +1,146 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+The paper evaluates on real embedding datasets (its Table 2) that are not
+available here; these generators stand in for them with Gaussian mixtures of
+the sizes and dimensions the workloads use.  This module holds only input
+generation (random numbers, mixture sampling, normalisation of generated
+points, request-stream shapes); it contains none of the search or update
+arithmetic, so both the HIP path and the CPU oracle may take their inputs
+from it.
+
+Every stream is a numpy ``Philox`` counter-based generator keyed by
+``1000 * workload + role`` with roles::
+
+    0 component means   1 base vectors   2 queries   3 request stream
+    4 training queries  5 clustering
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+ROLE_MEANS, ROLE_BASE, ROLE_QUERIES, ROLE_STREAM, ROLE_TRAIN, ROLE_CLUSTER = range(6)
+
+
+def rng(workload: int, role: int) -> np.random.Generator:
+    return np.random.Generator(np.random.Philox(key=1000 * workload + role))
+
+
+def _chunked_mixture(g, means, n, sigma, comp_p=None, chunk=1 << 18):
+    """Draw n points m_c + sigma * N(0, I); component c uniform (or comp_p)."""
+    k, d = means.shape
+    out = np.empty((n, d), dtype=np.float32)
+    comps = np.empty(n, dtype=np.int32)
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        if comp_p is None:
+            c = g.integers(0, k, size=e - s)
+        else:
+            c = g.choice(k, size=e - s, p=comp_p)
+        x = means[c] + sigma * g.standard_normal((e - s, d))
+        out[s:e] = x.astype(np.float32)
+        comps[s:e] = c
+    return out, comps
+
+
+def zipf_weights(k: int, s: float, perm_rng: np.random.Generator) -> np.ndarray:
+    """Zipf(s) probabilities over k components, ranked by a seeded permutation."""
+    w = 1.0 / np.arange(1, k + 1, dtype=np.float64) ** s
+    w /= w.sum()
+    p = np.empty(k)
+    p[perm_rng.permutation(k)] = w
+    return p
+
+
+# ----------------------------------------------------------------------------
+# Workload 1: 16-component mixture, dim 128, float values, L2.
+# ----------------------------------------------------------------------------
+def gmm_float(workload: int, n_base: int, n_query: int, dim: int, n_comp: int,
+              mean_std: float = 2.0, sigma: float = 1.0, normalise: bool = False,
+              query_zipf: float | None = None):
+    """Means ~ N(0, mean_std^2 I); points m_c + sigma N(0, I); optional unit norm."""
+    means = rng(workload, ROLE_MEANS).standard_normal((n_comp, dim)) * mean_std
+    base, _ = _chunked_mixture(rng(workload, ROLE_BASE), means, n_base, sigma)
+    qp = None
+    if query_zipf is not None:
+        qp = zipf_weights(n_comp, query_zipf, rng(workload, ROLE_CLUSTER))
+    queries, _ = _chunked_mixture(rng(workload, ROLE_QUERIES), means, n_query, sigma, qp)
+    if normalise:
+        base /= np.linalg.norm(base, axis=1, keepdims=True).astype(np.float32)
+        queries /= np.linalg.norm(queries, axis=1, keepdims=True).astype(np.float32)
+    return np.ascontiguousarray(base), np.ascontiguousarray(queries)
+
+
+def gmm_uint8_valued(workload: int, n_base: int, n_query: int, dim: int, n_comp: int,
+                     mean_mu: float = 128.0, mean_std: float = 32.0, sigma: float = 16.0):
+    """Integer-valued mixture: means ~ N(128, 32^2) per dim, sigma 16, rint, clip [0,255].
+
+    Stored as float32; every value is an integer in 0..255.
+    """
+    means = mean_mu + mean_std * rng(workload, ROLE_MEANS).standard_normal((n_comp, dim))
+    base, _ = _chunked_mixture(rng(workload, ROLE_BASE), means, n_base, sigma)
+    queries, _ = _chunked_mixture(rng(workload, ROLE_QUERIES), means, n_query, sigma)
+    for a in (base, queries):
+        np.rint(a, out=a)
+        np.clip(a, 0, 255, out=a)
+    return np.ascontiguousarray(base), np.ascontiguousarray(queries)
+
+
+def training_queries_uint8(workload: int, n: int, dim: int, n_comp: int,
+                           mean_mu: float = 128.0, mean_std: float = 32.0, sigma: float = 16.0):
+    means = mean_mu + mean_std * rng(workload, ROLE_MEANS).standard_normal((n_comp, dim))
+    q, _ = _chunked_mixture(rng(workload, ROLE_TRAIN), means, n, sigma)
+    np.rint(q, out=q)
+    np.clip(q, 0, 255, out=q)
+    return np.ascontiguousarray(q)
+
+
+# Named workloads ----------------------------------------------------------------
+def workload_small_float(n_base=10_000, n_query=100):
+    """10k x 128 float mixture (16 comps), 100 queries, L2, degree 32, k 10, beam 64."""
+    return gmm_float(1, n_base, n_query, 128, 16)
+
+
+def workload_1m_int(n_base=1_000_000, n_query=10_000):
+    """1M x 128 integer-valued mixture (256 comps), 10k queries, L2, degree 64."""
+    return gmm_uint8_valued(2, n_base, n_query, 128, 256)
+
+
+def workload_stream_ip(n_base, n_query, query_zipf=1.1):
+    """Unit-norm 96-d mixture (1024 comps) for the inner-product streaming mix."""
+    return gmm_float(3, n_base, n_query, 96, 1024, normalise=True, query_zipf=query_zipf)
+
+
+@dataclass
+class Request:
+    kind: str          # "search" | "insert" | "delete"
+    size: int
+    arrival_s: float
+
+
+def request_stream(n_rounds: int, insert_batch: int, delete_batch: int,
+                   queries_per_round: int, max_query: int, rate_hz: float,
+                   workload: int = 3):
+    """Open-loop request stream: per round one insert, one delete and
+    ``queries_per_round`` query batches with log-uniform sizes in [1, max_query],
+    Poisson arrivals at ``rate_hz`` requests per second."""
+    g = rng(workload, ROLE_STREAM)
+    reqs = []
+    t = 0.0
+    for _ in range(n_rounds):
+        kinds = ["insert", "delete"] + ["search"] * queries_per_round
+        order = g.permutation(len(kinds))
+        for i in order:
+            t += g.exponential(1.0 / rate_hz)
+            kind = kinds[i]
+            if kind == "insert":
+                size = insert_batch
+            elif kind == "delete":
+                size = delete_batch
+            else:
+                size = int(math.floor(math.exp(g.uniform(0.0, math.log(max_query)))))
+                size = max(1, min(max_query, size))
+            reqs.append(Request(kind, size, t))
+    return reqs

@@ -1,0 +1,332 @@
+"""The CPU oracle pinned against things other than itself: published test
+vectors, library routines, brute force, hand-worked examples and
+invariants of the method.  No GPU needed."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2601_08528_amd import datagen
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def load(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+def inf_list(xs):
+    return [math.inf if x == "inf" else x for x in xs]
+
+
+# --- published generator definitions ------------------------------------------
+def test_fnv1a64_published_vectors():
+    # FNV-1a 64-bit reference values (Fowler/Noll/Vo test suite)
+    assert O.fnv1a64(b"") == 0xCBF29CE484222325
+    assert O.fnv1a64(b"a") == 0xAF63DC4C8601EC8C
+    assert O.fnv1a64(b"foobar") == 0x85944171F73967E8
+
+
+def test_splitmix64_published_vectors():
+    # SplitMix64 seeded with 1234567: the first outputs of the reference generator
+    got = [O.splitmix64(1234567, j) for j in range(5)]
+    assert got == [6457827717110365317, 3203168211198807973, 9817491932198370423,
+                   4593380528125082431, 16408922859458223821]
+
+
+# --- reduced-precision grids vs library conversions ---------------------------
+def test_fp16_rounding_matches_numpy():
+    g = np.random.Generator(np.random.Philox(11))
+    xs = np.concatenate([g.standard_normal(2000) * 10.0 ** g.integers(-6, 5, 2000),
+                         np.arange(-300, 300, 0.37), [2 ** -24, 3 * 2 ** -25, 65504.0, 1 + 2 ** -11,
+                                                      1 + 3 * 2 ** -11]]).astype(np.float32)
+    ref = xs.astype(np.float16).astype(np.float64)
+    got = np.array([O.round_fp16(float(x)) for x in xs])
+    np.testing.assert_array_equal(got, ref)
+
+
+def test_bf16_rounding_matches_torch():
+    torch = pytest.importorskip("torch")
+    g = np.random.Generator(np.random.Philox(12))
+    xs = np.concatenate([g.standard_normal(2000) * 10.0 ** g.integers(-30, 30, 2000),
+                         [1 + 2 ** -8, 1 + 3 * 2 ** -8, 255.0, 257.0]]).astype(np.float32)
+    ref = torch.from_numpy(xs).to(torch.bfloat16).to(torch.float64).numpy()
+    got = np.array([O.round_bf16(float(x)) for x in xs])
+    np.testing.assert_array_equal(got, ref)
+
+
+# --- exact kNN ------------------------------------------------------------------
+@pytest.mark.parametrize("metric", [O.L2, O.IP])
+def test_bruteforce_matches_numpy_lexsort(metric):
+    base, q = datagen.gmm_uint8_valued(91, 500, 20, 16, 4)  # integer data: exact ties occur
+    ids, d = O.bruteforce(base, q, 10, metric=metric)
+    b64, q64 = base.astype(np.float64), q.astype(np.float64)
+    if metric == O.L2:
+        full = ((q64[:, None, :] - b64[None]) ** 2).sum(-1)
+    else:
+        full = -(q64 @ b64.T)
+    for i in range(q.shape[0]):
+        order = np.lexsort((np.arange(base.shape[0]), full[i]))[:10]
+        np.testing.assert_array_equal(ids[i], order)
+        np.testing.assert_array_equal(d[i], full[i][order])
+
+
+def test_bruteforce_respects_alive_and_pads():
+    base, q = datagen.gmm_float(92, 30, 3, 8, 2)
+    alive = np.zeros(30, np.uint8)
+    alive[[3, 7, 11]] = 1
+    ids, d = O.bruteforce(base, q, 5, alive=alive)
+    assert set(ids[:, :3].ravel()) <= {3, 7, 11}
+    assert (ids[:, 3:] == -1).all() and np.isinf(d[:, 3:]).all()
+
+
+# --- search ---------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def small_index():
+    base, q = datagen.gmm_float(93, 300, 25, 16, 4)
+    ix = O.OracleIndex(16, 8, O.L2, seed=5)
+    ix.build(base, batch_max=64)
+    return ix, base, q
+
+
+def test_full_width_pool_equals_bruteforce(small_index):
+    """Pool as wide as the data and entries covering every id: exact kNN."""
+    ix, base, q = small_index
+    ix.set("entry_samples", 4096)
+    try:
+        ids, d, _ = ix.search(q, 10, 300)
+    finally:
+        ix.set("entry_samples", 0)
+    gi, gd = O.bruteforce(base, q, 10)
+    np.testing.assert_array_equal(ids, gi)
+    np.testing.assert_array_equal(d, gd)
+
+
+def _reachable_all(rows, alive):
+    n = rows.shape[0]
+    for s in range(0, n, max(1, n // 7)):
+        seen = np.zeros(n, bool)
+        seen[s] = True
+        stack = [s]
+        while stack:
+            u = stack.pop()
+            for v in rows[u]:
+                if v >= 0 and alive[v] and not seen[v]:
+                    seen[v] = True
+                    stack.append(v)
+        if not seen[alive.astype(bool)].all():
+            return False
+    return True
+
+
+def test_pool_of_n_on_connected_graph_equals_bruteforce(small_index):
+    """Hashed entries, pool = n, strongly connected graph: exhaustive traversal."""
+    ix, base, q = small_index
+    rows, _, alive = ix.export()
+    assert _reachable_all(rows, alive)
+    ids, d, st = ix.search(q, 10, 300)
+    gi, gd = O.bruteforce(base, q, 10)
+    np.testing.assert_array_equal(ids, gi)
+    assert (st["n_exp"] == 300).all()
+
+
+def test_search_thread_and_batch_invariance(small_index):
+    ix, base, q = small_index
+    a = ix.search(q, 10, 32, threads=1)
+    b = ix.search(q, 10, 32, threads=4)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+    for i in (0, 7, 24):
+        c = ix.search(q[i:i + 1], 10, 32)
+        np.testing.assert_array_equal(c[0][0], a[0][i])
+
+
+def test_search_counters_and_iteration_cap(small_index):
+    ix, base, q = small_index
+    ids, d, st = ix.search(q, 5, 16)
+    assert (st["n_exp"] == st["iters"]).all()          # one parent per iteration
+    assert (st["n_dist"] >= 16).all()
+    assert (np.diff(d, axis=1) >= 0).all()             # ascending
+    ix.set("max_iters", 3)
+    try:
+        _, _, st3 = ix.search(q, 5, 16)
+    finally:
+        ix.set("max_iters", 0)
+    assert (st3["iters"] <= 3).all()
+
+
+def test_recall_small_float_workload():
+    """Tie-aware recall@10 >= 0.95 at beam 64 on the 10k x 128 mixture."""
+    base, q = datagen.workload_small_float()
+    ix = O.OracleIndex(128, 32, O.L2, seed=1)
+    ix.build(base)
+    ids, d, st = ix.search(q, 10, 64, threads=4)
+    gi, gd = O.bruteforce(base, q, 10, threads=4)
+    assert O.recall_at_k(ids, ix.query_dists(q, ids), gd, 10) >= 0.95
+    rows, ed, alive = ix.export()
+    assert ((rows >= 0).sum(1) == 32).all()
+
+
+# --- build and graph invariants ---------------------------------------------------
+def test_seed_graph_is_exact_rnn():
+    """With only the seed (n = 4R), every row is the exact R-nearest list."""
+    R = 6
+    base, _ = datagen.gmm_float(94, 4 * R, 1, 12, 3)
+    ix = O.OracleIndex(12, R, O.L2, seed=2)
+    ix.build(base)
+    rows, ed, alive = ix.export()
+    for v in range(4 * R):
+        mask = np.ones(4 * R, np.uint8)
+        mask[v] = 0
+        gi, gd = O.bruteforce(base, base[v:v + 1], R, alive=mask)
+        np.testing.assert_array_equal(rows[v], gi[0])
+        np.testing.assert_array_equal(ed[v], gd[0])
+
+
+def check_invariants(ix, base, exact_degree=True):
+    rows, ed, alive = ix.export()
+    n_alive = int(alive.sum())
+    for v in np.nonzero(alive)[0]:
+        r = rows[v][rows[v] >= 0]
+        assert len(set(r.tolist())) == len(r)
+        assert v not in r
+        assert (r < ix.n_slots).all()
+        if exact_degree:
+            assert len(r) == min(ix.R, n_alive - 1)
+        dd = ed[v][: len(r)]
+        key = list(zip(dd.tolist(), r.tolist()))
+        assert key == sorted(key)                     # canonical (d,id) order
+        for u, du in zip(r, dd):
+            assert du == ix.dist_ids(v, u)            # stored distance is the exact one
+    return rows, ed, alive
+
+
+def test_build_invariants_integer_data():
+    base, _ = datagen.gmm_uint8_valued(95, 800, 1, 16, 8)
+    ix = O.OracleIndex(16, 10, O.L2, seed=3)
+    ix.build(base, batch_max=100)
+    check_invariants(ix, base)
+
+
+# --- hand-worked prune / insert / repair ------------------------------------------
+@pytest.mark.parametrize("case", load("prune_examples.json")["cases"], ids=lambda c: c["name"])
+def test_prune_hand_worked(case):
+    R = case["R"]
+    n = 1 + max([int(k) for k in case["rows"]] + case["cand_ids"])
+    tab = -np.ones((n, R), np.int32)
+    for k, r in case["rows"].items():
+        tab[int(k)] = r
+    oi, od = O.prune_explicit(R, case["cand_ids"], case["cand_d"], tab)
+    assert oi.tolist() == case["out_ids"]
+    assert od.tolist() == inf_list(case["out_d"])
+
+
+def _import(g):
+    ix = O.OracleIndex(g["dim"], g["R"], g["metric"], seed=g["seed"])
+    for key in ("beam_insert", "repair_c", "consolidate_frac"):
+        if key in g:
+            ix.set(key, g[key])
+    pts = np.array(g["points"], np.float32).reshape(-1, g["dim"])
+    ix.import_state(pts, np.array(g["rows"]), np.array(g["edge_d"]), np.ones(len(pts), np.uint8))
+    return ix
+
+
+def test_insert_hand_worked():
+    g = load("insert_example.json")
+    ix = _import(g)
+    ids = ix.insert(np.array(g["insert"], np.float32).reshape(-1, g["dim"]))
+    assert ids.tolist() == [4]
+    rows, ed, alive = ix.export()
+    assert rows.tolist() == g["expect_rows"]
+    assert ed.tolist() == g["expect_edge_d"]
+    assert alive.tolist() == [1] * 5
+
+
+def test_insert_after_delete_hand_worked():
+    g = load("insert_after_delete_example.json")
+    ix = _import(g)
+    assert ix.delete(g["delete"]) == 0
+    ix.insert(np.array(g["insert"], np.float32).reshape(-1, g["dim"]))
+    rows, ed, alive = ix.export()
+    assert rows.tolist() == g["expect_rows"]
+    assert ed.tolist() == g["expect_edge_d"]
+    assert alive.tolist() == [0, 1, 1, 1, 1]
+
+
+def test_repair_and_consolidate_hand_worked():
+    g = load("repair_example.json")
+    ix = _import(g)
+    assert ix.delete(g["delete"]) == 0
+    rows, ed, alive = ix.export()
+    assert rows.tolist() == g["expect_after_delete"]
+    assert ed.tolist() == g["expect_after_delete_d"]
+    assert alive.tolist() == [1, 0, 0, 1, 1, 1]
+    ix.consolidate()
+    rows, ed, _ = ix.export()
+    v, row = g["expect_after_consolidate"]
+    assert rows[v].tolist() == row
+    assert ed[v].tolist() == g["expect_after_consolidate_d"]
+    for u in (0, 3, 4, 5):
+        assert not set(rows[u].tolist()) & {1, 2}
+
+
+# --- insert / delete properties ----------------------------------------------------
+def test_insert_properties_and_delete_invariants():
+    base, q = datagen.gmm_uint8_valued(96, 900, 30, 16, 6)
+    ix = O.OracleIndex(16, 8, O.L2, seed=4, beam_insert=24)
+    ix.build(base[:600], batch_max=80)
+    before, bd, _ = ix.export()
+    new = ix.insert(base[600:900])
+    assert new.tolist() == list(range(600, 900))
+    rows, ed, alive = ix.export()
+    # batch-mates do not see each other: forward rows name only old ids
+    assert (rows[600:900] < 600).all()
+    # each rewritten old row draws only on its old alive row and new vertices
+    for t in range(600):
+        extra = set(rows[t][rows[t] >= 0].tolist()) - set(before[t].tolist())
+        assert all(600 <= x < 900 for x in extra)
+    check_invariants(ix, base)
+    # deletes: bad id -> NOTFOUND and no change
+    assert ix.delete([5, 10_000]) == -4
+    assert ix.n_alive == 900
+    g = np.random.Generator(np.random.Philox(1))
+    victims = g.choice(900, 100, replace=False).astype(np.int32)
+    assert ix.delete(victims) == 0
+    assert ix.delete(victims[:10]) == 0                    # idempotent
+    assert ix.n_alive == 800
+    ids, d, _ = ix.search(q, 10, 32)
+    assert not set(ids.ravel().tolist()) & set(victims.tolist())
+    rows, ed, alive = ix.export()
+    for v in np.nonzero(alive)[0]:
+        r = rows[v][rows[v] >= 0]
+        dead = (~alive[r].astype(bool)).sum()
+        assert 2 * dead <= len(r)                          # repair left no >50% rows
+    ix.consolidate()
+    check_invariants(ix, base)                             # fixed degree, no dead edges
+
+
+def test_reduced_precision_exact_on_integer_data(small_index):
+    base, q = datagen.gmm_uint8_valued(97, 400, 20, 16, 4)
+    ix = O.OracleIndex(16, 8, O.L2, seed=6)
+    ix.build(base, batch_max=64)
+    ref = ix.search(q, 10, 24)
+    for p in (O.P_FP16, O.P_BF16):
+        ix.set("precision", p)
+        got = ix.search(q, 10, 24, rerank=False)
+        np.testing.assert_array_equal(got[0], ref[0])
+        np.testing.assert_array_equal(got[1], ref[1])
+    ix.set("precision", O.P_FP32)
+
+
+def test_inner_product_full_width_equals_bruteforce():
+    base, q = datagen.gmm_float(98, 200, 10, 12, 3, normalise=True)
+    ix = O.OracleIndex(12, 8, O.IP, seed=8, entry_samples=4096)
+    ix.build(base, batch_max=50)
+    ids, d, _ = ix.search(q, 10, 200)
+    gi, gd = O.bruteforce(base, q, 10, metric=O.IP)
+    np.testing.assert_array_equal(ids, gi)
+    np.testing.assert_array_equal(d, gd)
