@@ -1,0 +1,162 @@
+/*
+ * svf.h -- C ABI of the MI355X streaming graph-ANN library.
+ *
+ * The library keeps one proximity-graph index per handle entirely in the
+ * GPU's HBM and runs every step of search, insertion, deletion and repair in
+ * hand-written HIP kernels for gfx950.  The operations follow the streaming
+ * ANNS problem statement of SVFusion (arXiv 2601.08528, Sec. 2.2): Build,
+ * Search(q, k), Insert(x) and Delete(x) evolve a dataset state one operation
+ * (here: one batch) at a time.
+ *
+ * Conventions shared by every call
+ *  - Every function returns an int status (SVF_OK or a negative SVF_E_* code);
+ *    no C++ exception crosses this boundary.  svf_last_error() gives a
+ *    message for the last failure on the calling thread.
+ *  - Ids are dense int32 numbers assigned in insertion order from 0 and never
+ *    reused.  INVALID ids are -1.
+ *  - Distances are squared Euclidean for SVF_METRIC_L2 (the ranking of the
+ *    paper's L2 norm, Sec. 2.1) and -<q,x> for SVF_METRIC_IP.
+ *  - Ordering is by the key (distance, id), lexicographically.
+ *  - Host-pointer calls copy their inputs before returning and block until
+ *    their outputs are written.  The caller owns every buffer.
+ *  - *_dev calls take device pointers and a hipStream_t (passed as void *,
+ *    NULL = the handle's own stream); they enqueue work on that stream and
+ *    return without waiting, unless noted.
+ *  - A failed call leaves the index as it was; outputs are then undefined.
+ *  - Calls on one handle are serialised by the library.
+ */
+#ifndef SVF_H
+#define SVF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct svf_index svf_index;
+
+enum { SVF_METRIC_L2 = 0, SVF_METRIC_IP = 1 };
+
+enum {
+    SVF_OK = 0,
+    SVF_E_INVAL = -1,     /* bad argument or option value                   */
+    SVF_E_NOMEM = -2,     /* device memory exhausted (index unchanged)      */
+    SVF_E_DEVICE = -3,    /* HIP runtime error                              */
+    SVF_E_NOTFOUND = -4,  /* an id outside [0, n_slots)                     */
+    SVF_E_BUSY = -5,      /* serving loop state does not allow the call     */
+    SVF_E_INTERNAL = -6
+};
+
+/* Precision of the distances evaluated during graph traversal.  Reduced
+ * precision keeps an FP16 / BF16 copy of every vector, computes in FP32, and
+ * re-scores the final candidate pool with exact FP32 distances. */
+enum { SVF_PREC_FP32 = 0, SVF_PREC_FP16 = 1, SVF_PREC_BF16 = 2 };
+
+typedef struct svf_stats {
+    int64_t n_slots;          /* ids assigned so far                          */
+    int64_t n_alive;          /* ids not deleted                              */
+    int64_t capacity;         /* id slots allocated on the device             */
+    /* last search call (sums over its queries) */
+    int64_t last_queries;
+    int64_t last_n_dist;      /* distance evaluations                         */
+    int64_t last_n_exp;       /* expanded vertices (graph rows read)          */
+    double last_search_ms;    /* device time of the search kernels            */
+    /* last insert / delete call, device time per phase (ms) */
+    double ins_search_ms, ins_prune_ms, ins_reverse_ms, ins_commit_ms;
+    double del_mark_ms, del_repair_ms;
+    int64_t last_repaired;    /* rows rewritten by the last delete/consolidate */
+    int64_t device_bytes;     /* HBM held by the index                        */
+} svf_stats;
+
+/* Create an empty index.  Sec. 2.3: a directed graph with a fixed number of
+ * out-edges (degree) per vertex.  dim >= 1 and <= 1024; 1 <= degree <= 128;
+ * metric is SVF_METRIC_L2 or SVF_METRIC_IP.  *out receives the handle.
+ * Allocates a small initial capacity on the current HIP device. */
+int svf_create(int32_t dim, int32_t degree, int32_t metric, svf_index **out);
+
+/* Release the handle and all its device memory.  NULL is accepted. */
+int svf_destroy(svf_index *ix);
+
+/* Set a numeric option.  Keys (range; default):
+ *   seed            entry-point hash seed (any; 0)
+ *   beam_insert     candidate pool size of the insertion search (degree..512; 2*degree)
+ *   entry_samples   random entry points per query, 0 = the pool size (0..1024; 0)
+ *   max_iters       cap on expansions per query, 0 = none (>= 0; 0)
+ *   visited_slots   LDS visited-table slots per query, power of two (256..8192; 2048)
+ *   repair_c        out-neighbours taken from each deleted neighbour (1..min(16, degree); 8)
+ *   prune_cap       longest candidate list given to the prune, 0 = max(4*degree, beam_insert)
+ *   consolidate_frac deleted fraction that triggers consolidation ((0,1]; 0.2)
+ *   insert_batch_max largest batch of one insertion pass (1..1<<20; 10000)
+ *   precision       SVF_PREC_* of traversal distances (0..2; 0)
+ *   rerank          exact FP32 re-scoring of the final pool under reduced precision (0/1; 1)
+ * Unknown key or out-of-range value: SVF_E_INVAL. */
+int svf_set_option(svf_index *ix, const char *key, double value);
+int svf_get_option(const svf_index *ix, const char *key, double *value);
+
+/* Insert n vectors (n x dim row-major FP32, host memory) as one batch
+ * (Sec. 5.1): each new vector searches the pre-batch graph for candidates,
+ * keeps the rank-based reordering of them as its out-edges, and its chosen
+ * neighbours receive reverse edges.  Batches larger than insert_batch_max are
+ * split.  out_ids (n entries, may be NULL) receives the assigned ids.
+ * Non-finite input: SVF_E_INVAL. */
+int svf_insert(svf_index *ix, const float *vecs, int64_t n, int32_t *out_ids);
+/* Same with device pointers; synchronises the stream before returning. */
+int svf_insert_dev(svf_index *ix, const float *d_vecs, int64_t n, int32_t *d_out_ids, void *stream);
+
+/* Build from scratch by the insertion rule: the first min(n, 4*degree)
+ * vectors form an exact nearest-neighbour seed graph, the rest are inserted in
+ * batches of min(insert_batch_max, ceil(n_alive / 8)).  The index must be
+ * empty.  vecs: host memory. */
+int svf_build(svf_index *ix, const float *vecs, int64_t n);
+
+/* Delete ids (Sec. 5.2): mark them in the deletion bitset, then repair every
+ * alive vertex with more than half of its neighbours deleted from at most
+ * repair_c out-neighbours of each deleted neighbour; consolidate when the
+ * deleted fraction since the last consolidation reaches consolidate_frac.
+ * An id outside [0, n_slots) gives SVF_E_NOTFOUND and no change; deleting an
+ * id twice is harmless.  ids: host memory. */
+int svf_delete(svf_index *ix, const int32_t *ids, int64_t n);
+
+/* Global consolidation (Sec. 5.2): rebuild every alive row that names a
+ * deleted vertex.  Afterwards no edge points at a deleted id. */
+int svf_consolidate(svf_index *ix);
+
+/* Batched search (Sec. 4.2, Algorithm 1): for each of nq queries (nq x dim
+ * FP32, host memory) a best-first search with a candidate pool of `beam`
+ * entries (k <= beam <= 512) from random entry points, stopping when every
+ * pool entry is expanded; the k nearest found are written to out_ids and
+ * out_dists (nq x k each, ascending).  Fewer than k alive vectors: the rest
+ * is padded with id -1 and distance +inf. */
+int svf_search(svf_index *ix, const float *queries, int64_t nq, int32_t k, int32_t beam,
+               int32_t *out_ids, float *out_dists);
+
+/* Device-pointer search, enqueued on `stream` without waiting.  Optional
+ * d_n_dist / d_n_exp (nq int32 each, may be NULL) receive per-query counts of
+ * distance evaluations and expansions. */
+int svf_search_dev(svf_index *ix, const float *d_queries, int64_t nq, int32_t k, int32_t beam,
+                   int32_t *d_out_ids, float *d_out_dists, int32_t *d_n_dist, int32_t *d_n_exp,
+                   void *stream);
+
+/* Statistics of the index and of its last calls. */
+int svf_stats_get(const svf_index *ix, svf_stats *out);
+
+/* Copy the graph out (host memory): rows (n_slots x degree ids), edge_d
+ * (n_slots x degree FP32 distances) and alive (n_slots bytes), each may be
+ * NULL.  cap_slots must be >= n_slots. */
+int svf_export_graph(const svf_index *ix, int32_t *rows, float *edge_d, uint8_t *alive,
+                     int64_t cap_slots);
+
+/* Replace the state of an EMPTY index by n vectors, their rows, edge
+ * distances and alive flags (host memory).  Used to start two
+ * implementations from one identical state. */
+int svf_import_graph(svf_index *ix, const float *vecs, int64_t n, const int32_t *rows,
+                     const float *edge_d, const uint8_t *alive);
+
+/* Thread-local message of the last failing call on this thread. */
+const char *svf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SVF_H */

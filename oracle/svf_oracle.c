@@ -61,6 +61,7 @@ typedef struct {
     int prune_cap;        /* longest candidate list handed to the prune      */
     int precision;        /* ORC_P_*: value grid of the search distances     */
     double consolidate_frac;
+    int64_t insert_batch_max; /* largest batch of one insertion pass          */
     int64_t deleted_since;  /* deletions since the last consolidation        */
     int64_t alive_at_consolidate;
 } orc_index;
@@ -141,6 +142,7 @@ orc_index *orc_create(int dim, int R, int metric, uint64_t seed)
     ix->prune_cap = 0;   /* 0: max(4R, beam_insert) */
     ix->precision = ORC_P_FP32;
     ix->consolidate_frac = 0.2;
+    ix->insert_batch_max = 10000;
     return ix;
 }
 
@@ -168,6 +170,7 @@ int orc_set(orc_index *ix, const char *key, double v)
     else if (!strcmp(key, "prune_cap")) { if (v < 0) return ORC_E_INVAL; ix->prune_cap = (int)v; }
     else if (!strcmp(key, "consolidate_frac")) { if (v <= 0 || v > 1) return ORC_E_INVAL; ix->consolidate_frac = v; }
     else if (!strcmp(key, "seed")) { ix->seed = (uint64_t)v; }
+    else if (!strcmp(key, "insert_batch_max")) { if (v < 1) return ORC_E_INVAL; ix->insert_batch_max = (int64_t)v; }
     else if (!strcmp(key, "precision")) {
         if (v != 0 && v != 1 && v != 2) return ORC_E_INVAL;
         ix->precision = (int)v;
@@ -603,7 +606,7 @@ static int cmp_cand(const void *a, const void *b) { return cmp_pentry(a, b); }
  * committed together at the end of the batch. */
 typedef struct { int32_t v; double d; } incoming;
 
-int orc_insert(orc_index *ix, const float *vecs, int64_t b, int32_t *out_ids)
+static int insert_one_batch(orc_index *ix, const float *vecs, int64_t b, int32_t *out_ids)
 {
     if (b < 0) return ORC_E_INVAL;
     if (b == 0) return ORC_OK;
@@ -696,6 +699,28 @@ int orc_insert(orc_index *ix, const float *vecs, int64_t b, int32_t *out_ids)
     return ORC_OK;
 }
 
+int orc_build(orc_index *ix, const float *vecs, int64_t n, int64_t batch_max);
+
+/* Insertion of n vectors: into an empty index this is the build rule below;
+ * otherwise consecutive batches of at most insert_batch_max vectors. */
+int orc_insert(orc_index *ix, const float *vecs, int64_t n, int32_t *out_ids)
+{
+    if (n < 0) return ORC_E_INVAL;
+    if (n == 0) return ORC_OK;
+    if (ix->n_slots == 0) {
+        int rc = orc_build(ix, vecs, n, ix->insert_batch_max);
+        if (!rc && out_ids) for (int64_t i = 0; i < n; ++i) out_ids[i] = (int32_t)i;
+        return rc;
+    }
+    for (int64_t done = 0; done < n;) {
+        int64_t b = n - done < ix->insert_batch_max ? n - done : ix->insert_batch_max;
+        int rc = insert_one_batch(ix, vecs + done * ix->dim, b, out_ids ? out_ids + done : NULL);
+        if (rc) return rc;
+        done += b;
+    }
+    return ORC_OK;
+}
+
 /* Seed graph: the first S0 = min(n, 4R) vectors, each row pruned from all the
  * other seed vectors with empty neighbour lists, so every detour count is 0
  * and each row is the exact R-nearest list among the seed.  The remaining
@@ -732,7 +757,7 @@ int orc_build(orc_index *ix, const float *vecs, int64_t n, int64_t batch_max)
         int64_t b = (ix->n_alive + 7) / 8;
         if (b > batch_max) b = batch_max;
         if (b > n - done) b = n - done;
-        rc = orc_insert(ix, vecs + done * d, b, NULL);
+        rc = insert_one_batch(ix, vecs + done * d, b, NULL);
         if (rc) return rc;
         done += b;
     }

@@ -1,0 +1,178 @@
+"""MI355X-native streaming graph-ANN hot path (SVFusion, arXiv 2601.08528).
+
+Thin Python binding of the C ABI in ``include/svf.h``: argument marshalling
+only.  Every step of search, insertion, deletion and repair runs in the HIP
+kernels of ``libsvf.so``; importing the binding without that library raises.
+Host arrays are numpy; device buffers are passed as raw pointers (for
+example ``torch.Tensor.data_ptr()``) together with a stream handle.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsvf.so")
+
+METRIC_L2, METRIC_IP = 0, 1
+PREC_FP32, PREC_FP16, PREC_BF16 = 0, 1, 2
+OK, E_INVAL, E_NOMEM, E_DEVICE, E_NOTFOUND, E_BUSY, E_INTERNAL = 0, -1, -2, -3, -4, -5, -6
+
+EXPORTED = [
+    "svf_create", "svf_destroy", "svf_set_option", "svf_get_option", "svf_insert",
+    "svf_insert_dev", "svf_build", "svf_delete", "svf_consolidate", "svf_search",
+    "svf_search_dev", "svf_stats_get", "svf_export_graph", "svf_import_graph", "svf_last_error",
+]
+
+
+class SvfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("svf status %d: %s" % (code, msg))
+        self.code = code
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("n_slots", C.c_int64), ("n_alive", C.c_int64), ("capacity", C.c_int64),
+        ("last_queries", C.c_int64), ("last_n_dist", C.c_int64), ("last_n_exp", C.c_int64),
+        ("last_search_ms", C.c_double),
+        ("ins_search_ms", C.c_double), ("ins_prune_ms", C.c_double),
+        ("ins_reverse_ms", C.c_double), ("ins_commit_ms", C.c_double),
+        ("del_mark_ms", C.c_double), ("del_repair_ms", C.c_double),
+        ("last_repaired", C.c_int64), ("device_bytes", C.c_int64),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libsvf.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libsvf.so is not built: run python -m paper_2601_08528_amd.build")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.svf_create.argtypes = [i32, i32, i32, C.POINTER(vp)]
+        L.svf_destroy.argtypes = [vp]
+        L.svf_set_option.argtypes = [vp, C.c_char_p, f64]
+        L.svf_get_option.argtypes = [vp, C.c_char_p, C.POINTER(f64)]
+        L.svf_insert.argtypes = [vp, vp, i64, vp]
+        L.svf_insert_dev.argtypes = [vp, vp, i64, vp, vp]
+        L.svf_build.argtypes = [vp, vp, i64]
+        L.svf_delete.argtypes = [vp, vp, i64]
+        L.svf_consolidate.argtypes = [vp]
+        L.svf_search.argtypes = [vp, vp, i64, i32, i32, vp, vp]
+        L.svf_search_dev.argtypes = [vp, vp, i64, i32, i32, vp, vp, vp, vp, vp]
+        L.svf_stats_get.argtypes = [vp, C.POINTER(Stats)]
+        L.svf_export_graph.argtypes = [vp, vp, vp, vp, i64]
+        L.svf_import_graph.argtypes = [vp, vp, i64, vp, vp, vp]
+        L.svf_last_error.restype = C.c_char_p
+        for name in EXPORTED:
+            if name != "svf_last_error":
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise SvfError(rc, lib().svf_last_error().decode())
+    return rc
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+class Index:
+    """One index handle (``svf_create`` ... ``svf_destroy``)."""
+
+    def __init__(self, dim: int, degree: int, metric: int = METRIC_L2, **options):
+        h = C.c_void_p()
+        _check(lib().svf_create(dim, degree, metric, C.byref(h)))
+        self.h = h
+        self.dim, self.degree, self.metric = dim, degree, metric
+        for k, v in options.items():
+            self.set_option(k, v)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().svf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_option(self, key: str, value: float):
+        _check(lib().svf_set_option(self.h, key.encode(), float(value)))
+
+    def get_option(self, key: str) -> float:
+        out = C.c_double()
+        _check(lib().svf_get_option(self.h, key.encode(), C.byref(out)))
+        return out.value
+
+    def insert(self, vecs) -> np.ndarray:
+        v = np.ascontiguousarray(vecs, dtype=np.float32).reshape(-1, self.dim)
+        ids = np.empty(v.shape[0], np.int32)
+        _check(lib().svf_insert(self.h, _p(v), v.shape[0], _p(ids)))
+        return ids
+
+    def insert_dev(self, d_vecs: int, n: int, d_out_ids: int | None = None, stream: int | None = None):
+        _check(lib().svf_insert_dev(self.h, d_vecs, n, d_out_ids, stream))
+
+    def build(self, vecs):
+        v = np.ascontiguousarray(vecs, dtype=np.float32).reshape(-1, self.dim)
+        _check(lib().svf_build(self.h, _p(v), v.shape[0]))
+
+    def delete(self, ids):
+        a = np.ascontiguousarray(ids, dtype=np.int32).reshape(-1)
+        _check(lib().svf_delete(self.h, _p(a), a.shape[0]))
+
+    def consolidate(self):
+        _check(lib().svf_consolidate(self.h))
+
+    def search(self, queries, k: int, beam: int):
+        q = np.ascontiguousarray(queries, dtype=np.float32).reshape(-1, self.dim)
+        ids = np.empty((q.shape[0], k), np.int32)
+        d = np.empty((q.shape[0], k), np.float32)
+        _check(lib().svf_search(self.h, _p(q), q.shape[0], k, beam, _p(ids), _p(d)))
+        return ids, d
+
+    def search_dev(self, d_queries: int, nq: int, k: int, beam: int, d_ids: int, d_dists: int,
+                   d_n_dist: int | None = None, d_n_exp: int | None = None, stream: int | None = None):
+        _check(lib().svf_search_dev(self.h, d_queries, nq, k, beam, d_ids, d_dists, d_n_dist,
+                                    d_n_exp, stream))
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib().svf_stats_get(self.h, C.byref(s)))
+        return s.as_dict()
+
+    @property
+    def n_slots(self) -> int:
+        return self.stats()["n_slots"]
+
+    def export_graph(self):
+        n = self.n_slots
+        rows = np.empty((n, self.degree), np.int32)
+        ed = np.empty((n, self.degree), np.float32)
+        alive = np.empty(n, np.uint8)
+        _check(lib().svf_export_graph(self.h, _p(rows), _p(ed), _p(alive), n))
+        return rows, ed, alive
+
+    def import_graph(self, vecs, rows, edge_d, alive):
+        v = np.ascontiguousarray(vecs, dtype=np.float32).reshape(-1, self.dim)
+        r = np.ascontiguousarray(rows, dtype=np.int32)
+        e = np.ascontiguousarray(edge_d, dtype=np.float32)
+        a = np.ascontiguousarray(alive, dtype=np.uint8)
+        _check(lib().svf_import_graph(self.h, _p(v), v.shape[0], _p(r), _p(e), _p(a)))

@@ -1,0 +1,785 @@
+// C ABI of the library: index state in HBM, batch orchestration of the
+// search, insertion and deletion kernels, option handling and errors.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "index.hpp"
+#include "kernels.hpp"
+
+using svf::DevBuf;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+int hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? SVF_E_NOMEM : SVF_E_DEVICE;
+}
+
+#define CK(call)                                         \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);    \
+  } while (0)
+
+constexpr int kMaxBeam = 512;
+constexpr int kMaxEntries = 1024;
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+int beam_insert(const svf_index* ix) {
+  return ix->opt.beam_insert > 0 ? ix->opt.beam_insert : std::min(2 * ix->R, kMaxBeam);
+}
+int prune_cap(const svf_index* ix) {
+  if (ix->opt.prune_cap > 0) return ix->opt.prune_cap;
+  return std::max(4 * ix->R, beam_insert(ix));
+}
+int visited_slots(const svf_index* ix, int E) {
+  int T = ix->opt.visited_slots;
+  while (T < 2 * E) T <<= 1;   // entry phase needs an exact table
+  return T;
+}
+
+template <class T>
+int scratch(DevBuf& b, size_t count, T** out) {
+  hipError_t e = b.ensure(count * sizeof(T) + 16);
+  if (e != hipSuccess) return hip_fail(e, "scratch allocation");
+  *out = b.as<T>();
+  return SVF_OK;
+}
+
+// Grow the device arrays to hold `need` id slots, keeping the contents.
+int reserve(svf_index* ix, int64_t need) {
+  if (need <= ix->cap) return SVF_OK;
+  if (need > (int64_t)INT32_MAX - 64) return fail(SVF_E_INVAL, "index would exceed int32 ids");
+  int64_t cap = std::max<int64_t>({need, ix->cap * 2, 1024});
+  cap = round_up(cap, 64);
+  const int64_t words = cap / 32;
+  float *v32 = nullptr, *ed = nullptr;
+  void* vlp = nullptr;
+  int32_t *g = nullptr, *tc = nullptr, *ti = nullptr;
+  uint32_t* al = nullptr;
+  auto cleanup = [&]() {
+    if (v32) (void)hipFree(v32);
+    if (vlp) (void)hipFree(vlp);
+    if (g) (void)hipFree(g);
+    if (ed) (void)hipFree(ed);
+    if (al) (void)hipFree(al);
+    if (tc) (void)hipFree(tc);
+    if (ti) (void)hipFree(ti);
+  };
+  hipError_t e = hipSuccess;
+  if ((e = hipMalloc(&v32, cap * ix->stride * 4)) != hipSuccess ||
+      (ix->veclp_prec && (e = hipMalloc(&vlp, cap * ix->stride * 2)) != hipSuccess) ||
+      (e = hipMalloc(&g, cap * ix->R * 4)) != hipSuccess ||
+      (e = hipMalloc(&ed, cap * ix->R * 4)) != hipSuccess ||
+      (e = hipMalloc(&al, words * 4)) != hipSuccess ||
+      (e = hipMalloc(&tc, cap * 4)) != hipSuccess || (e = hipMalloc(&ti, cap * 4)) != hipSuccess) {
+    cleanup();
+    return hip_fail(e, "index allocation");
+  }
+  hipStream_t st = ix->stream;
+  const int64_t n = ix->n_slots;
+  CK(svf::launch_fill_u32(v32, cap * ix->stride, 0u, st));
+  if (vlp) CK(svf::launch_fill_u32(vlp, cap * ix->stride / 2, 0u, st));
+  CK(svf::launch_fill_u32(g, cap * ix->R, 0xffffffffu, st));
+  CK(svf::launch_fill_u32(ed, cap * ix->R, 0x7f800000u, st));
+  CK(svf::launch_fill_u32(al, words, 0u, st));
+  CK(svf::launch_fill_u32(tc, cap, 0u, st));
+  if (n > 0) {
+    CK(hipMemcpyAsync(v32, ix->vec32, n * ix->stride * 4, hipMemcpyDeviceToDevice, st));
+    if (vlp) CK(hipMemcpyAsync(vlp, ix->veclp, n * ix->stride * 2, hipMemcpyDeviceToDevice, st));
+    CK(hipMemcpyAsync(g, ix->graph, n * ix->R * 4, hipMemcpyDeviceToDevice, st));
+    CK(hipMemcpyAsync(ed, ix->edge_d, n * ix->R * 4, hipMemcpyDeviceToDevice, st));
+    CK(hipMemcpyAsync(al, ix->alive, ((n + 31) / 32) * 4, hipMemcpyDeviceToDevice, st));
+  }
+  CK(hipStreamSynchronize(st));
+  if (ix->vec32) (void)hipFree(ix->vec32);
+  if (ix->veclp) (void)hipFree(ix->veclp);
+  if (ix->graph) (void)hipFree(ix->graph);
+  if (ix->edge_d) (void)hipFree(ix->edge_d);
+  if (ix->alive) (void)hipFree(ix->alive);
+  ix->vec32 = v32;
+  ix->veclp = vlp;
+  ix->graph = g;
+  ix->edge_d = ed;
+  ix->alive = al;
+  ix->cap = cap;
+  // tcount / tidx are per-slot scratch of the reverse-edge step
+  static_assert(sizeof(int32_t) == 4, "");
+  ix->s_misc[10].release();
+  ix->s_misc[11].release();
+  ix->s_misc[10].p = tc; ix->s_misc[10].bytes = cap * 4;
+  ix->s_misc[11].p = ti; ix->s_misc[11].bytes = cap * 4;
+  return SVF_OK;
+}
+
+int32_t* tcount(svf_index* ix) { return ix->s_misc[10].as<int32_t>(); }
+int32_t* tidx(svf_index* ix) { return ix->s_misc[11].as<int32_t>(); }
+
+// Make the reduced-precision copy match the chosen precision.
+int sync_lowp(svf_index* ix) {
+  const int prec = ix->opt.precision;
+  if (prec == ix->veclp_prec) return SVF_OK;
+  if (ix->veclp) (void)hipFree(ix->veclp);
+  ix->veclp = nullptr;
+  ix->veclp_prec = prec;
+  if (prec == 0 || ix->cap == 0) return SVF_OK;
+  CK(hipMalloc(&ix->veclp, ix->cap * ix->stride * 2));
+  CK(svf::launch_fill_u32(ix->veclp, ix->cap * ix->stride / 2, 0u, ix->stream));
+  CK(svf::launch_store_lowp(ix->vec32, ix->veclp, 0, ix->n_slots, ix->stride, prec, ix->stream));
+  CK(hipStreamSynchronize(ix->stream));
+  return SVF_OK;
+}
+
+// Copy n rows (pitch dim floats, device memory) into slots [at, at + n).
+int store_rows(svf_index* ix, const float* d_src, int64_t n, int64_t at, hipStream_t st) {
+  if (n <= 0) return SVF_OK;
+  CK(hipMemcpy2DAsync(ix->vec32 + at * ix->stride, ix->stride * 4, d_src, ix->dim * 4,
+                      ix->dim * 4, n, hipMemcpyDeviceToDevice, st));
+  if (ix->veclp_prec)
+    CK(svf::launch_store_lowp(ix->vec32, ix->veclp, at, n, ix->stride, ix->veclp_prec, st));
+  return SVF_OK;
+}
+
+const void* traversal_store(const svf_index* ix) {
+  return ix->veclp_prec ? ix->veclp : (const void*)ix->vec32;
+}
+
+svf::SearchArgs base_args(const svf_index* ix) {
+  svf::SearchArgs a{};
+  a.vec = traversal_store(ix);
+  a.vec32 = ix->vec32;
+  a.stride = ix->stride;
+  a.dim = ix->dim;
+  a.graph = ix->graph;
+  a.R = ix->R;
+  a.alive = ix->alive;
+  a.n_slots = (int32_t)ix->n_slots;
+  a.n_alive = (int32_t)ix->n_alive;
+  a.metric = ix->metric;
+  a.max_iters = ix->opt.max_iters;
+  return a;
+}
+
+void set_beam(svf::SearchArgs& a, const svf_index* ix, int L) {
+  a.L = L;
+  int Lp = 64;
+  while (Lp < L) Lp <<= 1;
+  a.L_pow2 = Lp;
+  a.E = ix->opt.entry_samples > 0 ? ix->opt.entry_samples : L;
+  a.T = visited_slots(ix, a.E);
+  a.rerank = (ix->veclp_prec != 0 && ix->opt.rerank) ? 1 : 0;
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventSynchronize(b) != hipSuccess) return 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
+  return ms;
+}
+
+// One insertion batch of b vectors already on the device (pitch dim).
+int insert_batch(svf_index* ix, const float* d_vecs, int64_t b, int32_t* d_out_ids,
+                 int32_t* h_out_ids) {
+  if (b <= 0) return SVF_OK;
+  int rc = reserve(ix, ix->n_slots + b);
+  if (rc) return rc;
+  hipStream_t st = ix->stream;
+  const int R = ix->R;
+  const int64_t n0 = ix->n_slots;
+  if (n0 == 0) {
+    // empty index: the seed rule (exact R-nearest among the seed vectors)
+    if (b > 4 * R) return fail(SVF_E_INTERNAL, "seed batch larger than 4 * degree");
+    rc = store_rows(ix, d_vecs, b, 0, st);
+    if (rc) return rc;
+    CK(svf::launch_seed(ix->vec32, ix->stride, ix->dim, ix->metric, (int)b, R, ix->graph,
+                        ix->edge_d, st));
+    CK(svf::launch_set_alive(ix->alive, 0, b, st));
+    CK(hipStreamSynchronize(st));
+    ix->n_slots = b;
+    ix->n_alive = b;
+  } else {
+    const int Lins = beam_insert(ix);
+    rc = store_rows(ix, d_vecs, b, n0, st);
+    if (rc) return rc;
+    uint64_t *qkey, *pool;
+    int32_t *fwd, *cnt;
+    float* fwd_d;
+    if ((rc = scratch(ix->s_qkey, b, &qkey)) || (rc = scratch(ix->s_pool, b * Lins, &pool)) ||
+        (rc = scratch(ix->s_misc[0], b * R, &fwd)) || (rc = scratch(ix->s_misc[1], b * R, &fwd_d)) ||
+        (rc = scratch(ix->s_misc[2], 8, &cnt)))
+      return rc;
+    // phase 1: batched search of the pre-batch graph
+    CK(hipEventRecord(ix->ev0, st));
+    svf::SearchArgs a = base_args(ix);
+    set_beam(a, ix, Lins);
+    a.max_iters = 0;
+    a.k = 0;
+    a.queries = ix->vec32 + n0 * ix->stride;
+    a.qstride = ix->stride;
+    a.nq = (int)b;
+    a.out_pool = pool;
+    a.n_slots = (int32_t)n0;
+    CK(svf::launch_query_keys(a.queries, a.qstride, nullptr, ix->dim, a.nq, ix->opt.seed, qkey, st));
+    a.qkey = qkey;
+    CK(svf::launch_search(a, ix->veclp_prec, st));
+    CK(hipEventRecord(ix->ev1, st));
+    ix->st.ins_search_ms = elapsed(ix->ev0, ix->ev1);
+    // phase 2: rank-based reordering of each candidate list -> forward rows
+    CK(hipEventRecord(ix->ev0, st));
+    svf::PruneArgs pa{};
+    pa.cand = pool;
+    pa.cstride = Lins;
+    pa.cap = prune_cap(ix);
+    pa.graph = ix->graph;
+    pa.fwd = nullptr;
+    pa.n_old = (int32_t)n0;
+    pa.R = R;
+    pa.out_ids = fwd;
+    pa.out_d = fwd_d;
+    pa.nlists = (int)b;
+    CK(svf::launch_prune_lists(pa, st));
+    CK(hipEventRecord(ix->ev1, st));
+    ix->st.ins_prune_ms = elapsed(ix->ev0, ix->ev1);
+    // phase 3: reverse edges grouped by target, re-pruned
+    CK(hipEventRecord(ix->ev0, st));
+    svf::ReverseArgs ra{};
+    ra.fwd_ids = fwd;
+    ra.fwd_d = fwd_d;
+    ra.b = (int)b;
+    ra.R = R;
+    ra.n0 = (int32_t)n0;
+    ra.tcount = tcount(ix);
+    ra.tidx = tidx(ix);
+    ra.graph = ix->graph;
+    ra.edge_d = ix->edge_d;
+    ra.alive = ix->alive;
+    ra.cap = prune_cap(ix);
+    const int64_t npairs = b * R;
+    if ((rc = scratch(ix->s_misc[3], npairs, &ra.tlist))) return rc;
+    ra.n_targets = cnt;
+    CK(svf::launch_fill_u32(cnt, 1, 0u, st));
+    CK(svf::launch_reverse_count(ra, st));
+    int32_t n_targets = 0;
+    CK(hipMemcpyAsync(&n_targets, cnt, 4, hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    if ((rc = scratch(ix->s_misc[4], n_targets + 1, &ra.off)) ||
+        (rc = scratch(ix->s_misc[5], n_targets + 1, &ra.cursor)) ||
+        (rc = scratch(ix->s_misc[6], npairs, &ra.inc)) ||
+        (rc = scratch(ix->s_misc[7], (size_t)n_targets * R, &ra.trow)) ||
+        (rc = scratch(ix->s_misc[8], (size_t)n_targets * R, &ra.trow_d)))
+      return rc;
+    CK(svf::launch_reverse_scan_scatter(ra, n_targets, st));
+    CK(svf::launch_reverse_prune(ra, n_targets, st));
+    CK(hipEventRecord(ix->ev1, st));
+    ix->st.ins_reverse_ms = elapsed(ix->ev0, ix->ev1);
+    // phase 4: commit
+    CK(hipEventRecord(ix->ev0, st));
+    CK(svf::launch_commit_batch(ra, n_targets, ix->graph, ix->edge_d, ix->alive, st));
+    CK(hipEventRecord(ix->ev1, st));
+    CK(hipStreamSynchronize(st));
+    ix->st.ins_commit_ms = elapsed(ix->ev0, ix->ev1);
+    ix->n_slots = n0 + b;
+    ix->n_alive += b;
+  }
+  if (h_out_ids)
+    for (int64_t i = 0; i < b; ++i) h_out_ids[i] = (int32_t)(n0 + i);
+  if (d_out_ids) {
+    std::vector<int32_t> ids(b);
+    for (int64_t i = 0; i < b; ++i) ids[i] = (int32_t)(n0 + i);
+    CK(hipMemcpy(d_out_ids, ids.data(), b * 4, hipMemcpyHostToDevice));
+  }
+  return SVF_OK;
+}
+
+// Repair (consolidate = 0) or consolidation (1) of the rows that name deleted ids.
+int repair(svf_index* ix, int consolidate) {
+  hipStream_t st = ix->stream;
+  const int R = ix->R;
+  const int cap = prune_cap(ix);
+  int32_t *list, *cnt;
+  int rc;
+  if ((rc = scratch(ix->s_misc[0], std::max<int64_t>(ix->n_slots, 1), &list)) ||
+      (rc = scratch(ix->s_misc[2], 8, &cnt)))
+    return rc;
+  CK(hipEventRecord(ix->ev0, st));
+  svf::RepairArgs a{};
+  a.vec32 = ix->vec32;
+  a.stride = ix->stride;
+  a.dim = ix->dim;
+  a.metric = ix->metric;
+  a.R = R;
+  a.graph = ix->graph;
+  a.edge_d = ix->edge_d;
+  a.alive = ix->alive;
+  a.n_slots = (int32_t)ix->n_slots;
+  a.consolidate = consolidate;
+  a.c = consolidate ? R : ix->opt.repair_c;
+  a.cap = cap;
+  a.list = list;
+  a.n_list = cnt;
+  a.n_topup = cnt + 1;
+  CK(svf::launch_fill_u32(cnt, 2, 0u, st));
+  CK(svf::launch_affected(a, st));
+  int32_t n_aff = 0;
+  CK(hipMemcpyAsync(&n_aff, cnt, 4, hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  ix->st.last_repaired = n_aff;
+  if (n_aff == 0) {
+    ix->st.del_repair_ms = 0;
+    return SVF_OK;
+  }
+  int32_t *rows, *mcount, *topup, *topup_v;
+  float* rows_d;
+  uint64_t* cand;
+  const int64_t chunk = std::min<int64_t>(n_aff, 131072);
+  if ((rc = scratch(ix->s_misc[7], (size_t)n_aff * R, &rows)) ||
+      (rc = scratch(ix->s_misc[8], (size_t)n_aff * R, &rows_d)) ||
+      (rc = scratch(ix->s_misc[6], (size_t)chunk * cap, &cand)) ||
+      (rc = scratch(ix->s_misc[3], chunk, &mcount)) || (rc = scratch(ix->s_misc[4], chunk, &topup)) ||
+      (rc = scratch(ix->s_misc[5], chunk, &topup_v)))
+    return rc;
+  a.cand = cand;
+  a.mcount = mcount;
+  a.topup = topup;
+  a.topup_v = topup_v;
+  const int Lins = beam_insert(ix);
+  for (int64_t first = 0; first < n_aff; first += chunk) {
+    const int count = (int)std::min<int64_t>(chunk, n_aff - first);
+    CK(svf::launch_fill_u32(cnt + 1, 1, 0u, st));
+    CK(svf::launch_repair_candidates(a, (int)first, count, st));
+    int32_t ntop = 0;
+    CK(hipMemcpyAsync(&ntop, cnt + 1, 4, hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    if (ntop > 0) {
+      uint64_t *qkey, *pool;
+      if ((rc = scratch(ix->s_qkey, ntop, &qkey)) || (rc = scratch(ix->s_pool, (size_t)ntop * Lins, &pool)))
+        return rc;
+      svf::SearchArgs s = base_args(ix);
+      set_beam(s, ix, Lins);
+      s.max_iters = 0;
+      s.k = 0;
+      s.queries = ix->vec32;
+      s.qstride = ix->stride;
+      s.qids = topup_v;
+      s.nq = ntop;
+      s.out_pool = pool;
+      CK(svf::launch_query_keys(ix->vec32, ix->stride, topup_v, ix->dim, ntop, ix->opt.seed, qkey, st));
+      s.qkey = qkey;
+      CK(svf::launch_search(s, ix->veclp_prec, st));
+      CK(svf::launch_topup_merge(a, pool, Lins, (int)first, ntop, st));
+    }
+    svf::PruneArgs pa{};
+    pa.cand = cand;
+    pa.cstride = cap;
+    pa.cap = cap;
+    pa.graph = ix->graph;
+    pa.fwd = nullptr;
+    pa.n_old = (int32_t)ix->n_slots;
+    pa.R = R;
+    pa.out_ids = rows + first * R;
+    pa.out_d = rows_d + first * R;
+    pa.nlists = count;
+    CK(svf::launch_prune_lists(pa, st));
+  }
+  CK(svf::launch_commit_rows(list, n_aff, rows, rows_d, R, ix->graph, ix->edge_d, st));
+  CK(hipEventRecord(ix->ev1, st));
+  CK(hipStreamSynchronize(st));
+  ix->st.del_repair_ms = elapsed(ix->ev0, ix->ev1);
+  return SVF_OK;
+}
+
+int search_impl(svf_index* ix, const float* d_q, int64_t nq, int k, int beam, int32_t* d_ids,
+                float* d_d, int32_t* d_nd, int32_t* d_ne, hipStream_t st) {
+  if (nq == 0) return SVF_OK;
+  uint64_t* qkey;
+  unsigned long long* tot;
+  int rc;
+  if ((rc = scratch(ix->s_qkey, nq, &qkey)) || (rc = scratch(ix->s_tot, 2, &tot))) return rc;
+  if (ix->n_slots == 0) {
+    // nothing indexed: every result is padding
+    CK(svf::launch_fill_u32(d_ids, nq * k, 0xffffffffu, st));
+    CK(svf::launch_fill_u32(d_d, nq * k, 0x7f800000u, st));
+    if (d_nd) CK(svf::launch_fill_u32(d_nd, nq, 0u, st));
+    if (d_ne) CK(svf::launch_fill_u32(d_ne, nq, 0u, st));
+    return SVF_OK;
+  }
+  svf::SearchArgs a = base_args(ix);
+  set_beam(a, ix, beam);
+  a.k = k;
+  a.queries = d_q;
+  a.qstride = ix->dim;
+  a.nq = (int)nq;
+  a.out_ids = d_ids;
+  a.out_d = d_d;
+  a.n_dist = d_nd;
+  a.n_exp = d_ne;
+  a.totals = tot;
+  CK(svf::launch_fill_u32(tot, 4, 0u, st));
+  CK(svf::launch_query_keys(d_q, ix->dim, nullptr, ix->dim, a.nq, ix->opt.seed, qkey, st));
+  a.qkey = qkey;
+  CK(hipEventRecord(ix->ev0, st));
+  CK(svf::launch_search(a, ix->veclp_prec, st));
+  CK(hipEventRecord(ix->ev1, st));
+  ix->st.last_queries = nq;
+  return SVF_OK;
+}
+
+// Insert n device-resident vectors.  Into an empty index this is the build
+// rule: a seed of min(n, 4R) vectors, then batches of
+// min(insert_batch_max, ceil(n_alive / 8)); otherwise batches of
+// insert_batch_max.
+int insert_stream(svf_index* ix, const float* d, int64_t n, int32_t* d_out_ids, int32_t* h_out_ids) {
+  int64_t done = 0;
+  const bool grow = ix->n_slots == 0;
+  int rc = reserve(ix, ix->n_slots + n);
+  if (rc) return rc;
+  if (grow && n > 0) {
+    const int64_t s0 = std::min<int64_t>(n, 4 * ix->R);
+    rc = insert_batch(ix, d, s0, d_out_ids, h_out_ids);
+    if (rc) return rc;
+    done = s0;
+  }
+  while (done < n) {
+    int64_t b = std::min<int64_t>(ix->opt.insert_batch_max, n - done);
+    if (grow) b = std::min<int64_t>(b, (ix->n_alive + 7) / 8);
+    rc = insert_batch(ix, d + done * ix->dim, b, d_out_ids ? d_out_ids + done : nullptr,
+                      h_out_ids ? h_out_ids + done : nullptr);
+    if (rc) return rc;
+    done += b;
+  }
+  return SVF_OK;
+}
+
+int check_search_args(const svf_index* ix, int64_t nq, int k, int beam) {
+  if (!ix) return fail(SVF_E_INVAL, "null index");
+  if (nq < 0 || nq > INT32_MAX) return fail(SVF_E_INVAL, "nq out of range");
+  if (k < 1) return fail(SVF_E_INVAL, "k must be >= 1");
+  if (beam < k) return fail(SVF_E_INVAL, "beam must be >= k");
+  if (beam > kMaxBeam) return fail(SVF_E_INVAL, "beam must be <= 512");
+  return SVF_OK;
+}
+
+bool all_finite(const float* p, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+void finish_search_stats(svf_index* ix) {
+  unsigned long long tot[2] = {0, 0};
+  if (ix->s_tot.p && hipMemcpy(tot, ix->s_tot.p, sizeof tot, hipMemcpyDeviceToHost) == hipSuccess) {
+    ix->st.last_n_dist = (int64_t)tot[0];
+    ix->st.last_n_exp = (int64_t)tot[1];
+  }
+  ix->st.last_search_ms = elapsed(ix->ev0, ix->ev1);
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char* svf_last_error(void) { return g_err.c_str(); }
+
+int svf_create(int32_t dim, int32_t degree, int32_t metric, svf_index** out) {
+  if (!out) return fail(SVF_E_INVAL, "null output handle");
+  *out = nullptr;
+  if (dim < 1 || dim > 1024) return fail(SVF_E_INVAL, "dim must be in [1, 1024]");
+  if (degree < 1 || degree > 128) return fail(SVF_E_INVAL, "degree must be in [1, 128]");
+  if (metric != SVF_METRIC_L2 && metric != SVF_METRIC_IP) return fail(SVF_E_INVAL, "unknown metric");
+  svf_index* ix = new (std::nothrow) svf_index();
+  if (!ix) return fail(SVF_E_NOMEM, "host allocation");
+  ix->dim = dim;
+  ix->R = degree;
+  ix->metric = metric;
+  ix->stride = round_up(dim, 8);
+  hipError_t e;
+  if ((e = hipGetDevice(&ix->device)) != hipSuccess ||
+      (e = hipStreamCreateWithFlags(&ix->stream, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipEventCreate(&ix->ev0)) != hipSuccess || (e = hipEventCreate(&ix->ev1)) != hipSuccess) {
+    delete ix;
+    return hip_fail(e, "device setup");
+  }
+  int rc = reserve(ix, 1024);
+  if (rc) {
+    svf_destroy(ix);
+    return rc;
+  }
+  *out = ix;
+  return SVF_OK;
+}
+
+int svf_destroy(svf_index* ix) {
+  if (!ix) return SVF_OK;
+  {
+    std::lock_guard<std::mutex> g(ix->mu);
+    if (ix->stream) (void)hipStreamSynchronize(ix->stream);
+    if (ix->vec32) (void)hipFree(ix->vec32);
+    if (ix->veclp) (void)hipFree(ix->veclp);
+    if (ix->graph) (void)hipFree(ix->graph);
+    if (ix->edge_d) (void)hipFree(ix->edge_d);
+    if (ix->alive) (void)hipFree(ix->alive);
+    if (ix->ev0) (void)hipEventDestroy(ix->ev0);
+    if (ix->ev1) (void)hipEventDestroy(ix->ev1);
+    if (ix->stream) (void)hipStreamDestroy(ix->stream);
+  }
+  delete ix;
+  return SVF_OK;
+}
+
+int svf_set_option(svf_index* ix, const char* key, double v) {
+  if (!ix || !key) return fail(SVF_E_INVAL, "null argument");
+  std::lock_guard<std::mutex> g(ix->mu);
+  auto is_int = [](double x) { return std::floor(x) == x; };
+  std::string k(key);
+  svf::Options& o = ix->opt;
+  if (!std::isfinite(v)) return fail(SVF_E_INVAL, "option value must be finite");
+  if (k == "seed") {
+    if (v < 0 || !is_int(v)) return fail(SVF_E_INVAL, "seed must be a non-negative integer");
+    o.seed = (uint64_t)v;
+  } else if (k == "beam_insert") {
+    if (!is_int(v) || v < ix->R || v > kMaxBeam) return fail(SVF_E_INVAL, "beam_insert in [degree, 512]");
+    o.beam_insert = (int)v;
+  } else if (k == "entry_samples") {
+    if (!is_int(v) || v < 0 || v > kMaxEntries) return fail(SVF_E_INVAL, "entry_samples in [0, 1024]");
+    o.entry_samples = (int)v;
+  } else if (k == "max_iters") {
+    if (!is_int(v) || v < 0 || v > 1e9) return fail(SVF_E_INVAL, "max_iters >= 0");
+    o.max_iters = (int)v;
+  } else if (k == "visited_slots") {
+    int t = (int)v;
+    if (!is_int(v) || t < 256 || t > 8192 || (t & (t - 1))) return fail(SVF_E_INVAL, "visited_slots: power of two in [256, 8192]");
+    o.visited_slots = t;
+  } else if (k == "repair_c") {
+    if (!is_int(v) || v < 1 || v > 16 || v > ix->R) return fail(SVF_E_INVAL, "repair_c in [1, min(16, degree)]");
+    o.repair_c = (int)v;
+  } else if (k == "prune_cap") {
+    if (!is_int(v) || (v != 0 && (v < ix->R || v > 1024))) return fail(SVF_E_INVAL, "prune_cap 0 or in [degree, 1024]");
+    o.prune_cap = (int)v;
+  } else if (k == "consolidate_frac") {
+    if (v <= 0 || v > 1) return fail(SVF_E_INVAL, "consolidate_frac in (0, 1]");
+    o.consolidate_frac = v;
+  } else if (k == "insert_batch_max") {
+    if (!is_int(v) || v < 1 || v > (1 << 20)) return fail(SVF_E_INVAL, "insert_batch_max in [1, 2^20]");
+    o.insert_batch_max = (int)v;
+  } else if (k == "precision") {
+    if (v != 0 && v != 1 && v != 2) return fail(SVF_E_INVAL, "precision 0 (FP32), 1 (FP16) or 2 (BF16)");
+    o.precision = (int)v;
+    return sync_lowp(ix);
+  } else if (k == "rerank") {
+    if (v != 0 && v != 1) return fail(SVF_E_INVAL, "rerank 0 or 1");
+    o.rerank = (int)v;
+  } else {
+    return fail(SVF_E_INVAL, "unknown option " + k);
+  }
+  return SVF_OK;
+}
+
+int svf_get_option(const svf_index* ix, const char* key, double* out) {
+  if (!ix || !key || !out) return fail(SVF_E_INVAL, "null argument");
+  std::string k(key);
+  const svf::Options& o = ix->opt;
+  if (k == "seed") *out = (double)o.seed;
+  else if (k == "beam_insert") *out = beam_insert(ix);
+  else if (k == "entry_samples") *out = o.entry_samples;
+  else if (k == "max_iters") *out = o.max_iters;
+  else if (k == "visited_slots") *out = o.visited_slots;
+  else if (k == "repair_c") *out = o.repair_c;
+  else if (k == "prune_cap") *out = prune_cap(ix);
+  else if (k == "consolidate_frac") *out = o.consolidate_frac;
+  else if (k == "insert_batch_max") *out = o.insert_batch_max;
+  else if (k == "precision") *out = o.precision;
+  else if (k == "rerank") *out = o.rerank;
+  else return fail(SVF_E_INVAL, "unknown option " + k);
+  return SVF_OK;
+}
+
+int svf_insert_dev(svf_index* ix, const float* d_vecs, int64_t n, int32_t* d_out_ids, void* stream) {
+  if (!ix || (n > 0 && !d_vecs)) return fail(SVF_E_INVAL, "null argument");
+  if (n < 0) return fail(SVF_E_INVAL, "n < 0");
+  std::lock_guard<std::mutex> g(ix->mu);
+  if (stream) CK(hipStreamSynchronize((hipStream_t)stream));
+  return insert_stream(ix, d_vecs, n, d_out_ids, nullptr);
+}
+
+int svf_insert(svf_index* ix, const float* vecs, int64_t n, int32_t* out_ids) {
+  if (!ix || (n > 0 && !vecs)) return fail(SVF_E_INVAL, "null argument");
+  if (n < 0) return fail(SVF_E_INVAL, "n < 0");
+  if (n == 0) return SVF_OK;
+  if (!all_finite(vecs, n * ix->dim)) return fail(SVF_E_INVAL, "non-finite vector value");
+  std::lock_guard<std::mutex> g(ix->mu);
+  float* d;
+  int rc = scratch(ix->s_q, (size_t)n * ix->dim, &d);
+  if (rc) return rc;
+  CK(hipMemcpyAsync(d, vecs, (size_t)n * ix->dim * 4, hipMemcpyHostToDevice, ix->stream));
+  return insert_stream(ix, d, n, nullptr, out_ids);
+}
+
+int svf_build(svf_index* ix, const float* vecs, int64_t n) {
+  if (!ix || (n > 0 && !vecs)) return fail(SVF_E_INVAL, "null argument");
+  if (n < 1) return fail(SVF_E_INVAL, "n must be >= 1");
+  if (ix->n_slots != 0) return fail(SVF_E_INVAL, "build needs an empty index");
+  if (!all_finite(vecs, n * ix->dim)) return fail(SVF_E_INVAL, "non-finite vector value");
+  std::lock_guard<std::mutex> g(ix->mu);
+  int rc = reserve(ix, n);
+  if (rc) return rc;
+  float* d;
+  if ((rc = scratch(ix->s_q, (size_t)n * ix->dim, &d))) return rc;
+  CK(hipMemcpyAsync(d, vecs, (size_t)n * ix->dim * 4, hipMemcpyHostToDevice, ix->stream));
+  return insert_stream(ix, d, n, nullptr, nullptr);
+}
+
+int svf_delete(svf_index* ix, const int32_t* ids, int64_t n) {
+  if (!ix || (n > 0 && !ids)) return fail(SVF_E_INVAL, "null argument");
+  if (n < 0) return fail(SVF_E_INVAL, "n < 0");
+  std::lock_guard<std::mutex> g(ix->mu);
+  for (int64_t i = 0; i < n; ++i)
+    if (ids[i] < 0 || ids[i] >= ix->n_slots) return fail(SVF_E_NOTFOUND, "id out of range");
+  if (n == 0) return SVF_OK;
+  hipStream_t st = ix->stream;
+  int32_t *d, *cnt;
+  int rc;
+  if ((rc = scratch(ix->s_misc[9], n, &d)) || (rc = scratch(ix->s_tot, 2, &cnt))) return rc;
+  CK(hipEventRecord(ix->ev0, st));
+  CK(hipMemcpyAsync(d, ids, n * 4, hipMemcpyHostToDevice, st));
+  CK(svf::launch_fill_u32(cnt, 1, 0u, st));
+  CK(svf::launch_mark_deleted(d, n, ix->alive, cnt, st));
+  int32_t newly = 0;
+  CK(hipMemcpyAsync(&newly, cnt, 4, hipMemcpyDeviceToHost, st));
+  CK(hipEventRecord(ix->ev1, st));
+  CK(hipStreamSynchronize(st));
+  ix->st.del_mark_ms = elapsed(ix->ev0, ix->ev1);
+  if (ix->alive_at_consolidate == 0) ix->alive_at_consolidate = ix->n_alive;
+  ix->n_alive -= newly;
+  ix->deleted_since += newly;
+  if (newly == 0) return SVF_OK;
+  if ((double)ix->deleted_since >= ix->opt.consolidate_frac * (double)ix->alive_at_consolidate) {
+    rc = repair(ix, 1);
+    ix->deleted_since = 0;
+    ix->alive_at_consolidate = ix->n_alive;
+  } else {
+    rc = repair(ix, 0);
+  }
+  return rc;
+}
+
+int svf_consolidate(svf_index* ix) {
+  if (!ix) return fail(SVF_E_INVAL, "null index");
+  std::lock_guard<std::mutex> g(ix->mu);
+  int rc = repair(ix, 1);
+  ix->deleted_since = 0;
+  ix->alive_at_consolidate = ix->n_alive;
+  return rc;
+}
+
+int svf_search_dev(svf_index* ix, const float* d_queries, int64_t nq, int32_t k, int32_t beam,
+                   int32_t* d_out_ids, float* d_out_dists, int32_t* d_n_dist, int32_t* d_n_exp,
+                   void* stream) {
+  int rc = check_search_args(ix, nq, k, beam);
+  if (rc) return rc;
+  if (nq > 0 && (!d_queries || !d_out_ids || !d_out_dists)) return fail(SVF_E_INVAL, "null buffer");
+  std::lock_guard<std::mutex> g(ix->mu);
+  hipStream_t st = stream ? (hipStream_t)stream : ix->stream;
+  return search_impl(ix, d_queries, nq, k, beam, d_out_ids, d_out_dists, d_n_dist, d_n_exp, st);
+}
+
+int svf_search(svf_index* ix, const float* queries, int64_t nq, int32_t k, int32_t beam,
+               int32_t* out_ids, float* out_dists) {
+  int rc = check_search_args(ix, nq, k, beam);
+  if (rc) return rc;
+  if (nq == 0) return SVF_OK;
+  if (!queries || !out_ids || !out_dists) return fail(SVF_E_INVAL, "null buffer");
+  if (!all_finite(queries, nq * ix->dim)) return fail(SVF_E_INVAL, "non-finite query value");
+  std::lock_guard<std::mutex> g(ix->mu);
+  hipStream_t st = ix->stream;
+  float *dq, *dd;
+  int32_t* di;
+  if ((rc = scratch(ix->s_q, (size_t)nq * ix->dim, &dq)) || (rc = scratch(ix->s_ids, (size_t)nq * k, &di)) ||
+      (rc = scratch(ix->s_d, (size_t)nq * k, &dd)))
+    return rc;
+  CK(hipMemcpyAsync(dq, queries, (size_t)nq * ix->dim * 4, hipMemcpyHostToDevice, st));
+  rc = search_impl(ix, dq, nq, k, beam, di, dd, nullptr, nullptr, st);
+  if (rc) return rc;
+  CK(hipMemcpyAsync(out_ids, di, (size_t)nq * k * 4, hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(out_dists, dd, (size_t)nq * k * 4, hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  finish_search_stats(ix);
+  return SVF_OK;
+}
+
+int svf_stats_get(const svf_index* cix, svf_stats* out) {
+  if (!cix || !out) return fail(SVF_E_INVAL, "null argument");
+  svf_index* ix = const_cast<svf_index*>(cix);
+  std::lock_guard<std::mutex> g(ix->mu);
+  (void)hipDeviceSynchronize();
+  finish_search_stats(ix);
+  ix->st.n_slots = ix->n_slots;
+  ix->st.n_alive = ix->n_alive;
+  ix->st.capacity = ix->cap;
+  ix->st.device_bytes = ix->cap * (ix->stride * (4 + (ix->veclp_prec ? 2 : 0)) + ix->R * 8 + 8) + ix->cap / 8;
+  *out = ix->st;
+  return SVF_OK;
+}
+
+int svf_export_graph(const svf_index* cix, int32_t* rows, float* edge_d, uint8_t* alive, int64_t cap_slots) {
+  if (!cix) return fail(SVF_E_INVAL, "null index");
+  svf_index* ix = const_cast<svf_index*>(cix);
+  std::lock_guard<std::mutex> g(ix->mu);
+  if (cap_slots < ix->n_slots) return fail(SVF_E_INVAL, "cap_slots < n_slots");
+  const int64_t n = ix->n_slots;
+  CK(hipStreamSynchronize(ix->stream));
+  if (rows && n) CK(hipMemcpy(rows, ix->graph, n * ix->R * 4, hipMemcpyDeviceToHost));
+  if (edge_d && n) CK(hipMemcpy(edge_d, ix->edge_d, n * ix->R * 4, hipMemcpyDeviceToHost));
+  if (alive && n) {
+    std::vector<uint32_t> bits((n + 31) / 32);
+    CK(hipMemcpy(bits.data(), ix->alive, bits.size() * 4, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < n; ++i) alive[i] = (bits[i >> 5] >> (i & 31)) & 1u;
+  }
+  return SVF_OK;
+}
+
+int svf_import_graph(svf_index* ix, const float* vecs, int64_t n, const int32_t* rows,
+                     const float* edge_d, const uint8_t* alive) {
+  if (!ix || (n > 0 && (!vecs || !rows || !edge_d || !alive))) return fail(SVF_E_INVAL, "null argument");
+  if (n < 0) return fail(SVF_E_INVAL, "n < 0");
+  std::lock_guard<std::mutex> g(ix->mu);
+  if (ix->n_slots != 0) return fail(SVF_E_INVAL, "import needs an empty index");
+  if (!all_finite(vecs, n * ix->dim)) return fail(SVF_E_INVAL, "non-finite vector value");
+  for (int64_t i = 0; i < n * ix->R; ++i)
+    if (rows[i] < -1 || rows[i] >= n) return fail(SVF_E_INVAL, "row entry out of range");
+  int rc = reserve(ix, std::max<int64_t>(n, 1));
+  if (rc) return rc;
+  hipStream_t st = ix->stream;
+  float* d;
+  if ((rc = scratch(ix->s_q, (size_t)std::max<int64_t>(n, 1) * ix->dim, &d))) return rc;
+  CK(hipMemcpyAsync(d, vecs, n * ix->dim * 4, hipMemcpyHostToDevice, st));
+  rc = store_rows(ix, d, n, 0, st);
+  if (rc) return rc;
+  CK(hipMemcpyAsync(ix->graph, rows, n * ix->R * 4, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(ix->edge_d, edge_d, n * ix->R * 4, hipMemcpyHostToDevice, st));
+  std::vector<uint32_t> bits((n + 31) / 32 + 1, 0u);
+  int64_t na = 0;
+  for (int64_t i = 0; i < n; ++i)
+    if (alive[i]) { bits[i >> 5] |= 1u << (i & 31); ++na; }
+  CK(hipMemcpyAsync(ix->alive, bits.data(), ((n + 31) / 32) * 4, hipMemcpyHostToDevice, st));
+  CK(hipStreamSynchronize(st));
+  ix->n_slots = n;
+  ix->n_alive = na;
+  return SVF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+// Host-side state of one index handle.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <string>
+
+#include "../../include/svf.h"
+
+namespace svf {
+
+// A device allocation that only grows.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  // Make at least `need` bytes available; old contents are not kept.
+  hipError_t ensure(size_t need) {
+    if (need <= bytes && p) return hipSuccess;
+    release();
+    size_t b = need < 256 ? 256 : need;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) { p = nullptr; return e; }
+    bytes = b;
+    return hipSuccess;
+  }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+struct Options {
+  uint64_t seed = 0;
+  int beam_insert = 0;        // 0: 2 * degree
+  int entry_samples = 0;
+  int max_iters = 0;
+  int visited_slots = 2048;
+  int repair_c = 8;
+  int prune_cap = 0;
+  double consolidate_frac = 0.2;
+  int insert_batch_max = 10000;
+  int precision = 0;
+  int rerank = 1;
+};
+
+}  // namespace svf
+
+struct svf_index {
+  int dim = 0, R = 0, metric = 0;
+  int64_t stride = 0;                // stored row length in elements (multiple of 8)
+  int64_t cap = 0, n_slots = 0, n_alive = 0;
+  int device = 0;
+  // device-resident state
+  float* vec32 = nullptr;            // cap x stride FP32
+  void* veclp = nullptr;             // cap x stride FP16/BF16 (reduced-precision traversal)
+  int veclp_prec = 0;
+  int32_t* graph = nullptr;          // cap x R
+  float* edge_d = nullptr;           // cap x R
+  uint32_t* alive = nullptr;         // ceil(cap/32) words
+  svf::Options opt;
+  int64_t deleted_since = 0, alive_at_consolidate = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::mutex mu;
+  // scratch
+  svf::DevBuf s_q, s_qkey, s_ids, s_d, s_pool, s_tot, s_misc[12];
+  svf_stats st{};
+};

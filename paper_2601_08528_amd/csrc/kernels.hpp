@@ -1,0 +1,118 @@
+// Launch interfaces of the library's HIP kernels (host side).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace svf {
+
+struct SearchArgs {
+  // index snapshot
+  const void* vec;          // traversal store: FP32 / FP16 / BF16, n x stride
+  const float* vec32;       // exact FP32 store (re-scoring), n x stride
+  int64_t stride;           // elements per stored row (multiple of 8)
+  int dim;
+  const int32_t* graph;     // n x R ids
+  int R;
+  const uint32_t* alive;    // deletion bitset (1 = alive)
+  int32_t n_slots;          // ids in [0, n_slots) exist in the snapshot
+  int32_t n_alive;
+  int metric;               // 0 = squared L2, 1 = -inner product
+  // search parameters
+  int L, L_pow2, k, E, max_iters, T, rerank;
+  // queries
+  const float* queries;     // FP32 rows, qstride apart
+  int64_t qstride;
+  const int32_t* qids;      // optional: query i is row qids[i] of `queries`
+  const uint64_t* qkey;     // per-query entry stream keys
+  int nq;
+  // outputs (any may be null)
+  int32_t* out_ids;         // nq x k
+  float* out_d;             // nq x k
+  uint64_t* out_pool;       // nq x L final pool keys (flag cleared)
+  int32_t* n_dist;
+  int32_t* n_exp;
+  unsigned long long* totals;  // [0] distances, [1] expansions
+};
+
+size_t search_lds_bytes(int L, int T);
+hipError_t launch_search(const SearchArgs& a, int precision, hipStream_t st);
+hipError_t launch_query_keys(const float* q, int64_t qstride, const int32_t* qids, int dim, int nq,
+                             uint64_t seed, uint64_t* out, hipStream_t st);
+
+// ---- index maintenance (update.hip) ----
+hipError_t launch_fill_u32(void* p, int64_t n, uint32_t v, hipStream_t st);
+hipError_t launch_store_lowp(const float* vec32, void* veclp, int64_t row0, int64_t nrows,
+                             int64_t stride, int precision, hipStream_t st);
+hipError_t launch_seed(const float* vec32, int64_t stride, int dim, int metric, int s0, int R,
+                       int32_t* graph, float* edge_d, hipStream_t st);
+hipError_t launch_set_alive(uint32_t* alive, int64_t lo, int64_t hi, hipStream_t st);
+
+struct PruneArgs {
+  const uint64_t* cand;     // lists of sorted keys, cstride apart (kKeyInf padded)
+  int cstride;
+  int cap;                  // at most this many candidates per list are pruned
+  const int32_t* graph;     // rows of ids < n_old
+  const int32_t* fwd;       // rows of ids >= n_old (staged rows of a batch)
+  int32_t n_old;
+  int R;
+  int32_t* out_ids;         // nlists x R
+  float* out_d;
+  int nlists;
+};
+size_t prune_lds_bytes(int cap);
+hipError_t launch_prune_lists(const PruneArgs& a, hipStream_t st);
+
+struct ReverseArgs {
+  const int32_t* fwd_ids;   // b x R forward rows of the batch
+  const float* fwd_d;
+  int b, R;
+  int32_t n0;               // first id of the batch
+  int32_t* tcount;          // per-vertex incoming counts (cap entries, zero outside a batch)
+  int32_t* tidx;            // per-vertex index into the target list
+  int32_t* tlist;           // targets (b x R max)
+  int32_t* n_targets;       // device counter
+  int32_t* off;             // n_targets + 1 offsets
+  int32_t* cursor;          // n_targets
+  uint64_t* inc;            // incoming keys grouped by target
+  const int32_t* graph;
+  const float* edge_d;
+  const uint32_t* alive;
+  int cap;
+  int32_t* trow;            // n_targets x R
+  float* trow_d;
+};
+hipError_t launch_reverse_count(const ReverseArgs& a, hipStream_t st);
+hipError_t launch_reverse_scan_scatter(const ReverseArgs& a, int n_targets, hipStream_t st);
+hipError_t launch_reverse_prune(const ReverseArgs& a, int n_targets, hipStream_t st);
+hipError_t launch_commit_batch(const ReverseArgs& a, int n_targets, int32_t* graph, float* edge_d,
+                               uint32_t* alive, hipStream_t st);
+
+struct RepairArgs {
+  const float* vec32;
+  int64_t stride;
+  int dim, metric, R;
+  const int32_t* graph;
+  const float* edge_d;
+  const uint32_t* alive;
+  int32_t n_slots;
+  int consolidate;          // 0: more than half deleted, c = repair_c; 1: any deleted, c = R
+  int c;
+  int cap;
+  int32_t* list;            // affected vertices
+  int32_t* n_list;          // device counter
+  uint64_t* cand;           // nlist x cap
+  int32_t* mcount;          // nlist
+  int32_t* topup;           // chunk-local indices needing a search top-up
+  int32_t* topup_v;         // their vertex ids
+  int32_t* n_topup;
+};
+hipError_t launch_mark_deleted(const int32_t* ids, int64_t n, uint32_t* alive, int32_t* newly,
+                               hipStream_t st);
+hipError_t launch_affected(const RepairArgs& a, hipStream_t st);
+hipError_t launch_repair_candidates(const RepairArgs& a, int first, int count, hipStream_t st);
+hipError_t launch_topup_merge(const RepairArgs& a, const uint64_t* pool, int L, int first,
+                              int ntop, hipStream_t st);
+hipError_t launch_commit_rows(const int32_t* list, int n, const int32_t* rows, const float* rows_d,
+                              int R, int32_t* graph, float* edge_d, hipStream_t st);
+
+}  // namespace svf

@@ -1,0 +1,639 @@
+// Index maintenance kernels: seed graph, insertion (Sec. 5.1) and deletion
+// with localized repair and consolidation (Sec. 5.2).
+//
+// Rank-based candidate reordering (Sec. 5.1) is computed without distance
+// evaluations.  For a vertex with candidates c_0..c_{m-1} in (d,id) order, the
+// wave builds an LDS map id -> position, scans the neighbour rows of every
+// candidate c_j with coalesced loads, and for each row entry that is a later
+// candidate c_i (i > j) adds one to its detour count with an LDS atomic.  The
+// R kept candidates are those of smallest (count, position): a histogram of
+// the counts gives the threshold count tau, then one ordered ballot pass keeps
+// every candidate below tau and the first ones equal to tau, and writes them
+// in position order, which is (d,id) order.
+//
+// Every batch reads one snapshot and writes staged rows; a commit kernel
+// copies them into the graph afterwards, so the result never depends on the
+// order in which waves run.
+#include "common.hpp"
+#include "kernels.hpp"
+#include "wave_ops.hpp"
+
+namespace svf {
+
+namespace {
+
+__device__ __forceinline__ int wave_incl_scan(int x) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    int t = __shfl_up(x, o);
+    if (lane >= o) x += t;
+  }
+  return x;
+}
+
+struct RowSource {
+  const int32_t* graph;
+  const int32_t* fwd;
+  int32_t n_old;
+  int R;
+  __device__ __forceinline__ const int32_t* row(int32_t id) const {
+    return id < n_old ? graph + (int64_t)id * R : fwd + (int64_t)(id - n_old) * R;
+  }
+};
+
+struct PruneLds {
+  uint32_t* mkey;   // S slots
+  uint32_t* mval;   // S slots
+  uint32_t* cnt;    // cap
+  uint32_t* hist;   // cap + 1
+  int S;
+};
+
+__device__ __forceinline__ int pow2_at_least(int x, int lo) {
+  int p = lo;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// Rank-based reordering of the m sorted candidate keys in LDS; writes R ids
+// and distances (INVALID / +inf padded) to out.
+__device__ void prune_core(const uint64_t* keys, int m, const RowSource& rs, int R, PruneLds& s,
+                           int32_t* __restrict__ out_ids, float* __restrict__ out_d) {
+  const int lane = lane_id();
+  int tau = 0, need = 0;
+  const bool full = m > R;
+  if (full) {
+    for (int i = lane; i < s.S; i += kWave) s.mkey[i] = kEmpty;
+    for (int i = lane; i <= m; i += kWave) { s.hist[i] = 0; if (i < m) s.cnt[i] = 0; }
+    __syncthreads();
+    const uint32_t mask = (uint32_t)s.S - 1u;
+    for (int i = lane; i < m; i += kWave) {
+      const uint32_t id = (uint32_t)key_id(keys[i]);
+      uint32_t sl = slot_hash(id, mask);
+      for (;;) {
+        uint32_t old = atomicCAS(&s.mkey[sl], kEmpty, id);
+        if (old == kEmpty) { s.mval[sl] = (uint32_t)i; break; }
+        sl = (sl + 1) & mask;
+      }
+    }
+    __syncthreads();
+    // detour counts: entry r of row(c_j) naming c_i with i > j
+    const int total = m * R;
+    for (int t = lane; t < total; t += kWave) {
+      const int j = t / R;
+      const int r = t - j * R;
+      const int32_t e = rs.row(key_id(keys[j]))[r];
+      if (e < 0) continue;
+      uint32_t sl = slot_hash((uint32_t)e, mask);
+      for (;;) {
+        const uint32_t k = s.mkey[sl];
+        if (k == (uint32_t)e) {
+          const int i = (int)s.mval[sl];
+          if (i > j) atomicAdd(&s.cnt[i], 1u);
+          break;
+        }
+        if (k == kEmpty) break;
+        sl = (sl + 1) & mask;
+      }
+    }
+    __syncthreads();
+    for (int i = lane; i < m; i += kWave) atomicAdd(&s.hist[s.cnt[i]], 1u);
+    __syncthreads();
+    // tau: smallest count value whose cumulative frequency reaches R
+    int run = 0;
+    tau = -1;
+    for (int c0 = 0; c0 < m && tau < 0; c0 += kWave) {
+      const int h = c0 + lane < m ? (int)s.hist[c0 + lane] : 0;
+      const int incl = wave_incl_scan(h);
+      const uint64_t hit = ballot(run + incl >= R);
+      if (hit) {
+        const int l = __ffsll((unsigned long long)hit) - 1;
+        const int incl_l = __shfl(incl, l);
+        const int h_l = __shfl(h, l);
+        tau = c0 + l;
+        need = R - (run + incl_l - h_l);
+      }
+      run += __shfl(incl, kWave - 1);
+    }
+  }
+  // keep: all below tau, then the first `need` equal to tau, in position order
+  int outpos = 0, eq_seen = 0;
+  for (int c0 = 0; c0 < m; c0 += kWave) {
+    const int i = c0 + lane;
+    const bool on = i < m;
+    bool sel = on;
+    if (full) {
+      const int c = on ? (int)s.cnt[i] : 0x7fffffff;
+      const bool eq = on && c == tau;
+      const uint64_t eb = ballot(eq);
+      sel = on && (c < tau || (eq && eq_seen + lanes_below(eb) < need));
+      eq_seen += popc64(eb);
+    }
+    const uint64_t sb = ballot(sel);
+    if (sel) {
+      const int p = outpos + lanes_below(sb);
+      const uint64_t k = keys[i];
+      out_ids[p] = key_id(k);
+      out_d[p] = key_dist(k);
+    }
+    outpos += popc64(sb);
+  }
+  for (int i = outpos + lane; i < R; i += kWave) { out_ids[i] = -1; out_d[i] = __builtin_inff(); }
+  __syncthreads();
+}
+
+__device__ __forceinline__ PruneLds carve_prune_lds(unsigned char* p, int cap) {
+  PruneLds s;
+  s.S = pow2_at_least(2 * cap, 64);
+  s.mkey = reinterpret_cast<uint32_t*>(p);
+  s.mval = s.mkey + s.S;
+  s.cnt = s.mval + s.S;
+  s.hist = s.cnt + cap;
+  return s;
+}
+size_t prune_scratch_bytes(int cap) {
+  int S = 64;
+  while (S < 2 * cap) S <<= 1;
+  return (size_t)S * 8 + (size_t)cap * 4 + (size_t)(cap + 1) * 4 + 16;
+}
+
+// Number of non-padding keys in a sorted LDS list of n keys.
+__device__ __forceinline__ int count_keys(const uint64_t* a, int n) {
+  int m = 0;
+  for (int c0 = 0; c0 < n; c0 += kWave) {
+    const int i = c0 + lane_id();
+    m += popc64(ballot(i < n && a[i] != kKeyInf));
+  }
+  return m;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+__global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+hipError_t launch_fill_u32(void* p, int64_t n, uint32_t v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)blocks), dim3(256), 0, st,
+                     static_cast<uint32_t*>(p), n, v);
+  return hipGetLastError();
+}
+
+// FP32 rows -> FP16 / BF16 rows (round to nearest even).
+__global__ void store_lowp_kernel(const float* __restrict__ src, uint16_t* __restrict__ dst,
+                                  int64_t n, int precision) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float x = src[i];
+    dst[i] = precision == 1 ? __half_as_ushort(__float2half_rn(x)) : f32_to_bf16_rne(x);
+  }
+}
+hipError_t launch_store_lowp(const float* vec32, void* veclp, int64_t row0, int64_t nrows,
+                             int64_t stride, int precision, hipStream_t st) {
+  const int64_t n = nrows * stride;
+  if (n <= 0 || precision == 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(store_lowp_kernel, dim3((unsigned)blocks), dim3(256), 0, st,
+                     vec32 + row0 * stride, static_cast<uint16_t*>(veclp) + row0 * stride, n,
+                     precision);
+  return hipGetLastError();
+}
+
+__global__ void set_alive_kernel(uint32_t* alive, int64_t lo, int64_t hi) {
+  const int64_t i = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < hi) atomicOr(&alive[i >> 5], 1u << (i & 31));
+}
+hipError_t launch_set_alive(uint32_t* alive, int64_t lo, int64_t hi, hipStream_t st) {
+  if (hi <= lo) return hipSuccess;
+  hipLaunchKernelGGL(set_alive_kernel, dim3((unsigned)((hi - lo + 255) / 256)), dim3(256), 0, st,
+                     alive, lo, hi);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Seed graph: with every neighbour list empty all detour counts are 0, so each
+// seed vertex keeps its R nearest other seed vertices.
+template <int NC>
+__global__ __launch_bounds__(64) void seed_kernel(const float* __restrict__ vec32, int64_t stride,
+                                                  int dim, int metric, int s0, int R,
+                                                  int32_t* graph, float* edge_d) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int v = blockIdx.x;
+  const int lane = lane_id();
+  const int n = pow2_at_least(s0, 64);
+  uint64_t* keys = reinterpret_cast<uint64_t*>(smem);
+  int32_t* cid = reinterpret_cast<int32_t*>(keys + n);
+  QuerySlice<float, NC> q;
+  q.load(vec32 + (int64_t)v * stride, dim, lane % QuerySlice<float, NC>::kLanesPerVec);
+  for (int c0 = 0; c0 < n; c0 += kWave) {
+    const int u = c0 + lane;
+    const bool on = u < s0 && u != v;
+    const uint64_t ob = ballot(on);
+    if (on) cid[lanes_below(ob)] = u;
+    __syncthreads();
+    const uint64_t k = gather_keys<float, NC>(q, vec32, stride, cid, popc64(ob), metric);
+    keys[c0 + lane] = k;
+    __syncthreads();
+  }
+  wave_sort_lds(keys, n);
+  for (int r = lane; r < R; r += kWave) {
+    const uint64_t k = r < s0 - 1 ? keys[r] : kKeyInf;
+    graph[(int64_t)v * R + r] = key_id(k);
+    edge_d[(int64_t)v * R + r] = key_dist(k);
+  }
+}
+hipError_t launch_seed(const float* vec32, int64_t stride, int dim, int metric, int s0, int R,
+                       int32_t* graph, float* edge_d, hipStream_t st) {
+  if (s0 <= 0) return hipSuccess;
+  int n = 64;
+  while (n < s0) n <<= 1;
+  const size_t lds = (size_t)n * 8 + kWave * 4;
+  const int chunks = (int)((stride + 127) / 128);
+  dim3 g(s0), b(kWave);
+  switch (chunks <= 1 ? 1 : chunks <= 2 ? 2 : chunks <= 4 ? 4 : 8) {
+    case 1: hipLaunchKernelGGL(seed_kernel<1>, g, b, lds, st, vec32, stride, dim, metric, s0, R, graph, edge_d); break;
+    case 2: hipLaunchKernelGGL(seed_kernel<2>, g, b, lds, st, vec32, stride, dim, metric, s0, R, graph, edge_d); break;
+    case 4: hipLaunchKernelGGL(seed_kernel<4>, g, b, lds, st, vec32, stride, dim, metric, s0, R, graph, edge_d); break;
+    default: hipLaunchKernelGGL(seed_kernel<8>, g, b, lds, st, vec32, stride, dim, metric, s0, R, graph, edge_d); break;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Prune of candidate lists held in global memory (forward rows of a batch,
+// repaired rows).
+__global__ __launch_bounds__(64) void prune_lists_kernel(PruneArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int li = blockIdx.x;
+  if (li >= a.nlists) return;
+  const int lane = lane_id();
+  const int cap = a.cap < a.cstride ? a.cap : a.cstride;
+  uint64_t* keys = reinterpret_cast<uint64_t*>(smem);
+  PruneLds s = carve_prune_lds(reinterpret_cast<unsigned char*>(keys + cap), cap);
+  const uint64_t* src = a.cand + (int64_t)li * a.cstride;
+  for (int i = lane; i < cap; i += kWave) keys[i] = src[i];
+  __syncthreads();
+  const int m = count_keys(keys, cap);
+  RowSource rs{a.graph, a.fwd, a.n_old, a.R};
+  prune_core(keys, m, rs, a.R, s, a.out_ids + (int64_t)li * a.R, a.out_d + (int64_t)li * a.R);
+}
+size_t prune_lds_bytes(int cap) { return (size_t)cap * 8 + prune_scratch_bytes(cap); }
+hipError_t launch_prune_lists(const PruneArgs& a, hipStream_t st) {
+  if (a.nlists <= 0) return hipSuccess;
+  const int cap = a.cap < a.cstride ? a.cap : a.cstride;
+  hipLaunchKernelGGL(prune_lists_kernel, dim3(a.nlists), dim3(kWave), prune_lds_bytes(cap), st, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Reverse edges (Sec. 5.1): group (target, new vertex, distance) by target.
+__global__ void reverse_count_kernel(ReverseArgs a) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= (int64_t)a.b * a.R) return;
+  const int32_t t = a.fwd_ids[i];
+  if (t < 0) return;
+  if (atomicAdd(&a.tcount[t], 1) == 0) {
+    const int k = atomicAdd(a.n_targets, 1);
+    a.tlist[k] = t;
+    a.tidx[t] = k;
+  }
+}
+hipError_t launch_reverse_count(const ReverseArgs& a, hipStream_t st) {
+  const int64_t n = (int64_t)a.b * a.R;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(reverse_count_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// Exclusive scan of the per-target counts in one workgroup of 1024 threads,
+// each owning a contiguous run of targets.
+__global__ __launch_bounds__(1024) void reverse_scan_kernel(ReverseArgs a, int n) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x;
+  const int per = (n + 1023) / 1024;
+  const int lo = t * per, hi = lo + per < n ? lo + per : n;
+  int s = 0;
+  for (int i = lo; i < hi; ++i) s += a.tcount[a.tlist[i]];
+  part[t] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    int v = t >= o ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = t == 0 ? 0 : part[t - 1];
+  for (int i = lo; i < hi; ++i) {
+    a.off[i] = run;
+    a.cursor[i] = 0;
+    run += a.tcount[a.tlist[i]];
+  }
+  if (t == 1023) a.off[n] = part[1023];
+}
+__global__ void reverse_scatter_kernel(ReverseArgs a) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= (int64_t)a.b * a.R) return;
+  const int32_t t = a.fwd_ids[i];
+  if (t < 0) return;
+  const int k = a.tidx[t];
+  const int pos = a.off[k] + atomicAdd(&a.cursor[k], 1);
+  a.inc[pos] = make_key(a.fwd_d[i], a.n0 + (int32_t)(i / a.R));
+}
+hipError_t launch_reverse_scan_scatter(const ReverseArgs& a, int n_targets, hipStream_t st) {
+  if (n_targets <= 0) return hipSuccess;
+  hipLaunchKernelGGL(reverse_scan_kernel, dim3(1), dim3(1024), 0, st, a, n_targets);
+  const int64_t n = (int64_t)a.b * a.R;
+  hipLaunchKernelGGL(reverse_scatter_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// One wave per target: candidates = alive row entries (stored distances) and
+// the new vertices pointing at it, the `cap` smallest in (d,id) order, pruned
+// against the pre-batch rows of old vertices and the forward rows of new ones.
+__global__ __launch_bounds__(64) void reverse_prune_kernel(ReverseArgs a, int n_targets) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int k = blockIdx.x;
+  if (k >= n_targets) return;
+  const int lane = lane_id();
+  const int cap = a.cap;
+  WaveCtx w;
+  w.pool = reinterpret_cast<uint64_t*>(smem);
+  w.next = w.pool + cap;
+  w.kept = w.next + cap;
+  w.L = cap;
+  PruneLds s = carve_prune_lds(reinterpret_cast<unsigned char*>(w.kept + kWave), cap);
+  for (int i = lane; i < 2 * cap; i += kWave) w.pool[i] = kKeyInf;
+  __syncthreads();
+  const int32_t t = a.tlist[k];
+  for (int r0 = 0; r0 < a.R; r0 += kWave) {
+    const int r = r0 + lane;
+    uint64_t key = kKeyInf;
+    if (r < a.R) {
+      const int32_t u = a.graph[(int64_t)t * a.R + r];
+      if (u >= 0 && alive_bit(a.alive, u)) key = make_key(a.edge_d[(int64_t)t * a.R + r], u);
+    }
+    key = wave_sort64(key);
+    merge_into_pool(w, key);
+  }
+  const int lo = a.off[k], hi = a.off[k + 1];
+  for (int c0 = lo; c0 < hi; c0 += kWave) {
+    const int i = c0 + lane;
+    uint64_t key = i < hi ? a.inc[i] : kKeyInf;
+    key = wave_sort64(key);
+    merge_into_pool(w, key);
+  }
+  const int m = count_keys(w.pool, cap);
+  RowSource rs{a.graph, a.fwd_ids, a.n0, a.R};
+  prune_core(w.pool, m, rs, a.R, s, a.trow + (int64_t)k * a.R, a.trow_d + (int64_t)k * a.R);
+}
+hipError_t launch_reverse_prune(const ReverseArgs& a, int n_targets, hipStream_t st) {
+  if (n_targets <= 0) return hipSuccess;
+  const size_t lds = (size_t)(2 * a.cap + kWave) * 8 + prune_scratch_bytes(a.cap);
+  hipLaunchKernelGGL(reverse_prune_kernel, dim3(n_targets), dim3(kWave), lds, st, a, n_targets);
+  return hipGetLastError();
+}
+
+// Commit of a batch: target rows, forward rows of the new ids, alive bits,
+// and reset of the per-target counts.
+__global__ void commit_targets_kernel(ReverseArgs a, int n_targets, int32_t* graph, float* edge_d) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n_targets * a.R) return;
+  const int k = (int)(i / a.R), r = (int)(i - (int64_t)k * a.R);
+  const int32_t t = a.tlist[k];
+  graph[(int64_t)t * a.R + r] = a.trow[i];
+  edge_d[(int64_t)t * a.R + r] = a.trow_d[i];
+  if (r == 0) a.tcount[t] = 0;
+}
+__global__ void commit_new_kernel(ReverseArgs a, int32_t* graph, float* edge_d, uint32_t* alive) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= (int64_t)a.b * a.R) return;
+  graph[(int64_t)a.n0 * a.R + i] = a.fwd_ids[i];
+  edge_d[(int64_t)a.n0 * a.R + i] = a.fwd_d[i];
+  if (i % a.R == 0) {
+    const int64_t id = a.n0 + i / a.R;
+    atomicOr(&alive[id >> 5], 1u << (id & 31));
+  }
+}
+hipError_t launch_commit_batch(const ReverseArgs& a, int n_targets, int32_t* graph, float* edge_d,
+                               uint32_t* alive, hipStream_t st) {
+  if (n_targets > 0) {
+    const int64_t n = (int64_t)n_targets * a.R;
+    hipLaunchKernelGGL(commit_targets_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       a, n_targets, graph, edge_d);
+  }
+  const int64_t n = (int64_t)a.b * a.R;
+  if (n > 0)
+    hipLaunchKernelGGL(commit_new_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a,
+                       graph, edge_d, alive);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Deletion (Sec. 5.2).
+__global__ void mark_deleted_kernel(const int32_t* ids, int64_t n, uint32_t* alive, int32_t* newly) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t id = ids[i];
+  const uint32_t bit = 1u << (id & 31);
+  const uint32_t old = atomicAnd(&alive[(uint32_t)id >> 5], ~bit);
+  if (old & bit) atomicAdd(newly, 1);
+}
+hipError_t launch_mark_deleted(const int32_t* ids, int64_t n, uint32_t* alive, int32_t* newly,
+                               hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mark_deleted_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ids,
+                     n, alive, newly);
+  return hipGetLastError();
+}
+
+// Affected vertices: alive rows with more than half of their valid entries
+// deleted (repair) or with any deleted entry (consolidation).  One wave per
+// row, grid-stride.
+__global__ __launch_bounds__(256) void affected_kernel(RepairArgs a) {
+  const int lane = lane_id();
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+  for (int64_t v = wave; v < a.n_slots; v += nwaves) {
+    if (!alive_bit(a.alive, (int32_t)v)) continue;
+    int nv = 0, nd = 0;
+    for (int r0 = 0; r0 < a.R; r0 += kWave) {
+      const int r = r0 + lane;
+      const int32_t e = r < a.R ? a.graph[v * a.R + r] : -1;
+      const bool valid = e >= 0;
+      nv += popc64(ballot(valid));
+      nd += popc64(ballot(valid && !alive_bit(a.alive, e)));
+    }
+    const bool aff = a.consolidate ? nd >= 1 : 2 * nd > nv;
+    if (aff && lane == 0) a.list[atomicAdd(a.n_list, 1)] = (int32_t)v;
+  }
+}
+hipError_t launch_affected(const RepairArgs& a, hipStream_t st) {
+  if (a.n_slots <= 0) return hipSuccess;
+  int64_t blocks = ((int64_t)a.n_slots + 3) / 4;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(affected_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// Candidates of an affected vertex v: its alive neighbours, then for each
+// deleted neighbour p (row order) the first c entries of p's row that are
+// alive, not v and not yet candidates.  All distances are evaluated against
+// v's own vector.  The `cap` smallest keys are kept; a list shorter than R is
+// queued for a search top-up.
+template <int NC>
+__global__ __launch_bounds__(64) void repair_candidates_kernel(RepairArgs a, int first, int count) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int li = blockIdx.x;
+  if (li >= count) return;
+  const int lane = lane_id();
+  const int cap = a.cap;
+  const int32_t v = a.list[first + li];
+  WaveCtx w;
+  w.pool = reinterpret_cast<uint64_t*>(smem);
+  w.next = w.pool + cap;
+  w.kept = w.next + cap;
+  w.cid = reinterpret_cast<int32_t*>(w.kept + kWave);
+  w.vis = reinterpret_cast<uint32_t*>(w.cid + kWave);
+  w.L = cap;
+  const bool exact = a.c < a.R;       // "first c" needs exact membership
+  int H = 64;
+  if (exact) while (H < 2 * a.R * (1 + a.c)) H <<= 1;
+  w.tmask = (uint32_t)H - 1u;
+  for (int i = lane; i < 2 * cap; i += kWave) w.pool[i] = kKeyInf;
+  if (exact) for (int i = lane; i < H; i += kWave) w.vis[i] = kEmpty;
+  QuerySlice<float, NC> q;
+  q.load(a.vec32 + (int64_t)v * a.stride, a.dim, lane % QuerySlice<float, NC>::kLanesPerVec);
+  __syncthreads();
+  const int32_t* rowv = a.graph + (int64_t)v * a.R;
+  // alive neighbours
+  for (int r0 = 0; r0 < a.R; r0 += kWave) {
+    const int r = r0 + lane;
+    const int32_t u = r < a.R ? rowv[r] : -1;
+    const bool ok = u >= 0 && alive_bit(a.alive, u);
+    if (ok && exact) vis_insert_exact(w.vis, w.tmask, u);
+    const uint64_t ob = ballot(ok);
+    if (ok) w.cid[lanes_below(ob)] = u;
+    __syncthreads();
+    uint64_t k = gather_keys<float, NC>(q, a.vec32, a.stride, w.cid, popc64(ob), a.metric);
+    k = wave_sort64(k);
+    merge_into_pool(w, k);
+  }
+  // entries of deleted neighbours
+  for (int r = 0; r < a.R; ++r) {
+    const int32_t p = rowv[r];
+    if (p < 0 || alive_bit(a.alive, p)) continue;
+    const int32_t* rowp = a.graph + (int64_t)p * a.R;
+    int taken = 0;
+    for (int e0 = 0; e0 < a.R && (!exact || taken < a.c); e0 += kWave) {
+      const int e = e0 + lane;
+      const int32_t u = e < a.R ? rowp[e] : -1;
+      bool ok = u >= 0 && u != v && alive_bit(a.alive, u);
+      if (exact) {
+        if (ok) ok = !vis_contains_exact(w.vis, w.tmask, u);
+        const uint64_t cb = ballot(ok);
+        ok = ok && taken + lanes_below(cb) < a.c;
+        __syncthreads();
+        if (ok) vis_insert_exact(w.vis, w.tmask, u);
+      }
+      const uint64_t ob = ballot(ok);
+      if (ok) w.cid[lanes_below(ob)] = u;
+      taken += popc64(ob);
+      __syncthreads();
+      if (ob == 0) continue;
+      uint64_t k = gather_keys<float, NC>(q, a.vec32, a.stride, w.cid, popc64(ob), a.metric);
+      k = wave_sort64(k);
+      merge_into_pool(w, k);
+    }
+  }
+  const int m = count_keys(w.pool, cap);
+  for (int i = lane; i < cap; i += kWave) a.cand[(int64_t)li * cap + i] = w.pool[i];
+  if (lane == 0) {
+    a.mcount[li] = m;
+    if (m < a.R) {
+      const int t = atomicAdd(a.n_topup, 1);
+      a.topup[t] = li;
+      a.topup_v[t] = v;
+    }
+  }
+}
+hipError_t launch_repair_candidates(const RepairArgs& a, int first, int count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  int H = 64;
+  if (a.c < a.R) while (H < 2 * a.R * (1 + a.c)) H <<= 1;
+  const size_t lds = (size_t)(2 * a.cap + kWave) * 8 + kWave * 4 + (size_t)H * 4;
+  const int chunks = (int)((a.stride + 127) / 128);
+  dim3 g(count), b(kWave);
+  switch (chunks <= 1 ? 1 : chunks <= 2 ? 2 : chunks <= 4 ? 4 : 8) {
+    case 1: hipLaunchKernelGGL(repair_candidates_kernel<1>, g, b, lds, st, a, first, count); break;
+    case 2: hipLaunchKernelGGL(repair_candidates_kernel<2>, g, b, lds, st, a, first, count); break;
+    case 4: hipLaunchKernelGGL(repair_candidates_kernel<4>, g, b, lds, st, a, first, count); break;
+    default: hipLaunchKernelGGL(repair_candidates_kernel<8>, g, b, lds, st, a, first, count); break;
+  }
+  return hipGetLastError();
+}
+
+// Merge the search pool of a topped-up vertex (its own id excluded) into its
+// candidate list.
+__global__ __launch_bounds__(64) void topup_merge_kernel(RepairArgs a, const uint64_t* pool, int L,
+                                                         int ntop) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int ti = blockIdx.x;
+  if (ti >= ntop) return;
+  const int lane = lane_id();
+  const int cap = a.cap;
+  const int li = a.topup[ti];
+  const int32_t v = a.topup_v[ti];
+  WaveCtx w;
+  w.pool = reinterpret_cast<uint64_t*>(smem);
+  w.next = w.pool + cap;
+  w.kept = w.next + cap;
+  w.L = cap;
+  uint64_t* dst = a.cand + (int64_t)li * cap;
+  for (int i = lane; i < cap; i += kWave) { w.pool[i] = dst[i]; w.next[i] = kKeyInf; }
+  __syncthreads();
+  for (int c0 = 0; c0 < L; c0 += kWave) {
+    const int i = c0 + lane;
+    uint64_t k = i < L ? pool[(int64_t)ti * L + i] : kKeyInf;
+    if (key_id(k) == v) k = kKeyInf;
+    k = wave_sort64(k);
+    merge_into_pool(w, k);
+  }
+  const int m = count_keys(w.pool, cap);
+  for (int i = lane; i < cap; i += kWave) dst[i] = w.pool[i];
+  if (lane == 0) a.mcount[li] = m;
+}
+hipError_t launch_topup_merge(const RepairArgs& a, const uint64_t* pool, int L, int first,
+                              int ntop, hipStream_t st) {
+  (void)first;
+  if (ntop <= 0) return hipSuccess;
+  const size_t lds = (size_t)(2 * a.cap + kWave) * 8;
+  hipLaunchKernelGGL(topup_merge_kernel, dim3(ntop), dim3(kWave), lds, st, a, pool, L, ntop);
+  return hipGetLastError();
+}
+
+__global__ void commit_rows_kernel(const int32_t* list, int n, const int32_t* rows,
+                                   const float* rows_d, int R, int32_t* graph, float* edge_d) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n * R) return;
+  const int k = (int)(i / R), r = (int)(i - (int64_t)k * R);
+  const int64_t v = list[k];
+  graph[v * R + r] = rows[i];
+  edge_d[v * R + r] = rows_d[i];
+}
+hipError_t launch_commit_rows(const int32_t* list, int n, const int32_t* rows, const float* rows_d,
+                              int R, int32_t* graph, float* edge_d, hipStream_t st) {
+  const int64_t t = (int64_t)n * R;
+  if (t <= 0) return hipSuccess;
+  hipLaunchKernelGGL(commit_rows_kernel, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st, list,
+                     n, rows, rows_d, R, graph, edge_d);
+  return hipGetLastError();
+}
+
+}  // namespace svf

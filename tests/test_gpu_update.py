@@ -1,0 +1,123 @@
+"""Insertion, deletion, repair and consolidation on the GPU against the
+FP64 oracle.  On integer-valued data every distance is exact, so the whole
+graph (ids and edge distances) must be identical after every operation."""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2601_08528_amd as svf
+from paper_2601_08528_amd import datagen
+from gpu_util import gpu_from_oracle, oracle_index
+
+pytestmark = pytest.mark.gpu
+
+
+def assert_same_graph(g, oix, check_dist=True):
+    gr, ge, ga = g.export_graph()
+    orows, oe, oa = oix.export()
+    np.testing.assert_array_equal(ga, oa)
+    np.testing.assert_array_equal(gr, orows)
+    if check_dist:
+        np.testing.assert_array_equal(ge.astype(np.float64), oe)
+
+
+@pytest.mark.parametrize("dim,R,metric,n", [(128, 16, O.L2, 3000), (72, 24, O.IP, 2000)])
+def test_build_bit_exact_integer(dim, R, metric, n):
+    base, _ = datagen.gmm_uint8_valued(301, n, 1, dim, 12)
+    oix = oracle_index(base, R, metric=metric, seed=7, batch_max=400)
+    g = svf.Index(dim, R, metric, seed=7, insert_batch_max=400)
+    g.build(base)
+    assert_same_graph(g, oix)
+
+
+def test_insert_and_delete_sequence_bit_exact():
+    base, q = datagen.gmm_uint8_valued(302, 4200, 50, 64, 10)
+    R = 20
+    oix = oracle_index(base[:3000], R, seed=9, batch_max=500)
+    g = gpu_from_oracle(oix, base[:3000], seed=9, insert_batch_max=500)
+    rng = np.random.Generator(np.random.Philox(3))
+    # interleave inserts and deletes: batches of new vectors, random live ids
+    pos = 3000
+    for step in range(4):
+        new = base[pos:pos + 300]
+        pos += 300
+        assert g.insert(new).tolist() == oix.insert(new).tolist()
+        assert_same_graph(g, oix)
+        _, _, alive = oix.export()
+        victims = rng.choice(np.nonzero(alive)[0], 120, replace=False).astype(np.int32)
+        g.delete(victims)
+        assert oix.delete(victims) == 0
+        assert_same_graph(g, oix)
+        st = g.stats()
+        assert st["n_alive"] == oix.n_alive
+    oi, od, _ = oix.search(q, 10, 40)
+    gi, gd = g.search(q, 10, 40)
+    np.testing.assert_array_equal(gi, oi)
+    g.consolidate()
+    oix.consolidate()
+    assert_same_graph(g, oix)
+    gr, ge, ga = g.export_graph()
+    for v in np.nonzero(ga)[0]:
+        r = gr[v][gr[v] >= 0]
+        assert ga[r].all() and v not in r and len(set(r.tolist())) == len(r)
+
+
+def test_repair_topup_path_bit_exact():
+    """Heavy deletion: many rows fall short of R candidates and take the
+    search top-up; consolidation threshold set out of reach first."""
+    base, _ = datagen.gmm_uint8_valued(303, 1500, 1, 32, 6)
+    R = 12
+    oix = oracle_index(base, R, seed=4, batch_max=300, consolidate_frac=0.95, repair_c=2)
+    g = gpu_from_oracle(oix, base, seed=4, insert_batch_max=300, consolidate_frac=0.95, repair_c=2)
+    victims = np.arange(0, 1500, 3, dtype=np.int32)
+    g.delete(victims)
+    oix.delete(victims)
+    assert_same_graph(g, oix)
+    assert g.stats()["last_repaired"] > 0
+
+
+def test_delete_errors_leave_index_unchanged():
+    base, _ = datagen.gmm_uint8_valued(304, 600, 1, 16, 3)
+    g = svf.Index(16, 8, svf.METRIC_L2)
+    g.build(base)
+    before = g.export_graph()
+    with pytest.raises(svf.SvfError) as e:
+        g.delete([3, 600])
+    assert e.value.code == svf.E_NOTFOUND
+    after = g.export_graph()
+    for a, b in zip(before, after):
+        np.testing.assert_array_equal(a, b)
+    g.delete([3, 3, 4])
+    g.delete([3])
+    assert g.stats()["n_alive"] == 598
+
+
+def test_reduced_precision_exact_on_integer_data():
+    base, q = datagen.gmm_uint8_valued(305, 3000, 80, 128, 10)
+    oix = oracle_index(base, 24, seed=2)
+    ref_i, ref_d, _ = oix.search(q, 10, 48)
+    for prec in (svf.PREC_FP16, svf.PREC_BF16):
+        g = gpu_from_oracle(oix, base, seed=2, precision=prec)
+        gi, gd = g.search(q, 10, 48)
+        np.testing.assert_array_equal(gi, ref_i)
+        np.testing.assert_array_equal(gd.astype(np.float64), ref_d)
+
+
+def test_build_float_recall_and_invariants():
+    base, q = datagen.workload_small_float()
+    g = svf.Index(128, 32, svf.METRIC_L2, seed=1)
+    g.build(base)
+    rows, ed, alive = g.export_graph()
+    assert ((rows >= 0).sum(1) == 32).all()
+    assert (rows != np.arange(len(rows))[:, None]).all()
+    srt = np.sort(rows, axis=1)
+    assert (np.diff(srt, axis=1) != 0).all()
+    oix = O.OracleIndex(128, 32, O.L2)
+    oix.import_state(base, rows, ed.astype(np.float64), alive)
+    for v in range(0, 10_000, 997):
+        for r in range(32):
+            ex = oix.dist_ids(v, rows[v, r])
+            assert abs(ed[v, r] - ex) <= 1e-5 * ex
+    gi, gd = g.search(q, 10, 64)
+    gt_i, gt_d = O.bruteforce(base, q, 10)
+    assert O.recall_at_k(gi, oix.query_dists(q, gi), gt_d, 10) >= 0.95
