@@ -83,7 +83,8 @@ int svf_destroy(svf_index *ix);
  *   beam_insert     candidate pool size of the insertion search (degree..512; 2*degree)
  *   entry_samples   random entry points per query, 0 = the pool size (0..1024; 0)
  *   max_iters       cap on expansions per query, 0 = none (>= 0; 0)
- *   visited_slots   LDS visited-table slots per query, power of two (256..8192; 2048)
+ *   visited_slots   LDS visited-table slots per query, power of two (256..8192; 4096)
+ *   visited_compact 16-bit visited tags in 4-way sets when the ids fit (0/1; 1)
  *   repair_c        out-neighbours taken from each deleted neighbour (1..min(16, degree); 8)
  *   prune_cap       longest candidate list given to the prune, 0 = max(4*degree, beam_insert)
  *   consolidate_frac deleted fraction that triggers consolidation ((0,1]; 0.2)

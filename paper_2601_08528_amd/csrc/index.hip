@@ -182,6 +182,7 @@ void set_beam(svf::SearchArgs& a, const svf_index* ix, int L) {
   a.E = ix->opt.entry_samples > 0 ? ix->opt.entry_samples : L;
   a.T = visited_slots(ix, a.E);
   a.rerank = (ix->veclp_prec != 0 && ix->opt.rerank) ? 1 : 0;
+  a.vis_compact = ix->opt.visited_compact;
 }
 
 float elapsed(hipEvent_t a, hipEvent_t b) {
@@ -277,7 +278,7 @@ int insert_batch(svf_index* ix, const float* d_vecs, int64_t b, int32_t* d_out_i
     CK(hipMemcpyAsync(&n_targets, cnt, 4, hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
     if ((rc = scratch(ix->s_misc[4], n_targets + 1, &ra.off)) ||
-        (rc = scratch(ix->s_misc[5], n_targets + 1, &ra.cursor)) ||
+        (rc = scratch(ix->s_misc[5], (size_t)n_targets + 2 + n_targets / 1024 + 2, &ra.cursor)) ||
         (rc = scratch(ix->s_misc[6], npairs, &ra.inc)) ||
         (rc = scratch(ix->s_misc[7], (size_t)n_targets * R, &ra.trow)) ||
         (rc = scratch(ix->s_misc[8], (size_t)n_targets * R, &ra.trow_d)))
@@ -564,6 +565,9 @@ int svf_set_option(svf_index* ix, const char* key, double v) {
     int t = (int)v;
     if (!is_int(v) || t < 256 || t > 8192 || (t & (t - 1))) return fail(SVF_E_INVAL, "visited_slots: power of two in [256, 8192]");
     o.visited_slots = t;
+  } else if (k == "visited_compact") {
+    if (v != 0 && v != 1) return fail(SVF_E_INVAL, "visited_compact 0 or 1");
+    o.visited_compact = (int)v;
   } else if (k == "repair_c") {
     if (!is_int(v) || v < 1 || v > 16 || v > ix->R) return fail(SVF_E_INVAL, "repair_c in [1, min(16, degree)]");
     o.repair_c = (int)v;
@@ -598,6 +602,7 @@ int svf_get_option(const svf_index* ix, const char* key, double* out) {
   else if (k == "entry_samples") *out = o.entry_samples;
   else if (k == "max_iters") *out = o.max_iters;
   else if (k == "visited_slots") *out = o.visited_slots;
+  else if (k == "visited_compact") *out = o.visited_compact;
   else if (k == "repair_c") *out = o.repair_c;
   else if (k == "prune_cap") *out = prune_cap(ix);
   else if (k == "consolidate_frac") *out = o.consolidate_frac;

@@ -38,7 +38,8 @@ struct Options {
   int beam_insert = 0;        // 0: 2 * degree
   int entry_samples = 0;
   int max_iters = 0;
-  int visited_slots = 2048;
+  int visited_slots = 4096;
+  int visited_compact = 1;
   int repair_c = 8;
   int prune_cap = 0;
   double consolidate_frac = 0.2;

@@ -19,6 +19,8 @@ struct SearchArgs {
   int metric;               // 0 = squared L2, 1 = -inner product
   // search parameters
   int L, L_pow2, k, E, max_iters, T, rerank;
+  int vis_compact;          // allow 16-bit visited tags when ids fit
+  int id_bits;              // set by the launcher
   // queries
   const float* queries;     // FP32 rows, qstride apart
   int64_t qstride;
@@ -34,7 +36,6 @@ struct SearchArgs {
   unsigned long long* totals;  // [0] distances, [1] expansions
 };
 
-size_t search_lds_bytes(int L, int T);
 hipError_t launch_search(const SearchArgs& a, int precision, hipStream_t st);
 hipError_t launch_query_keys(const float* q, int64_t qstride, const int32_t* qids, int dim, int nq,
                              uint64_t seed, uint64_t* out, hipStream_t st);

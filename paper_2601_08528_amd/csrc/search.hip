@@ -29,7 +29,7 @@ namespace svf {
 
 
 // ---------------------------------------------------------------------------
-template <typename VT, int NC>
+template <typename VT, int NC, typename VIS>
 __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int qi = blockIdx.x;
@@ -41,11 +41,11 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
   w.next = w.pool + Lp;
   w.kept = w.next + Lp;
   w.cid = reinterpret_cast<int32_t*>(w.kept + kWave);
-  w.vis = reinterpret_cast<uint32_t*>(w.cid + kWave);
-  w.tmask = (uint32_t)a.T - 1u;
+  void* vis_mem = reinterpret_cast<void*>(w.cid + kWave);
   w.L = a.L;
+  VIS vis;
+  vis.setup(vis_mem, a.T, a.id_bits);
 
-  for (int i = lane; i < a.T; i += kWave) w.vis[i] = kEmpty;
   for (int i = lane; i < 2 * Lp; i += kWave) w.pool[i] = kKeyInf;
 
   using QS = QuerySlice<VT, NC>;
@@ -58,38 +58,51 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
   int n_dist = 0, n_exp = 0;
 
   // ---- InitCandidatePool: random entries from the query's own stream -------
-  const uint64_t skey = a.qkey[qi];
-  const int E = a.E;
-  const int want = E < a.n_alive ? E : a.n_alive;
-  const int attempts = 8 * E + 64;
-  int got = 0;
-  for (int a0 = 0; a0 < attempts && got < want; a0 += kWave) {
-    const int j = a0 + lane;
-    int32_t id = -1;
-    bool valid = false;
-    if (j < attempts) {
-      id = range_reduce(splitmix64_at(skey, (uint64_t)j), (uint32_t)a.n_slots);
-      valid = alive_bit(a.alive, id);
+  // The first min(E, n_alive) distinct alive ids in attempt order; the ids
+  // accepted so far sit in an exact list that borrows the visited-table LDS.
+  {
+    int32_t* acc = static_cast<int32_t*>(vis_mem);
+    const uint64_t skey = a.qkey[qi];
+    const int E = a.E;
+    const int want = E < a.n_alive ? E : a.n_alive;
+    const int attempts = 8 * E + 64;
+    int got = 0;
+    for (int a0 = 0; a0 < attempts && got < want; a0 += kWave) {
+      const int j = a0 + lane;
+      int32_t id = -1;
+      bool valid = false;
+      if (j < attempts) {
+        id = range_reduce(splitmix64_at(skey, (uint64_t)j), (uint32_t)a.n_slots);
+        valid = alive_bit(a.alive, id);
+      }
+      bool dup = false;
+      for (int t = 0; t < kWave; ++t) {
+        const int32_t o = __shfl(id, t);
+        dup |= (t < lane) && (o == id);
+      }
+      for (int i = 0; i < got; ++i) dup |= acc[i] == id;
+      const bool cand = valid && !dup;
+      const uint64_t cb = ballot(cand);
+      const int r = lanes_below(cb);
+      const int room = want - got;
+      const bool take = cand && r < room;
+      __syncthreads();
+      if (take) { acc[got + r] = id; w.cid[r] = id; }
+      const int nt = popc64(cb) < room ? popc64(cb) : room;
+      got += nt;
+      __syncthreads();
+      uint64_t k = gather_keys<VT, NC>(qs, base, a.stride, w.cid, nt, a.metric);
+      n_dist += nt;
+      sort_merge(w, k);
     }
-    bool dup = false;
-    for (int t = 0; t < kWave; ++t) {
-      const int32_t o = __shfl(id, t);
-      dup |= (t < lane) && (o == id);
+    __syncthreads();
+    vis.clear(a.T);
+    __syncthreads();
+    for (int i = lane; i < a.L; i += kWave) {
+      const int32_t id = key_id(w.pool[i]);
+      if (id >= 0) (void)vis.test_and_set(id);
     }
-    const bool cand = valid && !dup && !vis_contains_exact(w.vis, w.tmask, id);
-    const uint64_t cb = ballot(cand);
-    const int r = lanes_below(cb);
-    const int room = want - got;
-    const bool take = cand && r < room;
     __syncthreads();
-    if (take) { vis_insert_exact(w.vis, w.tmask, id); w.cid[r] = id; }
-    const int nt = popc64(cb) < room ? popc64(cb) : room;
-    got += nt;
-    __syncthreads();
-    uint64_t k = gather_keys<VT, NC>(qs, base, a.stride, w.cid, nt, a.metric);
-    n_dist += nt;
-    k = wave_sort64(k);
-    merge_into_pool(w, k);
   }
 
   // ---- repeat: nearest unexpanded -> neighbours -> distances -> update ------
@@ -111,19 +124,22 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
     const int32_t* row = a.graph + (int64_t)parent * a.R;
     for (int r0 = 0; r0 < a.R; r0 += kWave) {
       const int rr = r0 + lane;
-      int32_t nb = rr < a.R ? row[rr] : -1;
-      bool ok = nb >= 0 && nb < a.n_slots && alive_bit(a.alive, nb);
+      const int32_t nb = rr < a.R ? row[rr] : -1;
+      bool ok = nb >= 0 && nb < a.n_slots;
       __syncthreads();
-      if (ok) ok = !vis_test_and_set(w.vis, w.tmask, nb);
+      if (ok) ok = !vis.test_and_set(nb);
       const uint64_t ob = ballot(ok);
       if (ok) w.cid[lanes_below(ob)] = nb;
       const int m = popc64(ob);
       __syncthreads();
       if (m == 0) continue;
+      // the deletion bits load while the vectors are gathered
+      const int32_t mine = lane < m ? w.cid[lane] : 0;
+      const uint32_t aword = a.alive[(uint32_t)mine >> 5];
       uint64_t k = gather_keys<VT, NC>(qs, base, a.stride, w.cid, m, a.metric);
+      if (lane < m && !((aword >> (mine & 31)) & 1u)) k = kKeyInf;
       n_dist += m;
-      k = wave_sort64(k);
-      merge_into_pool(w, k);
+      sort_merge(w, k);
     }
   }
 
@@ -194,37 +210,63 @@ __global__ void query_key_kernel(const float* __restrict__ q, int64_t qstride, c
 }
 
 // ---------------------------------------------------------------------------
-size_t search_lds_bytes(int L, int T) {
-  int Lp = 64;
-  while (Lp < L) Lp <<= 1;
-  return (size_t)2 * Lp * 8 + kWave * 8 + kWave * 4 + (size_t)T * 4;
+// Visited-table layout: 16-bit tags in 4-way sets when the ids fit (tag width
+// id_bits - log2(sets) <= 15), else 32-bit ids.
+static int id_bits_for(int32_t n_slots) {
+  int b = 1;
+  while (b < 31 && (1ll << b) < (long long)n_slots) ++b;
+  return b;
 }
+static bool use_assoc16(int32_t n_slots, int T) {
+  int set_bits = 0;
+  while ((1 << (set_bits + 1)) <= T / 4) ++set_bits;
+  int b = id_bits_for(n_slots);
+  if (b < set_bits + 1) b = set_bits + 1;
+  return b - set_bits <= 15;
+}
+static size_t vis_bytes(int T, bool assoc16) { return assoc16 ? (size_t)T * 2 : (size_t)T * 4; }
 
-template <typename VT>
-static hipError_t launch_vt(const SearchArgs& a, int nc, hipStream_t st) {
-  const size_t lds = search_lds_bytes(a.L, a.T);
+template <typename VT, typename VIS>
+static hipError_t launch_vt(const SearchArgs& a, int nc, size_t lds, hipStream_t st) {
   dim3 grid(a.nq), block(kWave);
   switch (nc) {
-    case 1: hipLaunchKernelGGL((search_kernel<VT, 1>), grid, block, lds, st, a); break;
-    case 2: hipLaunchKernelGGL((search_kernel<VT, 2>), grid, block, lds, st, a); break;
-    case 4: hipLaunchKernelGGL((search_kernel<VT, 4>), grid, block, lds, st, a); break;
-    case 8: hipLaunchKernelGGL((search_kernel<VT, 8>), grid, block, lds, st, a); break;
+    case 1: hipLaunchKernelGGL((search_kernel<VT, 1, VIS>), grid, block, lds, st, a); break;
+    case 2: hipLaunchKernelGGL((search_kernel<VT, 2, VIS>), grid, block, lds, st, a); break;
+    case 4: hipLaunchKernelGGL((search_kernel<VT, 4, VIS>), grid, block, lds, st, a); break;
+    case 8: hipLaunchKernelGGL((search_kernel<VT, 8, VIS>), grid, block, lds, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_search(const SearchArgs& a, int precision, hipStream_t st) {
-  if (a.nq <= 0) return hipSuccess;
+template <typename VIS>
+static hipError_t launch_vis(const SearchArgs& a, int precision, int nc, size_t lds, hipStream_t st) {
+  switch (precision) {
+    case 0: return launch_vt<float, VIS>(a, nc, lds, st);
+    case 1: return launch_vt<__half, VIS>(a, nc, lds, st);
+    case 2: return launch_vt<bf16_t, VIS>(a, nc, lds, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_search(const SearchArgs& in, int precision, hipStream_t st) {
+  if (in.nq <= 0) return hipSuccess;
+  SearchArgs a = in;
   const int chunks = (int)((a.stride + 127) / 128);
   const int nc = chunks <= 1 ? 1 : chunks <= 2 ? 2 : chunks <= 4 ? 4 : 8;
   if (chunks > 8) return hipErrorInvalidValue;
-  switch (precision) {
-    case 0: return launch_vt<float>(a, nc, st);
-    case 1: return launch_vt<__half>(a, nc, st);
-    case 2: return launch_vt<bf16_t>(a, nc, st);
-  }
-  return hipErrorInvalidValue;
+  const bool assoc = a.vis_compact && use_assoc16(a.n_slots, a.T);
+  // the entry phase keeps its exact list of accepted ids in the table's LDS
+  while (vis_bytes(a.T, assoc) < (size_t)a.E * 4) a.T <<= 1;
+  int set_bits = 0;
+  while ((1 << (set_bits + 1)) <= a.T / 4) ++set_bits;
+  a.id_bits = id_bits_for(a.n_slots);
+  if (a.id_bits < set_bits + 1) a.id_bits = set_bits + 1;
+  int Lp = 64;
+  while (Lp < a.L) Lp <<= 1;
+  const size_t lds = (size_t)2 * Lp * 8 + kWave * 8 + kWave * 4 + vis_bytes(a.T, assoc);
+  return assoc ? launch_vis<VisAssoc16>(a, precision, nc, lds, st)
+               : launch_vis<VisLinear32>(a, precision, nc, lds, st);
 }
 
 hipError_t launch_query_keys(const float* q, int64_t qstride, const int32_t* qids, int dim, int nq,

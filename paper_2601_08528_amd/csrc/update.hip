@@ -312,30 +312,57 @@ hipError_t launch_reverse_count(const ReverseArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Exclusive scan of the per-target counts in one workgroup of 1024 threads,
-// each owning a contiguous run of targets.
-__global__ __launch_bounds__(1024) void reverse_scan_kernel(ReverseArgs a, int n) {
-  __shared__ int part[1024];
-  const int t = threadIdx.x;
-  const int per = (n + 1023) / 1024;
-  const int lo = t * per, hi = lo + per < n ? lo + per : n;
-  int s = 0;
-  for (int i = lo; i < hi; ++i) s += a.tcount[a.tlist[i]];
-  part[t] = s;
+// Exclusive scan of the per-target counts: each 256-thread block scans 1024
+// targets and records its total; one block scans the totals; a last pass adds
+// the block offsets and resets the scatter cursors.
+constexpr int kScanBlock = 1024;
+__device__ __forceinline__ int block_excl_scan_256(int v, int* sh, int* total) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  int incl = wave_incl_scan(v);
+  if (lane == 63) sh[wv] = incl;
   __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    int v = t >= o ? part[t - o] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
+  int base = 0;
+  for (int i = 0; i < wv; ++i) base += sh[i];
+  *total = sh[0] + sh[1] + sh[2] + sh[3];
+  __syncthreads();
+  return base + incl - v;
+}
+__global__ __launch_bounds__(256) void scan_blocks_kernel(ReverseArgs a, int n, int32_t* bsum) {
+  __shared__ int sh[4];
+  const int b0 = blockIdx.x * kScanBlock + threadIdx.x * 4;
+  int v[4], s = 0;
+  for (int i = 0; i < 4; ++i) {
+    v[i] = b0 + i < n ? a.tcount[a.tlist[b0 + i]] : 0;
+    s += v[i];
   }
-  int run = t == 0 ? 0 : part[t - 1];
-  for (int i = lo; i < hi; ++i) {
-    a.off[i] = run;
+  int total;
+  int e = block_excl_scan_256(s, sh, &total);
+  for (int i = 0; i < 4; ++i) {
+    if (b0 + i < n) a.off[b0 + i] = e;
+    e += v[i];
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+__global__ __launch_bounds__(256) void scan_totals_kernel(int32_t* bsum, int nb) {
+  __shared__ int sh[4];
+  int run = 0;
+  for (int c0 = 0; c0 < nb; c0 += 256) {
+    const int i = c0 + threadIdx.x;
+    const int v = i < nb ? bsum[i] : 0;
+    int total;
+    const int e = block_excl_scan_256(v, sh, &total);
+    if (i < nb) bsum[i] = run + e;
+    run += total;
+  }
+  if (threadIdx.x == 0) bsum[nb] = run;
+}
+__global__ __launch_bounds__(256) void scan_add_kernel(ReverseArgs a, int n, const int32_t* bsum, int nb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    a.off[i] += bsum[i / kScanBlock];
     a.cursor[i] = 0;
-    run += a.tcount[a.tlist[i]];
   }
-  if (t == 1023) a.off[n] = part[1023];
+  if (i == 0) a.off[n] = bsum[nb];
 }
 __global__ void reverse_scatter_kernel(ReverseArgs a) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -348,7 +375,12 @@ __global__ void reverse_scatter_kernel(ReverseArgs a) {
 }
 hipError_t launch_reverse_scan_scatter(const ReverseArgs& a, int n_targets, hipStream_t st) {
   if (n_targets <= 0) return hipSuccess;
-  hipLaunchKernelGGL(reverse_scan_kernel, dim3(1), dim3(1024), 0, st, a, n_targets);
+  const int nb = (n_targets + kScanBlock - 1) / kScanBlock;
+  int32_t* bsum = a.cursor + n_targets + 1;   // nb + 1 scratch words after the cursors
+  hipLaunchKernelGGL(scan_blocks_kernel, dim3(nb), dim3(256), 0, st, a, n_targets, bsum);
+  hipLaunchKernelGGL(scan_totals_kernel, dim3(1), dim3(256), 0, st, bsum, nb);
+  hipLaunchKernelGGL(scan_add_kernel, dim3((n_targets + 255) / 256), dim3(256), 0, st, a, n_targets,
+                     (const int32_t*)bsum, nb);
   const int64_t n = (int64_t)a.b * a.R;
   hipLaunchKernelGGL(reverse_scatter_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
   return hipGetLastError();
@@ -379,15 +411,13 @@ __global__ __launch_bounds__(64) void reverse_prune_kernel(ReverseArgs a, int n_
       const int32_t u = a.graph[(int64_t)t * a.R + r];
       if (u >= 0 && alive_bit(a.alive, u)) key = make_key(a.edge_d[(int64_t)t * a.R + r], u);
     }
-    key = wave_sort64(key);
-    merge_into_pool(w, key);
+    sort_merge(w, key);
   }
   const int lo = a.off[k], hi = a.off[k + 1];
   for (int c0 = lo; c0 < hi; c0 += kWave) {
     const int i = c0 + lane;
     uint64_t key = i < hi ? a.inc[i] : kKeyInf;
-    key = wave_sort64(key);
-    merge_into_pool(w, key);
+    sort_merge(w, key);
   }
   const int m = count_keys(w.pool, cap);
   RowSource rs{a.graph, a.fwd_ids, a.n0, a.R};
@@ -522,8 +552,7 @@ __global__ __launch_bounds__(64) void repair_candidates_kernel(RepairArgs a, int
     if (ok) w.cid[lanes_below(ob)] = u;
     __syncthreads();
     uint64_t k = gather_keys<float, NC>(q, a.vec32, a.stride, w.cid, popc64(ob), a.metric);
-    k = wave_sort64(k);
-    merge_into_pool(w, k);
+    sort_merge(w, k);
   }
   // entries of deleted neighbours
   for (int r = 0; r < a.R; ++r) {
@@ -548,8 +577,7 @@ __global__ __launch_bounds__(64) void repair_candidates_kernel(RepairArgs a, int
       __syncthreads();
       if (ob == 0) continue;
       uint64_t k = gather_keys<float, NC>(q, a.vec32, a.stride, w.cid, popc64(ob), a.metric);
-      k = wave_sort64(k);
-      merge_into_pool(w, k);
+      sort_merge(w, k);
     }
   }
   const int m = count_keys(w.pool, cap);
@@ -602,8 +630,7 @@ __global__ __launch_bounds__(64) void topup_merge_kernel(RepairArgs a, const uin
     const int i = c0 + lane;
     uint64_t k = i < L ? pool[(int64_t)ti * L + i] : kKeyInf;
     if (key_id(k) == v) k = kKeyInf;
-    k = wave_sort64(k);
-    merge_into_pool(w, k);
+    sort_merge(w, k);
   }
   const int m = count_keys(w.pool, cap);
   for (int i = lane; i < cap; i += kWave) dst[i] = w.pool[i];

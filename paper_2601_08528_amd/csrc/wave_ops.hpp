@@ -7,7 +7,6 @@
 namespace svf {
 
 constexpr int kProbe = 8;
-constexpr int kUnroll = 4;   // vector loads in flight per lane group
 
 struct WaveCtx {
   uint64_t* pool;     // current pool (L keys)
@@ -58,6 +57,61 @@ __device__ __forceinline__ bool vis_test_and_set(uint32_t* vis, uint32_t mask, i
   return false;
 }
 
+// ---- visited tables ----------------------------------------------------------
+// Both policies answer "seen before?" without false positives and may forget
+// (the search result does not depend on forgetting, only the work does).
+//
+// VisLinear32: 32-bit ids, open addressing with a bounded probe run; on a
+// full run the first slot is overwritten.
+struct VisLinear32 {
+  uint32_t* t;
+  uint32_t mask;
+  __device__ static size_t bytes(int T) { return (size_t)T * 4; }
+  __device__ void setup(void* p, int T, int /*id_bits*/) {
+    t = static_cast<uint32_t*>(p);
+    mask = (uint32_t)T - 1u;
+  }
+  __device__ void clear(int T) {
+    for (int i = lane_id(); i < T; i += kWave) t[i] = kEmpty;
+  }
+  __device__ bool test_and_set(int32_t id) { return vis_test_and_set(t, mask, id); }
+};
+
+// VisAssoc16: ids below 2^B are scrambled by a bijection of [0, 2^B)
+// (multiplication by an odd constant modulo 2^B); the high bits pick a set of
+// four 16-bit ways, the low bits are the tag, so a tag match identifies the id
+// exactly.  Needs B - log2(sets) <= 15.  A set is read with one 64-bit load.
+struct VisAssoc16 {
+  uint64_t* sets;
+  uint32_t idmask;
+  int tag_bits;
+  __device__ void setup(void* p, int T, int id_bits) {
+    sets = static_cast<uint64_t*>(p);
+    const int set_bits = 31 - __clz(T / 4);
+    idmask = id_bits >= 32 ? 0xffffffffu : ((1u << id_bits) - 1u);
+    tag_bits = id_bits - set_bits;
+  }
+  __device__ void clear(int T) {
+    for (int i = lane_id(); i < T / 4; i += kWave) sets[i] = 0ull;
+  }
+  __device__ bool test_and_set(int32_t id) {
+    const uint32_t h = ((uint32_t)id * 0x9E3779B1u) & idmask;
+    const uint32_t set = h >> tag_bits;
+    const uint16_t tag = (uint16_t)((h & ((1u << tag_bits) - 1u)) + 1u);
+    const uint64_t w = sets[set];
+    int empty = -1;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint16_t v = (uint16_t)(w >> (16 * k));
+      if (v == tag) return true;
+      if (v == 0 && empty < 0) empty = k;
+    }
+    const int way = empty >= 0 ? empty : (int)(id & 3);
+    reinterpret_cast<uint16_t*>(&sets[set])[way] = tag;
+    return false;
+  }
+};
+
 // ---- distances --------------------------------------------------------------
 // Query slice held by each lane: NC chunks of 128 elements; within a chunk the
 // lane's group covers the vector with kPer16B elements per lane.
@@ -99,25 +153,63 @@ __device__ __forceinline__ float partial_dist(const QuerySlice<VT, NC>& qs, cons
   return acc;
 }
 
+// Sum of U per-lane partials across each group of LPV lanes, as a
+// reduce-scatter: every stage halves the values a lane holds and exchanges the
+// other half with its partner, so U sums need about U + log2(LPV) shuffles
+// instead of U * log2(LPV).  Each pairwise addition combines the same two
+// subtrees as a plain butterfly would, so every sum is bitwise the value a
+// butterfly reduction gives, whatever its position in the batch.  Lane l of a
+// group ends with the sum of step l / (LPV / U).
+template <int LPV, int U>
+__device__ __forceinline__ float reduce_scatter(float (&acc)[U]) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int s = 0; (U >> s) > 1; ++s) {
+    const int o = LPV >> (s + 1);
+    const int half = (U >> s) / 2;
+    const bool hi = (lane & o) != 0;
+#pragma unroll
+    for (int i = 0; i < half; ++i) {
+      const float send = hi ? acc[i] : acc[i + half];
+      const float keep = hi ? acc[i + half] : acc[i];
+      acc[i] = keep + __shfl_xor(send, o);
+    }
+  }
+  float r = acc[0];
+#pragma unroll
+  for (int o = LPV / U / 2; o >= 1; o >>= 1) r += __shfl_xor(r, o);
+  return r;
+}
+
+// Vector steps gathered per round trip: 32 vectors of one 128-element chunk
+// (16 x 16-byte loads per lane for FP32, 8 for 16-bit stores), fewer steps
+// for wider vectors.
+template <typename VT, int NC> struct GatherSteps {
+  static constexpr int base = sizeof(VT) == 4 ? 16 : 8;
+  static constexpr int value = base / NC < 2 ? 2 : base / NC;
+};
+
 // Distances of the m (<= 64) ids in cid[] to the query; returns, in lane j,
-// the key of cid[j] (kKeyInf for j >= m).
+// the key of cid[j] (kKeyInf for j >= m).  A step gathers VPW vectors, one per
+// group of LPV lanes; U steps are loaded before any is consumed.
 template <typename VT, int NC>
 __device__ inline uint64_t gather_keys(const QuerySlice<VT, NC>& qs, const VT* __restrict__ base,
-                                int64_t stride, const int32_t* cid, int m, int metric) {
+                                       int64_t stride, const int32_t* cid, int m, int metric) {
   using QS = QuerySlice<VT, NC>;
   constexpr int E = QS::E;
   constexpr int LPV = QS::kLanesPerVec;
   constexpr int VPW = QS::kVecPerWave;
+  constexpr int U = GatherSteps<VT, NC>::value < LPV ? GatherSteps<VT, NC>::value : LPV;
   const int lane = lane_id();
   const int sub = lane / LPV, sl = lane % LPV;
   float mine = 0.0f;
   const int steps = (m + VPW - 1) / VPW;
-  for (int s0 = 0; s0 < steps; s0 += kUnroll) {
-    uint4 w[kUnroll][NC];
+  for (int s0 = 0; s0 < steps; s0 += U) {
+    uint4 w[U][NC];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int j = (s0 + u) * VPW + sub;
-      const bool on = (s0 + u) < steps && j < m;
+      const bool on = j < m;
       const int32_t id = on ? cid[j] : 0;
       const VT* row = base + (int64_t)id * stride;
 #pragma unroll
@@ -129,15 +221,16 @@ __device__ inline uint64_t gather_keys(const QuerySlice<VT, NC>& qs, const VT* _
           w[u][c] = make_uint4(0, 0, 0, 0);
       }
     }
+    float acc[U];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      float acc = partial_dist<VT, NC>(qs, w[u], metric);
-#pragma unroll
-      for (int o = LPV / 2; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
-      // vector j = step * VPW + slot lives in lanes [slot*LPV, slot*LPV+LPV)
-      const float got = __shfl(acc, (lane % VPW) * LPV);
-      if (lane / VPW == s0 + u) mine = got;
-    }
+    for (int u = 0; u < U; ++u) acc[u] = partial_dist<VT, NC>(qs, w[u], metric);
+    const float r = reduce_scatter<LPV, U>(acc);
+    // lane j takes vector j = (s0 + u) * VPW + h from lane h * LPV + u * (LPV / U)
+    const int u = lane / VPW - s0;
+    const int h = lane % VPW;
+    const int src = h * LPV + ((u >= 0 && u < U) ? u : 0) * (LPV / U);
+    const float got = __shfl(r, src);
+    if (u >= 0 && u < U) mine = got;
   }
   if (lane >= m) return kKeyInf;
   const float d = metric == 0 ? mine : -mine;
@@ -186,5 +279,43 @@ __device__ inline void merge_into_pool(WaveCtx& w, uint64_t nk) {
   uint64_t* t = w.pool; w.pool = w.next; w.next = t;
 }
 
+
+// Ascending bitonic sort of the keys held by the first W lanes (W a power of
+// two); the other lanes must hold kKeyInf.
+__device__ __forceinline__ uint64_t wave_sort_width(uint64_t key, int W) {
+  const int lane = lane_id();
+  for (int k = 2; k <= W; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const uint64_t other = __shfl_xor(key, j);
+      const bool up = (lane & k) == 0;
+      const bool low = (lane & j) == 0;
+      const uint64_t mn = key < other ? key : other;
+      const uint64_t mx = key < other ? other : key;
+      key = (low == up) ? mn : mx;
+    }
+  }
+  return key;
+}
+
+// Merge one unsorted key per lane (kKeyInf = none) into the pool: keys that
+// cannot enter a full pool are dropped first, the rest are compacted and
+// sorted over the narrowest power-of-two width, then merged.
+__device__ inline void sort_merge(WaveCtx& w, uint64_t k) {
+  const int lane = lane_id();
+  const uint64_t last = w.pool[w.L - 1];
+  const bool live = k != kKeyInf && (last == kKeyInf || key_ord(k) < key_ord(last));
+  const uint64_t lb = ballot(live);
+  const int s = popc64(lb);
+  if (s == 0) return;
+  __syncthreads();
+  if (live) w.kept[lanes_below(lb)] = k;
+  __syncthreads();
+  uint64_t c = lane < s ? w.kept[lane] : kKeyInf;
+  int W = 1;
+  while (W < s) W <<= 1;
+  c = wave_sort_width(c, W);
+  __syncthreads();
+  merge_into_pool(w, c);
+}
 
 }  // namespace svf
