@@ -67,6 +67,11 @@ def lib():
         L.orc_splitmix64.argtypes = [u64, u64]
         L.orc_prune_explicit.argtypes = [i32, i32, vp, vp, vp, i64, vp, vp]
         L.orc_query_dists.argtypes = [vp, vp, i64, i32, vp, vp]
+        L.orc_search_listed.argtypes = [vp, vp, i64, i32, i32, vp, i32, vp, vp, vp, vp]
+        L.orc_search_trace.argtypes = [vp, vp, i64, i32, i32, vp, vp]
+        L.orc_mlp_forward.argtypes = [i32, i32, i32] + [vp] * 6 + [vp, i64, vp]
+        L.orc_mlp_loss_grad.restype = f64
+        L.orc_mlp_loss_grad.argtypes = [i32, i32, i32] + [vp] * 6 + [vp, vp, vp, i64, f64, f64] + [vp] * 6
         _lib = L
     return _lib
 
@@ -137,6 +142,29 @@ class OracleIndex:
         _check(lib().orc_search(self.h, _p(q), nq, k, beam, int(rerank), _p(ids), _p(d), _p(nd),
                                 _p(ne), _p(it), _p(mg), threads))
         return ids, d, dict(n_dist=nd, n_exp=ne, iters=it, margin=mg)
+
+    def search_listed(self, q, k, beam, entries, max_iters=None):
+        """Search whose pools start from given entry lists (nq x ecap, -1 pad)
+        with optional per-query expansion caps."""
+        q = np.ascontiguousarray(q, dtype=np.float32)
+        e = np.ascontiguousarray(entries, dtype=np.int32)
+        mi = None if max_iters is None else np.ascontiguousarray(max_iters, dtype=np.int32)
+        nq = q.shape[0]
+        ids = np.empty((nq, k), np.int32)
+        d = np.empty((nq, k), np.float64)
+        ne = np.empty(nq, np.int64)
+        _check(lib().orc_search_listed(self.h, _p(q), nq, k, beam, _p(e), e.shape[1], _p(mi),
+                                       _p(ids), _p(d), _p(ne)))
+        return ids, d, ne
+
+    def search_trace(self, q, k, beam):
+        """Plain search plus the expansion count after which the top-k stopped
+        changing."""
+        q = np.ascontiguousarray(q, dtype=np.float32)
+        ids = np.empty((q.shape[0], k), np.int32)
+        lc = np.empty(q.shape[0], np.int32)
+        _check(lib().orc_search_trace(self.h, _p(q), q.shape[0], k, beam, _p(ids), _p(lc)))
+        return ids, lc
 
     def export(self):
         n = self.n_slots
@@ -212,3 +240,29 @@ def recall_at_k(found_ids, exact_d, gt_d, k):
     kth = gt_d[:, k - 1:k]
     ok = (found_ids[:, :k] >= 0) & (exact_d[:, :k] <= kth)
     return ok.sum() / (found_ids.shape[0] * k)
+
+
+class MLP:
+    """FP64 reference of the entry/stop predictor din -> h -> h -> nc+1 (ReLU).
+    Weights are row-major (in x out) numpy float64 arrays."""
+
+    def __init__(self, w1, b1, w2, b2, w3, b3):
+        self.p = [np.ascontiguousarray(a, dtype=np.float64) for a in (w1, b1, w2, b2, w3, b3)]
+        self.din, self.h = self.p[0].shape
+        self.nc = self.p[4].shape[1] - 1
+
+    def forward(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        out = np.empty((x.shape[0], self.nc + 1))
+        lib().orc_mlp_forward(self.din, self.h, self.nc, *[_p(a) for a in self.p], _p(x), x.shape[0],
+                              _p(out))
+        return out
+
+    def loss_grad(self, x, label, log_stop, lam=0.1, delta=1.0):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        lab = np.ascontiguousarray(label, dtype=np.int32)
+        ls = np.ascontiguousarray(log_stop, dtype=np.float64)
+        g = [np.empty_like(a) for a in self.p]
+        loss = lib().orc_mlp_loss_grad(self.din, self.h, self.nc, *[_p(a) for a in self.p], _p(x),
+                                       _p(lab), _p(ls), x.shape[0], lam, delta, *[_p(a) for a in g])
+        return loss, g

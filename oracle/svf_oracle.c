@@ -319,10 +319,25 @@ typedef struct {
  * grid; qf are its FP32 words (for the entry hash).  n_slots and the alive
  * flags describe the snapshot searched.  Returns the final pool size, pool in
  * s->pool sorted by (d,id). */
+static int search_one_t(const orc_index *ix, int64_t n_slots, const float *qf, const double *q_lp,
+                        int L, int E, int width, int max_iters, scratch_t *s, qstats *st,
+                        double ip_scale, int ktrack, int32_t *last_change);
 static int search_one(const orc_index *ix, int64_t n_slots, const float *qf, const double *q_lp,
                       int L, int E, int width, int max_iters, scratch_t *s, qstats *st,
                       double ip_scale)
 {
+    return search_one_t(ix, n_slots, qf, q_lp, L, E, width, max_iters, s, st, ip_scale, 0, NULL);
+}
+
+/* ktrack > 0: *last_change receives the number of expansions done when the
+ * ids of the first ktrack pool entries last changed (0: never after the
+ * initial pool) -- the stopping step a predictor learns. */
+static int search_one_t(const orc_index *ix, int64_t n_slots, const float *qf, const double *q_lp,
+                        int L, int E, int width, int max_iters, scratch_t *s, qstats *st,
+                        double ip_scale, int ktrack, int32_t *last_change)
+{
+    int32_t topk_before[64];
+    int32_t lc = 0;
     const int d = ix->dim, R = ix->R;
     const double *V = ix->vec_lp;
     memset(st, 0, sizeof *st);
@@ -383,16 +398,28 @@ static int search_one(const orc_index *ix, int64_t n_slots, const float *qf, con
             }
         }
         ++st->iters;
+        int kt = ktrack < np ? ktrack : np;
+        if (kt > 64) kt = 64;
+        for (int t = 0; t < kt; ++t) topk_before[t] = s->pool[t].id;
         /* Update: merge and keep the L smallest keys. */
         memcpy(s->merged, s->pool, np * sizeof(pentry));
         memcpy(s->merged + np, s->fresh, nf * sizeof(pentry));
         int nm = np + nf;
         qsort(s->merged, nm, sizeof(pentry), cmp_pentry);
         if (nm > L) st->margin = fmin(st->margin, rel_gap(ix, s->merged[L - 1].d, s->merged[L].d, ip_scale));
-        np = nm < L ? nm : L;
-        memcpy(s->pool, s->merged, np * sizeof(pentry));
+        int np_new = nm < L ? nm : L;
+        memcpy(s->pool, s->merged, np_new * sizeof(pentry));
+        if (ktrack > 0) {
+            int kn = ktrack < np_new ? ktrack : np_new;
+            if (kn > 64) kn = 64;
+            int changed = kn != kt;
+            for (int t = 0; t < kn && !changed; ++t) changed = topk_before[t] != s->pool[t].id;
+            if (changed) lc = (int32_t)st->iters;
+        }
+        np = np_new;
     }
     unvisit_all(s);
+    if (last_change) *last_change = lc;
     return np;
 }
 
@@ -947,4 +974,214 @@ void orc_query_dists(const orc_index *ix, const float *q, int64_t nq, int k, con
         }
     }
     free(qd);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Search with caller-given entry points and per-query expansion caps.
+ * entries: nq x ecap ids (-1 = none); the first min(L, n_alive) distinct alive
+ * ids of a query's list, in list order, start its pool (a list with no usable
+ * id leaves the random initialisation).  max_iters: nq caps (0 = none).  The
+ * rest is the search above.  This is how predicted entry points and a
+ * predicted stopping step enter the method (random entry points being one
+ * choice among algorithm-supplied ones, Sec. 2.3). */
+static int search_one_listed(const orc_index *ix, const float *qf, const double *q_lp, int L,
+                             const int32_t *list, int ecap, int max_iters, scratch_t *s,
+                             qstats *st, int32_t *last_change)
+{
+    const int d = ix->dim, R = ix->R;
+    const double *V = ix->vec_lp;
+    memset(st, 0, sizeof *st);
+    st->margin = INFINITY;
+    int ne = 0;
+    for (int j = 0; j < ecap && ne < L; ++j) {
+        int32_t id = list[j];
+        if (id < 0 || id >= ix->n_slots || !ix->alive[id] || s->visited[id]) continue;
+        visit(s, id);
+        s->fresh[ne].id = id;
+        s->fresh[ne].d = dist(ix->metric, q_lp, V + (int64_t)id * d, d);
+        s->fresh[ne].expanded = 0;
+        ++ne; ++st->n_dist;
+    }
+    if (ne == 0) {
+        unvisit_all(s);
+        double xm = 0.0;
+        int np = search_one(ix, ix->n_slots, qf, q_lp, L, ix->entry_samples, ix->search_width,
+                            max_iters, s, st, xm);
+        if (last_change) *last_change = -1;
+        return np;
+    }
+    qsort(s->fresh, ne, sizeof(pentry), cmp_pentry);
+    int np = ne;
+    memcpy(s->pool, s->fresh, np * sizeof(pentry));
+    int32_t lc = 0;
+    for (;;) {
+        if (max_iters > 0 && st->iters >= max_iters) break;
+        int par = -1;
+        for (int i = 0; i < np; ++i) if (!s->pool[i].expanded) { par = i; break; }
+        if (par < 0) break;
+        s->pool[par].expanded = 1;
+        ++st->n_exp;
+        const int32_t *row = ix->rows + (int64_t)s->pool[par].id * R;
+        int nf = 0;
+        for (int r = 0; r < R; ++r) {
+            int32_t u = row[r];
+            if (u < 0 || u >= ix->n_slots || !ix->alive[u] || s->visited[u]) continue;
+            visit(s, u);
+            s->fresh[nf].id = u;
+            s->fresh[nf].d = dist(ix->metric, q_lp, V + (int64_t)u * d, d);
+            s->fresh[nf].expanded = 0;
+            ++nf; ++st->n_dist;
+        }
+        ++st->iters;
+        memcpy(s->merged, s->pool, np * sizeof(pentry));
+        memcpy(s->merged + np, s->fresh, nf * sizeof(pentry));
+        int nm = np + nf;
+        qsort(s->merged, nm, sizeof(pentry), cmp_pentry);
+        np = nm < L ? nm : L;
+        memcpy(s->pool, s->merged, np * sizeof(pentry));
+    }
+    unvisit_all(s);
+    if (last_change) *last_change = lc;
+    return np;
+}
+
+/* Plain search that also reports, per query, the expansion count after which
+ * its top-k never changed (the stopping-step label of the predictor). */
+int orc_search_trace(const orc_index *ix, const float *q, int64_t nq, int k, int L,
+                     int32_t *ids, int32_t *last_change)
+{
+    if (k < 1 || L < k || k > 64) return ORC_E_INVAL;
+    scratch_t s;
+    if (scratch_init(&s, ix->n_slots, L, ix->search_width, ix->R)) return ORC_E_NOMEM;
+    const int d = ix->dim;
+    double *qlp = malloc(sizeof(double) * d);
+    for (int64_t i = 0; i < nq; ++i) {
+        const float *qf = q + i * d;
+        for (int t = 0; t < d; ++t) qlp[t] = lp_value(ix->precision, qf[t]);
+        qstats st;
+        int np = search_one_t(ix, ix->n_slots, qf, qlp, L, ix->entry_samples, ix->search_width,
+                              ix->max_iters, &s, &st, 0.0, k, last_change + i);
+        for (int t = 0; t < k; ++t) ids[i * k + t] = t < np ? s.pool[t].id : ORC_INVALID;
+    }
+    free(qlp);
+    scratch_free(&s);
+    return ORC_OK;
+}
+
+int orc_search_listed(const orc_index *ix, const float *q, int64_t nq, int k, int L,
+                      const int32_t *entries, int ecap, const int32_t *max_iters,
+                      int32_t *ids, double *dd, int64_t *n_exp)
+{
+    if (k < 1 || L < k) return ORC_E_INVAL;
+    scratch_t s;
+    if (scratch_init(&s, ix->n_slots, L, ix->search_width, ix->R)) return ORC_E_NOMEM;
+    const int d = ix->dim;
+    double *qlp = malloc(sizeof(double) * d);
+    for (int64_t i = 0; i < nq; ++i) {
+        const float *qf = q + i * d;
+        for (int t = 0; t < d; ++t) qlp[t] = lp_value(ix->precision, qf[t]);
+        qstats st;
+        int np = search_one_listed(ix, qf, qlp, L, entries + i * ecap, ecap,
+                                   max_iters ? max_iters[i] : 0, &s, &st, NULL);
+        for (int t = 0; t < k; ++t) {
+            ids[i * k + t] = t < np ? s.pool[t].id : ORC_INVALID;
+            dd[i * k + t] = t < np ? s.pool[t].d : INFINITY;
+        }
+        if (n_exp) n_exp[i] = st.n_exp;
+    }
+    free(qlp);
+    scratch_free(&s);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The entry/stop predictor: a multilayer perceptron din -> h -> h -> nc + 1
+ * with ReLU, FP64 here.  Outputs 0..nc-1 are logits of the entry cluster,
+ * output nc predicts log(stop step).  Loss per sample: softmax cross-entropy
+ * on the cluster label plus lambda * Huber(z_nc - log_stop; delta); the batch
+ * loss is the mean.  Weights are row-major (in x out). */
+typedef struct {
+    int din, h, nc;
+    const double *w1, *b1, *w2, *b2, *w3, *b3;
+} mlp_view;
+
+static void mlp_fwd_one(const mlp_view *m, const double *x, double *h1, double *h2, double *z)
+{
+    const int din = m->din, h = m->h, no = m->nc + 1;
+    for (int j = 0; j < h; ++j) {
+        double s = m->b1[j];
+        for (int i = 0; i < din; ++i) s += x[i] * m->w1[i * h + j];
+        h1[j] = s > 0 ? s : 0;
+    }
+    for (int j = 0; j < h; ++j) {
+        double s = m->b2[j];
+        for (int i = 0; i < h; ++i) s += h1[i] * m->w2[i * h + j];
+        h2[j] = s > 0 ? s : 0;
+    }
+    for (int j = 0; j < no; ++j) {
+        double s = m->b3[j];
+        for (int i = 0; i < h; ++i) s += h2[i] * m->w3[i * no + j];
+        z[j] = s;
+    }
+}
+
+void orc_mlp_forward(int din, int h, int nc, const double *w1, const double *b1, const double *w2,
+                     const double *b2, const double *w3, const double *b3, const double *x,
+                     int64_t n, double *out)
+{
+    mlp_view m = {din, h, nc, w1, b1, w2, b2, w3, b3};
+    double *h1 = malloc(sizeof(double) * h), *h2 = malloc(sizeof(double) * h);
+    for (int64_t i = 0; i < n; ++i) mlp_fwd_one(&m, x + i * din, h1, h2, out + i * (nc + 1));
+    free(h1); free(h2);
+}
+
+double orc_mlp_loss_grad(int din, int h, int nc, const double *w1, const double *b1,
+                         const double *w2, const double *b2, const double *w3, const double *b3,
+                         const double *x, const int32_t *label, const double *log_stop, int64_t n,
+                         double lambda, double delta, double *g1, double *gb1, double *g2,
+                         double *gb2, double *g3, double *gb3)
+{
+    mlp_view m = {din, h, nc, w1, b1, w2, b2, w3, b3};
+    const int no = nc + 1;
+    memset(g1, 0, sizeof(double) * din * h); memset(gb1, 0, sizeof(double) * h);
+    memset(g2, 0, sizeof(double) * h * h);   memset(gb2, 0, sizeof(double) * h);
+    memset(g3, 0, sizeof(double) * h * no);  memset(gb3, 0, sizeof(double) * no);
+    double *h1 = malloc(sizeof(double) * h), *h2 = malloc(sizeof(double) * h);
+    double *z = malloc(sizeof(double) * no), *dz = malloc(sizeof(double) * no);
+    double *dh2 = malloc(sizeof(double) * h), *dh1 = malloc(sizeof(double) * h);
+    double loss = 0.0;
+    for (int64_t s = 0; s < n; ++s) {
+        const double *xs = x + s * din;
+        mlp_fwd_one(&m, xs, h1, h2, z);
+        /* cross-entropy over the nc logits (shifted by the max for range) */
+        double mx = z[0];
+        for (int j = 1; j < nc; ++j) if (z[j] > mx) mx = z[j];
+        double se = 0.0;
+        for (int j = 0; j < nc; ++j) se += exp(z[j] - mx);
+        loss += log(se) + mx - z[label[s]];
+        for (int j = 0; j < nc; ++j) dz[j] = exp(z[j] - mx) / se - (j == label[s] ? 1.0 : 0.0);
+        double r = z[nc] - log_stop[s];
+        double ar = fabs(r);
+        loss += lambda * (ar <= delta ? 0.5 * r * r : delta * (ar - 0.5 * delta));
+        dz[nc] = lambda * (ar <= delta ? r : (r > 0 ? delta : -delta));
+        for (int j = 0; j < no; ++j) dz[j] /= (double)n;
+        /* backward through the three layers */
+        for (int j = 0; j < no; ++j) gb3[j] += dz[j];
+        for (int i = 0; i < h; ++i) {
+            double acc = 0.0;
+            for (int j = 0; j < no; ++j) { g3[i * no + j] += h2[i] * dz[j]; acc += w3[i * no + j] * dz[j]; }
+            dh2[i] = h2[i] > 0 ? acc : 0.0;
+        }
+        for (int j = 0; j < h; ++j) gb2[j] += dh2[j];
+        for (int i = 0; i < h; ++i) {
+            double acc = 0.0;
+            for (int j = 0; j < h; ++j) { g2[i * h + j] += h1[i] * dh2[j]; acc += w2[i * h + j] * dh2[j]; }
+            dh1[i] = h1[i] > 0 ? acc : 0.0;
+        }
+        for (int j = 0; j < h; ++j) gb1[j] += dh1[j];
+        for (int i = 0; i < din; ++i)
+            for (int j = 0; j < h; ++j) g1[i * h + j] += xs[i] * dh1[j];
+    }
+    free(h1); free(h2); free(z); free(dz); free(dh2); free(dh1);
+    return loss / (double)n;
 }

@@ -1,0 +1,109 @@
+"""Pins of the oracle parts used by the learned entry/stop form: the FP64
+predictor network (finite differences, closed forms) and search from given
+entry points with expansion caps (brute force, invariants)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2601_08528_amd import datagen
+
+
+def rand_mlp(rng, din=12, h=16, nc=5, scale=0.4):
+    return O.MLP(rng.standard_normal((din, h)) * scale, rng.standard_normal(h) * 0.1,
+                 rng.standard_normal((h, h)) * scale, rng.standard_normal(h) * 0.1,
+                 rng.standard_normal((h, nc + 1)) * scale, rng.standard_normal(nc + 1) * 0.1)
+
+
+def test_mlp_gradients_match_central_differences():
+    rng = np.random.Generator(np.random.Philox(21))
+    m = rand_mlp(rng)
+    x = rng.standard_normal((7, m.din))
+    lab = rng.integers(0, m.nc, 7)
+    ls = rng.standard_normal(7)
+    loss, g = m.loss_grad(x, lab, ls, lam=0.3, delta=0.5)
+    eps = 1e-6
+    for t in range(6):
+        flat = m.p[t].reshape(-1)
+        for idx in rng.choice(flat.size, min(12, flat.size), replace=False):
+            old = flat[idx]
+            flat[idx] = old + eps
+            lp, _ = m.loss_grad(x, lab, ls, lam=0.3, delta=0.5)
+            flat[idx] = old - eps
+            lm, _ = m.loss_grad(x, lab, ls, lam=0.3, delta=0.5)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * eps)
+            assert abs(fd - g[t].reshape(-1)[idx]) <= 1e-6 + 1e-5 * abs(fd)
+
+
+def test_mlp_closed_form_with_zero_weights():
+    """All weights zero: outputs equal b3; the cross-entropy gradient on b3 is
+    mean(softmax(b3) - onehot), and Huber in its linear range gives
+    lambda * delta * sign."""
+    din, h, nc = 6, 8, 4
+    b3 = np.array([0.5, -1.0, 2.0, 0.0, 3.0])
+    m = O.MLP(np.zeros((din, h)), np.zeros(h), np.zeros((h, h)), np.zeros(h),
+              np.zeros((h, nc + 1)), b3)
+    x = np.ones((3, din))
+    np.testing.assert_array_equal(m.forward(x), np.tile(b3, (3, 1)))
+    lab = np.array([0, 2, 2])
+    ls = np.array([0.0, 10.0, 3.0])       # residuals 3, -7, 0: delta = 1
+    loss, g = m.loss_grad(x, lab, ls, lam=0.5, delta=1.0)
+    sm = np.exp(b3[:4]) / np.exp(b3[:4]).sum()
+    want = np.zeros(5)
+    for l in lab:
+        want[:4] += sm - np.eye(4)[l]
+    want[4] = 0.5 * (1.0 + (-1.0) + 0.0)
+    np.testing.assert_allclose(g[5], want / 3, rtol=1e-12, atol=1e-15)
+    ce = np.mean([np.log(np.exp(b3[:4]).sum()) - b3[l] for l in lab])
+    hub = 0.5 * np.mean([(3 - 0.5), (7 - 0.5), 0.0])
+    assert abs(loss - (ce + hub)) < 1e-12
+    for t in range(5):
+        assert not g[t].any()
+
+
+@pytest.fixture(scope="module")
+def idx():
+    base, q = datagen.gmm_uint8_valued(401, 500, 30, 16, 5)
+    ix = O.OracleIndex(16, 8, O.L2, seed=3)
+    ix.build(base, batch_max=100)
+    return ix, base, q
+
+
+def test_listed_entries_all_ids_give_bruteforce(idx):
+    ix, base, q = idx
+    ent = np.tile(np.arange(500, dtype=np.int32), (q.shape[0], 1))
+    ids, d, ne = ix.search_listed(q, 10, 500, ent)
+    gi, gd = O.bruteforce(base, q, 10)
+    np.testing.assert_array_equal(ids, gi)
+    np.testing.assert_array_equal(d, gd)
+
+
+def test_listed_without_usable_ids_is_plain_search(idx):
+    ix, base, q = idx
+    ent = -np.ones((q.shape[0], 4), np.int32)
+    a = ix.search_listed(q, 10, 24, ent)
+    b = ix.search(q, 10, 24)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[2], b[2]["n_exp"])
+
+
+def test_expansion_caps(idx):
+    ix, base, q = idx
+    ent = np.tile(np.arange(0, 500, 7, dtype=np.int32), (q.shape[0], 1))
+    caps = np.arange(q.shape[0], dtype=np.int32) % 5
+    ids, d, ne = ix.search_listed(q, 5, 24, ent, caps)
+    assert ((ne <= caps) | (caps == 0)).all()
+
+
+def test_stop_step_label_is_where_topk_settles(idx):
+    """Capping a search at the recorded stopping step leaves its top-k as is."""
+    ix, base, q = idx
+    ids, lc = ix.search_trace(q, 10, 32)
+    ref = ix.search(q, 10, 32)
+    np.testing.assert_array_equal(ids, ref[0])
+    assert (lc <= ref[2]["iters"]).all() and (lc >= 0).all()
+    for i in range(q.shape[0]):
+        ix.set("max_iters", max(int(lc[i]), 1))
+        capped = ix.search(q[i:i + 1], 10, 32)
+        np.testing.assert_array_equal(capped[0][0], ref[0][i])
+    ix.set("max_iters", 0)
