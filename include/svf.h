@@ -91,6 +91,10 @@ int svf_destroy(svf_index *ix);
  *   insert_batch_max largest batch of one insertion pass (1..1<<20; 10000)
  *   precision       SVF_PREC_* of traversal distances (0..2; 0)
  *   rerank          exact FP32 re-scoring of the final pool under reduced precision (0/1; 1)
+ *   use_model       learned entry points and stopping step (0/1; 0; needs svf_model_fit)
+ *   model_conf      softmax confidence below which a query falls back to plain search ([0,1]; 0.5)
+ *   model_stop_scale expansion cap = ceil(scale * predicted stop step) (>0; 1.5)
+ *   model_min_iters smallest expansion cap of a gated query (>=1; 8)
  * Unknown key or out-of-range value: SVF_E_INVAL. */
 int svf_set_option(svf_index *ix, const char *key, double value);
 int svf_get_option(const svf_index *ix, const char *key, double *value);
@@ -138,6 +142,63 @@ int svf_search(svf_index *ix, const float *queries, int64_t nq, int32_t k, int32
 int svf_search_dev(svf_index *ix, const float *d_queries, int64_t nq, int32_t k, int32_t beam,
                    int32_t *d_out_ids, float *d_out_dists, int32_t *d_n_dist, int32_t *d_n_exp,
                    void *stream);
+
+/* Learned entry points and stopping step (an extension of the method: the
+ * paper starts from random entry points, Sec. 4.2, and notes that entry
+ * points may come from a separate algorithm, Sec. 2.3).  Trains, on the GPU,
+ * a predictor din -> 256 -> 256 -> (n_clusters + 1) with BF16 weights and
+ * FP32 accumulation on search traces this index produces:
+ *   1. Lloyd k-means (12 iterations) of an evenly spaced sample of at most
+ *      65,536 stored vectors into n_clusters centroids;
+ *   2. plain search of the n training queries (host memory, n x dim FP32)
+ *      with k and beam, recording each query's top-1 id and the expansion
+ *      count after which its top-k stopped changing;
+ *   3. labels: the centroid nearest to the top-1 vector, and log(max(1, step));
+ *   4. Adam over `epochs` passes of batches of 1024, loss = cross-entropy +
+ *      0.1 * Huber(log step);
+ *   5. per cluster, the 64 nearest stored vectors to its centroid become
+ *      that cluster's entry list.
+ * Afterwards option use_model = 1 makes svf_search start confident queries
+ * from their cluster's list with a predicted expansion cap; others (softmax
+ * below model_conf) run plain search.  n >= 1024; 2 <= n_clusters <= 256.
+ * *last_loss (may be NULL) receives the mean loss of the last epoch. */
+int svf_model_fit(svf_index *ix, const float *train_queries, int64_t n, int32_t k, int32_t beam,
+                  int32_t n_clusters, int32_t epochs, float *last_loss);
+
+/* The predictor on its own (the network svf_model_fit trains), for checks of
+ * its forward pass, gradients and training.  Parameters are one flat FP32
+ * vector: W1 (din x hidden), b1, W2 (hidden x hidden), b2,
+ * W3 (hidden x (n_clusters + 1)), b3, row-major (input x output).  Weights are
+ * held on the BF16 grid (FP32 masters while training); activations are
+ * rounded to BF16 between layers; products accumulate in FP32.  All pointers
+ * are host memory. */
+typedef struct svf_mlp svf_mlp;
+int svf_mlp_create(int32_t din, int32_t hidden, int32_t n_clusters, uint64_t seed, svf_mlp **out);
+int svf_mlp_destroy(svf_mlp *m);
+int svf_mlp_num_params(const svf_mlp *m, int64_t *n);
+int svf_mlp_set_params(svf_mlp *m, const float *params);
+int svf_mlp_get_params(const svf_mlp *m, float *params);
+/* out: n x (n_clusters + 1) outputs (cluster logits, then log stop step). */
+int svf_mlp_forward(svf_mlp *m, const float *x, int64_t n, float *out);
+/* Mean over n samples of cross-entropy(label) + lambda * Huber(z_last -
+ * log_stop; delta); grad receives its gradient in the flat parameter order. */
+int svf_mlp_loss_grad(svf_mlp *m, const float *x, const int32_t *label, const float *log_stop,
+                      int64_t n, float lambda, float delta, float *loss, float *grad);
+/* Adam (lr, betas 0.9 / 0.999) over `epochs` passes of consecutive batches. */
+int svf_mlp_train(svf_mlp *m, const float *x, const int32_t *label, const float *log_stop,
+                  int64_t n, int32_t epochs, int32_t batch, float lr, float lambda, float delta,
+                  float *last_loss);
+const char *svf_mlp_last_error(void);
+
+/* Search whose pools start from caller-given entry points: entries is nq x
+ * ecap ids (host memory, -1 = unused); a query's pool starts from the first
+ * min(beam, n_alive) distinct alive ids of its list, in list order, and a
+ * list with no usable id falls back to random entry points.  max_iters (nq
+ * ints, may be NULL) caps each query's expansions (0 = none).  This is the
+ * search step of the learned form with the predictions supplied directly. */
+int svf_search_listed(svf_index *ix, const float *queries, int64_t nq, int32_t k, int32_t beam,
+                      const int32_t *entries, int32_t ecap, const int32_t *max_iters,
+                      int32_t *out_ids, float *out_dists);
 
 /* Statistics of the index and of its last calls. */
 int svf_stats_get(const svf_index *ix, svf_stats *out);

@@ -24,6 +24,9 @@ EXPORTED = [
     "svf_create", "svf_destroy", "svf_set_option", "svf_get_option", "svf_insert",
     "svf_insert_dev", "svf_build", "svf_delete", "svf_consolidate", "svf_search",
     "svf_search_dev", "svf_stats_get", "svf_export_graph", "svf_import_graph", "svf_last_error",
+    "svf_search_listed", "svf_model_fit", "svf_mlp_create", "svf_mlp_destroy",
+    "svf_mlp_num_params", "svf_mlp_set_params", "svf_mlp_get_params", "svf_mlp_forward",
+    "svf_mlp_loss_grad", "svf_mlp_train", "svf_mlp_last_error",
 ]
 
 
@@ -73,9 +76,22 @@ def lib():
         L.svf_stats_get.argtypes = [vp, C.POINTER(Stats)]
         L.svf_export_graph.argtypes = [vp, vp, vp, vp, i64]
         L.svf_import_graph.argtypes = [vp, vp, i64, vp, vp, vp]
+        L.svf_search_listed.argtypes = [vp, vp, i64, i32, i32, vp, i32, vp, vp, vp]
+        L.svf_model_fit.argtypes = [vp, vp, i64, i32, i32, i32, i32, C.POINTER(C.c_float)]
+        L.svf_mlp_create.argtypes = [i32, i32, i32, C.c_uint64, C.POINTER(vp)]
+        L.svf_mlp_destroy.argtypes = [vp]
+        L.svf_mlp_num_params.argtypes = [vp, C.POINTER(i64)]
+        L.svf_mlp_set_params.argtypes = [vp, vp]
+        L.svf_mlp_get_params.argtypes = [vp, vp]
+        L.svf_mlp_forward.argtypes = [vp, vp, i64, vp]
+        L.svf_mlp_loss_grad.argtypes = [vp, vp, vp, vp, i64, C.c_float, C.c_float,
+                                        C.POINTER(C.c_float), vp]
+        L.svf_mlp_train.argtypes = [vp, vp, vp, vp, i64, i32, i32, C.c_float, C.c_float,
+                                    C.c_float, C.POINTER(C.c_float)]
         L.svf_last_error.restype = C.c_char_p
+        L.svf_mlp_last_error.restype = C.c_char_p
         for name in EXPORTED:
-            if name != "svf_last_error":
+            if not name.endswith("last_error"):
                 getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -153,6 +169,23 @@ class Index:
         _check(lib().svf_search_dev(self.h, d_queries, nq, k, beam, d_ids, d_dists, d_n_dist,
                                     d_n_exp, stream))
 
+    def search_listed(self, queries, k: int, beam: int, entries, max_iters=None):
+        q = np.ascontiguousarray(queries, dtype=np.float32).reshape(-1, self.dim)
+        e = np.ascontiguousarray(entries, dtype=np.int32).reshape(q.shape[0], -1)
+        mi = None if max_iters is None else np.ascontiguousarray(max_iters, dtype=np.int32)
+        ids = np.empty((q.shape[0], k), np.int32)
+        d = np.empty((q.shape[0], k), np.float32)
+        _check(lib().svf_search_listed(self.h, _p(q), q.shape[0], k, beam, _p(e), e.shape[1],
+                                       _p(mi), _p(ids), _p(d)))
+        return ids, d
+
+    def model_fit(self, train_queries, k: int, beam: int, n_clusters: int = 64, epochs: int = 10):
+        q = np.ascontiguousarray(train_queries, dtype=np.float32).reshape(-1, self.dim)
+        loss = C.c_float()
+        _check(lib().svf_model_fit(self.h, _p(q), q.shape[0], k, beam, n_clusters, epochs,
+                                   C.byref(loss)))
+        return loss.value
+
     def stats(self) -> dict:
         s = Stats()
         _check(lib().svf_stats_get(self.h, C.byref(s)))
@@ -176,3 +209,72 @@ class Index:
         e = np.ascontiguousarray(edge_d, dtype=np.float32)
         a = np.ascontiguousarray(alive, dtype=np.uint8)
         _check(lib().svf_import_graph(self.h, _p(v), v.shape[0], _p(r), _p(e), _p(a)))
+
+
+def _mcheck(rc):
+    if rc != 0:
+        raise SvfError(rc, lib().svf_mlp_last_error().decode())
+
+
+class Mlp:
+    """The entry/stop predictor on its own (``svf_mlp_*``)."""
+
+    def __init__(self, din: int, hidden: int, n_clusters: int, seed: int = 0):
+        h = C.c_void_p()
+        _mcheck(lib().svf_mlp_create(din, hidden, n_clusters, seed, C.byref(h)))
+        self.h = h
+        self.din, self.hidden, self.nc = din, hidden, n_clusters
+        n = C.c_int64()
+        _mcheck(lib().svf_mlp_num_params(self.h, C.byref(n)))
+        self.n_params = n.value
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().svf_mlp_destroy(self.h)
+            self.h = None
+
+    def shapes(self):
+        d, h, no = self.din, self.hidden, self.nc + 1
+        return [(d, h), (h,), (h, h), (h,), (h, no), (no,)]
+
+    def split(self, flat):
+        out, o = [], 0
+        for s in self.shapes():
+            n = int(np.prod(s))
+            out.append(flat[o:o + n].reshape(s))
+            o += n
+        return out
+
+    def get_params(self):
+        p = np.empty(self.n_params, np.float32)
+        _mcheck(lib().svf_mlp_get_params(self.h, _p(p)))
+        return p
+
+    def set_params(self, flat):
+        p = np.ascontiguousarray(flat, dtype=np.float32)
+        _mcheck(lib().svf_mlp_set_params(self.h, _p(p)))
+
+    def forward(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        out = np.empty((x.shape[0], self.nc + 1), np.float32)
+        _mcheck(lib().svf_mlp_forward(self.h, _p(x), x.shape[0], _p(out)))
+        return out
+
+    def loss_grad(self, x, label, log_stop, lam=0.1, delta=1.0):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        lab = np.ascontiguousarray(label, dtype=np.int32)
+        ls = np.ascontiguousarray(log_stop, dtype=np.float32)
+        g = np.empty(self.n_params, np.float32)
+        loss = C.c_float()
+        _mcheck(lib().svf_mlp_loss_grad(self.h, _p(x), _p(lab), _p(ls), x.shape[0], lam, delta,
+                                        C.byref(loss), _p(g)))
+        return loss.value, g
+
+    def train(self, x, label, log_stop, epochs=5, batch=256, lr=1e-3, lam=0.1, delta=1.0):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        lab = np.ascontiguousarray(label, dtype=np.int32)
+        ls = np.ascontiguousarray(log_stop, dtype=np.float32)
+        loss = C.c_float()
+        _mcheck(lib().svf_mlp_train(self.h, _p(x), _p(lab), _p(ls), x.shape[0], epochs, batch, lr,
+                                    lam, delta, C.byref(loss)))
+        return loss.value

@@ -424,6 +424,20 @@ int search_impl(svf_index* ix, const float* d_q, int64_t nq, int k, int beam, in
   a.queries = d_q;
   a.qstride = ix->dim;
   a.nq = (int)nq;
+  if (ix->opt.use_model && ix->model) {
+    float* z;
+    int32_t *qe, *qm;
+    if ((rc = scratch(ix->s_z, (size_t)nq * (ix->model_nc + 1), &z)) ||
+        (rc = scratch(ix->s_qentry, nq, &qe)) || (rc = scratch(ix->s_qmax, nq, &qm)))
+      return rc;
+    CK(ix->model->forward(d_q, nq, z, st));
+    CK(svf::launch_model_decide(z, nq, ix->model_nc, (float)ix->opt.model_conf,
+                                (float)ix->opt.model_stop_scale, ix->opt.model_min_iters, qe, qm, st));
+    a.entry_lists = ix->entry_lists.as<int32_t>();
+    a.entry_cap = ix->entry_cap;
+    a.q_entry = qe;
+    a.q_max_iters = qm;
+  }
   a.out_ids = d_ids;
   a.out_d = d_d;
   a.n_dist = d_nd;
@@ -537,6 +551,8 @@ int svf_destroy(svf_index* ix) {
     if (ix->ev0) (void)hipEventDestroy(ix->ev0);
     if (ix->ev1) (void)hipEventDestroy(ix->ev1);
     if (ix->stream) (void)hipStreamDestroy(ix->stream);
+    delete ix->model;
+    ix->model = nullptr;
   }
   delete ix;
   return SVF_OK;
@@ -587,6 +603,19 @@ int svf_set_option(svf_index* ix, const char* key, double v) {
   } else if (k == "rerank") {
     if (v != 0 && v != 1) return fail(SVF_E_INVAL, "rerank 0 or 1");
     o.rerank = (int)v;
+  } else if (k == "use_model") {
+    if (v != 0 && v != 1) return fail(SVF_E_INVAL, "use_model 0 or 1");
+    if (v == 1 && !ix->model) return fail(SVF_E_INVAL, "use_model needs svf_model_fit first");
+    o.use_model = (int)v;
+  } else if (k == "model_conf") {
+    if (v < 0 || v > 1) return fail(SVF_E_INVAL, "model_conf in [0, 1]");
+    o.model_conf = v;
+  } else if (k == "model_stop_scale") {
+    if (v <= 0 || v > 1e6) return fail(SVF_E_INVAL, "model_stop_scale > 0");
+    o.model_stop_scale = v;
+  } else if (k == "model_min_iters") {
+    if (!is_int(v) || v < 1 || v > 1e9) return fail(SVF_E_INVAL, "model_min_iters >= 1");
+    o.model_min_iters = (int)v;
   } else {
     return fail(SVF_E_INVAL, "unknown option " + k);
   }
@@ -609,6 +638,10 @@ int svf_get_option(const svf_index* ix, const char* key, double* out) {
   else if (k == "insert_batch_max") *out = o.insert_batch_max;
   else if (k == "precision") *out = o.precision;
   else if (k == "rerank") *out = o.rerank;
+  else if (k == "use_model") *out = o.use_model;
+  else if (k == "model_conf") *out = o.model_conf;
+  else if (k == "model_stop_scale") *out = o.model_stop_scale;
+  else if (k == "model_min_iters") *out = o.model_min_iters;
   else return fail(SVF_E_INVAL, "unknown option " + k);
   return SVF_OK;
 }
@@ -723,6 +756,141 @@ int svf_search(svf_index* ix, const float* queries, int64_t nq, int32_t k, int32
   CK(hipMemcpyAsync(out_dists, dd, (size_t)nq * k * 4, hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
   finish_search_stats(ix);
+  return SVF_OK;
+}
+
+int svf_search_listed(svf_index* ix, const float* queries, int64_t nq, int32_t k, int32_t beam,
+                      const int32_t* entries, int32_t ecap, const int32_t* max_iters,
+                      int32_t* out_ids, float* out_dists) {
+  int rc = check_search_args(ix, nq, k, beam);
+  if (rc) return rc;
+  if (nq == 0) return SVF_OK;
+  if (!queries || !entries || !out_ids || !out_dists || ecap < 1) return fail(SVF_E_INVAL, "bad buffer");
+  if (!all_finite(queries, nq * ix->dim)) return fail(SVF_E_INVAL, "non-finite query value");
+  std::lock_guard<std::mutex> g(ix->mu);
+  hipStream_t st = ix->stream;
+  float *dq, *dd;
+  int32_t *di, *de, *dqe, *dqm;
+  uint64_t* qkey;
+  if ((rc = scratch(ix->s_q, (size_t)nq * ix->dim, &dq)) || (rc = scratch(ix->s_ids, (size_t)nq * k, &di)) ||
+      (rc = scratch(ix->s_d, (size_t)nq * k, &dd)) || (rc = scratch(ix->s_misc[0], (size_t)nq * ecap, &de)) ||
+      (rc = scratch(ix->s_misc[1], nq, &dqe)) || (rc = scratch(ix->s_misc[2], nq, &dqm)) ||
+      (rc = scratch(ix->s_qkey, nq, &qkey)))
+    return rc;
+  std::vector<int32_t> qe(nq), qm(nq, 0);
+  for (int64_t i = 0; i < nq; ++i) {
+    qe[i] = (int32_t)i;
+    if (max_iters) qm[i] = max_iters[i];
+  }
+  CK(hipMemcpyAsync(dq, queries, (size_t)nq * ix->dim * 4, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(de, entries, (size_t)nq * ecap * 4, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(dqe, qe.data(), (size_t)nq * 4, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(dqm, qm.data(), (size_t)nq * 4, hipMemcpyHostToDevice, st));
+  if (ix->n_slots == 0) {
+    CK(svf::launch_fill_u32(di, nq * k, 0xffffffffu, st));
+    CK(svf::launch_fill_u32(dd, nq * k, 0x7f800000u, st));
+  } else {
+    svf::SearchArgs a = base_args(ix);
+    set_beam(a, ix, beam);
+    a.k = k;
+    a.queries = dq;
+    a.qstride = ix->dim;
+    a.nq = (int)nq;
+    a.entry_lists = de;
+    a.entry_cap = ecap;
+    a.q_entry = dqe;
+    a.q_max_iters = dqm;
+    a.out_ids = di;
+    a.out_d = dd;
+    CK(svf::launch_query_keys(dq, ix->dim, nullptr, ix->dim, a.nq, ix->opt.seed, qkey, st));
+    a.qkey = qkey;
+    CK(svf::launch_search(a, ix->veclp_prec, st));
+  }
+  CK(hipMemcpyAsync(out_ids, di, (size_t)nq * k * 4, hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(out_dists, dd, (size_t)nq * k * 4, hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  return SVF_OK;
+}
+
+int svf_model_fit(svf_index* ix, const float* train_queries, int64_t n, int32_t k, int32_t beam,
+                  int32_t n_clusters, int32_t epochs, float* last_loss) {
+  int rc = check_search_args(ix, n, k, beam);
+  if (rc) return rc;
+  if (!train_queries || n < 1024) return fail(SVF_E_INVAL, "need at least 1024 training queries");
+  if (n_clusters < 2 || n_clusters > 256) return fail(SVF_E_INVAL, "n_clusters in [2, 256]");
+  if (epochs < 1 || epochs > 1000) return fail(SVF_E_INVAL, "epochs in [1, 1000]");
+  if (!all_finite(train_queries, n * ix->dim)) return fail(SVF_E_INVAL, "non-finite query value");
+  std::lock_guard<std::mutex> g(ix->mu);
+  if (ix->n_alive < 2 * n_clusters) return fail(SVF_E_INVAL, "index too small for the clusters");
+  hipStream_t st = ix->stream;
+  const int dim = ix->dim, nc = n_clusters, ecap = 64;
+  // 1. entry clusters: Lloyd k-means over an evenly spaced sample of rows
+  const int64_t ns = std::min<int64_t>(ix->n_slots, 65536);
+  const int64_t step = ix->n_slots / ns;
+  float* cent;
+  int32_t* sassign;
+  if ((rc = scratch(ix->centroids, (size_t)nc * dim, &cent)) ||
+      (rc = scratch(ix->s_misc[0], ns, &sassign)))
+    return rc;
+  CK(hipMemcpy2DAsync(cent, dim * 4, ix->vec32, step * ix->stride * 4, dim * 4, nc,
+                      hipMemcpyDeviceToDevice, st));
+  CK(svf::kmeans(ix->vec32, ns, step * ix->stride, dim, nc, 12, cent, sassign, st));
+  // 2. traces of plain search: top-k ids and the step where the top-k settled
+  float* dq;
+  int32_t *ids, *lcg, *labels;
+  float *dd, *lstop;
+  uint64_t* qkey;
+  if ((rc = scratch(ix->s_q, (size_t)n * dim, &dq)) || (rc = scratch(ix->s_ids, (size_t)n * k, &ids)) ||
+      (rc = scratch(ix->s_d, (size_t)n * k, &dd)) || (rc = scratch(ix->s_misc[1], n, &lcg)) ||
+      (rc = scratch(ix->s_misc[2], n, &labels)) || (rc = scratch(ix->s_misc[3], n, &lstop)) ||
+      (rc = scratch(ix->s_qkey, n, &qkey)))
+    return rc;
+  CK(hipMemcpyAsync(dq, train_queries, (size_t)n * dim * 4, hipMemcpyHostToDevice, st));
+  svf::SearchArgs a = base_args(ix);
+  set_beam(a, ix, beam);
+  a.k = k;
+  a.queries = dq;
+  a.qstride = dim;
+  a.nq = (int)n;
+  a.out_ids = ids;
+  a.out_d = dd;
+  a.last_change = lcg;
+  CK(svf::launch_query_keys(dq, dim, nullptr, dim, a.nq, ix->opt.seed, qkey, st));
+  a.qkey = qkey;
+  CK(svf::launch_search(a, ix->veclp_prec, st));
+  // 3. labels: cluster of the top-1 result; log of the settling step
+  CK(svf::assign_rows(ix->vec32, ix->stride, dim, ids, n, k, cent, nc, labels, st));
+  CK(svf::launch_log_steps(lcg, n, lstop, st));
+  CK(hipStreamSynchronize(st));
+  // 4. train the predictor on the GPU
+  delete ix->model;
+  ix->model = new (std::nothrow) svf::Mlp(dim, 256, nc, ix->opt.seed + 12345);
+  if (!ix->model) return fail(SVF_E_NOMEM, "host allocation");
+  CK(ix->model->init_device(st));
+  float loss = 0.f;
+  CK(ix->model->train(dq, labels, lstop, n, epochs, 1024, 2e-3f, 0.1f, 1.0f, &loss, st));
+  if (last_loss) *last_loss = loss;
+  ix->model_nc = nc;
+  // 5. per-cluster entry lists: the nearest alive vectors to each centroid
+  int32_t* el;
+  float* eld;
+  uint64_t* ckey;
+  if ((rc = scratch(ix->entry_lists, (size_t)nc * ecap, &el)) ||
+      (rc = scratch(ix->s_misc[4], (size_t)nc * ecap, &eld)) || (rc = scratch(ix->s_misc[5], nc, &ckey)))
+    return rc;
+  svf::SearchArgs c = base_args(ix);
+  set_beam(c, ix, std::max(2 * ecap, beam));
+  c.k = ecap;
+  c.queries = cent;
+  c.qstride = dim;
+  c.nq = nc;
+  c.out_ids = el;
+  c.out_d = eld;
+  CK(svf::launch_query_keys(cent, dim, nullptr, dim, nc, ix->opt.seed, ckey, st));
+  c.qkey = ckey;
+  CK(svf::launch_search(c, ix->veclp_prec, st));
+  CK(hipStreamSynchronize(st));
+  ix->entry_cap = ecap;
   return SVF_OK;
 }
 

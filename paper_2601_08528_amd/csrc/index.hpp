@@ -7,6 +7,7 @@
 #include <string>
 
 #include "../../include/svf.h"
+#include "mlp.hpp"
 
 namespace svf {
 
@@ -46,6 +47,11 @@ struct Options {
   int insert_batch_max = 10000;
   int precision = 0;
   int rerank = 1;
+  // learned entry points / stopping step
+  int use_model = 0;
+  double model_conf = 0.5;
+  double model_stop_scale = 1.5;
+  int model_min_iters = 8;
 };
 
 }  // namespace svf
@@ -69,5 +75,9 @@ struct svf_index {
   std::mutex mu;
   // scratch
   svf::DevBuf s_q, s_qkey, s_ids, s_d, s_pool, s_tot, s_misc[12];
+  // learned form
+  svf::Mlp* model = nullptr;
+  int model_nc = 0, entry_cap = 0;
+  svf::DevBuf centroids, entry_lists, s_z, s_qentry, s_qmax;
   svf_stats st{};
 };

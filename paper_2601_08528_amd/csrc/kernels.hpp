@@ -33,6 +33,12 @@ struct SearchArgs {
   uint64_t* out_pool;       // nq x L final pool keys (flag cleared)
   int32_t* n_dist;
   int32_t* n_exp;
+  // learned entry points and stopping steps (all optional)
+  const int32_t* entry_lists;  // nlists x entry_cap ids (-1 padded)
+  int entry_cap;
+  const int32_t* q_entry;      // per query: list index, or -1 for random entries
+  const int32_t* q_max_iters;  // per query expansion cap (0: none)
+  int32_t* last_change;        // per query: expansions done when the top-k last changed
   unsigned long long* totals;  // [0] distances, [1] expansions
 };
 

@@ -43,6 +43,7 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
   w.cid = reinterpret_cast<int32_t*>(w.kept + kWave);
   void* vis_mem = reinterpret_cast<void*>(w.cid + kWave);
   w.L = a.L;
+  w.ktrack = a.last_change ? (a.k > 0 ? a.k : 1) : 0;
   VIS vis;
   vis.setup(vis_mem, a.T, a.id_bits);
 
@@ -57,24 +58,16 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
 
   int n_dist = 0, n_exp = 0;
 
-  // ---- InitCandidatePool: random entries from the query's own stream -------
-  // The first min(E, n_alive) distinct alive ids in attempt order; the ids
-  // accepted so far sit in an exact list that borrows the visited-table LDS.
+  // ---- InitCandidatePool ------------------------------------------------------
+  // Random entries: the first min(E, n_alive) distinct alive ids in the order
+  // of the query's own SplitMix64 stream.  Listed entries (learned form): the
+  // first min(L, n_alive) distinct alive ids of the query's list, in list
+  // order; a list with no usable id falls back to random entries.  Accepted
+  // ids sit in an exact list that borrows the visited-table LDS.
   {
     int32_t* acc = static_cast<int32_t*>(vis_mem);
-    const uint64_t skey = a.qkey[qi];
-    const int E = a.E;
-    const int want = E < a.n_alive ? E : a.n_alive;
-    const int attempts = 8 * E + 64;
     int got = 0;
-    for (int a0 = 0; a0 < attempts && got < want; a0 += kWave) {
-      const int j = a0 + lane;
-      int32_t id = -1;
-      bool valid = false;
-      if (j < attempts) {
-        id = range_reduce(splitmix64_at(skey, (uint64_t)j), (uint32_t)a.n_slots);
-        valid = alive_bit(a.alive, id);
-      }
+    auto accept_chunk = [&](int32_t id, bool valid, int want) {
       bool dup = false;
       for (int t = 0; t < kWave; ++t) {
         const int32_t o = __shfl(id, t);
@@ -94,6 +87,33 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
       uint64_t k = gather_keys<VT, NC>(qs, base, a.stride, w.cid, nt, a.metric);
       n_dist += nt;
       sort_merge(w, k);
+    };
+    const int list = a.q_entry ? a.q_entry[qi] : -1;
+    if (list >= 0) {
+      const int32_t* ent = a.entry_lists + (int64_t)list * a.entry_cap;
+      const int want = a.L < a.n_alive ? a.L : a.n_alive;
+      for (int j0 = 0; j0 < a.entry_cap && got < want; j0 += kWave) {
+        const int j = j0 + lane;
+        const int32_t id = j < a.entry_cap ? ent[j] : -1;
+        const bool valid = id >= 0 && id < a.n_slots && alive_bit(a.alive, id);
+        accept_chunk(id, valid, want);
+      }
+    }
+    if (got == 0) {
+      const uint64_t skey = a.qkey[qi];
+      const int E = a.E;
+      const int want = E < a.n_alive ? E : a.n_alive;
+      const int attempts = 8 * E + 64;
+      for (int a0 = 0; a0 < attempts && got < want; a0 += kWave) {
+        const int j = a0 + lane;
+        int32_t id = -1;
+        bool valid = false;
+        if (j < attempts) {
+          id = range_reduce(splitmix64_at(skey, (uint64_t)j), (uint32_t)a.n_slots);
+          valid = alive_bit(a.alive, id);
+        }
+        accept_chunk(id, valid, want);
+      }
     }
     __syncthreads();
     vis.clear(a.T);
@@ -106,8 +126,10 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
   }
 
   // ---- repeat: nearest unexpanded -> neighbours -> distances -> update ------
+  const int cap_iters = (a.q_max_iters && a.q_max_iters[qi] > 0) ? a.q_max_iters[qi] : a.max_iters;
+  int last_change = 0;
   for (;;) {
-    if (a.max_iters > 0 && n_exp >= a.max_iters) break;
+    if (cap_iters > 0 && n_exp >= cap_iters) break;
     int ppos = -1;
     for (int b0 = 0; b0 < a.L; b0 += kWave) {
       const int i = b0 + lane;
@@ -139,7 +161,7 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
       uint64_t k = gather_keys<VT, NC>(qs, base, a.stride, w.cid, m, a.metric);
       if (lane < m && !((aword >> (mine & 31)) & 1u)) k = kKeyInf;
       n_dist += m;
-      sort_merge(w, k);
+      if (sort_merge(w, k)) last_change = n_exp;
     }
   }
 
@@ -185,6 +207,7 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
   if (lane == 0) {
     if (a.n_dist) a.n_dist[qi] = n_dist;
     if (a.n_exp) a.n_exp[qi] = n_exp;
+    if (a.last_change) a.last_change[qi] = last_change;
     if (a.totals) {
       atomicAdd(&a.totals[0], (unsigned long long)n_dist);
       atomicAdd(&a.totals[1], (unsigned long long)n_exp);

@@ -396,6 +396,7 @@ __global__ __launch_bounds__(64) void reverse_prune_kernel(ReverseArgs a, int n_
   const int lane = lane_id();
   const int cap = a.cap;
   WaveCtx w;
+  w.ktrack = 0;
   w.pool = reinterpret_cast<uint64_t*>(smem);
   w.next = w.pool + cap;
   w.kept = w.next + cap;
@@ -526,6 +527,7 @@ __global__ __launch_bounds__(64) void repair_candidates_kernel(RepairArgs a, int
   const int cap = a.cap;
   const int32_t v = a.list[first + li];
   WaveCtx w;
+  w.ktrack = 0;
   w.pool = reinterpret_cast<uint64_t*>(smem);
   w.next = w.pool + cap;
   w.kept = w.next + cap;
@@ -619,6 +621,7 @@ __global__ __launch_bounds__(64) void topup_merge_kernel(RepairArgs a, const uin
   const int li = a.topup[ti];
   const int32_t v = a.topup_v[ti];
   WaveCtx w;
+  w.ktrack = 0;
   w.pool = reinterpret_cast<uint64_t*>(smem);
   w.next = w.pool + cap;
   w.kept = w.next + cap;

@@ -16,6 +16,7 @@ struct WaveCtx {
   uint32_t* vis;      // T slots
   uint32_t tmask;
   int L;
+  int ktrack;         // report merges that change the first ktrack keys (0: off)
 };
 
 // ---- visited table --------------------------------------------------------
@@ -241,7 +242,7 @@ __device__ inline uint64_t gather_keys(const QuerySlice<VT, NC>& qs, const VT* _
 // Merge one sorted key per lane (kKeyInf padded) into the sorted pool of L
 // keys, keeping the L smallest; keys equal in (dist,id) to a pool entry are
 // dropped (the pool entry keeps its expanded flag).
-__device__ inline void merge_into_pool(WaveCtx& w, uint64_t nk) {
+__device__ inline bool merge_into_pool(WaveCtx& w, uint64_t nk) {
   const int lane = lane_id();
   const int L = w.L;
   const uint64_t* cur = w.pool;
@@ -263,7 +264,8 @@ __device__ inline void merge_into_pool(WaveCtx& w, uint64_t nk) {
   const int mk = popc64(kb);
   if (keep) w.kept[r] = nk;
   __syncthreads();
-  if (mk == 0) return;
+  if (mk == 0) return false;
+  const bool topk = ballot(keep && r + lo < w.ktrack) != 0;
   if (keep && r + lo < L) w.next[r + lo] = nk;
   for (int i = lane; i < L; i += kWave) {
     const uint64_t pk = cur[i];
@@ -277,6 +279,7 @@ __device__ inline void merge_into_pool(WaveCtx& w, uint64_t nk) {
   }
   __syncthreads();
   uint64_t* t = w.pool; w.pool = w.next; w.next = t;
+  return topk;
 }
 
 
@@ -300,13 +303,13 @@ __device__ __forceinline__ uint64_t wave_sort_width(uint64_t key, int W) {
 // Merge one unsorted key per lane (kKeyInf = none) into the pool: keys that
 // cannot enter a full pool are dropped first, the rest are compacted and
 // sorted over the narrowest power-of-two width, then merged.
-__device__ inline void sort_merge(WaveCtx& w, uint64_t k) {
+__device__ inline bool sort_merge(WaveCtx& w, uint64_t k) {
   const int lane = lane_id();
   const uint64_t last = w.pool[w.L - 1];
   const bool live = k != kKeyInf && (last == kKeyInf || key_ord(k) < key_ord(last));
   const uint64_t lb = ballot(live);
   const int s = popc64(lb);
-  if (s == 0) return;
+  if (s == 0) return false;
   __syncthreads();
   if (live) w.kept[lanes_below(lb)] = k;
   __syncthreads();
@@ -315,7 +318,7 @@ __device__ inline void sort_merge(WaveCtx& w, uint64_t k) {
   while (W < s) W <<= 1;
   c = wave_sort_width(c, W);
   __syncthreads();
-  merge_into_pool(w, c);
+  return merge_into_pool(w, c);
 }
 
 }  // namespace svf
