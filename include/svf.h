@@ -200,6 +200,43 @@ int svf_search_listed(svf_index *ix, const float *queries, int64_t nq, int32_t k
                       const int32_t *entries, int32_t ecap, const int32_t *max_iters,
                       int32_t *out_ids, float *out_dists);
 
+/* Serving loop (the paper's real-time coordination, Sec. 4.4, on one GPU).
+ * A dispatcher thread owns the index between svf_serve_start and
+ * svf_serve_stop; during that time the direct calls above return SVF_E_BUSY
+ * (svf_stats_get and svf_get_option still work).
+ *  - Search requests are coalesced in arrival order into batches of at most
+ *    max_batch queries (same k and beam) and run on `streams` search streams
+ *    (1..16), so batches overlap on the device.  A batch is admitted when a
+ *    stream is free and its buffers fit in the HBM budget (hbm_budget bytes,
+ *    0 = 80% of the free device memory at start); a request that can never
+ *    fit fails with SVF_E_NOMEM.
+ *  - Inserts and deletes apply one at a time in arrival order.  An insert's
+ *    search and prune phases run while search batches continue; its commit
+ *    and every delete wait for in-flight search batches.  Each committed
+ *    insert batch (insert_batch_max vectors) or delete advances the epoch.
+ *  - A search sees the epoch committed when its batch launches, so its
+ *    result equals that of the same search issued alone at that point.
+ * Submit calls copy their inputs and return a ticket at once; output buffers
+ * must stay valid until svf_wait returns for that ticket.  The learned form
+ * (use_model) is not served. */
+typedef struct svf_request_info {
+    int32_t status;          /* SVF_OK or the request's error                 */
+    double queue_ms;         /* submit -> launch on the device (host clock)   */
+    double total_ms;         /* submit -> completion seen by the dispatcher    */
+    int64_t batch_queries;   /* queries of the device batch a search ran in    */
+    int64_t epoch;           /* epoch a search saw / a mutation produced        */
+} svf_request_info;
+int svf_serve_start(svf_index *ix, int32_t streams, int64_t max_batch, int64_t hbm_budget);
+int svf_serve_stop(svf_index *ix);   /* finishes every submitted request first */
+int svf_submit_search(svf_index *ix, const float *queries, int64_t nq, int32_t k, int32_t beam,
+                      int32_t *out_ids, float *out_dists, uint64_t *ticket);
+int svf_submit_insert(svf_index *ix, const float *vecs, int64_t n, int32_t *out_ids,
+                      uint64_t *ticket);
+int svf_submit_delete(svf_index *ix, const int32_t *ids, int64_t n, uint64_t *ticket);
+/* Block until the request finishes (timeout_s < 0: no limit); info may be
+ * NULL.  Returns the request's status; a ticket can be waited for once. */
+int svf_wait(svf_index *ix, uint64_t ticket, double timeout_s, svf_request_info *info);
+
 /* Statistics of the index and of its last calls. */
 int svf_stats_get(const svf_index *ix, svf_stats *out);
 

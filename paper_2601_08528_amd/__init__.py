@@ -27,7 +27,14 @@ EXPORTED = [
     "svf_search_listed", "svf_model_fit", "svf_mlp_create", "svf_mlp_destroy",
     "svf_mlp_num_params", "svf_mlp_set_params", "svf_mlp_get_params", "svf_mlp_forward",
     "svf_mlp_loss_grad", "svf_mlp_train", "svf_mlp_last_error",
+    "svf_serve_start", "svf_serve_stop", "svf_submit_search", "svf_submit_insert",
+    "svf_submit_delete", "svf_wait",
 ]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("status", C.c_int32), ("queue_ms", C.c_double), ("total_ms", C.c_double),
+                ("batch_queries", C.c_int64), ("epoch", C.c_int64)]
 
 
 class SvfError(RuntimeError):
@@ -88,6 +95,12 @@ def lib():
                                         C.POINTER(C.c_float), vp]
         L.svf_mlp_train.argtypes = [vp, vp, vp, vp, i64, i32, i32, C.c_float, C.c_float,
                                     C.c_float, C.POINTER(C.c_float)]
+        L.svf_serve_start.argtypes = [vp, i32, i64, i64]
+        L.svf_serve_stop.argtypes = [vp]
+        L.svf_submit_search.argtypes = [vp, vp, i64, i32, i32, vp, vp, C.POINTER(C.c_uint64)]
+        L.svf_submit_insert.argtypes = [vp, vp, i64, vp, C.POINTER(C.c_uint64)]
+        L.svf_submit_delete.argtypes = [vp, vp, i64, C.POINTER(C.c_uint64)]
+        L.svf_wait.argtypes = [vp, C.c_uint64, f64, C.POINTER(RequestInfo)]
         L.svf_last_error.restype = C.c_char_p
         L.svf_mlp_last_error.restype = C.c_char_p
         for name in EXPORTED:
@@ -185,6 +198,45 @@ class Index:
         _check(lib().svf_model_fit(self.h, _p(q), q.shape[0], k, beam, n_clusters, epochs,
                                    C.byref(loss)))
         return loss.value
+
+    # ---- serving loop -----------------------------------------------------
+    def serve_start(self, streams: int = 4, max_batch: int = 16384, hbm_budget: int = 0):
+        _check(lib().svf_serve_start(self.h, streams, max_batch, hbm_budget))
+
+    def serve_stop(self):
+        _check(lib().svf_serve_stop(self.h))
+
+    def submit_search(self, queries, k: int, beam: int):
+        """Returns (ticket, ids, dists); the arrays fill in when the ticket
+        completes (keep them alive until wait())."""
+        q = np.ascontiguousarray(queries, dtype=np.float32).reshape(-1, self.dim)
+        ids = np.empty((q.shape[0], k), np.int32)
+        d = np.empty((q.shape[0], k), np.float32)
+        t = C.c_uint64()
+        _check(lib().svf_submit_search(self.h, _p(q), q.shape[0], k, beam, _p(ids), _p(d),
+                                       C.byref(t)))
+        return t.value, ids, d
+
+    def submit_insert(self, vecs):
+        v = np.ascontiguousarray(vecs, dtype=np.float32).reshape(-1, self.dim)
+        ids = np.empty(v.shape[0], np.int32)
+        t = C.c_uint64()
+        _check(lib().svf_submit_insert(self.h, _p(v), v.shape[0], _p(ids), C.byref(t)))
+        return t.value, ids
+
+    def submit_delete(self, ids):
+        a = np.ascontiguousarray(ids, dtype=np.int32).reshape(-1)
+        t = C.c_uint64()
+        _check(lib().svf_submit_delete(self.h, _p(a), a.shape[0], C.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int, timeout_s: float = -1.0) -> dict:
+        info = RequestInfo()
+        rc = lib().svf_wait(self.h, ticket, timeout_s, C.byref(info))
+        out = {k: getattr(info, k) for k, _ in RequestInfo._fields_}
+        if rc != 0:
+            raise SvfError(rc, lib().svf_last_error().decode())
+        return out
 
     def stats(self) -> dict:
         s = Stats()

@@ -11,11 +11,12 @@
 #include <vector>
 
 #include "index.hpp"
+#include "index_internal.hpp"
 #include "kernels.hpp"
 
 using svf::DevBuf;
 
-namespace {
+namespace svf_detail {
 
 thread_local std::string g_err;
 
@@ -27,12 +28,6 @@ int hip_fail(hipError_t e, const char* what) {
   g_err = std::string(what) + ": " + hipGetErrorString(e);
   return e == hipErrorOutOfMemory ? SVF_E_NOMEM : SVF_E_DEVICE;
 }
-
-#define CK(call)                                         \
-  do {                                                   \
-    hipError_t e_ = (call);                              \
-    if (e_ != hipSuccess) return hip_fail(e_, #call);    \
-  } while (0)
 
 constexpr int kMaxBeam = 512;
 constexpr int kMaxEntries = 1024;
@@ -52,13 +47,6 @@ int visited_slots(const svf_index* ix, int E) {
   return T;
 }
 
-template <class T>
-int scratch(DevBuf& b, size_t count, T** out) {
-  hipError_t e = b.ensure(count * sizeof(T) + 16);
-  if (e != hipSuccess) return hip_fail(e, "scratch allocation");
-  *out = b.as<T>();
-  return SVF_OK;
-}
 
 // Grow the device arrays to hold `need` id slots, keeping the contents.
 int reserve(svf_index* ix, int64_t need) {
@@ -192,110 +180,141 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
   return ms;
 }
 
-// One insertion batch of b vectors already on the device (pitch dim).
-int insert_batch(svf_index* ix, const float* d_vecs, int64_t b, int32_t* d_out_ids,
-                 int32_t* h_out_ids) {
+// Insertion of one batch, in two parts.  insert_prepare stores the vectors in
+// slots beyond n_slots and runs the batched search, the forward prune and the
+// reverse-edge grouping and prune into staged rows: it only reads state that
+// searches also read, so searches may run beside it.  insert_commit writes
+// the staged rows, the new rows and the alive bits and advances n_slots.
+int insert_prepare(svf_index* ix, const float* d_vecs, int64_t b, PendingInsert* p) {
+  p->b = b;
+  p->n0 = ix->n_slots;
+  p->seed = ix->n_slots == 0;
+  p->n_targets = 0;
   if (b <= 0) return SVF_OK;
   int rc = reserve(ix, ix->n_slots + b);
   if (rc) return rc;
   hipStream_t st = ix->stream;
   const int R = ix->R;
   const int64_t n0 = ix->n_slots;
-  if (n0 == 0) {
+  if (p->seed) {
     // empty index: the seed rule (exact R-nearest among the seed vectors)
     if (b > 4 * R) return fail(SVF_E_INTERNAL, "seed batch larger than 4 * degree");
     rc = store_rows(ix, d_vecs, b, 0, st);
     if (rc) return rc;
     CK(svf::launch_seed(ix->vec32, ix->stride, ix->dim, ix->metric, (int)b, R, ix->graph,
                         ix->edge_d, st));
-    CK(svf::launch_set_alive(ix->alive, 0, b, st));
     CK(hipStreamSynchronize(st));
-    ix->n_slots = b;
-    ix->n_alive = b;
-  } else {
-    const int Lins = beam_insert(ix);
-    rc = store_rows(ix, d_vecs, b, n0, st);
-    if (rc) return rc;
-    uint64_t *qkey, *pool;
-    int32_t *fwd, *cnt;
-    float* fwd_d;
-    if ((rc = scratch(ix->s_qkey, b, &qkey)) || (rc = scratch(ix->s_pool, b * Lins, &pool)) ||
-        (rc = scratch(ix->s_misc[0], b * R, &fwd)) || (rc = scratch(ix->s_misc[1], b * R, &fwd_d)) ||
-        (rc = scratch(ix->s_misc[2], 8, &cnt)))
-      return rc;
-    // phase 1: batched search of the pre-batch graph
-    CK(hipEventRecord(ix->ev0, st));
-    svf::SearchArgs a = base_args(ix);
-    set_beam(a, ix, Lins);
-    a.max_iters = 0;
-    a.k = 0;
-    a.queries = ix->vec32 + n0 * ix->stride;
-    a.qstride = ix->stride;
-    a.nq = (int)b;
-    a.out_pool = pool;
-    a.n_slots = (int32_t)n0;
-    CK(svf::launch_query_keys(a.queries, a.qstride, nullptr, ix->dim, a.nq, ix->opt.seed, qkey, st));
-    a.qkey = qkey;
-    CK(svf::launch_search(a, ix->veclp_prec, st));
-    CK(hipEventRecord(ix->ev1, st));
-    ix->st.ins_search_ms = elapsed(ix->ev0, ix->ev1);
-    // phase 2: rank-based reordering of each candidate list -> forward rows
-    CK(hipEventRecord(ix->ev0, st));
-    svf::PruneArgs pa{};
-    pa.cand = pool;
-    pa.cstride = Lins;
-    pa.cap = prune_cap(ix);
-    pa.graph = ix->graph;
-    pa.fwd = nullptr;
-    pa.n_old = (int32_t)n0;
-    pa.R = R;
-    pa.out_ids = fwd;
-    pa.out_d = fwd_d;
-    pa.nlists = (int)b;
-    CK(svf::launch_prune_lists(pa, st));
-    CK(hipEventRecord(ix->ev1, st));
-    ix->st.ins_prune_ms = elapsed(ix->ev0, ix->ev1);
-    // phase 3: reverse edges grouped by target, re-pruned
-    CK(hipEventRecord(ix->ev0, st));
-    svf::ReverseArgs ra{};
-    ra.fwd_ids = fwd;
-    ra.fwd_d = fwd_d;
-    ra.b = (int)b;
-    ra.R = R;
-    ra.n0 = (int32_t)n0;
-    ra.tcount = tcount(ix);
-    ra.tidx = tidx(ix);
-    ra.graph = ix->graph;
-    ra.edge_d = ix->edge_d;
-    ra.alive = ix->alive;
-    ra.cap = prune_cap(ix);
-    const int64_t npairs = b * R;
-    if ((rc = scratch(ix->s_misc[3], npairs, &ra.tlist))) return rc;
-    ra.n_targets = cnt;
-    CK(svf::launch_fill_u32(cnt, 1, 0u, st));
-    CK(svf::launch_reverse_count(ra, st));
-    int32_t n_targets = 0;
-    CK(hipMemcpyAsync(&n_targets, cnt, 4, hipMemcpyDeviceToHost, st));
-    CK(hipStreamSynchronize(st));
-    if ((rc = scratch(ix->s_misc[4], n_targets + 1, &ra.off)) ||
-        (rc = scratch(ix->s_misc[5], (size_t)n_targets + 2 + n_targets / 1024 + 2, &ra.cursor)) ||
-        (rc = scratch(ix->s_misc[6], npairs, &ra.inc)) ||
-        (rc = scratch(ix->s_misc[7], (size_t)n_targets * R, &ra.trow)) ||
-        (rc = scratch(ix->s_misc[8], (size_t)n_targets * R, &ra.trow_d)))
-      return rc;
-    CK(svf::launch_reverse_scan_scatter(ra, n_targets, st));
-    CK(svf::launch_reverse_prune(ra, n_targets, st));
-    CK(hipEventRecord(ix->ev1, st));
-    ix->st.ins_reverse_ms = elapsed(ix->ev0, ix->ev1);
-    // phase 4: commit
-    CK(hipEventRecord(ix->ev0, st));
-    CK(svf::launch_commit_batch(ra, n_targets, ix->graph, ix->edge_d, ix->alive, st));
-    CK(hipEventRecord(ix->ev1, st));
-    CK(hipStreamSynchronize(st));
-    ix->st.ins_commit_ms = elapsed(ix->ev0, ix->ev1);
-    ix->n_slots = n0 + b;
-    ix->n_alive += b;
+    return SVF_OK;
   }
+  const int Lins = beam_insert(ix);
+  rc = store_rows(ix, d_vecs, b, n0, st);
+  if (rc) return rc;
+  uint64_t *qkey, *pool;
+  int32_t *fwd, *cnt;
+  float* fwd_d;
+  if ((rc = scratch(ix->s_qkey, b, &qkey)) || (rc = scratch(ix->s_pool, b * Lins, &pool)) ||
+      (rc = scratch(ix->s_misc[0], b * R, &fwd)) || (rc = scratch(ix->s_misc[1], b * R, &fwd_d)) ||
+      (rc = scratch(ix->s_misc[2], 8, &cnt)))
+    return rc;
+  // phase 1: batched search of the pre-batch graph
+  CK(hipEventRecord(ix->ev0, st));
+  svf::SearchArgs a = base_args(ix);
+  set_beam(a, ix, Lins);
+  a.max_iters = 0;
+  a.k = 0;
+  a.queries = ix->vec32 + n0 * ix->stride;
+  a.qstride = ix->stride;
+  a.nq = (int)b;
+  a.out_pool = pool;
+  a.n_slots = (int32_t)n0;
+  CK(svf::launch_query_keys(a.queries, a.qstride, nullptr, ix->dim, a.nq, ix->opt.seed, qkey, st));
+  a.qkey = qkey;
+  CK(svf::launch_search(a, ix->veclp_prec, st));
+  CK(hipEventRecord(ix->ev1, st));
+  ix->st.ins_search_ms = elapsed(ix->ev0, ix->ev1);
+  // phase 2: rank-based reordering of each candidate list -> forward rows
+  CK(hipEventRecord(ix->ev0, st));
+  svf::PruneArgs pa{};
+  pa.cand = pool;
+  pa.cstride = Lins;
+  pa.cap = prune_cap(ix);
+  pa.graph = ix->graph;
+  pa.fwd = nullptr;
+  pa.n_old = (int32_t)n0;
+  pa.R = R;
+  pa.out_ids = fwd;
+  pa.out_d = fwd_d;
+  pa.nlists = (int)b;
+  CK(svf::launch_prune_lists(pa, st));
+  CK(hipEventRecord(ix->ev1, st));
+  ix->st.ins_prune_ms = elapsed(ix->ev0, ix->ev1);
+  // phase 3: reverse edges grouped by target, re-pruned into staged rows
+  CK(hipEventRecord(ix->ev0, st));
+  svf::ReverseArgs& ra = p->ra;
+  ra = svf::ReverseArgs{};
+  ra.fwd_ids = fwd;
+  ra.fwd_d = fwd_d;
+  ra.b = (int)b;
+  ra.R = R;
+  ra.n0 = (int32_t)n0;
+  ra.tcount = tcount(ix);
+  ra.tidx = tidx(ix);
+  ra.graph = ix->graph;
+  ra.edge_d = ix->edge_d;
+  ra.alive = ix->alive;
+  ra.cap = prune_cap(ix);
+  const int64_t npairs = b * R;
+  if ((rc = scratch(ix->s_misc[3], npairs, &ra.tlist))) return rc;
+  ra.n_targets = cnt;
+  CK(svf::launch_fill_u32(cnt, 1, 0u, st));
+  CK(svf::launch_reverse_count(ra, st));
+  int32_t n_targets = 0;
+  CK(hipMemcpyAsync(&n_targets, cnt, 4, hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  if ((rc = scratch(ix->s_misc[4], n_targets + 1, &ra.off)) ||
+      (rc = scratch(ix->s_misc[5], (size_t)n_targets + 2 + n_targets / 1024 + 2, &ra.cursor)) ||
+      (rc = scratch(ix->s_misc[6], npairs, &ra.inc)) ||
+      (rc = scratch(ix->s_misc[7], (size_t)n_targets * R, &ra.trow)) ||
+      (rc = scratch(ix->s_misc[8], (size_t)n_targets * R, &ra.trow_d)))
+    return rc;
+  CK(svf::launch_reverse_scan_scatter(ra, n_targets, st));
+  CK(svf::launch_reverse_prune(ra, n_targets, st));
+  CK(hipEventRecord(ix->ev1, st));
+  ix->st.ins_reverse_ms = elapsed(ix->ev0, ix->ev1);
+  p->n_targets = n_targets;
+  return SVF_OK;
+}
+
+int insert_commit(svf_index* ix, PendingInsert* p) {
+  if (p->b <= 0) return SVF_OK;
+  hipStream_t st = ix->stream;
+  if (p->seed) {
+    CK(svf::launch_set_alive(ix->alive, 0, p->b, st));
+    CK(hipStreamSynchronize(st));
+    ix->n_slots = p->b;
+    ix->n_alive = p->b;
+    return SVF_OK;
+  }
+  CK(hipEventRecord(ix->ev0, st));
+  CK(svf::launch_commit_batch(p->ra, p->n_targets, ix->graph, ix->edge_d, ix->alive, st));
+  CK(hipEventRecord(ix->ev1, st));
+  CK(hipStreamSynchronize(st));
+  ix->st.ins_commit_ms = elapsed(ix->ev0, ix->ev1);
+  ix->n_slots = p->n0 + p->b;
+  ix->n_alive += p->b;
+  return SVF_OK;
+}
+
+// One insertion batch of b vectors already on the device (pitch dim).
+int insert_batch(svf_index* ix, const float* d_vecs, int64_t b, int32_t* d_out_ids,
+                 int32_t* h_out_ids) {
+  if (b <= 0) return SVF_OK;
+  PendingInsert p;
+  int rc = insert_prepare(ix, d_vecs, b, &p);
+  if (rc) return rc;
+  rc = insert_commit(ix, &p);
+  if (rc) return rc;
+  const int64_t n0 = p.n0;
   if (h_out_ids)
     for (int64_t i = 0; i < b; ++i) h_out_ids[i] = (int32_t)(n0 + i);
   if (d_out_ids) {
@@ -503,7 +522,42 @@ void finish_search_stats(svf_index* ix) {
   ix->st.last_search_ms = elapsed(ix->ev0, ix->ev1);
 }
 
-}  // namespace
+// Mark ids deleted (host ids, validated against n_slots first), then repair
+// or consolidate.  The caller holds the index.
+int delete_ids(svf_index* ix, const int32_t* ids, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (ids[i] < 0 || ids[i] >= ix->n_slots) return fail(SVF_E_NOTFOUND, "id out of range");
+  if (n == 0) return SVF_OK;
+  hipStream_t st = ix->stream;
+  int32_t *d, *cnt;
+  int rc;
+  if ((rc = scratch(ix->s_misc[9], n, &d)) || (rc = scratch(ix->s_tot, 2, &cnt))) return rc;
+  CK(hipEventRecord(ix->ev0, st));
+  CK(hipMemcpyAsync(d, ids, n * 4, hipMemcpyHostToDevice, st));
+  CK(svf::launch_fill_u32(cnt, 1, 0u, st));
+  CK(svf::launch_mark_deleted(d, n, ix->alive, cnt, st));
+  int32_t newly = 0;
+  CK(hipMemcpyAsync(&newly, cnt, 4, hipMemcpyDeviceToHost, st));
+  CK(hipEventRecord(ix->ev1, st));
+  CK(hipStreamSynchronize(st));
+  ix->st.del_mark_ms = elapsed(ix->ev0, ix->ev1);
+  if (ix->alive_at_consolidate == 0) ix->alive_at_consolidate = ix->n_alive;
+  ix->n_alive -= newly;
+  ix->deleted_since += newly;
+  if (newly == 0) return SVF_OK;
+  if ((double)ix->deleted_since >= ix->opt.consolidate_frac * (double)ix->alive_at_consolidate) {
+    rc = repair(ix, 1);
+    ix->deleted_since = 0;
+    ix->alive_at_consolidate = ix->n_alive;
+  } else {
+    rc = repair(ix, 0);
+  }
+  return rc;
+}
+
+}  // namespace svf_detail
+
+using namespace svf_detail;
 
 // ===========================================================================
 extern "C" {
@@ -540,6 +594,7 @@ int svf_create(int32_t dim, int32_t degree, int32_t metric, svf_index** out) {
 
 int svf_destroy(svf_index* ix) {
   if (!ix) return SVF_OK;
+  if (ix->server) serve_shutdown(ix);
   {
     std::lock_guard<std::mutex> g(ix->mu);
     if (ix->stream) (void)hipStreamSynchronize(ix->stream);
@@ -596,6 +651,8 @@ int svf_set_option(svf_index* ix, const char* key, double v) {
   } else if (k == "insert_batch_max") {
     if (!is_int(v) || v < 1 || v > (1 << 20)) return fail(SVF_E_INVAL, "insert_batch_max in [1, 2^20]");
     o.insert_batch_max = (int)v;
+  } else if (ix->server && (k == "precision" || k == "use_model")) {
+    return fail(SVF_E_BUSY, "option cannot change while serving");
   } else if (k == "precision") {
     if (v != 0 && v != 1 && v != 2) return fail(SVF_E_INVAL, "precision 0 (FP32), 1 (FP16) or 2 (BF16)");
     o.precision = (int)v;
@@ -647,6 +704,7 @@ int svf_get_option(const svf_index* ix, const char* key, double* out) {
 }
 
 int svf_insert_dev(svf_index* ix, const float* d_vecs, int64_t n, int32_t* d_out_ids, void* stream) {
+  if (ix && ix->server) return fail(SVF_E_BUSY, "index is serving: use svf_submit_insert");
   if (!ix || (n > 0 && !d_vecs)) return fail(SVF_E_INVAL, "null argument");
   if (n < 0) return fail(SVF_E_INVAL, "n < 0");
   std::lock_guard<std::mutex> g(ix->mu);
@@ -655,6 +713,7 @@ int svf_insert_dev(svf_index* ix, const float* d_vecs, int64_t n, int32_t* d_out
 }
 
 int svf_insert(svf_index* ix, const float* vecs, int64_t n, int32_t* out_ids) {
+  if (ix && ix->server) return fail(SVF_E_BUSY, "index is serving: use svf_submit_insert");
   if (!ix || (n > 0 && !vecs)) return fail(SVF_E_INVAL, "null argument");
   if (n < 0) return fail(SVF_E_INVAL, "n < 0");
   if (n == 0) return SVF_OK;
@@ -668,6 +727,7 @@ int svf_insert(svf_index* ix, const float* vecs, int64_t n, int32_t* out_ids) {
 }
 
 int svf_build(svf_index* ix, const float* vecs, int64_t n) {
+  if (ix && ix->server) return fail(SVF_E_BUSY, "index is serving: stop serving first");
   if (!ix || (n > 0 && !vecs)) return fail(SVF_E_INVAL, "null argument");
   if (n < 1) return fail(SVF_E_INVAL, "n must be >= 1");
   if (ix->n_slots != 0) return fail(SVF_E_INVAL, "build needs an empty index");
@@ -684,38 +744,13 @@ int svf_build(svf_index* ix, const float* vecs, int64_t n) {
 int svf_delete(svf_index* ix, const int32_t* ids, int64_t n) {
   if (!ix || (n > 0 && !ids)) return fail(SVF_E_INVAL, "null argument");
   if (n < 0) return fail(SVF_E_INVAL, "n < 0");
+  if (ix->server) return fail(SVF_E_BUSY, "index is serving: use svf_submit_delete");
   std::lock_guard<std::mutex> g(ix->mu);
-  for (int64_t i = 0; i < n; ++i)
-    if (ids[i] < 0 || ids[i] >= ix->n_slots) return fail(SVF_E_NOTFOUND, "id out of range");
-  if (n == 0) return SVF_OK;
-  hipStream_t st = ix->stream;
-  int32_t *d, *cnt;
-  int rc;
-  if ((rc = scratch(ix->s_misc[9], n, &d)) || (rc = scratch(ix->s_tot, 2, &cnt))) return rc;
-  CK(hipEventRecord(ix->ev0, st));
-  CK(hipMemcpyAsync(d, ids, n * 4, hipMemcpyHostToDevice, st));
-  CK(svf::launch_fill_u32(cnt, 1, 0u, st));
-  CK(svf::launch_mark_deleted(d, n, ix->alive, cnt, st));
-  int32_t newly = 0;
-  CK(hipMemcpyAsync(&newly, cnt, 4, hipMemcpyDeviceToHost, st));
-  CK(hipEventRecord(ix->ev1, st));
-  CK(hipStreamSynchronize(st));
-  ix->st.del_mark_ms = elapsed(ix->ev0, ix->ev1);
-  if (ix->alive_at_consolidate == 0) ix->alive_at_consolidate = ix->n_alive;
-  ix->n_alive -= newly;
-  ix->deleted_since += newly;
-  if (newly == 0) return SVF_OK;
-  if ((double)ix->deleted_since >= ix->opt.consolidate_frac * (double)ix->alive_at_consolidate) {
-    rc = repair(ix, 1);
-    ix->deleted_since = 0;
-    ix->alive_at_consolidate = ix->n_alive;
-  } else {
-    rc = repair(ix, 0);
-  }
-  return rc;
+  return delete_ids(ix, ids, n);
 }
 
 int svf_consolidate(svf_index* ix) {
+  if (ix && ix->server) return fail(SVF_E_BUSY, "index is serving: stop serving first");
   if (!ix) return fail(SVF_E_INVAL, "null index");
   std::lock_guard<std::mutex> g(ix->mu);
   int rc = repair(ix, 1);
@@ -727,6 +762,7 @@ int svf_consolidate(svf_index* ix) {
 int svf_search_dev(svf_index* ix, const float* d_queries, int64_t nq, int32_t k, int32_t beam,
                    int32_t* d_out_ids, float* d_out_dists, int32_t* d_n_dist, int32_t* d_n_exp,
                    void* stream) {
+  if (ix && ix->server) return fail(SVF_E_BUSY, "index is serving: use svf_submit_search");
   int rc = check_search_args(ix, nq, k, beam);
   if (rc) return rc;
   if (nq > 0 && (!d_queries || !d_out_ids || !d_out_dists)) return fail(SVF_E_INVAL, "null buffer");
@@ -737,6 +773,7 @@ int svf_search_dev(svf_index* ix, const float* d_queries, int64_t nq, int32_t k,
 
 int svf_search(svf_index* ix, const float* queries, int64_t nq, int32_t k, int32_t beam,
                int32_t* out_ids, float* out_dists) {
+  if (ix && ix->server) return fail(SVF_E_BUSY, "index is serving: use svf_submit_search");
   int rc = check_search_args(ix, nq, k, beam);
   if (rc) return rc;
   if (nq == 0) return SVF_OK;
@@ -762,6 +799,7 @@ int svf_search(svf_index* ix, const float* queries, int64_t nq, int32_t k, int32
 int svf_search_listed(svf_index* ix, const float* queries, int64_t nq, int32_t k, int32_t beam,
                       const int32_t* entries, int32_t ecap, const int32_t* max_iters,
                       int32_t* out_ids, float* out_dists) {
+  if (ix && ix->server) return fail(SVF_E_BUSY, "index is serving: stop serving first");
   int rc = check_search_args(ix, nq, k, beam);
   if (rc) return rc;
   if (nq == 0) return SVF_OK;
@@ -814,6 +852,7 @@ int svf_search_listed(svf_index* ix, const float* queries, int64_t nq, int32_t k
 
 int svf_model_fit(svf_index* ix, const float* train_queries, int64_t n, int32_t k, int32_t beam,
                   int32_t n_clusters, int32_t epochs, float* last_loss) {
+  if (ix && ix->server) return fail(SVF_E_BUSY, "index is serving: stop serving first");
   int rc = check_search_args(ix, n, k, beam);
   if (rc) return rc;
   if (!train_queries || n < 1024) return fail(SVF_E_INVAL, "need at least 1024 training queries");
@@ -927,6 +966,7 @@ int svf_export_graph(const svf_index* cix, int32_t* rows, float* edge_d, uint8_t
 
 int svf_import_graph(svf_index* ix, const float* vecs, int64_t n, const int32_t* rows,
                      const float* edge_d, const uint8_t* alive) {
+  if (ix && ix->server) return fail(SVF_E_BUSY, "index is serving: stop serving first");
   if (!ix || (n > 0 && (!vecs || !rows || !edge_d || !alive))) return fail(SVF_E_INVAL, "null argument");
   if (n < 0) return fail(SVF_E_INVAL, "n < 0");
   std::lock_guard<std::mutex> g(ix->mu);

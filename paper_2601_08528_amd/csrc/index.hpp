@@ -56,6 +56,8 @@ struct Options {
 
 }  // namespace svf
 
+namespace svf { struct Server; }
+
 struct svf_index {
   int dim = 0, R = 0, metric = 0;
   int64_t stride = 0;                // stored row length in elements (multiple of 8)
@@ -80,4 +82,5 @@ struct svf_index {
   int model_nc = 0, entry_cap = 0;
   svf::DevBuf centroids, entry_lists, s_z, s_qentry, s_qmax;
   svf_stats st{};
+  svf::Server* server = nullptr;   // non-null while the serving loop runs
 };

@@ -1,0 +1,49 @@
+// Internal helpers of the index shared by the C ABI (index.hip) and the
+// serving runtime (serve.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "index.hpp"
+#include "kernels.hpp"
+
+namespace svf_detail {
+
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define CK(call)                                         \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return svf_detail::hip_fail(e_, #call); \
+  } while (0)
+
+template <class T>
+int scratch(svf::DevBuf& b, size_t count, T** out) {
+  hipError_t e = b.ensure(count * sizeof(T) + 16);
+  if (e != hipSuccess) return hip_fail(e, "scratch allocation");
+  *out = b.as<T>();
+  return SVF_OK;
+}
+
+struct PendingInsert {
+  bool seed = false;
+  int64_t n0 = 0, b = 0;
+  int n_targets = 0;
+  svf::ReverseArgs ra{};
+};
+
+int reserve(svf_index* ix, int64_t need);
+int insert_prepare(svf_index* ix, const float* d_vecs, int64_t b, PendingInsert* p);
+int insert_commit(svf_index* ix, PendingInsert* p);
+int repair(svf_index* ix, int consolidate);
+int delete_ids(svf_index* ix, const int32_t* ids, int64_t n);
+svf::SearchArgs base_args(const svf_index* ix);
+void set_beam(svf::SearchArgs& a, const svf_index* ix, int L);
+int check_search_args(const svf_index* ix, int64_t nq, int k, int beam);
+bool all_finite(const float* p, int64_t n);
+int beam_insert(const svf_index* ix);
+void serve_shutdown(svf_index* ix);
+
+}  // namespace svf_detail

@@ -1,0 +1,112 @@
+"""Serving loop: every search in a concurrent mix of searches, inserts and
+deletes returns exactly what the same search returns alone against the
+state of its epoch, replayed one request at a time; reads after a waited-for
+insert see the insert; admission refuses what can never fit."""
+import numpy as np
+import pytest
+
+import paper_2601_08528_amd as svf
+from paper_2601_08528_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+def make(base, **opt):
+    g = svf.Index(64, 24, svf.METRIC_L2, seed=3, insert_batch_max=512, **opt)
+    g.build(base)
+    return g
+
+
+def test_mix_equals_alone_replay():
+    base, q = datagen.gmm_uint8_valued(601, 9000, 600, 64, 32)
+    build, extra = base[:6000], base[6000:]
+    rng = np.random.Generator(np.random.Philox(2))
+    # request stream: inserts of <= 512 vectors, deletes of live ids, searches of 1..300 queries
+    reqs = []
+    pos, qpos = 0, 0
+    live = list(range(6000))
+    for step in range(24):
+        kind = rng.choice(["search", "search", "search", "insert", "delete"])
+        if kind == "insert" and pos < len(extra):
+            n = int(rng.integers(50, 512))
+            reqs.append(("insert", extra[pos:pos + n]))
+            live += list(range(6000 + pos, 6000 + pos + n))
+            pos += n
+        elif kind == "delete":
+            vic = rng.choice(live, 60, replace=False)
+            live = [x for x in live if x not in set(vic.tolist())]
+            reqs.append(("delete", vic.astype(np.int32)))
+        else:
+            n = int(rng.integers(1, 300))
+            idx = rng.integers(0, q.shape[0], n)
+            reqs.append(("search", q[idx]))
+    served = make(build)
+    served.serve_start(streams=4, max_batch=256)
+    tickets = []
+    for kind, data in reqs:
+        if kind == "search":
+            t, ids, d = served.submit_search(data, 10, 32)
+            tickets.append((t, kind, data, ids, d))
+        elif kind == "insert":
+            t, ids = served.submit_insert(data)
+            tickets.append((t, kind, data, ids, None))
+        else:
+            tickets.append((served.submit_delete(data), kind, data, None, None))
+    infos = [served.wait(t[0], 120.0) for t in tickets]
+    served.serve_stop()
+    # replay: mutations in arrival order; each search alone at its epoch
+    alone = make(build)
+    epoch = 0
+    mut = [(i, t) for i, t in enumerate(tickets) if t[1] != "search"]
+    srch = [(i, t) for i, t in enumerate(tickets) if t[1] == "search"]
+    by_epoch = {}
+    for i, t in srch:
+        by_epoch.setdefault(infos[i]["epoch"], []).append((i, t))
+    checked = 0
+    for e in range(len(mut) + 1):
+        for i, t in by_epoch.get(e, []):
+            ids, d = alone.search(t[2], 10, 32)
+            np.testing.assert_array_equal(ids, t[3])
+            np.testing.assert_array_equal(d, t[4])
+            checked += 1
+        if e < len(mut):
+            i, t = mut[e]
+            assert infos[i]["epoch"] == e + 1
+            if t[1] == "insert":
+                np.testing.assert_array_equal(alone.insert(t[2]), t[3])
+            else:
+                alone.delete(t[2])
+    assert checked == len(srch)
+    np.testing.assert_array_equal(served.export_graph()[0], alone.export_graph()[0])
+    assert max(inf["batch_queries"] for inf in infos) > 1
+
+
+def test_read_after_write_and_busy_calls():
+    base, q = datagen.gmm_uint8_valued(602, 5000, 50, 64, 16)
+    g = make(base[:4000])
+    g.serve_start(streams=2, max_batch=1024)
+    with pytest.raises(svf.SvfError) as e:
+        g.search(q, 10, 32)
+    assert e.value.code == svf.E_BUSY
+    t, new_ids = g.submit_insert(base[4000:4400])
+    g.wait(t, 60.0)
+    t, ids, d = g.submit_search(base[4000:4400], 1, 32)
+    g.wait(t, 60.0)
+    # each freshly inserted vector finds itself (an exact duplicate at distance 0)
+    assert (d[:, 0] == 0).all()
+    assert np.isin(ids[:, 0], new_ids).mean() > 0.99
+    g.serve_stop()
+    g.search(q, 10, 32)                                  # direct calls work again
+
+
+def test_admission_refuses_what_never_fits():
+    base, q = datagen.gmm_uint8_valued(603, 3000, 600, 64, 8)
+    g = make(base)
+    g.serve_start(streams=2, max_batch=4096, hbm_budget=64 * 1024)
+    t, ids, d = g.submit_search(q[:600], 10, 32)        # 600 x (256 + 80 + 8) B > 64 KiB
+    with pytest.raises(svf.SvfError) as e:
+        g.wait(t, 60.0)
+    assert e.value.code == svf.E_NOMEM
+    t, ids, d = g.submit_search(q[:20], 10, 32)
+    g.wait(t, 60.0)
+    g.serve_stop()
