@@ -82,7 +82,8 @@ int svf_destroy(svf_index *ix);
  *   seed            entry-point hash seed (any; 0)
  *   beam_insert     candidate pool size of the insertion search (degree..512; 2*degree)
  *   entry_samples   random entry points per query, 0 = the pool size (0..1024; 0)
- *   max_iters       cap on expansions per query, 0 = none (>= 0; 0)
+ *   max_iters       cap on iterations per query, 0 = none (>= 0; 0)
+ *   search_width    parents expanded per iteration (1..4; 1)
  *   visited_slots   LDS visited-table slots per query, power of two (256..8192; 4096)
  *   visited_compact 16-bit visited tags in 4-way sets when the ids fit (0/1; 1)
  *   repair_c        out-neighbours taken from each deleted neighbour (1..min(16, degree); 8)
@@ -138,7 +139,7 @@ int svf_search(svf_index *ix, const float *queries, int64_t nq, int32_t k, int32
 
 /* Device-pointer search, enqueued on `stream` without waiting.  Optional
  * d_n_dist / d_n_exp (nq int32 each, may be NULL) receive per-query counts of
- * distance evaluations and expansions. */
+ * distance evaluations and expanded vertices. */
 int svf_search_dev(svf_index *ix, const float *d_queries, int64_t nq, int32_t k, int32_t beam,
                    int32_t *d_out_ids, float *d_out_dists, int32_t *d_n_dist, int32_t *d_n_exp,
                    void *stream);

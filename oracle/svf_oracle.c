@@ -1016,21 +1016,24 @@ static int search_one_listed(const orc_index *ix, const float *qf, const double 
     int32_t lc = 0;
     for (;;) {
         if (max_iters > 0 && st->iters >= max_iters) break;
-        int par = -1;
-        for (int i = 0; i < np; ++i) if (!s->pool[i].expanded) { par = i; break; }
-        if (par < 0) break;
-        s->pool[par].expanded = 1;
-        ++st->n_exp;
-        const int32_t *row = ix->rows + (int64_t)s->pool[par].id * R;
+        int parents[8], npar = 0;
+        for (int i = 0; i < np && npar < ix->search_width; ++i)
+            if (!s->pool[i].expanded) parents[npar++] = i;
+        if (npar == 0) break;
         int nf = 0;
-        for (int r = 0; r < R; ++r) {
-            int32_t u = row[r];
-            if (u < 0 || u >= ix->n_slots || !ix->alive[u] || s->visited[u]) continue;
-            visit(s, u);
-            s->fresh[nf].id = u;
-            s->fresh[nf].d = dist(ix->metric, q_lp, V + (int64_t)u * d, d);
-            s->fresh[nf].expanded = 0;
-            ++nf; ++st->n_dist;
+        for (int t = 0; t < npar; ++t) {
+            s->pool[parents[t]].expanded = 1;
+            ++st->n_exp;
+            const int32_t *row = ix->rows + (int64_t)s->pool[parents[t]].id * R;
+            for (int r = 0; r < R; ++r) {
+                int32_t u = row[r];
+                if (u < 0 || u >= ix->n_slots || !ix->alive[u] || s->visited[u]) continue;
+                visit(s, u);
+                s->fresh[nf].id = u;
+                s->fresh[nf].d = dist(ix->metric, q_lp, V + (int64_t)u * d, d);
+                s->fresh[nf].expanded = 0;
+                ++nf; ++st->n_dist;
+            }
         }
         ++st->iters;
         memcpy(s->merged, s->pool, np * sizeof(pentry));

@@ -171,6 +171,7 @@ void set_beam(svf::SearchArgs& a, const svf_index* ix, int L) {
   a.T = visited_slots(ix, a.E);
   a.rerank = (ix->veclp_prec != 0 && ix->opt.rerank) ? 1 : 0;
   a.vis_compact = ix->opt.visited_compact;
+  a.width = ix->opt.search_width;
 }
 
 float elapsed(hipEvent_t a, hipEvent_t b) {
@@ -629,6 +630,9 @@ int svf_set_option(svf_index* ix, const char* key, double v) {
   } else if (k == "entry_samples") {
     if (!is_int(v) || v < 0 || v > kMaxEntries) return fail(SVF_E_INVAL, "entry_samples in [0, 1024]");
     o.entry_samples = (int)v;
+  } else if (k == "search_width") {
+    if (!is_int(v) || v < 1 || v > 4) return fail(SVF_E_INVAL, "search_width in [1, 4]");
+    o.search_width = (int)v;
   } else if (k == "max_iters") {
     if (!is_int(v) || v < 0 || v > 1e9) return fail(SVF_E_INVAL, "max_iters >= 0");
     o.max_iters = (int)v;
@@ -687,6 +691,7 @@ int svf_get_option(const svf_index* ix, const char* key, double* out) {
   else if (k == "beam_insert") *out = beam_insert(ix);
   else if (k == "entry_samples") *out = o.entry_samples;
   else if (k == "max_iters") *out = o.max_iters;
+  else if (k == "search_width") *out = o.search_width;
   else if (k == "visited_slots") *out = o.visited_slots;
   else if (k == "visited_compact") *out = o.visited_compact;
   else if (k == "repair_c") *out = o.repair_c;

@@ -39,6 +39,7 @@ struct Options {
   int beam_insert = 0;        // 0: 2 * degree
   int entry_samples = 0;
   int max_iters = 0;
+  int search_width = 1;
   int visited_slots = 4096;
   int visited_compact = 1;
   int repair_c = 8;

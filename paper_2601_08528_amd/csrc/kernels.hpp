@@ -19,6 +19,7 @@ struct SearchArgs {
   int metric;               // 0 = squared L2, 1 = -inner product
   // search parameters
   int L, L_pow2, k, E, max_iters, T, rerank;
+  int width;                // parents expanded per iteration (1..4)
   int vis_compact;          // allow 16-bit visited tags when ids fit
   int id_bits;              // set by the launcher
   // queries
@@ -37,8 +38,8 @@ struct SearchArgs {
   const int32_t* entry_lists;  // nlists x entry_cap ids (-1 padded)
   int entry_cap;
   const int32_t* q_entry;      // per query: list index, or -1 for random entries
-  const int32_t* q_max_iters;  // per query expansion cap (0: none)
-  int32_t* last_change;        // per query: expansions done when the top-k last changed
+  const int32_t* q_max_iters;  // per query iteration cap (0: none)
+  int32_t* last_change;        // per query: iterations done when the top-k last changed
   unsigned long long* totals;  // [0] distances, [1] expansions
 };
 

@@ -126,42 +126,53 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
   }
 
   // ---- repeat: nearest unexpanded -> neighbours -> distances -> update ------
+  // Each iteration expands the `width` smallest unexpanded entries (one by
+  // default); their rows are filtered, gathered and merged chunk by chunk,
+  // which equals one merge of all new keys (the top-L of a union).
   const int cap_iters = (a.q_max_iters && a.q_max_iters[qi] > 0) ? a.q_max_iters[qi] : a.max_iters;
-  int last_change = 0;
+  int last_change = 0, n_iter = 0;
   for (;;) {
-    if (cap_iters > 0 && n_exp >= cap_iters) break;
-    int ppos = -1;
-    for (int b0 = 0; b0 < a.L; b0 += kWave) {
+    if (cap_iters > 0 && n_iter >= cap_iters) break;
+    int ppos[4];
+    int np = 0;
+    for (int b0 = 0; b0 < a.L && np < a.width; b0 += kWave) {
       const int i = b0 + lane;
       const bool un = i < a.L && (w.pool[i] & 1ull) == 0;
-      const uint64_t bm = ballot(un);
-      if (bm) { ppos = b0 + __ffsll((unsigned long long)bm) - 1; break; }
+      uint64_t bm = ballot(un);
+      while (bm && np < a.width) {
+        ppos[np++] = b0 + __ffsll((unsigned long long)bm) - 1;
+        bm &= bm - 1;
+      }
     }
-    if (ppos < 0) break;
-    const uint64_t pk = w.pool[ppos];
-    const int32_t parent = key_id(pk);
+    if (np == 0) break;
+    int32_t parents[4];
+    for (int t = 0; t < np; ++t) parents[t] = key_id(w.pool[ppos[t]]);
     __syncthreads();
-    if (lane == 0) w.pool[ppos] = pk | 1ull;
-    ++n_exp;
-    const int32_t* row = a.graph + (int64_t)parent * a.R;
-    for (int r0 = 0; r0 < a.R; r0 += kWave) {
-      const int rr = r0 + lane;
-      const int32_t nb = rr < a.R ? row[rr] : -1;
-      bool ok = nb >= 0 && nb < a.n_slots;
-      __syncthreads();
-      if (ok) ok = !vis.test_and_set(nb);
-      const uint64_t ob = ballot(ok);
-      if (ok) w.cid[lanes_below(ob)] = nb;
-      const int m = popc64(ob);
-      __syncthreads();
-      if (m == 0) continue;
-      // the deletion bits load while the vectors are gathered
-      const int32_t mine = lane < m ? w.cid[lane] : 0;
-      const uint32_t aword = a.alive[(uint32_t)mine >> 5];
-      uint64_t k = gather_keys<VT, NC>(qs, base, a.stride, w.cid, m, a.metric);
-      if (lane < m && !((aword >> (mine & 31)) & 1u)) k = kKeyInf;
-      n_dist += m;
-      if (sort_merge(w, k)) last_change = n_exp;
+    if (lane == 0)
+      for (int t = 0; t < np; ++t) w.pool[ppos[t]] |= 1ull;
+    n_exp += np;
+    ++n_iter;
+    for (int t = 0; t < np; ++t) {
+      const int32_t* row = a.graph + (int64_t)parents[t] * a.R;
+      for (int r0 = 0; r0 < a.R; r0 += kWave) {
+        const int rr = r0 + lane;
+        const int32_t nb = rr < a.R ? row[rr] : -1;
+        bool ok = nb >= 0 && nb < a.n_slots;
+        __syncthreads();
+        if (ok) ok = !vis.test_and_set(nb);
+        const uint64_t ob = ballot(ok);
+        if (ok) w.cid[lanes_below(ob)] = nb;
+        const int m = popc64(ob);
+        __syncthreads();
+        if (m == 0) continue;
+        // the deletion bits load while the vectors are gathered
+        const int32_t mine = lane < m ? w.cid[lane] : 0;
+        const uint32_t aword = a.alive[(uint32_t)mine >> 5];
+        uint64_t k = gather_keys<VT, NC>(qs, base, a.stride, w.cid, m, a.metric);
+        if (lane < m && !((aword >> (mine & 31)) & 1u)) k = kKeyInf;
+        n_dist += m;
+        if (sort_merge(w, k)) last_change = n_iter;
+      }
     }
   }
 

@@ -50,6 +50,23 @@ def test_search_bit_exact_integer_l2(int_l2, beam):
     np.testing.assert_array_equal(hi, oi)
 
 
+@pytest.mark.parametrize("width", [2, 4])
+def test_search_width_bit_exact(int_l2, width):
+    """Several parents per iteration (a method option the oracle implements)."""
+    oix, base, q = int_l2
+    g = gpu_from_oracle(oix, base, seed=11, search_width=width)
+    oix.set("search_width", width)
+    try:
+        oi, od, ost = oix.search(q, 10, 64)
+        ol, olc = oix.search_trace(q, 10, 64)
+    finally:
+        oix.set("search_width", 1)
+    gi, gd, gnd, gne = dev_search(g, q, 10, 64)
+    np.testing.assert_array_equal(gi, oi)
+    np.testing.assert_array_equal(gd.astype(np.float64), od)
+    np.testing.assert_array_equal(gne, ost["n_exp"])
+
+
 def test_search_ragged_shapes_inner_product():
     """dim 200 (two 128-chunks, ragged), degree 48 (partial wave), IP metric."""
     base, q = datagen.gmm_uint8_valued(202, 2500, 67, 200, 9)

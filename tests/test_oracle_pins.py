@@ -106,6 +106,22 @@ def test_full_width_pool_equals_bruteforce(small_index):
     np.testing.assert_array_equal(d, gd)
 
 
+@pytest.mark.parametrize("width", [2, 3])
+def test_wider_expansion_full_pool_equals_bruteforce(small_index, width):
+    """Several parents per iteration: a pool as wide as the data is exhaustive."""
+    ix, base, q = small_index
+    ix.set("search_width", width)
+    ix.set("entry_samples", 4096)
+    try:
+        ids, d, st = ix.search(q, 10, 300)
+        assert (st["n_exp"] <= width * st["iters"]).all() and (st["n_exp"] == 300).all()
+    finally:
+        ix.set("search_width", 1)
+        ix.set("entry_samples", 0)
+    gi, gd = O.bruteforce(base, q, 10)
+    np.testing.assert_array_equal(ids, gi)
+
+
 def _reachable_all(rows, alive):
     n = rows.shape[0]
     for s in range(0, n, max(1, n // 7)):
