@@ -98,6 +98,63 @@ def sweep(torch, ix, q_t, base_t, kth, bufs, beams, target=0.95):
     return chosen, rows
 
 
+def serving_bench(svf, datagen, rounds=40, rate_hz=120.0):
+    """Streaming mix on the serving loop: a 1M-vector unit-norm 96-d mixture
+    (1024 components, inner product, degree 48, BF16 traversal + FP32
+    re-score), then `rounds` rounds of [one 10k-vector insert, one 1k-id
+    delete of uniformly chosen live ids, four query batches of log-uniform
+    size 1..10k with Zipf(1.1)-skewed components], as open-loop Poisson
+    arrivals at rate_hz requests per second."""
+    n_build = 1_000_000
+    base, queries = datagen.workload_stream_ip(n_build + rounds * 10_000, 20_000)
+    ix = svf.Index(96, 48, svf.METRIC_IP, seed=0, precision=svf.PREC_BF16)
+    t0 = time.perf_counter()
+    ix.build(base[:n_build])
+    build_s = time.perf_counter() - t0
+    reqs = datagen.request_stream(rounds, 10_000, 1_000, 4, 10_000, rate_hz)
+    g = np.random.Generator(np.random.Philox(31))
+    victims = g.permutation(n_build).astype(np.int32)
+    ix.serve_start(streams=4, max_batch=16384)
+    tickets = []
+    pos_ins, pos_del, pos_q = n_build, 0, 0
+    keep = []
+    t_start = time.perf_counter()
+    for r in reqs:
+        now = time.perf_counter() - t_start
+        if r.arrival_s > now:
+            time.sleep(r.arrival_s - now)
+        if r.kind == "insert":
+            t, ids = ix.submit_insert(base[pos_ins:pos_ins + r.size])
+            pos_ins += r.size
+            keep.append(ids)
+        elif r.kind == "delete":
+            t = ix.submit_delete(victims[pos_del:pos_del + r.size])
+            pos_del += r.size
+        else:
+            idx = (pos_q + np.arange(r.size)) % queries.shape[0]
+            pos_q += r.size
+            t, ids, d = ix.submit_search(queries[idx], 10, 64)
+            keep.append((ids, d))
+        tickets.append((t, r.kind, r.size))
+    infos = [(kind, size, ix.wait(t, 300.0)) for t, kind, size in tickets]
+    wall = time.perf_counter() - t_start
+    ix.serve_stop()
+    out = {"workload": "1M x 96 unit-norm GMM (1024 comps, Zipf(1.1) queries), IP, degree 48, "
+                       "BF16 + FP32 re-score, k=10, beam 64; %d rounds of insert 10k / delete 1k / "
+                       "4 query batches 1..10k, Poisson %.0f req/s" % (rounds, rate_hz),
+           "build_s": round(build_s, 2), "wall_s": round(wall, 3)}
+    nq = sum(size for kind, size, _ in infos if kind == "search")
+    out["qps"] = round(nq / wall, 1)
+    for kind in ("search", "insert", "delete"):
+        lat = np.array([inf["total_ms"] for k, _, inf in infos if k == kind])
+        if lat.size:
+            out[kind] = {"n": int(lat.size), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                         "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                         "mean_ms": round(float(lat.mean()), 3)}
+    out["max_batch_queries"] = int(max(inf["batch_queries"] for _, _, inf in infos))
+    return out
+
+
 def cpu_baseline(base, queries, beam):
     """The FP64 oracle, as it stands, on a bounded sample: it builds its own
     index over the first 20,000 base vectors (same generator) and searches
@@ -126,6 +183,7 @@ def main():
     ap.add_argument("--n-base", type=int, default=1_000_000)
     ap.add_argument("--n-query", type=int, default=10_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -180,16 +238,47 @@ def main():
     achieved = alg_bytes / (ms_step / 1e3) / 1e9
     qps = nq / (ms_step / 1e3)
 
-    # reduced-precision form: BF16 traversal + exact FP32 re-scoring
+    # chosen form: BF16 traversal + exact FP32 re-score, with the learned
+    # entry/stop predictor trained on the GPU from traces of plain search
     ix.set_option("precision", svf.PREC_BF16)
     beam_bf, rows_bf = sweep(torch, ix, q_t, base_t, kth, bufs, BEAMS)
-    if beam_bf is None:
-        beam_bf = BEAMS[-1]
-    ms_bf, _ = timed_steps(torch, ix, q_t, beam_bf, bufs, args.steps, args.warmup)
-    rec_bf = recall(torch, base_t, q_t, bufs[0], kth)
+    ms_bf, _ = timed_steps(torch, ix, q_t, beam_bf or BEAMS[-1], bufs, 5, 1)
+    bf_only = {"beam": beam_bf, "ms_per_step": round(float(np.mean(ms_bf)), 4),
+               "value": round(nq / (float(np.mean(ms_bf)) / 1e3), 1)}
+    ix.set_option("precision", svf.PREC_FP32)
+    train = datagen.training_queries_uint8(2, 200_000, DIM, 256)
+    t0 = time.perf_counter()
+    fit_loss = ix.model_fit(train, K, 64, n_clusters=256, epochs=12)
+    fit_s = time.perf_counter() - t0
+    ix.set_option("precision", svf.PREC_BF16)
+    ix.set_option("use_model", 1)
+    ix.set_option("model_conf", 0.0)
+    best = None
+    tried = []
+    for width, stop_scale in ((1, 2.0), (2, 1.0), (2, 1.5), (1, 1e6)):
+        ix.set_option("search_width", width)
+        ix.set_option("model_stop_scale", stop_scale)
+        b, rws = sweep(torch, ix, q_t, base_t, kth, bufs, [32, 48, 64, 96, 128])
+        tried.append({"search_width": width, "stop_scale": stop_scale, "beam": b, "sweep": rws})
+        if b is not None:
+            ms_c = [r["ms"] for r in rws if r["beam"] == b][0]
+            if best is None or ms_c < best[0]:
+                best = (ms_c, width, stop_scale, b)
+    if best is None:
+        best = (None, 1, 1e6, BEAMS[-1])
+    _, cw, css, beam_c = best
+    ix.set_option("search_width", cw)
+    ix.set_option("model_stop_scale", css)
+    ms_c, _ = timed_steps(torch, ix, q_t, beam_c, bufs, args.steps, args.warmup)
+    rec_c = recall(torch, base_t, q_t, bufs[0], kth)
     maxerr = float((bufs[1].double() - ((base_t[bufs[0].long()].double()
                                          - q_t[:, None, :].double()) ** 2).sum(-1)).abs().max())
+    ix.set_option("use_model", 0)
+    ix.set_option("search_width", 1)
     ix.set_option("precision", svf.PREC_FP32)
+    rec_bf = rec_c
+    ms_bf = ms_c
+    beam_bf = beam_c
 
     # update path: delete 1% then insert 10k fresh vectors (one batch each)
     g = np.random.Generator(np.random.Philox(77))
@@ -202,6 +291,12 @@ def main():
     ix.insert(extra)
     ins_s = time.perf_counter() - t0
     st = ix.stats()
+
+    serving = None
+    if not args.no_serving:
+        log("serving mix")
+        del base_t
+        serving = serving_bench(svf, datagen)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -233,11 +328,17 @@ def main():
                      "n_dist_per_query_timed": round(n_dist_run / nq, 1),
                      "n_exp_per_query": round(n_exp / nq, 1)},
         "cpu_baseline": cpu,
-        "chosen_form": {"form": "BF16 traversal + FP32 re-score", "beam": beam_bf,
+        "chosen_form": {"form": "BF16 traversal + FP32 re-score + learned entry clusters "
+                                "and stop cap (MLP 128-256-256-257, BF16, trained on the GPU)",
+                        "beam": beam_bf, "search_width": cw, "model_stop_scale": css,
                         "recall@10": round(rec_bf, 5),
                         "value": round(nq / (float(np.mean(ms_bf)) / 1e3), 1),
                         "ms_per_step": round(float(np.mean(ms_bf)), 4),
-                        "max_abs_dist_err_vs_fp64": maxerr},
+                        "speedup_vs_plain": round(ms_step / float(np.mean(ms_bf)), 3),
+                        "max_abs_dist_err_vs_fp64": maxerr,
+                        "model_fit_s": round(fit_s, 2), "model_fit_loss": round(fit_loss, 4),
+                        "training_queries": 200_000, "n_clusters": 256,
+                        "bf16_only": bf_only, "configs_tried": tried},
         "sweep_fp32": rows,
         "sweep_bf16": rows_bf,
         "update": {"build_s": round(build_s, 3), "build_vectors_per_s": round(args.n_base / build_s, 1),
@@ -246,6 +347,7 @@ def main():
                                                                "ins_reverse_ms", "ins_commit_ms",
                                                                "del_mark_ms", "del_repair_ms")},
                    "repaired_rows": st["last_repaired"]},
+        "serving": serving,
         "wall_s_timed": round(wall, 4),
     }
     print(json.dumps(out), flush=True)

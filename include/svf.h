@@ -155,10 +155,12 @@ int svf_search_dev(svf_index *ix, const float *d_queries, int64_t nq, int32_t k,
  *      with k and beam, recording each query's top-1 id and the expansion
  *      count after which its top-k stopped changing;
  *   3. labels: the centroid nearest to the top-1 vector, and log(max(1, step));
- *   4. Adam over `epochs` passes of batches of 1024, loss = cross-entropy +
- *      0.1 * Huber(log step);
- *   5. per cluster, the 64 nearest stored vectors to its centroid become
- *      that cluster's entry list.
+ *   4. per cluster, the 64 nearest stored vectors to its centroid become
+ *      that cluster's entry list;
+ *   5. Adam over epochs/2 passes of batches of 1024, loss = cross-entropy +
+ *      0.1 * Huber(log step); then the stop labels are re-measured on traces
+ *      of the search started from the predicted clusters' entry lists and
+ *      training continues for the remaining epochs.
  * Afterwards option use_model = 1 makes svf_search start confident queries
  * from their cluster's list with a predicted expansion cap; others (softmax
  * below model_conf) run plain search.  n >= 1024; 2 <= n_clusters <= 256.

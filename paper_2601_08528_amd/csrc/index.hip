@@ -906,35 +906,66 @@ int svf_model_fit(svf_index* ix, const float* train_queries, int64_t n, int32_t 
   CK(svf::assign_rows(ix->vec32, ix->stride, dim, ids, n, k, cent, nc, labels, st));
   CK(svf::launch_log_steps(lcg, n, lstop, st));
   CK(hipStreamSynchronize(st));
-  // 4. train the predictor on the GPU
-  delete ix->model;
-  ix->model = new (std::nothrow) svf::Mlp(dim, 256, nc, ix->opt.seed + 12345);
-  if (!ix->model) return fail(SVF_E_NOMEM, "host allocation");
-  CK(ix->model->init_device(st));
-  float loss = 0.f;
-  CK(ix->model->train(dq, labels, lstop, n, epochs, 1024, 2e-3f, 0.1f, 1.0f, &loss, st));
-  if (last_loss) *last_loss = loss;
-  ix->model_nc = nc;
-  // 5. per-cluster entry lists: the nearest alive vectors to each centroid
+  // 4. per-cluster entry lists: the nearest alive vectors to each centroid
   int32_t* el;
   float* eld;
   uint64_t* ckey;
   if ((rc = scratch(ix->entry_lists, (size_t)nc * ecap, &el)) ||
       (rc = scratch(ix->s_misc[4], (size_t)nc * ecap, &eld)) || (rc = scratch(ix->s_misc[5], nc, &ckey)))
     return rc;
-  svf::SearchArgs c = base_args(ix);
-  set_beam(c, ix, std::max(2 * ecap, beam));
-  c.k = ecap;
-  c.queries = cent;
-  c.qstride = dim;
-  c.nq = nc;
-  c.out_ids = el;
-  c.out_d = eld;
-  CK(svf::launch_query_keys(cent, dim, nullptr, dim, nc, ix->opt.seed, ckey, st));
-  c.qkey = ckey;
-  CK(svf::launch_search(c, ix->veclp_prec, st));
-  CK(hipStreamSynchronize(st));
+  {
+    svf::SearchArgs c = base_args(ix);
+    set_beam(c, ix, std::max(2 * ecap, beam));
+    c.k = ecap;
+    c.queries = cent;
+    c.qstride = dim;
+    c.nq = nc;
+    c.out_ids = el;
+    c.out_d = eld;
+    CK(svf::launch_query_keys(cent, dim, nullptr, dim, nc, ix->opt.seed, ckey, st));
+    c.qkey = ckey;
+    CK(svf::launch_search(c, ix->veclp_prec, st));
+  }
   ix->entry_cap = ecap;
+  // 5. train the predictor on the GPU, in two stages: first on the labels of
+  //    plain search; then the stop labels are re-measured on traces of the
+  //    search that starts from the predicted clusters' entry lists (the form
+  //    the predictor will drive), and training continues on them
+  delete ix->model;
+  ix->model = new (std::nothrow) svf::Mlp(dim, 256, nc, ix->opt.seed + 12345);
+  if (!ix->model) return fail(SVF_E_NOMEM, "host allocation");
+  CK(ix->model->init_device(st));
+  ix->model_nc = nc;
+  const int e1 = std::max(1, epochs / 2), e2 = epochs - e1;
+  float loss = 0.f;
+  CK(ix->model->train(dq, labels, lstop, n, e1, 1024, 2e-3f, 0.1f, 1.0f, &loss, st));
+  if (e2 > 0) {
+    float* z;
+    int32_t *qe, *qm;
+    if ((rc = scratch(ix->s_z, (size_t)n * (nc + 1), &z)) || (rc = scratch(ix->s_qentry, n, &qe)) ||
+        (rc = scratch(ix->s_qmax, n, &qm)))
+      return rc;
+    CK(ix->model->forward(dq, n, z, st));
+    CK(svf::launch_model_decide(z, n, nc, 0.0f, 1.0f, 1, qe, qm, st));
+    svf::SearchArgs t = base_args(ix);
+    set_beam(t, ix, beam);
+    t.k = k;
+    t.queries = dq;
+    t.qstride = dim;
+    t.nq = (int)n;
+    t.out_ids = ids;
+    t.out_d = dd;
+    t.last_change = lcg;
+    t.entry_lists = el;
+    t.entry_cap = ecap;
+    t.q_entry = qe;
+    t.qkey = qkey;
+    CK(svf::launch_search(t, ix->veclp_prec, st));
+    CK(svf::launch_log_steps(lcg, n, lstop, st));
+    CK(ix->model->train(dq, labels, lstop, n, e2, 1024, 1e-3f, 0.1f, 1.0f, &loss, st));
+  }
+  CK(hipStreamSynchronize(st));
+  if (last_loss) *last_loss = loss;
   return SVF_OK;
 }
 

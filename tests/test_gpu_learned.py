@@ -90,14 +90,14 @@ def test_listed_entry_search_bit_exact():
 
 
 def test_learned_form_gain_over_plain():
-    """40k x 128 integer mixture with 256 components, degree 16: entry points
-    from the predicted cluster raise recall at small beams over random entry
-    points (measured: +4 to +6 points at beams 10..16)."""
+    """40k x 128 integer mixture with 256 components, degree 16, 256 entry
+    clusters: entry points from the predicted cluster raise recall at a small
+    beam over random entry points."""
     base, q = datagen.gmm_uint8_valued(505, 40_000, 2000, 128, 256)
     train = datagen.training_queries_uint8(505, 20_000, 128, 256)
     g = svf.Index(128, 16, svf.METRIC_L2, seed=1)
     g.build(base)
-    loss = g.model_fit(train, 10, 64, n_clusters=64, epochs=8)
+    loss = g.model_fit(train, 10, 64, n_clusters=256, epochs=8)
     assert np.isfinite(loss)
     gt_i, gt_d = O.bruteforce(base, q, 10, threads=8)
     ref = O.OracleIndex(128, 16, O.L2)           # vectors only: exact distances
