@@ -67,6 +67,13 @@ typedef struct svf_stats {
     double del_mark_ms, del_repair_ms;
     int64_t last_repaired;    /* rows rewritten by the last delete/consolidate */
     int64_t device_bytes;     /* HBM held by the index                        */
+    /* tiered store (cache_bytes set) */
+    int64_t cache_slots;            /* vectors the HBM cache holds            */
+    int64_t cache_gather_hits;      /* search gathers served by the cache     */
+    int64_t cache_gather_misses;    /* search gathers read from host memory   */
+    int64_t cache_last_trace_hits;  /* last batch: expansions of cached vectors */
+    int64_t cache_last_placed;      /* last batch: vectors placed in the cache */
+    int64_t cache_promotions, cache_evictions;
 } svf_stats;
 
 /* Create an empty index.  Sec. 2.3: a directed graph with a fixed number of
@@ -92,6 +99,16 @@ int svf_destroy(svf_index *ix);
  *   insert_batch_max largest batch of one insertion pass (1..1<<20; 10000)
  *   precision       SVF_PREC_* of traversal distances (0..2; 0)
  *   rerank          exact FP32 re-scoring of the final pool under reduced precision (0/1; 1)
+ *   cache_bytes     tiered store (Sec. 4.2-4.3): all vectors in pinned host memory, an HBM
+ *                   cache of cache_bytes / (4 * round_up(dim, 8)) rows in front; set on an
+ *                   empty index, FP32 traversal only.  Searches read cached rows from HBM
+ *                   and the rest over the host link; after every direct search call the
+ *                   batched workload-aware placement (Alg. 2) updates the cache, and
+ *                   svf_build warms it with the highest in-degree vectors (Sec. 4.4)
+ *   cache_theta     placement threshold on F_lambda (>= 0; 1.0)
+ *   cache_alpha_ratio alpha / (alpha + beta) of F_lambda, alpha + beta = 1 ([0,1]; 0.6)
+ *   cache_promote_max placements per query batch (>= 0; 2048)
+ *   cache_trace_cap expansions per query recorded for placement (16..8192; 512)
  *   use_model       learned entry points and stopping step (0/1; 0; needs svf_model_fit)
  *   model_conf      softmax confidence below which a query falls back to plain search ([0,1]; 0.5)
  *   model_stop_scale expansion cap = ceil(scale * predicted stop step) (>0; 1.5)

@@ -67,6 +67,8 @@ def lib():
         L.orc_splitmix64.argtypes = [u64, u64]
         L.orc_prune_explicit.argtypes = [i32, i32, vp, vp, vp, i64, vp, vp]
         L.orc_query_dists.argtypes = [vp, vp, i64, i32, vp, vp]
+        L.orc_search_expansions.argtypes = [vp, vp, i64, i32, vp, i32, vp]
+        L.orc_wavp_replay.argtypes = [i64, i64, vp, vp, vp, vp, i32, f64, f64, f64, i32, vp, vp]
         L.orc_search_listed.argtypes = [vp, vp, i64, i32, i32, vp, i32, vp, vp, vp, vp]
         L.orc_search_trace.argtypes = [vp, vp, i64, i32, i32, vp, vp]
         L.orc_mlp_forward.argtypes = [i32, i32, i32] + [vp] * 6 + [vp, i64, vp]
@@ -165,6 +167,14 @@ class OracleIndex:
         lc = np.empty(q.shape[0], np.int32)
         _check(lib().orc_search_trace(self.h, _p(q), q.shape[0], k, beam, _p(ids), _p(lc)))
         return ids, lc
+
+    def search_expansions(self, q, beam, cap=4096):
+        """Per query, the vertices expanded in order (first `cap`), and counts."""
+        q = np.ascontiguousarray(q, dtype=np.float32)
+        tr = np.full((q.shape[0], cap), -1, np.int32)
+        cnt = np.empty(q.shape[0], np.int32)
+        _check(lib().orc_search_expansions(self.h, _p(q), q.shape[0], beam, _p(tr), cap, _p(cnt)))
+        return tr, cnt
 
     def export(self):
         n = self.n_slots
@@ -266,3 +276,19 @@ class MLP:
         loss = lib().orc_mlp_loss_grad(self.din, self.h, self.nc, *[_p(a) for a in self.p], _p(x),
                                        _p(lab), _p(ls), x.shape[0], lam, delta, *[_p(a) for a in g])
         return loss, g
+
+
+def wavp_replay(n, C, e_in, alive, batches, alpha=0.6, beta=0.4, theta=1.0, promote_max=2048):
+    """Batched workload-aware placement over per-batch access traces; returns
+    (hits per batch, final slot table)."""
+    e = np.ascontiguousarray(e_in, dtype=np.int32)
+    a = np.ascontiguousarray(alive, dtype=np.uint8)
+    flat = np.ascontiguousarray(np.concatenate([np.asarray(b, np.int32) for b in batches])
+                                if batches else np.zeros(0, np.int32), dtype=np.int32)
+    off = np.zeros(len(batches) + 1, np.int64)
+    off[1:] = np.cumsum([len(b) for b in batches])
+    hits = np.empty(len(batches), np.int64)
+    slots = np.empty(max(C, 1), np.int32)
+    lib().orc_wavp_replay(n, C, _p(e), _p(a), _p(flat), _p(off), len(batches), alpha, beta, theta,
+                          promote_max, _p(hits), _p(slots))
+    return hits, slots[:C]

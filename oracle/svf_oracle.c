@@ -1188,3 +1188,158 @@ double orc_mlp_loss_grad(int din, int h, int nc, const double *w1, const double 
     free(h1); free(h2); free(z); free(dz); free(dh2); free(dh1);
     return loss / (double)n;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Expansion traces: the vertices each query expands, in order (at most cap
+ * per query; counts receive the full number). */
+int orc_search_expansions(const orc_index *ix, const float *q, int64_t nq, int L, int32_t *trace,
+                          int cap, int32_t *counts)
+{
+    scratch_t s;
+    if (scratch_init(&s, ix->n_slots, L, ix->search_width, ix->R)) return ORC_E_NOMEM;
+    const int d = ix->dim, R = ix->R;
+    double *qlp = malloc(sizeof(double) * d);
+    for (int64_t i = 0; i < nq; ++i) {
+        const float *qf = q + i * d;
+        for (int t = 0; t < d; ++t) qlp[t] = lp_value(ix->precision, qf[t]);
+        /* the search of search_one, recording parents */
+        qstats st;
+        memset(&st, 0, sizeof st);
+        int E = ix->entry_samples > 0 ? ix->entry_samples : L;
+        int64_t alive_n = 0;
+        for (int64_t u = 0; u < ix->n_slots; ++u) alive_n += ix->alive[u];
+        uint64_t key = ix->seed ^ fnv1a64((const unsigned char *)qf, (size_t)d * sizeof(float));
+        int64_t want = E < alive_n ? E : alive_n;
+        int ne = 0;
+        for (int64_t j = 0; j < 8LL * E + 64 && ne < want; ++j) {
+            int64_t id = (int64_t)(((splitmix64_out(key, (uint64_t)j) >> 32) * (uint64_t)ix->n_slots) >> 32);
+            if (!ix->alive[id] || s.visited[id]) continue;
+            visit(&s, (int32_t)id);
+            s.fresh[ne].id = (int32_t)id;
+            s.fresh[ne].d = dist(ix->metric, qlp, ix->vec_lp + id * d, d);
+            s.fresh[ne].expanded = 0;
+            ++ne;
+        }
+        qsort(s.fresh, ne, sizeof(pentry), cmp_pentry);
+        int np = ne < L ? ne : L;
+        memcpy(s.pool, s.fresh, np * sizeof(pentry));
+        int nt = 0;
+        for (;;) {
+            int par[8], npar = 0;
+            for (int t = 0; t < np && npar < ix->search_width; ++t) if (!s.pool[t].expanded) par[npar++] = t;
+            if (npar == 0) break;
+            int nf = 0;
+            for (int t = 0; t < npar; ++t) {
+                s.pool[par[t]].expanded = 1;
+                if (nt < cap) trace[i * cap + nt] = s.pool[par[t]].id;
+                ++nt;
+                const int32_t *row = ix->rows + (int64_t)s.pool[par[t]].id * R;
+                for (int r = 0; r < R; ++r) {
+                    int32_t u = row[r];
+                    if (u < 0 || u >= ix->n_slots || !ix->alive[u] || s.visited[u]) continue;
+                    visit(&s, u);
+                    s.fresh[nf].id = u;
+                    s.fresh[nf].d = dist(ix->metric, qlp, ix->vec_lp + (int64_t)u * d, d);
+                    s.fresh[nf].expanded = 0;
+                    ++nf;
+                }
+            }
+            memcpy(s.merged, s.pool, np * sizeof(pentry));
+            memcpy(s.merged + np, s.fresh, nf * sizeof(pentry));
+            int nm = np + nf;
+            qsort(s.merged, nm, sizeof(pentry), cmp_pentry);
+            np = nm < L ? nm : L;
+            memcpy(s.pool, s.merged, np * sizeof(pentry));
+        }
+        unvisit_all(&s);
+        counts[i] = nt;
+    }
+    free(qlp);
+    scratch_free(&s);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Workload-aware vector placement (Sec. 4.3, Alg. 2, Eq. 2) replayed over
+ * per-batch access traces, in the batched form:
+ *   F_lambda(x) = alpha * F_recent(x) + beta * log(1 + E_in(x));
+ *   per batch: F_recent halves, then counts this batch's accesses; accesses to
+ *   resident vectors are hits and set the reference bit of their slot; the
+ *   distinct missed vectors with F_lambda > theta, by (F_lambda desc, id asc),
+ *   at most `promote_max` of them, are placed: into a free slot, else by a
+ *   clock sweep (at most 2C steps) that clears set reference bits and evicts
+ *   the first slot with a clear bit whose vector has a lower F_lambda (a
+ *   deleted vector counts as -1); a candidate that finds no victim ends the
+ *   batch's placements.
+ * trace: concatenated accesses, batch b spanning [off[b], off[b+1]).
+ * Out: hits per batch, and the final slot -> id table (-1 empty). */
+void orc_wavp_replay(int64_t n, int64_t C, const int32_t *e_in, const uint8_t *alive,
+                     const int32_t *trace, const int64_t *off, int nb, double alpha, double beta,
+                     double theta, int promote_max, int64_t *hits, int32_t *slot_id)
+{
+    double *fr = calloc(n, sizeof(double));
+    int32_t *where = malloc(sizeof(int32_t) * n);
+    uint8_t *ref = calloc(C > 0 ? C : 1, 1);
+    uint8_t *cand_mark = calloc(n, 1);
+    for (int64_t i = 0; i < n; ++i) where[i] = -1;
+    for (int64_t s = 0; s < C; ++s) slot_id[s] = -1;
+    int64_t used = 0, clock = 0;
+    typedef struct { double f; int32_t id; } cand_t;
+    int64_t maxlen = 0;
+    for (int b = 0; b < nb; ++b) if (off[b + 1] - off[b] > maxlen) maxlen = off[b + 1] - off[b];
+    cand_t *cand = malloc(sizeof(cand_t) * (maxlen + 1));
+#define FLAM(x) (alive[(x)] ? alpha * fr[(x)] + beta * log(1.0 + (double)e_in[(x)]) : -1.0)
+    for (int b = 0; b < nb; ++b) {
+        for (int64_t i = 0; i < n; ++i) fr[i] *= 0.5;
+        int64_t h = 0;
+        for (int64_t t = off[b]; t < off[b + 1]; ++t) {
+            int32_t x = trace[t];
+            fr[x] += 1.0;
+            if (where[x] >= 0) { ++h; ref[where[x]] = 1; }
+        }
+        hits[b] = h;
+        int nc = 0;
+        for (int64_t t = off[b]; t < off[b + 1]; ++t) {
+            int32_t x = trace[t];
+            if (where[x] >= 0 || cand_mark[x]) continue;
+            cand_mark[x] = 1;
+            double f = FLAM(x);
+            if (f > theta) { cand[nc].f = f; cand[nc].id = x; ++nc; }
+        }
+        for (int64_t t = off[b]; t < off[b + 1]; ++t) cand_mark[trace[t]] = 0;
+        /* order: F_lambda descending, id ascending */
+        for (int i = 1; i < nc; ++i) {
+            cand_t c = cand[i];
+            int j = i - 1;
+            while (j >= 0 && (cand[j].f < c.f || (cand[j].f == c.f && cand[j].id > c.id))) {
+                cand[j + 1] = cand[j];
+                --j;
+            }
+            cand[j + 1] = c;
+        }
+        if (nc > promote_max) nc = promote_max;
+        for (int i = 0; i < nc; ++i) {
+            int32_t x = cand[i].id;
+            if (used < C) {
+                slot_id[used] = x; where[x] = (int32_t)used; ref[used] = 0; ++used;
+                continue;
+            }
+            int placed = 0;
+            for (int64_t step = 0; step < 2 * C; ++step) {
+                int64_t s = clock;
+                clock = (clock + 1) % C;
+                if (ref[s]) { ref[s] = 0; continue; }
+                int32_t y = slot_id[s];
+                if (FLAM(y) < cand[i].f) {
+                    where[y] = -1;
+                    slot_id[s] = x; where[x] = (int32_t)s; ref[s] = 0;
+                    placed = 1;
+                    break;
+                }
+            }
+            if (!placed) break;
+        }
+    }
+#undef FLAM
+    free(fr); free(where); free(ref); free(cand_mark); free(cand);
+}

@@ -52,6 +52,10 @@ class Stats(C.Structure):
         ("ins_reverse_ms", C.c_double), ("ins_commit_ms", C.c_double),
         ("del_mark_ms", C.c_double), ("del_repair_ms", C.c_double),
         ("last_repaired", C.c_int64), ("device_bytes", C.c_int64),
+        ("cache_slots", C.c_int64), ("cache_gather_hits", C.c_int64),
+        ("cache_gather_misses", C.c_int64), ("cache_last_trace_hits", C.c_int64),
+        ("cache_last_placed", C.c_int64), ("cache_promotions", C.c_int64),
+        ("cache_evictions", C.c_int64),
     ]
 
     def as_dict(self):

@@ -60,7 +60,7 @@ int reserve(svf_index* ix, int64_t need) {
   int32_t *g = nullptr, *tc = nullptr, *ti = nullptr;
   uint32_t* al = nullptr;
   auto cleanup = [&]() {
-    if (v32) (void)hipFree(v32);
+    if (v32) (void)(ix->tier.on ? hipHostFree(v32) : hipFree(v32));
     if (vlp) (void)hipFree(vlp);
     if (g) (void)hipFree(g);
     if (ed) (void)hipFree(ed);
@@ -69,32 +69,50 @@ int reserve(svf_index* ix, int64_t need) {
     if (ti) (void)hipFree(ti);
   };
   hipError_t e = hipSuccess;
-  if ((e = hipMalloc(&v32, cap * ix->stride * 4)) != hipSuccess ||
+  const bool tier = ix->tier.on;
+  int32_t* tmap = nullptr;
+  if (tier && (e = hipMalloc(&tmap, cap * 4)) != hipSuccess) return hip_fail(e, "index allocation");
+  if ((e = tier ? hipHostMalloc((void**)&v32, cap * ix->stride * 4, 0)
+                : hipMalloc(&v32, cap * ix->stride * 4)) != hipSuccess ||
       (ix->veclp_prec && (e = hipMalloc(&vlp, cap * ix->stride * 2)) != hipSuccess) ||
       (e = hipMalloc(&g, cap * ix->R * 4)) != hipSuccess ||
       (e = hipMalloc(&ed, cap * ix->R * 4)) != hipSuccess ||
       (e = hipMalloc(&al, words * 4)) != hipSuccess ||
       (e = hipMalloc(&tc, cap * 4)) != hipSuccess || (e = hipMalloc(&ti, cap * 4)) != hipSuccess) {
     cleanup();
+    if (tmap) (void)hipFree(tmap);
     return hip_fail(e, "index allocation");
   }
   hipStream_t st = ix->stream;
   const int64_t n = ix->n_slots;
-  CK(svf::launch_fill_u32(v32, cap * ix->stride, 0u, st));
+  if (tier) {
+    std::memset(v32, 0, cap * ix->stride * 4);
+    if (n > 0) std::memcpy(v32, ix->vec32, n * ix->stride * 4);
+    CK(svf::launch_fill_u32(tmap, cap, 0xffffffffu, st));
+    if (n > 0 && ix->tier.map) CK(hipMemcpyAsync(tmap, ix->tier.map, n * 4, hipMemcpyDeviceToDevice, st));
+    ix->tier.where.resize(cap, -1);
+    ix->tier.fr.resize(cap, 0.0);
+  } else {
+    CK(svf::launch_fill_u32(v32, cap * ix->stride, 0u, st));
+  }
   if (vlp) CK(svf::launch_fill_u32(vlp, cap * ix->stride / 2, 0u, st));
   CK(svf::launch_fill_u32(g, cap * ix->R, 0xffffffffu, st));
   CK(svf::launch_fill_u32(ed, cap * ix->R, 0x7f800000u, st));
   CK(svf::launch_fill_u32(al, words, 0u, st));
   CK(svf::launch_fill_u32(tc, cap, 0u, st));
   if (n > 0) {
-    CK(hipMemcpyAsync(v32, ix->vec32, n * ix->stride * 4, hipMemcpyDeviceToDevice, st));
+    if (!tier) CK(hipMemcpyAsync(v32, ix->vec32, n * ix->stride * 4, hipMemcpyDeviceToDevice, st));
     if (vlp) CK(hipMemcpyAsync(vlp, ix->veclp, n * ix->stride * 2, hipMemcpyDeviceToDevice, st));
     CK(hipMemcpyAsync(g, ix->graph, n * ix->R * 4, hipMemcpyDeviceToDevice, st));
     CK(hipMemcpyAsync(ed, ix->edge_d, n * ix->R * 4, hipMemcpyDeviceToDevice, st));
     CK(hipMemcpyAsync(al, ix->alive, ((n + 31) / 32) * 4, hipMemcpyDeviceToDevice, st));
   }
   CK(hipStreamSynchronize(st));
-  if (ix->vec32) (void)hipFree(ix->vec32);
+  if (ix->vec32) (void)(tier ? hipHostFree(ix->vec32) : hipFree(ix->vec32));
+  if (tier) {
+    if (ix->tier.map) (void)hipFree(ix->tier.map);
+    ix->tier.map = tmap;
+  }
   if (ix->veclp) (void)hipFree(ix->veclp);
   if (ix->graph) (void)hipFree(ix->graph);
   if (ix->edge_d) (void)hipFree(ix->edge_d);
@@ -136,7 +154,7 @@ int sync_lowp(svf_index* ix) {
 int store_rows(svf_index* ix, const float* d_src, int64_t n, int64_t at, hipStream_t st) {
   if (n <= 0) return SVF_OK;
   CK(hipMemcpy2DAsync(ix->vec32 + at * ix->stride, ix->stride * 4, d_src, ix->dim * 4,
-                      ix->dim * 4, n, hipMemcpyDeviceToDevice, st));
+                      ix->dim * 4, n, hipMemcpyDefault, st));
   if (ix->veclp_prec)
     CK(svf::launch_store_lowp(ix->vec32, ix->veclp, at, n, ix->stride, ix->veclp_prec, st));
   return SVF_OK;
@@ -159,6 +177,10 @@ svf::SearchArgs base_args(const svf_index* ix) {
   a.n_alive = (int32_t)ix->n_alive;
   a.metric = ix->metric;
   a.max_iters = ix->opt.max_iters;
+  if (ix->tier.on) {
+    a.tmap = ix->tier.map;
+    a.tcache = ix->tier.cache;
+  }
   return a;
 }
 
@@ -294,6 +316,7 @@ int insert_commit(svf_index* ix, PendingInsert* p) {
     CK(hipStreamSynchronize(st));
     ix->n_slots = p->b;
     ix->n_alive = p->b;
+    ++ix->graph_epoch;
     return SVF_OK;
   }
   CK(hipEventRecord(ix->ev0, st));
@@ -301,6 +324,7 @@ int insert_commit(svf_index* ix, PendingInsert* p) {
   CK(hipEventRecord(ix->ev1, st));
   CK(hipStreamSynchronize(st));
   ix->st.ins_commit_ms = elapsed(ix->ev0, ix->ev1);
+  ++ix->graph_epoch;
   ix->n_slots = p->n0 + p->b;
   ix->n_alive += p->b;
   return SVF_OK;
@@ -417,6 +441,7 @@ int repair(svf_index* ix, int consolidate) {
     CK(svf::launch_prune_lists(pa, st));
   }
   CK(svf::launch_commit_rows(list, n_aff, rows, rows_d, R, ix->graph, ix->edge_d, st));
+  ++ix->graph_epoch;
   CK(hipEventRecord(ix->ev1, st));
   CK(hipStreamSynchronize(st));
   ix->st.del_repair_ms = elapsed(ix->ev0, ix->ev1);
@@ -463,6 +488,16 @@ int search_impl(svf_index* ix, const float* d_q, int64_t nq, int k, int beam, in
   a.n_dist = d_nd;
   a.n_exp = d_ne;
   a.totals = tot;
+  if (ix->tier.on) {
+    svf::TierState& T = ix->tier;
+    unsigned long long* cnt;
+    if ((rc = scratch(T.trace, (size_t)nq * T.trace_cap, &a.trace)) ||
+        (rc = scratch(T.trace_n, nq, &a.trace_n)) || (rc = scratch(T.counts, 2, &cnt)))
+      return rc;
+    a.trace_cap = T.trace_cap;
+    a.tier_counts = cnt;
+    CK(svf::launch_fill_u32(cnt, 4, 0u, st));
+  }
   CK(svf::launch_fill_u32(tot, 4, 0u, st));
   CK(svf::launch_query_keys(d_q, ix->dim, nullptr, ix->dim, a.nq, ix->opt.seed, qkey, st));
   a.qkey = qkey;
@@ -542,6 +577,7 @@ int delete_ids(svf_index* ix, const int32_t* ids, int64_t n) {
   CK(hipEventRecord(ix->ev1, st));
   CK(hipStreamSynchronize(st));
   ix->st.del_mark_ms = elapsed(ix->ev0, ix->ev1);
+  ++ix->graph_epoch;
   if (ix->alive_at_consolidate == 0) ix->alive_at_consolidate = ix->n_alive;
   ix->n_alive -= newly;
   ix->deleted_since += newly;
@@ -554,6 +590,179 @@ int delete_ids(svf_index* ix, const int32_t* ids, int64_t n) {
     rc = repair(ix, 0);
   }
   return rc;
+}
+
+// ---- tiered store: placement after each query batch ------------------------
+// The batched form of workload-aware placement (Sec. 4.3, Alg. 2, Eq. 2): per
+// batch F_recent halves and counts the batch's expansion trace (queries in
+// order, each query's expanded vertices in order); accesses to cached vectors
+// are hits and set their slot's reference bit; the distinct missed vectors
+// with F_lambda = alpha F_recent + beta log(1 + E_in) above theta, by
+// (F_lambda desc, id asc), at most promote_max of them, are placed into a free
+// slot or by a clock sweep (at most 2C steps) that clears set reference bits
+// and evicts the first clear slot holding a lower F_lambda (a deleted vector
+// counts -1); a candidate without a victim ends the batch's placements.
+int tier_refresh_indegree(svf_index* ix, hipStream_t st) {
+  svf::TierState& T = ix->tier;
+  if (T.e_in_epoch == ix->graph_epoch && (int64_t)T.e_in.size() >= ix->n_slots) return SVF_OK;
+  int32_t* d;
+  int rc = scratch(T.e_in_d, std::max<int64_t>(ix->n_slots, 1), &d);
+  if (rc) return rc;
+  CK(svf::launch_indegree(ix->graph, ix->alive, ix->n_slots, ix->R, d, st));
+  T.e_in.assign(std::max<int64_t>(ix->n_slots, 1), 0);
+  CK(hipMemcpyAsync(T.e_in.data(), d, ix->n_slots * 4, hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  T.e_in_epoch = ix->graph_epoch;
+  return SVF_OK;
+}
+
+int tier_apply(svf_index* ix, const std::vector<int32_t>& place, hipStream_t st) {
+  svf::TierState& T = ix->tier;
+  const int np = (int)(place.size() / 3);
+  T.last_placed = np;
+  if (np == 0) return SVF_OK;
+  int32_t* d;
+  int rc = scratch(T.place, place.size(), &d);
+  if (rc) return rc;
+  CK(hipMemcpyAsync(d, place.data(), place.size() * 4, hipMemcpyHostToDevice, st));
+  CK(svf::launch_place(d, np, ix->vec32, T.cache, ix->stride, T.map, st));
+  CK(hipStreamSynchronize(st));
+  return SVF_OK;
+}
+
+int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
+  svf::TierState& T = ix->tier;
+  const int cap = T.trace_cap;
+  std::vector<int32_t> tn(nq), tr((size_t)nq * cap);
+  unsigned long long cnt[2] = {0, 0};
+  const int64_t n = ix->n_slots;
+  std::vector<uint32_t> bits((n + 31) / 32 + 1, 0u);
+  CK(hipMemcpyAsync(tn.data(), T.trace_n.p, nq * 4, hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(tr.data(), T.trace.p, (size_t)nq * cap * 4, hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(cnt, T.counts.p, sizeof cnt, hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(bits.data(), ix->alive, ((n + 31) / 32) * 4, hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  int rc = tier_refresh_indegree(ix, st);
+  if (rc) return rc;
+  T.gather_hits += cnt[0];
+  T.gather_misses += cnt[1];
+  auto alive = [&](int32_t x) { return ((bits[x >> 5] >> (x & 31)) & 1u) != 0; };
+  auto flam = [&](int32_t x) -> double {
+    return alive(x) ? T.alpha * T.fr[x] + T.beta * std::log(1.0 + (double)T.e_in[x]) : -1.0;
+  };
+  for (int64_t i = 0; i < n; ++i) T.fr[i] *= 0.5;
+  int64_t hits = 0;
+  for (int64_t q = 0; q < nq; ++q) {
+    const int len = std::min(tn[q], cap);
+    for (int t = 0; t < len; ++t) {
+      const int32_t x = tr[(size_t)q * cap + t];
+      T.fr[x] += 1.0;
+      if (T.where[x] >= 0) {
+        ++hits;
+        T.ref[T.where[x]] = 1;
+      }
+    }
+  }
+  T.last_trace_hits = hits;
+  std::vector<std::pair<double, int32_t>> cand;
+  std::vector<int32_t> marked;
+  std::vector<uint8_t> mark(n, 0);
+  for (int64_t q = 0; q < nq; ++q) {
+    const int len = std::min(tn[q], cap);
+    for (int t = 0; t < len; ++t) {
+      const int32_t x = tr[(size_t)q * cap + t];
+      if (T.where[x] >= 0 || mark[x]) continue;
+      mark[x] = 1;
+      const double f = flam(x);
+      if (f > T.theta) cand.emplace_back(f, x);
+    }
+  }
+  std::sort(cand.begin(), cand.end(), [](const std::pair<double, int32_t>& a, const std::pair<double, int32_t>& b) {
+    return a.first > b.first || (a.first == b.first && a.second < b.second);
+  });
+  if ((int64_t)cand.size() > T.promote_max) cand.resize(T.promote_max);
+  std::vector<int32_t> place;
+  for (const auto& c : cand) {
+    const int32_t x = c.second;
+    if (T.used < T.C) {
+      const int64_t slot = T.used++;
+      T.slot_id[slot] = x;
+      T.where[x] = (int32_t)slot;
+      T.ref[slot] = 0;
+      place.insert(place.end(), {(int32_t)slot, x, -1});
+      continue;
+    }
+    bool placed = false;
+    for (int64_t step = 0; step < 2 * T.C; ++step) {
+      const int64_t s_ = T.clock;
+      T.clock = (T.clock + 1) % T.C;
+      if (T.ref[s_]) {
+        T.ref[s_] = 0;
+        continue;
+      }
+      const int32_t y = T.slot_id[s_];
+      if (flam(y) < c.first) {
+        T.where[y] = -1;
+        T.slot_id[s_] = x;
+        T.where[x] = (int32_t)s_;
+        T.ref[s_] = 0;
+        place.insert(place.end(), {(int32_t)s_, x, y});
+        ++T.evictions;
+        placed = true;
+        break;
+      }
+    }
+    if (!placed) break;
+  }
+  T.promotions += place.size() / 3;
+  return tier_apply(ix, place, st);
+}
+
+// Cold start (Sec. 4.4): fill the cache with the highest in-degree vectors.
+int tier_warmup(svf_index* ix, hipStream_t st) {
+  svf::TierState& T = ix->tier;
+  int rc = tier_refresh_indegree(ix, st);
+  if (rc) return rc;
+  const int64_t n = ix->n_slots;
+  std::vector<int32_t> order(n);
+  for (int64_t i = 0; i < n; ++i) order[i] = (int32_t)i;
+  const int64_t take = std::min<int64_t>(T.C - T.used, n);
+  std::partial_sort(order.begin(), order.begin() + take, order.end(), [&](int32_t a, int32_t b) {
+    return T.e_in[a] > T.e_in[b] || (T.e_in[a] == T.e_in[b] && a < b);
+  });
+  std::vector<int32_t> place;
+  for (int64_t i = 0; i < take; ++i) {
+    const int32_t x = order[i];
+    if (T.where[x] >= 0) continue;
+    const int64_t slot = T.used++;
+    T.slot_id[slot] = x;
+    T.where[x] = (int32_t)slot;
+    T.ref[slot] = 0;
+    place.insert(place.end(), {(int32_t)slot, x, -1});
+  }
+  T.promotions += place.size() / 3;
+  return tier_apply(ix, place, st);
+}
+
+int tier_enable(svf_index* ix, double bytes) {
+  svf::TierState& T = ix->tier;
+  if (ix->n_slots != 0) return fail(SVF_E_INVAL, "cache_bytes must be set on an empty index");
+  if (ix->veclp_prec != 0) return fail(SVF_E_INVAL, "the tiered store runs FP32 traversal");
+  const int64_t C = (int64_t)(bytes / (double)(ix->stride * 4));
+  if (C < 1) return fail(SVF_E_INVAL, "cache_bytes below one vector");
+  if (T.on) return fail(SVF_E_INVAL, "cache already configured");
+  CK(hipMalloc(&T.cache, C * ix->stride * 4));
+  if (ix->vec32) (void)hipFree(ix->vec32);
+  ix->vec32 = nullptr;
+  T.on = true;
+  T.C = C;
+  T.slot_id.assign(C, -1);
+  T.ref.assign(C, 0);
+  T.used = 0;
+  T.clock = 0;
+  const int64_t cap = ix->cap;
+  ix->cap = 0;                      // re-create the stores in their tiered form
+  return reserve(ix, std::max<int64_t>(cap, 1024));
 }
 
 }  // namespace svf_detail
@@ -599,11 +808,13 @@ int svf_destroy(svf_index* ix) {
   {
     std::lock_guard<std::mutex> g(ix->mu);
     if (ix->stream) (void)hipStreamSynchronize(ix->stream);
-    if (ix->vec32) (void)hipFree(ix->vec32);
+    if (ix->vec32) (void)(ix->tier.on ? hipHostFree(ix->vec32) : hipFree(ix->vec32));
     if (ix->veclp) (void)hipFree(ix->veclp);
     if (ix->graph) (void)hipFree(ix->graph);
     if (ix->edge_d) (void)hipFree(ix->edge_d);
     if (ix->alive) (void)hipFree(ix->alive);
+    if (ix->tier.cache) (void)hipFree(ix->tier.cache);
+    if (ix->tier.map) (void)hipFree(ix->tier.map);
     if (ix->ev0) (void)hipEventDestroy(ix->ev0);
     if (ix->ev1) (void)hipEventDestroy(ix->ev1);
     if (ix->stream) (void)hipStreamDestroy(ix->stream);
@@ -657,7 +868,24 @@ int svf_set_option(svf_index* ix, const char* key, double v) {
     o.insert_batch_max = (int)v;
   } else if (ix->server && (k == "precision" || k == "use_model")) {
     return fail(SVF_E_BUSY, "option cannot change while serving");
+  } else if (k == "cache_bytes") {
+    if (v <= 0) return fail(SVF_E_INVAL, "cache_bytes > 0");
+    return tier_enable(ix, v);
+  } else if (k == "cache_theta") {
+    if (v < 0) return fail(SVF_E_INVAL, "cache_theta >= 0");
+    ix->tier.theta = v;
+  } else if (k == "cache_alpha_ratio") {
+    if (v < 0 || v > 1) return fail(SVF_E_INVAL, "cache_alpha_ratio in [0, 1]");
+    ix->tier.alpha = v;
+    ix->tier.beta = 1.0 - v;
+  } else if (k == "cache_promote_max") {
+    if (!is_int(v) || v < 0 || v > (1 << 24)) return fail(SVF_E_INVAL, "cache_promote_max in [0, 2^24]");
+    ix->tier.promote_max = (int)v;
+  } else if (k == "cache_trace_cap") {
+    if (!is_int(v) || v < 16 || v > 8192) return fail(SVF_E_INVAL, "cache_trace_cap in [16, 8192]");
+    ix->tier.trace_cap = (int)v;
   } else if (k == "precision") {
+    if (v != 0 && ix->tier.on) return fail(SVF_E_INVAL, "the tiered store runs FP32 traversal");
     if (v != 0 && v != 1 && v != 2) return fail(SVF_E_INVAL, "precision 0 (FP32), 1 (FP16) or 2 (BF16)");
     o.precision = (int)v;
     return sync_lowp(ix);
@@ -701,6 +929,11 @@ int svf_get_option(const svf_index* ix, const char* key, double* out) {
   else if (k == "precision") *out = o.precision;
   else if (k == "rerank") *out = o.rerank;
   else if (k == "use_model") *out = o.use_model;
+  else if (k == "cache_bytes") *out = (double)(ix->tier.C * ix->stride * 4);
+  else if (k == "cache_theta") *out = ix->tier.theta;
+  else if (k == "cache_alpha_ratio") *out = ix->tier.alpha;
+  else if (k == "cache_promote_max") *out = ix->tier.promote_max;
+  else if (k == "cache_trace_cap") *out = ix->tier.trace_cap;
   else if (k == "model_conf") *out = o.model_conf;
   else if (k == "model_stop_scale") *out = o.model_stop_scale;
   else if (k == "model_min_iters") *out = o.model_min_iters;
@@ -743,7 +976,9 @@ int svf_build(svf_index* ix, const float* vecs, int64_t n) {
   float* d;
   if ((rc = scratch(ix->s_q, (size_t)n * ix->dim, &d))) return rc;
   CK(hipMemcpyAsync(d, vecs, (size_t)n * ix->dim * 4, hipMemcpyHostToDevice, ix->stream));
-  return insert_stream(ix, d, n, nullptr, nullptr);
+  rc = insert_stream(ix, d, n, nullptr, nullptr);
+  if (rc == SVF_OK && ix->tier.on) rc = tier_warmup(ix, ix->stream);
+  return rc;
 }
 
 int svf_delete(svf_index* ix, const int32_t* ids, int64_t n) {
@@ -773,7 +1008,9 @@ int svf_search_dev(svf_index* ix, const float* d_queries, int64_t nq, int32_t k,
   if (nq > 0 && (!d_queries || !d_out_ids || !d_out_dists)) return fail(SVF_E_INVAL, "null buffer");
   std::lock_guard<std::mutex> g(ix->mu);
   hipStream_t st = stream ? (hipStream_t)stream : ix->stream;
-  return search_impl(ix, d_queries, nq, k, beam, d_out_ids, d_out_dists, d_n_dist, d_n_exp, st);
+  rc = search_impl(ix, d_queries, nq, k, beam, d_out_ids, d_out_dists, d_n_dist, d_n_exp, st);
+  if (rc == SVF_OK && ix->tier.on && ix->n_slots > 0 && nq > 0) rc = tier_after_batch(ix, nq, st);
+  return rc;
 }
 
 int svf_search(svf_index* ix, const float* queries, int64_t nq, int32_t k, int32_t beam,
@@ -798,6 +1035,7 @@ int svf_search(svf_index* ix, const float* queries, int64_t nq, int32_t k, int32
   CK(hipMemcpyAsync(out_dists, dd, (size_t)nq * k * 4, hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
   finish_search_stats(ix);
+  if (ix->tier.on && ix->n_slots > 0) return tier_after_batch(ix, nq, st);
   return SVF_OK;
 }
 
@@ -978,7 +1216,15 @@ int svf_stats_get(const svf_index* cix, svf_stats* out) {
   ix->st.n_slots = ix->n_slots;
   ix->st.n_alive = ix->n_alive;
   ix->st.capacity = ix->cap;
-  ix->st.device_bytes = ix->cap * (ix->stride * (4 + (ix->veclp_prec ? 2 : 0)) + ix->R * 8 + 8) + ix->cap / 8;
+  ix->st.device_bytes = ix->cap * ((ix->tier.on ? 0 : ix->stride * 4) + ix->stride * (ix->veclp_prec ? 2 : 0) +
+                                    ix->R * 8 + 8) + ix->cap / 8 + ix->tier.C * ix->stride * 4;
+  ix->st.cache_slots = ix->tier.C;
+  ix->st.cache_gather_hits = (int64_t)ix->tier.gather_hits;
+  ix->st.cache_gather_misses = (int64_t)ix->tier.gather_misses;
+  ix->st.cache_last_trace_hits = ix->tier.last_trace_hits;
+  ix->st.cache_last_placed = ix->tier.last_placed;
+  ix->st.cache_promotions = (int64_t)ix->tier.promotions;
+  ix->st.cache_evictions = (int64_t)ix->tier.evictions;
   *out = ix->st;
   return SVF_OK;
 }

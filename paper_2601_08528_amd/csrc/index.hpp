@@ -5,6 +5,7 @@
 
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/svf.h"
 #include "mlp.hpp"
@@ -57,7 +58,29 @@ struct Options {
 
 }  // namespace svf
 
-namespace svf { struct Server; }
+namespace svf {
+struct Server;
+
+// Tiered vector store: every vector lives in pinned host memory; an HBM cache
+// of C rows, a device mapping table id -> slot, and the placement state.
+struct TierState {
+  bool on = false;
+  int64_t C = 0;
+  float* cache = nullptr;          // device, C x stride
+  int32_t* map = nullptr;          // device, cap entries (-1 = not cached)
+  std::vector<int32_t> slot_id;    // slot -> id (-1 empty)
+  std::vector<int32_t> where;      // id -> slot (host mirror of map)
+  std::vector<uint8_t> ref;        // reference bits per slot
+  std::vector<double> fr;          // F_recent per id
+  std::vector<int32_t> e_in;       // in-degree per id
+  int64_t used = 0, clock = 0, e_in_epoch = -1;
+  double alpha = 0.6, beta = 0.4, theta = 1.0;
+  int promote_max = 2048, trace_cap = 512;
+  uint64_t gather_hits = 0, gather_misses = 0, promotions = 0, evictions = 0;
+  int64_t last_trace_hits = 0, last_placed = 0;
+  DevBuf trace, trace_n, place, counts, e_in_d;
+};
+}  // namespace svf
 
 struct svf_index {
   int dim = 0, R = 0, metric = 0;
@@ -84,4 +107,6 @@ struct svf_index {
   svf::DevBuf centroids, entry_lists, s_z, s_qentry, s_qmax;
   svf_stats st{};
   svf::Server* server = nullptr;   // non-null while the serving loop runs
+  svf::TierState tier;
+  int64_t graph_epoch = 0;         // advances whenever rows are committed
 };

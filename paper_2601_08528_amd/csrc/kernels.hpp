@@ -40,12 +40,25 @@ struct SearchArgs {
   const int32_t* q_entry;      // per query: list index, or -1 for random entries
   const int32_t* q_max_iters;  // per query iteration cap (0: none)
   int32_t* last_change;        // per query: iterations done when the top-k last changed
+  // tiered vector store (FP32 traversal only): vec is the host-resident store
+  const int32_t* tmap;         // id -> HBM cache slot, -1 when not cached
+  const float* tcache;         // cache rows, stride apart
+  int32_t* trace;              // per query: expanded vertices in order (trace_cap each)
+  int trace_cap;
+  int32_t* trace_n;            // per query: number of expansions
+  unsigned long long* tier_counts;  // [0] gathers from the cache, [1] from the host store
   unsigned long long* totals;  // [0] distances, [1] expansions
 };
 
 hipError_t launch_search(const SearchArgs& a, int precision, hipStream_t st);
 hipError_t launch_query_keys(const float* q, int64_t qstride, const int32_t* qids, int dim, int nq,
                              uint64_t seed, uint64_t* out, hipStream_t st);
+
+// ---- tiered store (tier.hip) ----
+hipError_t launch_indegree(const int32_t* graph, const uint32_t* alive, int64_t n, int R,
+                           int32_t* e_in, hipStream_t st);
+hipError_t launch_place(const int32_t* place, int np, const float* store, float* cache,
+                        int64_t stride, int32_t* map, hipStream_t st);
 
 // ---- index maintenance (update.hip) ----
 hipError_t launch_fill_u32(void* p, int64_t n, uint32_t v, hipStream_t st);

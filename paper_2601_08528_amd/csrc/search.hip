@@ -41,7 +41,10 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
   w.next = w.pool + Lp;
   w.kept = w.next + Lp;
   w.cid = reinterpret_cast<int32_t*>(w.kept + kWave);
-  void* vis_mem = reinterpret_cast<void*>(w.cid + kWave);
+  int32_t* slot = w.cid + kWave;                 // tier slots of the survivors
+  void* vis_mem = reinterpret_cast<void*>(slot + kWave);
+  const bool tier = a.tmap != nullptr;
+  unsigned long long t_hit = 0, t_miss = 0;
   w.L = a.L;
   w.ktrack = a.last_change ? (a.k > 0 ? a.k : 1) : 0;
   VIS vis;
@@ -80,11 +83,22 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
       const int room = want - got;
       const bool take = cand && r < room;
       __syncthreads();
-      if (take) { acc[got + r] = id; w.cid[r] = id; }
+      if (take) {
+        acc[got + r] = id;
+        w.cid[r] = id;
+        if (tier) slot[r] = a.tmap[id];
+      }
       const int nt = popc64(cb) < room ? popc64(cb) : room;
       got += nt;
       __syncthreads();
-      uint64_t k = gather_keys<VT, NC>(qs, base, a.stride, w.cid, nt, a.metric);
+      if (tier) {
+        const bool h = lane < nt && slot[lane] >= 0;
+        t_hit += popc64(ballot(h));
+        t_miss += nt - popc64(ballot(h));
+      }
+      uint64_t k = gather_keys<VT, NC>(qs, base, a.stride, w.cid, nt, a.metric,
+                                       tier ? slot : nullptr,
+                                       reinterpret_cast<const VT*>(a.tcache));
       n_dist += nt;
       sort_merge(w, k);
     };
@@ -148,8 +162,12 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
     int32_t parents[4];
     for (int t = 0; t < np; ++t) parents[t] = key_id(w.pool[ppos[t]]);
     __syncthreads();
-    if (lane == 0)
-      for (int t = 0; t < np; ++t) w.pool[ppos[t]] |= 1ull;
+    if (lane == 0) {
+      for (int t = 0; t < np; ++t) {
+        w.pool[ppos[t]] |= 1ull;
+        if (a.trace && n_exp + t < a.trace_cap) a.trace[(int64_t)qi * a.trace_cap + n_exp + t] = parents[t];
+      }
+    }
     n_exp += np;
     ++n_iter;
     for (int t = 0; t < np; ++t) {
@@ -161,14 +179,24 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
         __syncthreads();
         if (ok) ok = !vis.test_and_set(nb);
         const uint64_t ob = ballot(ok);
-        if (ok) w.cid[lanes_below(ob)] = nb;
+        if (ok) {
+          w.cid[lanes_below(ob)] = nb;
+          if (tier) slot[lanes_below(ob)] = a.tmap[nb];
+        }
         const int m = popc64(ob);
         __syncthreads();
         if (m == 0) continue;
+        if (tier) {
+          const bool h = lane < m && slot[lane] >= 0;
+          t_hit += popc64(ballot(h));
+          t_miss += m - popc64(ballot(h));
+        }
         // the deletion bits load while the vectors are gathered
         const int32_t mine = lane < m ? w.cid[lane] : 0;
         const uint32_t aword = a.alive[(uint32_t)mine >> 5];
-        uint64_t k = gather_keys<VT, NC>(qs, base, a.stride, w.cid, m, a.metric);
+        uint64_t k = gather_keys<VT, NC>(qs, base, a.stride, w.cid, m, a.metric,
+                                         tier ? slot : nullptr,
+                                         reinterpret_cast<const VT*>(a.tcache));
         if (lane < m && !((aword >> (mine & 31)) & 1u)) k = kKeyInf;
         n_dist += m;
         if (sort_merge(w, k)) last_change = n_iter;
@@ -219,6 +247,11 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
     if (a.n_dist) a.n_dist[qi] = n_dist;
     if (a.n_exp) a.n_exp[qi] = n_exp;
     if (a.last_change) a.last_change[qi] = last_change;
+    if (a.trace_n) a.trace_n[qi] = n_exp;
+    if (a.tier_counts) {
+      atomicAdd(&a.tier_counts[0], t_hit);
+      atomicAdd(&a.tier_counts[1], t_miss);
+    }
     if (a.totals) {
       atomicAdd(&a.totals[0], (unsigned long long)n_dist);
       atomicAdd(&a.totals[1], (unsigned long long)n_exp);
@@ -298,7 +331,7 @@ hipError_t launch_search(const SearchArgs& in, int precision, hipStream_t st) {
   if (a.id_bits < set_bits + 1) a.id_bits = set_bits + 1;
   int Lp = 64;
   while (Lp < a.L) Lp <<= 1;
-  const size_t lds = (size_t)2 * Lp * 8 + kWave * 8 + kWave * 4 + vis_bytes(a.T, assoc);
+  const size_t lds = (size_t)2 * Lp * 8 + kWave * 8 + 2 * kWave * 4 + vis_bytes(a.T, assoc);
   return assoc ? launch_vis<VisAssoc16>(a, precision, nc, lds, st)
                : launch_vis<VisLinear32>(a, precision, nc, lds, st);
 }

@@ -193,9 +193,13 @@ template <typename VT, int NC> struct GatherSteps {
 // Distances of the m (<= 64) ids in cid[] to the query; returns, in lane j,
 // the key of cid[j] (kKeyInf for j >= m).  A step gathers VPW vectors, one per
 // group of LPV lanes; U steps are loaded before any is consumed.
+// With a tier (slot != null), vector j is read from tcache row slot[j] when
+// that slot is >= 0 and from base row cid[j] otherwise.
 template <typename VT, int NC>
 __device__ inline uint64_t gather_keys(const QuerySlice<VT, NC>& qs, const VT* __restrict__ base,
-                                       int64_t stride, const int32_t* cid, int m, int metric) {
+                                       int64_t stride, const int32_t* cid, int m, int metric,
+                                       const int32_t* slot = nullptr,
+                                       const VT* __restrict__ tcache = nullptr) {
   using QS = QuerySlice<VT, NC>;
   constexpr int E = QS::E;
   constexpr int LPV = QS::kLanesPerVec;
@@ -212,7 +216,8 @@ __device__ inline uint64_t gather_keys(const QuerySlice<VT, NC>& qs, const VT* _
       const int j = (s0 + u) * VPW + sub;
       const bool on = j < m;
       const int32_t id = on ? cid[j] : 0;
-      const VT* row = base + (int64_t)id * stride;
+      const int32_t sl_ = (on && slot) ? slot[j] : -1;
+      const VT* row = sl_ >= 0 ? tcache + (int64_t)sl_ * stride : base + (int64_t)id * stride;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const int off = c * 128 + sl * E;

@@ -1,0 +1,80 @@
+"""Tiered store: vectors in pinned host memory behind an HBM cache.  The
+cache only moves bytes, so every result equals the untiered index; the
+per-batch placement (batched Alg. 2) equals the oracle's replay over the
+oracle's own expansion traces."""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2601_08528_amd as svf
+from paper_2601_08528_amd import datagen
+from gpu_util import oracle_index
+
+pytestmark = pytest.mark.gpu
+
+
+def tiered_from_oracle(oix, base, cache_rows, **opts):
+    rows, ed, alive = oix.export()
+    g = svf.Index(base.shape[1], oix.R, oix.metric, seed=opts.pop("seed", 0))
+    g.set_option("cache_bytes", cache_rows * 4 * ((base.shape[1] + 7) // 8 * 8))
+    for k, v in opts.items():
+        g.set_option(k, v)
+    g.import_graph(base, rows, ed.astype(np.float32), alive)
+    return g
+
+
+@pytest.fixture(scope="module")
+def state():
+    base, q = datagen.gmm_uint8_valued(701, 6000, 400, 64, 24)
+    return oracle_index(base, 24, seed=6), base, q
+
+
+def test_results_independent_of_cache(state):
+    oix, base, q = state
+    ref_i, ref_d, _ = oix.search(q, 10, 48)
+    g = tiered_from_oracle(oix, base, 600, seed=6)
+    for b in range(4):
+        gi, gd = g.search(q[b * 100:(b + 1) * 100], 10, 48)
+        np.testing.assert_array_equal(gi, ref_i[b * 100:(b + 1) * 100])
+        np.testing.assert_array_equal(gd.astype(np.float64), ref_d[b * 100:(b + 1) * 100])
+    st = g.stats()
+    assert st["cache_slots"] == 600
+    assert st["cache_gather_hits"] > 0 and st["cache_gather_misses"] > 0
+    assert st["cache_promotions"] > 0
+
+
+@pytest.mark.parametrize("theta,cap_rows,promote", [(1.0, 300, 2048), (0.5, 120, 64)])
+def test_placement_matches_oracle_replay(state, theta, cap_rows, promote):
+    oix, base, q = state
+    trace_cap = 64
+    g = tiered_from_oracle(oix, base, cap_rows, seed=6, cache_theta=theta,
+                           cache_promote_max=promote, cache_trace_cap=trace_cap)
+    rows, _, alive = oix.export()
+    e_in = np.zeros(len(alive), np.int64)
+    src = rows[alive.astype(bool)]
+    np.add.at(e_in, src[src >= 0], 1)
+    batches, got = [], []
+    for b in range(5):
+        qb = q[b * 80:(b + 1) * 80]
+        g.search(qb, 10, 40)
+        got.append(g.stats()["cache_last_trace_hits"])
+        tr, cnt = oix.search_expansions(qb, 40, cap=trace_cap)
+        batches.append(np.concatenate([tr[i, :min(cnt[i], trace_cap)] for i in range(len(qb))]))
+    hits, slots = O.wavp_replay(len(alive), cap_rows, e_in, alive, batches, 0.6, 0.4, theta, promote)
+    assert got == hits.tolist()
+    assert sum(got) > 0
+
+
+def test_updates_on_tiered_store_bit_exact():
+    base, q = datagen.gmm_uint8_valued(702, 3500, 60, 32, 8)
+    plain = svf.Index(32, 12, svf.METRIC_L2, seed=2, insert_batch_max=400)
+    tier = svf.Index(32, 12, svf.METRIC_L2, seed=2, insert_batch_max=400)
+    tier.set_option("cache_bytes", 500 * 32 * 4)
+    for g in (plain, tier):
+        g.build(base[:3000])
+        g.insert(base[3000:])
+        g.delete(np.arange(0, 3500, 7, dtype=np.int32))
+    for a, b in zip(plain.export_graph(), tier.export_graph()):
+        np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(plain.search(q, 10, 32)[0], tier.search(q, 10, 32)[0])
+    assert tier.stats()["cache_slots"] == 500

@@ -107,3 +107,34 @@ def test_stop_step_label_is_where_topk_settles(idx):
         capped = ix.search(q[i:i + 1], 10, 32)
         np.testing.assert_array_equal(capped[0][0], ref[0][i])
     ix.set("max_iters", 0)
+
+
+def test_wavp_hand_worked():
+    import json, os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "wavp_example.json")))
+    hits, slots = O.wavp_replay(g["n"], g["C"], g["e_in"], np.ones(g["n"], np.uint8), g["batches"],
+                                g["alpha"], g["beta"], g["theta"], g["promote_max"])
+    assert hits.tolist() == g["expect_hits"]
+    assert slots.tolist() == g["expect_slots"]
+
+
+def test_wavp_threshold_and_indegree_terms():
+    """theta above every prediction keeps the cache empty; with no recency,
+    in-degree alone orders the placements (Eq. 2)."""
+    hits, slots = O.wavp_replay(4, 2, [0, 0, 0, 0], np.ones(4, np.uint8), [[0, 1, 2, 3]] * 3,
+                                theta=10.0)
+    assert (slots == -1).all() and (hits == 0).all()
+    e_in = [1, 50, 7, 200]
+    hits, slots = O.wavp_replay(4, 2, e_in, np.ones(4, np.uint8), [[0, 1, 2, 3]], alpha=0.0,
+                                beta=1.0, theta=0.0)
+    assert slots.tolist() == [3, 1]
+
+
+def test_expansion_trace_matches_search(idx):
+    ix, base, q = idx
+    tr, cnt = ix.search_expansions(q, 24)
+    ref = ix.search(q, 10, 24)
+    np.testing.assert_array_equal(cnt, ref[2]["n_exp"])
+    for i in range(q.shape[0]):
+        t = tr[i, :cnt[i]]
+        assert len(set(t.tolist())) == len(t)        # each vertex expanded once
