@@ -211,9 +211,9 @@ int svf_mlp_train(svf_mlp *m, const float *x, const int32_t *label, const float 
 const char *svf_mlp_last_error(void);
 
 /* Search whose pools start from caller-given entry points: entries is nq x
- * ecap ids (host memory, -1 = unused); a query's pool starts from the first
- * min(beam, n_alive) distinct alive ids of its list, in list order, and a
- * list with no usable id falls back to random entry points.  max_iters (nq
+ * ecap ids (host memory, -1 = unused); every distinct alive id of a query's
+ * list is evaluated and the best `beam` of them start its pool; a list with
+ * no usable id falls back to random entry points.  max_iters (nq
  * ints, may be NULL) caps each query's expansions (0 = none).  This is the
  * search step of the learned form with the predictions supplied directly. */
 int svf_search_listed(svf_index *ix, const float *queries, int64_t nq, int32_t k, int32_t beam,

@@ -978,9 +978,9 @@ void orc_query_dists(const orc_index *ix, const float *q, int64_t nq, int k, con
 
 /* ------------------------------------------------------------------------ */
 /* Search with caller-given entry points and per-query expansion caps.
- * entries: nq x ecap ids (-1 = none); the first min(L, n_alive) distinct alive
- * ids of a query's list, in list order, start its pool (a list with no usable
- * id leaves the random initialisation).  max_iters: nq caps (0 = none).  The
+ * entries: nq x ecap ids (-1 = none); every distinct alive id of a query's
+ * list is evaluated and the best L of them by (d,id) start its pool (a list
+ * with no usable id leaves the random initialisation).  max_iters: nq caps (0 = none).  The
  * rest is the search above.  This is how predicted entry points and a
  * predicted stopping step enter the method (random entry points being one
  * choice among algorithm-supplied ones, Sec. 2.3). */
@@ -993,7 +993,7 @@ static int search_one_listed(const orc_index *ix, const float *qf, const double 
     memset(st, 0, sizeof *st);
     st->margin = INFINITY;
     int ne = 0;
-    for (int j = 0; j < ecap && ne < L; ++j) {
+    for (int j = 0; j < ecap; ++j) {
         int32_t id = list[j];
         if (id < 0 || id >= ix->n_slots || !ix->alive[id] || s->visited[id]) continue;
         visit(s, id);
@@ -1011,7 +1011,7 @@ static int search_one_listed(const orc_index *ix, const float *qf, const double 
         return np;
     }
     qsort(s->fresh, ne, sizeof(pentry), cmp_pentry);
-    int np = ne;
+    int np = ne < L ? ne : L;
     memcpy(s->pool, s->fresh, np * sizeof(pentry));
     int32_t lc = 0;
     for (;;) {

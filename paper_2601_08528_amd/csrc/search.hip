@@ -63,9 +63,9 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
 
   // ---- InitCandidatePool ------------------------------------------------------
   // Random entries: the first min(E, n_alive) distinct alive ids in the order
-  // of the query's own SplitMix64 stream.  Listed entries (learned form): the
-  // first min(L, n_alive) distinct alive ids of the query's list, in list
-  // order; a list with no usable id falls back to random entries.  Accepted
+  // of the query's own SplitMix64 stream.  Listed entries (learned form): every
+  // distinct alive id of the query's list; a list with no usable id falls back
+  // to random entries.  In both cases the best L keys start the pool.  Accepted
   // ids sit in an exact list that borrows the visited-table LDS.
   {
     int32_t* acc = static_cast<int32_t*>(vis_mem);
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
     const int list = a.q_entry ? a.q_entry[qi] : -1;
     if (list >= 0) {
       const int32_t* ent = a.entry_lists + (int64_t)list * a.entry_cap;
-      const int want = a.L < a.n_alive ? a.L : a.n_alive;
+      const int want = a.entry_cap;
       for (int j0 = 0; j0 < a.entry_cap && got < want; j0 += kWave) {
         const int j = j0 + lane;
         const int32_t id = j < a.entry_cap ? ent[j] : -1;
