@@ -184,6 +184,9 @@ def main():
     ap.add_argument("--n-query", type=int, default=10_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy 1 GiB device-to-device three times (a reference "
+                         "kernel of known traffic for hardware counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -198,6 +201,13 @@ def main():
     # a dedicated stream: the search kernels and the timing events share it
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
+    if args.copy_probe:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     log("generating workload")
     base, queries = datagen.workload_1m_int(args.n_base, args.n_query)
     ix = svf.Index(DIM, DEGREE, svf.METRIC_L2, seed=0)

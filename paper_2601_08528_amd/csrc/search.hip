@@ -29,7 +29,7 @@ namespace svf {
 
 
 // ---------------------------------------------------------------------------
-template <typename VT, int NC, typename VIS>
+template <typename VT, int NC, typename VIS, bool TIER>
 __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int qi = blockIdx.x;
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
   w.cid = reinterpret_cast<int32_t*>(w.kept + kWave);
   int32_t* slot = w.cid + kWave;                 // tier slots of the survivors
   void* vis_mem = reinterpret_cast<void*>(slot + kWave);
-  const bool tier = a.tmap != nullptr;
+  constexpr bool tier = TIER;
   unsigned long long t_hit = 0, t_miss = 0;
   w.L = a.L;
   w.ktrack = a.last_change ? (a.k > 0 ? a.k : 1) : 0;
@@ -96,9 +96,8 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
         t_hit += popc64(ballot(h));
         t_miss += nt - popc64(ballot(h));
       }
-      uint64_t k = gather_keys<VT, NC>(qs, base, a.stride, w.cid, nt, a.metric,
-                                       tier ? slot : nullptr,
-                                       reinterpret_cast<const VT*>(a.tcache));
+      uint64_t k = gather_keys<VT, NC, TIER>(qs, base, a.stride, w.cid, nt, a.metric, slot,
+                                             reinterpret_cast<const VT*>(a.tcache));
       n_dist += nt;
       sort_merge(w, k);
     };
@@ -165,7 +164,8 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
     if (lane == 0) {
       for (int t = 0; t < np; ++t) {
         w.pool[ppos[t]] |= 1ull;
-        if (a.trace && n_exp + t < a.trace_cap) a.trace[(int64_t)qi * a.trace_cap + n_exp + t] = parents[t];
+        if (TIER && a.trace && n_exp + t < a.trace_cap)
+          a.trace[(int64_t)qi * a.trace_cap + n_exp + t] = parents[t];
       }
     }
     n_exp += np;
@@ -194,9 +194,8 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
         // the deletion bits load while the vectors are gathered
         const int32_t mine = lane < m ? w.cid[lane] : 0;
         const uint32_t aword = a.alive[(uint32_t)mine >> 5];
-        uint64_t k = gather_keys<VT, NC>(qs, base, a.stride, w.cid, m, a.metric,
-                                         tier ? slot : nullptr,
-                                         reinterpret_cast<const VT*>(a.tcache));
+        uint64_t k = gather_keys<VT, NC, TIER>(qs, base, a.stride, w.cid, m, a.metric, slot,
+                                               reinterpret_cast<const VT*>(a.tcache));
         if (lane < m && !((aword >> (mine & 31)) & 1u)) k = kKeyInf;
         n_dist += m;
         if (sort_merge(w, k)) last_change = n_iter;
@@ -247,8 +246,8 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
     if (a.n_dist) a.n_dist[qi] = n_dist;
     if (a.n_exp) a.n_exp[qi] = n_exp;
     if (a.last_change) a.last_change[qi] = last_change;
-    if (a.trace_n) a.trace_n[qi] = n_exp;
-    if (a.tier_counts) {
+    if (TIER && a.trace_n) a.trace_n[qi] = n_exp;
+    if (TIER && a.tier_counts) {
       atomicAdd(&a.tier_counts[0], t_hit);
       atomicAdd(&a.tier_counts[1], t_miss);
     }
@@ -293,14 +292,14 @@ static bool use_assoc16(int32_t n_slots, int T) {
 }
 static size_t vis_bytes(int T, bool assoc16) { return assoc16 ? (size_t)T * 2 : (size_t)T * 4; }
 
-template <typename VT, typename VIS>
+template <typename VT, typename VIS, bool TIER>
 static hipError_t launch_vt(const SearchArgs& a, int nc, size_t lds, hipStream_t st) {
   dim3 grid(a.nq), block(kWave);
   switch (nc) {
-    case 1: hipLaunchKernelGGL((search_kernel<VT, 1, VIS>), grid, block, lds, st, a); break;
-    case 2: hipLaunchKernelGGL((search_kernel<VT, 2, VIS>), grid, block, lds, st, a); break;
-    case 4: hipLaunchKernelGGL((search_kernel<VT, 4, VIS>), grid, block, lds, st, a); break;
-    case 8: hipLaunchKernelGGL((search_kernel<VT, 8, VIS>), grid, block, lds, st, a); break;
+    case 1: hipLaunchKernelGGL((search_kernel<VT, 1, VIS, TIER>), grid, block, lds, st, a); break;
+    case 2: hipLaunchKernelGGL((search_kernel<VT, 2, VIS, TIER>), grid, block, lds, st, a); break;
+    case 4: hipLaunchKernelGGL((search_kernel<VT, 4, VIS, TIER>), grid, block, lds, st, a); break;
+    case 8: hipLaunchKernelGGL((search_kernel<VT, 8, VIS, TIER>), grid, block, lds, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -309,9 +308,11 @@ static hipError_t launch_vt(const SearchArgs& a, int nc, size_t lds, hipStream_t
 template <typename VIS>
 static hipError_t launch_vis(const SearchArgs& a, int precision, int nc, size_t lds, hipStream_t st) {
   switch (precision) {
-    case 0: return launch_vt<float, VIS>(a, nc, lds, st);
-    case 1: return launch_vt<__half, VIS>(a, nc, lds, st);
-    case 2: return launch_vt<bf16_t, VIS>(a, nc, lds, st);
+    case 0:
+      return a.tmap ? launch_vt<float, VIS, true>(a, nc, lds, st)
+                    : launch_vt<float, VIS, false>(a, nc, lds, st);
+    case 1: return a.tmap ? hipErrorInvalidValue : launch_vt<__half, VIS, false>(a, nc, lds, st);
+    case 2: return a.tmap ? hipErrorInvalidValue : launch_vt<bf16_t, VIS, false>(a, nc, lds, st);
   }
   return hipErrorInvalidValue;
 }

@@ -193,9 +193,9 @@ template <typename VT, int NC> struct GatherSteps {
 // Distances of the m (<= 64) ids in cid[] to the query; returns, in lane j,
 // the key of cid[j] (kKeyInf for j >= m).  A step gathers VPW vectors, one per
 // group of LPV lanes; U steps are loaded before any is consumed.
-// With a tier (slot != null), vector j is read from tcache row slot[j] when
-// that slot is >= 0 and from base row cid[j] otherwise.
-template <typename VT, int NC>
+// With a tier (TIER), vector j is read from tcache row slot[j] when that slot
+// is >= 0 and from base row cid[j] otherwise.
+template <typename VT, int NC, bool TIER = false>
 __device__ inline uint64_t gather_keys(const QuerySlice<VT, NC>& qs, const VT* __restrict__ base,
                                        int64_t stride, const int32_t* cid, int m, int metric,
                                        const int32_t* slot = nullptr,
@@ -204,7 +204,10 @@ __device__ inline uint64_t gather_keys(const QuerySlice<VT, NC>& qs, const VT* _
   constexpr int E = QS::E;
   constexpr int LPV = QS::kLanesPerVec;
   constexpr int VPW = QS::kVecPerWave;
-  constexpr int U = GatherSteps<VT, NC>::value < LPV ? GatherSteps<VT, NC>::value : LPV;
+  // the tiered variant keeps half as many loads in flight (its row choice
+  // needs registers); the reduction tree, and so every sum, is the same
+  constexpr int UB = GatherSteps<VT, NC>::value < LPV ? GatherSteps<VT, NC>::value : LPV;
+  constexpr int U = TIER ? (UB / 2 < 2 ? 2 : UB / 2) : UB;
   const int lane = lane_id();
   const int sub = lane / LPV, sl = lane % LPV;
   float mine = 0.0f;
@@ -216,8 +219,11 @@ __device__ inline uint64_t gather_keys(const QuerySlice<VT, NC>& qs, const VT* _
       const int j = (s0 + u) * VPW + sub;
       const bool on = j < m;
       const int32_t id = on ? cid[j] : 0;
-      const int32_t sl_ = (on && slot) ? slot[j] : -1;
-      const VT* row = sl_ >= 0 ? tcache + (int64_t)sl_ * stride : base + (int64_t)id * stride;
+      const VT* row = base + (int64_t)id * stride;
+      if constexpr (TIER) {
+        const int32_t sl_ = on ? slot[j] : -1;
+        if (sl_ >= 0) row = tcache + (int64_t)sl_ * stride;
+      }
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const int off = c * 128 + sl * E;

@@ -90,25 +90,26 @@ def test_listed_entry_search_bit_exact():
 
 
 def test_learned_form_gain_over_plain():
-    """40k x 128 integer mixture with 256 components, degree 16, 256 entry
-    clusters: entry points from the predicted cluster raise recall at a small
-    beam over random entry points."""
-    base, q = datagen.gmm_uint8_valued(505, 40_000, 2000, 128, 256)
-    train = datagen.training_queries_uint8(505, 20_000, 128, 256)
-    g = svf.Index(128, 16, svf.METRIC_L2, seed=1)
+    """200k x 128 integer mixture with 256 components: random entry points
+    rarely land in the query's component, so at a small beam the search often
+    ends in the wrong one; entry points from the predicted cluster raise
+    recall@10 at the same beam."""
+    base, q = datagen.gmm_uint8_valued(505, 200_000, 1000, 128, 256)
+    train = datagen.training_queries_uint8(505, 50_000, 128, 256)
+    g = svf.Index(128, 32, svf.METRIC_L2, seed=1)
     g.build(base)
     loss = g.model_fit(train, 10, 64, n_clusters=256, epochs=8)
     assert np.isfinite(loss)
-    gt_i, gt_d = O.bruteforce(base, q, 10, threads=8)
-    ref = O.OracleIndex(128, 16, O.L2)           # vectors only: exact distances
+    gt_i, gt_d = O.bruteforce(base, q, 10, threads=16)
     n = base.shape[0]
-    ref.import_state(base, -np.ones((n, 16), np.int32), np.full((n, 16), np.inf),
+    ref = O.OracleIndex(128, 32, O.L2)           # vectors only: exact distances
+    ref.import_state(base, -np.ones((n, 32), np.int32), np.full((n, 32), np.inf),
                      np.ones(n, np.uint8))
 
     def rec(ids):
         return O.recall_at_k(ids, ref.query_dists(q, ids), gt_d, 10)
 
-    beam = 12
+    beam = 32
     plain = rec(g.search(q, 10, beam)[0])
     g.set_option("use_model", 1)
     g.set_option("model_conf", 0.0)
