@@ -30,6 +30,30 @@ HBM_PEAK_GBS = 8000.0
 DIM, DEGREE, K = 128, 64, 10
 BEAMS = [32, 48, 64, 96, 128, 192, 256, 384, 512]
 
+# Beyond-L2 traffic of one timed search launch (FP32, beam 96, this workload), from
+# two rocprofv3 counter passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean
+# of the steady dispatches).  Each counter is scaled by what it reads for a 1 GiB
+# device-to-device copy in the same process (FETCH_SIZE reads 524,300 KiB there,
+# WRITE_SIZE 1,048,576).  The figure describes the kernel built from the sources
+# whose hash is recorded; any edit to them makes it stale and it is reported as null.
+COUNTED = {"sources": ("common.hpp", "wave_ops.hpp", "search.hip"),
+           "sha256_16": "188e966edd9a72ce", "beam": 96,
+           "fetch_kib": 9735444.0, "fetch_scale": 1048576.0 / 524300.0,
+           "write_kib": 2516.1, "write_scale": 1.0}
+
+
+def counted_traffic(beam):
+    import hashlib
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2601_08528_amd", "csrc")
+    h = hashlib.sha256()
+    for f in COUNTED["sources"]:
+        with open(os.path.join(here, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != COUNTED["sha256_16"] or beam != COUNTED["beam"]:
+        return None
+    return round((COUNTED["fetch_kib"] * COUNTED["fetch_scale"]
+                  + COUNTED["write_kib"] * COUNTED["write_scale"]) * 1024.0)
+
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
@@ -184,6 +208,9 @@ def main():
     ap.add_argument("--n-query", type=int, default=10_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--search-only", type=int, default=0, metavar="BEAM",
+                    help="build, then only time the plain FP32 search at this beam (for "
+                         "hardware counter runs); prints a short JSON line")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device-to-device three times (a reference "
                          "kernel of known traffic for hardware counter runs)")
@@ -224,6 +251,14 @@ def main():
             torch.empty((nq, K), dtype=torch.float32, device="cuda"),
             torch.empty(nq, dtype=torch.int32, device="cuda"),
             torch.empty(nq, dtype=torch.int32, device="cuda"))
+    if args.search_only:
+        ms, _ = timed_steps(torch, ix, q_t, args.search_only, bufs, args.steps, args.warmup)
+        n_dist = int(bufs[2].sum().item())
+        n_exp = int(bufs[3].sum().item())
+        print(json.dumps({"beam": args.search_only, "ms_per_step": round(float(np.mean(ms)), 4),
+                          "n_dist": n_dist, "n_exp": n_exp,
+                          "alg_bytes": n_dist * DIM * 4 + n_exp * DEGREE * 4}), flush=True)
+        return
     kth = exact_kth(torch, base_t, q_t, K)
     torch.cuda.synchronize()
 
@@ -331,7 +366,8 @@ def main():
                    "n_base": args.n_base, "n_query": nq, "dim": DIM, "degree": DEGREE, "k": K,
                    "beam": beam, "recall@10": round(rec, 5)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": counted_traffic(beam), "traffic_unit": "bytes/launch",
                      "kernel": "search_kernel<float,1>",
                      "alg_bytes_per_launch": alg_bytes,
                      "n_dist_per_query": round(n_dist / nq, 1),
