@@ -17,7 +17,7 @@ SRC = os.path.join(HERE, "svf_oracle.c")
 LIB = os.path.join(HERE, "liborc.so")
 
 L2, IP = 0, 1
-P_FP32, P_FP16, P_BF16 = 0, 1, 2
+P_FP32, P_FP16, P_BF16, P_FP8 = 0, 1, 2, 3
 
 
 def build(force: bool = False) -> str:
@@ -61,6 +61,9 @@ def lib():
         L.orc_round_fp16.argtypes = [f64]
         L.orc_round_bf16.restype = f64
         L.orc_round_bf16.argtypes = [f64]
+        L.orc_round_e4m3.restype = f64
+        L.orc_round_e4m3.argtypes = [f64]
+        L.orc_fp8_vectors.argtypes = [vp, i64, i32, i32, vp, vp]
         L.orc_fnv1a64.restype = u64
         L.orc_fnv1a64.argtypes = [vp, i64]
         L.orc_splitmix64.restype = u64
@@ -221,6 +224,22 @@ def round_fp16(x: float) -> float:
 
 def round_bf16(x: float) -> float:
     return lib().orc_round_bf16(float(x))
+
+
+def round_e4m3(x: float) -> float:
+    """OCP FP8 E4M3 value grid, round to nearest even, saturating at 448."""
+    return lib().orc_round_e4m3(float(x))
+
+
+def fp8_vectors(x, query: bool = False):
+    """FP8 form of the rows of x (float32): (per-row scale, reconstructed values
+    in float64).  query=True gives the query form (FP32 products)."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    n, d = x.shape
+    sc = np.empty(n, dtype=np.float32)
+    out = np.empty((n, d), dtype=np.float64)
+    lib().orc_fp8_vectors(_p(x), n, d, 1 if query else 0, _p(sc), _p(out))
+    return sc, out
 
 
 def fnv1a64(b: bytes) -> int:

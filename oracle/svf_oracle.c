@@ -41,7 +41,7 @@
 #define ORC_INVALID (-1)
 enum { ORC_L2 = 0, ORC_IP = 1 };
 enum { ORC_OK = 0, ORC_E_INVAL = -1, ORC_E_NOMEM = -2, ORC_E_NOTFOUND = -4 };
-enum { ORC_P_FP32 = 0, ORC_P_FP16 = 1, ORC_P_BF16 = 2 };
+enum { ORC_P_FP32 = 0, ORC_P_FP16 = 1, ORC_P_BF16 = 2, ORC_P_FP8 = 3 };
 
 typedef struct {
     int dim, R, metric;
@@ -91,6 +91,44 @@ static double lp_value(int precision, float v)
     if (precision == ORC_P_FP16) return to_fp16((double)v);
     if (precision == ORC_P_BF16) return to_bf16((double)v);
     return (double)v;
+}
+
+/* OCP FP8 E4M3 ("E4M3FN"): 4 exponent bits with bias 7, 3 fraction bits,
+ * smallest normal 2^-6, no infinities, largest finite 448.  Round to nearest,
+ * ties to even; magnitudes beyond 448 saturate to 448. */
+static double to_e4m3(double x)
+{
+    double r = round_to_grid(x, 3, -6, 448.0);
+    if (isinf(r)) r = copysign(448.0, x);
+    return r;
+}
+
+/* Per-vector scale of the FP8 form: the largest magnitude over 448, an FP32
+ * quotient (1 for an all-zero vector), so that the largest element maps to
+ * the largest finite code. */
+static float fp8_scale(const float *x, int d)
+{
+    float m = 0.0f;
+    for (int i = 0; i < d; ++i) { float a = fabsf(x[i]); if (a > m) m = a; }
+    return m > 0.0f ? m / 448.0f : 1.0f;
+}
+
+/* The values a vector takes on the search grid.  FP16/BF16: each element
+ * rounded.  FP8: code c_i = E4M3(x_i / s) of the FP32 quotient; a stored
+ * vector is reconstructed exactly as s * c_i, a query as the FP32 product
+ * s * c_i (it is held in FP32 while it searches). */
+static void lp_vector(int precision, const float *x, int d, int is_query, double *out)
+{
+    if (precision == ORC_P_FP8) {
+        const float s = fp8_scale(x, d);
+        for (int i = 0; i < d; ++i) {
+            const float t = x[i] / s;
+            const double c = to_e4m3((double)t);
+            out[i] = is_query ? (double)(s * (float)c) : (double)s * c;
+        }
+        return;
+    }
+    for (int i = 0; i < d; ++i) out[i] = lp_value(precision, x[i]);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -172,10 +210,10 @@ int orc_set(orc_index *ix, const char *key, double v)
     else if (!strcmp(key, "seed")) { ix->seed = (uint64_t)v; }
     else if (!strcmp(key, "insert_batch_max")) { if (v < 1) return ORC_E_INVAL; ix->insert_batch_max = (int64_t)v; }
     else if (!strcmp(key, "precision")) {
-        if (v != 0 && v != 1 && v != 2) return ORC_E_INVAL;
+        if (v != 0 && v != 1 && v != 2 && v != 3) return ORC_E_INVAL;
         ix->precision = (int)v;
-        for (int64_t i = 0; i < ix->n_slots * ix->dim; ++i)
-            ix->vec_lp[i] = lp_value(ix->precision, ix->vec_f32[i]);
+        for (int64_t i = 0; i < ix->n_slots; ++i)
+            lp_vector(ix->precision, ix->vec_f32 + i * ix->dim, ix->dim, 0, ix->vec_lp + i * ix->dim);
     }
     else return ORC_E_INVAL;
     return ORC_OK;
@@ -220,8 +258,8 @@ static void store_vectors(orc_index *ix, int64_t at, const float *v, int64_t n)
             float x = v[i * d + j];
             ix->vec_f32[(at + i) * d + j] = x;
             ix->vec[(at + i) * d + j] = (double)x;
-            ix->vec_lp[(at + i) * d + j] = lp_value(ix->precision, x);
         }
+        lp_vector(ix->precision, v + i * d, d, 0, ix->vec_lp + (at + i) * d);
         for (int r = 0; r < ix->R; ++r) {
             ix->rows[(at + i) * ix->R + r] = ORC_INVALID;
             ix->edge_d[(at + i) * ix->R + r] = INFINITY;
@@ -456,8 +494,9 @@ static void *search_worker(void *arg)
         const float *qf = j->q + i * d;
         double qn = 0.0;
         for (int t = 0; t < d; ++t) {
-            q[t] = (double)qf[t]; qlp[t] = lp_value(ix->precision, qf[t]); qn += q[t] * q[t];
+            q[t] = (double)qf[t]; qn += q[t] * q[t];
         }
+        lp_vector(ix->precision, qf, d, 1, qlp);
         qstats st;
         int np = search_one(ix, ix->n_slots, qf, qlp, j->L, ix->entry_samples, ix->search_width,
                             ix->max_iters, &s, &st, sqrt(qn) * j->xmax);
@@ -651,10 +690,12 @@ static int insert_one_batch(orc_index *ix, const float *vecs, int64_t b, int32_t
     int32_t *cid = malloc(sizeof(int32_t) * (Lins + 8));
     double *cdd = malloc(sizeof(double) * (Lins + 8));
     snap_ctx sc = {ix->rows, n0, NULL, 0, R};
+    double *qlp = malloc(sizeof(double) * d);
     for (int64_t i = 0; i < b; ++i) {
         const int64_t v = n0 + i;
         qstats st;
-        int np = search_one(ix, n0, ix->vec_f32 + v * d, ix->vec_lp + v * d, Lins, ix->entry_samples,
+        lp_vector(ix->precision, ix->vec_f32 + v * d, d, 1, qlp);
+        int np = search_one(ix, n0, ix->vec_f32 + v * d, qlp, Lins, ix->entry_samples,
                             ix->search_width, 0, &s, &st, xmax);
         /* exact distances for the edges when the search ran on a coarser grid */
         if (ix->precision != ORC_P_FP32) {
@@ -664,7 +705,7 @@ static int insert_one_batch(orc_index *ix, const float *vecs, int64_t b, int32_t
         for (int t = 0; t < np; ++t) { cid[t] = s.pool[t].id; cdd[t] = s.pool[t].d; }
         prune(R, np, cid, cdd, snap_row, &sc, fwd + i * R, fwd_d + i * R);
     }
-    free(cid); free(cdd);
+    free(cid); free(cdd); free(qlp);
     scratch_free(&s);
 
     /* Group reverse edges by target. */
@@ -853,7 +894,9 @@ static void repair(orc_index *ix, int consolidate)
         }
         if (m < R) {
             qstats st;
-            int np = search_one(ix, n, ix->vec_f32 + v * d, ix->vec_lp + v * d, ix->beam_insert,
+            double *qlp = malloc(sizeof(double) * d);
+            lp_vector(ix->precision, ix->vec_f32 + v * d, d, 1, qlp);
+            int np = search_one(ix, n, ix->vec_f32 + v * d, qlp, ix->beam_insert,
                                 ix->entry_samples, ix->search_width, 0, &s, &st, xmax);
             for (int t = 0; t < np; ++t) {
                 int32_t u = s.pool[t].id;
@@ -862,6 +905,7 @@ static void repair(orc_index *ix, int consolidate)
                 cl[m].d = dist(ix->metric, ix->vec + v * d, ix->vec + (int64_t)u * d, d);
                 incand[u] = 1; ++m;
             }
+            free(qlp);
         }
         for (int i = 0; i < m; ++i) incand[cl[i].id] = 0;
         qsort(cl, m, sizeof(pentry), cmp_cand);
@@ -941,6 +985,16 @@ double orc_dist_ids(const orc_index *ix, int32_t a, int32_t b)
 /* The value grids, exposed so tests can pin them against published formats. */
 double orc_round_fp16(double x) { return to_fp16(x); }
 double orc_round_bf16(double x) { return to_bf16(x); }
+double orc_round_e4m3(double x) { return to_e4m3(x); }
+/* The FP8 form of n vectors: per-vector scale and the reconstructed values
+ * (stored-vector form, or query form when is_query != 0). */
+void orc_fp8_vectors(const float *x, int64_t n, int d, int is_query, float *scale, double *out)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        scale[i] = fp8_scale(x + i * d, d);
+        lp_vector(ORC_P_FP8, x + i * d, d, is_query, out + i * d);
+    }
+}
 uint64_t orc_fnv1a64(const unsigned char *p, int64_t n) { return fnv1a64(p, (size_t)n); }
 uint64_t orc_splitmix64(uint64_t state, uint64_t j) { return splitmix64_out(state, j); }
 
@@ -1060,7 +1114,7 @@ int orc_search_trace(const orc_index *ix, const float *q, int64_t nq, int k, int
     double *qlp = malloc(sizeof(double) * d);
     for (int64_t i = 0; i < nq; ++i) {
         const float *qf = q + i * d;
-        for (int t = 0; t < d; ++t) qlp[t] = lp_value(ix->precision, qf[t]);
+        lp_vector(ix->precision, qf, d, 1, qlp);
         qstats st;
         int np = search_one_t(ix, ix->n_slots, qf, qlp, L, ix->entry_samples, ix->search_width,
                               ix->max_iters, &s, &st, 0.0, k, last_change + i);
@@ -1082,7 +1136,7 @@ int orc_search_listed(const orc_index *ix, const float *q, int64_t nq, int k, in
     double *qlp = malloc(sizeof(double) * d);
     for (int64_t i = 0; i < nq; ++i) {
         const float *qf = q + i * d;
-        for (int t = 0; t < d; ++t) qlp[t] = lp_value(ix->precision, qf[t]);
+        lp_vector(ix->precision, qf, d, 1, qlp);
         qstats st;
         int np = search_one_listed(ix, qf, qlp, L, entries + i * ecap, ecap,
                                    max_iters ? max_iters[i] : 0, &s, &st, NULL);
@@ -1201,7 +1255,7 @@ int orc_search_expansions(const orc_index *ix, const float *q, int64_t nq, int L
     double *qlp = malloc(sizeof(double) * d);
     for (int64_t i = 0; i < nq; ++i) {
         const float *qf = q + i * d;
-        for (int t = 0; t < d; ++t) qlp[t] = lp_value(ix->precision, qf[t]);
+        lp_vector(ix->precision, qf, d, 1, qlp);
         /* the search of search_one, recording parents */
         qstats st;
         memset(&st, 0, sizeof st);

@@ -88,6 +88,28 @@ def gmm_uint8_valued(workload: int, n_base: int, n_query: int, dim: int, n_comp:
     return np.ascontiguousarray(base), np.ascontiguousarray(queries)
 
 
+# Integers whose eightfold lies on the FP8 E4M3 grid: 0..16, even 18..32,
+# multiples of 4 from 36 to 56.
+FP8_EXACT_LEVELS = np.array(list(range(0, 17)) + list(range(18, 33, 2)) + list(range(36, 57, 4)),
+                            dtype=np.float32)
+
+
+def gmm_fp8_exact_valued(workload: int, n_base: int, n_query: int, dim: int, n_comp: int):
+    """The integer-valued mixture mapped onto FP8_EXACT_LEVELS (each value v in
+    0..255 goes to the level nearest 56 v / 255), with coordinate 0 set to 56
+    in every row, so each row's largest magnitude is 56."""
+    out = []
+    for a in gmm_uint8_valued(workload, n_base, n_query, dim, n_comp):
+        t = a * np.float32(56.0 / 255.0)
+        idx = np.searchsorted(FP8_EXACT_LEVELS, t)
+        idx = np.clip(idx, 1, len(FP8_EXACT_LEVELS) - 1)
+        lo, hi = FP8_EXACT_LEVELS[idx - 1], FP8_EXACT_LEVELS[idx]
+        v = np.where(t - lo <= hi - t, lo, hi).astype(np.float32)
+        v[:, 0] = 56.0
+        out.append(np.ascontiguousarray(v))
+    return out[0], out[1]
+
+
 def training_queries_uint8(workload: int, n: int, dim: int, n_comp: int,
                            mean_mu: float = 128.0, mean_std: float = 32.0, sigma: float = 16.0):
     means = mean_mu + mean_std * rng(workload, ROLE_MEANS).standard_normal((n_comp, dim))

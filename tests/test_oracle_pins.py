@@ -346,3 +346,96 @@ def test_inner_product_full_width_equals_bruteforce():
     gi, gd = O.bruteforce(base, q, 10, metric=O.IP)
     np.testing.assert_array_equal(ids, gi)
     np.testing.assert_array_equal(d, gd)
+
+
+# --- FP8 (E4M3, per-vector scale) -------------------------------------------------
+def _e4m3_grid():
+    torch = pytest.importorskip("torch")
+    codes = torch.arange(256, dtype=torch.int32).to(torch.uint8).view(torch.float8_e4m3fn)
+    v = codes.to(torch.float64).numpy()
+    return np.unique(v[np.isfinite(v)])
+
+
+def test_e4m3_rounding_matches_torch():
+    """In-range values (|x| <= 448) against torch's float8_e4m3fn conversion,
+    including every midpoint between neighbouring grid values (ties to even)."""
+    torch = pytest.importorskip("torch")
+    grid = _e4m3_grid()
+    assert grid.max() == 448.0 and len(grid) == 253          # 126 positive, 126 negative, 0
+    g = np.random.Generator(np.random.Philox(13))
+    mids = ((grid[1:] + grid[:-1]) / 2).astype(np.float32)
+    xs = np.concatenate([g.standard_normal(20000) * np.exp(g.uniform(-12, 6, 20000)),
+                         mids, grid]).astype(np.float32)
+    xs = xs[np.abs(xs) <= 448]
+    ref = torch.from_numpy(xs).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    got = np.array([O.round_e4m3(float(x)) for x in xs])
+    np.testing.assert_array_equal(got, ref)
+
+
+def test_e4m3_saturates():
+    for x, want in [(448.0, 448.0), (449.0, 448.0), (463.99, 448.0), (464.0, 448.0),
+                    (1e30, 448.0), (-500.0, -448.0), (2.0 ** -10, 0.0), (3 * 2.0 ** -10, 2.0 ** -8)]:
+        assert O.round_e4m3(x) == want, x
+
+
+def test_fp8_vector_form():
+    """Scale = FP32 max|x| / 448; stored values = scale * E4M3(x / scale) exactly;
+    query values = the FP32 product; error within half a grid step."""
+    torch = pytest.importorskip("torch")
+    g = np.random.Generator(np.random.Philox(14))
+    x = (g.standard_normal((50, 37)) * np.exp(g.uniform(-8, 8, (50, 1)))).astype(np.float32)
+    x[3] = 0.0                                                # all-zero row: scale 1
+    sc, xs = O.fp8_vectors(x)
+    sq, xq = O.fp8_vectors(x, query=True)
+    m = np.abs(x).max(axis=1)
+    want_sc = np.where(m > 0, m / np.float32(448.0), np.float32(1.0)).astype(np.float32)
+    np.testing.assert_array_equal(sc, want_sc)
+    np.testing.assert_array_equal(sq, want_sc)
+    t = (x / want_sc[:, None]).astype(np.float32)
+    c = torch.from_numpy(t).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    np.testing.assert_array_equal(xs, want_sc[:, None].astype(np.float64) * c)
+    np.testing.assert_array_equal(xq, (want_sc[:, None] * c.astype(np.float32)).astype(np.float64))
+    # E4M3 keeps 3 fraction bits: half a step is 2^-4 relative (normal range),
+    # 2^-10 absolute below 2^-6 (before scaling)
+    bound = 2.0 ** -4 * np.abs(x) + want_sc[:, None] * 2.0 ** -10 + 1e-6 * np.abs(x)
+    assert np.all(np.abs(xs - x) <= bound)
+    assert np.abs(xs[3]).max() == 0.0
+
+
+def test_fp8_exact_levels_are_exact():
+    """Rows of the FP8-exact workload have scale 1/8 and reconstruct exactly."""
+    base, q = datagen.gmm_fp8_exact_valued(99, 200, 10, 24, 4)
+    for a in (base, q):
+        for query in (False, True):
+            sc, xs = O.fp8_vectors(a, query=query)
+            assert np.all(sc == np.float32(0.125))
+            np.testing.assert_array_equal(xs, a.astype(np.float64))
+
+
+def test_fp8_search_equals_fp32_on_exact_levels():
+    """Where the FP8 form reconstructs every value exactly, the FP8 search
+    (without re-scoring) is the FP32 search."""
+    base, q = datagen.gmm_fp8_exact_valued(99, 400, 20, 16, 4)
+    ix = O.OracleIndex(16, 8, O.L2, seed=6)
+    ix.build(base, batch_max=64)
+    ref = ix.search(q, 10, 24)
+    ix.set("precision", O.P_FP8)
+    got = ix.search(q, 10, 24, rerank=False)
+    np.testing.assert_array_equal(got[0], ref[0])
+    np.testing.assert_array_equal(got[1], ref[1])
+    ix.set("precision", O.P_FP32)
+
+
+def test_fp8_search_recall_and_rescore():
+    """On float data the FP8 traversal with exact re-scoring keeps recall, and
+    the returned distances are the exact ones."""
+    base, q = datagen.gmm_float(93, 2000, 40, 32, 8)
+    ix = O.OracleIndex(32, 16, O.L2, seed=5)
+    ix.build(base, batch_max=256)
+    ix.set("precision", O.P_FP8)
+    ids, d, _ = ix.search(q, 10, 64)
+    gi, gd = O.bruteforce(base, q, 10)
+    assert np.mean([len(set(a) & set(b)) / 10 for a, b in zip(ids, gi)]) >= 0.95
+    ex = ((base[ids].astype(np.float64) - q[:, None, :].astype(np.float64)) ** 2).sum(-1)
+    np.testing.assert_allclose(d, ex, rtol=1e-12)
+    ix.set("precision", O.P_FP32)
