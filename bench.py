@@ -10,9 +10,13 @@ A step is one search of the whole 10k-query batch with the plain FP32 form
 at the smallest beam of the sweep that reaches recall@10 >= 0.95 (tie-aware,
 against exact ground truth).  Inputs are resident in HBM before timing; HIP
 events on the launch stream bracket the timed steps.  The same JSON line
-reports the reduced-precision form (BF16 traversal + exact FP32 re-scoring),
+reports the reduced-precision forms (BF16 or FP8-E4M3 traversal + exact FP32
+re-scoring, with their distance errors against FP64), the chosen form
+(reduced precision + the learned entry/stop predictor),
 the insertion (build) and deletion throughput of the update path, the
-roofline of the search kernel and the CPU oracle timed on a bounded sample.
+roofline of the search kernel, the same search on a 5M x 96 index whose
+vectors are far larger than the Infinity Cache, the serving mix and the CPU
+oracle timed on a bounded sample.
 
     python bench.py [--gpus 1] [--steps 20] [--warmup 3]
 """
@@ -79,6 +83,18 @@ def recall(torch, base_t, q_t, ids_t, kth):
     ex = ((base_t[safe].double() - q_t[:, None, :].double()) ** 2).sum(-1)
     hit = valid & (ex <= kth[:, None])
     return hit.double().mean().item()
+
+
+def dist_errors(torch, base_t, q_t, bufs):
+    """Largest absolute and relative error of the returned distances against
+    FP64 distances of the same ids."""
+    ids, d = bufs[0], bufs[1]
+    ok = ids >= 0
+    safe = torch.where(ok, ids, torch.zeros_like(ids)).long()
+    ex = ((base_t[safe].double() - q_t[:, None, :].double()) ** 2).sum(-1)
+    err = (d.double() - ex).abs()[ok]
+    rel = err / ex[ok].clamp_min(1e-30)
+    return {"max_abs": float(err.max()), "max_rel": float(rel.max())}
 
 
 def run_search(torch, ix, q_t, beam, bufs):
@@ -179,6 +195,80 @@ def serving_bench(svf, datagen, rounds=40, rate_hz=120.0):
     return out
 
 
+def exact_kth_ip(torch, base_t, q_t, k, extra=64, chunk=64):
+    """Exact k-th smallest -<q,x> per query: FP32 GEMM screening of all base
+    vectors, then FP64 re-evaluation of the best k+extra."""
+    out = torch.empty(q_t.shape[0], dtype=torch.float64, device=q_t.device)
+    for s in range(0, q_t.shape[0], chunk):
+        q = q_t[s:s + chunk]
+        cand = torch.topk(q @ base_t.T, k + extra, dim=1, largest=True).indices
+        ex = -(base_t[cand].double() * q[:, None, :].double()).sum(-1)
+        out[s:s + chunk] = torch.sort(ex, dim=1).values[:, k - 1]
+    return out
+
+
+def large_bench(torch, svf, datagen, n_base, steps, warmup):
+    """Plain FP32 search on an index whose vectors are far larger than the
+    256 MB Infinity Cache: n_base x 96 unit-norm mixture (1024 components,
+    Zipf(1.1)-skewed queries), inner product, degree 48, 10k-query batch,
+    k = 10, at the smallest beam reaching recall@10 >= 0.95."""
+    dim, R = 96, 48
+    base, queries = datagen.workload_stream_ip(n_base, 10_000)
+    ix = svf.Index(dim, R, svf.METRIC_IP, seed=0)
+    t0 = time.perf_counter()
+    ix.build(base)
+    build_s = time.perf_counter() - t0
+    base_t = torch.from_numpy(base).cuda()
+    q_t = torch.from_numpy(queries).cuda()
+    del base
+    nq = q_t.shape[0]
+    kth = exact_kth_ip(torch, base_t, q_t, K)
+    bufs = (torch.empty((nq, K), dtype=torch.int32, device="cuda"),
+            torch.empty((nq, K), dtype=torch.float32, device="cuda"),
+            torch.empty(nq, dtype=torch.int32, device="cuda"),
+            torch.empty(nq, dtype=torch.int32, device="cuda"))
+
+    def rec_ip():
+        ids = bufs[0]
+        ok = ids >= 0
+        safe = torch.where(ok, ids, torch.zeros_like(ids)).long()
+        ex = -(base_t[safe].double() * q_t[:, None, :].double()).sum(-1)
+        return (ok & (ex <= kth[:, None])).double().mean().item()
+
+    rows, beam = [], None
+    for b in BEAMS:
+        run_search(torch, ix, q_t, b, bufs)
+        torch.cuda.synchronize()
+        r = rec_ip()
+        rows.append({"beam": b, "recall@10": round(r, 5)})
+        if r >= 0.95:
+            beam = b
+            break
+    beam = beam or BEAMS[-1]
+    ms, _ = timed_steps(torch, ix, q_t, beam, bufs, steps, warmup)
+    n_exp = int(bufs[3].sum().item())
+    slots = ix.get_option("visited_slots")
+    ix.set_option("visited_slots", 8192)
+    run_search(torch, ix, q_t, beam, bufs)
+    torch.cuda.synchronize()
+    n_dist = int(bufs[2].sum().item())
+    ix.set_option("visited_slots", slots)
+    alg = n_dist * dim * 4 + n_exp * R * 4
+    ms_step = float(np.mean(ms))
+    achieved = alg / (ms_step / 1e3) / 1e9
+    del base_t
+    return {"workload": "%dM x 96 unit-norm GMM (1024 comps, Zipf(1.1) queries), IP, degree 48, "
+                        "10k-query batch, k=10, plain FP32" % (n_base // 1_000_000),
+            "vector_bytes": n_base * dim * 4, "build_s": round(build_s, 2),
+            "beam": beam, "recall@10": rows[-1]["recall@10"], "sweep": rows,
+            "ms_per_step": round(ms_step, 4), "qps": round(nq / (ms_step / 1e3), 1),
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "alg_bytes_per_launch": alg,
+                         "n_dist_per_query": round(n_dist / nq, 1),
+                         "n_exp_per_query": round(n_exp / nq, 1)}}
+
+
 def cpu_baseline(base, queries, beam):
     """The FP64 oracle, as it stands, on a bounded sample: it builds its own
     index over the first 20,000 base vectors (same generator) and searches
@@ -208,6 +298,9 @@ def main():
     ap.add_argument("--n-query", type=int, default=10_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the large-footprint (5M x 96) search leg")
+    ap.add_argument("--large-n", type=int, default=5_000_000)
     ap.add_argument("--search-only", type=int, default=0, metavar="BEAM",
                     help="build, then only time the plain FP32 search at this beam (for "
                          "hardware counter runs); prints a short JSON line")
@@ -283,47 +376,59 @@ def main():
     achieved = alg_bytes / (ms_step / 1e3) / 1e9
     qps = nq / (ms_step / 1e3)
 
-    # chosen form: BF16 traversal + exact FP32 re-score, with the learned
-    # entry/stop predictor trained on the GPU from traces of plain search
-    ix.set_option("precision", svf.PREC_BF16)
-    beam_bf, rows_bf = sweep(torch, ix, q_t, base_t, kth, bufs, BEAMS)
-    ms_bf, _ = timed_steps(torch, ix, q_t, beam_bf or BEAMS[-1], bufs, 5, 1)
-    bf_only = {"beam": beam_bf, "ms_per_step": round(float(np.mean(ms_bf)), 4),
-               "value": round(nq / (float(np.mean(ms_bf)) / 1e3), 1)}
+    # reduced-precision forms: BF16 or FP8 traversal + exact FP32 re-score
+    lowp = {}
+    for name, prec in (("bf16", svf.PREC_BF16), ("fp8", svf.PREC_FP8)):
+        ix.set_option("precision", prec)
+        b, rws = sweep(torch, ix, q_t, base_t, kth, bufs, BEAMS)
+        bb = b or BEAMS[-1]
+        ms_p, _ = timed_steps(torch, ix, q_t, bb, bufs, 5, 1)
+        err_post = dist_errors(torch, base_t, q_t, bufs)
+        ix.set_option("rerank", 0)
+        run_search(torch, ix, q_t, bb, bufs)
+        torch.cuda.synchronize()
+        err_pre = dist_errors(torch, base_t, q_t, bufs)
+        ix.set_option("rerank", 1)
+        lowp[name] = {"beam": b, "ms_per_step": round(float(np.mean(ms_p)), 4),
+                      "value": round(nq / (float(np.mean(ms_p)) / 1e3), 1),
+                      "dist_err_vs_fp64": {"pre_rerank": err_pre, "post_rerank": err_post},
+                      "sweep": rws}
     ix.set_option("precision", svf.PREC_FP32)
+
+    # chosen form: reduced precision + the learned entry/stop predictor,
+    # trained on the GPU from traces of plain search
     train = datagen.training_queries_uint8(2, 200_000, DIM, 256)
     t0 = time.perf_counter()
     fit_loss = ix.model_fit(train, K, 64, n_clusters=256, epochs=12)
     fit_s = time.perf_counter() - t0
-    ix.set_option("precision", svf.PREC_BF16)
     ix.set_option("use_model", 1)
     ix.set_option("model_conf", 0.0)
     best = None
     tried = []
-    for width, stop_scale in ((1, 2.0), (2, 1.0), (2, 1.5), (1, 1e6)):
-        ix.set_option("search_width", width)
-        ix.set_option("model_stop_scale", stop_scale)
-        b, rws = sweep(torch, ix, q_t, base_t, kth, bufs, [32, 48, 64, 96, 128])
-        tried.append({"search_width": width, "stop_scale": stop_scale, "beam": b, "sweep": rws})
-        if b is not None:
-            ms_c = [r["ms"] for r in rws if r["beam"] == b][0]
-            if best is None or ms_c < best[0]:
-                best = (ms_c, width, stop_scale, b)
+    for pname, prec in (("bf16", svf.PREC_BF16), ("fp8", svf.PREC_FP8)):
+        ix.set_option("precision", prec)
+        for width, stop_scale in ((1, 2.0), (2, 1.0), (2, 1.5), (1, 1e6)):
+            ix.set_option("search_width", width)
+            ix.set_option("model_stop_scale", stop_scale)
+            b, rws = sweep(torch, ix, q_t, base_t, kth, bufs, [32, 48, 64, 96, 128])
+            tried.append({"precision": pname, "search_width": width, "stop_scale": stop_scale,
+                          "beam": b, "sweep": rws})
+            if b is not None:
+                ms_c = [r["ms"] for r in rws if r["beam"] == b][0]
+                if best is None or ms_c < best[0]:
+                    best = (ms_c, pname, prec, width, stop_scale, b)
     if best is None:
-        best = (None, 1, 1e6, BEAMS[-1])
-    _, cw, css, beam_c = best
+        best = (None, "bf16", svf.PREC_BF16, 1, 1e6, BEAMS[-1])
+    _, cpname, cprec, cw, css, beam_c = best
+    ix.set_option("precision", cprec)
     ix.set_option("search_width", cw)
     ix.set_option("model_stop_scale", css)
     ms_c, _ = timed_steps(torch, ix, q_t, beam_c, bufs, args.steps, args.warmup)
     rec_c = recall(torch, base_t, q_t, bufs[0], kth)
-    maxerr = float((bufs[1].double() - ((base_t[bufs[0].long()].double()
-                                         - q_t[:, None, :].double()) ** 2).sum(-1)).abs().max())
+    maxerr = dist_errors(torch, base_t, q_t, bufs)["max_abs"]
     ix.set_option("use_model", 0)
     ix.set_option("search_width", 1)
     ix.set_option("precision", svf.PREC_FP32)
-    rec_bf = rec_c
-    ms_bf = ms_c
-    beam_bf = beam_c
 
     # update path: delete 1% then insert 10k fresh vectors (one batch each)
     g = np.random.Generator(np.random.Philox(77))
@@ -337,10 +442,17 @@ def main():
     ins_s = time.perf_counter() - t0
     st = ix.stats()
 
+    large = None
+    if not args.no_large:
+        log("large-footprint search leg")
+        del base_t
+        ix.close()
+        torch.cuda.empty_cache()
+        large = large_bench(torch, svf, datagen, args.large_n, args.steps, args.warmup)
+
     serving = None
     if not args.no_serving:
         log("serving mix")
-        del base_t
         serving = serving_bench(svf, datagen)
 
     cpu = None
@@ -374,25 +486,28 @@ def main():
                      "n_dist_per_query_timed": round(n_dist_run / nq, 1),
                      "n_exp_per_query": round(n_exp / nq, 1)},
         "cpu_baseline": cpu,
-        "chosen_form": {"form": "BF16 traversal + FP32 re-score + learned entry clusters "
-                                "and stop cap (MLP 128-256-256-257, BF16, trained on the GPU)",
-                        "beam": beam_bf, "search_width": cw, "model_stop_scale": css,
-                        "recall@10": round(rec_bf, 5),
-                        "value": round(nq / (float(np.mean(ms_bf)) / 1e3), 1),
-                        "ms_per_step": round(float(np.mean(ms_bf)), 4),
-                        "speedup_vs_plain": round(ms_step / float(np.mean(ms_bf)), 3),
+        "chosen_form": {"form": "%s traversal + FP32 re-score + learned entry clusters "
+                                "and stop cap (MLP 128-256-256-257, BF16, trained on the GPU)"
+                                % cpname.upper(),
+                        "precision": cpname,
+                        "beam": beam_c, "search_width": cw, "model_stop_scale": css,
+                        "recall@10": round(rec_c, 5),
+                        "value": round(nq / (float(np.mean(ms_c)) / 1e3), 1),
+                        "ms_per_step": round(float(np.mean(ms_c)), 4),
+                        "speedup_vs_plain": round(ms_step / float(np.mean(ms_c)), 3),
                         "max_abs_dist_err_vs_fp64": maxerr,
                         "model_fit_s": round(fit_s, 2), "model_fit_loss": round(fit_loss, 4),
                         "training_queries": 200_000, "n_clusters": 256,
-                        "bf16_only": bf_only, "configs_tried": tried},
+                        "configs_tried": tried},
+        "reduced_precision": lowp,
         "sweep_fp32": rows,
-        "sweep_bf16": rows_bf,
         "update": {"build_s": round(build_s, 3), "build_vectors_per_s": round(args.n_base / build_s, 1),
                    "delete_10k_ms": round(del_s * 1e3, 3), "insert_10k_ms": round(ins_s * 1e3, 3),
                    "phase_ms": {k: round(st[k], 3) for k in ("ins_search_ms", "ins_prune_ms",
                                                                "ins_reverse_ms", "ins_commit_ms",
                                                                "del_mark_ms", "del_repair_ms")},
                    "repaired_rows": st["last_repaired"]},
+        "large_footprint": large,
         "serving": serving,
         "wall_s_timed": round(wall, 4),
     }

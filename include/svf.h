@@ -51,7 +51,7 @@ enum {
 /* Precision of the distances evaluated during graph traversal.  Reduced
  * precision keeps an FP16 / BF16 copy of every vector, computes in FP32, and
  * re-scores the final candidate pool with exact FP32 distances. */
-enum { SVF_PREC_FP32 = 0, SVF_PREC_FP16 = 1, SVF_PREC_BF16 = 2 };
+enum { SVF_PREC_FP32 = 0, SVF_PREC_FP16 = 1, SVF_PREC_BF16 = 2, SVF_PREC_FP8 = 3 };
 
 typedef struct svf_stats {
     int64_t n_slots;          /* ids assigned so far                          */
@@ -97,11 +97,16 @@ int svf_destroy(svf_index *ix);
  *   prune_cap       longest candidate list given to the prune, 0 = max(4*degree, beam_insert)
  *   consolidate_frac deleted fraction that triggers consolidation ((0,1]; 0.2)
  *   insert_batch_max largest batch of one insertion pass (1..1<<20; 10000)
- *   precision       SVF_PREC_* of traversal distances (0..2; 0)
+ *   precision       SVF_PREC_* of traversal distances (0..3; 0).  FP16/BF16: each element
+ *                   rounded to nearest even.  FP8: OCP E4M3 codes of x / s with one FP32
+ *                   scale s = max|x| / 448 per vector (the query quantised the same way);
+ *                   distances accumulate in FP32
  *   rerank          exact FP32 re-scoring of the final pool under reduced precision (0/1; 1)
  *   cache_bytes     tiered store (Sec. 4.2-4.3): all vectors in pinned host memory, an HBM
- *                   cache of cache_bytes / (4 * round_up(dim, 8)) rows in front; set on an
- *                   empty index, FP32 traversal only.  Searches read cached rows from HBM
+ *                   cache of cache_bytes / (4 * round_up(dim, 8)) rows in front; FP32
+ *                   traversal only.  Set on an empty index, or on a filled one (its vectors
+ *                   then move to host memory and the cache is warmed by in-degree, as
+ *                   after svf_build).  Once set it stays.  Searches read cached rows from HBM
  *                   and the rest over the host link; after every direct search call the
  *                   batched workload-aware placement (Alg. 2) updates the cache, and
  *                   svf_build warms it with the highest in-degree vectors (Sec. 4.4)

@@ -71,7 +71,7 @@ def lib():
         L.orc_prune_explicit.argtypes = [i32, i32, vp, vp, vp, i64, vp, vp]
         L.orc_query_dists.argtypes = [vp, vp, i64, i32, vp, vp]
         L.orc_search_expansions.argtypes = [vp, vp, i64, i32, vp, i32, vp]
-        L.orc_wavp_replay.argtypes = [i64, i64, vp, vp, vp, vp, i32, f64, f64, f64, i32, vp, vp]
+        L.orc_wavp_replay.argtypes = [i64, i64, vp, vp, vp, vp, i32, f64, f64, f64, i32, i32, vp, vp]
         L.orc_search_listed.argtypes = [vp, vp, i64, i32, i32, vp, i32, vp, vp, vp, vp]
         L.orc_search_trace.argtypes = [vp, vp, i64, i32, i32, vp, vp]
         L.orc_mlp_forward.argtypes = [i32, i32, i32] + [vp] * 6 + [vp, i64, vp]
@@ -297,9 +297,11 @@ class MLP:
         return loss, g
 
 
-def wavp_replay(n, C, e_in, alive, batches, alpha=0.6, beta=0.4, theta=1.0, promote_max=2048):
+def wavp_replay(n, C, e_in, alive, batches, alpha=0.6, beta=0.4, theta=1.0, promote_max=2048,
+                warm=False):
     """Batched workload-aware placement over per-batch access traces; returns
-    (hits per batch, final slot table)."""
+    (hits per batch, final slot table).  warm=True starts from the cold-start
+    placement (highest in-degree alive vectors first)."""
     e = np.ascontiguousarray(e_in, dtype=np.int32)
     a = np.ascontiguousarray(alive, dtype=np.uint8)
     flat = np.ascontiguousarray(np.concatenate([np.asarray(b, np.int32) for b in batches])
@@ -309,5 +311,5 @@ def wavp_replay(n, C, e_in, alive, batches, alpha=0.6, beta=0.4, theta=1.0, prom
     hits = np.empty(len(batches), np.int64)
     slots = np.empty(max(C, 1), np.int32)
     lib().orc_wavp_replay(n, C, _p(e), _p(a), _p(flat), _p(off), len(batches), alpha, beta, theta,
-                          promote_max, _p(hits), _p(slots))
+                          promote_max, int(warm), _p(hits), _p(slots))
     return hits, slots[:C]

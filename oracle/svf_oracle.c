@@ -1325,11 +1325,13 @@ int orc_search_expansions(const orc_index *ix, const float *q, int64_t nq, int L
  *   the first slot with a clear bit whose vector has a lower F_lambda (a
  *   deleted vector counts as -1); a candidate that finds no victim ends the
  *   batch's placements.
+ * With warm != 0 the cache starts warm (cold-start placement, Sec. 4.4): the
+ * alive vectors of highest E_in, ties by id, fill slots 0, 1, ... in order.
  * trace: concatenated accesses, batch b spanning [off[b], off[b+1]).
  * Out: hits per batch, and the final slot -> id table (-1 empty). */
 void orc_wavp_replay(int64_t n, int64_t C, const int32_t *e_in, const uint8_t *alive,
                      const int32_t *trace, const int64_t *off, int nb, double alpha, double beta,
-                     double theta, int promote_max, int64_t *hits, int32_t *slot_id)
+                     double theta, int promote_max, int warm, int64_t *hits, int32_t *slot_id)
 {
     double *fr = calloc(n, sizeof(double));
     int32_t *where = malloc(sizeof(int32_t) * n);
@@ -1338,6 +1340,21 @@ void orc_wavp_replay(int64_t n, int64_t C, const int32_t *e_in, const uint8_t *a
     for (int64_t i = 0; i < n; ++i) where[i] = -1;
     for (int64_t s = 0; s < C; ++s) slot_id[s] = -1;
     int64_t used = 0, clock = 0;
+    if (warm) {
+        /* repeatedly take the best remaining alive vector by (E_in desc, id asc) */
+        uint8_t *taken = calloc(n > 0 ? n : 1, 1);
+        while (used < C) {
+            int64_t best = -1;
+            for (int64_t x = 0; x < n; ++x) {
+                if (!alive[x] || taken[x]) continue;
+                if (best < 0 || e_in[x] > e_in[best]) best = x;
+            }
+            if (best < 0) break;
+            taken[best] = 1;
+            slot_id[used] = (int32_t)best; where[best] = (int32_t)used; ++used;
+        }
+        free(taken);
+    }
     typedef struct { double f; int32_t id; } cand_t;
     int64_t maxlen = 0;
     for (int b = 0; b < nb; ++b) if (off[b + 1] - off[b] > maxlen) maxlen = off[b + 1] - off[b];

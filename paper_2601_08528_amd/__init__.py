@@ -17,7 +17,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libsvf.so")
 
 METRIC_L2, METRIC_IP = 0, 1
-PREC_FP32, PREC_FP16, PREC_BF16 = 0, 1, 2
+PREC_FP32, PREC_FP16, PREC_BF16, PREC_FP8 = 0, 1, 2, 3
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_NOTFOUND, E_BUSY, E_INTERNAL = 0, -1, -2, -3, -4, -5, -6
 
 EXPORTED = [

@@ -127,9 +127,11 @@ template <> struct Elem<float> {
     out[2] = __uint_as_float(w.z); out[3] = __uint_as_float(w.w);
   }
   __device__ static __forceinline__ float round(float x) { return x; }
+  static constexpr bool kScaled = false;
 };
 template <> struct Elem<__half> {
   static constexpr int kPer16B = 8;
+  static constexpr bool kScaled = false;
   __device__ static __forceinline__ void unpack(const uint4& w, float* out) {
     const uint32_t v[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
@@ -148,6 +150,7 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
 }
 template <> struct Elem<bf16_t> {
   static constexpr int kPer16B = 8;
+  static constexpr bool kScaled = false;
   __device__ static __forceinline__ void unpack(const uint4& w, float* out) {
     const uint32_t v[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
@@ -158,6 +161,56 @@ template <> struct Elem<bf16_t> {
   }
   __device__ static __forceinline__ float round(float x) {
     return __uint_as_float((uint32_t)f32_to_bf16_rne(x) << 16);
+  }
+};
+
+
+// ---------------------------------------------------------------------------
+// FP8 store: OCP E4M3 codes (4 exponent bits, bias 7, 3 fraction bits, no
+// infinities, largest finite 448) with one FP32 scale per vector,
+// s = max|x| / 448.  A stored vector stands for s * value(code).
+// ---------------------------------------------------------------------------
+struct fp8_t { uint8_t bits; };
+
+constexpr float kE4M3Max = 448.0f;
+
+// Code of the E4M3 value nearest to v (ties to even); magnitudes beyond 448
+// saturate to 448.  Built from the format's definition: below the smallest
+// normal 2^-6 the grid step is 2^-9; in binade [2^E, 2^(E+1)) it is 2^(E-3).
+__device__ __forceinline__ uint32_t f32_to_e4m3_sat(float v) {
+  const uint32_t sign = (__float_as_uint(v) >> 24) & 0x80u;
+  const float a = __builtin_fabsf(v);
+  if (!(a < kE4M3Max)) return sign | 0x7Eu;
+  if (a < 0.015625f) return sign | (uint32_t)__builtin_rintf(a * 512.0f);   // 0..8
+  int e = __builtin_amdgcn_frexp_expf(a) - 1;                               // a in [2^e, 2^(e+1))
+  uint32_t q = (uint32_t)__builtin_rintf(__builtin_ldexpf(a, 3 - e));       // 8..16
+  if (q == 16u) { q = 8u; ++e; }
+  uint32_t code = ((uint32_t)(e + 7) << 3) | (q - 8u);
+  if (code > 0x7Eu) code = 0x7Eu;
+  return sign | code;
+}
+
+// Per-vector scale from the largest magnitude (1 for an all-zero vector).
+__device__ __forceinline__ float fp8_scale_of(float maxabs) {
+  return maxabs > 0.0f ? __fdiv_rn(maxabs, kE4M3Max) : 1.0f;
+}
+
+template <> struct Elem<fp8_t> {
+  static constexpr int kPer16B = 16;
+  static constexpr bool kScaled = true;
+  // gfx950 converts OCP E4M3 pairs to FP32 exactly in hardware
+  __device__ static __forceinline__ void unpack(const uint4& w, float* out) {
+    const uint32_t v[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)v[i], false);
+      const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)v[i], true);
+      out[4 * i] = lo[0]; out[4 * i + 1] = lo[1];
+      out[4 * i + 2] = hi[0]; out[4 * i + 3] = hi[1];
+    }
+  }
+  __device__ static __forceinline__ float value(uint32_t code) {
+    return __builtin_amdgcn_cvt_f32_fp8((int)code, 0);
   }
 };
 

@@ -41,6 +41,23 @@ int prune_cap(const svf_index* ix) {
   if (ix->opt.prune_cap > 0) return ix->opt.prune_cap;
   return std::max(4 * ix->R, beam_insert(ix));
 }
+// Reduced-precision traversal store: FP16/BF16 rows of `stride` 2-byte
+// elements; FP8 rows of round_up(dim, 16) codes followed, after all cap rows,
+// by cap FP32 scales.
+int64_t lp_stride(const svf_index* ix, int prec) {
+  return prec == 3 ? round_up(ix->dim, 16) : ix->stride;
+}
+size_t lp_row_bytes(const svf_index* ix, int prec) {
+  return prec == 3 ? (size_t)lp_stride(ix, 3) : (size_t)ix->stride * 2;
+}
+size_t lp_bytes(const svf_index* ix, int prec, int64_t cap) {
+  return (size_t)cap * lp_row_bytes(ix, prec) + (prec == 3 ? (size_t)cap * 4 : 0);
+}
+float* lp_scale(void* veclp, const svf_index* ix, int prec, int64_t cap) {
+  if (prec != 3 || !veclp) return nullptr;
+  return reinterpret_cast<float*>(static_cast<char*>(veclp) + (size_t)cap * lp_row_bytes(ix, prec));
+}
+
 int visited_slots(const svf_index* ix, int E) {
   int T = ix->opt.visited_slots;
   while (T < 2 * E) T <<= 1;   // entry phase needs an exact table
@@ -74,7 +91,7 @@ int reserve(svf_index* ix, int64_t need) {
   if (tier && (e = hipMalloc(&tmap, cap * 4)) != hipSuccess) return hip_fail(e, "index allocation");
   if ((e = tier ? hipHostMalloc((void**)&v32, cap * ix->stride * 4, 0)
                 : hipMalloc(&v32, cap * ix->stride * 4)) != hipSuccess ||
-      (ix->veclp_prec && (e = hipMalloc(&vlp, cap * ix->stride * 2)) != hipSuccess) ||
+      (ix->veclp_prec && (e = hipMalloc(&vlp, lp_bytes(ix, ix->veclp_prec, cap))) != hipSuccess) ||
       (e = hipMalloc(&g, cap * ix->R * 4)) != hipSuccess ||
       (e = hipMalloc(&ed, cap * ix->R * 4)) != hipSuccess ||
       (e = hipMalloc(&al, words * 4)) != hipSuccess ||
@@ -95,14 +112,20 @@ int reserve(svf_index* ix, int64_t need) {
   } else {
     CK(svf::launch_fill_u32(v32, cap * ix->stride, 0u, st));
   }
-  if (vlp) CK(svf::launch_fill_u32(vlp, cap * ix->stride / 2, 0u, st));
+  if (vlp) CK(svf::launch_fill_u32(vlp, lp_bytes(ix, ix->veclp_prec, cap) / 4, 0u, st));
   CK(svf::launch_fill_u32(g, cap * ix->R, 0xffffffffu, st));
   CK(svf::launch_fill_u32(ed, cap * ix->R, 0x7f800000u, st));
   CK(svf::launch_fill_u32(al, words, 0u, st));
   CK(svf::launch_fill_u32(tc, cap, 0u, st));
   if (n > 0) {
     if (!tier) CK(hipMemcpyAsync(v32, ix->vec32, n * ix->stride * 4, hipMemcpyDeviceToDevice, st));
-    if (vlp) CK(hipMemcpyAsync(vlp, ix->veclp, n * ix->stride * 2, hipMemcpyDeviceToDevice, st));
+    if (vlp) {
+      const int p = ix->veclp_prec;
+      CK(hipMemcpyAsync(vlp, ix->veclp, n * lp_row_bytes(ix, p), hipMemcpyDeviceToDevice, st));
+      if (p == 3)
+        CK(hipMemcpyAsync(lp_scale(vlp, ix, p, cap), lp_scale(ix->veclp, ix, p, ix->cap), n * 4,
+                          hipMemcpyDeviceToDevice, st));
+    }
     CK(hipMemcpyAsync(g, ix->graph, n * ix->R * 4, hipMemcpyDeviceToDevice, st));
     CK(hipMemcpyAsync(ed, ix->edge_d, n * ix->R * 4, hipMemcpyDeviceToDevice, st));
     CK(hipMemcpyAsync(al, ix->alive, ((n + 31) / 32) * 4, hipMemcpyDeviceToDevice, st));
@@ -143,9 +166,11 @@ int sync_lowp(svf_index* ix) {
   ix->veclp = nullptr;
   ix->veclp_prec = prec;
   if (prec == 0 || ix->cap == 0) return SVF_OK;
-  CK(hipMalloc(&ix->veclp, ix->cap * ix->stride * 2));
-  CK(svf::launch_fill_u32(ix->veclp, ix->cap * ix->stride / 2, 0u, ix->stream));
-  CK(svf::launch_store_lowp(ix->vec32, ix->veclp, 0, ix->n_slots, ix->stride, prec, ix->stream));
+  CK(hipMalloc(&ix->veclp, lp_bytes(ix, prec, ix->cap)));
+  CK(svf::launch_fill_u32(ix->veclp, lp_bytes(ix, prec, ix->cap) / 4, 0u, ix->stream));
+  CK(svf::launch_store_lowp(ix->vec32, ix->stride, ix->dim, ix->veclp, lp_stride(ix, prec),
+                            lp_scale(ix->veclp, ix, prec, ix->cap), 0, ix->n_slots, prec,
+                            ix->stream));
   CK(hipStreamSynchronize(ix->stream));
   return SVF_OK;
 }
@@ -155,8 +180,10 @@ int store_rows(svf_index* ix, const float* d_src, int64_t n, int64_t at, hipStre
   if (n <= 0) return SVF_OK;
   CK(hipMemcpy2DAsync(ix->vec32 + at * ix->stride, ix->stride * 4, d_src, ix->dim * 4,
                       ix->dim * 4, n, hipMemcpyDefault, st));
-  if (ix->veclp_prec)
-    CK(svf::launch_store_lowp(ix->vec32, ix->veclp, at, n, ix->stride, ix->veclp_prec, st));
+  const int p = ix->veclp_prec;
+  if (p)
+    CK(svf::launch_store_lowp(ix->vec32, ix->stride, ix->dim, ix->veclp, lp_stride(ix, p),
+                              lp_scale(ix->veclp, ix, p, ix->cap), at, n, p, st));
   return SVF_OK;
 }
 
@@ -169,6 +196,8 @@ svf::SearchArgs base_args(const svf_index* ix) {
   a.vec = traversal_store(ix);
   a.vec32 = ix->vec32;
   a.stride = ix->stride;
+  a.vstride = ix->veclp_prec ? lp_stride(ix, ix->veclp_prec) : ix->stride;
+  a.vscale = lp_scale(ix->veclp, ix, ix->veclp_prec, ix->cap);
   a.dim = ix->dim;
   a.graph = ix->graph;
   a.R = ix->R;
@@ -718,15 +747,21 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
   return tier_apply(ix, place, st);
 }
 
-// Cold start (Sec. 4.4): fill the cache with the highest in-degree vectors.
+// Cold start (Sec. 4.4): fill the cache with the highest in-degree alive
+// vectors (ties by id), in that order.
 int tier_warmup(svf_index* ix, hipStream_t st) {
   svf::TierState& T = ix->tier;
   int rc = tier_refresh_indegree(ix, st);
   if (rc) return rc;
   const int64_t n = ix->n_slots;
-  std::vector<int32_t> order(n);
-  for (int64_t i = 0; i < n; ++i) order[i] = (int32_t)i;
-  const int64_t take = std::min<int64_t>(T.C - T.used, n);
+  std::vector<uint32_t> bits((n + 31) / 32 + 1, 0u);
+  CK(hipMemcpyAsync(bits.data(), ix->alive, ((n + 31) / 32) * 4, hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  std::vector<int32_t> order;
+  order.reserve(n);
+  for (int64_t i = 0; i < n; ++i)
+    if ((bits[i >> 5] >> (i & 31)) & 1u) order.push_back((int32_t)i);
+  const int64_t take = std::min<int64_t>(T.C - T.used, (int64_t)order.size());
   std::partial_sort(order.begin(), order.begin() + take, order.end(), [&](int32_t a, int32_t b) {
     return T.e_in[a] > T.e_in[b] || (T.e_in[a] == T.e_in[b] && a < b);
   });
@@ -746,23 +781,49 @@ int tier_warmup(svf_index* ix, hipStream_t st) {
 
 int tier_enable(svf_index* ix, double bytes) {
   svf::TierState& T = ix->tier;
-  if (ix->n_slots != 0) return fail(SVF_E_INVAL, "cache_bytes must be set on an empty index");
   if (ix->veclp_prec != 0) return fail(SVF_E_INVAL, "the tiered store runs FP32 traversal");
   const int64_t C = (int64_t)(bytes / (double)(ix->stride * 4));
   if (C < 1) return fail(SVF_E_INVAL, "cache_bytes below one vector");
   if (T.on) return fail(SVF_E_INVAL, "cache already configured");
   CK(hipMalloc(&T.cache, C * ix->stride * 4));
-  if (ix->vec32) (void)hipFree(ix->vec32);
-  ix->vec32 = nullptr;
-  T.on = true;
   T.C = C;
   T.slot_id.assign(C, -1);
   T.ref.assign(C, 0);
   T.used = 0;
   T.clock = 0;
-  const int64_t cap = ix->cap;
-  ix->cap = 0;                      // re-create the stores in their tiered form
-  return reserve(ix, std::max<int64_t>(cap, 1024));
+  if (ix->n_slots == 0) {
+    if (ix->vec32) (void)hipFree(ix->vec32);
+    ix->vec32 = nullptr;
+    T.on = true;
+    const int64_t cap = ix->cap;
+    ix->cap = 0;                      // re-create the stores in their tiered form
+    return reserve(ix, std::max<int64_t>(cap, 1024));
+  }
+  // a filled index: its FP32 store moves to pinned host memory, then the
+  // cache is warmed with the highest in-degree vectors
+  const size_t vbytes = (size_t)ix->cap * ix->stride * 4;
+  float* host = nullptr;
+  int32_t* map = nullptr;
+  hipError_t e;
+  if ((e = hipHostMalloc((void**)&host, vbytes, 0)) != hipSuccess ||
+      (e = hipMalloc(&map, ix->cap * 4)) != hipSuccess ||
+      (e = hipMemcpyAsync(host, ix->vec32, vbytes, hipMemcpyDeviceToHost, ix->stream)) != hipSuccess ||
+      (e = svf::launch_fill_u32(map, ix->cap, 0xffffffffu, ix->stream)) != hipSuccess ||
+      (e = hipStreamSynchronize(ix->stream)) != hipSuccess) {
+    if (host) (void)hipHostFree(host);
+    if (map) (void)hipFree(map);
+    (void)hipFree(T.cache);
+    T.cache = nullptr;
+    T.C = 0;
+    return hip_fail(e, "tiered store setup");
+  }
+  (void)hipFree(ix->vec32);
+  ix->vec32 = host;
+  T.map = map;
+  T.where.assign(ix->cap, -1);
+  T.fr.assign(ix->cap, 0.0);
+  T.on = true;
+  return tier_warmup(ix, ix->stream);
 }
 
 }  // namespace svf_detail
@@ -886,7 +947,8 @@ int svf_set_option(svf_index* ix, const char* key, double v) {
     ix->tier.trace_cap = (int)v;
   } else if (k == "precision") {
     if (v != 0 && ix->tier.on) return fail(SVF_E_INVAL, "the tiered store runs FP32 traversal");
-    if (v != 0 && v != 1 && v != 2) return fail(SVF_E_INVAL, "precision 0 (FP32), 1 (FP16) or 2 (BF16)");
+    if (v != 0 && v != 1 && v != 2 && v != 3)
+      return fail(SVF_E_INVAL, "precision 0 (FP32), 1 (FP16), 2 (BF16) or 3 (FP8)");
     o.precision = (int)v;
     return sync_lowp(ix);
   } else if (k == "rerank") {
@@ -1216,8 +1278,9 @@ int svf_stats_get(const svf_index* cix, svf_stats* out) {
   ix->st.n_slots = ix->n_slots;
   ix->st.n_alive = ix->n_alive;
   ix->st.capacity = ix->cap;
-  ix->st.device_bytes = ix->cap * ((ix->tier.on ? 0 : ix->stride * 4) + ix->stride * (ix->veclp_prec ? 2 : 0) +
-                                    ix->R * 8 + 8) + ix->cap / 8 + ix->tier.C * ix->stride * 4;
+  ix->st.device_bytes = ix->cap * ((ix->tier.on ? 0 : ix->stride * 4) + ix->R * 8 + 8) + ix->cap / 8 +
+                        (ix->veclp_prec ? (int64_t)lp_bytes(ix, ix->veclp_prec, ix->cap) : 0) +
+                        ix->tier.C * ix->stride * 4;
   ix->st.cache_slots = ix->tier.C;
   ix->st.cache_gather_hits = (int64_t)ix->tier.gather_hits;
   ix->st.cache_gather_misses = (int64_t)ix->tier.gather_misses;

@@ -89,7 +89,8 @@ struct svf_index {
   int device = 0;
   // device-resident state
   float* vec32 = nullptr;            // cap x stride FP32
-  void* veclp = nullptr;             // cap x stride FP16/BF16 (reduced-precision traversal)
+  void* veclp = nullptr;             // reduced-precision traversal store (FP16/BF16 rows, or FP8
+                                     // rows then per-vector scales)
   int veclp_prec = 0;
   int32_t* graph = nullptr;          // cap x R
   float* edge_d = nullptr;           // cap x R

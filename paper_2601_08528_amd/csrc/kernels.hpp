@@ -7,9 +7,11 @@ namespace svf {
 
 struct SearchArgs {
   // index snapshot
-  const void* vec;          // traversal store: FP32 / FP16 / BF16, n x stride
+  const void* vec;          // traversal store: FP32 / FP16 / BF16 / FP8, n x vstride
   const float* vec32;       // exact FP32 store (re-scoring), n x stride
-  int64_t stride;           // elements per stored row (multiple of 8)
+  int64_t stride;           // elements per FP32 row (multiple of 8)
+  int64_t vstride;          // elements per traversal row (0: stride; FP8: multiple of 16)
+  const float* vscale;      // FP8: per-vector scales
   int dim;
   const int32_t* graph;     // n x R ids
   int R;
@@ -62,8 +64,9 @@ hipError_t launch_place(const int32_t* place, int np, const float* store, float*
 
 // ---- index maintenance (update.hip) ----
 hipError_t launch_fill_u32(void* p, int64_t n, uint32_t v, hipStream_t st);
-hipError_t launch_store_lowp(const float* vec32, void* veclp, int64_t row0, int64_t nrows,
-                             int64_t stride, int precision, hipStream_t st);
+hipError_t launch_store_lowp(const float* vec32, int64_t stride, int dim, void* veclp,
+                             int64_t lp_stride, float* vscale, int64_t row0, int64_t nrows,
+                             int precision, hipStream_t st);
 hipError_t launch_seed(const float* vec32, int64_t stride, int dim, int metric, int s0, int R,
                        int32_t* graph, float* edge_d, hipStream_t st);
 hipError_t launch_set_alive(uint32_t* alive, int64_t lo, int64_t hi, hipStream_t st);

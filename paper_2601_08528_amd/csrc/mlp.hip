@@ -78,42 +78,69 @@ __global__ void to_bf16_kernel(const float* x, int64_t rows, int cols, int64_t l
   y[i] = f32_to_bf16_rne(x[r * ldx + c]);
 }
 
-__global__ void colsum_kernel(const float* x, int64_t rows, int cols, float* out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cols) return;
+// Column sums of an n x cols FP32 matrix: a block of 1024 threads covers 64
+// columns, its 16 waves take every 16th row, and the 16 partial sums are
+// added in wave order (the same order on every run).
+__global__ __launch_bounds__(1024) void colsum_kernel(const float* x, int64_t rows, int cols,
+                                                      float* out) {
+  __shared__ float part[16][64];
+  const int cl = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + cl;
   float s = 0.f;
-  for (int64_t r = 0; r < rows; ++r) s += x[r * cols + c];
-  out[c] = s;
+  if (c < cols)
+    for (int64_t r = wv; r < rows; r += 16) s += x[r * cols + c];
+  part[wv][cl] = s;
+  __syncthreads();
+  if (wv == 0 && c < cols) {
+    float t = 0.f;
+    for (int k = 0; k < 16; ++k) t += part[k][cl];
+    out[c] = t;
+  }
 }
 
-// Per sample: softmax cross-entropy on the nc logits and lambda * Huber on the
-// stop output; gradients scaled by 1/n (the batch mean).
-__global__ void loss_grad_kernel(const float* z, const int32_t* label, const float* log_stop,
-                                 int64_t n, int nc, float lambda, float delta, float* dzf,
-                                 uint16_t* dzb, float* loss) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__device__ __forceinline__ float wave_max(float v) {
+  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// One wave per sample: softmax cross-entropy on the nc logits and lambda *
+// Huber on the stop output; gradients scaled by 1/n (the batch mean).
+__global__ __launch_bounds__(256) void loss_grad_kernel(const float* z, const int32_t* label,
+                                                        const float* log_stop, int64_t n, int nc,
+                                                        float lambda, float delta, float* dzf,
+                                                        uint16_t* dzb, float* loss) {
+  const int64_t i = blockIdx.x * (int64_t)(blockDim.x / 64) + threadIdx.x / 64;
   if (i >= n) return;
+  const int lane = threadIdx.x & 63;
   const int no = nc + 1;
   const float* zi = z + i * no;
-  float mx = zi[0];
-  for (int j = 1; j < nc; ++j) mx = fmaxf(mx, zi[j]);
+  float mx = -__builtin_inff();
+  for (int j = lane; j < nc; j += 64) mx = fmaxf(mx, zi[j]);
+  mx = wave_max(mx);
   float se = 0.f;
-  for (int j = 0; j < nc; ++j) se += __expf(zi[j] - mx);
+  for (int j = lane; j < nc; j += 64) se += __expf(zi[j] - mx);
+  se = wave_sum(se);
   const int lab = label[i];
-  float l = logf(se) + mx - zi[lab];
   const float inv = 1.0f / (float)n;
-  for (int j = 0; j < nc; ++j) {
+  for (int j = lane; j < nc; j += 64) {
     const float gj = (__expf(zi[j] - mx) / se - (j == lab ? 1.f : 0.f)) * inv;
     dzf[i * no + j] = gj;
     dzb[i * no + j] = f32_to_bf16_rne(gj);
   }
-  const float r = zi[nc] - log_stop[i];
-  const float ar = fabsf(r);
-  l += lambda * (ar <= delta ? 0.5f * r * r : delta * (ar - 0.5f * delta));
-  const float gs = lambda * (ar <= delta ? r : (r > 0.f ? delta : -delta)) * inv;
-  dzf[i * no + nc] = gs;
-  dzb[i * no + nc] = f32_to_bf16_rne(gs);
-  atomicAdd(loss, l * inv);
+  if (lane == 0) {
+    float l = logf(se) + mx - zi[lab];
+    const float r = zi[nc] - log_stop[i];
+    const float ar = fabsf(r);
+    l += lambda * (ar <= delta ? 0.5f * r * r : delta * (ar - 0.5f * delta));
+    const float gs = lambda * (ar <= delta ? r : (r > 0.f ? delta : -delta)) * inv;
+    dzf[i * no + nc] = gs;
+    dzb[i * no + nc] = f32_to_bf16_rne(gs);
+    atomicAdd(loss, l * inv);
+  }
 }
 
 __global__ void adam_kernel(float* p, const float* g, float* m, float* v, int64_t n, float lr,
@@ -392,7 +419,7 @@ hipError_t Mlp::run_forward(const float* d_x, int64_t n, hipStream_t st) {
 hipError_t Mlp::run_backward(const int32_t* d_label, const float* d_log_stop, int64_t n,
                              float lambda, float delta, float* d_grad, hipStream_t st) {
   const int din = d_.din, h = d_.h, no = d_.no();
-  hipLaunchKernelGGL(loss_grad_kernel, dim3(blocks(n)), dim3(256), 0, st, zf_, d_label, d_log_stop,
+  hipLaunchKernelGGL(loss_grad_kernel, dim3(blocks(n, 4)), dim3(256), 0, st, zf_, d_label, d_log_stop,
                      n, d_.nc, lambda, delta, dzf_, dzb_, loss_);
   GemmArgs g{};
   // dW3 = H2^T dZ  (h x no), db3 = colsum dZ
@@ -401,7 +428,7 @@ hipError_t Mlp::run_backward(const int32_t* d_label, const float* d_log_stop, in
   g.M = h; g.N = no; g.K = (int)n;
   g.C32 = d_grad + d_.o_w3(); g.ldc = no;
   MCK(gemm(g, st));
-  hipLaunchKernelGGL(colsum_kernel, dim3(blocks(no)), dim3(256), 0, st, dzf_, n, no,
+  hipLaunchKernelGGL(colsum_kernel, dim3(blocks(no, 64)), dim3(1024), 0, st, dzf_, n, no,
                      d_grad + d_.o_b3());
   // dH2 = (dZ W3^T) masked by H2 > 0
   g = GemmArgs{};
@@ -418,7 +445,7 @@ hipError_t Mlp::run_backward(const int32_t* d_label, const float* d_log_stop, in
   g.M = h; g.N = h; g.K = (int)n;
   g.C32 = d_grad + d_.o_w2(); g.ldc = h;
   MCK(gemm(g, st));
-  hipLaunchKernelGGL(colsum_kernel, dim3(blocks(h)), dim3(256), 0, st, dh2f_, n, h,
+  hipLaunchKernelGGL(colsum_kernel, dim3(blocks(h, 64)), dim3(1024), 0, st, dh2f_, n, h,
                      d_grad + d_.o_b2());
   // dH1 = (dH2 W2^T) masked by H1 > 0
   g = GemmArgs{};
@@ -435,7 +462,7 @@ hipError_t Mlp::run_backward(const int32_t* d_label, const float* d_log_stop, in
   g.M = din; g.N = h; g.K = (int)n;
   g.C32 = d_grad + d_.o_w1(); g.ldc = h;
   MCK(gemm(g, st));
-  hipLaunchKernelGGL(colsum_kernel, dim3(blocks(h)), dim3(256), 0, st, dh1f_, n, h,
+  hipLaunchKernelGGL(colsum_kernel, dim3(blocks(h, 64)), dim3(1024), 0, st, dh1f_, n, h,
                      d_grad + d_.o_b1());
   return hipGetLastError();
 }

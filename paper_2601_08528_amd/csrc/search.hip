@@ -15,8 +15,8 @@
 // One iteration: the smallest unexpanded key is the parent (Algorithm 1,
 // GetNearest); its row of R ids is read with one coalesced load; ids that are
 // INVALID, deleted (bitset) or visited are dropped; the survivors are compacted
-// and their vectors gathered so that each 16-lane (16-bit store) or 32-lane
-// (FP32 store) group reads one 256/512-byte vector with 16-byte loads; the
+// and their vectors gathered so that each 8-lane (FP8), 16-lane (16-bit) or
+// 32-lane (FP32) group reads one 128/256/512-byte vector with 16-byte loads; the
 // group reduces its partial sums by lane shuffles; the new keys are sorted
 // across the wave (bitonic) and merged into the pool by rank (merge path),
 // which also drops re-evaluated ids.  The loop ends when every pool entry is
@@ -25,8 +25,11 @@
 #include "kernels.hpp"
 #include "wave_ops.hpp"
 
-namespace svf {
+#ifndef SVF_ROW_PREFETCH
+#define SVF_ROW_PREFETCH 1
+#endif
 
+namespace svf {
 
 // ---------------------------------------------------------------------------
 template <typename VT, int NC, typename VIS, bool TIER>
@@ -96,8 +99,8 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
         t_hit += popc64(ballot(h));
         t_miss += nt - popc64(ballot(h));
       }
-      uint64_t k = gather_keys<VT, NC, TIER>(qs, base, a.stride, w.cid, nt, a.metric, slot,
-                                             reinterpret_cast<const VT*>(a.tcache));
+      uint64_t k = gather_keys<VT, NC, TIER>(qs, base, a.vstride, w.cid, nt, a.metric, slot,
+                                             reinterpret_cast<const VT*>(a.tcache), a.vscale);
       n_dist += nt;
       sort_merge(w, k);
     };
@@ -142,24 +145,44 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
   // Each iteration expands the `width` smallest unexpanded entries (one by
   // default); their rows are filtered, gathered and merged chunk by chunk,
   // which equals one merge of all new keys (the top-L of a union).
+  //
+  // With one parent per iteration, the row of the next unexpanded entry after
+  // the parent is loaded while this iteration gathers; when that entry is the
+  // next parent (no closer key arrived), its row is already in registers.
+  // Rows do not change during a search, so this only moves a load earlier.
   const int cap_iters = (a.q_max_iters && a.q_max_iters[qi] > 0) ? a.q_max_iters[qi] : a.max_iters;
+  const bool pf_on = SVF_ROW_PREFETCH && a.width == 1 && a.R <= kWave;
+  int32_t pf_id = -1, pf_nb = -1;
   int last_change = 0, n_iter = 0;
   for (;;) {
     if (cap_iters > 0 && n_iter >= cap_iters) break;
     int ppos[4];
-    int np = 0;
-    for (int b0 = 0; b0 < a.L && np < a.width; b0 += kWave) {
+    int pnext = -1;
+    const int want = a.width + (pf_on ? 1 : 0);
+    int found = 0;
+    for (int b0 = 0; b0 < a.L && found < want; b0 += kWave) {
       const int i = b0 + lane;
       const bool un = i < a.L && (w.pool[i] & 1ull) == 0;
       uint64_t bm = ballot(un);
-      while (bm && np < a.width) {
-        ppos[np++] = b0 + __ffsll((unsigned long long)bm) - 1;
+      while (bm && found < want) {
+        const int pos = b0 + __ffsll((unsigned long long)bm) - 1;
+        if (found < a.width) ppos[found] = pos;
+        else pnext = pos;
+        ++found;
         bm &= bm - 1;
       }
     }
+    const int np = found < a.width ? found : a.width;
     if (np == 0) break;
     int32_t parents[4];
     for (int t = 0; t < np; ++t) parents[t] = key_id(w.pool[ppos[t]]);
+    int32_t row_nb = -1;
+    if (pf_on) {
+      row_nb = parents[0] == pf_id ? pf_nb
+                                   : (lane < a.R ? a.graph[(int64_t)parents[0] * a.R + lane] : -1);
+      pf_id = pnext >= 0 ? key_id(w.pool[pnext]) : -1;
+      pf_nb = (pf_id >= 0 && lane < a.R) ? a.graph[(int64_t)pf_id * a.R + lane] : -1;
+    }
     __syncthreads();
     if (lane == 0) {
       for (int t = 0; t < np; ++t) {
@@ -174,7 +197,7 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
       const int32_t* row = a.graph + (int64_t)parents[t] * a.R;
       for (int r0 = 0; r0 < a.R; r0 += kWave) {
         const int rr = r0 + lane;
-        const int32_t nb = rr < a.R ? row[rr] : -1;
+        const int32_t nb = pf_on ? row_nb : (rr < a.R ? row[rr] : -1);
         bool ok = nb >= 0 && nb < a.n_slots;
         __syncthreads();
         if (ok) ok = !vis.test_and_set(nb);
@@ -194,8 +217,8 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
         // the deletion bits load while the vectors are gathered
         const int32_t mine = lane < m ? w.cid[lane] : 0;
         const uint32_t aword = a.alive[(uint32_t)mine >> 5];
-        uint64_t k = gather_keys<VT, NC, TIER>(qs, base, a.stride, w.cid, m, a.metric, slot,
-                                               reinterpret_cast<const VT*>(a.tcache));
+        uint64_t k = gather_keys<VT, NC, TIER>(qs, base, a.vstride, w.cid, m, a.metric, slot,
+                                               reinterpret_cast<const VT*>(a.tcache), a.vscale);
         if (lane < m && !((aword >> (mine & 31)) & 1u)) k = kKeyInf;
         n_dist += m;
         if (sort_merge(w, k)) last_change = n_iter;
@@ -313,6 +336,9 @@ static hipError_t launch_vis(const SearchArgs& a, int precision, int nc, size_t 
                     : launch_vt<float, VIS, false>(a, nc, lds, st);
     case 1: return a.tmap ? hipErrorInvalidValue : launch_vt<__half, VIS, false>(a, nc, lds, st);
     case 2: return a.tmap ? hipErrorInvalidValue : launch_vt<bf16_t, VIS, false>(a, nc, lds, st);
+    case 3:
+      return (a.tmap || !a.vscale || a.vstride % 16) ? hipErrorInvalidValue
+                                                     : launch_vt<fp8_t, VIS, false>(a, nc, lds, st);
   }
   return hipErrorInvalidValue;
 }
@@ -320,6 +346,7 @@ static hipError_t launch_vis(const SearchArgs& a, int precision, int nc, size_t 
 hipError_t launch_search(const SearchArgs& in, int precision, hipStream_t st) {
   if (in.nq <= 0) return hipSuccess;
   SearchArgs a = in;
+  if (a.vstride == 0) a.vstride = a.stride;
   const int chunks = (int)((a.stride + 127) / 128);
   const int nc = chunks <= 1 ? 1 : chunks <= 2 ? 2 : chunks <= 4 ? 4 : 8;
   if (chunks > 8) return hipErrorInvalidValue;

@@ -194,10 +194,43 @@ __global__ void store_lowp_kernel(const float* __restrict__ src, uint16_t* __res
     dst[i] = precision == 1 ? __half_as_ushort(__float2half_rn(x)) : f32_to_bf16_rne(x);
   }
 }
-hipError_t launch_store_lowp(const float* vec32, void* veclp, int64_t row0, int64_t nrows,
-                             int64_t stride, int precision, hipStream_t st) {
+// FP32 rows -> FP8 rows, one wave per row: the scale from the row's largest
+// magnitude, then the E4M3 code of each x / s; the row's tail up to lp_stride
+// is zero.
+__global__ __launch_bounds__(256) void store_fp8_kernel(const float* __restrict__ src,
+                                                        int64_t stride, int dim,
+                                                        uint8_t* __restrict__ dst,
+                                                        int64_t lp_stride, float* __restrict__ scale,
+                                                        int64_t nrows) {
+  const int64_t r = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave;
+  if (r >= nrows) return;
+  const int lane = lane_id();
+  const float* x = src + r * stride;
+  float m = 0.0f;
+  for (int i = lane; i < dim; i += kWave) m = __builtin_fmaxf(m, __builtin_fabsf(x[i]));
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) m = __builtin_fmaxf(m, __shfl_xor(m, o));
+  const float s = fp8_scale_of(m);
+  uint8_t* y = dst + r * lp_stride;
+  for (int i = lane; i < lp_stride; i += kWave)
+    y[i] = i < dim ? (uint8_t)f32_to_e4m3_sat(__fdiv_rn(x[i], s)) : (uint8_t)0;
+  if (lane == 0) scale[r] = s;
+}
+
+hipError_t launch_store_lowp(const float* vec32, int64_t stride, int dim, void* veclp,
+                             int64_t lp_stride, float* vscale, int64_t row0, int64_t nrows,
+                             int precision, hipStream_t st) {
+  if (nrows <= 0 || precision == 0) return hipSuccess;
+  if (precision == 3) {
+    const int64_t blocks = (nrows + 3) / 4;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(store_fp8_kernel, dim3((unsigned)blocks), dim3(256), 0, st,
+                       vec32 + row0 * stride, stride, dim,
+                       static_cast<uint8_t*>(veclp) + row0 * lp_stride, lp_stride, vscale + row0,
+                       nrows);
+    return hipGetLastError();
+  }
   const int64_t n = nrows * stride;
-  if (n <= 0 || precision == 0) return hipSuccess;
   int64_t blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(store_lowp_kernel, dim3((unsigned)blocks), dim3(256), 0, st,

@@ -123,20 +123,47 @@ struct QuerySlice {
   static constexpr int kVecPerWave = kWave / kLanesPerVec;
   float q[NC][E];
 
+  // All lanes of the wave call load; the lanes of one group hold one copy of
+  // the query between them.  The FP8 form quantises the query like a stored
+  // vector (its own scale, E4M3 codes) and keeps the FP32 products s * value.
   __device__ void load(const float* qrow, int dim, int sl) {
+    if constexpr (Elem<VT>::kScaled) {
+      float m = 0.0f;
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+      for (int c = 0; c < NC; ++c)
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        int idx = c * 128 + sl * E + e;
-        q[c][e] = idx < dim ? Elem<VT>::round(qrow[idx]) : 0.0f;
-      }
+        for (int e = 0; e < E; ++e) {
+          const int idx = c * 128 + sl * E + e;
+          q[c][e] = idx < dim ? qrow[idx] : 0.0f;
+          m = __builtin_fmaxf(m, __builtin_fabsf(q[c][e]));
+        }
+#pragma unroll
+      for (int o = 1; o < kLanesPerVec; o <<= 1) m = __builtin_fmaxf(m, __shfl_xor(m, o));
+      const float s = fp8_scale_of(m);
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          q[c][e] = __fmul_rn(s, Elem<VT>::value(f32_to_e4m3_sat(__fdiv_rn(q[c][e], s))));
+    } else {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          int idx = c * 128 + sl * E + e;
+          q[c][e] = idx < dim ? Elem<VT>::round(qrow[idx]) : 0.0f;
+        }
+    }
   }
 };
 
+// Partial distance over the lane's slice.  A scaled (FP8) vector stands for
+// xs * value(code): for L2 each difference q - xs * value is formed by one
+// fused multiply-add; for the inner product the sum of q * value is returned
+// and the caller multiplies the whole sum by xs.
 template <typename VT, int NC>
 __device__ __forceinline__ float partial_dist(const QuerySlice<VT, NC>& qs, const uint4 (&w)[NC],
-                                              int metric) {
+                                              int metric, float xs = 1.0f) {
   constexpr int E = Elem<VT>::kPer16B;
   float acc = 0.0f;
 #pragma unroll
@@ -144,8 +171,16 @@ __device__ __forceinline__ float partial_dist(const QuerySlice<VT, NC>& qs, cons
     float x[E];
     Elem<VT>::unpack(w[c], x);
     if (metric == 0) {
+      if constexpr (Elem<VT>::kScaled) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) { float t = qs.q[c][e] - x[e]; acc = __builtin_fmaf(t, t, acc); }
+        for (int e = 0; e < E; ++e) {
+          const float t = __builtin_fmaf(-xs, x[e], qs.q[c][e]);
+          acc = __builtin_fmaf(t, t, acc);
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) { float t = qs.q[c][e] - x[e]; acc = __builtin_fmaf(t, t, acc); }
+      }
     } else {
 #pragma unroll
       for (int e = 0; e < E; ++e) acc = __builtin_fmaf(qs.q[c][e], x[e], acc);
@@ -185,8 +220,15 @@ __device__ __forceinline__ float reduce_scatter(float (&acc)[U]) {
 // Vector steps gathered per round trip: 32 vectors of one 128-element chunk
 // (16 x 16-byte loads per lane for FP32, 8 for 16-bit stores), fewer steps
 // for wider vectors.
+#ifndef SVF_GATHER_STEPS_F32
+#define SVF_GATHER_STEPS_F32 16
+#endif
+#ifndef SVF_GATHER_STEPS_LOWP
+#define SVF_GATHER_STEPS_LOWP 8
+#endif
 template <typename VT, int NC> struct GatherSteps {
-  static constexpr int base = sizeof(VT) == 4 ? 16 : 8;
+  // powers of two; FP8 default: 8 steps of 8 vectors
+  static constexpr int base = sizeof(VT) == 4 ? SVF_GATHER_STEPS_F32 : SVF_GATHER_STEPS_LOWP;
   static constexpr int value = base / NC < 2 ? 2 : base / NC;
 };
 
@@ -194,12 +236,15 @@ template <typename VT, int NC> struct GatherSteps {
 // the key of cid[j] (kKeyInf for j >= m).  A step gathers VPW vectors, one per
 // group of LPV lanes; U steps are loaded before any is consumed.
 // With a tier (TIER), vector j is read from tcache row slot[j] when that slot
-// is >= 0 and from base row cid[j] otherwise.
+// is >= 0 and from base row cid[j] otherwise.  A scaled (FP8) store reads the
+// vector's scale from vscale[id] with its row.
 template <typename VT, int NC, bool TIER = false>
 __device__ inline uint64_t gather_keys(const QuerySlice<VT, NC>& qs, const VT* __restrict__ base,
                                        int64_t stride, const int32_t* cid, int m, int metric,
                                        const int32_t* slot = nullptr,
-                                       const VT* __restrict__ tcache = nullptr) {
+                                       const VT* __restrict__ tcache = nullptr,
+                                       const float* __restrict__ vscale = nullptr) {
+  constexpr bool kScaled = Elem<VT>::kScaled;
   using QS = QuerySlice<VT, NC>;
   constexpr int E = QS::E;
   constexpr int LPV = QS::kLanesPerVec;
@@ -214,12 +259,15 @@ __device__ inline uint64_t gather_keys(const QuerySlice<VT, NC>& qs, const VT* _
   const int steps = (m + VPW - 1) / VPW;
   for (int s0 = 0; s0 < steps; s0 += U) {
     uint4 w[U][NC];
+    float xs[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int j = (s0 + u) * VPW + sub;
       const bool on = j < m;
       const int32_t id = on ? cid[j] : 0;
       const VT* row = base + (int64_t)id * stride;
+      if constexpr (kScaled) xs[u] = on ? vscale[id] : 0.0f;
+      else xs[u] = 1.0f;
       if constexpr (TIER) {
         const int32_t sl_ = on ? slot[j] : -1;
         if (sl_ >= 0) row = tcache + (int64_t)sl_ * stride;
@@ -235,7 +283,7 @@ __device__ inline uint64_t gather_keys(const QuerySlice<VT, NC>& qs, const VT* _
     }
     float acc[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) acc[u] = partial_dist<VT, NC>(qs, w[u], metric);
+    for (int u = 0; u < U; ++u) acc[u] = partial_dist<VT, NC>(qs, w[u], metric, xs[u]);
     const float r = reduce_scatter<LPV, U>(acc);
     // lane j takes vector j = (s0 + u) * VPW + h from lane h * LPV + u * (LPV / U)
     const int u = lane / VPW - s0;
@@ -245,6 +293,7 @@ __device__ inline uint64_t gather_keys(const QuerySlice<VT, NC>& qs, const VT* _
     if (u >= 0 && u < U) mine = got;
   }
   if (lane >= m) return kKeyInf;
+  if (kScaled && metric != 0) mine *= vscale[cid[lane]];
   const float d = metric == 0 ? mine : -mine;
   return make_key(d, cid[lane]);
 }

@@ -1,0 +1,100 @@
+"""FP8 traversal (OCP E4M3 codes, one FP32 scale per vector, FP32
+accumulation, exact FP32 re-scoring) on the GPU against the FP64 oracle.
+
+On rows whose values are levels of FP8_EXACT_LEVELS with largest magnitude 56
+the scale is 1/8 and every code is exact, and all distances are integers
+below 2^24: the FP8 search must then equal the oracle's bit for bit.  On float
+data the two may differ only where the oracle decided by a near tie."""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2601_08528_amd as svf
+from paper_2601_08528_amd import datagen
+from gpu_util import gpu_from_oracle, oracle_index, tol_close
+
+pytestmark = pytest.mark.gpu
+
+
+def dev_counts(g, q, k, beam):
+    import torch
+    qt = torch.from_numpy(np.ascontiguousarray(q, np.float32)).cuda()
+    nq = q.shape[0]
+    ids = torch.empty((nq, k), dtype=torch.int32, device="cuda")
+    d = torch.empty((nq, k), dtype=torch.float32, device="cuda")
+    nd = torch.empty(nq, dtype=torch.int32, device="cuda")
+    ne = torch.empty(nq, dtype=torch.int32, device="cuda")
+    g.search_dev(qt.data_ptr(), nq, k, beam, ids.data_ptr(), d.data_ptr(), nd.data_ptr(),
+                 ne.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    return ids.cpu().numpy(), d.cpu().numpy(), ne.cpu().numpy()
+
+
+@pytest.mark.parametrize("dim", [128, 72])
+@pytest.mark.parametrize("rerank", [0, 1])
+def test_fp8_search_bit_exact_on_exact_levels(dim, rerank):
+    base, q = datagen.gmm_fp8_exact_valued(401, 5000, 131, dim, 16)
+    oix = oracle_index(base, 24, seed=3)
+    oix.set("precision", O.P_FP8)
+    g = gpu_from_oracle(oix, base, seed=3, precision=svf.PREC_FP8, rerank=rerank)
+    for beam in (16, 96):
+        oi, od, ost = oix.search(q, 10, beam, rerank=bool(rerank))
+        gi, gd, gne = dev_counts(g, q, 10, beam)
+        np.testing.assert_array_equal(gi, oi)
+        np.testing.assert_array_equal(gd.astype(np.float64), od)
+        np.testing.assert_array_equal(gne, ost["n_exp"])
+
+
+def test_fp8_build_bit_exact_on_exact_levels():
+    """Insertion with FP8 traversal (edges take exact distances) builds the
+    oracle's graph."""
+    base, _ = datagen.gmm_fp8_exact_valued(402, 2500, 1, 128, 12)
+    oix = O.OracleIndex(128, 16, O.L2, seed=4, insert_batch_max=300)
+    oix.set("precision", O.P_FP8)
+    oix.build(base, batch_max=300)
+    g = svf.Index(128, 16, svf.METRIC_L2, seed=4, insert_batch_max=300, precision=svf.PREC_FP8)
+    g.build(base)
+    gr, ge, ga = g.export_graph()
+    orows, oe, oa = oix.export()
+    np.testing.assert_array_equal(ga, oa)
+    np.testing.assert_array_equal(gr, orows)
+    np.testing.assert_array_equal(ge.astype(np.float64), oe)
+
+
+@pytest.mark.parametrize("metric,dim", [(O.L2, 128), (O.IP, 200)])
+def test_fp8_float_matches_except_near_ties(metric, dim):
+    base, q = datagen.gmm_float(403, 8000, 120, dim, 16, normalise=(metric == O.IP))
+    oix = oracle_index(base, 32, metric=metric, seed=5)
+    oix.set("precision", O.P_FP8)
+    g = gpu_from_oracle(oix, base, seed=5, precision=svf.PREC_FP8)
+    oi, od, ost = oix.search(q, 10, 64)
+    gi, gd = g.search(q, 10, 64)
+    decisive = ost["margin"] > 1e-5
+    same = (gi == oi).all(axis=1)
+    assert same[decisive].all(), np.nonzero(decisive & ~same)
+    assert decisive.mean() > 0.3
+    exact = oix.query_dists(q, gi)
+    scale = np.linalg.norm(q, axis=1)[:, None] * np.linalg.norm(base, axis=1).max()
+    assert tol_close(gd, exact, metric, scale=scale).all()
+    assert (np.diff(gd, axis=1) >= 0).all()
+    gt_i, gt_d = O.bruteforce(base, q, 10, metric=metric)
+    assert O.recall_at_k(gi, exact, gt_d, 10) >= 0.9
+
+
+def test_fp8_switch_and_growth_keep_results():
+    """Switching precision on a filled index, then growing it by insertion,
+    gives the results of an index built in FP8 form from the start."""
+    base, q = datagen.gmm_fp8_exact_valued(404, 3000, 60, 96, 10)
+    a = svf.Index(96, 16, svf.METRIC_L2, seed=9, insert_batch_max=500)
+    a.build(base[:1200])
+    a.set_option("precision", svf.PREC_FP8)
+    a.insert(base[1200:])
+    b = svf.Index(96, 16, svf.METRIC_L2, seed=9, insert_batch_max=500)
+    b.build(base[:1200])
+    b.insert(base[1200:])
+    b.set_option("precision", svf.PREC_FP8)
+    ia, da = a.search(q, 10, 48)
+    ib, db = b.search(q, 10, 48)
+    # exact levels: FP8 traversal equals FP32 traversal, so both graphs agree
+    np.testing.assert_array_equal(ia, ib)
+    np.testing.assert_array_equal(da, db)

@@ -78,3 +78,39 @@ def test_updates_on_tiered_store_bit_exact():
         np.testing.assert_array_equal(a, b)
     np.testing.assert_array_equal(plain.search(q, 10, 32)[0], tier.search(q, 10, 32)[0])
     assert tier.stats()["cache_slots"] == 500
+
+
+def test_tiering_a_filled_index_warm_start_matches_replay():
+    """cache_bytes on a filled index (with deleted vectors): the FP32 store moves
+    to host memory, the cache is warmed with the highest in-degree alive
+    vectors, results stay those of the untiered index, and the placements of
+    the following batches equal the oracle's replay from the same warm start."""
+    base, q = datagen.gmm_uint8_valued(703, 4000, 400, 48, 16)
+    oix = oracle_index(base, 16, seed=8)
+    oix.delete(np.arange(0, 4000, 11, dtype=np.int32))
+    rows, ed, alive = oix.export()
+    g = svf.Index(48, 16, svf.METRIC_L2, seed=8)
+    g.import_graph(base, rows, ed.astype(np.float32), alive)
+    ref_i, ref_d = g.search(q[:100], 10, 40)
+    cap_rows, trace_cap, theta = 250, 64, 1.0
+    g.set_option("cache_trace_cap", trace_cap)
+    g.set_option("cache_theta", theta)
+    g.set_option("cache_bytes", cap_rows * 4 * 48)
+    assert g.stats()["cache_promotions"] == cap_rows          # warm-up filled every slot
+    e_in = np.zeros(len(alive), np.int64)
+    src = rows[alive.astype(bool)]
+    np.add.at(e_in, src[src >= 0], 1)
+    batches, got = [], []
+    for b in range(4):
+        qb = q[b * 100:(b + 1) * 100]
+        gi, gd = g.search(qb, 10, 40)
+        if b == 0:
+            np.testing.assert_array_equal(gi, ref_i)
+            np.testing.assert_array_equal(gd, ref_d)
+        got.append(g.stats()["cache_last_trace_hits"])
+        tr, cnt = oix.search_expansions(qb, 40, cap=trace_cap)
+        batches.append(np.concatenate([tr[i, :min(cnt[i], trace_cap)] for i in range(len(qb))]))
+    hits, _ = O.wavp_replay(len(alive), cap_rows, e_in, alive, batches, 0.6, 0.4, theta, 2048,
+                            warm=True)
+    assert got == hits.tolist()
+    assert got[0] > 0

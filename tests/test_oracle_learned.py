@@ -130,6 +130,21 @@ def test_wavp_threshold_and_indegree_terms():
     assert slots.tolist() == [3, 1]
 
 
+def test_wavp_warm_start_hand_worked():
+    """Cold-start placement: alive vectors by in-degree (ties by id) fill the
+    slots in order; then one batch worked by hand with theta = 0.5:
+    F(3) = 0.6*1 + 0.4*ln 2 = 0.877 beats F(0) = 0.4*ln 5 = 0.644 but not
+    F(2) = 0.4*ln 10 = 0.921, and slot 0 (vector 1, just hit) is skipped once."""
+    e_in = [4, 9, 9, 1, 7]
+    alive = np.array([1, 1, 1, 1, 0], np.uint8)        # vector 4 is deleted
+    hits, slots = O.wavp_replay(5, 3, e_in, alive, [], warm=True)
+    assert slots.tolist() == [1, 2, 0]
+    hits, slots = O.wavp_replay(5, 3, e_in, alive, [[3, 1]], theta=0.5, warm=True)
+    assert hits.tolist() == [1] and slots.tolist() == [1, 2, 3]
+    hits, slots = O.wavp_replay(5, 3, e_in, alive, [[3, 1]], theta=1.0, warm=True)
+    assert hits.tolist() == [1] and slots.tolist() == [1, 2, 0]
+
+
 def test_expansion_trace_matches_search(idx):
     ix, base, q = idx
     tr, cnt = ix.search_expansions(q, 24)
