@@ -269,6 +269,101 @@ def large_bench(torch, svf, datagen, n_base, steps, warmup):
                          "n_exp_per_query": round(n_exp / nq, 1)}}
 
 
+def tier_bench(torch, svf, datagen, n_base, rounds=20, cache_frac=0.25):
+    """Tiered store (X4) on a scaled version of the paper's largest workload:
+    n_base x 128 mixture of 4096 components, L2, degree 32, batches of 10k
+    queries whose components follow Zipf(1.2).  The index is built in HBM
+    and searched untiered; then its FP32 vectors move to pinned host memory
+    behind an HBM cache of cache_frac of them (warmed by in-degree).  Two
+    phases of `rounds` fresh batches follow: FP32 traversal through the
+    cache, then FP8 traversal (codes in HBM) with only the exact FP32
+    re-scoring going through the cache.  After every batch the workload-aware
+    placement updates the cache."""
+    dim, R, nq = 128, 32, 10_000
+    base, queries = datagen.gmm_float(5, n_base, (2 * rounds + 1) * nq, dim, 4096, query_zipf=1.2)
+    ix = svf.Index(dim, R, svf.METRIC_L2, seed=0)
+    t0 = time.perf_counter()
+    ix.build(base)
+    build_s = time.perf_counter() - t0
+    bufs = (torch.empty((nq, K), dtype=torch.int32, device="cuda"),
+            torch.empty((nq, K), dtype=torch.float32, device="cuda"),
+            torch.empty(nq, dtype=torch.int32, device="cuda"),
+            torch.empty(nq, dtype=torch.int32, device="cuda"))
+    q0 = torch.from_numpy(queries[:nq]).cuda()
+    base_t = torch.from_numpy(base).cuda()
+    del base
+
+    def rec1k(qs):
+        kth = exact_kth(torch, base_t, qs, K, chunk=128)
+        ids = bufs[0][:qs.shape[0]].long()
+        ex = ((base_t[ids].double() - qs[:, None, :].double()) ** 2).sum(-1)
+        return (ex <= kth[:, None]).double().mean().item()
+
+    def pick_beam():
+        # smallest beam of the sweep reaching recall@10 >= 0.95 (1k-query sample)
+        rows = []
+        for b in BEAMS:
+            run_search(torch, ix, q0, b, bufs)
+            torch.cuda.synchronize()
+            r = rec1k(q0[:1000])
+            rows.append({"beam": b, "recall@10_1k": round(r, 4)})
+            if r >= 0.95:
+                return b, rows
+        return BEAMS[-1], rows
+
+    def run_rounds(beam, first):
+        out = []
+        for r in range(first, first + rounds):
+            qr = torch.from_numpy(queries[r * nq:(r + 1) * nq]).cuda()
+            s0 = ix.stats()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            run_search(torch, ix, qr, beam, bufs)
+            torch.cuda.synchronize()
+            wall_ms = (time.perf_counter() - t0) * 1e3
+            s1 = ix.stats()
+            h = s1["cache_gather_hits"] - s0["cache_gather_hits"]
+            m = s1["cache_gather_misses"] - s0["cache_gather_misses"]
+            kms = s1["last_search_ms"]
+            out.append({"round": r, "kernel_ms": round(kms, 3), "call_ms": round(wall_ms, 3),
+                        "gather_hit_rate": round(h / max(h + m, 1), 4),
+                        "host_link_gbs": round(m * dim * 4 / (kms / 1e3) / 1e9, 1),
+                        "placed": s1["cache_last_placed"]})
+        steady = out[-10:]
+        kms = float(np.mean([x["kernel_ms"] for x in steady]))
+        cms = float(np.mean([x["call_ms"] for x in steady]))
+        return {"beam": beam, "steady_kernel_ms": round(kms, 3), "steady_call_ms": round(cms, 3),
+                "steady_qps_kernel": round(nq / (kms / 1e3), 1),
+                "steady_qps_with_placement": round(nq / (cms / 1e3), 1),
+                "steady_gather_hit_rate":
+                    round(float(np.mean([x["gather_hit_rate"] for x in steady])), 4),
+                "recall@10_last_batch_1k": round(rec1k(qr[:1000]), 4), "rounds": out}
+
+    beam, sweep_rows = pick_beam()
+    ms_hbm, _ = timed_steps(torch, ix, q0, beam, bufs, 5, 1)
+    ref_ids = bufs[0].clone()
+    cache_bytes = int(cache_frac * n_base) * dim * 4
+    ix.set_option("cache_bytes", cache_bytes)
+    run_search(torch, ix, q0, beam, bufs)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(bufs[0], ref_ids))
+    fp32 = run_rounds(beam, 1)
+    ix.set_option("precision", svf.PREC_FP8)
+    beam8, sweep8 = pick_beam()
+    fp8 = run_rounds(beam8, rounds + 1)
+    fp8["beam_sweep"] = sweep8
+    del base_t
+    return {"workload": "%dM x 128 GMM (4096 comps, Zipf(1.2) queries), L2, degree 32, "
+                        "10k-query batches, k=10; cache of %d%% of the FP32 vectors in HBM, the "
+                        "rest in pinned host memory" % (n_base // 1_000_000, round(cache_frac * 100)),
+            "build_s": round(build_s, 2), "cache_bytes": cache_bytes, "beam_sweep": sweep_rows,
+            "untiered_fp32": {"beam": beam, "ms_per_batch": round(float(np.mean(ms_hbm)), 4),
+                              "qps": round(nq / (float(np.mean(ms_hbm)) / 1e3), 1)},
+            "tiered_same_results_as_untiered": same,
+            "tiered_fp32_traversal": fp32,
+            "tiered_fp8_traversal_fp32_rescore": fp8}
+
+
 def cpu_baseline(base, queries, beam):
     """The FP64 oracle, as it stands, on a bounded sample: it builds its own
     index over the first 20,000 base vectors (same generator) and searches
@@ -301,6 +396,8 @@ def main():
     ap.add_argument("--no-large", action="store_true",
                     help="skip the large-footprint (5M x 96) search leg")
     ap.add_argument("--large-n", type=int, default=5_000_000)
+    ap.add_argument("--no-tier", action="store_true", help="skip the tiered-store leg")
+    ap.add_argument("--tier-n", type=int, default=4_000_000)
     ap.add_argument("--search-only", type=int, default=0, metavar="BEAM",
                     help="build, then only time the plain FP32 search at this beam (for "
                          "hardware counter runs); prints a short JSON line")
@@ -450,6 +547,12 @@ def main():
         torch.cuda.empty_cache()
         large = large_bench(torch, svf, datagen, args.large_n, args.steps, args.warmup)
 
+    tier = None
+    if not args.no_tier:
+        log("tiered-store leg")
+        torch.cuda.empty_cache()
+        tier = tier_bench(torch, svf, datagen, args.tier_n)
+
     serving = None
     if not args.no_serving:
         log("serving mix")
@@ -508,6 +611,7 @@ def main():
                                                                "del_mark_ms", "del_repair_ms")},
                    "repaired_rows": st["last_repaired"]},
         "large_footprint": large,
+        "tiered": tier,
         "serving": serving,
         "wall_s_timed": round(wall, 4),
     }

@@ -102,9 +102,11 @@ int svf_destroy(svf_index *ix);
  *                   scale s = max|x| / 448 per vector (the query quantised the same way);
  *                   distances accumulate in FP32
  *   rerank          exact FP32 re-scoring of the final pool under reduced precision (0/1; 1)
- *   cache_bytes     tiered store (Sec. 4.2-4.3): all vectors in pinned host memory, an HBM
- *                   cache of cache_bytes / (4 * round_up(dim, 8)) rows in front; FP32
- *                   traversal only.  Set on an empty index, or on a filled one (its vectors
+ *   cache_bytes     tiered store (Sec. 4.2-4.3): all FP32 vectors in pinned host memory, an
+ *                   HBM cache of cache_bytes / (4 * round_up(dim, 8)) rows in front.  An FP32
+ *                   traversal reads through the cache; with FP16/BF16/FP8 traversal that
+ *                   store stays in HBM and only the exact re-scoring reads go through the
+ *                   cache.  Set on an empty index, or on a filled one (its vectors
  *                   then move to host memory and the cache is warmed by in-degree, as
  *                   after svf_build).  Once set it stays.  Searches read cached rows from HBM
  *                   and the rest over the host link; after every direct search call the

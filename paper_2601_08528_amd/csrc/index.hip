@@ -109,6 +109,7 @@ int reserve(svf_index* ix, int64_t need) {
     if (n > 0 && ix->tier.map) CK(hipMemcpyAsync(tmap, ix->tier.map, n * 4, hipMemcpyDeviceToDevice, st));
     ix->tier.where.resize(cap, -1);
     ix->tier.fr.resize(cap, 0.0);
+    ix->tier.fr_stamp.resize(cap, 0);
   } else {
     CK(svf::launch_fill_u32(v32, cap * ix->stride, 0u, st));
   }
@@ -225,10 +226,15 @@ void set_beam(svf::SearchArgs& a, const svf_index* ix, int L) {
   a.width = ix->opt.search_width;
 }
 
+// Milliseconds between two recorded events, 0 when they cannot be timed.  A
+// failure here must not stay behind as the thread's last HIP error, where
+// the next launch check would report it.
 float elapsed(hipEvent_t a, hipEvent_t b) {
   float ms = 0.f;
-  if (hipEventSynchronize(b) != hipSuccess) return 0.f;
-  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
+  if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0.f;
+  }
   return ms;
 }
 
@@ -659,57 +665,104 @@ int tier_apply(svf_index* ix, const std::vector<int32_t>& place, hipStream_t st)
   return SVF_OK;
 }
 
+// F_recent halves once per placement batch; a vertex's value is brought up
+// to date only when it is used.  Repeated halving is an exact power-of-two
+// scaling while the result stays a normal double, so whole runs of halvings
+// are one ldexp; below the normal range they are applied one by one, with
+// the rounding each single halving has.
+double halve_times(double v, int64_t k) {
+  while (k > 0 && v != 0.0) {
+    int e;
+    (void)std::frexp(v, &e);                 // |v| = m 2^e, m in [0.5, 1)
+    const int64_t room = (int64_t)e + 1021;  // halvings that keep |v| >= 2^-1022
+    if (room > 0) {
+      const int64_t j = std::min(k, room);
+      v = std::ldexp(v, -(int)j);
+      k -= j;
+    } else {
+      v *= 0.5;
+      --k;
+    }
+  }
+  return v;
+}
+double fr_now(const svf::TierState& T, int32_t x) {
+  return halve_times(T.fr[x], T.batch - T.fr_stamp[x]);
+}
+
 int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
   svf::TierState& T = ix->tier;
   const int cap = T.trace_cap;
-  std::vector<int32_t> tn(nq), tr((size_t)nq * cap);
-  unsigned long long cnt[2] = {0, 0};
   const int64_t n = ix->n_slots;
-  std::vector<uint32_t> bits((n + 31) / 32 + 1, 0u);
-  CK(hipMemcpyAsync(tn.data(), T.trace_n.p, nq * 4, hipMemcpyDeviceToHost, st));
-  CK(hipMemcpyAsync(tr.data(), T.trace.p, (size_t)nq * cap * 4, hipMemcpyDeviceToHost, st));
-  CK(hipMemcpyAsync(cnt, T.counts.p, sizeof cnt, hipMemcpyDeviceToHost, st));
-  CK(hipMemcpyAsync(bits.data(), ix->alive, ((n + 31) / 32) * 4, hipMemcpyDeviceToHost, st));
+  const int64_t words = (n + 31) / 32;
+  // per-vertex access counts and the touched bitmap, counted on the GPU
+  int32_t* cnt_d;
+  uint32_t* touched_d;
+  int rc;
+  if ((rc = scratch(T.acc_cnt, n, &cnt_d)) || (rc = scratch(T.touched, words, &touched_d))) return rc;
+  if (T.host_n < n) {
+    if (T.cnt_h) (void)hipHostFree(T.cnt_h);
+    if (T.touched_h) (void)hipHostFree(T.touched_h);
+    T.cnt_h = nullptr;
+    T.touched_h = nullptr;
+    T.host_n = 0;
+    const int64_t hn = std::max<int64_t>(n, ix->cap);
+    CK(hipHostMalloc((void**)&T.cnt_h, hn * 4, 0));
+    CK(hipHostMalloc((void**)&T.touched_h, ((hn + 31) / 32) * 4, 0));
+    T.host_n = hn;
+  }
+  CK(svf::launch_fill_u32(cnt_d, n, 0u, st));
+  CK(svf::launch_fill_u32(touched_d, words, 0u, st));
+  CK(svf::launch_trace_count(T.trace.as<int32_t>(), T.trace_n.as<int32_t>(), (int)nq, cap, cnt_d,
+                             touched_d, st));
+  unsigned long long gcnt[2] = {0, 0};
+  std::vector<uint32_t> bits(words + 1, 0u);
+  CK(hipMemcpyAsync(T.cnt_h, cnt_d, n * 4, hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(T.touched_h, touched_d, words * 4, hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(gcnt, T.counts.p, sizeof gcnt, hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(bits.data(), ix->alive, words * 4, hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
-  int rc = tier_refresh_indegree(ix, st);
+  rc = tier_refresh_indegree(ix, st);
   if (rc) return rc;
-  T.gather_hits += cnt[0];
-  T.gather_misses += cnt[1];
+  T.gather_hits += gcnt[0];
+  T.gather_misses += gcnt[1];
   auto alive = [&](int32_t x) { return ((bits[x >> 5] >> (x & 31)) & 1u) != 0; };
-  auto flam = [&](int32_t x) -> double {
-    return alive(x) ? T.alpha * T.fr[x] + T.beta * std::log(1.0 + (double)T.e_in[x]) : -1.0;
-  };
-  for (int64_t i = 0; i < n; ++i) T.fr[i] *= 0.5;
+  auto lg = [&](int32_t x) { return T.beta * std::log(1.0 + (double)T.e_in[x]); };
+  ++T.batch;
+  // every touched vertex in id order: F_recent halves, then gains one per
+  // access; accesses of cached vertices are hits and set their slot's
+  // reference bit; uncached vertices above theta become candidates
   int64_t hits = 0;
-  for (int64_t q = 0; q < nq; ++q) {
-    const int len = std::min(tn[q], cap);
-    for (int t = 0; t < len; ++t) {
-      const int32_t x = tr[(size_t)q * cap + t];
-      T.fr[x] += 1.0;
+  std::vector<std::pair<double, int32_t>> cand;
+  for (int64_t wi = 0; wi < words; ++wi) {
+    uint32_t m = T.touched_h[wi];
+    while (m) {
+      const int32_t x = (int32_t)(wi * 32 + __builtin_ctz(m));
+      m &= m - 1;
+      double v = fr_now(T, x);
+      const int32_t c = T.cnt_h[x];
+      for (int32_t t = 0; t < c; ++t) v += 1.0;
+      T.fr[x] = v;
+      T.fr_stamp[x] = T.batch;
       if (T.where[x] >= 0) {
-        ++hits;
+        hits += c;
         T.ref[T.where[x]] = 1;
+      } else if (alive(x)) {
+        const double f = T.alpha * v + lg(x);
+        if (f > T.theta) cand.emplace_back(f, x);
       }
     }
   }
   T.last_trace_hits = hits;
-  std::vector<std::pair<double, int32_t>> cand;
-  std::vector<int32_t> marked;
-  std::vector<uint8_t> mark(n, 0);
-  for (int64_t q = 0; q < nq; ++q) {
-    const int len = std::min(tn[q], cap);
-    for (int t = 0; t < len; ++t) {
-      const int32_t x = tr[(size_t)q * cap + t];
-      if (T.where[x] >= 0 || mark[x]) continue;
-      mark[x] = 1;
-      const double f = flam(x);
-      if (f > T.theta) cand.emplace_back(f, x);
-    }
-  }
-  std::sort(cand.begin(), cand.end(), [](const std::pair<double, int32_t>& a, const std::pair<double, int32_t>& b) {
+  auto better = [](const std::pair<double, int32_t>& a, const std::pair<double, int32_t>& b) {
     return a.first > b.first || (a.first == b.first && a.second < b.second);
-  });
-  if ((int64_t)cand.size() > T.promote_max) cand.resize(T.promote_max);
+  };
+  if ((int64_t)cand.size() > T.promote_max) {
+    std::nth_element(cand.begin(), cand.begin() + T.promote_max, cand.end(), better);
+    cand.resize(T.promote_max);
+  }
+  std::sort(cand.begin(), cand.end(), better);
+  auto flam = [&](int32_t y) -> double { return alive(y) ? T.alpha * fr_now(T, y) + lg(y) : -1.0; };
   std::vector<int32_t> place;
   for (const auto& c : cand) {
     const int32_t x = c.second;
@@ -781,7 +834,6 @@ int tier_warmup(svf_index* ix, hipStream_t st) {
 
 int tier_enable(svf_index* ix, double bytes) {
   svf::TierState& T = ix->tier;
-  if (ix->veclp_prec != 0) return fail(SVF_E_INVAL, "the tiered store runs FP32 traversal");
   const int64_t C = (int64_t)(bytes / (double)(ix->stride * 4));
   if (C < 1) return fail(SVF_E_INVAL, "cache_bytes below one vector");
   if (T.on) return fail(SVF_E_INVAL, "cache already configured");
@@ -822,6 +874,7 @@ int tier_enable(svf_index* ix, double bytes) {
   T.map = map;
   T.where.assign(ix->cap, -1);
   T.fr.assign(ix->cap, 0.0);
+  T.fr_stamp.assign(ix->cap, 0);
   T.on = true;
   return tier_warmup(ix, ix->stream);
 }
@@ -850,7 +903,10 @@ int svf_create(int32_t dim, int32_t degree, int32_t metric, svf_index** out) {
   hipError_t e;
   if ((e = hipGetDevice(&ix->device)) != hipSuccess ||
       (e = hipStreamCreateWithFlags(&ix->stream, hipStreamNonBlocking)) != hipSuccess ||
-      (e = hipEventCreate(&ix->ev0)) != hipSuccess || (e = hipEventCreate(&ix->ev1)) != hipSuccess) {
+      (e = hipEventCreate(&ix->ev0)) != hipSuccess || (e = hipEventCreate(&ix->ev1)) != hipSuccess ||
+      // both events start recorded, so timings read before any work are 0
+      (e = hipEventRecord(ix->ev0, ix->stream)) != hipSuccess ||
+      (e = hipEventRecord(ix->ev1, ix->stream)) != hipSuccess) {
     delete ix;
     return hip_fail(e, "device setup");
   }
@@ -946,7 +1002,6 @@ int svf_set_option(svf_index* ix, const char* key, double v) {
     if (!is_int(v) || v < 16 || v > 8192) return fail(SVF_E_INVAL, "cache_trace_cap in [16, 8192]");
     ix->tier.trace_cap = (int)v;
   } else if (k == "precision") {
-    if (v != 0 && ix->tier.on) return fail(SVF_E_INVAL, "the tiered store runs FP32 traversal");
     if (v != 0 && v != 1 && v != 2 && v != 3)
       return fail(SVF_E_INVAL, "precision 0 (FP32), 1 (FP16), 2 (BF16) or 3 (FP8)");
     o.precision = (int)v;

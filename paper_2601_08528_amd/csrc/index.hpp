@@ -71,14 +71,22 @@ struct TierState {
   std::vector<int32_t> slot_id;    // slot -> id (-1 empty)
   std::vector<int32_t> where;      // id -> slot (host mirror of map)
   std::vector<uint8_t> ref;        // reference bits per slot
-  std::vector<double> fr;          // F_recent per id
+  std::vector<double> fr;          // F_recent per id, as of batch fr_stamp[id]
+  std::vector<int64_t> fr_stamp;   // (the halvings of later batches are applied on use)
   std::vector<int32_t> e_in;       // in-degree per id
-  int64_t used = 0, clock = 0, e_in_epoch = -1;
+  int64_t used = 0, clock = 0, e_in_epoch = -1, batch = 0;
   double alpha = 0.6, beta = 0.4, theta = 1.0;
   int promote_max = 2048, trace_cap = 512;
   uint64_t gather_hits = 0, gather_misses = 0, promotions = 0, evictions = 0;
   int64_t last_trace_hits = 0, last_placed = 0;
-  DevBuf trace, trace_n, place, counts, e_in_d;
+  DevBuf trace, trace_n, place, counts, e_in_d, acc_cnt, touched;
+  int32_t* cnt_h = nullptr;        // pinned host mirrors of acc_cnt / touched
+  uint32_t* touched_h = nullptr;
+  int64_t host_n = 0;
+  ~TierState() {
+    if (cnt_h) (void)hipHostFree(cnt_h);
+    if (touched_h) (void)hipHostFree(touched_h);
+  }
 };
 }  // namespace svf
 

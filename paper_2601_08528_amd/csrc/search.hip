@@ -25,10 +25,6 @@
 #include "kernels.hpp"
 #include "wave_ops.hpp"
 
-#ifndef SVF_ROW_PREFETCH
-#define SVF_ROW_PREFETCH 1
-#endif
-
 namespace svf {
 
 // ---------------------------------------------------------------------------
@@ -46,7 +42,10 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
   w.cid = reinterpret_cast<int32_t*>(w.kept + kWave);
   int32_t* slot = w.cid + kWave;                 // tier slots of the survivors
   void* vis_mem = reinterpret_cast<void*>(slot + kWave);
-  constexpr bool tier = TIER;
+  // With a tier the FP32 store sits in host memory behind an HBM cache.  An
+  // FP32 traversal reads through the cache; a reduced-precision traversal
+  // store stays in HBM and only the exact re-scoring reads go through it.
+  constexpr bool tier = TIER && sizeof(VT) == 4;
   unsigned long long t_hit = 0, t_miss = 0;
   w.L = a.L;
   w.ktrack = a.last_change ? (a.k > 0 ? a.k : 1) : 0;
@@ -99,7 +98,7 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
         t_hit += popc64(ballot(h));
         t_miss += nt - popc64(ballot(h));
       }
-      uint64_t k = gather_keys<VT, NC, TIER>(qs, base, a.vstride, w.cid, nt, a.metric, slot,
+      uint64_t k = gather_keys<VT, NC, tier>(qs, base, a.vstride, w.cid, nt, a.metric, slot,
                                              reinterpret_cast<const VT*>(a.tcache), a.vscale);
       n_dist += nt;
       sort_merge(w, k);
@@ -145,44 +144,24 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
   // Each iteration expands the `width` smallest unexpanded entries (one by
   // default); their rows are filtered, gathered and merged chunk by chunk,
   // which equals one merge of all new keys (the top-L of a union).
-  //
-  // With one parent per iteration, the row of the next unexpanded entry after
-  // the parent is loaded while this iteration gathers; when that entry is the
-  // next parent (no closer key arrived), its row is already in registers.
-  // Rows do not change during a search, so this only moves a load earlier.
   const int cap_iters = (a.q_max_iters && a.q_max_iters[qi] > 0) ? a.q_max_iters[qi] : a.max_iters;
-  const bool pf_on = SVF_ROW_PREFETCH && a.width == 1 && a.R <= kWave;
-  int32_t pf_id = -1, pf_nb = -1;
   int last_change = 0, n_iter = 0;
   for (;;) {
     if (cap_iters > 0 && n_iter >= cap_iters) break;
     int ppos[4];
-    int pnext = -1;
-    const int want = a.width + (pf_on ? 1 : 0);
-    int found = 0;
-    for (int b0 = 0; b0 < a.L && found < want; b0 += kWave) {
+    int np = 0;
+    for (int b0 = 0; b0 < a.L && np < a.width; b0 += kWave) {
       const int i = b0 + lane;
       const bool un = i < a.L && (w.pool[i] & 1ull) == 0;
       uint64_t bm = ballot(un);
-      while (bm && found < want) {
-        const int pos = b0 + __ffsll((unsigned long long)bm) - 1;
-        if (found < a.width) ppos[found] = pos;
-        else pnext = pos;
-        ++found;
+      while (bm && np < a.width) {
+        ppos[np++] = b0 + __ffsll((unsigned long long)bm) - 1;
         bm &= bm - 1;
       }
     }
-    const int np = found < a.width ? found : a.width;
     if (np == 0) break;
     int32_t parents[4];
     for (int t = 0; t < np; ++t) parents[t] = key_id(w.pool[ppos[t]]);
-    int32_t row_nb = -1;
-    if (pf_on) {
-      row_nb = parents[0] == pf_id ? pf_nb
-                                   : (lane < a.R ? a.graph[(int64_t)parents[0] * a.R + lane] : -1);
-      pf_id = pnext >= 0 ? key_id(w.pool[pnext]) : -1;
-      pf_nb = (pf_id >= 0 && lane < a.R) ? a.graph[(int64_t)pf_id * a.R + lane] : -1;
-    }
     __syncthreads();
     if (lane == 0) {
       for (int t = 0; t < np; ++t) {
@@ -197,7 +176,7 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
       const int32_t* row = a.graph + (int64_t)parents[t] * a.R;
       for (int r0 = 0; r0 < a.R; r0 += kWave) {
         const int rr = r0 + lane;
-        const int32_t nb = pf_on ? row_nb : (rr < a.R ? row[rr] : -1);
+        const int32_t nb = rr < a.R ? row[rr] : -1;
         bool ok = nb >= 0 && nb < a.n_slots;
         __syncthreads();
         if (ok) ok = !vis.test_and_set(nb);
@@ -217,7 +196,7 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
         // the deletion bits load while the vectors are gathered
         const int32_t mine = lane < m ? w.cid[lane] : 0;
         const uint32_t aword = a.alive[(uint32_t)mine >> 5];
-        uint64_t k = gather_keys<VT, NC, TIER>(qs, base, a.vstride, w.cid, m, a.metric, slot,
+        uint64_t k = gather_keys<VT, NC, tier>(qs, base, a.vstride, w.cid, m, a.metric, slot,
                                                reinterpret_cast<const VT*>(a.tcache), a.vscale);
         if (lane < m && !((aword >> (mine & 31)) & 1u)) k = kKeyInf;
         n_dist += m;
@@ -237,10 +216,19 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
       const int32_t id = key_id(pk);
       const bool on = id >= 0;
       const uint64_t ob = ballot(on);
-      if (on) w.cid[lanes_below(ob)] = id;
+      if (on) {
+        w.cid[lanes_below(ob)] = id;
+        if (TIER) slot[lanes_below(ob)] = a.tmap[id];
+      }
       const int m = popc64(ob);
       __syncthreads();
-      const uint64_t k = gather_keys<float, NC>(q32, a.vec32, a.stride, w.cid, m, a.metric);
+      if (TIER) {
+        const bool h = lane < m && slot[lane] >= 0;
+        t_hit += popc64(ballot(h));
+        t_miss += m - popc64(ballot(h));
+      }
+      const uint64_t k = gather_keys<float, NC, TIER>(q32, a.vec32, a.stride, w.cid, m, a.metric,
+                                                      slot, a.tcache);
       if (lane < m) buf[c0 + lane] = k;
       else if (c0 + lane < Lp) buf[c0 + lane] = kKeyInf;
       __syncthreads();
@@ -334,11 +322,16 @@ static hipError_t launch_vis(const SearchArgs& a, int precision, int nc, size_t 
     case 0:
       return a.tmap ? launch_vt<float, VIS, true>(a, nc, lds, st)
                     : launch_vt<float, VIS, false>(a, nc, lds, st);
-    case 1: return a.tmap ? hipErrorInvalidValue : launch_vt<__half, VIS, false>(a, nc, lds, st);
-    case 2: return a.tmap ? hipErrorInvalidValue : launch_vt<bf16_t, VIS, false>(a, nc, lds, st);
+    case 1:
+      return a.tmap ? launch_vt<__half, VIS, true>(a, nc, lds, st)
+                    : launch_vt<__half, VIS, false>(a, nc, lds, st);
+    case 2:
+      return a.tmap ? launch_vt<bf16_t, VIS, true>(a, nc, lds, st)
+                    : launch_vt<bf16_t, VIS, false>(a, nc, lds, st);
     case 3:
-      return (a.tmap || !a.vscale || a.vstride % 16) ? hipErrorInvalidValue
-                                                     : launch_vt<fp8_t, VIS, false>(a, nc, lds, st);
+      if (!a.vscale || a.vstride % 16) return hipErrorInvalidValue;
+      return a.tmap ? launch_vt<fp8_t, VIS, true>(a, nc, lds, st)
+                    : launch_vt<fp8_t, VIS, false>(a, nc, lds, st);
   }
   return hipErrorInvalidValue;
 }

@@ -142,16 +142,27 @@ void finish(Server* sv, ServeReq* r, int status) {
   if (r->kind != 0) r->epoch = sv->epoch;   // a search keeps its launch epoch
 }
 
-// Retire finished search batches (caller holds sv->mu).
+// Retire finished search batches (caller holds sv->mu).  A batch still
+// running is not an error: its status must not stay behind as the thread's
+// last HIP error.  A batch whose stream failed ends its requests with
+// SVF_E_DEVICE instead of waiting for ever.
 void retire(Server* sv) {
   for (Slot& s : sv->slots) {
-    if (!s.busy || hipEventQuery(s.ev) != hipSuccess) continue;
+    if (!s.busy) continue;
+    const hipError_t q = hipEventQuery(s.ev);
+    if (q == hipErrorNotReady) {
+      (void)hipGetLastError();
+      continue;
+    }
+    const int status = q == hipSuccess ? SVF_OK : SVF_E_DEVICE;
     int64_t off = 0;
     for (ServeReq* r : s.reqs) {
-      std::memcpy(r->out_ids, s.hid + off * s.bk, (size_t)r->n * r->k * 4);
-      std::memcpy(r->out_d, s.hd + off * s.bk, (size_t)r->n * r->k * 4);
+      if (status == SVF_OK) {
+        std::memcpy(r->out_ids, s.hid + off * s.bk, (size_t)r->n * r->k * 4);
+        std::memcpy(r->out_d, s.hd + off * s.bk, (size_t)r->n * r->k * 4);
+      }
       off += r->n;
-      finish(sv, r, SVF_OK);
+      finish(sv, r, status);
     }
     s.reqs.clear();
     s.busy = false;

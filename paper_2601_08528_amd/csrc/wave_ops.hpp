@@ -218,17 +218,22 @@ __device__ __forceinline__ float reduce_scatter(float (&acc)[U]) {
 }
 
 // Vector steps gathered per round trip: 32 vectors of one 128-element chunk
-// (16 x 16-byte loads per lane for FP32, 8 for 16-bit stores), fewer steps
-// for wider vectors.
+// (FP32 16 steps of 2 vectors, 16-bit 8 steps of 4, FP8 4 steps of 8), fewer
+// steps for wider vectors.  Powers of two; on the 1M x 128 workload more
+// steps in flight only cost registers.
 #ifndef SVF_GATHER_STEPS_F32
 #define SVF_GATHER_STEPS_F32 16
 #endif
-#ifndef SVF_GATHER_STEPS_LOWP
-#define SVF_GATHER_STEPS_LOWP 8
+#ifndef SVF_GATHER_STEPS_16
+#define SVF_GATHER_STEPS_16 8
+#endif
+#ifndef SVF_GATHER_STEPS_8
+#define SVF_GATHER_STEPS_8 4
 #endif
 template <typename VT, int NC> struct GatherSteps {
-  // powers of two; FP8 default: 8 steps of 8 vectors
-  static constexpr int base = sizeof(VT) == 4 ? SVF_GATHER_STEPS_F32 : SVF_GATHER_STEPS_LOWP;
+  static constexpr int base = sizeof(VT) == 4   ? SVF_GATHER_STEPS_F32
+                              : sizeof(VT) == 2 ? SVF_GATHER_STEPS_16
+                                                : SVF_GATHER_STEPS_8;
   static constexpr int value = base / NC < 2 ? 2 : base / NC;
 };
 

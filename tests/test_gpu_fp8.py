@@ -30,11 +30,13 @@ def dev_counts(g, q, k, beam):
     return ids.cpu().numpy(), d.cpu().numpy(), ne.cpu().numpy()
 
 
-@pytest.mark.parametrize("dim", [128, 72])
+@pytest.mark.parametrize("dim,metric", [(128, O.L2), (72, O.L2), (200, O.IP)])
 @pytest.mark.parametrize("rerank", [0, 1])
-def test_fp8_search_bit_exact_on_exact_levels(dim, rerank):
+def test_fp8_search_bit_exact_on_exact_levels(dim, metric, rerank):
+    """dim 72: a 16-byte-ragged FP8 row; dim 200: two 128-element chunks with
+    the inner product (a scale of 1/8 keeps s * sum exact)."""
     base, q = datagen.gmm_fp8_exact_valued(401, 5000, 131, dim, 16)
-    oix = oracle_index(base, 24, seed=3)
+    oix = oracle_index(base, 24, metric=metric, seed=3)
     oix.set("precision", O.P_FP8)
     g = gpu_from_oracle(oix, base, seed=3, precision=svf.PREC_FP8, rerank=rerank)
     for beam in (16, 96):
@@ -72,13 +74,17 @@ def test_fp8_float_matches_except_near_ties(metric, dim):
     decisive = ost["margin"] > 1e-5
     same = (gi == oi).all(axis=1)
     assert same[decisive].all(), np.nonzero(decisive & ~same)
-    assert decisive.mean() > 0.3
+    # coarse FP8 values leave many near ties among inner products of unit
+    # vectors, so fewer queries are decided by a clear margin there
+    assert decisive.mean() > (0.3 if metric == O.L2 else 0.03)
     exact = oix.query_dists(q, gi)
     scale = np.linalg.norm(q, axis=1)[:, None] * np.linalg.norm(base, axis=1).max()
     assert tol_close(gd, exact, metric, scale=scale).all()
     assert (np.diff(gd, axis=1) >= 0).all()
     gt_i, gt_d = O.bruteforce(base, q, 10, metric=metric)
-    assert O.recall_at_k(gi, exact, gt_d, 10) >= 0.9
+    grec = O.recall_at_k(gi, exact, gt_d, 10)
+    orec = O.recall_at_k(oi, oix.query_dists(q, oi), gt_d, 10)
+    assert grec >= 0.9 and abs(grec - orec) <= 0.02
 
 
 def test_fp8_switch_and_growth_keep_results():

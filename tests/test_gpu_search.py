@@ -164,3 +164,16 @@ def test_float_workload_matches_except_near_ties():
     assert (np.diff(gd, axis=1) >= 0).all()
     gt_i, gt_d = O.bruteforce(base, q, 10)
     assert O.recall_at_k(gi, exact, gt_d, 10) >= 0.95
+
+
+def test_stats_before_any_search_leave_no_error():
+    """Reading the statistics before any timed call (events never recorded by
+    work) leaves no stale HIP error behind for the next call."""
+    base, q = datagen.gmm_uint8_valued(203, 800, 20, 32, 4)
+    oix = oracle_index(base, 8, seed=2)
+    g = gpu_from_oracle(oix, base, seed=2)
+    st = g.stats()
+    assert st["last_search_ms"] >= 0.0
+    gi, gd = g.search(q, 5, 16)
+    oi, od, _ = oix.search(q, 5, 16)
+    np.testing.assert_array_equal(gi, oi)

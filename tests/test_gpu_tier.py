@@ -114,3 +114,44 @@ def test_tiering_a_filled_index_warm_start_matches_replay():
                             warm=True)
     assert got == hits.tolist()
     assert got[0] > 0
+
+
+@pytest.mark.parametrize("prec", [svf.PREC_FP8, svf.PREC_BF16])
+def test_reduced_precision_traversal_with_tiered_rescoring(prec):
+    """A reduced-precision traversal store stays in HBM; only the exact FP32
+    re-scoring goes through the cache.  Results equal the oracle's bit for
+    bit (the data is exact on both grids), every re-scoring read is either a
+    cache hit or a host read, and placement equals the oracle's replay."""
+    base, q = datagen.gmm_fp8_exact_valued(704, 5000, 300, 64, 16)
+    oix = oracle_index(base, 16, seed=9)
+    oix.set("precision", O.P_FP8 if prec == svf.PREC_FP8 else O.P_BF16)
+    L, cap_rows, trace_cap = 32, 400, 64
+    g = tiered_from_oracle(oix, base, cap_rows, seed=9, precision=prec,
+                           cache_trace_cap=trace_cap)
+    rows, _, alive = oix.export()
+    e_in = np.zeros(len(alive), np.int64)
+    src = rows[alive.astype(bool)]
+    np.add.at(e_in, src[src >= 0], 1)
+    batches, got = [], []
+    for b in range(3):
+        qb = q[b * 100:(b + 1) * 100]
+        s0 = g.stats()
+        gi, gd = g.search(qb, 10, L)
+        s1 = g.stats()
+        oi, od, _ = oix.search(qb, 10, L)
+        np.testing.assert_array_equal(gi, oi)
+        np.testing.assert_array_equal(gd.astype(np.float64), od)
+        reads = (s1["cache_gather_hits"] - s0["cache_gather_hits"]
+                 + s1["cache_gather_misses"] - s0["cache_gather_misses"])
+        assert reads == len(qb) * L                            # the final pools, re-scored
+        got.append(s1["cache_last_trace_hits"])
+        tr, cnt = oix.search_expansions(qb, L, cap=trace_cap)
+        batches.append(np.concatenate([tr[i, :min(cnt[i], trace_cap)] for i in range(len(qb))]))
+    hits, _ = O.wavp_replay(len(alive), cap_rows, e_in, alive, batches, 0.6, 0.4, 1.0, 2048)
+    assert got == hits.tolist()
+    g.set_option("rerank", 0)
+    s0 = g.stats()
+    g.search(q[:50], 10, L)
+    s1 = g.stats()
+    assert s1["cache_gather_hits"] == s0["cache_gather_hits"]
+    assert s1["cache_gather_misses"] == s0["cache_gather_misses"]
