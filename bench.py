@@ -138,61 +138,66 @@ def sweep(torch, ix, q_t, base_t, kth, bufs, beams, target=0.95):
     return chosen, rows
 
 
-def serving_bench(svf, datagen, rounds=40, rate_hz=120.0):
-    """Streaming mix on the serving loop: a 1M-vector unit-norm 96-d mixture
-    (1024 components, inner product, degree 48, BF16 traversal + FP32
-    re-score), then `rounds` rounds of [one 10k-vector insert, one 1k-id
-    delete of uniformly chosen live ids, four query batches of log-uniform
-    size 1..10k with Zipf(1.1)-skewed components], as open-loop Poisson
-    arrivals at rate_hz requests per second."""
-    n_build = 1_000_000
-    base, queries = datagen.workload_stream_ip(n_build + rounds * 10_000, 20_000)
+def serving_bench(svf, datagen, n_build=5_000_000, rounds=60, rates=(60.0, 240.0, 480.0)):
+    """Streaming mix on the serving loop: an n_build-vector unit-norm 96-d
+    mixture (1024 components, inner product, degree 48, BF16 traversal + FP32
+    re-score), then, at each offered load in turn, `rounds` rounds of [one
+    10k-vector insert, one 1k-id delete of uniformly chosen live ids, four
+    query batches of log-uniform size 1..10k with Zipf(1.1)-skewed
+    components] as open-loop Poisson arrivals.  The index keeps changing
+    from one load to the next."""
+    n_extra = len(rates) * rounds * 10_000
+    base, queries = datagen.workload_stream_ip(n_build + n_extra, 20_000)
     ix = svf.Index(96, 48, svf.METRIC_IP, seed=0, precision=svf.PREC_BF16)
     t0 = time.perf_counter()
     ix.build(base[:n_build])
     build_s = time.perf_counter() - t0
-    reqs = datagen.request_stream(rounds, 10_000, 1_000, 4, 10_000, rate_hz)
     g = np.random.Generator(np.random.Philox(31))
     victims = g.permutation(n_build).astype(np.int32)
     ix.serve_start(streams=4, max_batch=16384)
-    tickets = []
     pos_ins, pos_del, pos_q = n_build, 0, 0
-    keep = []
-    t_start = time.perf_counter()
-    for r in reqs:
-        now = time.perf_counter() - t_start
-        if r.arrival_s > now:
-            time.sleep(r.arrival_s - now)
-        if r.kind == "insert":
-            t, ids = ix.submit_insert(base[pos_ins:pos_ins + r.size])
-            pos_ins += r.size
-            keep.append(ids)
-        elif r.kind == "delete":
-            t = ix.submit_delete(victims[pos_del:pos_del + r.size])
-            pos_del += r.size
-        else:
-            idx = (pos_q + np.arange(r.size)) % queries.shape[0]
-            pos_q += r.size
-            t, ids, d = ix.submit_search(queries[idx], 10, 64)
-            keep.append((ids, d))
-        tickets.append((t, r.kind, r.size))
-    infos = [(kind, size, ix.wait(t, 300.0)) for t, kind, size in tickets]
-    wall = time.perf_counter() - t_start
+    loads = []
+    for rate_hz in rates:
+        reqs = datagen.request_stream(rounds, 10_000, 1_000, 4, 10_000, rate_hz)
+        tickets = []
+        keep = []
+        t_start = time.perf_counter()
+        for r in reqs:
+            now = time.perf_counter() - t_start
+            if r.arrival_s > now:
+                time.sleep(r.arrival_s - now)
+            if r.kind == "insert":
+                t, ids = ix.submit_insert(base[pos_ins:pos_ins + r.size])
+                pos_ins += r.size
+                keep.append(ids)
+            elif r.kind == "delete":
+                t = ix.submit_delete(victims[pos_del:pos_del + r.size])
+                pos_del += r.size
+            else:
+                idx = (pos_q + np.arange(r.size)) % queries.shape[0]
+                pos_q += r.size
+                t, ids, d = ix.submit_search(queries[idx], 10, 64)
+                keep.append((ids, d))
+            tickets.append((t, r.kind, r.size))
+        infos = [(kind, size, ix.wait(t, 300.0)) for t, kind, size in tickets]
+        wall = time.perf_counter() - t_start
+        out = {"offered_req_per_s": rate_hz, "requests": len(reqs), "wall_s": round(wall, 3)}
+        nq = sum(size for kind, size, _ in infos if kind == "search")
+        out["qps"] = round(nq / wall, 1)
+        for kind in ("search", "insert", "delete"):
+            lat = np.array([inf["total_ms"] for k, _, inf in infos if k == kind])
+            if lat.size:
+                out[kind] = {"n": int(lat.size), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                             "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                             "mean_ms": round(float(lat.mean()), 3)}
+        out["max_batch_queries"] = int(max(inf["batch_queries"] for _, _, inf in infos))
+        loads.append(out)
     ix.serve_stop()
-    out = {"workload": "1M x 96 unit-norm GMM (1024 comps, Zipf(1.1) queries), IP, degree 48, "
-                       "BF16 + FP32 re-score, k=10, beam 64; %d rounds of insert 10k / delete 1k / "
-                       "4 query batches 1..10k, Poisson %.0f req/s" % (rounds, rate_hz),
-           "build_s": round(build_s, 2), "wall_s": round(wall, 3)}
-    nq = sum(size for kind, size, _ in infos if kind == "search")
-    out["qps"] = round(nq / wall, 1)
-    for kind in ("search", "insert", "delete"):
-        lat = np.array([inf["total_ms"] for k, _, inf in infos if k == kind])
-        if lat.size:
-            out[kind] = {"n": int(lat.size), "p50_ms": round(float(np.percentile(lat, 50)), 3),
-                         "p99_ms": round(float(np.percentile(lat, 99)), 3),
-                         "mean_ms": round(float(lat.mean()), 3)}
-    out["max_batch_queries"] = int(max(inf["batch_queries"] for _, _, inf in infos))
-    return out
+    return {"workload": "%dM x 96 unit-norm GMM (1024 comps, Zipf(1.1) queries), IP, degree 48, "
+                        "BF16 + FP32 re-score, k=10, beam 64; per load %d rounds of insert 10k / "
+                        "delete 1k / 4 query batches 1..10k, Poisson arrivals"
+                        % (n_build // 1_000_000, rounds),
+            "build_s": round(build_s, 2), "loads": loads}
 
 
 def exact_kth_ip(torch, base_t, q_t, k, extra=64, chunk=64):
