@@ -4,13 +4,14 @@
 // Per query the wave keeps in LDS
 //   - the candidate pool: `L` sorted 64-bit keys (dist, id, expanded flag),
 //     double-buffered so a merge writes the next pool while reading this one;
-//   - a visited table of T id slots (open addressing).  During the entry phase
-//     it is exact; afterwards a probe sequence of kProbe slots that finds
-//     neither the id nor a free slot overwrites its first slot, so the table
-//     may forget ids but never reports an unvisited id as visited.  Forgetting
-//     costs only repeated distance evaluations: an id that left the pool had
-//     L smaller keys, the L-th key never grows, so it is rejected again, and an
-//     id still in the pool is recognised by its identical key during the merge.
+//   - a visited table: exact tags of the ids in small sets, the oldest of a
+//     full set forgotten (or, for ids too wide for tags, 32-bit ids with a
+//     bounded probe run).  The table may forget ids but never reports an
+//     unvisited id as visited.  Forgetting costs only repeated distance
+//     evaluations: an id that left the pool had L smaller keys, the L-th key
+//     never grows, so it is rejected again, and an id still in the pool is
+//     recognised by its identical key during the merge.  During the entry
+//     phase the table's LDS holds an exact list of the accepted entries.
 //
 // One iteration: the smallest unexpanded key is the parent (Algorithm 1,
 // GetNearest); its row of R ids is read with one coalesced load; ids that are
@@ -287,21 +288,21 @@ __global__ void query_key_kernel(const float* __restrict__ q, int64_t qstride, c
 }
 
 // ---------------------------------------------------------------------------
-// Visited-table layout: 16-bit tags in 4-way sets when the ids fit (tag width
-// id_bits - log2(sets) <= 15), else 32-bit ids.
+// Visited-table layout: T / 4 sets of packed tags (T * 2 bytes) when the ids
+// fit (tag width id_bits - log2(sets) <= 15), else T 32-bit ids.
 static int id_bits_for(int32_t n_slots) {
   int b = 1;
   while (b < 31 && (1ll << b) < (long long)n_slots) ++b;
   return b;
 }
-static bool use_assoc16(int32_t n_slots, int T) {
+static bool use_tags(int32_t n_slots, int T) {
   int set_bits = 0;
   while ((1 << (set_bits + 1)) <= T / 4) ++set_bits;
   int b = id_bits_for(n_slots);
   if (b < set_bits + 1) b = set_bits + 1;
   return b - set_bits <= 15;
 }
-static size_t vis_bytes(int T, bool assoc16) { return assoc16 ? (size_t)T * 2 : (size_t)T * 4; }
+static size_t vis_bytes(int T, bool tags) { return tags ? (size_t)T * 2 : (size_t)T * 4; }
 
 template <typename VT, typename VIS, bool TIER>
 static hipError_t launch_vt(const SearchArgs& a, int nc, size_t lds, hipStream_t st) {
@@ -343,7 +344,7 @@ hipError_t launch_search(const SearchArgs& in, int precision, hipStream_t st) {
   const int chunks = (int)((a.stride + 127) / 128);
   const int nc = chunks <= 1 ? 1 : chunks <= 2 ? 2 : chunks <= 4 ? 4 : 8;
   if (chunks > 8) return hipErrorInvalidValue;
-  const bool assoc = a.vis_compact && use_assoc16(a.n_slots, a.T);
+  const bool assoc = a.vis_compact && use_tags(a.n_slots, a.T);
   // the entry phase keeps its exact list of accepted ids in the table's LDS
   while (vis_bytes(a.T, assoc) < (size_t)a.E * 4) a.T <<= 1;
   int set_bits = 0;
@@ -353,7 +354,7 @@ hipError_t launch_search(const SearchArgs& in, int precision, hipStream_t st) {
   int Lp = 64;
   while (Lp < a.L) Lp <<= 1;
   const size_t lds = (size_t)2 * Lp * 8 + kWave * 8 + 2 * kWave * 4 + vis_bytes(a.T, assoc);
-  return assoc ? launch_vis<VisAssoc16>(a, precision, nc, lds, st)
+  return assoc ? launch_vis<VisTags>(a, precision, nc, lds, st)
                : launch_vis<VisLinear32>(a, precision, nc, lds, st);
 }
 

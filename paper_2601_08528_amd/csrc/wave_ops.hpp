@@ -78,19 +78,33 @@ struct VisLinear32 {
   __device__ bool test_and_set(int32_t id) { return vis_test_and_set(t, mask, id); }
 };
 
-// VisAssoc16: ids below 2^B are scrambled by a bijection of [0, 2^B)
-// (multiplication by an odd constant modulo 2^B); the high bits pick a set of
-// four 16-bit ways, the low bits are the tag, so a tag match identifies the id
-// exactly.  Needs B - log2(sets) <= 15.  A set is read with one 64-bit load.
-struct VisAssoc16 {
+// VisTags: ids below 2^B are scrambled by a bijection of [0, 2^B)
+// (multiplication by an odd constant modulo 2^B); the high bits pick a set,
+// the low bits are the tag, so a tag match identifies the id exactly.  Tags
+// are packed: 12-bit fields, five to a 64-bit set, when tag_bits <= 11, else
+// 16-bit fields, four to a set (needs B - log2(sets) <= 15).  A new id enters a
+// set by shifting the set word up one field, so the oldest id of a full set
+// is the one forgotten (ids seen early in a search lie farthest from where
+// it ends).  Lanes that race on one set can only lose insertions; every tag a
+// set holds was inserted, so the table still never reports an unseen id.
+// A tag is found without a loop: the set word XOR the tag copied into every
+// field has a zero field exactly when some field holds the tag, which the
+// borrow test (x - ones) & ~x & highs detects (a borrow can only start at a
+// zero field, so it reports no field that is not zero).
+struct VisTags {
   uint64_t* sets;
   uint32_t idmask;
-  int tag_bits;
+  int tag_bits, fb;
+  uint64_t keep, ones, highs;
   __device__ void setup(void* p, int T, int id_bits) {
     sets = static_cast<uint64_t*>(p);
     const int set_bits = 31 - __clz(T / 4);
     idmask = id_bits >= 32 ? 0xffffffffu : ((1u << id_bits) - 1u);
     tag_bits = id_bits - set_bits;
+    fb = tag_bits <= 11 ? 12 : 16;
+    keep = fb == 12 ? ((1ull << 60) - 1ull) : ~0ull;
+    ones = fb == 12 ? 0x001001001001001ull : 0x0001000100010001ull;
+    highs = ones << (fb - 1);
   }
   __device__ void clear(int T) {
     for (int i = lane_id(); i < T / 4; i += kWave) sets[i] = 0ull;
@@ -98,17 +112,11 @@ struct VisAssoc16 {
   __device__ bool test_and_set(int32_t id) {
     const uint32_t h = ((uint32_t)id * 0x9E3779B1u) & idmask;
     const uint32_t set = h >> tag_bits;
-    const uint16_t tag = (uint16_t)((h & ((1u << tag_bits) - 1u)) + 1u);
+    const uint64_t tag = (uint64_t)((h & ((1u << tag_bits) - 1u)) + 1u);
     const uint64_t w = sets[set];
-    int empty = -1;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const uint16_t v = (uint16_t)(w >> (16 * k));
-      if (v == tag) return true;
-      if (v == 0 && empty < 0) empty = k;
-    }
-    const int way = empty >= 0 ? empty : (int)(id & 3);
-    reinterpret_cast<uint16_t*>(&sets[set])[way] = tag;
+    const uint64_t x = w ^ (tag * ones);
+    if (((x - ones) & ~x & highs) != 0ull) return true;
+    sets[set] = ((w << fb) | tag) & keep;
     return false;
   }
 };
