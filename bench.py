@@ -41,9 +41,9 @@ BEAMS = [32, 48, 64, 96, 128, 192, 256, 384, 512]
 # WRITE_SIZE 1,048,576).  The figure describes the kernel built from the sources
 # whose hash is recorded; any edit to them makes it stale and it is reported as null.
 COUNTED = {"sources": ("common.hpp", "wave_ops.hpp", "search.hip"),
-           "sha256_16": "188e966edd9a72ce", "beam": 96,
-           "fetch_kib": 9735444.0, "fetch_scale": 1048576.0 / 524300.0,
-           "write_kib": 2516.1, "write_scale": 1.0}
+           "sha256_16": "16e0b4bc82cf0a22", "beam": 96,
+           "fetch_kib": 9267048.4, "fetch_scale": 1048576.0 / 524299.5,
+           "write_kib": 2518.4, "write_scale": 1.0}
 
 
 def counted_traffic(beam):
@@ -253,7 +253,7 @@ def large_bench(torch, svf, datagen, n_base, steps, warmup):
     ms, _ = timed_steps(torch, ix, q_t, beam, bufs, steps, warmup)
     n_exp = int(bufs[3].sum().item())
     slots = ix.get_option("visited_slots")
-    ix.set_option("visited_slots", 8192)
+    ix.set_option("visited_slots", 16384)
     run_search(torch, ix, q_t, beam, bufs)
     torch.cuda.synchronize()
     n_dist = int(bufs[2].sum().item())
@@ -406,6 +406,8 @@ def main():
     ap.add_argument("--search-only", type=int, default=0, metavar="BEAM",
                     help="build, then only time the plain FP32 search at this beam (for "
                          "hardware counter runs); prints a short JSON line")
+    ap.add_argument("--search-precision", choices=("fp32", "bf16", "fp8"), default="fp32",
+                    help="traversal precision of --search-only (re-scored in FP32)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device-to-device three times (a reference "
                          "kernel of known traffic for hardware counter runs)")
@@ -447,12 +449,17 @@ def main():
             torch.empty(nq, dtype=torch.int32, device="cuda"),
             torch.empty(nq, dtype=torch.int32, device="cuda"))
     if args.search_only:
+        prec = {"fp32": svf.PREC_FP32, "bf16": svf.PREC_BF16, "fp8": svf.PREC_FP8}[args.search_precision]
+        ix.set_option("precision", prec)
         ms, _ = timed_steps(torch, ix, q_t, args.search_only, bufs, args.steps, args.warmup)
         n_dist = int(bufs[2].sum().item())
         n_exp = int(bufs[3].sum().item())
-        print(json.dumps({"beam": args.search_only, "ms_per_step": round(float(np.mean(ms)), 4),
+        per = {"fp32": DIM * 4, "bf16": DIM * 2, "fp8": DIM + 4}[args.search_precision]
+        rescore = 0 if prec == svf.PREC_FP32 else nq * args.search_only * DIM * 4
+        print(json.dumps({"beam": args.search_only, "precision": args.search_precision,
+                          "ms_per_step": round(float(np.mean(ms)), 4),
                           "n_dist": n_dist, "n_exp": n_exp,
-                          "alg_bytes": n_dist * DIM * 4 + n_exp * DEGREE * 4}), flush=True)
+                          "alg_bytes": n_dist * per + n_exp * DEGREE * 4 + rescore}), flush=True)
         return
     kth = exact_kth(torch, base_t, q_t, K)
     torch.cuda.synchronize()
@@ -468,7 +475,7 @@ def main():
     # algorithmic bytes: count distance evaluations with the largest visited
     # table (results are identical; it re-evaluates the fewest vectors)
     slots = ix.get_option("visited_slots")
-    ix.set_option("visited_slots", 8192)
+    ix.set_option("visited_slots", 16384)
     run_search(torch, ix, q_t, beam, bufs)
     torch.cuda.synchronize()
     n_dist = int(bufs[2].sum().item())

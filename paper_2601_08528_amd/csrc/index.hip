@@ -966,7 +966,8 @@ int svf_set_option(svf_index* ix, const char* key, double v) {
     o.max_iters = (int)v;
   } else if (k == "visited_slots") {
     int t = (int)v;
-    if (!is_int(v) || t < 256 || t > 8192 || (t & (t - 1))) return fail(SVF_E_INVAL, "visited_slots: power of two in [256, 8192]");
+    if (!is_int(v) || t < 256 || t > 16384 || (t & (t - 1)))
+      return fail(SVF_E_INVAL, "visited_slots: power of two in [256, 16384]");
     o.visited_slots = t;
   } else if (k == "visited_compact") {
     if (v != 0 && v != 1) return fail(SVF_E_INVAL, "visited_compact 0 or 1");

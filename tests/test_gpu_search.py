@@ -83,7 +83,7 @@ def test_search_ragged_shapes_inner_product():
 def test_visited_table_size_does_not_change_results(int_l2):
     oix, base, q = int_l2
     ref = None
-    for slots, compact in ((256, 0), (256, 1), (2048, 1), (2048, 0), (8192, 1)):
+    for slots, compact in ((256, 0), (256, 1), (2048, 1), (2048, 0), (8192, 1), (16384, 1)):
         g = gpu_from_oracle(oix, base, seed=11, visited_slots=slots, visited_compact=compact)
         gi, gd, gnd, gne = dev_search(g, q, 10, 128)
         if ref is None:
