@@ -122,6 +122,7 @@ int svf_destroy(svf_index *ix);
  *   model_min_iters smallest expansion cap of a gated query (>=1; 8)
  * Unknown key or out-of-range value: SVF_E_INVAL. */
 int svf_set_option(svf_index *ix, const char *key, double value);
+/* Any key above, plus the read-only "dim", "degree" and "metric". */
 int svf_get_option(const svf_index *ix, const char *key, double *value);
 
 /* Insert n vectors (n x dim row-major FP32, host memory) as one batch
@@ -278,6 +279,22 @@ int svf_export_graph(const svf_index *ix, int32_t *rows, float *edge_d, uint8_t 
  * implementations from one identical state. */
 int svf_import_graph(svf_index *ix, const float *vecs, int64_t n, const int32_t *rows,
                      const float *edge_d, const uint8_t *alive);
+
+/* Checkpoint to a file: the FP32 vectors, rows, edge distances, alive flags,
+ * deletion counters and the options that shape results (seed, beam_insert,
+ * entry_samples, max_iters, search_width, visited_slots, visited_compact,
+ * repair_c, prune_cap, consolidate_frac, insert_batch_max, precision,
+ * rerank).  Not saved: a fitted predictor, the tiered-store state and the
+ * serving loop (a loaded index starts without them).  Format: the 8 bytes
+ * "SVFIDX01", a fixed header, the arrays, then a 64-bit checksum of all that
+ * precedes it; little-endian.  Not while serving (SVF_E_BUSY); a file that
+ * cannot be written gives SVF_E_INTERNAL and may be left incomplete. */
+int svf_save(const svf_index *ix, const char *path);
+/* Resume from svf_save's file into a new handle (*out; NULL on failure).
+ * Missing file: SVF_E_NOTFOUND.  Wrong magic or version, truncation or a
+ * checksum mismatch: SVF_E_INVAL.  Search results equal those of the index
+ * that was saved. */
+int svf_load(const char *path, svf_index **out);
 
 /* Thread-local message of the last failing call on this thread. */
 const char *svf_last_error(void);

@@ -28,7 +28,7 @@ EXPORTED = [
     "svf_mlp_num_params", "svf_mlp_set_params", "svf_mlp_get_params", "svf_mlp_forward",
     "svf_mlp_loss_grad", "svf_mlp_train", "svf_mlp_last_error",
     "svf_serve_start", "svf_serve_stop", "svf_submit_search", "svf_submit_insert",
-    "svf_submit_delete", "svf_wait",
+    "svf_submit_delete", "svf_wait", "svf_save", "svf_load",
 ]
 
 
@@ -87,6 +87,8 @@ def lib():
         L.svf_stats_get.argtypes = [vp, C.POINTER(Stats)]
         L.svf_export_graph.argtypes = [vp, vp, vp, vp, i64]
         L.svf_import_graph.argtypes = [vp, vp, i64, vp, vp, vp]
+        L.svf_save.argtypes = [vp, C.c_char_p]
+        L.svf_load.argtypes = [C.c_char_p, C.POINTER(vp)]
         L.svf_search_listed.argtypes = [vp, vp, i64, i32, i32, vp, i32, vp, vp, vp]
         L.svf_model_fit.argtypes = [vp, vp, i64, i32, i32, i32, i32, C.POINTER(C.c_float)]
         L.svf_mlp_create.argtypes = [i32, i32, i32, C.c_uint64, C.POINTER(vp)]
@@ -258,6 +260,20 @@ class Index:
         alive = np.empty(n, np.uint8)
         _check(lib().svf_export_graph(self.h, _p(rows), _p(ed), _p(alive), n))
         return rows, ed, alive
+
+    def save(self, path: str):
+        """Checkpoint to a file (``svf_save``)."""
+        _check(lib().svf_save(self.h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, path: str) -> "Index":
+        """A new handle resumed from ``save``'s file (``svf_load``)."""
+        h = C.c_void_p()
+        _check(lib().svf_load(os.fsencode(path), C.byref(h)))
+        ix = cls.__new__(cls)
+        ix.h = h
+        ix.dim, ix.degree, ix.metric = (int(ix.get_option(k)) for k in ("dim", "degree", "metric"))
+        return ix
 
     def import_graph(self, vecs, rows, edge_d, alive):
         v = np.ascontiguousarray(vecs, dtype=np.float32).reshape(-1, self.dim)

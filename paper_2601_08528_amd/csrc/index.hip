@@ -1034,6 +1034,9 @@ int svf_get_option(const svf_index* ix, const char* key, double* out) {
   std::string k(key);
   const svf::Options& o = ix->opt;
   if (k == "seed") *out = (double)o.seed;
+  else if (k == "dim") *out = ix->dim;
+  else if (k == "degree") *out = ix->R;
+  else if (k == "metric") *out = ix->metric;
   else if (k == "beam_insert") *out = beam_insert(ix);
   else if (k == "entry_samples") *out = o.entry_samples;
   else if (k == "max_iters") *out = o.max_iters;
