@@ -200,6 +200,33 @@ def serving_bench(svf, datagen, n_build=5_000_000, rounds=60, rates=(60.0, 240.0
             "build_s": round(build_s, 2), "loads": loads}
 
 
+def small_batch_bench(torch, ix, q_t, base_t, kth, beam, reps=30):
+    """Latency of small batches (1..1024 queries) of the plain FP32 search at
+    one beam: one parent per iteration, four parents with one wave per query,
+    and four parents with one wave per parent (the waves of a query sharing
+    its pool).  Recall@10 over the batch's queries."""
+    out = []
+    for nb in (1, 16, 128, 1024):
+        qb = q_t[:nb]
+        bufs = (torch.empty((nb, K), dtype=torch.int32, device="cuda"),
+                torch.empty((nb, K), dtype=torch.float32, device="cuda"),
+                torch.empty(nb, dtype=torch.int32, device="cuda"),
+                torch.empty(nb, dtype=torch.int32, device="cuda"))
+        row = {"batch": nb}
+        for name, width, coop in (("w1", 1, 0), ("w4_one_wave", 4, 0), ("w4_wave_per_parent", 4, 1 << 20)):
+            ix.set_option("search_width", width)
+            ix.set_option("coop_max_batch", coop)
+            ms, _ = timed_steps(torch, ix, qb, beam, bufs, reps, 3)
+            rec = recall(torch, base_t, qb, bufs[0], kth[:nb])
+            row[name] = {"ms": round(float(np.median(ms)), 4), "recall@10": round(rec, 4),
+                         "n_exp_per_query": round(float(bufs[3].double().mean()), 1)}
+        out.append(row)
+    ix.set_option("search_width", 1)
+    ix.set_option("coop_max_batch", 1024)
+    return {"workload": "1M x 128 integer-valued GMM, L2, degree 64, plain FP32, beam %d" % beam,
+            "batches": out}
+
+
 def exact_kth_ip(torch, base_t, q_t, k, extra=64, chunk=64):
     """Exact k-th smallest -<q,x> per query: FP32 GEMM screening of all base
     vectors, then FP64 re-evaluation of the best k+extra."""
@@ -484,6 +511,8 @@ def main():
     ms_step = float(np.mean(ms))
     achieved = alg_bytes / (ms_step / 1e3) / 1e9
     qps = nq / (ms_step / 1e3)
+    log("small batches")
+    small = small_batch_bench(torch, ix, q_t, base_t, kth, beam)
 
     # reduced-precision forms: BF16 or FP8 traversal + exact FP32 re-score
     lowp = {}
@@ -622,6 +651,7 @@ def main():
                                                                "ins_reverse_ms", "ins_commit_ms",
                                                                "del_mark_ms", "del_repair_ms")},
                    "repaired_rows": st["last_repaired"]},
+        "small_batches": small,
         "large_footprint": large,
         "tiered": tier,
         "serving": serving,

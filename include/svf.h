@@ -91,6 +91,10 @@ int svf_destroy(svf_index *ix);
  *   entry_samples   random entry points per query, 0 = the pool size (0..1024; 0)
  *   max_iters       cap on iterations per query, 0 = none (>= 0; 0)
  *   search_width    parents expanded per iteration (1..4; 1)
+ *   coop_max_batch  with search_width 2 or 4, batches of at most this many queries run
+ *                   one wave per parent, the waves of a query sharing its pool (results
+ *                   unchanged; FP32/BF16/FP8, degree <= 64, dim <= 256, untiered)
+ *                   (0..2^24; 1024; 0 = never)
  *   visited_slots   LDS visited-table slots per query, power of two (256..16384; 4096)
  *   visited_compact 16-bit visited tags in 4-way sets when the ids fit (0/1; 1)
  *   repair_c        out-neighbours taken from each deleted neighbour (1..min(16, degree); 8)

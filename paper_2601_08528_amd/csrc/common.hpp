@@ -67,7 +67,22 @@ __device__ __forceinline__ uint64_t wave_sort64(uint64_t key) {
   return key;
 }
 
+// Ordering of LDS traffic between the lanes of one wave.  A kernel whose
+// workgroup is one wave uses the workgroup barrier; code run by one wave of a
+// larger workgroup uses a wavefront-scope fence (a wave's LDS operations are
+// performed in order; the fence keeps the compiler from moving them).
+struct BlockSync {
+  __device__ static __forceinline__ void sync() { __syncthreads(); }
+};
+struct WaveSync {
+  __device__ static __forceinline__ void sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+};
+
 // Ascending bitonic sort of n (power of two, >= 64) keys in LDS by one wave.
+template <class S = BlockSync>
 __device__ inline void wave_sort_lds(uint64_t* a, int n) {
   const int lane = lane_id();
   for (int k = 2; k <= n; k <<= 1) {
@@ -80,7 +95,7 @@ __device__ inline void wave_sort_lds(uint64_t* a, int n) {
           if ((x > y) == up) { a[i] = y; a[p] = x; }
         }
       }
-      __syncthreads();
+      S::sync();
     }
   }
 }

@@ -224,6 +224,7 @@ void set_beam(svf::SearchArgs& a, const svf_index* ix, int L) {
   a.rerank = (ix->veclp_prec != 0 && ix->opt.rerank) ? 1 : 0;
   a.vis_compact = ix->opt.visited_compact;
   a.width = ix->opt.search_width;
+  a.coop_max_nq = ix->opt.coop_max_batch;
 }
 
 // Milliseconds between two recorded events, 0 when they cannot be timed.  A
@@ -955,6 +956,9 @@ int svf_set_option(svf_index* ix, const char* key, double v) {
   } else if (k == "beam_insert") {
     if (!is_int(v) || v < ix->R || v > kMaxBeam) return fail(SVF_E_INVAL, "beam_insert in [degree, 512]");
     o.beam_insert = (int)v;
+  } else if (k == "coop_max_batch") {
+    if (!is_int(v) || v < 0 || v > (1 << 24)) return fail(SVF_E_INVAL, "coop_max_batch in [0, 2^24]");
+    o.coop_max_batch = (int)v;
   } else if (k == "entry_samples") {
     if (!is_int(v) || v < 0 || v > kMaxEntries) return fail(SVF_E_INVAL, "entry_samples in [0, 1024]");
     o.entry_samples = (int)v;
@@ -1039,6 +1043,7 @@ int svf_get_option(const svf_index* ix, const char* key, double* out) {
   else if (k == "metric") *out = ix->metric;
   else if (k == "beam_insert") *out = beam_insert(ix);
   else if (k == "entry_samples") *out = o.entry_samples;
+  else if (k == "coop_max_batch") *out = o.coop_max_batch;
   else if (k == "max_iters") *out = o.max_iters;
   else if (k == "search_width") *out = o.search_width;
   else if (k == "visited_slots") *out = o.visited_slots;

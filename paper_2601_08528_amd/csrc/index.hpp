@@ -41,6 +41,7 @@ struct Options {
   int entry_samples = 0;
   int max_iters = 0;
   int search_width = 1;
+  int coop_max_batch = 1024;
   int visited_slots = 4096;
   int visited_compact = 1;
   int repair_c = 8;

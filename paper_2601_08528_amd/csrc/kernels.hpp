@@ -22,6 +22,8 @@ struct SearchArgs {
   // search parameters
   int L, L_pow2, k, E, max_iters, T, rerank;
   int width;                // parents expanded per iteration (1..4)
+  int coop_max_nq;          // batches up to this size run width 2 or 4 with one wave per
+                            // parent (0: never)
   int vis_compact;          // allow 16-bit visited tags when ids fit
   int id_bits;              // set by the launcher
   // queries
@@ -53,6 +55,9 @@ struct SearchArgs {
 };
 
 hipError_t launch_search(const SearchArgs& a, int precision, hipStream_t st);
+bool coop_eligible(const SearchArgs& a, int precision, int nc);
+hipError_t launch_search_coop(const SearchArgs& a, int precision, int nc, bool tags, size_t vis,
+                              hipStream_t st);
 hipError_t launch_query_keys(const float* q, int64_t qstride, const int32_t* qids, int dim, int nq,
                              uint64_t seed, uint64_t* out, hipStream_t st);
 

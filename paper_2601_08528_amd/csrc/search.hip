@@ -353,6 +353,9 @@ hipError_t launch_search(const SearchArgs& in, int precision, hipStream_t st) {
   if (a.id_bits < set_bits + 1) a.id_bits = set_bits + 1;
   int Lp = 64;
   while (Lp < a.L) Lp <<= 1;
+  a.L_pow2 = Lp;
+  if (coop_eligible(a, precision, nc))
+    return launch_search_coop(a, precision, nc, assoc, vis_bytes(a.T, assoc), st);
   const size_t lds = (size_t)2 * Lp * 8 + kWave * 8 + 2 * kWave * 4 + vis_bytes(a.T, assoc);
   return assoc ? launch_vis<VisTags>(a, precision, nc, lds, st)
                : launch_vis<VisLinear32>(a, precision, nc, lds, st);

@@ -315,6 +315,7 @@ __device__ inline uint64_t gather_keys(const QuerySlice<VT, NC>& qs, const VT* _
 // Merge one sorted key per lane (kKeyInf padded) into the sorted pool of L
 // keys, keeping the L smallest; keys equal in (dist,id) to a pool entry are
 // dropped (the pool entry keeps its expanded flag).
+template <class S = BlockSync>
 __device__ inline bool merge_into_pool(WaveCtx& w, uint64_t nk) {
   const int lane = lane_id();
   const int L = w.L;
@@ -336,7 +337,7 @@ __device__ inline bool merge_into_pool(WaveCtx& w, uint64_t nk) {
   const int r = lanes_below(kb);
   const int mk = popc64(kb);
   if (keep) w.kept[r] = nk;
-  __syncthreads();
+  S::sync();
   if (mk == 0) return false;
   const bool topk = ballot(keep && r + lo < w.ktrack) != 0;
   if (keep && r + lo < L) w.next[r + lo] = nk;
@@ -350,7 +351,7 @@ __device__ inline bool merge_into_pool(WaveCtx& w, uint64_t nk) {
     }
     if (i + a < L) w.next[i + a] = pk;
   }
-  __syncthreads();
+  S::sync();
   uint64_t* t = w.pool; w.pool = w.next; w.next = t;
   return topk;
 }
@@ -376,6 +377,7 @@ __device__ __forceinline__ uint64_t wave_sort_width(uint64_t key, int W) {
 // Merge one unsorted key per lane (kKeyInf = none) into the pool: keys that
 // cannot enter a full pool are dropped first, the rest are compacted and
 // sorted over the narrowest power-of-two width, then merged.
+template <class S = BlockSync>
 __device__ inline bool sort_merge(WaveCtx& w, uint64_t k) {
   const int lane = lane_id();
   const uint64_t last = w.pool[w.L - 1];
@@ -383,15 +385,15 @@ __device__ inline bool sort_merge(WaveCtx& w, uint64_t k) {
   const uint64_t lb = ballot(live);
   const int s = popc64(lb);
   if (s == 0) return false;
-  __syncthreads();
+  S::sync();
   if (live) w.kept[lanes_below(lb)] = k;
-  __syncthreads();
+  S::sync();
   uint64_t c = lane < s ? w.kept[lane] : kKeyInf;
   int W = 1;
   while (W < s) W <<= 1;
   c = wave_sort_width(c, W);
-  __syncthreads();
-  return merge_into_pool(w, c);
+  S::sync();
+  return merge_into_pool<S>(w, c);
 }
 
 }  // namespace svf

@@ -50,11 +50,14 @@ def test_search_bit_exact_integer_l2(int_l2, beam):
     np.testing.assert_array_equal(hi, oi)
 
 
+@pytest.mark.parametrize("coop", [0, 1024])
 @pytest.mark.parametrize("width", [2, 4])
-def test_search_width_bit_exact(int_l2, width):
-    """Several parents per iteration (a method option the oracle implements)."""
+def test_search_width_bit_exact(int_l2, width, coop):
+    """Several parents per iteration (a method option the oracle implements),
+    with one wave per query (coop 0) and with one wave per parent (coop 1024:
+    the 157-query batch runs the cooperative kernel)."""
     oix, base, q = int_l2
-    g = gpu_from_oracle(oix, base, seed=11, search_width=width)
+    g = gpu_from_oracle(oix, base, seed=11, search_width=width, coop_max_batch=coop)
     oix.set("search_width", width)
     try:
         oi, od, ost = oix.search(q, 10, 64)
@@ -177,3 +180,35 @@ def test_stats_before_any_search_leave_no_error():
     gi, gd = g.search(q, 5, 16)
     oi, od, _ = oix.search(q, 5, 16)
     np.testing.assert_array_equal(gi, oi)
+
+
+@pytest.mark.parametrize("width", [2, 4])
+def test_cooperative_search_shapes_and_forms(width):
+    """One wave per parent on: the inner product at dim 200 (two chunks, ragged)
+    with degree 48, deleted vertices, odd beams, and the BF16 and FP8 forms on
+    data exact on their grids; every case bit-exact against the oracle."""
+    base, q = datagen.gmm_uint8_valued(204, 2500, 67, 200, 9)
+    oix = oracle_index(base, 48, metric=O.IP, seed=3)
+    oix.delete(np.arange(5, 2500, 13, dtype=np.int32))
+    oix.set("search_width", width)
+    g = gpu_from_oracle(oix, base, seed=3, search_width=width, coop_max_batch=4096)
+    for beam in (17, 100):
+        oi, od, ost = oix.search(q, 7, beam)
+        gi, gd, _, gne = dev_search(g, q, 7, beam)
+        np.testing.assert_array_equal(gi, oi)
+        np.testing.assert_array_equal(gd.astype(np.float64), od)
+        np.testing.assert_array_equal(gne, ost["n_exp"])
+    base8, q8 = datagen.gmm_fp8_exact_valued(205, 3000, 50, 64, 8)
+    o8 = oracle_index(base8, 24, seed=4)
+    o8.set("search_width", width)
+    for prec, oprec in ((svf.PREC_BF16, O.P_BF16), (svf.PREC_FP8, O.P_FP8)):
+        o8.set("precision", oprec)
+        g8 = gpu_from_oracle(o8, base8, seed=4, search_width=width, coop_max_batch=4096,
+                             precision=prec)
+        for rr in (0, 1):
+            g8.set_option("rerank", rr)
+            oi, od, ost = o8.search(q8, 10, 48, rerank=bool(rr))
+            gi, gd, _, gne = dev_search(g8, q8, 10, 48)
+            np.testing.assert_array_equal(gi, oi)
+            np.testing.assert_array_equal(gd.astype(np.float64), od)
+            np.testing.assert_array_equal(gne, ost["n_exp"])
