@@ -72,6 +72,7 @@ def lib():
         L.orc_query_dists.argtypes = [vp, vp, i64, i32, vp, vp]
         L.orc_search_expansions.argtypes = [vp, vp, i64, i32, vp, i32, vp]
         L.orc_wavp_replay.argtypes = [i64, i64, vp, vp, vp, vp, i32, f64, f64, f64, i32, i32, vp, vp]
+        L.orc_policy_replay.argtypes = [i32, i64, i64, vp, vp, vp, vp, i32, i32, i32, vp, vp]
         L.orc_search_listed.argtypes = [vp, vp, i64, i32, i32, vp, i32, vp, vp, vp, vp]
         L.orc_search_trace.argtypes = [vp, vp, i64, i32, i32, vp, vp]
         L.orc_mlp_forward.argtypes = [i32, i32, i32] + [vp] * 6 + [vp, i64, vp]
@@ -312,4 +313,23 @@ def wavp_replay(n, C, e_in, alive, batches, alpha=0.6, beta=0.4, theta=1.0, prom
     slots = np.empty(max(C, 1), np.int32)
     lib().orc_wavp_replay(n, C, _p(e), _p(a), _p(flat), _p(off), len(batches), alpha, beta, theta,
                           promote_max, int(warm), _p(hits), _p(slots))
+    return hits, slots[:C]
+
+
+POLICY_WAVP, POLICY_LRU, POLICY_LFU, POLICY_LRFU = 0, 1, 2, 3
+
+
+def policy_replay(policy, n, C, e_in, alive, batches, promote_max=2048, warm=False):
+    """The classic replacement policies (LRU, LFU, LRFU) in the batched form
+    over per-batch access traces; returns (hits per batch, final slot table)."""
+    e = np.ascontiguousarray(e_in, dtype=np.int32)
+    a = np.ascontiguousarray(alive, dtype=np.uint8)
+    flat = np.ascontiguousarray(np.concatenate([np.asarray(b, np.int32) for b in batches])
+                                if batches else np.zeros(0, np.int32), dtype=np.int32)
+    off = np.zeros(len(batches) + 1, np.int64)
+    off[1:] = np.cumsum([len(b) for b in batches])
+    hits = np.empty(len(batches), np.int64)
+    slots = np.empty(max(C, 1), np.int32)
+    lib().orc_policy_replay(policy, n, C, _p(e), _p(a), _p(flat), _p(off), len(batches),
+                            promote_max, int(warm), _p(hits), _p(slots))
     return hits, slots[:C]

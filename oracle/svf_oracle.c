@@ -1414,3 +1414,91 @@ void orc_wavp_replay(int64_t n, int64_t C, const int32_t *e_in, const uint8_t *a
 #undef FLAM
     free(fr); free(where); free(ref); free(cand_mark); free(cand);
 }
+
+/* ------------------------------------------------------------------------ */
+/* The classic replacement policies the paper compares WAVP with (Sec. 6,
+ * replacement strategies), in the same batched form over the same traces:
+ *   LRU (policy 1): score = last access, ordered by (batch, position in the
+ *     batch's trace);
+ *   LFU (policy 2): score = number of accesses so far;
+ *   LRFU (policy 3): score = F_recent, the access count halved once per
+ *     batch (combined recency and frequency with one halving per batch).
+ * Per batch: accesses are counted (hits as for WAVP); the distinct missed
+ * vertices, best score first (ties by id), at most promote_max of them, are
+ * each placed into a free slot or in place of the resident vertex of lowest
+ * score (ties by id), which is always evicted.  warm: as in orc_wavp_replay. */
+void orc_policy_replay(int policy, int64_t n, int64_t C, const int32_t *e_in, const uint8_t *alive,
+                       const int32_t *trace, const int64_t *off, int nb, int promote_max, int warm,
+                       int64_t *hits, int32_t *slot_id)
+{
+    double *fr = calloc(n > 0 ? n : 1, sizeof(double));
+    int64_t *freq = calloc(n > 0 ? n : 1, sizeof(int64_t));
+    int64_t *last = malloc(sizeof(int64_t) * (n > 0 ? n : 1));
+    int32_t *where = malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+    uint8_t *mark = calloc(n > 0 ? n : 1, 1);
+    for (int64_t i = 0; i < n; ++i) { where[i] = -1; last[i] = -1; }
+    for (int64_t s = 0; s < C; ++s) slot_id[s] = -1;
+    int64_t used = 0;
+    if (warm) {
+        uint8_t *taken = calloc(n > 0 ? n : 1, 1);
+        while (used < C) {
+            int64_t best = -1;
+            for (int64_t x = 0; x < n; ++x) {
+                if (!alive[x] || taken[x]) continue;
+                if (best < 0 || e_in[x] > e_in[best]) best = x;
+            }
+            if (best < 0) break;
+            taken[best] = 1;
+            slot_id[used] = (int32_t)best; where[best] = (int32_t)used; ++used;
+        }
+        free(taken);
+    }
+    int64_t maxlen = 0;
+    for (int b = 0; b < nb; ++b) if (off[b + 1] - off[b] > maxlen) maxlen = off[b + 1] - off[b];
+    int32_t *cand = malloc(sizeof(int32_t) * (maxlen + 1));
+    /* a < b in the policy's order of importance (a less important) */
+#define SCORE_LESS(a, b) \
+    (policy == 1 ? last[(a)] < last[(b)] : \
+     policy == 2 ? (freq[(a)] < freq[(b)] || (freq[(a)] == freq[(b)] && (a) > (b))) : \
+                   (fr[(a)] < fr[(b)] || (fr[(a)] == fr[(b)] && (a) > (b))))
+    for (int b = 0; b < nb; ++b) {
+        for (int64_t i = 0; i < n; ++i) fr[i] *= 0.5;
+        int64_t h = 0;
+        for (int64_t t = off[b]; t < off[b + 1]; ++t) {
+            int32_t x = trace[t];
+            fr[x] += 1.0;
+            freq[x] += 1;
+            last[x] = ((int64_t)b << 40) + (t - off[b]);
+            if (where[x] >= 0) ++h;
+        }
+        hits[b] = h;
+        int nc = 0;
+        for (int64_t t = off[b]; t < off[b + 1]; ++t) {
+            int32_t x = trace[t];
+            if (where[x] >= 0 || mark[x]) continue;
+            mark[x] = 1;
+            cand[nc++] = x;
+        }
+        for (int i = 0; i < nc; ++i) mark[cand[i]] = 0;
+        /* most important first */
+        for (int i = 1; i < nc; ++i) {
+            int32_t c = cand[i];
+            int j = i - 1;
+            while (j >= 0 && SCORE_LESS(cand[j], c)) { cand[j + 1] = cand[j]; --j; }
+            cand[j + 1] = c;
+        }
+        if (nc > promote_max) nc = promote_max;
+        for (int i = 0; i < nc; ++i) {
+            int32_t x = cand[i];
+            if (used < C) { slot_id[used] = x; where[x] = (int32_t)used; ++used; continue; }
+            if (C == 0) break;
+            int64_t vs = 0;
+            for (int64_t s2 = 1; s2 < C; ++s2)
+                if (SCORE_LESS(slot_id[s2], slot_id[vs])) vs = s2;
+            where[slot_id[vs]] = -1;
+            slot_id[vs] = x; where[x] = (int32_t)vs;
+        }
+    }
+#undef SCORE_LESS
+    free(fr); free(freq); free(last); free(where); free(mark); free(cand);
+}

@@ -153,3 +153,28 @@ def test_expansion_trace_matches_search(idx):
     for i in range(q.shape[0]):
         t = tr[i, :cnt[i]]
         assert len(set(t.tolist())) == len(t)        # each vertex expanded once
+
+
+def test_classic_policies_hand_worked():
+    """LRU, LFU and LRFU in the batched form, worked by hand."""
+    ones = lambda n: np.ones(n, np.uint8)
+    # LRU, two slots: batch 0 admits 2, 1, then 0 evicts 1 (oldest of 2 and 1);
+    # batch 1 admits 3 (evicts 0) and 1 (evicts 2)
+    h, s = O.policy_replay(O.POLICY_LRU, 6, 2, [0] * 6, ones(6), [[0, 1, 2], [1, 3]])
+    assert h.tolist() == [0, 0] and s.tolist() == [1, 3]
+    # LFU: 0 (2 accesses) and 1 (1) fill the slots; in batch 1 vector 1 hits
+    # once, both have 2 accesses and the larger id (1) goes for 2
+    h, s = O.policy_replay(O.POLICY_LFU, 3, 2, [0] * 3, ones(3), [[0, 0, 1], [2, 2, 2, 1]])
+    assert h.tolist() == [0, 1] and s.tolist() == [0, 2]
+    # recency against recency-frequency on one stream: LRU admits 4 (latest)
+    # before 5 and later evicts 5 (accessed earlier in batch 0); LRFU admits 5
+    # (F_recent 3) before 4 and evicts 4 (F_recent 0.5 against 1.5)
+    tr = [[5, 5, 5, 4], [6]]
+    h, s = O.policy_replay(O.POLICY_LRU, 7, 2, [0] * 7, ones(7), tr)
+    assert s.tolist() == [4, 6]
+    h, s = O.policy_replay(O.POLICY_LRFU, 7, 2, [0] * 7, ones(7), tr)
+    assert s.tolist() == [5, 6]
+    # promote_max 0: nothing moves after the warm start
+    h, s = O.policy_replay(O.POLICY_LRU, 7, 2, [3, 9, 1, 0, 0, 0, 0], ones(7), tr, promote_max=0,
+                           warm=True)
+    assert s.tolist() == [1, 0] and h.tolist() == [0, 0]
