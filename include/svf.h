@@ -120,6 +120,9 @@ int svf_destroy(svf_index *ix);
  *   cache_alpha_ratio alpha / (alpha + beta) of F_lambda, alpha + beta = 1 ([0,1]; 0.6)
  *   cache_promote_max placements per query batch (>= 0; 2048)
  *   cache_trace_cap expansions per query recorded for placement (16..8192; 512)
+ *   cache_policy    placement policy: 0 workload-aware (Alg. 2), or one of the classic
+ *                   policies the paper compares it with, in the same batched form:
+ *                   1 LRU, 2 LFU, 3 LRFU (0..3; 0)
  *   use_model       learned entry points and stopping step (0/1; 0; needs svf_model_fit)
  *   model_conf      softmax confidence below which a query falls back to plain search ([0,1]; 0.5)
  *   model_stop_scale expansion cap = ceil(scale * predicted stop step) (>0; 1.5)

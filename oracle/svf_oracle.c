@@ -1419,7 +1419,7 @@ void orc_wavp_replay(int64_t n, int64_t C, const int32_t *e_in, const uint8_t *a
 /* The classic replacement policies the paper compares WAVP with (Sec. 6,
  * replacement strategies), in the same batched form over the same traces:
  *   LRU (policy 1): score = last access, ordered by (batch, position in the
- *     batch's trace);
+ *     batch's trace); vectors never accessed (a warm start) tie at the bottom;
  *   LFU (policy 2): score = number of accesses so far;
  *   LRFU (policy 3): score = F_recent, the access count halved once per
  *     batch (combined recency and frequency with one halving per batch).
@@ -1458,7 +1458,7 @@ void orc_policy_replay(int policy, int64_t n, int64_t C, const int32_t *e_in, co
     int32_t *cand = malloc(sizeof(int32_t) * (maxlen + 1));
     /* a < b in the policy's order of importance (a less important) */
 #define SCORE_LESS(a, b) \
-    (policy == 1 ? last[(a)] < last[(b)] : \
+    (policy == 1 ? (last[(a)] < last[(b)] || (last[(a)] == last[(b)] && (a) > (b))) : \
      policy == 2 ? (freq[(a)] < freq[(b)] || (freq[(a)] == freq[(b)] && (a) > (b))) : \
                    (fr[(a)] < fr[(b)] || (fr[(a)] == fr[(b)] && (a) > (b))))
     for (int b = 0; b < nb; ++b) {

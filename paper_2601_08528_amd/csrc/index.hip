@@ -110,6 +110,8 @@ int reserve(svf_index* ix, int64_t need) {
     ix->tier.where.resize(cap, -1);
     ix->tier.fr.resize(cap, 0.0);
     ix->tier.fr_stamp.resize(cap, 0);
+    ix->tier.freq.resize(cap, 0);
+    ix->tier.last.resize(cap, -1);
   } else {
     CK(svf::launch_fill_u32(v32, cap * ix->stride, 0u, st));
   }
@@ -652,16 +654,40 @@ int tier_refresh_indegree(svf_index* ix, hipStream_t st) {
   return SVF_OK;
 }
 
+// Move a batch's placements (slot, new id, evicted id or -1, in decision
+// order) to the device.  A slot can change hands more than once in a batch
+// (a vector placed early in the batch evicted by a later one), and the
+// placement kernel runs all entries at once, so the list is first reduced to
+// one entry per slot: the occupant at the start of the batch leaves, the
+// last one placed arrives; vectors placed and evicted within the batch never
+// reach the device map.
 int tier_apply(svf_index* ix, const std::vector<int32_t>& place, hipStream_t st) {
   svf::TierState& T = ix->tier;
   const int np = (int)(place.size() / 3);
   T.last_placed = np;
   if (np == 0) return SVF_OK;
+  std::vector<int32_t> net;
+  net.reserve(place.size());
+  std::vector<std::pair<int32_t, int32_t>> idx;   // (slot, position in net)
+  idx.reserve(np);
+  for (int p = 0; p < np; ++p) idx.emplace_back(place[3 * p], p);
+  std::stable_sort(idx.begin(), idx.end(),
+                   [](const std::pair<int32_t, int32_t>& a, const std::pair<int32_t, int32_t>& b) {
+                     return a.first < b.first;
+                   });
+  for (size_t i = 0; i < idx.size();) {
+    size_t j = i;
+    while (j + 1 < idx.size() && idx[j + 1].first == idx[i].first) ++j;
+    const int first = idx[i].second, lastp = idx[j].second;
+    net.insert(net.end(), {place[3 * first], place[3 * lastp + 1], place[3 * first + 2]});
+    i = j + 1;
+  }
+  const int nn = (int)(net.size() / 3);
   int32_t* d;
-  int rc = scratch(T.place, place.size(), &d);
+  int rc = scratch(T.place, net.size(), &d);
   if (rc) return rc;
-  CK(hipMemcpyAsync(d, place.data(), place.size() * 4, hipMemcpyHostToDevice, st));
-  CK(svf::launch_place(d, np, ix->vec32, T.cache, ix->stride, T.map, st));
+  CK(hipMemcpyAsync(d, net.data(), net.size() * 4, hipMemcpyHostToDevice, st));
+  CK(svf::launch_place(d, nn, ix->vec32, T.cache, ix->stride, T.map, st));
   CK(hipStreamSynchronize(st));
   return SVF_OK;
 }
@@ -691,35 +717,109 @@ double fr_now(const svf::TierState& T, int32_t x) {
   return halve_times(T.fr[x], T.batch - T.fr_stamp[x]);
 }
 
+// The classic replacement policies (LRU, LFU, LRFU) in the batched form: the
+// batch's missed vertices, most important first (ties by id), at most
+// promote_max, each take a free slot or the slot of the least important
+// resident vertex, which is always evicted.  Importance: last access (LRU),
+// accesses so far (LFU), F_recent (LRFU); scores do not change while a
+// batch is placed, so the least important resident comes off a heap.
+int tier_place_classic(svf_index* ix, std::vector<std::pair<double, int32_t>>& cand,
+                       hipStream_t st) {
+  svf::TierState& T = ix->tier;
+  const int pol = T.policy;
+  std::vector<double> frb;
+  auto less = [&](int32_t a, int32_t b) -> bool {   // a less important than b
+    if (pol == 1) return T.last[a] < T.last[b] || (T.last[a] == T.last[b] && a > b);
+    if (pol == 2) return T.freq[a] < T.freq[b] || (T.freq[a] == T.freq[b] && a > b);
+    const double fa = fr_now(T, a), fb = fr_now(T, b);
+    return fa < fb || (fa == fb && a > b);
+  };
+  std::vector<int32_t> order;
+  order.reserve(cand.size());
+  for (const auto& c : cand) order.push_back(c.second);
+  auto more = [&](int32_t a, int32_t b) { return less(b, a); };
+  if ((int64_t)order.size() > T.promote_max) {
+    std::nth_element(order.begin(), order.begin() + T.promote_max, order.end(), more);
+    order.resize(T.promote_max);
+  }
+  std::sort(order.begin(), order.end(), more);
+  // heap of the resident vertices, least important on top
+  std::vector<int32_t> heap;
+  const bool evicting = T.used + (int64_t)order.size() > T.C;
+  if (evicting) {
+    heap.reserve(T.used + order.size());
+    for (int64_t s_ = 0; s_ < T.used; ++s_) heap.push_back(T.slot_id[s_]);
+    std::make_heap(heap.begin(), heap.end(), more);
+  }
+  std::vector<int32_t> place;
+  for (const int32_t x : order) {
+    if (T.used < T.C) {
+      const int64_t slot = T.used++;
+      T.slot_id[slot] = x;
+      T.where[x] = (int32_t)slot;
+      T.ref[slot] = 0;
+      place.insert(place.end(), {(int32_t)slot, x, -1});
+      if (evicting) {
+        heap.push_back(x);
+        std::push_heap(heap.begin(), heap.end(), more);
+      }
+      continue;
+    }
+    if (T.C == 0) break;
+    std::pop_heap(heap.begin(), heap.end(), more);
+    const int32_t y = heap.back();
+    heap.pop_back();
+    const int32_t s_ = T.where[y];
+    T.where[y] = -1;
+    T.slot_id[s_] = x;
+    T.where[x] = s_;
+    T.ref[s_] = 0;
+    place.insert(place.end(), {s_, x, y});
+    ++T.evictions;
+    heap.push_back(x);
+    std::push_heap(heap.begin(), heap.end(), more);
+  }
+  T.promotions += place.size() / 3;
+  return tier_apply(ix, place, st);
+}
+
 int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
   svf::TierState& T = ix->tier;
   const int cap = T.trace_cap;
   const int64_t n = ix->n_slots;
   const int64_t words = (n + 31) / 32;
   // per-vertex access counts and the touched bitmap, counted on the GPU
-  int32_t* cnt_d;
+  const bool lru = T.policy == 1;
+  int32_t *cnt_d, *lastpos_d = nullptr;
   uint32_t* touched_d;
   int rc;
-  if ((rc = scratch(T.acc_cnt, n, &cnt_d)) || (rc = scratch(T.touched, words, &touched_d))) return rc;
+  if ((rc = scratch(T.acc_cnt, n, &cnt_d)) || (rc = scratch(T.touched, words, &touched_d)) ||
+      (lru && (rc = scratch(T.lastpos, n, &lastpos_d))))
+    return rc;
   if (T.host_n < n) {
     if (T.cnt_h) (void)hipHostFree(T.cnt_h);
     if (T.touched_h) (void)hipHostFree(T.touched_h);
+    if (T.lastpos_h) (void)hipHostFree(T.lastpos_h);
     T.cnt_h = nullptr;
     T.touched_h = nullptr;
+    T.lastpos_h = nullptr;
     T.host_n = 0;
     const int64_t hn = std::max<int64_t>(n, ix->cap);
     CK(hipHostMalloc((void**)&T.cnt_h, hn * 4, 0));
     CK(hipHostMalloc((void**)&T.touched_h, ((hn + 31) / 32) * 4, 0));
+    CK(hipHostMalloc((void**)&T.lastpos_h, hn * 4, 0));
     T.host_n = hn;
   }
   CK(svf::launch_fill_u32(cnt_d, n, 0u, st));
   CK(svf::launch_fill_u32(touched_d, words, 0u, st));
+  if (lru) CK(svf::launch_fill_u32(lastpos_d, n, 0xffffffffu, st));
   CK(svf::launch_trace_count(T.trace.as<int32_t>(), T.trace_n.as<int32_t>(), (int)nq, cap, cnt_d,
-                             touched_d, st));
+                             touched_d, lastpos_d, st));
   unsigned long long gcnt[2] = {0, 0};
   std::vector<uint32_t> bits(words + 1, 0u);
   CK(hipMemcpyAsync(T.cnt_h, cnt_d, n * 4, hipMemcpyDeviceToHost, st));
   CK(hipMemcpyAsync(T.touched_h, touched_d, words * 4, hipMemcpyDeviceToHost, st));
+  if (lru) CK(hipMemcpyAsync(T.lastpos_h, lastpos_d, n * 4, hipMemcpyDeviceToHost, st));
   CK(hipMemcpyAsync(gcnt, T.counts.p, sizeof gcnt, hipMemcpyDeviceToHost, st));
   CK(hipMemcpyAsync(bits.data(), ix->alive, words * 4, hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
@@ -745,16 +845,23 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
       for (int32_t t = 0; t < c; ++t) v += 1.0;
       T.fr[x] = v;
       T.fr_stamp[x] = T.batch;
+      T.freq[x] += c;
+      if (lru) T.last[x] = ((T.batch - 1) << 40) + T.lastpos_h[x];
       if (T.where[x] >= 0) {
         hits += c;
         T.ref[T.where[x]] = 1;
       } else if (alive(x)) {
-        const double f = T.alpha * v + lg(x);
-        if (f > T.theta) cand.emplace_back(f, x);
+        if (T.policy == 0) {
+          const double f = T.alpha * v + lg(x);
+          if (f > T.theta) cand.emplace_back(f, x);
+        } else {
+          cand.emplace_back(0.0, x);
+        }
       }
     }
   }
   T.last_trace_hits = hits;
+  if (T.policy != 0) return tier_place_classic(ix, cand, st);
   auto better = [](const std::pair<double, int32_t>& a, const std::pair<double, int32_t>& b) {
     return a.first > b.first || (a.first == b.first && a.second < b.second);
   };
@@ -876,6 +983,8 @@ int tier_enable(svf_index* ix, double bytes) {
   T.where.assign(ix->cap, -1);
   T.fr.assign(ix->cap, 0.0);
   T.fr_stamp.assign(ix->cap, 0);
+  T.freq.assign(ix->cap, 0);
+  T.last.assign(ix->cap, -1);
   T.on = true;
   return tier_warmup(ix, ix->stream);
 }
@@ -1003,6 +1112,9 @@ int svf_set_option(svf_index* ix, const char* key, double v) {
   } else if (k == "cache_promote_max") {
     if (!is_int(v) || v < 0 || v > (1 << 24)) return fail(SVF_E_INVAL, "cache_promote_max in [0, 2^24]");
     ix->tier.promote_max = (int)v;
+  } else if (k == "cache_policy") {
+    if (!is_int(v) || v < 0 || v > 3) return fail(SVF_E_INVAL, "cache_policy 0 (WAVP), 1 (LRU), 2 (LFU) or 3 (LRFU)");
+    ix->tier.policy = (int)v;
   } else if (k == "cache_trace_cap") {
     if (!is_int(v) || v < 16 || v > 8192) return fail(SVF_E_INVAL, "cache_trace_cap in [16, 8192]");
     ix->tier.trace_cap = (int)v;
@@ -1060,6 +1172,7 @@ int svf_get_option(const svf_index* ix, const char* key, double* out) {
   else if (k == "cache_alpha_ratio") *out = ix->tier.alpha;
   else if (k == "cache_promote_max") *out = ix->tier.promote_max;
   else if (k == "cache_trace_cap") *out = ix->tier.trace_cap;
+  else if (k == "cache_policy") *out = ix->tier.policy;
   else if (k == "model_conf") *out = o.model_conf;
   else if (k == "model_stop_scale") *out = o.model_stop_scale;
   else if (k == "model_min_iters") *out = o.model_min_iters;

@@ -76,17 +76,22 @@ struct TierState {
   std::vector<int64_t> fr_stamp;   // (the halvings of later batches are applied on use)
   std::vector<int32_t> e_in;       // in-degree per id
   int64_t used = 0, clock = 0, e_in_epoch = -1, batch = 0;
+  int policy = 0;                  // 0 workload-aware (WAVP), 1 LRU, 2 LFU, 3 LRFU
+  std::vector<int64_t> freq;       // LFU: accesses so far per id
+  std::vector<int64_t> last;       // LRU: last access, (batch << 40) + position, -1 never
   double alpha = 0.6, beta = 0.4, theta = 1.0;
   int promote_max = 2048, trace_cap = 512;
   uint64_t gather_hits = 0, gather_misses = 0, promotions = 0, evictions = 0;
   int64_t last_trace_hits = 0, last_placed = 0;
-  DevBuf trace, trace_n, place, counts, e_in_d, acc_cnt, touched;
-  int32_t* cnt_h = nullptr;        // pinned host mirrors of acc_cnt / touched
+  DevBuf trace, trace_n, place, counts, e_in_d, acc_cnt, touched, lastpos;
+  int32_t* cnt_h = nullptr;        // pinned host mirrors of acc_cnt / touched / lastpos
   uint32_t* touched_h = nullptr;
+  int32_t* lastpos_h = nullptr;
   int64_t host_n = 0;
   ~TierState() {
     if (cnt_h) (void)hipHostFree(cnt_h);
     if (touched_h) (void)hipHostFree(touched_h);
+    if (lastpos_h) (void)hipHostFree(lastpos_h);
   }
 };
 }  // namespace svf

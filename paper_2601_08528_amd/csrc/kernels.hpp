@@ -67,7 +67,7 @@ hipError_t launch_indegree(const int32_t* graph, const uint32_t* alive, int64_t 
 hipError_t launch_place(const int32_t* place, int np, const float* store, float* cache,
                         int64_t stride, int32_t* map, hipStream_t st);
 hipError_t launch_trace_count(const int32_t* trace, const int32_t* trace_n, int nq, int cap,
-                              int32_t* cnt, uint32_t* touched, hipStream_t st);
+                              int32_t* cnt, uint32_t* touched, int32_t* lastpos, hipStream_t st);
 
 // ---- index maintenance (update.hip) ----
 hipError_t launch_fill_u32(void* p, int64_t n, uint32_t v, hipStream_t st);

@@ -52,9 +52,13 @@ hipError_t launch_place(const int32_t* place, int np, const float* store, float*
 
 // Accesses of one batch: per-vertex counts and a bitmap of the vertices
 // touched, from the expansion traces (nq traces of at most cap entries).
+// Accesses of one batch: per-vertex counts, a bitmap of the vertices touched
+// and (when lastpos is given) each vertex's last position in the traces
+// taken in order (query, step), from nq traces of at most cap entries.
 __global__ void trace_count_kernel(const int32_t* __restrict__ trace,
                                    const int32_t* __restrict__ trace_n, int nq, int cap,
-                                   int32_t* __restrict__ cnt, uint32_t* __restrict__ touched) {
+                                   int32_t* __restrict__ cnt, uint32_t* __restrict__ touched,
+                                   int32_t* __restrict__ lastpos) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= (int64_t)nq * cap) return;
   const int q = (int)(i / cap), t = (int)(i - (int64_t)q * cap);
@@ -63,13 +67,15 @@ __global__ void trace_count_kernel(const int32_t* __restrict__ trace,
   const int32_t x = trace[i];
   atomicAdd(&cnt[x], 1);
   atomicOr(&touched[(uint32_t)x >> 5], 1u << (x & 31));
+  if (lastpos) atomicMax(&lastpos[x], (int32_t)i);
 }
 hipError_t launch_trace_count(const int32_t* trace, const int32_t* trace_n, int nq, int cap,
-                              int32_t* cnt, uint32_t* touched, hipStream_t st) {
+                              int32_t* cnt, uint32_t* touched, int32_t* lastpos, hipStream_t st) {
   const int64_t n = (int64_t)nq * cap;
   if (n <= 0) return hipSuccess;
+  if (n > INT32_MAX) return hipErrorInvalidValue;
   hipLaunchKernelGGL(trace_count_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, trace,
-                     trace_n, nq, cap, cnt, touched);
+                     trace_n, nq, cap, cnt, touched, lastpos);
   return hipGetLastError();
 }
 

@@ -155,3 +155,41 @@ def test_reduced_precision_traversal_with_tiered_rescoring(prec):
     s1 = g.stats()
     assert s1["cache_gather_hits"] == s0["cache_gather_hits"]
     assert s1["cache_gather_misses"] == s0["cache_gather_misses"]
+
+
+@pytest.mark.parametrize("policy", [1, 2, 3])
+@pytest.mark.parametrize("warm", [False, True])
+def test_classic_policies_match_oracle_replay(state, policy, warm):
+    """LRU, LFU and LRFU placement equal the oracle's replay over the oracle's
+    traces, from an empty cache and from the in-degree warm start."""
+    oix, base, q = state
+    trace_cap, cap_rows = 64, 150
+    rows, ed, alive = oix.export()
+    if warm:
+        g = svf.Index(base.shape[1], oix.R, oix.metric, seed=6)
+        g.import_graph(base, rows, ed.astype(np.float32), alive)
+        g.set_option("cache_trace_cap", trace_cap)
+        g.set_option("cache_policy", policy)
+        g.set_option("cache_promote_max", 100)
+        g.set_option("cache_bytes", cap_rows * 4 * ((base.shape[1] + 7) // 8 * 8))
+    else:
+        g = tiered_from_oracle(oix, base, cap_rows, seed=6, cache_trace_cap=trace_cap,
+                               cache_policy=policy, cache_promote_max=100)
+    e_in = np.zeros(len(alive), np.int64)
+    src = rows[alive.astype(bool)]
+    np.add.at(e_in, src[src >= 0], 1)
+    batches, got = [], []
+    for b in range(4):
+        qb = q[b * 60:(b + 1) * 60]
+        gi, gd = g.search(qb, 10, 40)
+        oi, od, _ = oix.search(qb, 10, 40)
+        np.testing.assert_array_equal(gi, oi)               # the cache only moves bytes
+        np.testing.assert_array_equal(gd.astype(np.float64), od)
+        got.append(g.stats()["cache_last_trace_hits"])
+        tr, cnt = oix.search_expansions(qb, 40, cap=trace_cap)
+        batches.append(np.concatenate([tr[i, :min(cnt[i], trace_cap)] for i in range(len(qb))]))
+    hits, _ = O.policy_replay(policy, len(alive), cap_rows, e_in, alive, batches, promote_max=100,
+                              warm=warm)
+    assert got == hits.tolist()
+    assert sum(got) > 0
+    assert g.stats()["cache_evictions"] > 0
