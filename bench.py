@@ -41,9 +41,9 @@ BEAMS = [32, 48, 64, 96, 128, 192, 256, 384, 512]
 # WRITE_SIZE 1,048,576).  The figure describes the kernel built from the sources
 # whose hash is recorded; any edit to them makes it stale and it is reported as null.
 COUNTED = {"sources": ("common.hpp", "wave_ops.hpp", "search.hip"),
-           "sha256_16": "16e0b4bc82cf0a22", "beam": 96,
-           "fetch_kib": 9267048.4, "fetch_scale": 1048576.0 / 524299.5,
-           "write_kib": 2518.4, "write_scale": 1.0}
+           "sha256_16": "60b2d19d5b9af490", "beam": 96,
+           "fetch_kib": 9267107.0, "fetch_scale": 1048576.0 / 524299.5,
+           "write_kib": 2518.0, "write_scale": 1.0}
 
 
 def counted_traffic(beam):
@@ -396,6 +396,76 @@ def tier_bench(torch, svf, datagen, n_base, rounds=20, cache_frac=0.25):
             "tiered_fp8_traversal_fp32_rescore": fp8}
 
 
+def policy_bench(torch, svf, datagen, n_total=2_000_000, steps=12, measured=8, beam=64,
+                 ratios=(0.2, 0.4, 0.6, 0.8, 1.0)):
+    """Replacement-policy ablation under a sliding window on the tiered store.
+    n_total x 128 mixture of 4096 components (L2, degree 32) in 200 equal
+    segments; the index starts from the first 100 (built once, then imported
+    into a fresh index per setting).  Each step inserts the next segment,
+    deletes the oldest live one and searches a batch of 10k queries whose
+    components follow Zipf(1.2), FP32 traversal through the cache.  For each
+    share of the live vectors held in HBM and each policy (workload-aware
+    placement, LRU, LFU, LRFU, none) the last `measured` steps are reported."""
+    dim, R, nq, nseg = 128, 32, 10_000, 200
+    seg = n_total // nseg
+    win = nseg // 2
+    base, queries = datagen.gmm_float(6, n_total, steps * nq, dim, 4096, query_zipf=1.2)
+    ix = svf.Index(dim, R, svf.METRIC_L2, seed=0)
+    t0 = time.perf_counter()
+    ix.build(base[:win * seg])
+    build_s = time.perf_counter() - t0
+    rows, ed, alive = ix.export_graph()
+    ix.close()
+    bufs = (torch.empty((nq, K), dtype=torch.int32, device="cuda"),
+            torch.empty((nq, K), dtype=torch.float32, device="cuda"),
+            torch.empty(nq, dtype=torch.int32, device="cuda"),
+            torch.empty(nq, dtype=torch.int32, device="cuda"))
+    qs = [torch.from_numpy(queries[r * nq:(r + 1) * nq]).cuda() for r in range(steps)]
+    out = []
+    for ratio in ratios:
+        for name, pol, pmax in (("wavp", 0, 2048), ("lru", 1, 2048), ("lfu", 2, 2048),
+                                ("lrfu", 3, 2048), ("none", 0, 0)):
+            g = svf.Index(dim, R, svf.METRIC_L2, seed=0)
+            g.import_graph(base[:win * seg], rows, ed, alive)
+            g.set_option("cache_policy", pol)
+            g.set_option("cache_promote_max", pmax)
+            g.set_option("cache_bytes", int(ratio * win * seg) * dim * 4)
+            res = []
+            for st in range(steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                g.insert(base[(win + st) * seg:(win + st + 1) * seg])
+                g.delete(np.arange(st * seg, (st + 1) * seg, dtype=np.int32))
+                t1 = time.perf_counter()
+                s0 = g.stats()
+                run_search(torch, g, qs[st], beam, bufs)
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                s1 = g.stats()
+                h = s1["cache_gather_hits"] - s0["cache_gather_hits"]
+                m = s1["cache_gather_misses"] - s0["cache_gather_misses"]
+                res.append(((t1 - t0) * 1e3, (t2 - t1) * 1e3, s1["last_search_ms"], h / max(h + m, 1)))
+            g.close()
+            st_ = res[steps - measured:]
+            upd = float(np.mean([x[0] for x in st_]))
+            srch = float(np.mean([x[1] for x in st_]))
+            out.append({"cache_share": ratio, "policy": name,
+                        "gather_hit_rate": round(float(np.mean([x[3] for x in st_])), 4),
+                        "update_ms": round(upd, 3), "search_call_ms": round(srch, 3),
+                        "search_kernel_ms": round(float(np.mean([x[2] for x in st_])), 3),
+                        "step_ms": round(upd + srch, 3),
+                        "updates_per_s": round(2 * seg / (upd / 1e3), 1),
+                        "queries_per_s": round(nq / (srch / 1e3), 1)})
+            log("policy %s share %.1f: hit %.3f, update %.1f ms, search %.1f ms"
+                % (name, ratio, out[-1]["gather_hit_rate"], upd, srch))
+    return {"workload": "sliding window over %dM x 128 GMM (4096 comps) in %d segments of %d, "
+                        "%d live; per step insert one segment, delete the oldest, search 10k "
+                        "queries (Zipf(1.2) comps), L2, degree 32, k=10, beam %d, FP32 traversal "
+                        "through the cache; cache share of the live vectors; %d steps, the last %d "
+                        "averaged" % (n_total // 1_000_000, nseg, seg, win * seg, beam, steps, measured),
+            "build_s": round(build_s, 2), "settings": out}
+
+
 def cpu_baseline(base, queries, beam):
     """The FP64 oracle, as it stands, on a bounded sample: it builds its own
     index over the first 20,000 base vectors (same generator) and searches
@@ -429,6 +499,8 @@ def main():
                     help="skip the large-footprint (5M x 96) search leg")
     ap.add_argument("--large-n", type=int, default=5_000_000)
     ap.add_argument("--no-tier", action="store_true", help="skip the tiered-store leg")
+    ap.add_argument("--no-policies", action="store_true",
+                    help="skip the replacement-policy and memory-share ablation")
     ap.add_argument("--tier-n", type=int, default=4_000_000)
     ap.add_argument("--search-only", type=int, default=0, metavar="BEAM",
                     help="build, then only time the plain FP32 search at this beam (for "
@@ -594,6 +666,12 @@ def main():
         torch.cuda.empty_cache()
         tier = tier_bench(torch, svf, datagen, args.tier_n)
 
+    policies = None
+    if not args.no_policies:
+        log("replacement policies")
+        torch.cuda.empty_cache()
+        policies = policy_bench(torch, svf, datagen)
+
     serving = None
     if not args.no_serving:
         log("serving mix")
@@ -654,6 +732,7 @@ def main():
         "small_batches": small,
         "large_footprint": large,
         "tiered": tier,
+        "cache_policies": policies,
         "serving": serving,
         "wall_s_timed": round(wall, 4),
     }

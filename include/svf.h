@@ -115,7 +115,10 @@ int svf_destroy(svf_index *ix);
  *                   after svf_build).  Once set it stays.  Searches read cached rows from HBM
  *                   and the rest over the host link; after every direct search call the
  *                   batched workload-aware placement (Alg. 2) updates the cache, and
- *                   svf_build warms it with the highest in-degree vectors (Sec. 4.4)
+ *                   svf_build warms it with the highest in-degree vectors (Sec. 4.4).
+ *                   A deleted vector leaves the cache at once; inserted vectors take
+ *                   free slots in id order.  While the serving loop runs the cache
+ *                   does not change.
  *   cache_theta     placement threshold on F_lambda (>= 0; 1.0)
  *   cache_alpha_ratio alpha / (alpha + beta) of F_lambda, alpha + beta = 1 ([0,1]; 0.6)
  *   cache_promote_max placements per query batch (>= 0; 2048)
@@ -129,7 +132,8 @@ int svf_destroy(svf_index *ix);
  *   model_min_iters smallest expansion cap of a gated query (>=1; 8)
  * Unknown key or out-of-range value: SVF_E_INVAL. */
 int svf_set_option(svf_index *ix, const char *key, double value);
-/* Any key above, plus the read-only "dim", "degree" and "metric". */
+/* Any key above, plus the read-only "dim", "degree", "metric" and
+ * "cache_resident" (vectors currently held in the HBM cache). */
 int svf_get_option(const svf_index *ix, const char *key, double *value);
 
 /* Insert n vectors (n x dim row-major FP32, host memory) as one batch

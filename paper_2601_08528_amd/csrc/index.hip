@@ -32,6 +32,10 @@ int hip_fail(hipError_t e, const char* what) {
 constexpr int kMaxBeam = 512;
 constexpr int kMaxEntries = 1024;
 
+int tier_release(svf_index* ix, const int32_t* ids, int64_t n);
+int tier_admit(svf_index* ix, int64_t id0, int64_t n);
+int tier_apply(svf_index* ix, const std::vector<int32_t>& place, hipStream_t st);
+
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 int beam_insert(const svf_index* ix) {
@@ -355,7 +359,7 @@ int insert_commit(svf_index* ix, PendingInsert* p) {
     ix->n_slots = p->b;
     ix->n_alive = p->b;
     ++ix->graph_epoch;
-    return SVF_OK;
+    return tier_admit(ix, 0, p->b);
   }
   CK(hipEventRecord(ix->ev0, st));
   CK(svf::launch_commit_batch(p->ra, p->n_targets, ix->graph, ix->edge_d, ix->alive, st));
@@ -365,7 +369,7 @@ int insert_commit(svf_index* ix, PendingInsert* p) {
   ++ix->graph_epoch;
   ix->n_slots = p->n0 + p->b;
   ix->n_alive += p->b;
-  return SVF_OK;
+  return tier_admit(ix, p->n0, p->b);
 }
 
 // One insertion batch of b vectors already on the device (pitch dim).
@@ -616,6 +620,7 @@ int delete_ids(svf_index* ix, const int32_t* ids, int64_t n) {
   CK(hipStreamSynchronize(st));
   ix->st.del_mark_ms = elapsed(ix->ev0, ix->ev1);
   ++ix->graph_epoch;
+  if ((rc = tier_release(ix, ids, n))) return rc;
   if (ix->alive_at_consolidate == 0) ix->alive_at_consolidate = ix->n_alive;
   ix->n_alive -= newly;
   ix->deleted_since += newly;
@@ -627,6 +632,51 @@ int delete_ids(svf_index* ix, const int32_t* ids, int64_t n) {
   } else {
     rc = repair(ix, 0);
   }
+  return rc;
+}
+
+// ---- tiered store: slots follow deletions and insertions ---------------------
+// A deleted vector leaves the cache at once and its slot becomes free; new
+// vectors take free slots in id order (write-allocate), so a cache that
+// holds every live vector keeps doing so under updates.  While the serving
+// loop runs the cache does not change (searches of other streams may be
+// reading it).
+int tier_release(svf_index* ix, const int32_t* ids, int64_t n) {
+  svf::TierState& T = ix->tier;
+  if (!T.on || ix->server || n == 0) return SVF_OK;
+  std::vector<int32_t> place;
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t x = ids[i];
+    const int32_t s_ = T.where[x];
+    if (s_ < 0) continue;
+    T.where[x] = -1;
+    T.slot_id[s_] = -1;
+    T.ref[s_] = 0;
+    T.free_slots.push_back(s_);
+    place.insert(place.end(), {s_, -1, x});
+  }
+  const int64_t placed = T.last_placed;
+  const int rc = tier_apply(ix, place, ix->stream);
+  T.last_placed = placed;
+  return rc;
+}
+
+int tier_admit(svf_index* ix, int64_t id0, int64_t n) {
+  svf::TierState& T = ix->tier;
+  if (!T.on || ix->server || T.building || n == 0) return SVF_OK;
+  std::vector<int32_t> place;
+  for (int64_t x = id0; x < id0 + n; ++x) {
+    const int64_t slot = T.take_slot();
+    if (slot < 0) break;
+    T.slot_id[slot] = (int32_t)x;
+    T.where[x] = (int32_t)slot;
+    T.ref[slot] = 0;
+    place.insert(place.end(), {(int32_t)slot, (int32_t)x, -1});
+  }
+  T.promotions += place.size() / 3;
+  const int64_t placed = T.last_placed;
+  const int rc = tier_apply(ix, place, ix->stream);
+  T.last_placed = placed;
   return rc;
 }
 
@@ -698,6 +748,15 @@ int tier_apply(svf_index* ix, const std::vector<int32_t>& place, hipStream_t st)
 // are one ldexp; below the normal range they are applied one by one, with
 // the rounding each single halving has.
 double halve_times(double v, int64_t k) {
+  if (k <= 0) return v;
+  uint64_t u;
+  std::memcpy(&u, &v, 8);
+  const int64_t eb = (int64_t)((u >> 52) & 0x7ff);
+  if (eb != 0x7ff && eb > k) {               // normal in and out: lower the exponent field
+    u -= (uint64_t)k << 52;
+    std::memcpy(&v, &u, 8);
+    return v;
+  }
   while (k > 0 && v != 0.0) {
     int e;
     (void)std::frexp(v, &e);                 // |v| = m 2^e, m in [0.5, 1)
@@ -721,53 +780,57 @@ double fr_now(const svf::TierState& T, int32_t x) {
 // batch's missed vertices, most important first (ties by id), at most
 // promote_max, each take a free slot or the slot of the least important
 // resident vertex, which is always evicted.  Importance: last access (LRU),
-// accesses so far (LFU), F_recent (LRFU); scores do not change while a
-// batch is placed, so the least important resident comes off a heap.
-int tier_place_classic(svf_index* ix, std::vector<std::pair<double, int32_t>>& cand,
-                       hipStream_t st) {
+// accesses so far (LFU), F_recent (LRFU), ties by id (the larger id is the
+// less important); scores do not change while a batch is placed.  With m
+// candidates at most m residents leave, and each one is the least important
+// of those left, so a heap over the m least important residents plus the
+// vertices placed in this batch yields the same evictions as one over all.
+template <class Key>
+int place_classic(svf_index* ix, std::vector<int32_t>& order, Key key, hipStream_t st) {
   svf::TierState& T = ix->tier;
-  const int pol = T.policy;
-  std::vector<double> frb;
-  auto less = [&](int32_t a, int32_t b) -> bool {   // a less important than b
-    if (pol == 1) return T.last[a] < T.last[b] || (T.last[a] == T.last[b] && a > b);
-    if (pol == 2) return T.freq[a] < T.freq[b] || (T.freq[a] == T.freq[b] && a > b);
-    const double fa = fr_now(T, a), fb = fr_now(T, b);
-    return fa < fb || (fa == fb && a > b);
+  using E = std::pair<decltype(key(0)), int32_t>;
+  auto more = [](const E& a, const E& b) {            // a more important than b
+    return a.first > b.first || (a.first == b.first && a.second < b.second);
   };
-  std::vector<int32_t> order;
-  order.reserve(cand.size());
-  for (const auto& c : cand) order.push_back(c.second);
-  auto more = [&](int32_t a, int32_t b) { return less(b, a); };
-  if ((int64_t)order.size() > T.promote_max) {
-    std::nth_element(order.begin(), order.begin() + T.promote_max, order.end(), more);
-    order.resize(T.promote_max);
+  std::vector<E> cand;
+  cand.reserve(order.size());
+  for (const int32_t x : order) cand.emplace_back(key(x), x);
+  if ((int64_t)cand.size() > T.promote_max) {
+    std::nth_element(cand.begin(), cand.begin() + T.promote_max, cand.end(), more);
+    cand.resize(T.promote_max);
   }
-  std::sort(order.begin(), order.end(), more);
-  // heap of the resident vertices, least important on top
-  std::vector<int32_t> heap;
-  const bool evicting = T.used + (int64_t)order.size() > T.C;
+  std::sort(cand.begin(), cand.end(), more);
+  const int64_t m = (int64_t)cand.size();
+  std::vector<E> heap;                                // least important on top
+  const bool evicting = m > T.free_count();
   if (evicting) {
-    heap.reserve(T.used + order.size());
-    for (int64_t s_ = 0; s_ < T.used; ++s_) heap.push_back(T.slot_id[s_]);
+    heap.reserve(T.used + m);
+    for (int64_t s_ = 0; s_ < T.used; ++s_)
+      if (T.slot_id[s_] >= 0) heap.emplace_back(key(T.slot_id[s_]), T.slot_id[s_]);
+    if ((int64_t)heap.size() > m) {
+      std::nth_element(heap.begin(), heap.end() - m, heap.end(), more);
+      heap.erase(heap.begin(), heap.end() - m);
+    }
     std::make_heap(heap.begin(), heap.end(), more);
   }
   std::vector<int32_t> place;
-  for (const int32_t x : order) {
-    if (T.used < T.C) {
-      const int64_t slot = T.used++;
+  for (const E& c : cand) {
+    const int32_t x = c.second;
+    const int64_t slot = T.take_slot();
+    if (slot >= 0) {
       T.slot_id[slot] = x;
       T.where[x] = (int32_t)slot;
       T.ref[slot] = 0;
       place.insert(place.end(), {(int32_t)slot, x, -1});
       if (evicting) {
-        heap.push_back(x);
+        heap.push_back(c);
         std::push_heap(heap.begin(), heap.end(), more);
       }
       continue;
     }
     if (T.C == 0) break;
     std::pop_heap(heap.begin(), heap.end(), more);
-    const int32_t y = heap.back();
+    const int32_t y = heap.back().second;
     heap.pop_back();
     const int32_t s_ = T.where[y];
     T.where[y] = -1;
@@ -776,11 +839,18 @@ int tier_place_classic(svf_index* ix, std::vector<std::pair<double, int32_t>>& c
     T.ref[s_] = 0;
     place.insert(place.end(), {s_, x, y});
     ++T.evictions;
-    heap.push_back(x);
+    heap.push_back(c);
     std::push_heap(heap.begin(), heap.end(), more);
   }
   T.promotions += place.size() / 3;
   return tier_apply(ix, place, st);
+}
+
+int tier_place_classic(svf_index* ix, std::vector<int32_t>& order, hipStream_t st) {
+  svf::TierState& T = ix->tier;
+  if (T.policy == 1) return place_classic(ix, order, [&](int32_t x) { return T.last[x]; }, st);
+  if (T.policy == 2) return place_classic(ix, order, [&](int32_t x) { return T.freq[x]; }, st);
+  return place_classic(ix, order, [&](int32_t x) { return fr_now(T, x); }, st);
 }
 
 int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
@@ -835,6 +905,7 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
   // reference bit; uncached vertices above theta become candidates
   int64_t hits = 0;
   std::vector<std::pair<double, int32_t>> cand;
+  std::vector<int32_t> missed;                  // classic policies: every uncached alive vertex
   for (int64_t wi = 0; wi < words; ++wi) {
     uint32_t m = T.touched_h[wi];
     while (m) {
@@ -855,13 +926,13 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
           const double f = T.alpha * v + lg(x);
           if (f > T.theta) cand.emplace_back(f, x);
         } else {
-          cand.emplace_back(0.0, x);
+          missed.push_back(x);
         }
       }
     }
   }
   T.last_trace_hits = hits;
-  if (T.policy != 0) return tier_place_classic(ix, cand, st);
+  if (T.policy != 0) return tier_place_classic(ix, missed, st);
   auto better = [](const std::pair<double, int32_t>& a, const std::pair<double, int32_t>& b) {
     return a.first > b.first || (a.first == b.first && a.second < b.second);
   };
@@ -874,8 +945,8 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
   std::vector<int32_t> place;
   for (const auto& c : cand) {
     const int32_t x = c.second;
-    if (T.used < T.C) {
-      const int64_t slot = T.used++;
+    const int64_t slot = T.take_slot();
+    if (slot >= 0) {
       T.slot_id[slot] = x;
       T.where[x] = (int32_t)slot;
       T.ref[slot] = 0;
@@ -922,7 +993,7 @@ int tier_warmup(svf_index* ix, hipStream_t st) {
   order.reserve(n);
   for (int64_t i = 0; i < n; ++i)
     if ((bits[i >> 5] >> (i & 31)) & 1u) order.push_back((int32_t)i);
-  const int64_t take = std::min<int64_t>(T.C - T.used, (int64_t)order.size());
+  const int64_t take = std::min<int64_t>(T.free_count(), (int64_t)order.size());
   std::partial_sort(order.begin(), order.begin() + take, order.end(), [&](int32_t a, int32_t b) {
     return T.e_in[a] > T.e_in[b] || (T.e_in[a] == T.e_in[b] && a < b);
   });
@@ -930,7 +1001,7 @@ int tier_warmup(svf_index* ix, hipStream_t st) {
   for (int64_t i = 0; i < take; ++i) {
     const int32_t x = order[i];
     if (T.where[x] >= 0) continue;
-    const int64_t slot = T.used++;
+    const int64_t slot = T.take_slot();
     T.slot_id[slot] = x;
     T.where[x] = (int32_t)slot;
     T.ref[slot] = 0;
@@ -949,6 +1020,7 @@ int tier_enable(svf_index* ix, double bytes) {
   T.C = C;
   T.slot_id.assign(C, -1);
   T.ref.assign(C, 0);
+  T.free_slots.clear();
   T.used = 0;
   T.clock = 0;
   if (ix->n_slots == 0) {
@@ -1153,6 +1225,8 @@ int svf_get_option(const svf_index* ix, const char* key, double* out) {
   else if (k == "dim") *out = ix->dim;
   else if (k == "degree") *out = ix->R;
   else if (k == "metric") *out = ix->metric;
+  else if (k == "cache_resident")
+    *out = (double)(ix->tier.used - (int64_t)ix->tier.free_slots.size());
   else if (k == "beam_insert") *out = beam_insert(ix);
   else if (k == "entry_samples") *out = o.entry_samples;
   else if (k == "coop_max_batch") *out = o.coop_max_batch;
@@ -1215,7 +1289,9 @@ int svf_build(svf_index* ix, const float* vecs, int64_t n) {
   float* d;
   if ((rc = scratch(ix->s_q, (size_t)n * ix->dim, &d))) return rc;
   CK(hipMemcpyAsync(d, vecs, (size_t)n * ix->dim * 4, hipMemcpyHostToDevice, ix->stream));
+  ix->tier.building = true;
   rc = insert_stream(ix, d, n, nullptr, nullptr);
+  ix->tier.building = false;
   if (rc == SVF_OK && ix->tier.on) rc = tier_warmup(ix, ix->stream);
   return rc;
 }

@@ -70,6 +70,7 @@ struct TierState {
   float* cache = nullptr;          // device, C x stride
   int32_t* map = nullptr;          // device, cap entries (-1 = not cached)
   std::vector<int32_t> slot_id;    // slot -> id (-1 empty)
+  std::vector<int32_t> free_slots; // slots below `used` released by deletions (a stack)
   std::vector<int32_t> where;      // id -> slot (host mirror of map)
   std::vector<uint8_t> ref;        // reference bits per slot
   std::vector<double> fr;          // F_recent per id, as of batch fr_stamp[id]
@@ -77,6 +78,7 @@ struct TierState {
   std::vector<int32_t> e_in;       // in-degree per id
   int64_t used = 0, clock = 0, e_in_epoch = -1, batch = 0;
   int policy = 0;                  // 0 workload-aware (WAVP), 1 LRU, 2 LFU, 3 LRFU
+  bool building = false;           // inside svf_build: the warm-up fills the cache afterwards
   std::vector<int64_t> freq;       // LFU: accesses so far per id
   std::vector<int64_t> last;       // LRU: last access, (batch << 40) + position, -1 never
   double alpha = 0.6, beta = 0.4, theta = 1.0;
@@ -88,6 +90,16 @@ struct TierState {
   uint32_t* touched_h = nullptr;
   int32_t* lastpos_h = nullptr;
   int64_t host_n = 0;
+  // A free slot (released ones first, then the untouched tail), -1 when full.
+  int64_t take_slot() {
+    if (!free_slots.empty()) {
+      const int64_t s = free_slots.back();
+      free_slots.pop_back();
+      return s;
+    }
+    return used < C ? used++ : -1;
+  }
+  int64_t free_count() const { return (int64_t)free_slots.size() + (C - used); }
   ~TierState() {
     if (cnt_h) (void)hipHostFree(cnt_h);
     if (touched_h) (void)hipHostFree(touched_h);

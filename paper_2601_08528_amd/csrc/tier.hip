@@ -27,20 +27,25 @@ hipError_t launch_indegree(const int32_t* graph, const uint32_t* alive, int64_t 
   return hipGetLastError();
 }
 
-// One workgroup per placement (slot, new id, evicted id or -1): the row is
-// read from the host-resident store over the host link and written to the
-// cache slot; the mapping entries of both ids are updated.  No two placements
-// of one batch share a slot or an id.
+// One workgroup per placement (slot, new id or -1, evicted id or -1): the
+// row is read from the host-resident store over the host link and written to
+// the cache slot, then the mapping entries of both ids are updated (a new id
+// of -1 only releases the slot).  No two placements of one batch share a slot
+// or an id.
 __global__ void place_kernel(const int32_t* __restrict__ place, const float* __restrict__ store,
                              float* __restrict__ cache, int64_t stride, int32_t* __restrict__ map) {
   const int p = blockIdx.x;
   const int32_t slot = place[3 * p], nid = place[3 * p + 1], oid = place[3 * p + 2];
-  const float* src = store + (int64_t)nid * stride;
-  float* dst = cache + (int64_t)slot * stride;
-  for (int64_t e = threadIdx.x; e < stride; e += blockDim.x) dst[e] = src[e];
+  if (nid >= 0) {
+    const float* src = store + (int64_t)nid * stride;
+    float* dst = cache + (int64_t)slot * stride;
+    for (int64_t e = threadIdx.x; e < stride; e += blockDim.x) dst[e] = src[e];
+  }
+  __threadfence();
+  __syncthreads();
   if (threadIdx.x == 0) {
     if (oid >= 0) map[oid] = -1;
-    map[nid] = slot;
+    if (nid >= 0) map[nid] = slot;
   }
 }
 hipError_t launch_place(const int32_t* place, int np, const float* store, float* cache,
@@ -50,8 +55,6 @@ hipError_t launch_place(const int32_t* place, int np, const float* store, float*
   return hipGetLastError();
 }
 
-// Accesses of one batch: per-vertex counts and a bitmap of the vertices
-// touched, from the expansion traces (nq traces of at most cap entries).
 // Accesses of one batch: per-vertex counts, a bitmap of the vertices touched
 // and (when lastpos is given) each vertex's last position in the traces
 // taken in order (query, step), from nq traces of at most cap entries.

@@ -80,6 +80,57 @@ def test_updates_on_tiered_store_bit_exact():
     assert tier.stats()["cache_slots"] == 500
 
 
+def _warm_set(rows, alive, c):
+    """The c alive vectors of highest in-degree from alive vertices, ties by id."""
+    e_in = np.zeros(len(alive), np.int64)
+    src = rows[alive.astype(bool)]
+    np.add.at(e_in, src[src >= 0], 1)
+    ids = np.flatnonzero(alive)
+    order = sorted(ids.tolist(), key=lambda x: (-e_in[x], x))
+    return set(order[:c])
+
+
+@pytest.mark.parametrize("cap_rows", [2600, 300])
+def test_cache_slots_follow_updates(cap_rows):
+    """Deleted vectors leave the cache at once and inserted ones take the free
+    slots: resident counts follow exactly from the warm set, a cache that
+    holds every live vector serves every gather, and graphs and results stay
+    those of the untiered index."""
+    base, q = datagen.gmm_uint8_valued(704, 3200, 100, 32, 8)
+    plain = svf.Index(32, 12, svf.METRIC_L2, seed=3, insert_batch_max=400)
+    tier = svf.Index(32, 12, svf.METRIC_L2, seed=3, insert_batch_max=400)
+    tier.set_option("cache_bytes", cap_rows * 32 * 4)
+    for g in (plain, tier):
+        g.build(base[:2500])
+    rows, _, alive = plain.export_graph()
+    warm = _warm_set(rows, alive, cap_rows)
+    assert tier.get_option("cache_resident") == min(cap_rows, 2500)
+    gone = np.arange(0, 2500, 5, dtype=np.int32)             # 20%: also consolidates
+    for g in (plain, tier):
+        g.delete(gone)
+    resident = min(cap_rows, 2500) - len(warm & set(gone.tolist()))
+    assert tier.get_option("cache_resident") == resident
+    for g in (plain, tier):
+        g.insert(base[2500:3100])
+    resident = min(cap_rows, resident + 600)
+    assert tier.get_option("cache_resident") == resident
+    for a, b in zip(plain.export_graph(), tier.export_graph()):
+        np.testing.assert_array_equal(a, b)
+    s0 = tier.stats()
+    pi, pd = plain.search(q, 10, 32)
+    ti, td = tier.search(q, 10, 32)
+    np.testing.assert_array_equal(pi, ti)
+    np.testing.assert_array_equal(pd, td)
+    s1 = tier.stats()
+    assert s1["cache_gather_hits"] > s0["cache_gather_hits"]
+    if cap_rows >= 2600:                                       # every live vector is cached
+        assert s1["cache_gather_misses"] == s0["cache_gather_misses"]
+    for g in (plain, tier):
+        g.insert(base[3100:])
+    assert tier.get_option("cache_resident") <= cap_rows
+    np.testing.assert_array_equal(plain.search(q, 10, 32)[0], tier.search(q, 10, 32)[0])
+
+
 def test_tiering_a_filled_index_warm_start_matches_replay():
     """cache_bytes on a filled index (with deleted vectors): the FP32 store moves
     to host memory, the cache is warmed with the highest in-degree alive
