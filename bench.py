@@ -396,6 +396,158 @@ def tier_bench(torch, svf, datagen, n_base, rounds=20, cache_frac=0.25):
             "tiered_fp8_traversal_fp32_rescore": fp8}
 
 
+def stream_exact_topk(torch, blocks, q, k, extra=64, sub=1 << 19):
+    """Exact nearest (k + extra) ids and FP64 squared-L2 distances of the
+    queries q over the base rows that `blocks` yields as (start row, rows)
+    on the device: an FP32 GEMM screen per sub-block, then FP64
+    re-evaluation of the screen's best k + extra."""
+    nq = q.shape[0]
+    m = k + extra
+    best_d = torch.full((nq, m), float("inf"), dtype=torch.float64, device=q.device)
+    best_i = torch.full((nq, m), -1, dtype=torch.int64, device=q.device)
+    qn = (q * q).sum(1, keepdim=True)
+    qd = q.double()
+    for s0, x in blocks:
+        for o in range(0, x.shape[0], sub):
+            xs = x[o:o + sub]
+            d = qn + (xs * xs).sum(1)[None, :] - 2.0 * (q @ xs.T)
+            c = torch.topk(d, min(m, xs.shape[0]), dim=1, largest=False).indices
+            ex = ((xs[c].double() - qd[:, None, :]) ** 2).sum(-1)
+            dd = torch.cat([best_d, ex], 1)
+            ii = torch.cat([best_i, c + (s0 + o)], 1)
+            top = torch.topk(dd, m, dim=1, largest=False)
+            best_d, best_i = top.values, torch.gather(ii, 1, top.indices)
+    order = torch.argsort(best_d, dim=1)
+    return torch.gather(best_i, 1, order), torch.gather(best_d, 1, order)
+
+
+def full_tier_bench(torch, svf, datagen, n_base, cache_gb=None, steps=8, sample=1000):
+    """The tiered workload at its own size: n_base x 128 mixture of 4096
+    components whose spread lies mostly in 16 dimensions each (a stand-in for
+    learned embeddings; see datagen.lowrank_mixture), L2, degree 32,
+    100k-vector insert batches, built in HBM,
+    then FP8-E4M3 traversal codes in HBM with the FP32 vectors moved to
+    pinned host memory behind a cache of cache_gb.  Queries: 10k batches with
+    Zipf(1.2) components.  Reports the build, an HBM-resident baseline, the
+    tiered search (FP32 re-scoring through the cache) and a stream of
+    insert-then-search steps.  The cache defaults to 32 GB per 200M vectors."""
+    W, dim, R, nq, ins_b, ncomp = 5, 128, 32, 10_000, 100_000, 4096
+    if cache_gb is None:
+        cache_gb = 32.0 * n_base / 200e6
+    chunk = 1 << 22
+    ix = svf.Index(dim, R, svf.METRIC_L2, seed=0, insert_batch_max=ins_b)
+    ix.set_option("capacity", n_base + steps * ins_b)
+    t0 = time.perf_counter()
+    for s0, x in datagen.lowrank_device_chunks(torch, W, n_base, dim, ncomp, chunk=chunk):
+        ix.insert_dev(x.data_ptr(), x.shape[0], stream=torch.cuda.current_stream().cuda_stream)
+        if (s0 // chunk) % 8 == 7 or s0 + x.shape[0] == n_base:
+            log("full tier: built %d vectors in %.0f s" % (s0 + x.shape[0], time.perf_counter() - t0))
+    build_s = time.perf_counter() - t0
+    del x
+    queries = datagen.lowrank_queries(W, (steps + 1) * nq, dim, ncomp, query_zipf=1.2)
+    q0 = torch.from_numpy(queries[:nq]).cuda()
+    t1 = time.perf_counter()
+    gt_i, gt_d = stream_exact_topk(
+        torch, datagen.lowrank_device_chunks(torch, W, n_base, dim, ncomp, chunk=chunk), q0[:sample], K)
+    torch.cuda.synchronize()
+    gt_s = time.perf_counter() - t1
+    kth = gt_d[:, K - 1]
+    log("full tier: exact top-%d of %d queries in %.0f s" % (K, sample, gt_s))
+    bufs = (torch.empty((nq, K), dtype=torch.int32, device="cuda"),
+            torch.empty((nq, K), dtype=torch.float32, device="cuda"),
+            torch.empty(nq, dtype=torch.int32, device="cuda"),
+            torch.empty(nq, dtype=torch.int32, device="cuda"))
+
+    def rec():
+        ids = bufs[0][:sample].long()
+        hit = (ids[:, :, None] == gt_i[:, None, :]) & (gt_d[:, None, :] <= kth[:, None, None])
+        return hit.any(-1).double().mean().item()
+
+    def pick(beams):
+        rows = []
+        for b in beams:
+            run_search(torch, ix, q0, b, bufs)
+            torch.cuda.synchronize()
+            r = rec()
+            ms, _ = timed_steps(torch, ix, q0, b, bufs, 3, 0)
+            st = ix.stats()
+            rows.append({"beam": b, "recall@10_sample": round(r, 4), "ms": round(float(np.median(ms)), 3),
+                         "n_dist_per_query": round(st["last_n_dist"] / nq, 1),
+                         "n_exp_per_query": round(st["last_n_exp"] / nq, 1)})
+            log("full tier: beam %d recall %.4f %.2f ms" % (b, r, rows[-1]["ms"]))
+            if r >= 0.95:
+                return b, rows
+        return beams[-1], rows
+
+    beam32, sweep32 = pick((64, 96, 128, 192, 256, 384))
+    fp32_row = sweep32[-1]
+    ix.set_option("precision", svf.PREC_FP8)
+    beam8, sweep8 = pick((64, 96, 128, 192, 256, 384))
+    run_search(torch, ix, q0, beam8, bufs)
+    torch.cuda.synchronize()
+    ref_ids = bufs[0].clone()
+    t2 = time.perf_counter()
+    ix.set_option("cache_bytes", cache_gb * 1e9)
+    tier_s = time.perf_counter() - t2
+    log("full tier: FP32 store moved to host memory, cache warmed, in %.0f s" % tier_s)
+    run_search(torch, ix, q0, beam8, bufs)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(bufs[0], ref_ids))
+    rows = []
+    gen = datagen.lowrank_device_chunks(torch, W, steps * ins_b, dim, ncomp, first=n_base, chunk=ins_b)
+    for r in range(steps):
+        _, xb = next(gen)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        ix.insert_dev(xb.data_ptr(), xb.shape[0], stream=torch.cuda.current_stream().cuda_stream)
+        tb = time.perf_counter()
+        qr = torch.from_numpy(queries[(r + 1) * nq:(r + 2) * nq]).cuda()
+        s0 = ix.stats()
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        run_search(torch, ix, qr, beam8, bufs)
+        torch.cuda.synchronize()
+        td = time.perf_counter()
+        s1 = ix.stats()
+        h = s1["cache_gather_hits"] - s0["cache_gather_hits"]
+        m = s1["cache_gather_misses"] - s0["cache_gather_misses"]
+        kms = s1["last_search_ms"]
+        rows.append({"step": r, "insert_100k_ms": round((tb - ta) * 1e3, 1),
+                     "search_kernel_ms": round(kms, 3), "search_call_ms": round((td - tc) * 1e3, 2),
+                     "gather_hit_rate": round(h / max(h + m, 1), 4),
+                     "host_link_gbs": round(m * dim * 4 / (kms / 1e3) / 1e9, 1)})
+        log("full tier: step", rows[-1])
+    st = rows[steps // 2:]
+    kms = float(np.mean([x["search_kernel_ms"] for x in st]))
+    cms = float(np.mean([x["search_call_ms"] for x in st]))
+    ims = float(np.mean([x["insert_100k_ms"] for x in st]))
+    sd = ix.stats()
+    out = {"workload": "%dM x 128 mixture of 4096 rank-16 components + 0.1 noise (Zipf(1.2) "
+                       "queries), L2, degree 32, 10k-query "
+                       "batches, k=10, 100k-vector insert batches; FP8-E4M3 traversal codes in HBM, "
+                       "FP32 vectors in pinned host memory behind a %.0f GB HBM cache"
+                       % (n_base // 1_000_000, cache_gb),
+           "build_s": round(build_s, 1), "build_vectors_per_s": round(n_base / build_s, 1),
+           "exact_topk_sample_s": round(gt_s, 1), "recall_sample_queries": sample,
+           "hbm_fp32": {"beam": beam32, "ms_per_batch": fp32_row["ms"],
+                        "qps": round(nq / (fp32_row["ms"] / 1e3), 1), "sweep": sweep32},
+           "hbm_fp8_rescore": {"beam": beam8, "ms_per_batch": sweep8[-1]["ms"],
+                               "qps": round(nq / (sweep8[-1]["ms"] / 1e3), 1), "sweep": sweep8},
+           "tier_setup_s": round(tier_s, 1), "cache_slots": sd["cache_slots"],
+           "device_bytes": sd["device_bytes"],
+           "tiered_same_results_as_hbm": same,
+           "tiered_stream": {"steady_search_kernel_ms": round(kms, 3),
+                             "steady_search_call_ms": round(cms, 2),
+                             "steady_qps_kernel": round(nq / (kms / 1e3), 1),
+                             "steady_qps_with_placement": round(nq / (cms / 1e3), 1),
+                             "steady_insert_100k_ms": round(ims, 1),
+                             "steady_gather_hit_rate":
+                                 round(float(np.mean([x["gather_hit_rate"] for x in st])), 4),
+                             "steps": rows}}
+    ix.close()
+    return out
+
+
 def policy_bench(torch, svf, datagen, n_total=2_000_000, steps=12, measured=8, beam=64,
                  ratios=(0.2, 0.4, 0.6, 0.8, 1.0)):
     """Replacement-policy ablation under a sliding window on the tiered store.
@@ -502,6 +654,9 @@ def main():
     ap.add_argument("--no-policies", action="store_true",
                     help="skip the replacement-policy and memory-share ablation")
     ap.add_argument("--tier-n", type=int, default=4_000_000)
+    ap.add_argument("--full-tier", type=int, default=0, metavar="N",
+                    help="also run the tiered workload at N base vectors (200M is its own size; "
+                         "takes minutes and about 110 GB of pinned host memory)")
     ap.add_argument("--search-only", type=int, default=0, metavar="BEAM",
                     help="build, then only time the plain FP32 search at this beam (for "
                          "hardware counter runs); prints a short JSON line")
@@ -666,6 +821,12 @@ def main():
         torch.cuda.empty_cache()
         tier = tier_bench(torch, svf, datagen, args.tier_n)
 
+    full_tier = None
+    if args.full_tier > 0:
+        log("full-size tiered workload")
+        torch.cuda.empty_cache()
+        full_tier = full_tier_bench(torch, svf, datagen, args.full_tier)
+
     policies = None
     if not args.no_policies:
         log("replacement policies")
@@ -733,6 +894,7 @@ def main():
         "large_footprint": large,
         "tiered": tier,
         "cache_policies": policies,
+        "tiered_full_size": full_tier,
         "serving": serving,
         "wall_s_timed": round(wall, 4),
     }

@@ -96,7 +96,8 @@ int svf_destroy(svf_index *ix);
  *                   unchanged; FP32/BF16/FP8, degree <= 64, dim <= 256, untiered)
  *                   (0..2^24; 1024; 0 = never)
  *   visited_slots   LDS visited-table slots per query, power of two (256..16384; 4096)
- *   visited_compact 16-bit visited tags in 4-way sets when the ids fit (0/1; 1)
+ *   visited_compact exact quotient tags of a scrambled id (12-bit, five per 64-bit set, or
+ *                   16-bit, four per set) instead of full 32-bit ids, when the ids fit (0/1; 1)
  *   repair_c        out-neighbours taken from each deleted neighbour (1..min(16, degree); 8)
  *   prune_cap       longest candidate list given to the prune, 0 = max(4*degree, beam_insert)
  *   consolidate_frac deleted fraction that triggers consolidation ((0,1]; 0.2)
@@ -106,6 +107,9 @@ int svf_destroy(svf_index *ix);
  *                   scale s = max|x| / 448 per vector (the query quantised the same way);
  *                   distances accumulate in FP32
  *   rerank          exact FP32 re-scoring of the final pool under reduced precision (0/1; 1)
+ *   capacity        reserve id slots for this many vectors now (never shrinks); otherwise
+ *                   the stores grow by reallocation to twice their size when full, which
+ *                   briefly holds both copies (1..2^31-65)
  *   cache_bytes     tiered store (Sec. 4.2-4.3): all FP32 vectors in pinned host memory, an
  *                   HBM cache of cache_bytes / (4 * round_up(dim, 8)) rows in front.  An FP32
  *                   traversal reads through the cache; with FP16/BF16/FP8 traversal that
@@ -143,7 +147,9 @@ int svf_get_option(const svf_index *ix, const char *key, double *value);
  * split.  out_ids (n entries, may be NULL) receives the assigned ids.
  * Non-finite input: SVF_E_INVAL. */
 int svf_insert(svf_index *ix, const float *vecs, int64_t n, int32_t *out_ids);
-/* Same with device pointers; synchronises the stream before returning. */
+/* Same with device pointers.  Waits for the work already queued on `stream`
+ * (the producer of d_vecs; NULL is the default stream), runs on the index's
+ * own stream and has finished when it returns. */
 int svf_insert_dev(svf_index *ix, const float *d_vecs, int64_t n, int32_t *d_out_ids, void *stream);
 
 /* Build from scratch by the insertion rule: the first min(n, 4*degree)
@@ -173,9 +179,13 @@ int svf_consolidate(svf_index *ix);
 int svf_search(svf_index *ix, const float *queries, int64_t nq, int32_t k, int32_t beam,
                int32_t *out_ids, float *out_dists);
 
-/* Device-pointer search, enqueued on `stream` without waiting.  Optional
- * d_n_dist / d_n_exp (nq int32 each, may be NULL) receive per-query counts of
- * distance evaluations and expanded vertices. */
+/* Device-pointer search, enqueued on `stream` (NULL is the default stream)
+ * after the work already queued there, without waiting for it to finish
+ * (with a tiered store the call waits, since placement follows the batch).
+ * The index's scratch buffers serve one search at a time: a search on another
+ * stream must not start before this one has finished.  Optional d_n_dist /
+ * d_n_exp (nq int32 each, may be NULL) receive per-query counts of distance
+ * evaluations and expanded vertices. */
 int svf_search_dev(svf_index *ix, const float *d_queries, int64_t nq, int32_t k, int32_t beam,
                    int32_t *d_out_ids, float *d_out_dists, int32_t *d_n_dist, int32_t *d_n_exp,
                    void *stream);

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "index.hpp"
@@ -33,6 +34,10 @@ constexpr int kMaxBeam = 512;
 constexpr int kMaxEntries = 1024;
 
 int tier_release(svf_index* ix, const int32_t* ids, int64_t n);
+// The device in-degree array while it is kept current, else null.
+int32_t* kept_indegree(svf_index* ix) {
+  return ix->tier.on && ix->tier.e_in_valid ? ix->tier.e_in_d.as<int32_t>() : nullptr;
+}
 int tier_admit(svf_index* ix, int64_t id0, int64_t n);
 int tier_apply(svf_index* ix, const std::vector<int32_t>& place, hipStream_t st);
 
@@ -106,6 +111,7 @@ int reserve(svf_index* ix, int64_t need) {
   }
   hipStream_t st = ix->stream;
   const int64_t n = ix->n_slots;
+  ix->tier.e_in_valid = false;             // sized by capacity: counted again when next needed
   if (tier) {
     std::memset(v32, 0, cap * ix->stride * 4);
     if (n > 0) std::memcpy(v32, ix->vec32, n * ix->stride * 4);
@@ -354,6 +360,7 @@ int insert_commit(svf_index* ix, PendingInsert* p) {
   if (p->b <= 0) return SVF_OK;
   hipStream_t st = ix->stream;
   if (p->seed) {
+    ix->tier.e_in_valid = false;
     CK(svf::launch_set_alive(ix->alive, 0, p->b, st));
     CK(hipStreamSynchronize(st));
     ix->n_slots = p->b;
@@ -362,6 +369,10 @@ int insert_commit(svf_index* ix, PendingInsert* p) {
     return tier_admit(ix, 0, p->b);
   }
   CK(hipEventRecord(ix->ev0, st));
+  if (int32_t* e = kept_indegree(ix)) {
+    CK(svf::launch_indegree_rows_delta(ix->graph, p->ra.tlist, p->n_targets, p->ra.trow, ix->R, e, st));
+    CK(svf::launch_indegree_add(p->ra.fwd_ids, p->b * ix->R, e, st));
+  }
   CK(svf::launch_commit_batch(p->ra, p->n_targets, ix->graph, ix->edge_d, ix->alive, st));
   CK(hipEventRecord(ix->ev1, st));
   CK(hipStreamSynchronize(st));
@@ -482,6 +493,8 @@ int repair(svf_index* ix, int consolidate) {
     pa.nlists = count;
     CK(svf::launch_prune_lists(pa, st));
   }
+  if (int32_t* e = kept_indegree(ix))
+    CK(svf::launch_indegree_rows_delta(ix->graph, list, n_aff, rows, R, e, st));
   CK(svf::launch_commit_rows(list, n_aff, rows, rows_d, R, ix->graph, ix->edge_d, st));
   ++ix->graph_epoch;
   CK(hipEventRecord(ix->ev1, st));
@@ -613,7 +626,7 @@ int delete_ids(svf_index* ix, const int32_t* ids, int64_t n) {
   CK(hipEventRecord(ix->ev0, st));
   CK(hipMemcpyAsync(d, ids, n * 4, hipMemcpyHostToDevice, st));
   CK(svf::launch_fill_u32(cnt, 1, 0u, st));
-  CK(svf::launch_mark_deleted(d, n, ix->alive, cnt, st));
+  CK(svf::launch_mark_deleted(d, n, ix->alive, cnt, ix->graph, ix->R, kept_indegree(ix), st));
   int32_t newly = 0;
   CK(hipMemcpyAsync(&newly, cnt, 4, hipMemcpyDeviceToHost, st));
   CK(hipEventRecord(ix->ev1, st));
@@ -692,14 +705,32 @@ int tier_admit(svf_index* ix, int64_t id0, int64_t n) {
 // counts -1); a candidate without a victim ends the batch's placements.
 int tier_refresh_indegree(svf_index* ix, hipStream_t st) {
   svf::TierState& T = ix->tier;
-  if (T.e_in_epoch == ix->graph_epoch && (int64_t)T.e_in.size() >= ix->n_slots) return SVF_OK;
+  const bool recount = !T.e_in_valid;
+  if (!recount && !T.verify_indegree && T.e_in_epoch == ix->graph_epoch && T.e_in_n >= ix->n_slots)
+    return SVF_OK;
+  const int64_t cap = std::max<int64_t>(ix->cap, 1);
   int32_t* d;
-  int rc = scratch(T.e_in_d, std::max<int64_t>(ix->n_slots, 1), &d);
+  int rc = scratch(T.e_in_d, cap, &d);
   if (rc) return rc;
-  CK(svf::launch_indegree(ix->graph, ix->alive, ix->n_slots, ix->R, d, st));
-  T.e_in.assign(std::max<int64_t>(ix->n_slots, 1), 0);
-  CK(hipMemcpyAsync(T.e_in.data(), d, ix->n_slots * 4, hipMemcpyDeviceToHost, st));
+  CK(T.e_in.ensure(cap * 4));
+  if (recount) {
+    CK(svf::launch_fill_u32(d, cap, 0u, st));
+    CK(svf::launch_indegree(ix->graph, ix->alive, ix->n_slots, ix->R, d, st));
+    T.e_in_valid = true;
+  }
+  CK(hipMemcpyAsync(T.e_in.p, d, ix->n_slots * 4, hipMemcpyDeviceToHost, st));
+  if (!recount && T.verify_indegree) {
+    int32_t* chk;
+    if ((rc = scratch(T.e_in_chk, cap, &chk))) return rc;
+    CK(svf::launch_indegree(ix->graph, ix->alive, ix->n_slots, ix->R, chk, st));
+    std::vector<int32_t> want(ix->n_slots);
+    CK(hipMemcpyAsync(want.data(), chk, ix->n_slots * 4, hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    for (int64_t i = 0; i < ix->n_slots; ++i)
+      if (want[i] != T.in_degree((int32_t)i)) return fail(SVF_E_INTERNAL, "kept in-degree differs from a recount");
+  }
   CK(hipStreamSynchronize(st));
+  T.e_in_n = ix->n_slots;
   T.e_in_epoch = ix->graph_epoch;
   return SVF_OK;
 }
@@ -858,78 +889,113 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
   const int cap = T.trace_cap;
   const int64_t n = ix->n_slots;
   const int64_t words = (n + 31) / 32;
-  // per-vertex access counts and the touched bitmap, counted on the GPU
+  // On the GPU: per-vertex access counts, the touched bitmap (and for LRU the
+  // last positions), then the list of touched vertices in id order; only that
+  // list comes back to the host.
   const bool lru = T.policy == 1;
-  int32_t *cnt_d, *lastpos_d = nullptr;
+  int32_t *cnt_d, *lastpos_d = nullptr, *blk_d;
   uint32_t* touched_d;
+  const int64_t nb = svf::touched_blocks(words);
   int rc;
   if ((rc = scratch(T.acc_cnt, n, &cnt_d)) || (rc = scratch(T.touched, words, &touched_d)) ||
-      (lru && (rc = scratch(T.lastpos, n, &lastpos_d))))
+      (lru && (rc = scratch(T.lastpos, n, &lastpos_d))) || (rc = scratch(T.blk, 2 * nb + 2, &blk_d)))
     return rc;
-  if (T.host_n < n) {
-    if (T.cnt_h) (void)hipHostFree(T.cnt_h);
-    if (T.touched_h) (void)hipHostFree(T.touched_h);
-    if (T.lastpos_h) (void)hipHostFree(T.lastpos_h);
-    T.cnt_h = nullptr;
-    T.touched_h = nullptr;
-    T.lastpos_h = nullptr;
-    T.host_n = 0;
-    const int64_t hn = std::max<int64_t>(n, ix->cap);
-    CK(hipHostMalloc((void**)&T.cnt_h, hn * 4, 0));
-    CK(hipHostMalloc((void**)&T.touched_h, ((hn + 31) / 32) * 4, 0));
-    CK(hipHostMalloc((void**)&T.lastpos_h, hn * 4, 0));
-    T.host_n = hn;
-  }
+  CK(T.blk_h.ensure((nb + 1) * 8));
+  CK(T.alive_h.ensure((words + 1) * 4));
   CK(svf::launch_fill_u32(cnt_d, n, 0u, st));
   CK(svf::launch_fill_u32(touched_d, words, 0u, st));
   if (lru) CK(svf::launch_fill_u32(lastpos_d, n, 0xffffffffu, st));
   CK(svf::launch_trace_count(T.trace.as<int32_t>(), T.trace_n.as<int32_t>(), (int)nq, cap, cnt_d,
                              touched_d, lastpos_d, st));
+  CK(svf::launch_touched_count(touched_d, words, blk_d, st));
   unsigned long long gcnt[2] = {0, 0};
-  std::vector<uint32_t> bits(words + 1, 0u);
-  CK(hipMemcpyAsync(T.cnt_h, cnt_d, n * 4, hipMemcpyDeviceToHost, st));
-  CK(hipMemcpyAsync(T.touched_h, touched_d, words * 4, hipMemcpyDeviceToHost, st));
-  if (lru) CK(hipMemcpyAsync(T.lastpos_h, lastpos_d, n * 4, hipMemcpyDeviceToHost, st));
+  int32_t* btot = T.blk_h.as<int32_t>();
+  uint32_t* bits = T.alive_h.as<uint32_t>();
+  CK(hipMemcpyAsync(btot, blk_d, nb * 4, hipMemcpyDeviceToHost, st));
   CK(hipMemcpyAsync(gcnt, T.counts.p, sizeof gcnt, hipMemcpyDeviceToHost, st));
-  CK(hipMemcpyAsync(bits.data(), ix->alive, words * 4, hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(bits, ix->alive, words * 4, hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  bits[words] = 0u;
+  int32_t* boff = btot + nb;                    // exclusive offsets, then the total
+  int64_t total = 0;
+  for (int64_t b = 0; b < nb; ++b) {
+    boff[b] = (int32_t)total;
+    total += btot[b];
+  }
+  int32_t *lid, *lcnt, *llast = nullptr;
+  if ((rc = scratch(T.lst_id, total + 1, &lid)) || (rc = scratch(T.lst_cnt, total + 1, &lcnt)) ||
+      (lru && (rc = scratch(T.lst_last, total + 1, &llast))))
+    return rc;
+  CK(T.lst_id_h.ensure((total + 1) * 4));
+  CK(T.lst_cnt_h.ensure((total + 1) * 4));
+  if (lru) CK(T.lst_last_h.ensure((total + 1) * 4));
+  CK(hipMemcpyAsync(blk_d + nb, boff, nb * 4, hipMemcpyHostToDevice, st));
+  CK(svf::launch_touched_list(touched_d, words, blk_d + nb, cnt_d, lastpos_d, lid, lcnt, llast, st));
+  const int32_t* tid = T.lst_id_h.as<int32_t>();
+  const int32_t* tcnt = T.lst_cnt_h.as<int32_t>();
+  const int32_t* tlast = lru ? T.lst_last_h.as<int32_t>() : nullptr;
+  CK(hipMemcpyAsync(T.lst_id_h.p, lid, total * 4, hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(T.lst_cnt_h.p, lcnt, total * 4, hipMemcpyDeviceToHost, st));
+  if (lru) CK(hipMemcpyAsync(T.lst_last_h.p, llast, total * 4, hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
   rc = tier_refresh_indegree(ix, st);
   if (rc) return rc;
   T.gather_hits += gcnt[0];
   T.gather_misses += gcnt[1];
   auto alive = [&](int32_t x) { return ((bits[x >> 5] >> (x & 31)) & 1u) != 0; };
-  auto lg = [&](int32_t x) { return T.beta * std::log(1.0 + (double)T.e_in[x]); };
+  auto lg = [&](int32_t x) { return T.beta * std::log(1.0 + (double)T.in_degree(x)); };
   ++T.batch;
   // every touched vertex in id order: F_recent halves, then gains one per
   // access; accesses of cached vertices are hits and set their slot's
-  // reference bit; uncached vertices above theta become candidates
-  int64_t hits = 0;
-  std::vector<std::pair<double, int32_t>> cand;
-  std::vector<int32_t> missed;                  // classic policies: every uncached alive vertex
-  for (int64_t wi = 0; wi < words; ++wi) {
-    uint32_t m = T.touched_h[wi];
-    while (m) {
-      const int32_t x = (int32_t)(wi * 32 + __builtin_ctz(m));
-      m &= m - 1;
+  // reference bit; uncached vertices above theta become candidates.  The
+  // vertices are independent, so contiguous ranges of the list run on
+  // separate threads and their candidates are joined in order.
+  const int nthr = (int)std::max<int64_t>(1, std::min<int64_t>({16, (total + 65535) / 65536,
+                                                                 (int64_t)std::thread::hardware_concurrency()}));
+  std::vector<std::vector<std::pair<double, int32_t>>> tcand(nthr);
+  std::vector<std::vector<int32_t>> tmissed(nthr);
+  std::vector<int64_t> thits(nthr, 0);
+  auto work = [&](int t) {
+    const int64_t lo = total * t / nthr, hi = total * (t + 1) / nthr;
+    int64_t h = 0;
+    for (int64_t i = lo; i < hi; ++i) {
+      const int32_t x = tid[i];
       double v = fr_now(T, x);
-      const int32_t c = T.cnt_h[x];
-      for (int32_t t = 0; t < c; ++t) v += 1.0;
+      const int32_t c = tcnt[i];
+      for (int32_t k = 0; k < c; ++k) v += 1.0;
       T.fr[x] = v;
       T.fr_stamp[x] = T.batch;
       T.freq[x] += c;
-      if (lru) T.last[x] = ((T.batch - 1) << 40) + T.lastpos_h[x];
+      if (lru) T.last[x] = ((T.batch - 1) << 40) + tlast[i];
       if (T.where[x] >= 0) {
-        hits += c;
+        h += c;
         T.ref[T.where[x]] = 1;
       } else if (alive(x)) {
         if (T.policy == 0) {
           const double f = T.alpha * v + lg(x);
-          if (f > T.theta) cand.emplace_back(f, x);
+          if (f > T.theta) tcand[t].emplace_back(f, x);
         } else {
-          missed.push_back(x);
+          tmissed[t].push_back(x);
         }
       }
     }
+    thits[t] = h;
+  };
+  if (nthr == 1) {
+    work(0);
+  } else {
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nthr; ++t) pool.emplace_back(work, t);
+    work(0);
+    for (auto& th : pool) th.join();
+  }
+  int64_t hits = 0;
+  std::vector<std::pair<double, int32_t>> cand;
+  std::vector<int32_t> missed;
+  for (int t = 0; t < nthr; ++t) {
+    hits += thits[t];
+    cand.insert(cand.end(), tcand[t].begin(), tcand[t].end());
+    missed.insert(missed.end(), tmissed[t].begin(), tmissed[t].end());
   }
   T.last_trace_hits = hits;
   if (T.policy != 0) return tier_place_classic(ix, missed, st);
@@ -994,9 +1060,11 @@ int tier_warmup(svf_index* ix, hipStream_t st) {
   for (int64_t i = 0; i < n; ++i)
     if ((bits[i >> 5] >> (i & 31)) & 1u) order.push_back((int32_t)i);
   const int64_t take = std::min<int64_t>(T.free_count(), (int64_t)order.size());
-  std::partial_sort(order.begin(), order.begin() + take, order.end(), [&](int32_t a, int32_t b) {
-    return T.e_in[a] > T.e_in[b] || (T.e_in[a] == T.e_in[b] && a < b);
-  });
+  auto first = [&](int32_t a, int32_t b) {
+    return T.in_degree(a) > T.in_degree(b) || (T.in_degree(a) == T.in_degree(b) && a < b);
+  };
+  if (take < (int64_t)order.size()) std::nth_element(order.begin(), order.begin() + take, order.end(), first);
+  std::sort(order.begin(), order.begin() + take, first);
   std::vector<int32_t> place;
   for (int64_t i = 0; i < take; ++i) {
     const int32_t x = order[i];
@@ -1021,6 +1089,7 @@ int tier_enable(svf_index* ix, double bytes) {
   T.slot_id.assign(C, -1);
   T.ref.assign(C, 0);
   T.free_slots.clear();
+  T.e_in_valid = false;
   T.used = 0;
   T.clock = 0;
   if (ix->n_slots == 0) {
@@ -1169,8 +1238,13 @@ int svf_set_option(svf_index* ix, const char* key, double v) {
   } else if (k == "insert_batch_max") {
     if (!is_int(v) || v < 1 || v > (1 << 20)) return fail(SVF_E_INVAL, "insert_batch_max in [1, 2^20]");
     o.insert_batch_max = (int)v;
-  } else if (ix->server && (k == "precision" || k == "use_model")) {
+  } else if (ix->server && (k == "precision" || k == "use_model" || k == "capacity" ||
+                            k == "cache_bytes")) {
     return fail(SVF_E_BUSY, "option cannot change while serving");
+  } else if (k == "capacity") {
+    if (!is_int(v) || v < 1 || v > (double)INT32_MAX - 64)
+      return fail(SVF_E_INVAL, "capacity in [1, 2^31 - 65]");
+    return reserve(ix, (int64_t)v);
   } else if (k == "cache_bytes") {
     if (v <= 0) return fail(SVF_E_INVAL, "cache_bytes > 0");
     return tier_enable(ix, v);
@@ -1184,6 +1258,9 @@ int svf_set_option(svf_index* ix, const char* key, double v) {
   } else if (k == "cache_promote_max") {
     if (!is_int(v) || v < 0 || v > (1 << 24)) return fail(SVF_E_INVAL, "cache_promote_max in [0, 2^24]");
     ix->tier.promote_max = (int)v;
+  } else if (k == "cache_indegree_verify") {
+    if (v != 0 && v != 1) return fail(SVF_E_INVAL, "cache_indegree_verify 0 or 1");
+    ix->tier.verify_indegree = (int)v;
   } else if (k == "cache_policy") {
     if (!is_int(v) || v < 0 || v > 3) return fail(SVF_E_INVAL, "cache_policy 0 (WAVP), 1 (LRU), 2 (LFU) or 3 (LRFU)");
     ix->tier.policy = (int)v;
@@ -1225,6 +1302,7 @@ int svf_get_option(const svf_index* ix, const char* key, double* out) {
   else if (k == "dim") *out = ix->dim;
   else if (k == "degree") *out = ix->R;
   else if (k == "metric") *out = ix->metric;
+  else if (k == "capacity") *out = (double)ix->cap;
   else if (k == "cache_resident")
     *out = (double)(ix->tier.used - (int64_t)ix->tier.free_slots.size());
   else if (k == "beam_insert") *out = beam_insert(ix);
@@ -1247,6 +1325,7 @@ int svf_get_option(const svf_index* ix, const char* key, double* out) {
   else if (k == "cache_promote_max") *out = ix->tier.promote_max;
   else if (k == "cache_trace_cap") *out = ix->tier.trace_cap;
   else if (k == "cache_policy") *out = ix->tier.policy;
+  else if (k == "cache_indegree_verify") *out = ix->tier.verify_indegree;
   else if (k == "model_conf") *out = o.model_conf;
   else if (k == "model_stop_scale") *out = o.model_stop_scale;
   else if (k == "model_min_iters") *out = o.model_min_iters;
@@ -1259,7 +1338,7 @@ int svf_insert_dev(svf_index* ix, const float* d_vecs, int64_t n, int32_t* d_out
   if (!ix || (n > 0 && !d_vecs)) return fail(SVF_E_INVAL, "null argument");
   if (n < 0) return fail(SVF_E_INVAL, "n < 0");
   std::lock_guard<std::mutex> g(ix->mu);
-  if (stream) CK(hipStreamSynchronize((hipStream_t)stream));
+  CK(hipStreamSynchronize((hipStream_t)stream));   // the producer of d_vecs (NULL: default stream)
   return insert_stream(ix, d_vecs, n, d_out_ids, nullptr);
 }
 
@@ -1322,7 +1401,7 @@ int svf_search_dev(svf_index* ix, const float* d_queries, int64_t nq, int32_t k,
   if (rc) return rc;
   if (nq > 0 && (!d_queries || !d_out_ids || !d_out_dists)) return fail(SVF_E_INVAL, "null buffer");
   std::lock_guard<std::mutex> g(ix->mu);
-  hipStream_t st = stream ? (hipStream_t)stream : ix->stream;
+  hipStream_t st = (hipStream_t)stream;        // NULL is the default stream
   rc = search_impl(ix, d_queries, nq, k, beam, d_out_ids, d_out_dists, d_n_dist, d_n_exp, st);
   if (rc == SVF_OK && ix->tier.on && ix->n_slots > 0 && nq > 0) rc = tier_after_batch(ix, nq, st);
   return rc;
@@ -1572,6 +1651,7 @@ int svf_import_graph(svf_index* ix, const float* vecs, int64_t n, const int32_t*
   if (!all_finite(vecs, n * ix->dim)) return fail(SVF_E_INVAL, "non-finite vector value");
   for (int64_t i = 0; i < n * ix->R; ++i)
     if (rows[i] < -1 || rows[i] >= n) return fail(SVF_E_INVAL, "row entry out of range");
+  ix->tier.e_in_valid = false;
   int rc = reserve(ix, std::max<int64_t>(n, 1));
   if (rc) return rc;
   hipStream_t st = ix->stream;

@@ -35,6 +35,28 @@ struct DevBuf {
   template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
+// A pinned host allocation that only grows (old contents are not kept).
+struct PinnedBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~PinnedBuf() { release(); }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t ensure(size_t need) {
+    if (need <= bytes && p) return hipSuccess;
+    release();
+    size_t b = need < 256 ? 256 : need + need / 4;
+    hipError_t e = hipHostMalloc(&p, b, 0);
+    if (e != hipSuccess) { p = nullptr; return e; }
+    bytes = b;
+    return hipSuccess;
+  }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
 struct Options {
   uint64_t seed = 0;
   int beam_insert = 0;        // 0: 2 * degree
@@ -75,7 +97,10 @@ struct TierState {
   std::vector<uint8_t> ref;        // reference bits per slot
   std::vector<double> fr;          // F_recent per id, as of batch fr_stamp[id]
   std::vector<int64_t> fr_stamp;   // (the halvings of later batches are applied on use)
-  std::vector<int32_t> e_in;       // in-degree per id
+  PinnedBuf e_in;                  // host copy: int32 in-degree per id, e_in_n of them
+  int64_t e_in_n = 0;
+  bool e_in_valid = false;         // e_in_d (cap entries) is kept current under updates
+  int verify_indegree = 0;         // check the kept in-degrees against a recount
   int64_t used = 0, clock = 0, e_in_epoch = -1, batch = 0;
   int policy = 0;                  // 0 workload-aware (WAVP), 1 LRU, 2 LFU, 3 LRFU
   bool building = false;           // inside svf_build: the warm-up fills the cache afterwards
@@ -86,10 +111,9 @@ struct TierState {
   uint64_t gather_hits = 0, gather_misses = 0, promotions = 0, evictions = 0;
   int64_t last_trace_hits = 0, last_placed = 0;
   DevBuf trace, trace_n, place, counts, e_in_d, acc_cnt, touched, lastpos;
-  int32_t* cnt_h = nullptr;        // pinned host mirrors of acc_cnt / touched / lastpos
-  uint32_t* touched_h = nullptr;
-  int32_t* lastpos_h = nullptr;
-  int64_t host_n = 0;
+  DevBuf blk, lst_id, lst_cnt, lst_last;   // the batch's touched vertices, in id order
+  DevBuf e_in_chk;                         // recount for cache_indegree_verify
+  PinnedBuf blk_h, lst_id_h, lst_cnt_h, lst_last_h, alive_h;
   // A free slot (released ones first, then the untouched tail), -1 when full.
   int64_t take_slot() {
     if (!free_slots.empty()) {
@@ -100,11 +124,7 @@ struct TierState {
     return used < C ? used++ : -1;
   }
   int64_t free_count() const { return (int64_t)free_slots.size() + (C - used); }
-  ~TierState() {
-    if (cnt_h) (void)hipHostFree(cnt_h);
-    if (touched_h) (void)hipHostFree(touched_h);
-    if (lastpos_h) (void)hipHostFree(lastpos_h);
-  }
+  int32_t in_degree(int32_t x) const { return e_in.as<int32_t>()[x]; }
 };
 }  // namespace svf
 

@@ -66,6 +66,12 @@ hipError_t launch_indegree(const int32_t* graph, const uint32_t* alive, int64_t 
                            int32_t* e_in, hipStream_t st);
 hipError_t launch_place(const int32_t* place, int np, const float* store, float* cache,
                         int64_t stride, int32_t* map, hipStream_t st);
+int64_t touched_blocks(int64_t words);
+hipError_t launch_touched_count(const uint32_t* touched, int64_t words, int32_t* block_tot,
+                                hipStream_t st);
+hipError_t launch_touched_list(const uint32_t* touched, int64_t words, const int32_t* block_off,
+                               const int32_t* cnt, const int32_t* lastpos, int32_t* out_id,
+                               int32_t* out_cnt, int32_t* out_last, hipStream_t st);
 hipError_t launch_trace_count(const int32_t* trace, const int32_t* trace_n, int nq, int cap,
                               int32_t* cnt, uint32_t* touched, int32_t* lastpos, hipStream_t st);
 
@@ -138,7 +144,10 @@ struct RepairArgs {
   int32_t* n_topup;
 };
 hipError_t launch_mark_deleted(const int32_t* ids, int64_t n, uint32_t* alive, int32_t* newly,
-                               hipStream_t st);
+                               const int32_t* graph, int R, int32_t* e_in, hipStream_t st);
+hipError_t launch_indegree_rows_delta(const int32_t* graph, const int32_t* list, int n,
+                                      const int32_t* rows, int R, int32_t* e_in, hipStream_t st);
+hipError_t launch_indegree_add(const int32_t* rows, int64_t n, int32_t* e_in, hipStream_t st);
 hipError_t launch_affected(const RepairArgs& a, hipStream_t st);
 hipError_t launch_repair_candidates(const RepairArgs& a, int first, int count, hipStream_t st);
 hipError_t launch_topup_merge(const RepairArgs& a, const uint64_t* pool, int L, int first,

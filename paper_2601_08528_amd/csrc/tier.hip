@@ -82,4 +82,89 @@ hipError_t launch_trace_count(const int32_t* trace, const int32_t* trace_n, int 
   return hipGetLastError();
 }
 
+// The touched vertices of a batch in id order.  A block of 256 threads covers
+// 1024 bitmap words, four per thread.  Pass 1 stores each block's number of
+// touched vertices; the caller turns these into exclusive offsets; pass 2
+// writes each vertex's id, access count and (when given) last position at
+// its rank.
+constexpr int kTouchThreads = 256;
+constexpr int kTouchWordsPerThread = 4;
+constexpr int64_t kTouchWordsPerBlock = (int64_t)kTouchThreads * kTouchWordsPerThread;
+
+__global__ __launch_bounds__(256) void touched_block_count_kernel(const uint32_t* __restrict__ touched,
+                                                                  int64_t words,
+                                                                  int32_t* __restrict__ block_tot) {
+  __shared__ int part[kTouchThreads / kWave];
+  const int64_t w0 = blockIdx.x * kTouchWordsPerBlock + (int64_t)threadIdx.x * kTouchWordsPerThread;
+  int c = 0;
+  for (int j = 0; j < kTouchWordsPerThread; ++j)
+    if (w0 + j < words) c += __popc(touched[w0 + j]);
+  for (int o = kWave / 2; o > 0; o >>= 1) c += __shfl_xor(c, o);
+  if (lane_id() == 0) part[threadIdx.x / kWave] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int i = 0; i < kTouchThreads / kWave; ++i) t += part[i];
+    block_tot[blockIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(256) void touched_list_kernel(
+    const uint32_t* __restrict__ touched, int64_t words, const int32_t* __restrict__ block_off,
+    const int32_t* __restrict__ cnt, const int32_t* __restrict__ lastpos,
+    int32_t* __restrict__ out_id, int32_t* __restrict__ out_cnt, int32_t* __restrict__ out_last) {
+  __shared__ int scan[kTouchThreads];
+  const int64_t w0 = blockIdx.x * kTouchWordsPerBlock + (int64_t)threadIdx.x * kTouchWordsPerThread;
+  uint32_t m[kTouchWordsPerThread];
+  int c = 0;
+  for (int j = 0; j < kTouchWordsPerThread; ++j) {
+    m[j] = w0 + j < words ? touched[w0 + j] : 0u;
+    c += __popc(m[j]);
+  }
+  scan[threadIdx.x] = c;
+  __syncthreads();
+  for (int o = 1; o < kTouchThreads; o <<= 1) {
+    const int v = (int)threadIdx.x >= o ? scan[threadIdx.x - o] : 0;
+    __syncthreads();
+    scan[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int pos = block_off[blockIdx.x] + scan[threadIdx.x] - c;
+  for (int j = 0; j < kTouchWordsPerThread; ++j) {
+    uint32_t w = m[j];
+    while (w) {
+      const int b = __ffs(w) - 1;
+      w &= w - 1;
+      const int32_t x = (int32_t)((w0 + j) * 32 + b);
+      out_id[pos] = x;
+      out_cnt[pos] = cnt[x];
+      if (out_last) out_last[pos] = lastpos[x];
+      ++pos;
+    }
+  }
+}
+
+int64_t touched_blocks(int64_t words) { return (words + kTouchWordsPerBlock - 1) / kTouchWordsPerBlock; }
+
+hipError_t launch_touched_count(const uint32_t* touched, int64_t words, int32_t* block_tot,
+                                hipStream_t st) {
+  const int64_t nb = touched_blocks(words);
+  if (nb <= 0) return hipSuccess;
+  if (nb > INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(touched_block_count_kernel, dim3((unsigned)nb), dim3(kTouchThreads), 0, st,
+                     touched, words, block_tot);
+  return hipGetLastError();
+}
+
+hipError_t launch_touched_list(const uint32_t* touched, int64_t words, const int32_t* block_off,
+                               const int32_t* cnt, const int32_t* lastpos, int32_t* out_id,
+                               int32_t* out_cnt, int32_t* out_last, hipStream_t st) {
+  const int64_t nb = touched_blocks(words);
+  if (nb <= 0) return hipSuccess;
+  if (nb > INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(touched_list_kernel, dim3((unsigned)nb), dim3(kTouchThreads), 0, st, touched,
+                     words, block_off, cnt, lastpos, out_id, out_cnt, out_last);
+  return hipGetLastError();
+}
+
 }  // namespace svf

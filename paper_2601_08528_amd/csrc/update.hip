@@ -499,21 +499,80 @@ hipError_t launch_commit_batch(const ReverseArgs& a, int n_targets, int32_t* gra
   return hipGetLastError();
 }
 
+// In-degrees from alive vertices, kept current under updates (used by the
+// tiered store's placement).  A row that is rewritten moves one count from
+// each entry it drops to each entry it gains; both rows are sets of ids.  One
+// 64-lane workgroup per row, both rows staged in LDS (degree <= 128).
+__global__ __launch_bounds__(64) void indegree_rows_delta_kernel(const int32_t* __restrict__ graph,
+                                                                 const int32_t* __restrict__ list,
+                                                                 const int32_t* __restrict__ rows,
+                                                                 int R, int32_t* __restrict__ e_in) {
+  __shared__ int32_t old_r[128], new_r[128];
+  const int k = blockIdx.x;
+  const int64_t t = list[k];
+  for (int r = threadIdx.x; r < R; r += kWave) {
+    old_r[r] = graph[t * R + r];
+    new_r[r] = rows[(int64_t)k * R + r];
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < R; r += kWave) {
+    const int32_t o = old_r[r], w = new_r[r];
+    bool o_kept = false, w_had = false;
+    for (int j = 0; j < R; ++j) {
+      o_kept |= new_r[j] == o;
+      w_had |= old_r[j] == w;
+    }
+    if (o >= 0 && !o_kept) atomicSub(&e_in[o], 1);
+    if (w >= 0 && !w_had) atomicAdd(&e_in[w], 1);
+  }
+}
+hipError_t launch_indegree_rows_delta(const int32_t* graph, const int32_t* list, int n,
+                                      const int32_t* rows, int R, int32_t* e_in, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (R > 128) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(indegree_rows_delta_kernel, dim3((unsigned)n), dim3(kWave), 0, st, graph, list,
+                     rows, R, e_in);
+  return hipGetLastError();
+}
+// Rows of vertices that become alive: one count to each entry.
+__global__ void indegree_add_kernel(const int32_t* __restrict__ rows, int64_t n,
+                                    int32_t* __restrict__ e_in) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t x = rows[i];
+  if (x >= 0) atomicAdd(&e_in[x], 1);
+}
+hipError_t launch_indegree_add(const int32_t* rows, int64_t n, int32_t* e_in, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(indegree_add_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, rows,
+                     n, e_in);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
-// Deletion (Sec. 5.2).
-__global__ void mark_deleted_kernel(const int32_t* ids, int64_t n, uint32_t* alive, int32_t* newly) {
+// Deletion (Sec. 5.2).  With in-degrees kept (e_in non-null), a vertex that
+// dies takes one count from each entry of its row.
+__global__ void mark_deleted_kernel(const int32_t* ids, int64_t n, uint32_t* alive, int32_t* newly,
+                                    const int32_t* graph, int R, int32_t* e_in) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int32_t id = ids[i];
   const uint32_t bit = 1u << (id & 31);
   const uint32_t old = atomicAnd(&alive[(uint32_t)id >> 5], ~bit);
-  if (old & bit) atomicAdd(newly, 1);
+  if (old & bit) {
+    atomicAdd(newly, 1);
+    if (e_in)
+      for (int r = 0; r < R; ++r) {
+        const int32_t x = graph[(int64_t)id * R + r];
+        if (x >= 0) atomicSub(&e_in[x], 1);
+      }
+  }
 }
 hipError_t launch_mark_deleted(const int32_t* ids, int64_t n, uint32_t* alive, int32_t* newly,
-                               hipStream_t st) {
+                               const int32_t* graph, int R, int32_t* e_in, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(mark_deleted_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ids,
-                     n, alive, newly);
+                     n, alive, newly, graph, R, e_in);
   return hipGetLastError();
 }
 

@@ -12,7 +12,7 @@ Every stream is a numpy ``Philox`` counter-based generator keyed by
 ``1000 * workload + role`` with roles::
 
     0 component means   1 base vectors   2 queries   3 request stream
-    4 training queries  5 clustering
+    4 training queries  5 clustering      6 component shapes
 """
 from __future__ import annotations
 
@@ -21,7 +21,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-ROLE_MEANS, ROLE_BASE, ROLE_QUERIES, ROLE_STREAM, ROLE_TRAIN, ROLE_CLUSTER = range(6)
+ROLE_MEANS, ROLE_BASE, ROLE_QUERIES, ROLE_STREAM, ROLE_TRAIN, ROLE_CLUSTER, ROLE_SHAPE = range(7)
 
 
 def rng(workload: int, role: int) -> np.random.Generator:
@@ -52,6 +52,79 @@ def zipf_weights(k: int, s: float, perm_rng: np.random.Generator) -> np.ndarray:
     p = np.empty(k)
     p[perm_rng.permutation(k)] = w
     return p
+
+
+def gmm_float_device_chunks(torch, workload: int, n_base: int, dim: int, n_comp: int,
+                            first: int = 0, chunk: int = 1 << 22, mean_std: float = 2.0,
+                            sigma: float = 1.0, device: str = "cuda"):
+    """The base points of gmm_float's mixture (same means), drawn on the device
+    for sizes that do not fit host memory.  Rows [first, first + n_base) are
+    yielded as (start row, n x dim FP32 tensor) blocks of at most `chunk`
+    rows; block i of the full sequence comes from a torch Philox generator
+    keyed by (workload, i), so any block can be drawn again on its own.
+    `first` must be a multiple of `chunk`."""
+    if first % chunk:
+        raise ValueError("first must be a multiple of chunk")
+    means = torch.from_numpy(rng(workload, ROLE_MEANS).standard_normal((n_comp, dim)) * mean_std)
+    means = means.to(device=device, dtype=torch.float32)
+    for s in range(first, first + n_base, chunk):
+        e = min(first + n_base, s + chunk)
+        g = torch.Generator(device=device)
+        g.manual_seed((1000 * workload + ROLE_BASE) * (1 << 24) + s // chunk)
+        c = torch.randint(0, n_comp, (e - s,), generator=g, device=device)
+        x = torch.randn((e - s, dim), generator=g, device=device, dtype=torch.float32)
+        yield s, means[c].add_(x, alpha=sigma)
+
+
+def lowrank_mixture(workload: int, dim: int, n_comp: int, rank: int = 16,
+                    mean_std: float = 2.0):
+    """Means m_c ~ N(0, mean_std^2 I) and loadings W_c (dim x rank, entries
+    N(0, 1/rank)) of a mixture whose component c draws m_c + W_c z + noise e,
+    z ~ N(0, I_rank), e ~ N(0, I_dim): most of each component's spread lies
+    in a rank-dimensional subspace, as in learned embeddings, with about
+    unit variance per coordinate."""
+    means = rng(workload, ROLE_MEANS).standard_normal((n_comp, dim)) * mean_std
+    w = rng(workload, ROLE_SHAPE).standard_normal((n_comp, dim, rank)) / math.sqrt(rank)
+    return means, w
+
+
+def lowrank_device_chunks(torch, workload: int, n_base: int, dim: int, n_comp: int,
+                          rank: int = 16, noise: float = 0.1, first: int = 0,
+                          chunk: int = 1 << 22, sub: int = 1 << 16, device: str = "cuda"):
+    """Base points of lowrank_mixture drawn on the device, in the block scheme
+    of gmm_float_device_chunks (block i keyed by (workload, i))."""
+    if first % chunk:
+        raise ValueError("first must be a multiple of chunk")
+    means, w = lowrank_mixture(workload, dim, n_comp, rank)
+    means = torch.from_numpy(means).to(device=device, dtype=torch.float32)
+    w = torch.from_numpy(w).to(device=device, dtype=torch.float32)
+    for s in range(first, first + n_base, chunk):
+        e = min(first + n_base, s + chunk)
+        g = torch.Generator(device=device)
+        g.manual_seed((1000 * workload + ROLE_BASE) * (1 << 24) + s // chunk)
+        c = torch.randint(0, n_comp, (e - s,), generator=g, device=device)
+        z = torch.randn((e - s, rank, 1), generator=g, device=device, dtype=torch.float32)
+        x = torch.randn((e - s, dim), generator=g, device=device, dtype=torch.float32).mul_(noise)
+        x += means[c]
+        for o in range(0, e - s, sub):
+            x[o:o + sub] += torch.bmm(w[c[o:o + sub]], z[o:o + sub]).squeeze(-1)
+        yield s, x
+
+
+def lowrank_queries(workload: int, n_query: int, dim: int, n_comp: int, rank: int = 16,
+                    noise: float = 0.1, query_zipf: float | None = 1.2, chunk: int = 8192):
+    """Queries of lowrank_mixture on the host, components Zipf(query_zipf)."""
+    means, w = lowrank_mixture(workload, dim, n_comp, rank)
+    qp = None if query_zipf is None else zipf_weights(n_comp, query_zipf, rng(workload, ROLE_CLUSTER))
+    g = rng(workload, ROLE_QUERIES)
+    out = np.empty((n_query, dim), dtype=np.float32)
+    for s in range(0, n_query, chunk):
+        e = min(n_query, s + chunk)
+        c = g.choice(n_comp, size=e - s, p=qp) if qp is not None else g.integers(0, n_comp, e - s)
+        z = g.standard_normal((e - s, rank))
+        x = means[c] + np.einsum("nij,nj->ni", w[c], z) + noise * g.standard_normal((e - s, dim))
+        out[s:e] = x.astype(np.float32)
+    return out
 
 
 # ----------------------------------------------------------------------------

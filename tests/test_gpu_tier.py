@@ -244,3 +244,27 @@ def test_classic_policies_match_oracle_replay(state, policy, warm):
     assert got == hits.tolist()
     assert sum(got) > 0
     assert g.stats()["cache_evictions"] > 0
+
+
+def test_kept_in_degrees_match_a_recount_under_updates():
+    """The in-degrees the placement uses are kept current by the insert,
+    delete, repair and consolidation kernels; with cache_indegree_verify each
+    placement step recounts them and fails on any difference."""
+    base, q = datagen.gmm_uint8_valued(706, 4000, 200, 32, 8)
+    g = svf.Index(32, 12, svf.METRIC_L2, seed=5, insert_batch_max=300)
+    g.set_option("cache_bytes", 800 * 32 * 4)
+    g.set_option("cache_indegree_verify", 1)
+    g.build(base[:2500])
+    g.search(q[:50], 10, 32)                                   # counts once, then kept
+    g.insert(base[2500:3200])
+    g.search(q[50:100], 10, 32)
+    rows = g.export_graph()[0]
+    keep = np.array([10, 20, 30, 40])
+    gone = np.setdiff1d(rows[keep, :8].ravel(), keep).astype(np.int32)
+    g.delete(gone)                                             # 8 of 12 neighbours: localized repair
+    assert g.stats()["last_repaired"] > 0
+    g.search(q[100:150], 10, 32)
+    g.delete(np.arange(1000, 3200, 4, dtype=np.int32))         # past 20%: consolidation
+    g.insert(base[3200:])
+    g.search(q[150:], 10, 32)
+    assert g.get_option("cache_indegree_verify") == 1

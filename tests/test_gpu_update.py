@@ -121,3 +121,28 @@ def test_build_float_recall_and_invariants():
     gi, gd = g.search(q, 10, 64)
     gt_i, gt_d = O.bruteforce(base, q, 10)
     assert O.recall_at_k(gi, oix.query_dists(q, gi), gt_d, 10) >= 0.95
+
+
+@pytest.mark.parametrize("pass_stream", [True, False])
+def test_insert_dev_waits_for_the_producer(pass_stream):
+    """svf_insert_dev reads device vectors only after the work queued on the
+    given stream (or the default stream) has finished: vectors whose
+    producer is still running insert exactly as host vectors do."""
+    import torch
+    base, _ = datagen.gmm_uint8_valued(705, 3000, 10, 64, 8)
+    host = svf.Index(64, 16, svf.METRIC_L2, seed=4, insert_batch_max=500)
+    dev = svf.Index(64, 16, svf.METRIC_L2, seed=4, insert_batch_max=500)
+    for g in (host, dev):
+        g.build(base[:2000])
+    host.insert(base[2000:])
+    src = torch.from_numpy(np.ascontiguousarray(base[2000:])).cuda()
+    torch.cuda.synchronize()
+    busy = torch.full((2048, 2048), 1.0 / 2048, device="cuda")
+    for _ in range(30):                        # keep the stream busy ahead of the copy
+        busy = busy @ busy
+    zero = torch.where(torch.isfinite(busy[0, 0]), busy[0, 0] * 0, torch.zeros((), device="cuda"))
+    x = src + zero
+    stream = torch.cuda.current_stream().cuda_stream if pass_stream else None
+    dev.insert_dev(x.data_ptr(), x.shape[0], stream=stream)
+    for a, b in zip(host.export_graph(), dev.export_graph()):
+        np.testing.assert_array_equal(a, b)
