@@ -94,7 +94,7 @@ int svf_destroy(svf_index *ix);
  *   coop_max_batch  with search_width 2 or 4, batches of at most this many queries run
  *                   one wave per parent, the waves of a query sharing its pool (results
  *                   unchanged; FP32/BF16/FP8, degree <= 64, dim <= 256, untiered)
- *                   (0..2^24; 1024; 0 = never)
+ *                   (0..2^22; 1024; 0 = never)
  *   visited_slots   LDS visited-table slots per query, power of two (256..16384; 4096)
  *   visited_compact exact quotient tags of a scrambled id (12-bit, five per 64-bit set, or
  *                   16-bit, four per set) instead of full 32-bit ids, when the ids fit (0/1; 1)
@@ -175,7 +175,8 @@ int svf_consolidate(svf_index *ix);
  * entries (k <= beam <= 512) from random entry points, stopping when every
  * pool entry is expanded; the k nearest found are written to out_ids and
  * out_dists (nq x k each, ascending).  Fewer than k alive vectors: the rest
- * is padded with id -1 and distance +inf. */
+ * is padded with id -1 and distance +inf.  nq <= 2^25 per call (SVF_E_INVAL
+ * beyond). */
 int svf_search(svf_index *ix, const float *queries, int64_t nq, int32_t k, int32_t beam,
                int32_t *out_ids, float *out_dists);
 

@@ -6,6 +6,11 @@
 
 namespace svf {
 
+// Grids are capped at kMaxBlocks workgroups and walk their work in a
+// grid-stride loop: a dispatch's work-items in one dimension must stay below
+// 2^32, which one workgroup per row of a 200M-row table would exceed.
+constexpr int64_t kMaxBlocks = 1 << 20;
+
 constexpr int kWave = 64;
 constexpr uint64_t kKeyInf = ~0ull;      // empty / padding key, flag bit set
 constexpr uint32_t kEmpty = 0xffffffffu; // empty slot of an LDS id table

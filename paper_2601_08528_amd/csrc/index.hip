@@ -591,7 +591,7 @@ int insert_stream(svf_index* ix, const float* d, int64_t n, int32_t* d_out_ids, 
 
 int check_search_args(const svf_index* ix, int64_t nq, int k, int beam) {
   if (!ix) return fail(SVF_E_INVAL, "null index");
-  if (nq < 0 || nq > INT32_MAX) return fail(SVF_E_INVAL, "nq out of range");
+  if (nq < 0 || nq > (1 << 25)) return fail(SVF_E_INVAL, "nq must be in [0, 2^25]");
   if (k < 1) return fail(SVF_E_INVAL, "k must be >= 1");
   if (beam < k) return fail(SVF_E_INVAL, "beam must be >= k");
   if (beam > kMaxBeam) return fail(SVF_E_INVAL, "beam must be <= 512");
@@ -1207,7 +1207,7 @@ int svf_set_option(svf_index* ix, const char* key, double v) {
     if (!is_int(v) || v < ix->R || v > kMaxBeam) return fail(SVF_E_INVAL, "beam_insert in [degree, 512]");
     o.beam_insert = (int)v;
   } else if (k == "coop_max_batch") {
-    if (!is_int(v) || v < 0 || v > (1 << 24)) return fail(SVF_E_INVAL, "coop_max_batch in [0, 2^24]");
+    if (!is_int(v) || v < 0 || v > (1 << 22)) return fail(SVF_E_INVAL, "coop_max_batch in [0, 2^22]");
     o.coop_max_batch = (int)v;
   } else if (k == "entry_samples") {
     if (!is_int(v) || v < 0 || v > kMaxEntries) return fail(SVF_E_INVAL, "entry_samples in [0, 1024]");

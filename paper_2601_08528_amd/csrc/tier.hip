@@ -2,6 +2,8 @@
 // the placement kernel that copies promoted rows from the host-resident store
 // into HBM cache slots and updates the device mapping table (Sec. 4.2: the
 // mapping h_id -> d_id | NONE; Sec. 4.3: promotion of missed vectors).
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -10,19 +12,19 @@ namespace svf {
 // E_in(x): edges pointing at x from alive vertices.
 __global__ void indegree_kernel(const int32_t* __restrict__ graph, const uint32_t* __restrict__ alive,
                                 int64_t n, int R, int32_t* __restrict__ e_in) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n * R) return;
-  const int64_t u = i / R;
-  if (!alive_bit(alive, (int32_t)u)) return;
-  const int32_t x = graph[i];
-  if (x >= 0) atomicAdd(&e_in[x], 1);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * R;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t x = graph[i];
+    if (x >= 0 && alive_bit(alive, (int32_t)(i / R))) atomicAdd(&e_in[x], 1);
+  }
 }
 hipError_t launch_indegree(const int32_t* graph, const uint32_t* alive, int64_t n, int R,
                            int32_t* e_in, hipStream_t st) {
   hipError_t e = launch_fill_u32(e_in, n, 0u, st);
   if (e != hipSuccess || n <= 0) return e;
   const int64_t t = n * R;
-  hipLaunchKernelGGL(indegree_kernel, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st, graph,
+  hipLaunchKernelGGL(indegree_kernel, dim3((unsigned)std::min<int64_t>((t + 255) / 256, kMaxBlocks)),
+                     dim3(256), 0, st, graph,
                      alive, n, R, e_in);
   return hipGetLastError();
 }
@@ -32,26 +34,29 @@ hipError_t launch_indegree(const int32_t* graph, const uint32_t* alive, int64_t 
 // the cache slot, then the mapping entries of both ids are updated (a new id
 // of -1 only releases the slot).  No two placements of one batch share a slot
 // or an id.
-__global__ void place_kernel(const int32_t* __restrict__ place, const float* __restrict__ store,
-                             float* __restrict__ cache, int64_t stride, int32_t* __restrict__ map) {
-  const int p = blockIdx.x;
-  const int32_t slot = place[3 * p], nid = place[3 * p + 1], oid = place[3 * p + 2];
-  if (nid >= 0) {
-    const float* src = store + (int64_t)nid * stride;
-    float* dst = cache + (int64_t)slot * stride;
-    for (int64_t e = threadIdx.x; e < stride; e += blockDim.x) dst[e] = src[e];
-  }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    if (oid >= 0) map[oid] = -1;
-    if (nid >= 0) map[nid] = slot;
+__global__ void place_kernel(const int32_t* __restrict__ place, int64_t np,
+                             const float* __restrict__ store, float* __restrict__ cache,
+                             int64_t stride, int32_t* __restrict__ map) {
+  for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
+    const int32_t slot = place[3 * p], nid = place[3 * p + 1], oid = place[3 * p + 2];
+    if (nid >= 0) {
+      const float* src = store + (int64_t)nid * stride;
+      float* dst = cache + (int64_t)slot * stride;
+      for (int64_t e = threadIdx.x; e < stride; e += blockDim.x) dst[e] = src[e];
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (oid >= 0) map[oid] = -1;
+      if (nid >= 0) map[nid] = slot;
+    }
   }
 }
 hipError_t launch_place(const int32_t* place, int np, const float* store, float* cache,
                         int64_t stride, int32_t* map, hipStream_t st) {
   if (np <= 0) return hipSuccess;
-  hipLaunchKernelGGL(place_kernel, dim3(np), dim3(128), 0, st, place, store, cache, stride, map);
+  hipLaunchKernelGGL(place_kernel, dim3((unsigned)std::min<int64_t>(np, kMaxBlocks)), dim3(128), 0, st,
+                     place, (int64_t)np, store, cache, stride, map);
   return hipGetLastError();
 }
 

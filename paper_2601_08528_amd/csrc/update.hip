@@ -14,6 +14,8 @@
 // Every batch reads one snapshot and writes staged rows; a commit kernel
 // copies them into the graph afterwards, so the result never depends on the
 // order in which waves run.
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "wave_ops.hpp"
@@ -202,19 +204,21 @@ __global__ __launch_bounds__(256) void store_fp8_kernel(const float* __restrict_
                                                         uint8_t* __restrict__ dst,
                                                         int64_t lp_stride, float* __restrict__ scale,
                                                         int64_t nrows) {
-  const int64_t r = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave;
-  if (r >= nrows) return;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
   const int lane = lane_id();
-  const float* x = src + r * stride;
-  float m = 0.0f;
-  for (int i = lane; i < dim; i += kWave) m = __builtin_fmaxf(m, __builtin_fabsf(x[i]));
+  for (int64_t r = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave; r < nrows;
+       r += waves) {
+    const float* x = src + r * stride;
+    float m = 0.0f;
+    for (int i = lane; i < dim; i += kWave) m = __builtin_fmaxf(m, __builtin_fabsf(x[i]));
 #pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) m = __builtin_fmaxf(m, __shfl_xor(m, o));
-  const float s = fp8_scale_of(m);
-  uint8_t* y = dst + r * lp_stride;
-  for (int i = lane; i < lp_stride; i += kWave)
-    y[i] = i < dim ? (uint8_t)f32_to_e4m3_sat(__fdiv_rn(x[i], s)) : (uint8_t)0;
-  if (lane == 0) scale[r] = s;
+    for (int o = 1; o < kWave; o <<= 1) m = __builtin_fmaxf(m, __shfl_xor(m, o));
+    const float s = fp8_scale_of(m);
+    uint8_t* y = dst + r * lp_stride;
+    for (int i = lane; i < lp_stride; i += kWave)
+      y[i] = i < dim ? (uint8_t)f32_to_e4m3_sat(__fdiv_rn(x[i], s)) : (uint8_t)0;
+    if (lane == 0) scale[r] = s;
+  }
 }
 
 hipError_t launch_store_lowp(const float* vec32, int64_t stride, int dim, void* veclp,
@@ -222,8 +226,7 @@ hipError_t launch_store_lowp(const float* vec32, int64_t stride, int dim, void* 
                              int precision, hipStream_t st) {
   if (nrows <= 0 || precision == 0) return hipSuccess;
   if (precision == 3) {
-    const int64_t blocks = (nrows + 3) / 4;
-    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    const int64_t blocks = std::min<int64_t>((nrows + 3) / 4, kMaxBlocks);
     hipLaunchKernelGGL(store_fp8_kernel, dim3((unsigned)blocks), dim3(256), 0, st,
                        vec32 + row0 * stride, stride, dim,
                        static_cast<uint8_t*>(veclp) + row0 * lp_stride, lp_stride, vscale + row0,
@@ -422,10 +425,15 @@ hipError_t launch_reverse_scan_scatter(const ReverseArgs& a, int n_targets, hipS
 // One wave per target: candidates = alive row entries (stored distances) and
 // the new vertices pointing at it, the `cap` smallest in (d,id) order, pruned
 // against the pre-batch rows of old vertices and the forward rows of new ones.
+__device__ void reverse_prune_one(ReverseArgs a, int k, unsigned char* smem);
 __global__ __launch_bounds__(64) void reverse_prune_kernel(ReverseArgs a, int n_targets) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int k = blockIdx.x;
-  if (k >= n_targets) return;
+  for (int k = blockIdx.x; k < n_targets; k += gridDim.x) {
+    reverse_prune_one(a, k, smem);
+    __syncthreads();
+  }
+}
+__device__ void reverse_prune_one(ReverseArgs a, int k, unsigned char* smem) {
   const int lane = lane_id();
   const int cap = a.cap;
   WaveCtx w;
@@ -460,20 +468,23 @@ __global__ __launch_bounds__(64) void reverse_prune_kernel(ReverseArgs a, int n_
 hipError_t launch_reverse_prune(const ReverseArgs& a, int n_targets, hipStream_t st) {
   if (n_targets <= 0) return hipSuccess;
   const size_t lds = (size_t)(2 * a.cap + kWave) * 8 + prune_scratch_bytes(a.cap);
-  hipLaunchKernelGGL(reverse_prune_kernel, dim3(n_targets), dim3(kWave), lds, st, a, n_targets);
+  const int blocks = (int)std::min<int64_t>(n_targets, kMaxBlocks);
+  hipLaunchKernelGGL(reverse_prune_kernel, dim3(blocks), dim3(kWave), lds, st, a, n_targets);
   return hipGetLastError();
 }
 
 // Commit of a batch: target rows, forward rows of the new ids, alive bits,
 // and reset of the per-target counts.
 __global__ void commit_targets_kernel(ReverseArgs a, int n_targets, int32_t* graph, float* edge_d) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= (int64_t)n_targets * a.R) return;
-  const int k = (int)(i / a.R), r = (int)(i - (int64_t)k * a.R);
-  const int32_t t = a.tlist[k];
-  graph[(int64_t)t * a.R + r] = a.trow[i];
-  edge_d[(int64_t)t * a.R + r] = a.trow_d[i];
-  if (r == 0) a.tcount[t] = 0;
+  const int64_t n = (int64_t)n_targets * a.R;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(i / a.R), r = (int)(i - (int64_t)k * a.R);
+    const int32_t t = a.tlist[k];
+    graph[(int64_t)t * a.R + r] = a.trow[i];
+    edge_d[(int64_t)t * a.R + r] = a.trow_d[i];
+    if (r == 0) a.tcount[t] = 0;
+  }
 }
 __global__ void commit_new_kernel(ReverseArgs a, int32_t* graph, float* edge_d, uint32_t* alive) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -489,8 +500,8 @@ hipError_t launch_commit_batch(const ReverseArgs& a, int n_targets, int32_t* gra
                                uint32_t* alive, hipStream_t st) {
   if (n_targets > 0) {
     const int64_t n = (int64_t)n_targets * a.R;
-    hipLaunchKernelGGL(commit_targets_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
-                       a, n_targets, graph, edge_d);
+    hipLaunchKernelGGL(commit_targets_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, kMaxBlocks)),
+                       dim3(256), 0, st, a, n_targets, graph, edge_d);
   }
   const int64_t n = (int64_t)a.b * a.R;
   if (n > 0)
@@ -506,32 +517,34 @@ hipError_t launch_commit_batch(const ReverseArgs& a, int n_targets, int32_t* gra
 __global__ __launch_bounds__(64) void indegree_rows_delta_kernel(const int32_t* __restrict__ graph,
                                                                  const int32_t* __restrict__ list,
                                                                  const int32_t* __restrict__ rows,
-                                                                 int R, int32_t* __restrict__ e_in) {
+                                                                 int n, int R, int32_t* __restrict__ e_in) {
   __shared__ int32_t old_r[128], new_r[128];
-  const int k = blockIdx.x;
-  const int64_t t = list[k];
-  for (int r = threadIdx.x; r < R; r += kWave) {
-    old_r[r] = graph[t * R + r];
-    new_r[r] = rows[(int64_t)k * R + r];
-  }
-  __syncthreads();
-  for (int r = threadIdx.x; r < R; r += kWave) {
-    const int32_t o = old_r[r], w = new_r[r];
-    bool o_kept = false, w_had = false;
-    for (int j = 0; j < R; ++j) {
-      o_kept |= new_r[j] == o;
-      w_had |= old_r[j] == w;
+  for (int k = blockIdx.x; k < n; k += gridDim.x) {
+    const int64_t t = list[k];
+    for (int r = threadIdx.x; r < R; r += kWave) {
+      old_r[r] = graph[t * R + r];
+      new_r[r] = rows[(int64_t)k * R + r];
     }
-    if (o >= 0 && !o_kept) atomicSub(&e_in[o], 1);
-    if (w >= 0 && !w_had) atomicAdd(&e_in[w], 1);
+    __syncthreads();
+    for (int r = threadIdx.x; r < R; r += kWave) {
+      const int32_t o = old_r[r], w = new_r[r];
+      bool o_kept = false, w_had = false;
+      for (int j = 0; j < R; ++j) {
+        o_kept |= new_r[j] == o;
+        w_had |= old_r[j] == w;
+      }
+      if (o >= 0 && !o_kept) atomicSub(&e_in[o], 1);
+      if (w >= 0 && !w_had) atomicAdd(&e_in[w], 1);
+    }
+    __syncthreads();
   }
 }
 hipError_t launch_indegree_rows_delta(const int32_t* graph, const int32_t* list, int n,
                                       const int32_t* rows, int R, int32_t* e_in, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   if (R > 128) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(indegree_rows_delta_kernel, dim3((unsigned)n), dim3(kWave), 0, st, graph, list,
-                     rows, R, e_in);
+  hipLaunchKernelGGL(indegree_rows_delta_kernel, dim3((unsigned)std::min<int64_t>(n, kMaxBlocks)),
+                     dim3(kWave), 0, st, graph, list, rows, n, R, e_in);
   return hipGetLastError();
 }
 // Rows of vertices that become alive: one count to each entry.
@@ -742,19 +755,20 @@ hipError_t launch_topup_merge(const RepairArgs& a, const uint64_t* pool, int L, 
 
 __global__ void commit_rows_kernel(const int32_t* list, int n, const int32_t* rows,
                                    const float* rows_d, int R, int32_t* graph, float* edge_d) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= (int64_t)n * R) return;
-  const int k = (int)(i / R), r = (int)(i - (int64_t)k * R);
-  const int64_t v = list[k];
-  graph[v * R + r] = rows[i];
-  edge_d[v * R + r] = rows_d[i];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (int64_t)n * R;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(i / R), r = (int)(i - (int64_t)k * R);
+    const int64_t v = list[k];
+    graph[v * R + r] = rows[i];
+    edge_d[v * R + r] = rows_d[i];
+  }
 }
 hipError_t launch_commit_rows(const int32_t* list, int n, const int32_t* rows, const float* rows_d,
                               int R, int32_t* graph, float* edge_d, hipStream_t st) {
   const int64_t t = (int64_t)n * R;
   if (t <= 0) return hipSuccess;
-  hipLaunchKernelGGL(commit_rows_kernel, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st, list,
-                     n, rows, rows_d, R, graph, edge_d);
+  hipLaunchKernelGGL(commit_rows_kernel, dim3((unsigned)std::min<int64_t>((t + 255) / 256, kMaxBlocks)),
+                     dim3(256), 0, st, list, n, rows, rows_d, R, graph, edge_d);
   return hipGetLastError();
 }
 
