@@ -556,6 +556,102 @@ def full_tier_bench(torch, svf, datagen, n_base, cache_gb=None, steps=8, sample=
     return out
 
 
+def workloads_bench(torch, svf, datagen, n=1_000_000, beam=64, nq=2000, evals=10):
+    """Streaming workload families of the paper (SlidingWindow, ExpirationTime,
+    Clustered; datagen's operation sequences) over n x 128 rows of a 64-component
+    low-rank mixture, L2, degree 32, under the three deletion strategies the
+    paper compares: lazy deletion alone, with global consolidation at 20%, and
+    with localized repair as well (the method).  Recall@10 of nq queries at
+    `evals` evenly spaced steps, against the exact top-10 of the live rows;
+    insert and delete times are summed over the whole sequence.  Also the
+    share of alive vertices by share of deleted neighbours after a lazy 10%
+    deletion."""
+    W, dim, R, ncomp = 8, 128, 32, 64
+    base, comps = datagen.lowrank_points(W, datagen.ROLE_BASE, n, dim, ncomp)
+    queries = datagen.lowrank_queries(W, nq, dim, ncomp, query_zipf=None)
+    base_t = torch.from_numpy(base).cuda()
+    q_t = torch.from_numpy(queries).cuda()
+    bufs = (torch.empty((nq, K), dtype=torch.int32, device="cuda"),
+            torch.empty((nq, K), dtype=torch.float32, device="cuda"),
+            torch.empty(nq, dtype=torch.int32, device="cuda"),
+            torch.empty(nq, dtype=torch.int32, device="cuda"))
+    # Clustered fills empty regions one cluster at a time; insert batches do
+    # not see their batch-mates, so they are kept small there (500 rows).
+    fams = {"sliding_window": (datagen.sliding_window_ops(n), 10_000),
+            "expiration_time": (datagen.expiration_time_ops(W, n), 10_000),
+            "clustered": (datagen.clustered_ops(W, comps, ncomp), 500)}
+    modes = {"lazy": dict(localized_repair=0, consolidate_frac=0.0),
+             "lazy+consolidation": dict(localized_repair=0, consolidate_frac=0.2),
+             "lazy+consolidation+localized_repair": dict(localized_repair=1, consolidate_frac=0.2)}
+    out = {"workload": "%dk x 128 mixture of 64 rank-16 components, L2, degree 32, beam %d, "
+                       "%d uniform queries per evaluation" % (n // 1000, beam, nq), "families": {}}
+    for fam, ((ops, first), ibm) in fams.items():
+        at = set(np.linspace(first, len(ops) - 1, evals).round().astype(int).tolist())
+        res = {}
+        for mname, mopts in modes.items():
+            ix = svf.Index(dim, R, svf.METRIC_L2, seed=0, insert_batch_max=ibm, **mopts)
+            id2row = np.full(n, -1, np.int64)
+            row2id = np.full(n, -1, np.int64)
+            alive = np.zeros(n, bool)
+            t_ins = t_del = 0.0
+            recs, sms = [], []
+            for t, (ins, dele) in enumerate(ops):
+                if len(ins):
+                    t0 = time.perf_counter()
+                    ids = ix.insert(base[ins])
+                    t_ins += time.perf_counter() - t0
+                    id2row[ids] = ins
+                    row2id[ins] = ids
+                    alive[ins] = True
+                if len(dele):
+                    t0 = time.perf_counter()
+                    ix.delete(row2id[dele].astype(np.int32))
+                    t_del += time.perf_counter() - t0
+                    alive[dele] = False
+                if t in at:
+                    live = torch.from_numpy(np.nonzero(alive)[0]).cuda()
+                    kth = exact_kth(torch, base_t[live], q_t, K, chunk=256)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    run_search(torch, ix, q_t, beam, bufs)
+                    torch.cuda.synchronize()
+                    sms.append((time.perf_counter() - t0) * 1e3)
+                    ids = bufs[0].long()
+                    rows = torch.from_numpy(id2row).cuda()[ids.clamp_min(0)]
+                    ex = ((base_t[rows].double() - q_t[:, None, :].double()) ** 2).sum(-1)
+                    hit = (ids >= 0) & (ex <= kth[:, None])
+                    recs.append(hit.double().mean().item())
+            ix.close()
+            res[mname] = {"mean_recall@10": round(float(np.mean(recs)), 4),
+                          "min_recall@10": round(float(np.min(recs)), 4),
+                          "insert_s": round(t_ins, 3), "delete_s": round(t_del, 3),
+                          "search_ms_%d_queries" % nq: round(float(np.mean(sms)), 3)}
+            log("workloads %s %s: recall %.4f, delete %.2f s, insert %.2f s"
+                % (fam, mname, res[mname]["mean_recall@10"], t_del, t_ins))
+        out["families"][fam] = {"steps": len(ops), "insert_batch_max": ibm,
+                                "evaluated_steps": sorted(at), "modes": res}
+    # deleted-neighbour shares after deleting 10% of the vertices lazily
+    ix = svf.Index(dim, R, svf.METRIC_L2, seed=0, localized_repair=0, consolidate_frac=0.0)
+    ix.build(base)
+    g = np.random.Generator(np.random.Philox(11))
+    gone = g.choice(n, n // 10, replace=False).astype(np.int32)
+    ix.delete(gone)
+    rows, _, al = ix.export_graph()
+    ix.close()
+    al = al.astype(bool)
+    valid = rows >= 0
+    dead = valid & ~al[np.where(valid, rows, 0)]
+    share = dead.sum(1) / np.maximum(valid.sum(1), 1)
+    share = share[al]
+    out["deleted_neighbour_share_after_10pct"] = {
+        "below_10pct": round(float((share < 0.1).mean()), 4),
+        "10_to_40pct": round(float(((share >= 0.1) & (share < 0.4)).mean()), 4),
+        "40pct_or_more": round(float((share >= 0.4).mean()), 4),
+        "above_half_(repaired_by_localized_repair)": round(float((share > 0.5).mean()), 5)}
+    del base_t
+    return out
+
+
 def policy_bench(torch, svf, datagen, n_total=2_000_000, steps=12, measured=8, beam=64,
                  ratios=(0.2, 0.4, 0.6, 0.8, 1.0)):
     """Replacement-policy ablation under a sliding window on the tiered store.
@@ -659,6 +755,8 @@ def main():
                     help="skip the large-footprint (5M x 96) search leg")
     ap.add_argument("--large-n", type=int, default=5_000_000)
     ap.add_argument("--no-tier", action="store_true", help="skip the tiered-store leg")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the workload-family / deletion-strategy ablation")
     ap.add_argument("--no-policies", action="store_true",
                     help="skip the replacement-policy and memory-share ablation")
     ap.add_argument("--tier-n", type=int, default=4_000_000)
@@ -835,6 +933,12 @@ def main():
         torch.cuda.empty_cache()
         full_tier = full_tier_bench(torch, svf, datagen, args.full_tier)
 
+    workloads = None
+    if not args.no_workloads:
+        log("workload families and deletion strategies")
+        torch.cuda.empty_cache()
+        workloads = workloads_bench(torch, svf, datagen)
+
     policies = None
     if not args.no_policies:
         log("replacement policies")
@@ -902,6 +1006,7 @@ def main():
         "large_footprint": large,
         "tiered": tier,
         "cache_policies": policies,
+        "workload_families": workloads,
         "tiered_full_size": full_tier,
         "serving": serving,
         "wall_s_timed": round(wall, 4),

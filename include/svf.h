@@ -100,7 +100,9 @@ int svf_destroy(svf_index *ix);
  *                   16-bit, four per set) instead of full 32-bit ids, when the ids fit (0/1; 1)
  *   repair_c        out-neighbours taken from each deleted neighbour (1..min(16, degree); 8)
  *   prune_cap       longest candidate list given to the prune, 0 = max(4*degree, beam_insert)
- *   consolidate_frac deleted fraction that triggers consolidation ((0,1]; 0.2)
+ *   consolidate_frac deleted fraction that triggers consolidation ([0,1]; 0.2; 0 = never)
+ *   localized_repair repair the affected vertices after each deletion (0/1; 1).  With 0
+ *                   and consolidate_frac 0 deletion is lazy only (the paper's ablation)
  *   insert_batch_max largest batch of one insertion pass (1..1<<20; 10000)
  *   precision       SVF_PREC_* of traversal distances (0..3; 0).  FP16/BF16: each element
  *                   rounded to nearest even.  FP8: OCP E4M3 codes of x / s with one FP32
@@ -305,11 +307,12 @@ int svf_import_graph(svf_index *ix, const float *vecs, int64_t n, const int32_t 
 /* Checkpoint to a file: the FP32 vectors, rows, edge distances, alive flags,
  * deletion counters and the options that shape results (seed, beam_insert,
  * entry_samples, max_iters, search_width, visited_slots, visited_compact,
- * repair_c, prune_cap, consolidate_frac, insert_batch_max, precision,
- * rerank).  Not saved: a fitted predictor, the tiered-store state and the
+ * repair_c, prune_cap, consolidate_frac, localized_repair, insert_batch_max,
+ * precision, rerank).  Not saved: a fitted predictor, the tiered-store state and the
  * serving loop (a loaded index starts without them).  Format: the 8 bytes
- * "SVFIDX01", a fixed header, the arrays, then a 64-bit checksum of all that
- * precedes it; little-endian.  Not while serving (SVF_E_BUSY); a file that
+ * "SVFIDX01", a fixed header (format version 2; version 1 files, which lack
+ * localized_repair, still load), the arrays, then a 64-bit checksum of all
+ * that precedes it; little-endian.  Not while serving (SVF_E_BUSY); a file that
  * cannot be written gives SVF_E_INTERNAL and may be left incomplete. */
 int svf_save(const svf_index *ix, const char *path);
 /* Resume from svf_save's file into a new handle (*out; NULL on failure).

@@ -58,6 +58,7 @@ typedef struct {
     int search_width;     /* parents expanded per iteration                  */
     int max_iters;        /* 0: no cap                                       */
     int repair_c;         /* c of the localized repair                       */
+    int localized_repair; /* repair affected vertices after each deletion    */
     int prune_cap;        /* longest candidate list handed to the prune      */
     int precision;        /* ORC_P_*: value grid of the search distances     */
     double consolidate_frac;
@@ -177,6 +178,7 @@ orc_index *orc_create(int dim, int R, int metric, uint64_t seed)
     ix->search_width = 1;
     ix->max_iters = 0;
     ix->repair_c = 8;
+    ix->localized_repair = 1;
     ix->prune_cap = 0;   /* 0: max(4R, beam_insert) */
     ix->precision = ORC_P_FP32;
     ix->consolidate_frac = 0.2;
@@ -206,7 +208,8 @@ int orc_set(orc_index *ix, const char *key, double v)
     else if (!strcmp(key, "max_iters")) { if (v < 0) return ORC_E_INVAL; ix->max_iters = (int)v; }
     else if (!strcmp(key, "repair_c")) { if (v < 1) return ORC_E_INVAL; ix->repair_c = (int)v; }
     else if (!strcmp(key, "prune_cap")) { if (v < 0) return ORC_E_INVAL; ix->prune_cap = (int)v; }
-    else if (!strcmp(key, "consolidate_frac")) { if (v <= 0 || v > 1) return ORC_E_INVAL; ix->consolidate_frac = v; }
+    else if (!strcmp(key, "consolidate_frac")) { if (v < 0 || v > 1) return ORC_E_INVAL; ix->consolidate_frac = v; }
+    else if (!strcmp(key, "localized_repair")) { if (v != 0 && v != 1) return ORC_E_INVAL; ix->localized_repair = (int)v; }
     else if (!strcmp(key, "seed")) { ix->seed = (uint64_t)v; }
     else if (!strcmp(key, "insert_batch_max")) { if (v < 1) return ORC_E_INVAL; ix->insert_batch_max = (int64_t)v; }
     else if (!strcmp(key, "precision")) {
@@ -931,11 +934,15 @@ int orc_delete(orc_index *ix, const int32_t *ids, int64_t n)
     ix->n_alive -= newly;
     ix->deleted_since += newly;
     if (newly == 0) return ORC_OK;
-    if ((double)ix->deleted_since >= ix->consolidate_frac * (double)ix->alive_at_consolidate) {
+    /* The paper's deletion ablation separates the three parts: lazy deletion
+     * alone (no repair, consolidate_frac 0 = never), lazy deletion with global
+     * consolidation, and both with localized repair (the method). */
+    if (ix->consolidate_frac > 0 &&
+        (double)ix->deleted_since >= ix->consolidate_frac * (double)ix->alive_at_consolidate) {
         repair(ix, 1);
         ix->deleted_since = 0;
         ix->alive_at_consolidate = ix->n_alive;
-    } else {
+    } else if (ix->localized_repair) {
         repair(ix, 0);
     }
     return ORC_OK;

@@ -638,11 +638,12 @@ int delete_ids(svf_index* ix, const int32_t* ids, int64_t n) {
   ix->n_alive -= newly;
   ix->deleted_since += newly;
   if (newly == 0) return SVF_OK;
-  if ((double)ix->deleted_since >= ix->opt.consolidate_frac * (double)ix->alive_at_consolidate) {
+  if (ix->opt.consolidate_frac > 0 &&
+      (double)ix->deleted_since >= ix->opt.consolidate_frac * (double)ix->alive_at_consolidate) {
     rc = repair(ix, 1);
     ix->deleted_since = 0;
     ix->alive_at_consolidate = ix->n_alive;
-  } else {
+  } else if (ix->opt.localized_repair) {
     rc = repair(ix, 0);
   }
   return rc;
@@ -1233,8 +1234,11 @@ int svf_set_option(svf_index* ix, const char* key, double v) {
     if (!is_int(v) || (v != 0 && (v < ix->R || v > 1024))) return fail(SVF_E_INVAL, "prune_cap 0 or in [degree, 1024]");
     o.prune_cap = (int)v;
   } else if (k == "consolidate_frac") {
-    if (v <= 0 || v > 1) return fail(SVF_E_INVAL, "consolidate_frac in (0, 1]");
+    if (v < 0 || v > 1) return fail(SVF_E_INVAL, "consolidate_frac in [0, 1]");
     o.consolidate_frac = v;
+  } else if (k == "localized_repair") {
+    if (v != 0 && v != 1) return fail(SVF_E_INVAL, "localized_repair 0 or 1");
+    o.localized_repair = (int)v;
   } else if (k == "insert_batch_max") {
     if (!is_int(v) || v < 1 || v > (1 << 20)) return fail(SVF_E_INVAL, "insert_batch_max in [1, 2^20]");
     o.insert_batch_max = (int)v;
@@ -1315,6 +1319,7 @@ int svf_get_option(const svf_index* ix, const char* key, double* out) {
   else if (k == "repair_c") *out = o.repair_c;
   else if (k == "prune_cap") *out = prune_cap(ix);
   else if (k == "consolidate_frac") *out = o.consolidate_frac;
+  else if (k == "localized_repair") *out = o.localized_repair;
   else if (k == "insert_batch_max") *out = o.insert_batch_max;
   else if (k == "precision") *out = o.precision;
   else if (k == "rerank") *out = o.rerank;

@@ -67,6 +67,7 @@ struct Options {
   int visited_slots = 4096;
   int visited_compact = 1;
   int repair_c = 8;
+  int localized_repair = 1;
   int prune_cap = 0;
   double consolidate_frac = 0.2;
   int insert_batch_max = 10000;

@@ -19,14 +19,15 @@ namespace {
 using svf_detail::fail;
 
 constexpr char kMagic[8] = {'S', 'V', 'F', 'I', 'D', 'X', '0', '1'};
-constexpr int32_t kVersion = 1;
+// Version 2 stores localized_repair where version 1 had padding (read as 1).
+constexpr int32_t kVersion = 2;
 
 struct FileHeader {
   int32_t version, dim, R, metric;
   int64_t n_slots, n_alive, deleted_since, alive_at_consolidate;
   uint64_t seed;
   int32_t beam_insert, entry_samples, max_iters, search_width, visited_slots, visited_compact,
-      repair_c, prune_cap, insert_batch_max, precision, rerank, pad;
+      repair_c, prune_cap, insert_batch_max, precision, rerank, localized_repair;
   double consolidate_frac;
 };
 
@@ -118,6 +119,7 @@ int svf_save(const svf_index* cix, const char* path) {
     h.precision = o.precision;
     h.rerank = o.rerank;
     h.consolidate_frac = o.consolidate_frac;
+    h.localized_repair = o.localized_repair;
   }
   int rc = svf_export_graph(ix, rows.data(), ed.data(), alive.data(), n);
   if (rc) return rc;
@@ -148,7 +150,8 @@ int svf_load(const char* path, svf_index** out) {
   if (!get(fl, cs, magic, 8) || std::memcmp(magic, kMagic, 8) != 0)
     return fail(SVF_E_INVAL, "not an index file");
   if (!get(fl, cs, &h, sizeof h)) return fail(SVF_E_INVAL, "truncated header");
-  if (h.version != kVersion) return fail(SVF_E_INVAL, "unsupported file version");
+  if (h.version != kVersion && h.version != 1) return fail(SVF_E_INVAL, "unsupported file version");
+  if (h.version == 1) h.localized_repair = 1;
   if (h.dim < 1 || h.dim > 1024 || h.R < 1 || h.R > 128 || h.n_slots < 0 ||
       h.n_slots > (int64_t)INT32_MAX - 64 || h.n_alive < 0 || h.n_alive > h.n_slots)
     return fail(SVF_E_INVAL, "corrupt header");
@@ -180,6 +183,7 @@ int svf_load(const char* path, svf_index** out) {
       {"consolidate_frac", h.consolidate_frac},
       {"insert_batch_max", (double)h.insert_batch_max},
       {"rerank", (double)h.rerank},
+      {"localized_repair", (double)h.localized_repair},
   };
   for (const auto& kv : opts) {
     if (kv.first == std::string("beam_insert") && h.beam_insert == 0) continue;   // default

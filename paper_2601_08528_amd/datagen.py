@@ -111,20 +111,93 @@ def lowrank_device_chunks(torch, workload: int, n_base: int, dim: int, n_comp: i
         yield s, x
 
 
-def lowrank_queries(workload: int, n_query: int, dim: int, n_comp: int, rank: int = 16,
-                    noise: float = 0.1, query_zipf: float | None = 1.2, chunk: int = 8192):
-    """Queries of lowrank_mixture on the host, components Zipf(query_zipf)."""
+def lowrank_points(workload: int, role: int, n: int, dim: int, n_comp: int, rank: int = 16,
+                   noise: float = 0.1, comp_p=None, chunk: int = 8192):
+    """n points of lowrank_mixture on the host and their components (uniform,
+    or comp_p), from the stream of `role`."""
     means, w = lowrank_mixture(workload, dim, n_comp, rank)
-    qp = None if query_zipf is None else zipf_weights(n_comp, query_zipf, rng(workload, ROLE_CLUSTER))
-    g = rng(workload, ROLE_QUERIES)
-    out = np.empty((n_query, dim), dtype=np.float32)
-    for s in range(0, n_query, chunk):
-        e = min(n_query, s + chunk)
-        c = g.choice(n_comp, size=e - s, p=qp) if qp is not None else g.integers(0, n_comp, e - s)
+    g = rng(workload, role)
+    out = np.empty((n, dim), dtype=np.float32)
+    comps = np.empty(n, dtype=np.int32)
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        c = g.choice(n_comp, size=e - s, p=comp_p) if comp_p is not None else g.integers(0, n_comp, e - s)
         z = g.standard_normal((e - s, rank))
         x = means[c] + np.einsum("nij,nj->ni", w[c], z) + noise * g.standard_normal((e - s, dim))
         out[s:e] = x.astype(np.float32)
-    return out
+        comps[s:e] = c
+    return out, comps
+
+
+def lowrank_queries(workload: int, n_query: int, dim: int, n_comp: int, rank: int = 16,
+                    noise: float = 0.1, query_zipf: float | None = 1.2, chunk: int = 8192):
+    """Queries of lowrank_mixture on the host, components Zipf(query_zipf)."""
+    qp = None if query_zipf is None else zipf_weights(n_comp, query_zipf, rng(workload, ROLE_CLUSTER))
+    return lowrank_points(workload, ROLE_QUERIES, n_query, dim, n_comp, rank, noise, qp, chunk)[0]
+
+
+# ----------------------------------------------------------------------------
+# Streaming workload families (operation sequences only).  Each returns a list
+# of steps (insert ids, delete ids) over rows 0..n-1 of a dataset, and the
+# first step at which evaluation starts.
+# ----------------------------------------------------------------------------
+def sliding_window_ops(n: int, t_max: int = 200):
+    """n rows in t_max equal segments; step t inserts segment t and, from
+    step t_max / 2 on, deletes the segment inserted t_max / 2 steps earlier;
+    evaluation starts at step t_max / 2 + 1 (counting from 1)."""
+    seg = np.array_split(np.arange(n, dtype=np.int32), t_max)
+    half = t_max // 2
+    ops = []
+    for t in range(t_max):
+        dele = seg[t - half] if t >= half else np.empty(0, np.int32)
+        ops.append((seg[t], dele))
+    return ops, half
+
+
+def expiration_time_ops(workload: int, n: int, t_max: int = 200, lifetimes=(10, 50, 100),
+                        ratio=(10, 2, 1)):
+    """Each step inserts the next n / t_max rows; a row lives for 10, 50 or
+    100 steps (drawn 10 : 2 : 1) and is deleted at the step its lifetime
+    ends; evaluation starts once the longest lifetime has passed once."""
+    g = rng(workload, ROLE_STREAM)
+    p = np.asarray(ratio, np.float64) / np.sum(ratio)
+    life = np.asarray(lifetimes)[g.choice(len(lifetimes), size=n, p=p)]
+    seg = np.array_split(np.arange(n, dtype=np.int32), t_max)
+    born = np.empty(n, np.int64)
+    for t, sg in enumerate(seg):
+        born[sg] = t
+    death = born + life
+    ops = []
+    for t in range(t_max):
+        ops.append((seg[t], np.nonzero(death == t)[0].astype(np.int32)))
+    return ops, max(lifetimes)
+
+
+def clustered_ops(workload: int, comps, n_clusters: int, rounds: int = 5):
+    """Spatially correlated updates over clusters of rows (comps[i] is row i's
+    cluster): each round inserts a fresh 1/rounds of every cluster, one
+    cluster per step in a seeded order, then deletes a random half of every
+    cluster's live rows, one cluster per step; evaluation starts after the
+    first round's insertions."""
+    g = rng(workload, ROLE_STREAM)
+    parts = []
+    for c in range(n_clusters):
+        rows_c = np.nonzero(comps == c)[0].astype(np.int32)
+        g.shuffle(rows_c)
+        parts.append(np.array_split(rows_c, rounds))
+    live = [np.empty(0, np.int32) for _ in range(n_clusters)]
+    ops = []
+    none = np.empty(0, np.int32)
+    for r in range(rounds):
+        for c in g.permutation(n_clusters):
+            ops.append((parts[c][r], none))
+            live[c] = np.concatenate([live[c], parts[c][r]])
+        for c in g.permutation(n_clusters):
+            k = len(live[c]) // 2
+            pick = g.permutation(len(live[c]))
+            ops.append((none, np.sort(live[c][pick[:k]])))
+            live[c] = np.sort(live[c][pick[k:]])
+    return ops, n_clusters
 
 
 # ----------------------------------------------------------------------------

@@ -146,3 +146,24 @@ def test_insert_dev_waits_for_the_producer(pass_stream):
     dev.insert_dev(x.data_ptr(), x.shape[0], stream=stream)
     for a, b in zip(host.export_graph(), dev.export_graph()):
         np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("lr,cf", [(0, 0.0), (0, 0.2), (1, 0.0)])
+def test_deletion_modes_bit_exact(lr, cf):
+    """Lazy deletion alone, with global consolidation alone, and with
+    localized repair but no consolidation: graphs equal the oracle's after
+    every delete and after inserts that follow them."""
+    base, _ = datagen.gmm_uint8_valued(707, 3500, 10, 64, 12)
+    oix = oracle_index(base[:3000], 16, seed=9, batch_max=500, localized_repair=lr,
+                       consolidate_frac=cf)
+    g = gpu_from_oracle(oix, base[:3000], seed=9, insert_batch_max=500, localized_repair=lr,
+                        consolidate_frac=cf)
+    gen = np.random.Generator(np.random.Philox(3))
+    for _ in range(3):
+        victims = gen.choice(3000, 250, replace=False).astype(np.int32)
+        assert oix.delete(victims) == 0
+        g.delete(victims)
+        assert_same_graph(g, oix)
+    oix.insert(base[3000:])
+    g.insert(base[3000:])
+    assert_same_graph(g, oix)

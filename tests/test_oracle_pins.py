@@ -325,6 +325,57 @@ def test_insert_properties_and_delete_invariants():
     check_invariants(ix, base)                             # fixed degree, no dead edges
 
 
+def test_deletion_modes_of_the_ablation():
+    """The three deletion strategies the paper compares: lazy deletion alone
+    rewrites no row; with global consolidation alone rows change only once
+    the deleted share reaches consolidate_frac, and then exactly the alive
+    rows that name a deleted id change and none names one afterwards; with
+    localized repair exactly the alive rows with more than half of their
+    entries deleted are rewritten."""
+    base, _ = datagen.gmm_uint8_valued(98, 700, 4, 16, 5)
+
+    def fresh(**o):
+        ix = O.OracleIndex(16, 8, O.L2, seed=7, **o)
+        ix.build(base, batch_max=100)
+        return ix
+
+    rows0, ed0, _ = fresh().export()
+    keep = [3, 50, 111]
+    gone = np.concatenate([rows0[keep, :6].ravel(), np.arange(200, 260)])
+    gone = np.setdiff1d(gone[gone >= 0], keep).astype(np.int32)
+    assert len(gone) < 0.2 * 700
+    alive0 = np.ones(700, bool)
+    alive0[gone] = False
+    valid = rows0 >= 0
+    dead = valid & ~alive0[np.where(valid, rows0, 0)]
+
+    lazy = fresh(localized_repair=0, consolidate_frac=0)
+    assert lazy.delete(gone) == 0
+    r, e, a = lazy.export()
+    assert (r == rows0).all() and (e == ed0).all() and not a[gone].any()
+
+    loc = fresh()
+    assert loc.delete(gone) == 0
+    r, _, _ = loc.export()
+    affected = alive0 & (2 * dead.sum(1) > valid.sum(1))
+    assert affected[keep].all()
+    assert ((r != rows0).any(1) == affected).all()
+
+    con = fresh(localized_repair=0, consolidate_frac=0.2)
+    assert con.delete(gone) == 0
+    assert (con.export()[0] == rows0).all()                # below the threshold
+    more = np.setdiff1d(np.arange(400, 470), keep).astype(np.int32)
+    assert con.delete(more) == 0                           # past 20%: consolidation
+    r, _, a = con.export()
+    alive1 = alive0.copy()
+    alive1[more] = False
+    names_dead = alive1 & (valid & ~alive1[np.where(valid, rows0, 0)]).any(1)
+    assert ((r != rows0).any(1) == names_dead).all()
+    for v in np.nonzero(a)[0]:
+        x = r[v][r[v] >= 0]
+        assert a[x].all()
+
+
 def test_reduced_precision_exact_on_integer_data(small_index):
     base, q = datagen.gmm_uint8_valued(97, 400, 20, 16, 4)
     ix = O.OracleIndex(16, 8, O.L2, seed=6)
