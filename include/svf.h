@@ -103,6 +103,9 @@ int svf_destroy(svf_index *ix);
  *   consolidate_frac deleted fraction that triggers consolidation ([0,1]; 0.2; 0 = never)
  *   localized_repair repair the affected vertices after each deletion (0/1; 1).  With 0
  *                   and consolidate_frac 0 deletion is lazy only (the paper's ablation)
+ *   consolidate_async run a consolidation that falls due in the background on a snapshot
+ *                   and merge it later (svf_consolidate_wait) (0/1; 0; with a tiered
+ *                   store consolidation stays synchronous)
  *   insert_batch_max largest batch of one insertion pass (1..1<<20; 10000)
  *   precision       SVF_PREC_* of traversal distances (0..3; 0).  FP16/BF16: each element
  *                   rounded to nearest even.  FP8: OCP E4M3 codes of x / s with one FP32
@@ -169,8 +172,22 @@ int svf_build(svf_index *ix, const float *vecs, int64_t n);
 int svf_delete(svf_index *ix, const int32_t *ids, int64_t n);
 
 /* Global consolidation (Sec. 5.2): rebuild every alive row that names a
- * deleted vertex.  Afterwards no edge points at a deleted id. */
+ * deleted vertex.  Afterwards no edge points at a deleted id.  A pending
+ * background consolidation is merged first. */
 int svf_consolidate(svf_index *ix);
+/* With consolidate_async = 1, a consolidation that falls due during a delete
+ * runs in the background (Sec. 5.3): on a snapshot of the graph taken then,
+ * on a stream and host thread of its own, while calls continue on the live
+ * graph (insertions are logged; deletions repair locally; a consolidation
+ * that falls due meanwhile waits for this one).  svf_consolidate_wait blocks
+ * until it has finished and merges it into the live graph: the consolidated
+ * rows are written, then each of them is re-pruned with the reverse edges
+ * that insertions since the snapshot gave it.  Rows of vertices inserted
+ * since, and rows the consolidation did not rewrite, keep their live state.
+ * No-op when nothing is pending; the serving loop merges by itself
+ * (SVF_E_BUSY while serving).  A failure of the background pass is reported
+ * here.  svf_get_option(ix, "consolidate_pending") tells whether one is. */
+int svf_consolidate_wait(svf_index *ix);
 
 /* Batched search (Sec. 4.2, Algorithm 1): for each of nq queries (nq x dim
  * FP32, host memory) a best-first search with a candidate pool of `beam`
@@ -266,6 +283,9 @@ int svf_search_listed(svf_index *ix, const float *queries, int64_t nq, int32_t k
  *    search and prune phases run while search batches continue; its commit
  *    and every delete wait for in-flight search batches.  Each committed
  *    insert batch (insert_batch_max vectors) or delete advances the epoch.
+ *  - With consolidate_async, a consolidation runs beside all of this and is
+ *    merged, between mutations and with no search in flight, once it has
+ *    finished; the merge advances the epoch too.
  *  - A search sees the epoch committed when its batch launches, so its
  *    result equals that of the same search issued alone at that point.
  * Submit calls copy their inputs and return a ticket at once; output buffers
@@ -309,7 +329,8 @@ int svf_import_graph(svf_index *ix, const float *vecs, int64_t n, const int32_t 
  * entry_samples, max_iters, search_width, visited_slots, visited_compact,
  * repair_c, prune_cap, consolidate_frac, localized_repair, insert_batch_max,
  * precision, rerank).  Not saved: a fitted predictor, the tiered-store state and the
- * serving loop (a loaded index starts without them).  Format: the 8 bytes
+ * serving loop (a loaded index starts without them).  SVF_E_BUSY while a
+ * background consolidation is pending.  Format: the 8 bytes
  * "SVFIDX01", a fixed header (format version 2; version 1 files, which lack
  * localized_repair, still load), the arrays, then a 64-bit checksum of all
  * that precedes it; little-endian.  Not while serving (SVF_E_BUSY); a file that

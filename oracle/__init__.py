@@ -51,6 +51,7 @@ def lib():
         L.orc_insert.argtypes = [vp, vp, i64, vp]
         L.orc_delete.argtypes = [vp, vp, i64]
         L.orc_consolidate.argtypes = [vp]
+        L.orc_consolidate_wait.argtypes = [vp]
         L.orc_search.argtypes = [vp, vp, i64, i32, i32, i32, vp, vp, vp, vp, vp, vp, i32]
         L.orc_bruteforce.argtypes = [vp, i64, i32, vp, i32, vp, i64, i32, vp, vp, i32]
         L.orc_export.argtypes = [vp, vp, vp, vp]
@@ -135,6 +136,10 @@ class OracleIndex:
 
     def consolidate(self):
         _check(lib().orc_consolidate(self.h))
+
+    def consolidate_wait(self):
+        """Merge a consolidation pending in the background (Sec. 5.3)."""
+        _check(lib().orc_consolidate_wait(self.h))
 
     def search(self, q: np.ndarray, k: int, beam: int, rerank: bool = True, threads: int = 1):
         q = np.ascontiguousarray(q, dtype=np.float32)

@@ -59,6 +59,17 @@ typedef struct {
     int max_iters;        /* 0: no cap                                       */
     int repair_c;         /* c of the localized repair                       */
     int localized_repair; /* repair affected vertices after each deletion    */
+    int consolidate_async; /* consolidations run on a snapshot, merged later */
+    /* a consolidation computed on a snapshot of bg_n0 vertices, staged, and
+     * the forward rows of the vertices inserted since (ids bg_n0 on) */
+    int bg_active;
+    int64_t bg_n0;
+    uint8_t *bg_changed;
+    int32_t *bg_rows;
+    double *bg_rows_d;
+    int32_t *log_rows;
+    double *log_d;
+    int64_t log_n, log_cap;
     int prune_cap;        /* longest candidate list handed to the prune      */
     int precision;        /* ORC_P_*: value grid of the search distances     */
     double consolidate_frac;
@@ -190,7 +201,8 @@ void orc_destroy(orc_index *ix)
 {
     if (!ix) return;
     free(ix->vec); free(ix->vec_lp); free(ix->vec_f32); free(ix->rows); free(ix->edge_d);
-    free(ix->alive); free(ix);
+    free(ix->alive); free(ix->bg_changed); free(ix->bg_rows); free(ix->bg_rows_d);
+    free(ix->log_rows); free(ix->log_d); free(ix);
 }
 
 static int effective_prune_cap(const orc_index *ix)
@@ -210,6 +222,7 @@ int orc_set(orc_index *ix, const char *key, double v)
     else if (!strcmp(key, "prune_cap")) { if (v < 0) return ORC_E_INVAL; ix->prune_cap = (int)v; }
     else if (!strcmp(key, "consolidate_frac")) { if (v < 0 || v > 1) return ORC_E_INVAL; ix->consolidate_frac = v; }
     else if (!strcmp(key, "localized_repair")) { if (v != 0 && v != 1) return ORC_E_INVAL; ix->localized_repair = (int)v; }
+    else if (!strcmp(key, "consolidate_async")) { if (v != 0 && v != 1) return ORC_E_INVAL; ix->consolidate_async = (int)v; }
     else if (!strcmp(key, "seed")) { ix->seed = (uint64_t)v; }
     else if (!strcmp(key, "insert_batch_max")) { if (v < 1) return ORC_E_INVAL; ix->insert_batch_max = (int64_t)v; }
     else if (!strcmp(key, "precision")) {
@@ -674,6 +687,7 @@ static int cmp_cand(const void *a, const void *b) { return cmp_pentry(a, b); }
  * rows of old vertices and the forward rows of new ones.  All rows are
  * committed together at the end of the batch. */
 typedef struct { int32_t v; double d; } incoming;
+static void bg_log(orc_index *ix, const int32_t *fwd, const double *fwd_d, int64_t b);
 
 static int insert_one_batch(orc_index *ix, const float *vecs, int64_t b, int32_t *out_ids)
 {
@@ -752,6 +766,7 @@ static int insert_one_batch(orc_index *ix, const float *vecs, int64_t b, int32_t
         prune(R, m, pid, pdd, snap_row, &sc2, trow + ti * R, trow_d + ti * R);
         tgt[ti++] = (int32_t)t;
     }
+    if (ix->bg_active) bg_log(ix, fwd, fwd_d, b);
     /* Commit. */
     for (int64_t i = 0; i < n_targets; ++i) {
         memcpy(ix->rows + (int64_t)tgt[i] * R, trow + i * R, sizeof(int32_t) * R);
@@ -847,7 +862,7 @@ int orc_build(orc_index *ix, const float *vecs, int64_t n, int64_t batch_max)
  * Consolidation uses the same routine with "at least one deleted neighbour"
  * and c = R.  It runs when the deleted fraction since the last consolidation
  * reaches consolidate_frac (the paper's example threshold is 20%). */
-static void repair(orc_index *ix, int consolidate)
+static void repair_compute(orc_index *ix, int consolidate, int32_t *out, double *out_d, uint8_t *changed)
 {
     const int d = ix->dim, R = ix->R;
     const int64_t n = ix->n_slots;
@@ -861,9 +876,6 @@ static void repair(orc_index *ix, int consolidate)
     int32_t *pid = malloc(sizeof(int32_t) * maxc);
     double *pdd = malloc(sizeof(double) * maxc);
     uint8_t *incand = calloc(n, 1);
-    int32_t *out = malloc(sizeof(int32_t) * n * R);
-    double *out_d = malloc(sizeof(double) * n * R);
-    uint8_t *changed = calloc(n, 1);
     scratch_t s;
     scratch_init(&s, n, ix->beam_insert, ix->search_width, R);
     double xmax = ix->metric == ORC_IP ? max_norm(ix) : 0.0;
@@ -917,12 +929,126 @@ static void repair(orc_index *ix, int consolidate)
         prune(R, m, pid, pdd, snap_row, &sc, out + v * R, out_d + v * R);
         changed[v] = 1;
     }
+    scratch_free(&s);
+    free(pre); free(cl); free(pid); free(pdd); free(incand);
+}
+
+static void commit_rows(orc_index *ix, int64_t n, const int32_t *out, const double *out_d,
+                        const uint8_t *changed)
+{
+    const int R = ix->R;
     for (int64_t v = 0; v < n; ++v) if (changed[v]) {
         memcpy(ix->rows + v * R, out + v * R, sizeof(int32_t) * R);
         memcpy(ix->edge_d + v * R, out_d + v * R, sizeof(double) * R);
     }
-    scratch_free(&s);
-    free(pre); free(cl); free(pid); free(pdd); free(incand); free(out); free(out_d); free(changed);
+}
+
+static void repair(orc_index *ix, int consolidate)
+{
+    const int64_t n = ix->n_slots, R = ix->R;
+    int32_t *out = malloc(sizeof(int32_t) * n * R);
+    double *out_d = malloc(sizeof(double) * n * R);
+    uint8_t *changed = calloc(n, 1);
+    repair_compute(ix, consolidate, out, out_d, changed);
+    commit_rows(ix, n, out, out_d, changed);
+    free(out); free(out_d); free(changed);
+}
+
+/* Consolidation in the background (Sec. 5.3), written out sequentially: a
+ * consolidation on a snapshot equals one computed when the snapshot is
+ * taken, so bg_begin computes it then and keeps the rows staged.  Insertion
+ * batches meanwhile append their forward rows to a log (their ids follow the
+ * snapshot's in order).  The merge writes the staged rows, then re-prunes
+ * every rewritten row that the logged rows name, with the candidates a
+ * reverse-edge update uses (its alive entries with their stored distances,
+ * then the logged vertices pointing at it, in (d,id) order, cut to the prune
+ * cap), against the rows as they stand after the first step; all re-pruned
+ * rows are written at the end.  Other rows keep their live state. */
+static void bg_begin(orc_index *ix)
+{
+    const int64_t n = ix->n_slots, R = ix->R;
+    ix->bg_n0 = n;
+    ix->bg_rows = malloc(sizeof(int32_t) * (n * R + 1));
+    ix->bg_rows_d = malloc(sizeof(double) * (n * R + 1));
+    ix->bg_changed = calloc(n + 1, 1);
+    repair_compute(ix, 1, ix->bg_rows, ix->bg_rows_d, ix->bg_changed);
+    ix->log_n = 0;
+    ix->bg_active = 1;
+}
+
+static void bg_log(orc_index *ix, const int32_t *fwd, const double *fwd_d, int64_t b)
+{
+    const int R = ix->R;
+    if (ix->log_n + b > ix->log_cap) {
+        int64_t cap = ix->log_n + b > 2 * ix->log_cap ? ix->log_n + b : 2 * ix->log_cap;
+        ix->log_rows = realloc(ix->log_rows, sizeof(int32_t) * cap * R);
+        ix->log_d = realloc(ix->log_d, sizeof(double) * cap * R);
+        ix->log_cap = cap;
+    }
+    memcpy(ix->log_rows + ix->log_n * R, fwd, sizeof(int32_t) * b * R);
+    memcpy(ix->log_d + ix->log_n * R, fwd_d, sizeof(double) * b * R);
+    ix->log_n += b;
+}
+
+int orc_consolidate_wait(orc_index *ix)
+{
+    if (!ix->bg_active) return ORC_OK;
+    ix->bg_active = 0;
+    const int R = ix->R;
+    const int64_t n0 = ix->bg_n0, n = ix->n_slots;
+    commit_rows(ix, n0, ix->bg_rows, ix->bg_rows_d, ix->bg_changed);
+    if (ix->log_n > 0) {
+        int64_t *cnt = calloc(n0 + 1, sizeof(int64_t));
+        for (int64_t i = 0; i < ix->log_n * R; ++i) {
+            int32_t t = ix->log_rows[i];
+            if (t >= 0 && t < n0 && ix->bg_changed[t]) cnt[t]++;
+        }
+        int64_t *off = malloc(sizeof(int64_t) * (n0 + 1));
+        off[0] = 0;
+        for (int64_t t = 0; t < n0; ++t) off[t + 1] = off[t] + cnt[t];
+        incoming *inc = malloc(sizeof(incoming) * (off[n0] + 1));
+        int64_t *cur = malloc(sizeof(int64_t) * (n0 + 1));
+        memcpy(cur, off, sizeof(int64_t) * (n0 + 1));
+        for (int64_t i = 0; i < ix->log_n; ++i)
+            for (int r = 0; r < R; ++r) {
+                int32_t t = ix->log_rows[i * R + r];
+                if (t >= 0 && t < n0 && ix->bg_changed[t])
+                    inc[cur[t]++] = (incoming){(int32_t)(n0 + i), ix->log_d[i * R + r]};
+            }
+        int32_t *pre = malloc(sizeof(int32_t) * n * R);
+        memcpy(pre, ix->rows, sizeof(int32_t) * n * R);
+        snap_ctx sc = {pre, n, NULL, 0, R};
+        int cap = effective_prune_cap(ix);
+        int64_t maxin = 0;
+        for (int64_t t = 0; t < n0; ++t) if (cnt[t] > maxin) maxin = cnt[t];
+        pentry *cl = malloc(sizeof(pentry) * (R + maxin + 1));
+        int32_t *pid = malloc(sizeof(int32_t) * (R + maxin + 1));
+        double *pdd = malloc(sizeof(double) * (R + maxin + 1));
+        int32_t *trow = malloc(sizeof(int32_t) * n0 * R + 1);
+        double *trow_d = malloc(sizeof(double) * n0 * R + 1);
+        uint8_t *hit = calloc(n0 + 1, 1);
+        for (int64_t t = 0; t < n0; ++t) {
+            if (!cnt[t]) continue;
+            int m = 0;
+            for (int r = 0; r < R; ++r) {
+                int32_t u = pre[t * R + r];
+                if (u >= 0 && ix->alive[u]) { cl[m].id = u; cl[m].d = ix->edge_d[t * R + r]; ++m; }
+            }
+            for (int64_t e = off[t]; e < off[t + 1]; ++e) { cl[m].id = inc[e].v; cl[m].d = inc[e].d; ++m; }
+            qsort(cl, m, sizeof(pentry), cmp_cand);
+            if (m > cap) m = cap;
+            for (int i = 0; i < m; ++i) { pid[i] = cl[i].id; pdd[i] = cl[i].d; }
+            prune(R, m, pid, pdd, snap_row, &sc, trow + t * R, trow_d + t * R);
+            hit[t] = 1;
+        }
+        commit_rows(ix, n0, trow, trow_d, hit);
+        free(cnt); free(off); free(inc); free(cur); free(pre); free(cl); free(pid); free(pdd);
+        free(trow); free(trow_d); free(hit);
+    }
+    free(ix->bg_rows); free(ix->bg_rows_d); free(ix->bg_changed);
+    ix->bg_rows = NULL; ix->bg_rows_d = NULL; ix->bg_changed = NULL;
+    ix->log_n = 0;
+    return ORC_OK;
 }
 
 int orc_delete(orc_index *ix, const int32_t *ids, int64_t n)
@@ -937,19 +1063,26 @@ int orc_delete(orc_index *ix, const int32_t *ids, int64_t n)
     /* The paper's deletion ablation separates the three parts: lazy deletion
      * alone (no repair, consolidate_frac 0 = never), lazy deletion with global
      * consolidation, and both with localized repair (the method). */
-    if (ix->consolidate_frac > 0 &&
-        (double)ix->deleted_since >= ix->consolidate_frac * (double)ix->alive_at_consolidate) {
+    int due = ix->consolidate_frac > 0 &&
+              (double)ix->deleted_since >= ix->consolidate_frac * (double)ix->alive_at_consolidate;
+    if (due && ix->consolidate_async && !ix->bg_active) {
+        bg_begin(ix);
+        ix->deleted_since = 0;
+        ix->alive_at_consolidate = ix->n_alive;
+    } else if (due && !ix->consolidate_async) {
+        orc_consolidate_wait(ix);
         repair(ix, 1);
         ix->deleted_since = 0;
         ix->alive_at_consolidate = ix->n_alive;
     } else if (ix->localized_repair) {
-        repair(ix, 0);
+        repair(ix, 0);   /* a due consolidation waits for the pending one */
     }
     return ORC_OK;
 }
 
 int orc_consolidate(orc_index *ix)
 {
+    orc_consolidate_wait(ix);
     repair(ix, 1);
     ix->deleted_since = 0;
     ix->alive_at_consolidate = ix->n_alive;

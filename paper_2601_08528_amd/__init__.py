@@ -22,7 +22,7 @@ OK, E_INVAL, E_NOMEM, E_DEVICE, E_NOTFOUND, E_BUSY, E_INTERNAL = 0, -1, -2, -3, 
 
 EXPORTED = [
     "svf_create", "svf_destroy", "svf_set_option", "svf_get_option", "svf_insert",
-    "svf_insert_dev", "svf_build", "svf_delete", "svf_consolidate", "svf_search",
+    "svf_insert_dev", "svf_build", "svf_delete", "svf_consolidate", "svf_consolidate_wait", "svf_search",
     "svf_search_dev", "svf_stats_get", "svf_export_graph", "svf_import_graph", "svf_last_error",
     "svf_search_listed", "svf_model_fit", "svf_mlp_create", "svf_mlp_destroy",
     "svf_mlp_num_params", "svf_mlp_set_params", "svf_mlp_get_params", "svf_mlp_forward",
@@ -82,6 +82,7 @@ def lib():
         L.svf_build.argtypes = [vp, vp, i64]
         L.svf_delete.argtypes = [vp, vp, i64]
         L.svf_consolidate.argtypes = [vp]
+        L.svf_consolidate_wait.argtypes = [vp]
         L.svf_search.argtypes = [vp, vp, i64, i32, i32, vp, vp]
         L.svf_search_dev.argtypes = [vp, vp, i64, i32, i32, vp, vp, vp, vp, vp]
         L.svf_stats_get.argtypes = [vp, C.POINTER(Stats)]
@@ -175,6 +176,9 @@ class Index:
 
     def consolidate(self):
         _check(lib().svf_consolidate(self.h))
+
+    def consolidate_wait(self):
+        _check(lib().svf_consolidate_wait(self.h))
 
     def search(self, queries, k: int, beam: int):
         q = np.ascontiguousarray(queries, dtype=np.float32).reshape(-1, self.dim)

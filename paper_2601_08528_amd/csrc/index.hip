@@ -40,6 +40,8 @@ int32_t* kept_indegree(svf_index* ix) {
 }
 int tier_admit(svf_index* ix, int64_t id0, int64_t n);
 int tier_apply(svf_index* ix, const std::vector<int32_t>& place, hipStream_t st);
+int bg_log(svf_index* ix, const int32_t* fwd, const float* fwd_d, int64_t b, hipStream_t st);
+void bg_join(svf_index* ix);
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -77,6 +79,7 @@ int visited_slots(const svf_index* ix, int E) {
 // Grow the device arrays to hold `need` id slots, keeping the contents.
 int reserve(svf_index* ix, int64_t need) {
   if (need <= ix->cap) return SVF_OK;
+  bg_join(ix);                              // it reads the vector stores that move below
   if (need > (int64_t)INT32_MAX - 64) return fail(SVF_E_INVAL, "index would exceed int32 ids");
   int64_t cap = std::max<int64_t>({need, ix->cap * 2, 1024});
   cap = round_up(cap, 64);
@@ -175,6 +178,7 @@ int32_t* tidx(svf_index* ix) { return ix->s_misc[11].as<int32_t>(); }
 int sync_lowp(svf_index* ix) {
   const int prec = ix->opt.precision;
   if (prec == ix->veclp_prec) return SVF_OK;
+  bg_join(ix);                              // it may be reading the store freed below
   if (ix->veclp) (void)hipFree(ix->veclp);
   ix->veclp = nullptr;
   ix->veclp_prec = prec;
@@ -368,6 +372,11 @@ int insert_commit(svf_index* ix, PendingInsert* p) {
     ++ix->graph_epoch;
     return tier_admit(ix, 0, p->b);
   }
+  if (ix->bg.active) {
+    if (p->n0 != ix->bg.n0 + ix->bg.log_n) return fail(SVF_E_INTERNAL, "insertion log out of order");
+    int rc = bg_log(ix, p->ra.fwd_ids, p->ra.fwd_d, p->b, st);
+    if (rc) return rc;
+  }
   CK(hipEventRecord(ix->ev0, st));
   if (int32_t* e = kept_indegree(ix)) {
     CK(svf::launch_indegree_rows_delta(ix->graph, p->ra.tlist, p->n_targets, p->ra.trow, ix->R, e, st));
@@ -403,29 +412,68 @@ int insert_batch(svf_index* ix, const float* d_vecs, int64_t b, int32_t* d_out_i
   return SVF_OK;
 }
 
-// Repair (consolidate = 0) or consolidation (1) of the rows that name deleted ids.
-int repair(svf_index* ix, int consolidate) {
-  hipStream_t st = ix->stream;
-  const int R = ix->R;
-  const int cap = prune_cap(ix);
+// What a repair / consolidation pass reads: the rows, edge distances and
+// alive bits (the live graph, or a snapshot of it), the vectors, and the
+// search used to top up short candidate lists (set up on the same graph).
+struct RepairJob {
+  const int32_t* graph;
+  const float* edge_d;
+  const uint32_t* alive;
+  int64_t n_slots;
+  const float* vec32;
+  int64_t stride;
+  int dim, metric, R, cap, c_local, Lins, prec;
+  uint64_t seed;
+  svf::SearchArgs proto;
+};
+
+RepairJob repair_job(svf_index* ix) {
+  RepairJob j;
+  j.graph = ix->graph;
+  j.edge_d = ix->edge_d;
+  j.alive = ix->alive;
+  j.n_slots = ix->n_slots;
+  j.vec32 = ix->vec32;
+  j.stride = ix->stride;
+  j.dim = ix->dim;
+  j.metric = ix->metric;
+  j.R = ix->R;
+  j.cap = prune_cap(ix);
+  j.c_local = ix->opt.repair_c;
+  j.Lins = beam_insert(ix);
+  j.prec = ix->veclp_prec;
+  j.seed = ix->opt.seed;
+  j.proto = base_args(ix);
+  set_beam(j.proto, ix, j.Lins);
+  j.proto.max_iters = 0;
+  j.proto.k = 0;
+  return j;
+}
+
+// Repair (consolidate = 0) or consolidation (1) of the rows that name deleted
+// ids: the new rows of the *n_aff affected vertices are left in s.list /
+// s.rows / s.rows_d; nothing is committed.
+int repair_compute(const RepairJob& j, int consolidate, svf::RepairScratch& s, hipStream_t st,
+                   int32_t* n_aff_out) {
+  const int R = j.R;
+  const int cap = j.cap;
   int32_t *list, *cnt;
   int rc;
-  if ((rc = scratch(ix->s_misc[0], std::max<int64_t>(ix->n_slots, 1), &list)) ||
-      (rc = scratch(ix->s_misc[2], 8, &cnt)))
+  *n_aff_out = 0;
+  if ((rc = scratch(s.list, std::max<int64_t>(j.n_slots, 1), &list)) || (rc = scratch(s.cnt, 8, &cnt)))
     return rc;
-  CK(hipEventRecord(ix->ev0, st));
   svf::RepairArgs a{};
-  a.vec32 = ix->vec32;
-  a.stride = ix->stride;
-  a.dim = ix->dim;
-  a.metric = ix->metric;
+  a.vec32 = j.vec32;
+  a.stride = j.stride;
+  a.dim = j.dim;
+  a.metric = j.metric;
   a.R = R;
-  a.graph = ix->graph;
-  a.edge_d = ix->edge_d;
-  a.alive = ix->alive;
-  a.n_slots = (int32_t)ix->n_slots;
+  a.graph = j.graph;
+  a.edge_d = j.edge_d;
+  a.alive = j.alive;
+  a.n_slots = (int32_t)j.n_slots;
   a.consolidate = consolidate;
-  a.c = consolidate ? R : ix->opt.repair_c;
+  a.c = consolidate ? R : j.c_local;
   a.cap = cap;
   a.list = list;
   a.n_list = cnt;
@@ -435,26 +483,21 @@ int repair(svf_index* ix, int consolidate) {
   int32_t n_aff = 0;
   CK(hipMemcpyAsync(&n_aff, cnt, 4, hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
-  ix->st.last_repaired = n_aff;
-  if (n_aff == 0) {
-    ix->st.del_repair_ms = 0;
-    return SVF_OK;
-  }
+  if (n_aff == 0) return SVF_OK;
   int32_t *rows, *mcount, *topup, *topup_v;
   float* rows_d;
   uint64_t* cand;
   const int64_t chunk = std::min<int64_t>(n_aff, 131072);
-  if ((rc = scratch(ix->s_misc[7], (size_t)n_aff * R, &rows)) ||
-      (rc = scratch(ix->s_misc[8], (size_t)n_aff * R, &rows_d)) ||
-      (rc = scratch(ix->s_misc[6], (size_t)chunk * cap, &cand)) ||
-      (rc = scratch(ix->s_misc[3], chunk, &mcount)) || (rc = scratch(ix->s_misc[4], chunk, &topup)) ||
-      (rc = scratch(ix->s_misc[5], chunk, &topup_v)))
+  if ((rc = scratch(s.rows, (size_t)n_aff * R, &rows)) ||
+      (rc = scratch(s.rows_d, (size_t)n_aff * R, &rows_d)) ||
+      (rc = scratch(s.cand, (size_t)chunk * cap, &cand)) ||
+      (rc = scratch(s.mcount, chunk, &mcount)) || (rc = scratch(s.topup, chunk, &topup)) ||
+      (rc = scratch(s.topup_v, chunk, &topup_v)))
     return rc;
   a.cand = cand;
   a.mcount = mcount;
   a.topup = topup;
   a.topup_v = topup_v;
-  const int Lins = beam_insert(ix);
   for (int64_t first = 0; first < n_aff; first += chunk) {
     const int count = (int)std::min<int64_t>(chunk, n_aff - first);
     CK(svf::launch_fill_u32(cnt + 1, 1, 0u, st));
@@ -464,42 +507,217 @@ int repair(svf_index* ix, int consolidate) {
     CK(hipStreamSynchronize(st));
     if (ntop > 0) {
       uint64_t *qkey, *pool;
-      if ((rc = scratch(ix->s_qkey, ntop, &qkey)) || (rc = scratch(ix->s_pool, (size_t)ntop * Lins, &pool)))
+      if ((rc = scratch(s.qkey, ntop, &qkey)) || (rc = scratch(s.pool, (size_t)ntop * j.Lins, &pool)))
         return rc;
-      svf::SearchArgs s = base_args(ix);
-      set_beam(s, ix, Lins);
-      s.max_iters = 0;
-      s.k = 0;
-      s.queries = ix->vec32;
-      s.qstride = ix->stride;
-      s.qids = topup_v;
-      s.nq = ntop;
-      s.out_pool = pool;
-      CK(svf::launch_query_keys(ix->vec32, ix->stride, topup_v, ix->dim, ntop, ix->opt.seed, qkey, st));
-      s.qkey = qkey;
-      CK(svf::launch_search(s, ix->veclp_prec, st));
-      CK(svf::launch_topup_merge(a, pool, Lins, (int)first, ntop, st));
+      svf::SearchArgs q = j.proto;
+      q.queries = j.vec32;
+      q.qstride = j.stride;
+      q.qids = topup_v;
+      q.nq = ntop;
+      q.out_pool = pool;
+      CK(svf::launch_query_keys(j.vec32, j.stride, topup_v, j.dim, ntop, j.seed, qkey, st));
+      q.qkey = qkey;
+      CK(svf::launch_search(q, j.prec, st));
+      CK(svf::launch_topup_merge(a, pool, j.Lins, (int)first, ntop, st));
     }
     svf::PruneArgs pa{};
     pa.cand = cand;
     pa.cstride = cap;
     pa.cap = cap;
-    pa.graph = ix->graph;
+    pa.graph = j.graph;
     pa.fwd = nullptr;
-    pa.n_old = (int32_t)ix->n_slots;
+    pa.n_old = (int32_t)j.n_slots;
     pa.R = R;
     pa.out_ids = rows + first * R;
     pa.out_d = rows_d + first * R;
     pa.nlists = count;
     CK(svf::launch_prune_lists(pa, st));
   }
+  CK(hipStreamSynchronize(st));
+  *n_aff_out = n_aff;
+  return SVF_OK;
+}
+
+// Write n rows computed by a repair pass into the live graph.
+int commit_repaired(svf_index* ix, const int32_t* list, int n, const int32_t* rows,
+                    const float* rows_d, hipStream_t st) {
+  if (n <= 0) return SVF_OK;
   if (int32_t* e = kept_indegree(ix))
-    CK(svf::launch_indegree_rows_delta(ix->graph, list, n_aff, rows, R, e, st));
-  CK(svf::launch_commit_rows(list, n_aff, rows, rows_d, R, ix->graph, ix->edge_d, st));
+    CK(svf::launch_indegree_rows_delta(ix->graph, list, n, rows, ix->R, e, st));
+  CK(svf::launch_commit_rows(list, n, rows, rows_d, ix->R, ix->graph, ix->edge_d, st));
   ++ix->graph_epoch;
+  return SVF_OK;
+}
+
+// Repair (consolidate = 0) or consolidation (1) of the live graph.
+int repair(svf_index* ix, int consolidate) {
+  hipStream_t st = ix->stream;
+  CK(hipEventRecord(ix->ev0, st));
+  int32_t n_aff = 0;
+  int rc = repair_compute(repair_job(ix), consolidate, ix->rs, st, &n_aff);
+  if (rc) return rc;
+  ix->st.last_repaired = n_aff;
+  if (n_aff == 0) {
+    ix->st.del_repair_ms = 0;
+    return SVF_OK;
+  }
+  if ((rc = commit_repaired(ix, ix->rs.list.as<int32_t>(), n_aff, ix->rs.rows.as<int32_t>(),
+                            ix->rs.rows_d.as<float>(), st)))
+    return rc;
   CK(hipEventRecord(ix->ev1, st));
   CK(hipStreamSynchronize(st));
   ix->st.del_repair_ms = elapsed(ix->ev0, ix->ev1);
+  return SVF_OK;
+}
+
+// ---- consolidation in the background (Sec. 5.3) ------------------------------
+// bg_begin copies the live rows, edge distances and alive bits and starts a
+// host thread that runs the consolidation on that snapshot on its own
+// stream.  Meanwhile the live graph keeps changing; every insertion batch
+// appends its forward rows to a log.  bg_merge waits for the thread, writes
+// the consolidated rows into the live graph, then re-prunes each rewritten
+// row with the edges that insertions since the snapshot gave it (the log's
+// pairs whose target is a rewritten row), as a reverse-edge pass reading
+// the rows as they stand after the first step.  Rows of vertices inserted
+// since the snapshot, and rows the consolidation did not rewrite, keep their
+// live state.
+void bg_join(svf_index* ix) {
+  if (ix->bg.th.joinable()) ix->bg.th.join();
+}
+
+int bg_begin(svf_index* ix) {
+  svf::BgConsolidation& B = ix->bg;
+  hipStream_t st = ix->stream;
+  if (!B.st) CK(hipStreamCreateWithFlags(&B.st, hipStreamNonBlocking));
+  const int64_t n = ix->n_slots, R = ix->R, words = (n + 31) / 32;
+  int32_t* g;
+  float* e;
+  uint32_t* al;
+  int rc;
+  if ((rc = scratch(B.graph, std::max<int64_t>(n * R, 1), &g)) ||
+      (rc = scratch(B.edge_d, std::max<int64_t>(n * R, 1), &e)) ||
+      (rc = scratch(B.alive, std::max<int64_t>(words, 1), &al)))
+    return rc;
+  CK(hipMemcpyAsync(g, ix->graph, n * R * 4, hipMemcpyDeviceToDevice, st));
+  CK(hipMemcpyAsync(e, ix->edge_d, n * R * 4, hipMemcpyDeviceToDevice, st));
+  CK(hipMemcpyAsync(al, ix->alive, words * 4, hipMemcpyDeviceToDevice, st));
+  CK(hipStreamSynchronize(st));
+  RepairJob j = repair_job(ix);
+  j.graph = g;
+  j.edge_d = e;
+  j.alive = al;
+  j.proto.graph = g;
+  j.proto.alive = al;
+  B.n0 = n;
+  B.log_n = 0;
+  B.n_aff = 0;
+  B.rc = 0;
+  B.err.clear();
+  B.done = false;
+  B.active = true;
+  const int dev = ix->device;
+  B.th = std::thread([&B, j, dev]() {
+    int32_t na = 0;
+    int rc2 = hipSetDevice(dev) == hipSuccess ? repair_compute(j, 1, B.rs, B.st, &na) : SVF_E_DEVICE;
+    B.n_aff = na;
+    B.rc = rc2;
+    if (rc2) B.err = g_err;
+    B.done = true;
+  });
+  return SVF_OK;
+}
+
+// Append the forward rows of an insertion batch (ids B.n0 + B.log_n on) to the log.
+int bg_log(svf_index* ix, const int32_t* fwd, const float* fwd_d, int64_t b, hipStream_t st) {
+  svf::BgConsolidation& B = ix->bg;
+  const int64_t R = ix->R;
+  if (B.log_n + b > B.log_cap) {
+    const int64_t cap = std::max<int64_t>(B.log_n + b, 2 * B.log_cap);
+    svf::DevBuf ni, nd;
+    CK(ni.ensure(cap * R * 4));
+    CK(nd.ensure(cap * R * 4));
+    if (B.log_n) {
+      CK(hipMemcpyAsync(ni.p, B.log_ids.p, B.log_n * R * 4, hipMemcpyDeviceToDevice, st));
+      CK(hipMemcpyAsync(nd.p, B.log_d.p, B.log_n * R * 4, hipMemcpyDeviceToDevice, st));
+      CK(hipStreamSynchronize(st));
+    }
+    std::swap(B.log_ids.p, ni.p);
+    std::swap(B.log_ids.bytes, ni.bytes);
+    std::swap(B.log_d.p, nd.p);
+    std::swap(B.log_d.bytes, nd.bytes);
+    B.log_cap = cap;
+  }
+  CK(hipMemcpyAsync(B.log_ids.as<int32_t>() + B.log_n * R, fwd, b * R * 4, hipMemcpyDeviceToDevice, st));
+  CK(hipMemcpyAsync(B.log_d.as<float>() + B.log_n * R, fwd_d, b * R * 4, hipMemcpyDeviceToDevice, st));
+  B.log_n += b;
+  return SVF_OK;
+}
+
+int bg_merge(svf_index* ix) {
+  svf::BgConsolidation& B = ix->bg;
+  if (!B.active) return SVF_OK;
+  bg_join(ix);
+  B.active = false;
+  if (B.rc) {
+    B.log_n = 0;
+    return fail(B.rc, "background consolidation: " + B.err);
+  }
+  hipStream_t st = ix->stream;
+  const int R = ix->R;
+  const int32_t n_aff = B.n_aff;
+  ix->st.last_repaired = n_aff;
+  int rc;
+  if (n_aff > 0) {
+    const int32_t* list = B.rs.list.as<int32_t>();
+    if ((rc = commit_repaired(ix, list, n_aff, B.rs.rows.as<int32_t>(), B.rs.rows_d.as<float>(), st)))
+      return rc;
+  }
+  if (n_aff > 0 && B.log_n > 0) {
+    const int64_t words = (ix->n_slots + 31) / 32;
+    uint32_t* mask;
+    int32_t* cnt;
+    if ((rc = scratch(B.mask, words, &mask)) || (rc = scratch(ix->s_misc[2], 8, &cnt))) return rc;
+    CK(svf::launch_fill_u32(mask, words, 0u, st));
+    CK(svf::launch_mark_list(B.rs.list.as<int32_t>(), n_aff, mask, st));
+    svf::ReverseArgs ra{};
+    ra.fwd_ids = B.log_ids.as<int32_t>();
+    ra.fwd_d = B.log_d.as<float>();
+    ra.b = (int)B.log_n;
+    ra.R = R;
+    ra.n0 = (int32_t)B.n0;
+    ra.rows_below = (int32_t)ix->n_slots;
+    ra.tmask = mask;
+    ra.tcount = tcount(ix);
+    ra.tidx = tidx(ix);
+    ra.graph = ix->graph;
+    ra.edge_d = ix->edge_d;
+    ra.alive = ix->alive;
+    ra.cap = prune_cap(ix);
+    const int64_t npairs = B.log_n * R;
+    if ((rc = scratch(ix->s_misc[3], npairs, &ra.tlist))) return rc;
+    ra.n_targets = cnt;
+    CK(svf::launch_fill_u32(cnt, 1, 0u, st));
+    CK(svf::launch_reverse_count(ra, st));
+    int32_t n_targets = 0;
+    CK(hipMemcpyAsync(&n_targets, cnt, 4, hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    if ((rc = scratch(ix->s_misc[4], n_targets + 1, &ra.off)) ||
+        (rc = scratch(ix->s_misc[5], (size_t)n_targets + 2 + n_targets / 1024 + 2, &ra.cursor)) ||
+        (rc = scratch(ix->s_misc[6], npairs, &ra.inc)) ||
+        (rc = scratch(ix->s_misc[7], (size_t)n_targets * R, &ra.trow)) ||
+        (rc = scratch(ix->s_misc[8], (size_t)n_targets * R, &ra.trow_d)))
+      return rc;
+    CK(svf::launch_reverse_scan_scatter(ra, n_targets, st));
+    CK(svf::launch_reverse_prune(ra, n_targets, st));
+    if (int32_t* e = kept_indegree(ix))
+      CK(svf::launch_indegree_rows_delta(ix->graph, ra.tlist, n_targets, ra.trow, R, e, st));
+    svf::ReverseArgs only_targets = ra;
+    only_targets.b = 0;                       // the logged rows are live already
+    CK(svf::launch_commit_batch(only_targets, n_targets, ix->graph, ix->edge_d, ix->alive, st));
+    ++ix->graph_epoch;
+  }
+  CK(hipStreamSynchronize(st));
+  B.log_n = 0;
   return SVF_OK;
 }
 
@@ -638,13 +856,20 @@ int delete_ids(svf_index* ix, const int32_t* ids, int64_t n) {
   ix->n_alive -= newly;
   ix->deleted_since += newly;
   if (newly == 0) return SVF_OK;
-  if (ix->opt.consolidate_frac > 0 &&
-      (double)ix->deleted_since >= ix->opt.consolidate_frac * (double)ix->alive_at_consolidate) {
+  const bool due = ix->opt.consolidate_frac > 0 &&
+                   (double)ix->deleted_since >= ix->opt.consolidate_frac * (double)ix->alive_at_consolidate;
+  const bool async = ix->opt.consolidate_async && !ix->tier.on;
+  if (due && async && !ix->bg.active) {
+    rc = bg_begin(ix);                     // the consolidation runs on a snapshot
+    ix->deleted_since = 0;
+    ix->alive_at_consolidate = ix->n_alive;
+  } else if (due && !async) {
+    if ((rc = bg_merge(ix))) return rc;
     rc = repair(ix, 1);
     ix->deleted_since = 0;
     ix->alive_at_consolidate = ix->n_alive;
   } else if (ix->opt.localized_repair) {
-    rc = repair(ix, 0);
+    rc = repair(ix, 0);                    // (a due consolidation waits for the pending one)
   }
   return rc;
 }
@@ -1082,6 +1307,7 @@ int tier_warmup(svf_index* ix, hipStream_t st) {
 
 int tier_enable(svf_index* ix, double bytes) {
   svf::TierState& T = ix->tier;
+  bg_join(ix);                              // the FP32 store moves below
   const int64_t C = (int64_t)(bytes / (double)(ix->stride * 4));
   if (C < 1) return fail(SVF_E_INVAL, "cache_bytes below one vector");
   if (T.on) return fail(SVF_E_INVAL, "cache already configured");
@@ -1176,6 +1402,9 @@ int svf_destroy(svf_index* ix) {
   if (ix->server) serve_shutdown(ix);
   {
     std::lock_guard<std::mutex> g(ix->mu);
+    bg_join(ix);
+    if (ix->bg.st) (void)hipStreamDestroy(ix->bg.st);
+    ix->bg.st = nullptr;
     if (ix->stream) (void)hipStreamSynchronize(ix->stream);
     if (ix->vec32) (void)(ix->tier.on ? hipHostFree(ix->vec32) : hipFree(ix->vec32));
     if (ix->veclp) (void)hipFree(ix->veclp);
@@ -1239,6 +1468,9 @@ int svf_set_option(svf_index* ix, const char* key, double v) {
   } else if (k == "localized_repair") {
     if (v != 0 && v != 1) return fail(SVF_E_INVAL, "localized_repair 0 or 1");
     o.localized_repair = (int)v;
+  } else if (k == "consolidate_async") {
+    if (v != 0 && v != 1) return fail(SVF_E_INVAL, "consolidate_async 0 or 1");
+    o.consolidate_async = (int)v;
   } else if (k == "insert_batch_max") {
     if (!is_int(v) || v < 1 || v > (1 << 20)) return fail(SVF_E_INVAL, "insert_batch_max in [1, 2^20]");
     o.insert_batch_max = (int)v;
@@ -1320,6 +1552,8 @@ int svf_get_option(const svf_index* ix, const char* key, double* out) {
   else if (k == "prune_cap") *out = prune_cap(ix);
   else if (k == "consolidate_frac") *out = o.consolidate_frac;
   else if (k == "localized_repair") *out = o.localized_repair;
+  else if (k == "consolidate_async") *out = o.consolidate_async;
+  else if (k == "consolidate_pending") *out = ix->bg.active ? 1.0 : 0.0;
   else if (k == "insert_batch_max") *out = o.insert_batch_max;
   else if (k == "precision") *out = o.precision;
   else if (k == "rerank") *out = o.rerank;
@@ -1392,10 +1626,19 @@ int svf_consolidate(svf_index* ix) {
   if (ix && ix->server) return fail(SVF_E_BUSY, "index is serving: stop serving first");
   if (!ix) return fail(SVF_E_INVAL, "null index");
   std::lock_guard<std::mutex> g(ix->mu);
-  int rc = repair(ix, 1);
+  int rc = bg_merge(ix);
+  if (rc) return rc;
+  rc = repair(ix, 1);
   ix->deleted_since = 0;
   ix->alive_at_consolidate = ix->n_alive;
   return rc;
+}
+
+int svf_consolidate_wait(svf_index* ix) {
+  if (ix && ix->server) return fail(SVF_E_BUSY, "index is serving: the serving loop merges");
+  if (!ix) return fail(SVF_E_INVAL, "null index");
+  std::lock_guard<std::mutex> g(ix->mu);
+  return bg_merge(ix);
 }
 
 int svf_search_dev(svf_index* ix, const float* d_queries, int64_t nq, int32_t k, int32_t beam,

@@ -3,7 +3,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <mutex>
+#include <thread>
 #include <string>
 #include <vector>
 
@@ -68,6 +70,7 @@ struct Options {
   int visited_compact = 1;
   int repair_c = 8;
   int localized_repair = 1;
+  int consolidate_async = 0;
   int prune_cap = 0;
   double consolidate_frac = 0.2;
   int insert_batch_max = 10000;
@@ -84,6 +87,30 @@ struct Options {
 
 namespace svf {
 struct Server;
+
+// Device buffers of one repair / consolidation pass.
+struct RepairScratch {
+  DevBuf list, cnt, rows, rows_d, cand, mcount, topup, topup_v, qkey, pool;
+};
+
+// A consolidation running in the background on a snapshot (Sec. 5.3): the
+// snapshot's rows, edge distances and alive bits, the staged result, and
+// the forward rows of the vertices inserted since the snapshot (their ids
+// follow the snapshot's, in order) for the merge.
+struct BgConsolidation {
+  bool active = false;
+  std::thread th;
+  std::atomic<bool> done{false};
+  int rc = 0;
+  std::string err;
+  hipStream_t st = nullptr;
+  int64_t n0 = 0;
+  int32_t n_aff = 0;
+  DevBuf graph, edge_d, alive, mask;
+  RepairScratch rs;
+  DevBuf log_ids, log_d;
+  int64_t log_n = 0, log_cap = 0;
+};
 
 // Tiered vector store: every vector lives in pinned host memory; an HBM cache
 // of C rows, a device mapping table id -> slot, and the placement state.
@@ -156,5 +183,7 @@ struct svf_index {
   svf_stats st{};
   svf::Server* server = nullptr;   // non-null while the serving loop runs
   svf::TierState tier;
+  svf::RepairScratch rs;             // foreground repair / consolidation
+  svf::BgConsolidation bg;
   int64_t graph_epoch = 0;         // advances whenever rows are committed
 };

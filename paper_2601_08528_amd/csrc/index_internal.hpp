@@ -39,6 +39,7 @@ int insert_prepare(svf_index* ix, const float* d_vecs, int64_t b, PendingInsert*
 int insert_commit(svf_index* ix, PendingInsert* p);
 int repair(svf_index* ix, int consolidate);
 int delete_ids(svf_index* ix, const int32_t* ids, int64_t n);
+int bg_merge(svf_index* ix);
 svf::SearchArgs base_args(const svf_index* ix);
 void set_beam(svf::SearchArgs& a, const svf_index* ix, int L);
 int check_search_args(const svf_index* ix, int64_t nq, int k, int beam);

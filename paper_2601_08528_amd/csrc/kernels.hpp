@@ -117,6 +117,8 @@ struct ReverseArgs {
   int cap;
   int32_t* trow;            // n_targets x R
   float* trow_d;
+  const uint32_t* tmask;    // only targets with their bit set take edges (null: all)
+  int32_t rows_below;       // the prune reads rows of ids below this from graph (0: n0)
 };
 hipError_t launch_reverse_count(const ReverseArgs& a, hipStream_t st);
 hipError_t launch_reverse_scan_scatter(const ReverseArgs& a, int n_targets, hipStream_t st);
@@ -148,6 +150,7 @@ hipError_t launch_mark_deleted(const int32_t* ids, int64_t n, uint32_t* alive, i
 hipError_t launch_indegree_rows_delta(const int32_t* graph, const int32_t* list, int n,
                                       const int32_t* rows, int R, int32_t* e_in, hipStream_t st);
 hipError_t launch_indegree_add(const int32_t* rows, int64_t n, int32_t* e_in, hipStream_t st);
+hipError_t launch_mark_list(const int32_t* list, int n, uint32_t* mask, hipStream_t st);
 hipError_t launch_affected(const RepairArgs& a, hipStream_t st);
 hipError_t launch_repair_candidates(const RepairArgs& a, int first, int count, hipStream_t st);
 hipError_t launch_topup_merge(const RepairArgs& a, const uint64_t* pool, int L, int first,

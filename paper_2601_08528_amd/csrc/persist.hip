@@ -83,6 +83,8 @@ extern "C" {
 int svf_save(const svf_index* cix, const char* path) {
   if (!cix || !path) return fail(SVF_E_INVAL, "null argument");
   if (cix->server) return fail(SVF_E_BUSY, "index is serving: stop serving first");
+  if (cix->bg.active)
+    return fail(SVF_E_BUSY, "a background consolidation is pending: call svf_consolidate_wait first");
   svf_index* ix = const_cast<svf_index*>(cix);
   const int64_t n = ix->n_slots;
   FileHeader h{};

@@ -376,6 +376,12 @@ void dispatcher(Server* sv) {
       commit_prepared(sv, lk);
       progressed = true;
     }
+    if (sv->prep_state == 0 && !sv->prep_req && sv->ix->bg.active && sv->ix->bg.done) {
+      // a background consolidation has finished: merge it like a commit
+      drain(sv, lk);
+      if (svf_detail::bg_merge(sv->ix) == SVF_OK) ++sv->epoch;
+      progressed = true;
+    }
     if (sv->prep_state == 0 && !sv->prep_req && !sv->mutations.empty()) {
       begin_mutation(sv, lk);
       progressed = true;

@@ -334,7 +334,7 @@ __global__ void reverse_count_kernel(ReverseArgs a) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= (int64_t)a.b * a.R) return;
   const int32_t t = a.fwd_ids[i];
-  if (t < 0) return;
+  if (t < 0 || (a.tmask && !((a.tmask[t >> 5] >> (t & 31)) & 1u))) return;
   if (atomicAdd(&a.tcount[t], 1) == 0) {
     const int k = atomicAdd(a.n_targets, 1);
     a.tlist[k] = t;
@@ -404,7 +404,7 @@ __global__ void reverse_scatter_kernel(ReverseArgs a) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= (int64_t)a.b * a.R) return;
   const int32_t t = a.fwd_ids[i];
-  if (t < 0) return;
+  if (t < 0 || (a.tmask && !((a.tmask[t >> 5] >> (t & 31)) & 1u))) return;
   const int k = a.tidx[t];
   const int pos = a.off[k] + atomicAdd(&a.cursor[k], 1);
   a.inc[pos] = make_key(a.fwd_d[i], a.n0 + (int32_t)(i / a.R));
@@ -462,7 +462,7 @@ __device__ void reverse_prune_one(ReverseArgs a, int k, unsigned char* smem) {
     sort_merge(w, key);
   }
   const int m = count_keys(w.pool, cap);
-  RowSource rs{a.graph, a.fwd_ids, a.n0, a.R};
+  RowSource rs{a.graph, a.fwd_ids, a.rows_below ? a.rows_below : a.n0, a.R};
   prune_core(w.pool, m, rs, a.R, s, a.trow + (int64_t)k * a.R, a.trow_d + (int64_t)k * a.R);
 }
 hipError_t launch_reverse_prune(const ReverseArgs& a, int n_targets, hipStream_t st) {
@@ -559,6 +559,17 @@ hipError_t launch_indegree_add(const int32_t* rows, int64_t n, int32_t* e_in, hi
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(indegree_add_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, rows,
                      n, e_in);
+  return hipGetLastError();
+}
+
+// Bits of the listed ids.
+__global__ void mark_list_kernel(const int32_t* list, int n, uint32_t* mask) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) atomicOr(&mask[(uint32_t)list[i] >> 5], 1u << (list[i] & 31));
+}
+hipError_t launch_mark_list(const int32_t* list, int n, uint32_t* mask, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mark_list_kernel, dim3((n + 255) / 256), dim3(256), 0, st, list, n, mask);
   return hipGetLastError();
 }
 

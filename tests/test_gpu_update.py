@@ -167,3 +167,37 @@ def test_deletion_modes_bit_exact(lr, cf):
     oix.insert(base[3000:])
     g.insert(base[3000:])
     assert_same_graph(g, oix)
+
+
+def test_background_consolidation_bit_exact(tmp_path):
+    """A consolidation that falls due runs in the background on a snapshot
+    while insertions and deletions continue on the live graph; live graphs
+    and the merged graph equal the oracle's, and saving waits for the merge."""
+    base, q = datagen.gmm_uint8_valued(708, 4200, 60, 64, 12)
+    oix = oracle_index(base[:3000], 16, seed=10, batch_max=400, consolidate_async=1)
+    g = gpu_from_oracle(oix, base[:3000], seed=10, insert_batch_max=400, consolidate_async=1)
+    gen = np.random.Generator(np.random.Philox(8))
+    for cycle in range(2):
+        lo = 3000 + 600 * cycle
+        victims = gen.choice(lo, int(0.25 * lo), replace=False).astype(np.int32)
+        assert oix.delete(victims) == 0
+        g.delete(victims)
+        assert g.get_option("consolidate_pending") == 1
+        assert_same_graph(g, oix)
+        oix.insert(base[lo:lo + 300])
+        g.insert(base[lo:lo + 300])
+        few = gen.choice(lo, 40, replace=False).astype(np.int32)
+        assert oix.delete(few) == 0
+        g.delete(few)
+        assert_same_graph(g, oix)
+        with pytest.raises(svf.SvfError):
+            g.save(str(tmp_path / "pending.svf"))
+        oix.insert(base[lo + 300:lo + 600])
+        g.insert(base[lo + 300:lo + 600])
+        oix.consolidate_wait()
+        g.consolidate_wait()
+        assert g.get_option("consolidate_pending") == 0
+        assert_same_graph(g, oix)
+        oi, od, _ = oix.search(q, 10, 48)
+        gi, gd = g.search(q, 10, 48)
+        np.testing.assert_array_equal(gi, oi)

@@ -376,6 +376,47 @@ def test_deletion_modes_of_the_ablation():
         assert a[x].all()
 
 
+def test_background_consolidation_merge():
+    """Consolidation on a snapshot (Sec. 5.3): merged with nothing logged it
+    equals the synchronous consolidation; with insertions in between, the
+    merge leaves the rows of the inserted vertices and of every vertex the
+    consolidation did not rewrite as they were, and no merged row names a
+    vertex deleted before the snapshot."""
+    base, _ = datagen.gmm_uint8_valued(99, 900, 4, 16, 5)
+
+    def fresh(**o):
+        ix = O.OracleIndex(16, 8, O.L2, seed=3, consolidate_frac=0.2, **o)
+        ix.build(base[:700], batch_max=100)
+        return ix
+
+    g = np.random.Generator(np.random.Philox(5))
+    gone = g.choice(700, 150, replace=False).astype(np.int32)   # past 20%: due
+    sync = fresh()
+    sync.delete(gone)
+    bg = fresh(consolidate_async=1)
+    bg.delete(gone)
+    bg.consolidate_wait()
+    for a_, b_ in zip(sync.export(), bg.export()):
+        np.testing.assert_array_equal(a_, b_)
+
+    bg = fresh(consolidate_async=1)
+    bg.delete(gone)                                   # snapshot of 700 taken here
+    pre_rows = bg.export()[0]
+    bg.insert(base[700:800])
+    bg.insert(base[800:])
+    live = bg.export()[0]
+    bg.consolidate_wait()
+    merged, _, alive = bg.export()
+    assert (merged[700:] == live[700:]).all()         # inserted since: untouched
+    rewritten = (sync.export()[0] != pre_rows).any(1)
+    assert ((merged[:700] != live[:700]).any(1) <= rewritten).all()
+    dead0 = np.zeros(900, bool)
+    dead0[gone] = True
+    for v in np.nonzero(rewritten)[0]:
+        x = merged[v][merged[v] >= 0]
+        assert not dead0[x].any()
+
+
 def test_reduced_precision_exact_on_integer_data(small_index):
     base, q = datagen.gmm_uint8_valued(97, 400, 20, 16, 4)
     ix = O.OracleIndex(16, 8, O.L2, seed=6)
