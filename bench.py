@@ -138,15 +138,18 @@ def sweep(torch, ix, q_t, base_t, kth, bufs, beams, target=0.95):
     return chosen, rows
 
 
-def serving_bench(svf, datagen, n_build=5_000_000, rounds=60, rates=(60.0, 240.0, 480.0)):
+def serving_bench(svf, datagen, n_build=5_000_000, rounds=60, rates=(60.0, 240.0, 480.0),
+                  consolidation_rate=240.0, consolidate_frac=0.004):
     """Streaming mix on the serving loop: an n_build-vector unit-norm 96-d
     mixture (1024 components, inner product, degree 48, BF16 traversal + FP32
     re-score), then, at each offered load in turn, `rounds` rounds of [one
     10k-vector insert, one 1k-id delete of uniformly chosen live ids, four
     query batches of log-uniform size 1..10k with Zipf(1.1)-skewed
     components] as open-loop Poisson arrivals.  The index keeps changing
-    from one load to the next."""
-    n_extra = len(rates) * rounds * 10_000
+    from one load to the next.  Then two more phases at one load with a
+    consolidation threshold low enough that consolidations happen inside the
+    phase: synchronous, then in the background on a snapshot."""
+    n_extra = (len(rates) + 2) * rounds * 10_000
     base, queries = datagen.workload_stream_ip(n_build + n_extra, 20_000)
     ix = svf.Index(96, 48, svf.METRIC_IP, seed=0, precision=svf.PREC_BF16)
     t0 = time.perf_counter()
@@ -157,8 +160,16 @@ def serving_bench(svf, datagen, n_build=5_000_000, rounds=60, rates=(60.0, 240.0
     ix.serve_start(streams=4, max_batch=16384)
     pos_ins, pos_del, pos_q = n_build, 0, 0
     loads = []
-    for rate_hz in rates:
+    phases = [(r, None) for r in rates] + [(consolidation_rate, 0), (consolidation_rate, 1)]
+    for rate_hz, async_mode in phases:
+        if async_mode is not None:
+            ix.serve_stop()
+            ix.consolidate_wait()
+            ix.set_option("consolidate_frac", consolidate_frac)
+            ix.set_option("consolidate_async", async_mode)
+            ix.serve_start(streams=4, max_batch=16384)
         reqs = datagen.request_stream(rounds, 10_000, 1_000, 4, 10_000, rate_hz)
+        cons0 = ix.stats()["consolidations"]
         tickets = []
         keep = []
         t_start = time.perf_counter()
@@ -182,6 +193,10 @@ def serving_bench(svf, datagen, n_build=5_000_000, rounds=60, rates=(60.0, 240.0
         infos = [(kind, size, ix.wait(t, 300.0)) for t, kind, size in tickets]
         wall = time.perf_counter() - t_start
         out = {"offered_req_per_s": rate_hz, "requests": len(reqs), "wall_s": round(wall, 3)}
+        if async_mode is not None:
+            out["consolidation"] = ("background on a snapshot" if async_mode else "synchronous") + \
+                " (consolidate_frac %g)" % consolidate_frac
+        out["consolidations_done"] = int(ix.stats()["consolidations"] - cons0)
         nq = sum(size for kind, size, _ in infos if kind == "search")
         out["qps"] = round(nq / wall, 1)
         for kind in ("search", "insert", "delete"):
@@ -193,6 +208,7 @@ def serving_bench(svf, datagen, n_build=5_000_000, rounds=60, rates=(60.0, 240.0
         out["max_batch_queries"] = int(max(inf["batch_queries"] for _, _, inf in infos))
         loads.append(out)
     ix.serve_stop()
+    ix.consolidate_wait()
     return {"workload": "%dM x 96 unit-norm GMM (1024 comps, Zipf(1.1) queries), IP, degree 48, "
                         "BF16 + FP32 re-score, k=10, beam 64; per load %d rounds of insert 10k / "
                         "delete 1k / 4 query batches 1..10k, Poisson arrivals"

@@ -74,6 +74,7 @@ typedef struct svf_stats {
     int64_t cache_last_trace_hits;  /* last batch: expansions of cached vectors */
     int64_t cache_last_placed;      /* last batch: vectors placed in the cache */
     int64_t cache_promotions, cache_evictions;
+    int64_t consolidations;         /* global consolidations done (a background one once merged) */
 } svf_stats;
 
 /* Create an empty index.  Sec. 2.3: a directed graph with a fixed number of

@@ -552,6 +552,7 @@ int commit_repaired(svf_index* ix, const int32_t* list, int n, const int32_t* ro
 // Repair (consolidate = 0) or consolidation (1) of the live graph.
 int repair(svf_index* ix, int consolidate) {
   hipStream_t st = ix->stream;
+  if (consolidate) ++ix->st.consolidations;
   CK(hipEventRecord(ix->ev0, st));
   int32_t n_aff = 0;
   int rc = repair_compute(repair_job(ix), consolidate, ix->rs, st, &n_aff);
@@ -666,6 +667,7 @@ int bg_merge(svf_index* ix) {
   const int R = ix->R;
   const int32_t n_aff = B.n_aff;
   ix->st.last_repaired = n_aff;
+  ++ix->st.consolidations;
   int rc;
   if (n_aff > 0) {
     const int32_t* list = B.rs.list.as<int32_t>();
