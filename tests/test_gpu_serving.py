@@ -112,3 +112,80 @@ def test_admission_refuses_what_never_fits():
     t, ids, d = g.submit_search(q[:20], 10, 32)
     g.wait(t, 60.0)
     g.serve_stop()
+
+
+def test_background_consolidation_while_serving():
+    """With consolidate_async the serving loop merges each finished background
+    consolidation between mutations; a merge advances the epoch without a
+    request of its own.  Replaying the mutations one at a time, and merging
+    where the epochs show a merge, gives every search's result and the final
+    graph exactly."""
+    base, q = datagen.gmm_uint8_valued(602, 8000, 400, 64, 32)
+    build, extra = base[:6000], base[6000:]
+    rng = np.random.Generator(np.random.Philox(4))
+    opts = dict(consolidate_async=1, consolidate_frac=0.015)
+    reqs, live, pos = [], list(range(6000)), 0
+    for step in range(30):
+        kind = rng.choice(["search", "search", "insert", "delete", "delete"])
+        if kind == "insert" and pos < len(extra):
+            n = int(rng.integers(50, 400))
+            reqs.append(("insert", extra[pos:pos + n]))
+            live += list(range(6000 + pos, 6000 + pos + n))
+            pos += n
+        elif kind == "delete":
+            vic = rng.choice(live, 60, replace=False)
+            gone = set(vic.tolist())
+            live = [x for x in live if x not in gone]
+            reqs.append(("delete", vic.astype(np.int32)))
+        else:
+            reqs.append(("search", q[rng.integers(0, q.shape[0], int(rng.integers(1, 200)))]))
+    served = make(build, **opts)
+    served.serve_start(streams=4, max_batch=256)
+    tickets = []
+    for kind, data in reqs:
+        if kind == "search":
+            t, ids, d = served.submit_search(data, 10, 32)
+            tickets.append((t, kind, data, ids, d))
+        elif kind == "insert":
+            t, ids = served.submit_insert(data)
+            tickets.append((t, kind, data, ids, None))
+        else:
+            tickets.append((served.submit_delete(data), kind, data, None, None))
+    infos = [served.wait(t[0], 120.0) for t in tickets]
+    served.serve_stop()
+    assert served.stats()["consolidations"] >= 1
+    alone = make(build, **opts)
+    by_epoch = {}
+    for i, t in enumerate(tickets):
+        if t[1] == "search":
+            by_epoch.setdefault(infos[i]["epoch"], []).append(t)
+    state = 0
+
+    def check(e):
+        for t in by_epoch.pop(e, []):
+            ids, d = alone.search(t[2], 10, 32)
+            np.testing.assert_array_equal(ids, t[3])
+            np.testing.assert_array_equal(d, t[4])
+
+    check(0)
+    for i, t in enumerate(tickets):
+        if t[1] == "search":
+            continue
+        while infos[i]["epoch"] > state + 1:             # a merge came first
+            alone.consolidate_wait()
+            state += 1
+            check(state)
+        if t[1] == "insert":
+            np.testing.assert_array_equal(alone.insert(t[2]), t[3])
+        else:
+            alone.delete(t[2])
+        state += 1
+        check(state)
+    while by_epoch:                                     # merges after the last mutation
+        alone.consolidate_wait()
+        state += 1
+        check(state)
+    served.consolidate_wait()
+    alone.consolidate_wait()
+    for a_, b_ in zip(served.export_graph(), alone.export_graph()):
+        np.testing.assert_array_equal(a_, b_)
