@@ -255,6 +255,62 @@ def exact_kth_ip(torch, base_t, q_t, k, extra=64, chunk=64):
     return out
 
 
+def big_int_bench(torch, svf, datagen, n_base, steps, warmup, sample=1000):
+    """The 1M integer-valued workload's shape at n_base vectors (128-d,
+    256 components, L2, degree 64; 10k-query batch, k = 10), far larger than
+    the 256 MB Infinity Cache: plain FP32 at the smallest beam reaching
+    recall@10 >= 0.95 on a `sample`-query subsample."""
+    dim, R = 128, 64
+    base, queries = datagen.gmm_uint8_valued(2, n_base, 10_000, dim, 256)
+    ix = svf.Index(dim, R, svf.METRIC_L2, seed=0)
+    t0 = time.perf_counter()
+    ix.build(base)
+    build_s = time.perf_counter() - t0
+    base_t = torch.from_numpy(base).cuda()
+    q_t = torch.from_numpy(queries).cuda()
+    del base
+    nq = q_t.shape[0]
+    kth = exact_kth(torch, base_t, q_t[:sample], K, chunk=128)
+    bufs = (torch.empty((nq, K), dtype=torch.int32, device="cuda"),
+            torch.empty((nq, K), dtype=torch.float32, device="cuda"),
+            torch.empty(nq, dtype=torch.int32, device="cuda"),
+            torch.empty(nq, dtype=torch.int32, device="cuda"))
+    rows, beam = [], None
+    for b in BEAMS:
+        run_search(torch, ix, q_t, b, bufs)
+        torch.cuda.synchronize()
+        r = recall(torch, base_t, q_t[:sample], bufs[0][:sample], kth)
+        rows.append({"beam": b, "recall@10_sample": round(r, 5)})
+        log("10M beam", b, "recall", round(r, 4))
+        if r >= 0.95:
+            beam = b
+            break
+    beam = beam or BEAMS[-1]
+    ms, _ = timed_steps(torch, ix, q_t, beam, bufs, steps, warmup)
+    n_exp = int(bufs[3].sum().item())
+    slots = ix.get_option("visited_slots")
+    ix.set_option("visited_slots", 16384)
+    run_search(torch, ix, q_t, beam, bufs)
+    torch.cuda.synchronize()
+    n_dist = int(bufs[2].sum().item())
+    ix.set_option("visited_slots", slots)
+    ix.close()
+    alg = n_dist * dim * 4 + n_exp * R * 4
+    ms_step = float(np.mean(ms))
+    achieved = alg / (ms_step / 1e3) / 1e9
+    del base_t
+    return {"workload": "%dM x 128 integer-valued GMM (256 comps), L2, degree 64, 10k-query batch, "
+                        "k=10, plain FP32; recall on a %d-query sample" % (n_base // 1_000_000, sample),
+            "vector_bytes": n_base * dim * 4, "build_s": round(build_s, 2),
+            "beam": beam, "recall@10_sample": rows[-1]["recall@10_sample"], "sweep": rows,
+            "ms_per_step": round(ms_step, 4), "qps": round(nq / (ms_step / 1e3), 1),
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "alg_bytes_per_launch": alg,
+                         "n_dist_per_query": round(n_dist / nq, 1),
+                         "n_exp_per_query": round(n_exp / nq, 1)}}
+
+
 def large_bench(torch, svf, datagen, n_base, steps, warmup):
     """Plain FP32 search on an index whose vectors are far larger than the
     256 MB Infinity Cache: n_base x 96 unit-norm mixture (1024 components,
@@ -770,6 +826,8 @@ def main():
     ap.add_argument("--no-large", action="store_true",
                     help="skip the large-footprint (5M x 96) search leg")
     ap.add_argument("--large-n", type=int, default=5_000_000)
+    ap.add_argument("--big-n", type=int, default=10_000_000,
+                    help="size of the integer-valued leg beside the large-footprint one")
     ap.add_argument("--no-tier", action="store_true", help="skip the tiered-store leg")
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the workload-family / deletion-strategy ablation")
@@ -936,6 +994,9 @@ def main():
         ix.close()
         torch.cuda.empty_cache()
         large = large_bench(torch, svf, datagen, args.large_n, args.steps, args.warmup)
+        torch.cuda.empty_cache()
+        log("10M integer-valued search leg")
+        large["integer_10m"] = big_int_bench(torch, svf, datagen, args.big_n, args.steps, args.warmup)
 
     tier = None
     if not args.no_tier:
