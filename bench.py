@@ -918,6 +918,15 @@ def main():
     ms_step = float(np.mean(ms))
     achieved = alg_bytes / (ms_step / 1e3) / 1e9
     qps = nq / (ms_step / 1e3)
+    # the same batch through svf_search with host buffers (copies included)
+    q_host = queries[:nq]
+    ix.search(q_host, K, beam)
+    e2e = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        ix.search(q_host, K, beam)
+        e2e.append((time.perf_counter() - t0) * 1e3)
+    e2e_ms = float(np.median(e2e))
     log("small batches")
     small = small_batch_bench(torch, ix, q_t, base_t, kth, beam)
 
@@ -1079,6 +1088,10 @@ def main():
                                                                "ins_reverse_ms", "ins_commit_ms",
                                                                "del_mark_ms", "del_repair_ms")},
                    "repaired_rows": st["last_repaired"]},
+        "end_to_end_host_buffers": {"note": "svf_search with host buffers: query upload and "
+                                            "result download included; not the value",
+                                    "beam": beam, "ms_per_batch": round(e2e_ms, 3),
+                                    "qps": round(nq / (e2e_ms / 1e3), 1)},
         "small_batches": small,
         "large_footprint": large,
         "tiered": tier,
