@@ -15,6 +15,8 @@
 // produced; after another, all threads place every surviving key at its
 // rank (the count of smaller keys over the pool and the W lists) in the next
 // pool.  The entry phase, the exact re-scoring and the output run on wave 0.
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "wave_ops.hpp"
@@ -280,7 +282,9 @@ __global__ __launch_bounds__(64 * W) void search_coop_kernel(SearchArgs a) {
   if (wv != 0) return;
   int nd_all = 0;
   for (int v = 0; v < W; ++v) nd_all += meta[v];
-  if (a.rerank) {
+  // an FP32 traversal is exact already: only reduced-precision kernels carry
+  // the re-score
+  if constexpr (!std::is_same<VT, float>::value) if (a.rerank) {
     QuerySlice<float, NC> q32;
     q32.load(a.queries + qrow * a.qstride, a.dim, lane % QuerySlice<float, NC>::kLanesPerVec);
     uint64_t* buf = nxt;

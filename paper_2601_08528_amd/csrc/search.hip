@@ -22,6 +22,8 @@
 // across the wave (bitonic) and merged into the pool by rank (merge path),
 // which also drops re-evaluated ids.  The loop ends when every pool entry is
 // expanded (or after max_iters expansions).
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "wave_ops.hpp"
@@ -29,7 +31,7 @@
 namespace svf {
 
 // ---------------------------------------------------------------------------
-template <typename VT, int NC, typename VIS, bool TIER>
+template <typename VT, int NC, typename VIS, bool TIER, bool FULL>
 __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int qi = blockIdx.x;
@@ -47,6 +49,9 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
   // FP32 traversal reads through the cache; a reduced-precision traversal
   // store stays in HBM and only the exact re-scoring reads go through it.
   constexpr bool tier = TIER && sizeof(VT) == 4;
+  // the traversal's gather: branch-free rounds for unscaled rows in HBM,
+  // without any per-lane test when the rows fill their chunks (FULL)
+  constexpr int form = (tier || Elem<VT>::kScaled) ? 0 : FULL ? 2 : 1;
   unsigned long long t_hit = 0, t_miss = 0;
   w.L = a.L;
   w.ktrack = a.last_change ? (a.k > 0 ? a.k : 1) : 0;
@@ -99,7 +104,7 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
         t_hit += popc64(ballot(h));
         t_miss += nt - popc64(ballot(h));
       }
-      uint64_t k = gather_keys<VT, NC, tier>(qs, base, a.vstride, w.cid, nt, a.metric, slot,
+      uint64_t k = gather_keys<VT, NC, tier, form>(qs, base, a.vstride, w.cid, nt, a.metric, slot,
                                              reinterpret_cast<const VT*>(a.tcache), a.vscale);
       n_dist += nt;
       sort_merge(w, k);
@@ -197,7 +202,7 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
         // the deletion bits load while the vectors are gathered
         const int32_t mine = lane < m ? w.cid[lane] : 0;
         const uint32_t aword = a.alive[(uint32_t)mine >> 5];
-        uint64_t k = gather_keys<VT, NC, tier>(qs, base, a.vstride, w.cid, m, a.metric, slot,
+        uint64_t k = gather_keys<VT, NC, tier, form>(qs, base, a.vstride, w.cid, m, a.metric, slot,
                                                reinterpret_cast<const VT*>(a.tcache), a.vscale);
         if (lane < m && !((aword >> (mine & 31)) & 1u)) k = kKeyInf;
         n_dist += m;
@@ -207,7 +212,9 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
   }
 
   // ---- exact re-scoring of the final pool (reduced-precision traversal) ------
-  if (a.rerank) {
+  // an FP32 traversal is exact already: only reduced-precision kernels carry
+  // the re-score
+  if constexpr (!std::is_same<VT, float>::value) if (a.rerank) {
     QuerySlice<float, NC> q32;
     q32.load(a.queries + qrow * a.qstride, a.dim, lane % QuerySlice<float, NC>::kLanesPerVec);
     uint64_t* buf = w.next;
@@ -304,17 +311,28 @@ static bool use_tags(int32_t n_slots, int T) {
 }
 static size_t vis_bytes(int T, bool tags) { return tags ? (size_t)T * 2 : (size_t)T * 4; }
 
-template <typename VT, typename VIS, bool TIER>
-static hipError_t launch_vt(const SearchArgs& a, int nc, size_t lds, hipStream_t st) {
+template <typename VT, typename VIS, bool TIER, bool FULL>
+static hipError_t launch_nc(const SearchArgs& a, int nc, size_t lds, hipStream_t st) {
   dim3 grid(a.nq), block(kWave);
   switch (nc) {
-    case 1: hipLaunchKernelGGL((search_kernel<VT, 1, VIS, TIER>), grid, block, lds, st, a); break;
-    case 2: hipLaunchKernelGGL((search_kernel<VT, 2, VIS, TIER>), grid, block, lds, st, a); break;
-    case 4: hipLaunchKernelGGL((search_kernel<VT, 4, VIS, TIER>), grid, block, lds, st, a); break;
-    case 8: hipLaunchKernelGGL((search_kernel<VT, 8, VIS, TIER>), grid, block, lds, st, a); break;
+    case 1: hipLaunchKernelGGL((search_kernel<VT, 1, VIS, TIER, FULL>), grid, block, lds, st, a); break;
+    case 2: hipLaunchKernelGGL((search_kernel<VT, 2, VIS, TIER, FULL>), grid, block, lds, st, a); break;
+    case 4: hipLaunchKernelGGL((search_kernel<VT, 4, VIS, TIER, FULL>), grid, block, lds, st, a); break;
+    case 8: hipLaunchKernelGGL((search_kernel<VT, 8, VIS, TIER, FULL>), grid, block, lds, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// Rows that fill all nc chunks of 128 elements (stride 128, 256, 512, 1024)
+// take the kernel whose gather loads carry no per-lane test.  Kernels that
+// gather with the predicated form either way have no such twin.
+template <typename VT, typename VIS, bool TIER>
+static hipError_t launch_vt(const SearchArgs& a, int nc, size_t lds, hipStream_t st) {
+  constexpr bool kTwin = !Elem<VT>::kScaled && !(TIER && sizeof(VT) == 4);
+  if constexpr (kTwin)
+    if (a.vstride >= (int64_t)nc * 128) return launch_nc<VT, VIS, TIER, true>(a, nc, lds, st);
+  return launch_nc<VT, VIS, TIER, false>(a, nc, lds, st);
 }
 
 template <typename VIS>

@@ -233,7 +233,7 @@ __device__ __forceinline__ float reduce_scatter(float (&acc)[U]) {
 #define SVF_GATHER_STEPS_F32 16
 #endif
 #ifndef SVF_GATHER_STEPS_16
-#define SVF_GATHER_STEPS_16 8
+#define SVF_GATHER_STEPS_16 4
 #endif
 #ifndef SVF_GATHER_STEPS_8
 #define SVF_GATHER_STEPS_8 4
@@ -245,18 +245,17 @@ template <typename VT, int NC> struct GatherSteps {
   static constexpr int value = base / NC < 2 ? 2 : base / NC;
 };
 
-// Distances of the m (<= 64) ids in cid[] to the query; returns, in lane j,
-// the key of cid[j] (kKeyInf for j >= m).  A step gathers VPW vectors, one per
-// group of LPV lanes; U steps are loaded before any is consumed.
-// With a tier (TIER), vector j is read from tcache row slot[j] when that slot
-// is >= 0 and from base row cid[j] otherwise.  A scaled (FP8) store reads the
-// vector's scale from vscale[id] with its row.
-template <typename VT, int NC, bool TIER = false>
-__device__ inline uint64_t gather_keys(const QuerySlice<VT, NC>& qs, const VT* __restrict__ base,
-                                       int64_t stride, const int32_t* cid, int m, int metric,
-                                       const int32_t* slot = nullptr,
-                                       const VT* __restrict__ tcache = nullptr,
-                                       const float* __restrict__ vscale = nullptr) {
+// The distance rounds of gather_keys: returns, in lane j < m, the summed
+// distance of candidate j.  FORM 0: each lane loads only its own candidate's
+// slice (predicated); FORM 1: lanes past m load candidate 0's row instead,
+// only the slices past a short row are predicated; FORM 2: as 1, for rows
+// whose every 16-byte slice lies inside (stride >= NC * 128 elements), with
+// no per-lane test at all.  The tiered variant is always FORM 0.
+template <typename VT, int NC, bool TIER, int FORM>
+__device__ inline float gather_rounds(const QuerySlice<VT, NC>& qs, const VT* __restrict__ base,
+                                      int64_t stride, const int32_t* cid, int m, int metric,
+                                      const int32_t* slot, const VT* __restrict__ tcache,
+                                      const float* __restrict__ vscale) {
   constexpr bool kScaled = Elem<VT>::kScaled;
   using QS = QuerySlice<VT, NC>;
   constexpr int E = QS::E;
@@ -266,8 +265,12 @@ __device__ inline uint64_t gather_keys(const QuerySlice<VT, NC>& qs, const VT* _
   // needs registers); the reduction tree, and so every sum, is the same
   constexpr int UB = GatherSteps<VT, NC>::value < LPV ? GatherSteps<VT, NC>::value : LPV;
   constexpr int U = TIER ? (UB / 2 < 2 ? 2 : UB / 2) : UB;
+  // the reduction hands whole lane groups down: U must be a power of two
+  // that divides LPV
+  static_assert(U >= 1 && (U & (U - 1)) == 0 && LPV % U == 0, "gather steps");
   const int lane = lane_id();
   const int sub = lane / LPV, sl = lane % LPV;
+  const uint32_t ustride = (uint32_t)stride;
   float mine = 0.0f;
   const int steps = (m + VPW - 1) / VPW;
   for (int s0 = 0; s0 < steps; s0 += U) {
@@ -277,21 +280,49 @@ __device__ inline uint64_t gather_keys(const QuerySlice<VT, NC>& qs, const VT* _
     for (int u = 0; u < U; ++u) {
       const int j = (s0 + u) * VPW + sub;
       const bool on = j < m;
-      const int32_t id = on ? cid[j] : 0;
-      const VT* row = base + (int64_t)id * stride;
-      if constexpr (kScaled) xs[u] = on ? vscale[id] : 0.0f;
-      else xs[u] = 1.0f;
       if constexpr (TIER) {
+        const int32_t id = on ? cid[j] : 0;
+        const VT* row = base + (uint64_t)(uint32_t)id * ustride;
+        if constexpr (kScaled) xs[u] = on ? vscale[id] : 0.0f;
+        else xs[u] = 1.0f;
         const int32_t sl_ = on ? slot[j] : -1;
-        if (sl_ >= 0) row = tcache + (int64_t)sl_ * stride;
-      }
+        if (sl_ >= 0) row = tcache + (uint64_t)(uint32_t)sl_ * ustride;
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        const int off = c * 128 + sl * E;
-        if (on && off < stride)
-          w[u][c] = *reinterpret_cast<const uint4*>(row + off);
-        else
-          w[u][c] = make_uint4(0, 0, 0, 0);
+        for (int c = 0; c < NC; ++c) {
+          const int off = c * 128 + sl * E;
+          if (on && off < stride)
+            w[u][c] = *reinterpret_cast<const uint4*>(row + off);
+          else
+            w[u][c] = make_uint4(0, 0, 0, 0);
+        }
+      } else if constexpr (FORM != 0) {
+        // lanes past m read candidate 0's row (its own lanes load it too);
+        // their sums stay in their own lane group and are dropped later
+        const int32_t id = cid[on ? j : 0];
+        const VT* row = base + (uint64_t)(uint32_t)id * ustride;
+        if constexpr (kScaled) xs[u] = vscale[id];
+        else xs[u] = 1.0f;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const int off = c * 128 + sl * E;
+          if (FORM == 2 || off < stride)
+            w[u][c] = *reinterpret_cast<const uint4*>(row + off);
+          else
+            w[u][c] = make_uint4(0, 0, 0, 0);
+        }
+      } else {
+        const int32_t id = on ? cid[j] : 0;
+        const VT* row = base + (uint64_t)(uint32_t)id * ustride;
+        if constexpr (kScaled) xs[u] = on ? vscale[id] : 0.0f;
+        else xs[u] = 1.0f;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const int off = c * 128 + sl * E;
+          if (on && off < stride)
+            w[u][c] = *reinterpret_cast<const uint4*>(row + off);
+          else
+            w[u][c] = make_uint4(0, 0, 0, 0);
+        }
       }
     }
     float acc[U];
@@ -305,9 +336,34 @@ __device__ inline uint64_t gather_keys(const QuerySlice<VT, NC>& qs, const VT* _
     const float got = __shfl(r, src);
     if (u >= 0 && u < U) mine = got;
   }
+  return mine;
+}
+
+// Distances of the m (<= 64) ids in cid[] to the query; returns, in lane j,
+// the key of cid[j] (kKeyInf for j >= m).  A step gathers VPW vectors, one per
+// group of LPV lanes; U steps are loaded before any is consumed.  FORM picks
+// the load rounds of gather_rounds; every form gives the same sums.  Forms 1
+// and 2 are for unscaled, untiered stores, and form 2 needs stride >= NC * 128.
+// A kernel inlines one form only: with two, the compiler keeps the step arrays
+// in scratch memory.
+// With a tier (TIER), vector j is read from tcache row slot[j] when that slot
+// is >= 0 and from base row cid[j] otherwise.  A scaled (FP8) store reads the
+// vector's scale from vscale[id] with its row.
+template <typename VT, int NC, bool TIER = false, int FORM = 0>
+__device__ inline uint64_t gather_keys(const QuerySlice<VT, NC>& qs, const VT* __restrict__ base,
+                                       int64_t stride, const int32_t* cid, int m, int metric,
+                                       const int32_t* slot = nullptr,
+                                       const VT* __restrict__ tcache = nullptr,
+                                       const float* __restrict__ vscale = nullptr) {
+  constexpr bool kScaled = Elem<VT>::kScaled;
+  static_assert(FORM == 0 || (!TIER && !kScaled), "gather form");
+  const int lane = lane_id();
+  const float mine =
+      gather_rounds<VT, NC, TIER, FORM>(qs, base, stride, cid, m, metric, slot, tcache, vscale);
   if (lane >= m) return kKeyInf;
-  if (kScaled && metric != 0) mine *= vscale[cid[lane]];
-  const float d = metric == 0 ? mine : -mine;
+  float x = mine;
+  if (kScaled && metric != 0) x *= vscale[cid[lane]];
+  const float d = metric == 0 ? x : -x;
   return make_key(d, cid[lane]);
 }
 
