@@ -214,8 +214,11 @@ __device__ __forceinline__ float reduce_scatter(float (&acc)[U]) {
     const bool hi = (lane & o) != 0;
 #pragma unroll
     for (int i = 0; i < half; ++i) {
-      const float send = hi ? acc[i] : acc[i + half];
-      const float keep = hi ? acc[i + half] : acc[i];
+      // select values, not array elements: a conditional over two elements
+      // is an address select, which keeps acc in scratch memory
+      const float lo_v = acc[i], hi_v = acc[i + half];
+      const float send = hi ? lo_v : hi_v;
+      const float keep = hi ? hi_v : lo_v;
       acc[i] = keep + __shfl_xor(send, o);
     }
   }
@@ -225,22 +228,27 @@ __device__ __forceinline__ float reduce_scatter(float (&acc)[U]) {
   return r;
 }
 
-// Vector steps gathered per round trip: 32 vectors of one 128-element chunk
-// (FP32 16 steps of 2 vectors, 16-bit 8 steps of 4, FP8 4 steps of 8), fewer
-// steps for wider vectors.  Powers of two; on the 1M x 128 workload more
-// steps in flight only cost registers.
+// Vector steps gathered per round trip, powers of two, fewer for wider
+// vectors: FP32 16 steps of 2 vectors (32 vectors of one 128-element chunk),
+// 16-bit 8 steps of 4 on full rows and 4 steps on short ones, FP8 4 steps of
+// 8.  Chosen by measurement on 1M-vector indexes of 128 and 96 dimensions;
+// more steps in flight only cost registers there.
 #ifndef SVF_GATHER_STEPS_F32
 #define SVF_GATHER_STEPS_F32 16
 #endif
 #ifndef SVF_GATHER_STEPS_16
 #define SVF_GATHER_STEPS_16 4
 #endif
+#ifndef SVF_GATHER_STEPS_16_FULL
+#define SVF_GATHER_STEPS_16_FULL 8
+#endif
 #ifndef SVF_GATHER_STEPS_8
 #define SVF_GATHER_STEPS_8 4
 #endif
-template <typename VT, int NC> struct GatherSteps {
+template <typename VT, int NC, int FORM> struct GatherSteps {
   static constexpr int base = sizeof(VT) == 4   ? SVF_GATHER_STEPS_F32
-                              : sizeof(VT) == 2 ? SVF_GATHER_STEPS_16
+                              : sizeof(VT) == 2 ? (FORM == 2 ? SVF_GATHER_STEPS_16_FULL
+                                                             : SVF_GATHER_STEPS_16)
                                                 : SVF_GATHER_STEPS_8;
   static constexpr int value = base / NC < 2 ? 2 : base / NC;
 };
@@ -263,7 +271,8 @@ __device__ inline float gather_rounds(const QuerySlice<VT, NC>& qs, const VT* __
   constexpr int VPW = QS::kVecPerWave;
   // the tiered variant keeps half as many loads in flight (its row choice
   // needs registers); the reduction tree, and so every sum, is the same
-  constexpr int UB = GatherSteps<VT, NC>::value < LPV ? GatherSteps<VT, NC>::value : LPV;
+  constexpr int kSteps = GatherSteps<VT, NC, FORM>::value;
+  constexpr int UB = kSteps < LPV ? kSteps : LPV;
   constexpr int U = TIER ? (UB / 2 < 2 ? 2 : UB / 2) : UB;
   // the reduction hands whole lane groups down: U must be a power of two
   // that divides LPV
