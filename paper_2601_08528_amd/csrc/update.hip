@@ -80,23 +80,41 @@ __device__ void prune_core(const uint64_t* keys, int m, const RowSource& rs, int
       }
     }
     __syncthreads();
-    // detour counts: entry r of row(c_j) naming c_i with i > j
+    // detour counts: entry r of row(c_j) naming c_i with i > j.  Entry
+    // t = j * R + r goes to lane t % 64; each lane loads kRowSteps entries
+    // (rows of different candidates) before it probes any, so that many row
+    // reads are in flight per wave.  The counts are sums, so the order in
+    // which entries are probed does not matter.
+    constexpr int kRowSteps = 8;
     const int total = m * R;
-    for (int t = lane; t < total; t += kWave) {
-      const int j = t / R;
-      const int r = t - j * R;
-      const int32_t e = rs.row(key_id(keys[j]))[r];
-      if (e < 0) continue;
-      uint32_t sl = slot_hash((uint32_t)e, mask);
-      for (;;) {
-        const uint32_t k = s.mkey[sl];
-        if (k == (uint32_t)e) {
-          const int i = (int)s.mval[sl];
-          if (i > j) atomicAdd(&s.cnt[i], 1u);
-          break;
+    int j0 = lane / R, r0 = lane - (lane / R) * R;   // (j, r) of entry t0 + lane
+    for (int t0 = 0; t0 < total; t0 += kWave * kRowSteps) {
+      int32_t e[kRowSteps];
+      int jj[kRowSteps];
+      int j = j0, r = r0;
+#pragma unroll
+      for (int u = 0; u < kRowSteps; ++u) {
+        jj[u] = j;
+        e[u] = t0 + u * kWave + lane < total ? rs.row(key_id(keys[j]))[r] : -1;
+        r += kWave;
+        while (r >= R) { r -= R; ++j; }
+      }
+      j0 = j;
+      r0 = r;
+#pragma unroll
+      for (int u = 0; u < kRowSteps; ++u) {
+        if (e[u] < 0) continue;
+        uint32_t sl = slot_hash((uint32_t)e[u], mask);
+        for (;;) {
+          const uint32_t k = s.mkey[sl];
+          if (k == (uint32_t)e[u]) {
+            const int i = (int)s.mval[sl];
+            if (i > jj[u]) atomicAdd(&s.cnt[i], 1u);
+            break;
+          }
+          if (k == kEmpty) break;
+          sl = (sl + 1) & mask;
         }
-        if (k == kEmpty) break;
-        sl = (sl + 1) & mask;
       }
     }
     __syncthreads();
