@@ -54,6 +54,29 @@ __device__ __forceinline__ int lanes_below(uint64_t mask) {
 __device__ __forceinline__ int popc64(uint64_t m) { return __popcll(m); }
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Value of lane (lane ^ J) for a constant power of two J: a DPP quad
+// permutation for 1 and 2 (a vector-ALU move, no LDS round trip), the LDS
+// swizzle network for 4 to 16 (no address register), a bpermute for 32.
+// Every lane of the wave must be active.  (DPP row shifts for 4 and 8, two
+// moves and a select, measured slower than the swizzle in the search kernel.)
+template <int J>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v) {
+  static_assert(J == 1 || J == 2 || J == 4 || J == 8 || J == 16 || J == 32, "xor_lane");
+  const int x = (int)v;
+  if constexpr (J == 1) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false);   // quad [1,0,3,2]
+  } else if constexpr (J == 2) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(x, x, 0x4E, 0xF, 0xF, false);   // quad [2,3,0,1]
+  } else if constexpr (J <= 16) {
+    return (uint32_t)__builtin_amdgcn_ds_swizzle(x, 0x1F | (J << 10));   // and 0x1f, xor J
+  } else {
+    return (uint32_t)__shfl_xor(x, 32);
+  }
+}
+template <int J>
+__device__ __forceinline__ float xor_lane_f(float v) {
+  return __uint_as_float(xor_lane<J>(__float_as_uint(v)));
+}
 // Ascending bitonic sort of one 64-bit key per lane across the wave.
 __device__ __forceinline__ uint64_t wave_sort64(uint64_t key) {
   const int lane = lane_id();

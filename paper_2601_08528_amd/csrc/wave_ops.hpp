@@ -204,13 +204,11 @@ __device__ __forceinline__ float partial_dist(const QuerySlice<VT, NC>& qs, cons
 // subtrees as a plain butterfly would, so every sum is bitwise the value a
 // butterfly reduction gives, whatever its position in the batch.  Lane l of a
 // group ends with the sum of step l / (LPV / U).
-template <int LPV, int U>
-__device__ __forceinline__ float reduce_scatter(float (&acc)[U]) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int s = 0; (U >> s) > 1; ++s) {
-    const int o = LPV >> (s + 1);
-    const int half = (U >> s) / 2;
+template <int LPV, int U, int S = 0>
+__device__ __forceinline__ void reduce_scatter_stage(float (&acc)[U], int lane) {
+  if constexpr ((U >> S) > 1) {
+    constexpr int o = LPV >> (S + 1);
+    constexpr int half = (U >> S) / 2;
     const bool hi = (lane & o) != 0;
 #pragma unroll
     for (int i = 0; i < half; ++i) {
@@ -219,13 +217,24 @@ __device__ __forceinline__ float reduce_scatter(float (&acc)[U]) {
       const float lo_v = acc[i], hi_v = acc[i + half];
       const float send = hi ? lo_v : hi_v;
       const float keep = hi ? hi_v : lo_v;
-      acc[i] = keep + __shfl_xor(send, o);
+      acc[i] = keep + xor_lane_f<o>(send);
     }
+    reduce_scatter_stage<LPV, U, S + 1>(acc, lane);
   }
-  float r = acc[0];
-#pragma unroll
-  for (int o = LPV / U / 2; o >= 1; o >>= 1) r += __shfl_xor(r, o);
-  return r;
+}
+template <int O>
+__device__ __forceinline__ float butterfly_down(float r) {
+  if constexpr (O >= 1) {
+    r += xor_lane_f<O>(r);
+    return butterfly_down<O / 2>(r);
+  } else {
+    return r;
+  }
+}
+template <int LPV, int U>
+__device__ __forceinline__ float reduce_scatter(float (&acc)[U]) {
+  reduce_scatter_stage<LPV, U>(acc, lane_id());
+  return butterfly_down<LPV / U / 2>(acc[0]);
 }
 
 // Vector steps gathered per round trip, powers of two, fewer for wider
@@ -423,7 +432,9 @@ __device__ inline bool merge_into_pool(WaveCtx& w, uint64_t nk) {
 
 
 // Ascending bitonic sort of the keys held by the first W lanes (W a power of
-// two); the other lanes must hold kKeyInf.
+// two); the other lanes must hold kKeyInf.  (A fully unrolled form with
+// constant exchange distances measured slower: its code grows with every
+// width it must cover.)
 __device__ __forceinline__ uint64_t wave_sort_width(uint64_t key, int W) {
   const int lane = lane_id();
   for (int k = 2; k <= W; k <<= 1) {
