@@ -979,14 +979,14 @@ def main():
     ix.set_option("use_model", 1)
     ix.set_option("model_conf", 0.0)
     # the visited table's size never changes results, only the balance of
-    # re-evaluations against LDS occupancy: with cheap reduced-precision
-    # distances the smaller table can be the faster one
+    # re-evaluations against LDS occupancy (the library's default for reduced
+    # precision is 2048 slots); both sizes are tried
     slots0 = int(ix.get_option("visited_slots"))
     best = None
     tried = []
     for pname, prec in (("bf16", svf.PREC_BF16), ("fp8", svf.PREC_FP8)):
         ix.set_option("precision", prec)
-        for slots in (slots0, 2048):
+        for slots in (4096, 2048):
             ix.set_option("visited_slots", slots)
             for width, stop_scale in ((1, 2.0), (2, 1.0), (2, 1.5), (1, 1e6)):
                 ix.set_option("search_width", width)

@@ -69,8 +69,13 @@ float* lp_scale(void* veclp, const svf_index* ix, int prec, int64_t cap) {
   return reinterpret_cast<float*>(static_cast<char*>(veclp) + (size_t)cap * lp_row_bytes(ix, prec));
 }
 
+// Visited-table slots of one search.  0 (the default) picks by traversal
+// precision: 4096 for FP32 and 2048 for reduced precision, whose cheaper
+// distances gain more from the smaller table's higher LDS occupancy than they
+// lose to its extra re-evaluations.  The size never changes results.
 int visited_slots(const svf_index* ix, int E) {
   int T = ix->opt.visited_slots;
+  if (T == 0) T = ix->veclp_prec != 0 ? 2048 : 4096;
   while (T < 2 * E) T <<= 1;   // entry phase needs an exact table
   return T;
 }
@@ -1452,8 +1457,8 @@ int svf_set_option(svf_index* ix, const char* key, double v) {
     o.max_iters = (int)v;
   } else if (k == "visited_slots") {
     int t = (int)v;
-    if (!is_int(v) || t < 256 || t > 16384 || (t & (t - 1)))
-      return fail(SVF_E_INVAL, "visited_slots: power of two in [256, 16384]");
+    if (!is_int(v) || (t != 0 && (t < 256 || t > 16384 || (t & (t - 1)))))
+      return fail(SVF_E_INVAL, "visited_slots: 0 or a power of two in [256, 16384]");
     o.visited_slots = t;
   } else if (k == "visited_compact") {
     if (v != 0 && v != 1) return fail(SVF_E_INVAL, "visited_compact 0 or 1");

@@ -66,7 +66,7 @@ struct Options {
   int max_iters = 0;
   int search_width = 1;
   int coop_max_batch = 1024;
-  int visited_slots = 4096;
+  int visited_slots = 0;        // 0: by traversal precision (visited_slots())
   int visited_compact = 1;
   int repair_c = 8;
   int localized_repair = 1;
