@@ -97,8 +97,9 @@ int svf_destroy(svf_index *ix);
  *                   unchanged; FP32/BF16/FP8, degree <= 64, dim <= 256, untiered)
  *                   (0..2^22; 1024; 0 = never)
  *   visited_slots   LDS visited-table slots per query: a power of two (256..16384), or 0
- *                   for 4096 with FP32 traversal and 2048 with reduced precision (0; the
- *                   size never changes results, only re-evaluations against occupancy)
+ *                   for 4096 with FP32 traversal and 2048 with reduced precision on up to
+ *                   2^24 ids (0; the size never changes results, only re-evaluations
+ *                   against occupancy)
  *   visited_compact exact quotient tags of a scrambled id (12-bit, five per 64-bit set, or
  *                   16-bit, four per set) instead of full 32-bit ids, when the ids fit (0/1; 1)
  *   repair_c        out-neighbours taken from each deleted neighbour (1..min(16, degree); 8)

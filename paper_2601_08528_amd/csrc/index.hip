@@ -72,10 +72,11 @@ float* lp_scale(void* veclp, const svf_index* ix, int prec, int64_t cap) {
 // Visited-table slots of one search.  0 (the default) picks by traversal
 // precision: 4096 for FP32 and 2048 for reduced precision, whose cheaper
 // distances gain more from the smaller table's higher LDS occupancy than they
-// lose to its extra re-evaluations.  The size never changes results.
+// lose to its extra re-evaluations, as long as the ids fit its 16-bit tags
+// (2^24 ids at 2048 slots); beyond that 4096.  The size never changes results.
 int visited_slots(const svf_index* ix, int E) {
   int T = ix->opt.visited_slots;
-  if (T == 0) T = ix->veclp_prec != 0 ? 2048 : 4096;
+  if (T == 0) T = (ix->veclp_prec != 0 && ix->n_slots <= (int64_t)1 << 24) ? 2048 : 4096;
   while (T < 2 * E) T <<= 1;   // entry phase needs an exact table
   return T;
 }
