@@ -72,11 +72,13 @@ def lib():
         L.orc_prune_explicit.argtypes = [i32, i32, vp, vp, vp, i64, vp, vp]
         L.orc_query_dists.argtypes = [vp, vp, i64, i32, vp, vp]
         L.orc_search_expansions.argtypes = [vp, vp, i64, i32, vp, i32, vp]
-        L.orc_wavp_replay.argtypes = [i64, i64, vp, vp, vp, vp, i32, f64, f64, f64, i32, i32, vp, vp]
+        L.orc_wavp_replay.argtypes = [i64, i64, vp, vp, vp, vp, i32, f64, f64, f64, i32, i32, f64, vp,
+                                      vp, vp]
         L.orc_policy_replay.argtypes = [i32, i64, i64, vp, vp, vp, vp, i32, i32, i32, vp, vp]
         L.orc_search_listed.argtypes = [vp, vp, i64, i32, i32, vp, i32, vp, vp, vp, vp]
         L.orc_search_trace.argtypes = [vp, vp, i64, i32, i32, vp, vp]
         L.orc_mlp_forward.argtypes = [i32, i32, i32] + [vp] * 6 + [vp, i64, vp]
+        L.orc_model_decide.argtypes = [vp, i64, i32, f64, f64, i32, vp, vp]
         L.orc_mlp_loss_grad.restype = f64
         L.orc_mlp_loss_grad.argtypes = [i32, i32, i32] + [vp] * 6 + [vp, vp, vp, i64, f64, f64] + [vp] * 6
         _lib = L
@@ -303,11 +305,25 @@ class MLP:
         return loss, g
 
 
+def model_decide(z, conf, stop_scale, min_iters):
+    """Gating of the learned form from outputs z (n x (nc + 1)): per query
+    the entry cluster or -1 (plain search), and the expansion cap (0 for
+    plain search)."""
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    n, nc = z.shape[0], z.shape[1] - 1
+    qe = np.empty(n, np.int32)
+    qm = np.empty(n, np.int32)
+    lib().orc_model_decide(_p(z), n, nc, conf, stop_scale, min_iters, _p(qe), _p(qm))
+    return qe, qm
+
+
 def wavp_replay(n, C, e_in, alive, batches, alpha=0.6, beta=0.4, theta=1.0, promote_max=2048,
-                warm=False):
-    """Batched workload-aware placement over per-batch access traces; returns
-    (hits per batch, final slot table).  warm=True starts from the cold-start
-    placement (highest in-degree alive vectors first)."""
+                warm=False, adapt=0.0, with_theta=False):
+    """Batched workload-aware placement (Alg. 2) over per-batch access
+    traces; returns (hits per batch, final slot table), plus the theta in
+    force for each batch when with_theta.  warm=True starts from the
+    cold-start placement (highest in-degree alive vectors first); adapt > 1
+    turns on the theta adaptation by that factor."""
     e = np.ascontiguousarray(e_in, dtype=np.int32)
     a = np.ascontiguousarray(alive, dtype=np.uint8)
     flat = np.ascontiguousarray(np.concatenate([np.asarray(b, np.int32) for b in batches])
@@ -316,8 +332,11 @@ def wavp_replay(n, C, e_in, alive, batches, alpha=0.6, beta=0.4, theta=1.0, prom
     off[1:] = np.cumsum([len(b) for b in batches])
     hits = np.empty(len(batches), np.int64)
     slots = np.empty(max(C, 1), np.int32)
+    th = np.empty(max(len(batches), 1), np.float64)
     lib().orc_wavp_replay(n, C, _p(e), _p(a), _p(flat), _p(off), len(batches), alpha, beta, theta,
-                          promote_max, int(warm), _p(hits), _p(slots))
+                          promote_max, int(warm), float(adapt), _p(hits), _p(slots), _p(th))
+    if with_theta:
+        return hits, slots[:C], th[:len(batches)]
     return hits, slots[:C]
 
 

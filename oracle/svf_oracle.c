@@ -1292,6 +1292,38 @@ int orc_search_listed(const orc_index *ix, const float *q, int64_t nq, int k, in
 }
 
 /* ------------------------------------------------------------------------ */
+/* The gating of the learned form (an extension of the method: entry points
+ * supplied by a separate algorithm, Sec. 2.3, and a stop before Alg. 1 has
+ * expanded everything).  From a query's outputs z (nc cluster logits, then
+ * the predicted log stop step): the cluster is the first largest logit; its
+ * softmax probability p = 1 / sum_j exp(z_j - z_max); with p >= conf the
+ * query starts from that cluster's entry list and its expansions are capped
+ * at max(min_iters, ceil(stop_scale * exp(min(z_nc, 20)))), the ceiling held
+ * at or below 2^30; otherwise it runs plain search (cluster -1, no cap). */
+void orc_model_decide(const double *z, int64_t n, int nc, double conf, double stop_scale,
+                      int min_iters, int32_t *q_entry, int32_t *q_max)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        const double *zi = z + i * (nc + 1);
+        int best = 0;
+        for (int j = 1; j < nc; ++j)
+            if (zi[j] > zi[best]) best = j;
+        double se = 0.0;
+        for (int j = 0; j < nc; ++j) se += exp(zi[j] - zi[best]);
+        const double p = 1.0 / se;
+        if (p >= conf) {
+            double cap = ceil(stop_scale * exp(zi[nc] < 20.0 ? zi[nc] : 20.0));
+            if (cap > 1073741824.0) cap = 1073741824.0;
+            q_entry[i] = best;
+            q_max[i] = cap < (double)min_iters ? min_iters : (int32_t)cap;
+        } else {
+            q_entry[i] = -1;
+            q_max[i] = 0;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* The entry/stop predictor: a multilayer perceptron din -> h -> h -> nc + 1
  * with ReLU, FP64 here.  Outputs 0..nc-1 are logits of the entry cluster,
  * output nc predicts log(stop step).  Loss per sample: softmax cross-entropy
@@ -1456,30 +1488,55 @@ int orc_search_expansions(const orc_index *ix, const float *q, int64_t nq, int L
 /* ------------------------------------------------------------------------ */
 /* Workload-aware vector placement (Sec. 4.3, Alg. 2, Eq. 2) replayed over
  * per-batch access traces, in the batched form:
- *   F_lambda(x) = alpha * F_recent(x) + beta * log(1 + E_in(x));
- *   per batch: F_recent halves, then counts this batch's accesses; accesses to
- *   resident vectors are hits and set the reference bit of their slot; the
- *   distinct missed vectors with F_lambda > theta, by (F_lambda desc, id asc),
- *   at most `promote_max` of them, are placed: into a free slot, else by a
- *   clock sweep (at most 2C steps) that clears set reference bits and evicts
- *   the first slot with a clear bit whose vector has a lower F_lambda (a
- *   deleted vector counts as -1); a candidate that finds no victim ends the
- *   batch's placements.
+ *   F_lambda(x) = alpha * F_recent(x) + beta * log(1 + E_in(x)).
+ * Per batch: F_recent halves, then counts this batch's accesses; accesses to
+ * resident vectors are hits and set the reference bit of their slot.  The
+ * distinct missed vectors with F_lambda > theta, by (F_lambda desc, id asc),
+ * at most `promote_max` of them, are placed one after another (Alg. 2):
+ *   - into a free slot while the cache is not full (Alg. 2 covers the full
+ *     cache);
+ *   - else F_min = the least F_lambda over residents whose reference bit is
+ *     clear; the clock hand then walks from where it stands: a slot with a
+ *     set bit has it cleared and the hand moves on; the first slot with a
+ *     clear bit whose vector has F_lambda = F_min is the victim.  The new
+ *     vector takes that slot with a clear bit, and the hand stays on it.
+ *     When every bit is set, the minimum over an empty set leaves the sweep
+ *     without a target: it then goes round once clearing every bit (the hand
+ *     comes back to where it started) and F_min is taken over all residents.
+ * A deleted vector counts F_lambda = -1.
+ * theta adaptation (Sec. 4.4), when adapt > 1: once a batch's accesses are
+ * counted, its miss rate (missed accesses / accesses) and the mean F_lambda
+ * of its distinct missed alive vectors (summed in id order) are compared
+ * with those of the previous batch that had accesses: if both rose, theta is
+ * multiplied by adapt; if both fell, it is divided by adapt but kept at or
+ * above the starting theta.  The theta in force for each batch's placements
+ * is written to theta_out[b] (may be NULL).
  * With warm != 0 the cache starts warm (cold-start placement, Sec. 4.4): the
  * alive vectors of highest E_in, ties by id, fill slots 0, 1, ... in order.
  * trace: concatenated accesses, batch b spanning [off[b], off[b+1]).
  * Out: hits per batch, and the final slot -> id table (-1 empty). */
+static int cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
 void orc_wavp_replay(int64_t n, int64_t C, const int32_t *e_in, const uint8_t *alive,
                      const int32_t *trace, const int64_t *off, int nb, double alpha, double beta,
-                     double theta, int promote_max, int warm, int64_t *hits, int32_t *slot_id)
+                     double theta, int promote_max, int warm, double adapt, int64_t *hits,
+                     int32_t *slot_id, double *theta_out)
 {
-    double *fr = calloc(n, sizeof(double));
-    int32_t *where = malloc(sizeof(int32_t) * n);
+    double *fr = calloc(n > 0 ? n : 1, sizeof(double));
+    int32_t *where = malloc(sizeof(int32_t) * (n > 0 ? n : 1));
     uint8_t *ref = calloc(C > 0 ? C : 1, 1);
-    uint8_t *cand_mark = calloc(n, 1);
+    uint8_t *cand_mark = calloc(n > 0 ? n : 1, 1);
     for (int64_t i = 0; i < n; ++i) where[i] = -1;
     for (int64_t s = 0; s < C; ++s) slot_id[s] = -1;
     int64_t used = 0, clock = 0;
+    const double theta0 = theta;
+    int have_prev = 0;
+    int64_t prev_miss = 0, prev_acc = 0;
+    double prev_mean = 0.0;
     if (warm) {
         /* repeatedly take the best remaining alive vector by (E_in desc, id asc) */
         uint8_t *taken = calloc(n > 0 ? n : 1, 1);
@@ -1499,6 +1556,7 @@ void orc_wavp_replay(int64_t n, int64_t C, const int32_t *e_in, const uint8_t *a
     int64_t maxlen = 0;
     for (int b = 0; b < nb; ++b) if (off[b + 1] - off[b] > maxlen) maxlen = off[b + 1] - off[b];
     cand_t *cand = malloc(sizeof(cand_t) * (maxlen + 1));
+    int32_t *missed = malloc(sizeof(int32_t) * (maxlen + 1));
 #define FLAM(x) (alive[(x)] ? alpha * fr[(x)] + beta * log(1.0 + (double)e_in[(x)]) : -1.0)
     for (int b = 0; b < nb; ++b) {
         for (int64_t i = 0; i < n; ++i) fr[i] *= 0.5;
@@ -1509,15 +1567,42 @@ void orc_wavp_replay(int64_t n, int64_t C, const int32_t *e_in, const uint8_t *a
             if (where[x] >= 0) { ++h; ref[where[x]] = 1; }
         }
         hits[b] = h;
-        int nc = 0;
+        /* the distinct missed vectors of the batch */
+        int nm = 0;
         for (int64_t t = off[b]; t < off[b + 1]; ++t) {
             int32_t x = trace[t];
             if (where[x] >= 0 || cand_mark[x]) continue;
             cand_mark[x] = 1;
-            double f = FLAM(x);
-            if (f > theta) { cand[nc].f = f; cand[nc].id = x; ++nc; }
+            missed[nm++] = x;
         }
-        for (int64_t t = off[b]; t < off[b + 1]; ++t) cand_mark[trace[t]] = 0;
+        for (int i = 0; i < nm; ++i) cand_mark[missed[i]] = 0;
+        qsort(missed, nm, sizeof(int32_t), cmp_i32);
+        /* theta adaptation from the batch's miss rate and mean prediction */
+        const int64_t acc = off[b + 1] - off[b], miss = acc - h;
+        if (adapt > 1.0 && acc > 0) {
+            double sum = 0.0;
+            int64_t cnt = 0;
+            for (int i = 0; i < nm; ++i)
+                if (alive[missed[i]]) { sum += FLAM(missed[i]); ++cnt; }
+            const double mean = cnt ? sum / (double)cnt : 0.0;
+            if (have_prev) {
+                /* miss / acc against prev_miss / prev_acc, exactly */
+                const int rose = miss * prev_acc > prev_miss * acc;
+                const int fell = miss * prev_acc < prev_miss * acc;
+                if (rose && mean > prev_mean) theta *= adapt;
+                else if (fell && mean < prev_mean) {
+                    theta /= adapt;
+                    if (theta < theta0) theta = theta0;
+                }
+            }
+            have_prev = 1; prev_miss = miss; prev_acc = acc; prev_mean = mean;
+        }
+        if (theta_out) theta_out[b] = theta;
+        int nc = 0;
+        for (int i = 0; i < nm; ++i) {
+            double f = FLAM(missed[i]);
+            if (f > theta) { cand[nc].f = f; cand[nc].id = missed[i]; ++nc; }
+        }
         /* order: F_lambda descending, id ascending */
         for (int i = 1; i < nc; ++i) {
             cand_t c = cand[i];
@@ -1535,24 +1620,32 @@ void orc_wavp_replay(int64_t n, int64_t C, const int32_t *e_in, const uint8_t *a
                 slot_id[used] = x; where[x] = (int32_t)used; ref[used] = 0; ++used;
                 continue;
             }
-            int placed = 0;
-            for (int64_t step = 0; step < 2 * C; ++step) {
-                int64_t s = clock;
-                clock = (clock + 1) % C;
-                if (ref[s]) { ref[s] = 0; continue; }
-                int32_t y = slot_id[s];
-                if (FLAM(y) < cand[i].f) {
-                    where[y] = -1;
+            if (C == 0) break;
+            /* F_min over residents with a clear reference bit */
+            int any = 0;
+            double fmin = 0.0;
+            for (int64_t s = 0; s < C; ++s)
+                if (!ref[s] && (!any || FLAM(slot_id[s]) < fmin)) { fmin = FLAM(slot_id[s]); any = 1; }
+            if (!any) {
+                /* every bit set: one full round clears them all */
+                for (int64_t s = 0; s < C; ++s) ref[s] = 0;
+                for (int64_t s = 0; s < C; ++s)
+                    if (s == 0 || FLAM(slot_id[s]) < fmin) fmin = FLAM(slot_id[s]);
+            }
+            for (;;) {
+                const int64_t s = clock;
+                if (!ref[s] && FLAM(slot_id[s]) == fmin) {
+                    where[slot_id[s]] = -1;
                     slot_id[s] = x; where[x] = (int32_t)s; ref[s] = 0;
-                    placed = 1;
                     break;
                 }
+                if (ref[s]) ref[s] = 0;
+                clock = (clock + 1) % C;
             }
-            if (!placed) break;
         }
     }
 #undef FLAM
-    free(fr); free(where); free(ref); free(cand_mark); free(cand);
+    free(fr); free(where); free(ref); free(cand_mark); free(cand); free(missed);
 }
 
 /* ------------------------------------------------------------------------ */

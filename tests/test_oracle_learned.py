@@ -110,31 +110,69 @@ def test_stop_step_label_is_where_topk_settles(idx):
 
 
 def test_wavp_hand_worked():
+    """Alg. 2 worked by hand: the victim is the first slot in clock order
+    whose bit is clear and whose prediction is the minimum over clear bits;
+    the second case separates this from "the first vector predicted below
+    the candidate" and covers the sweep with every bit set."""
     import json, os
     g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "wavp_example.json")))
-    hits, slots = O.wavp_replay(g["n"], g["C"], g["e_in"], np.ones(g["n"], np.uint8), g["batches"],
-                                g["alpha"], g["beta"], g["theta"], g["promote_max"])
-    assert hits.tolist() == g["expect_hits"]
-    assert slots.tolist() == g["expect_slots"]
+    for c in g["cases"]:
+        hits, slots = O.wavp_replay(c["n"], c["C"], c["e_in"], np.ones(c["n"], np.uint8),
+                                    c["batches"], c["alpha"], c["beta"], c["theta"],
+                                    c["promote_max"])
+        assert hits.tolist() == c["expect_hits"]
+        assert slots.tolist() == c["expect_slots"]
 
 
 def test_wavp_threshold_and_indegree_terms():
     """theta above every prediction keeps the cache empty; with no recency,
-    in-degree alone orders the placements (Eq. 2)."""
+    in-degree alone orders the candidates (Eq. 2): ln 201 and ln 51 fill the
+    two slots, then ln 8 replaces the minimum ln 51 and ln 2 replaces ln 8,
+    since Alg. 2 admits every candidate above theta whatever its rank."""
     hits, slots = O.wavp_replay(4, 2, [0, 0, 0, 0], np.ones(4, np.uint8), [[0, 1, 2, 3]] * 3,
                                 theta=10.0)
     assert (slots == -1).all() and (hits == 0).all()
     e_in = [1, 50, 7, 200]
     hits, slots = O.wavp_replay(4, 2, e_in, np.ones(4, np.uint8), [[0, 1, 2, 3]], alpha=0.0,
                                 beta=1.0, theta=0.0)
-    assert slots.tolist() == [3, 1]
+    assert slots.tolist() == [3, 0]
+    hits, slots = O.wavp_replay(4, 2, e_in, np.ones(4, np.uint8), [[0, 1, 2, 3]], alpha=0.0,
+                                beta=1.0, theta=2.1)
+    assert slots.tolist() == [3, 1]                      # ln 8 and ln 2 stay below theta
+
+
+def test_wavp_theta_adaptation_hand_worked():
+    """Sec. 4.4: theta rises when the miss rate and the mean prediction of
+    the missed vectors both rise, falls back (never below its start) when
+    both fall, and holds otherwise.  alpha = 1, beta = 0, one slot:
+      batch 0: miss rate 1/1, mean F 1 (vector 0): no previous batch, 0.5;
+      batch 1: rate 3/4 fell, mean F(1) = 3 rose: 0.5 held;
+      batch 2: rate 8/8 rose, mean of F(2) = F(3) = 4 rose: theta 1.0;
+      batch 3: rate 1/1 equal: 1.0 held, and vector 4 (F = 1) is not above it,
+      so 3 stays; with the adaptation off, 4 replaces 3."""
+    b = [[0], [0, 1, 1, 1], [2, 2, 2, 2, 3, 3, 3, 3], [4]]
+    hits, slots, th = O.wavp_replay(5, 1, [0] * 5, np.ones(5, np.uint8), b, alpha=1.0, beta=0.0,
+                                    theta=0.5, adapt=2.0, with_theta=True)
+    assert th.tolist() == [0.5, 0.5, 1.0, 1.0]
+    assert hits.tolist() == [0, 1, 0, 0] and slots.tolist() == [3]
+    hits, slots, th = O.wavp_replay(5, 1, [0] * 5, np.ones(5, np.uint8), b, alpha=1.0, beta=0.0,
+                                    theta=0.5, with_theta=True)
+    assert th.tolist() == [0.5] * 4 and slots.tolist() == [4]
+    # both fall: batch 3 of [3, 0] halves theta back to its start
+    b2 = [[0], [0, 1, 1, 1], [2, 2, 2, 2, 3, 3, 3, 3], [3, 0]]
+    hits, slots, th = O.wavp_replay(4, 1, [0] * 4, np.ones(4, np.uint8), b2, alpha=1.0, beta=0.0,
+                                    theta=0.5, adapt=2.0, with_theta=True)
+    assert th.tolist() == [0.5, 0.5, 1.0, 0.5] and hits.tolist() == [0, 1, 0, 1]
+    assert slots.tolist() == [0]
 
 
 def test_wavp_warm_start_hand_worked():
     """Cold-start placement: alive vectors by in-degree (ties by id) fill the
     slots in order; then one batch worked by hand with theta = 0.5:
-    F(3) = 0.6*1 + 0.4*ln 2 = 0.877 beats F(0) = 0.4*ln 5 = 0.644 but not
-    F(2) = 0.4*ln 10 = 0.921, and slot 0 (vector 1, just hit) is skipped once."""
+    F(3) = 0.6*1 + 0.4*ln 2 = 0.877 is above theta; among the clear bits
+    (slot 1: F(2) = 0.4*ln 10 = 0.921, slot 2: F(0) = 0.4*ln 5 = 0.644) the
+    minimum is F(0); the hand clears slot 0's bit (vector 1, just hit), passes
+    slot 1 and replaces 0.  With theta = 1.0 vector 3 stays on the host."""
     e_in = [4, 9, 9, 1, 7]
     alive = np.array([1, 1, 1, 1, 0], np.uint8)        # vector 4 is deleted
     hits, slots = O.wavp_replay(5, 3, e_in, alive, [], warm=True)
@@ -178,3 +216,27 @@ def test_classic_policies_hand_worked():
     h, s = O.policy_replay(O.POLICY_LRU, 7, 2, [3, 9, 1, 0, 0, 0, 0], ones(7), tr, promote_max=0,
                            warm=True)
     assert s.tolist() == [1, 0] and h.tolist() == [0, 0]
+
+
+def test_model_gating_hand_worked():
+    """The learned form's gating, worked by hand: the first largest logit
+    picks the cluster; its softmax probability against the threshold picks
+    listed or plain search; the cap is ceil(scale * exp(z_stop)) with z_stop
+    taken at most 20, at least min_iters, and held at 2^30."""
+    z = np.array([
+        [2.0, 0.0, 0.0, 2.0],      # p = 1/(1 + 2e^-2) = 0.787 >= 0.5; cap ceil(1.5 e^2 = 11.08) = 12
+        [0.0, 0.0, 0.0, 3.0],      # p = 1/3 < 0.5: plain search
+        [1.0, 3.0, 3.0, 0.0],      # tie: cluster 1; p = 1/(2 + e^-2) = 0.468 < 0.5
+        [0.0, -50.0, -50.0, 0.0],  # p ~ 1; cap ceil(1.5) = 2, raised to min_iters 8
+        [5.0, 0.0, 0.0, 30.0],     # z_stop taken at 20: ceil(1.5 e^20) = 727,747,794
+    ])
+    qe, qm = O.model_decide(z, 0.5, 1.5, 8)
+    assert qe.tolist() == [0, -1, -1, 0, 0]
+    assert qm.tolist() == [12, 0, 0, 8, int(np.ceil(1.5 * np.exp(20.0)))]
+    assert qm[4] == 727747794
+    qe, qm = O.model_decide(z[2:3], 0.4, 1.5, 8)           # now confident: the tie's first index
+    assert qe.tolist() == [1] and qm.tolist() == [8]
+    qe, qm = O.model_decide(z[4:5], 0.0, 1e6, 8)            # 1e6 e^20 = 4.85e14: held at 2^30
+    assert qm.tolist() == [1 << 30]
+    qe, qm = O.model_decide(np.array([[0.0, 0.0, 0.0]]), 0.5, 1.0, 1)   # p = conf exactly
+    assert qe.tolist() == [0]
