@@ -132,7 +132,13 @@ int svf_destroy(svf_index *ix);
  *                   A deleted vector leaves the cache at once; inserted vectors take
  *                   free slots in id order.  While the serving loop runs the cache
  *                   does not change.
- *   cache_theta     placement threshold on F_lambda (>= 0; 1.0)
+ *   cache_theta     placement threshold on F_lambda (>= 0; 1.0); also the floor of the
+ *                   adaptation below.  svf_cache_calibrate sets it from measured costs
+ *   cache_theta_adapt Sec. 4.4's adaptation of theta, by this factor, 0 = off (0 or (1, 16];
+ *                   0): after a batch's accesses are counted, its miss rate and the mean
+ *                   F_lambda of its distinct missed alive vectors are compared with the last
+ *                   batch's; both higher multiplies theta by the factor, both lower divides
+ *                   it (not below cache_theta); the value in force is readable as cache_theta
  *   cache_alpha_ratio alpha / (alpha + beta) of F_lambda, alpha + beta = 1 ([0,1]; 0.6)
  *   cache_promote_max placements per query batch (>= 0; 2048)
  *   cache_trace_cap expansions per query recorded for placement (16..8192; 512)
@@ -321,6 +327,26 @@ int svf_stats_get(const svf_index *ix, svf_stats *out);
  * NULL.  cap_slots must be >= n_slots. */
 int svf_export_graph(const svf_index *ix, int32_t *rows, float *edge_d, uint8_t *alive,
                      int64_t cap_slots);
+
+/* The tiered store's cache (Sec. 4.2's mapping table, seen from the slots):
+ * slot_ids receives, for each of the cache_slots slots, the id it holds or
+ * -1 (host memory, cap >= cache_slots entries); *clock (may be NULL) the
+ * position of Alg. 2's clock hand.  No tiered store: zero slots. */
+int svf_cache_slots(const svf_index *ix, int32_t *slot_ids, int64_t cap, int64_t *clock);
+
+/* Sec. 4.3's threshold from measured costs: theta = T_transfer / (T_miss -
+ * T_hit), the access count from which promoting a vector pays for itself
+ * (Eq. 1 with gain = 0).  Measured on this GPU with 65,536 random rows per
+ * probe (median of five runs): T_hit, the per-row time of a distance over
+ * rows read from the HBM cache; T_miss, the same over rows of the host store
+ * read across the host link (the miss path as built, in the place of the
+ * paper's CPU-side distance); T_transfer, the per-row time of copying 2048
+ * host rows into HBM (one promotion batch).  Sets cache_theta (and the floor
+ * of its adaptation) to theta; out (4 doubles, may be NULL) receives T_hit,
+ * T_miss, T_transfer in ns per row, and theta.  Needs a tiered store that
+ * holds at least one vector; SVF_E_INTERNAL if host reads measure no slower
+ * than cached ones. */
+int svf_cache_calibrate(svf_index *ix, double *out);
 
 /* Replace the state of an EMPTY index by n vectors, their rows, edge
  * distances and alive flags (host memory).  Used to start two

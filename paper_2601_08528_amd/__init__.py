@@ -28,7 +28,8 @@ EXPORTED = [
     "svf_mlp_num_params", "svf_mlp_set_params", "svf_mlp_get_params", "svf_mlp_forward",
     "svf_mlp_loss_grad", "svf_mlp_train", "svf_mlp_last_error",
     "svf_serve_start", "svf_serve_stop", "svf_submit_search", "svf_submit_insert",
-    "svf_submit_delete", "svf_wait", "svf_save", "svf_load",
+    "svf_submit_delete", "svf_wait", "svf_save", "svf_load", "svf_cache_slots",
+    "svf_cache_calibrate",
 ]
 
 
@@ -89,6 +90,8 @@ def lib():
         L.svf_stats_get.argtypes = [vp, C.POINTER(Stats)]
         L.svf_export_graph.argtypes = [vp, vp, vp, vp, i64]
         L.svf_import_graph.argtypes = [vp, vp, i64, vp, vp, vp]
+        L.svf_cache_slots.argtypes = [vp, vp, i64, C.POINTER(i64)]
+        L.svf_cache_calibrate.argtypes = [vp, vp]
         L.svf_save.argtypes = [vp, C.c_char_p]
         L.svf_load.argtypes = [C.c_char_p, C.POINTER(vp)]
         L.svf_search_listed.argtypes = [vp, vp, i64, i32, i32, vp, i32, vp, vp, vp]
@@ -265,6 +268,21 @@ class Index:
         alive = np.empty(n, np.uint8)
         _check(lib().svf_export_graph(self.h, _p(rows), _p(ed), _p(alive), n))
         return rows, ed, alive
+
+    def cache_slots(self):
+        """(slot -> id table of the tiered store's cache, -1 empty; clock hand)."""
+        c = int(self.stats()["cache_slots"])
+        out = np.empty(max(c, 1), np.int32)
+        clock = C.c_int64()
+        _check(lib().svf_cache_slots(self.h, _p(out), c, C.byref(clock)))
+        return out[:c], clock.value
+
+    def cache_calibrate(self) -> dict:
+        """Measure the hit, miss and transfer costs and set cache_theta from
+        them (``svf_cache_calibrate``)."""
+        out = np.empty(4, np.float64)
+        _check(lib().svf_cache_calibrate(self.h, _p(out)))
+        return dict(t_hit_ns=out[0], t_miss_ns=out[1], t_transfer_ns=out[2], theta=out[3])
 
     def save(self, path: str):
         """Checkpoint to a file (``svf_save``)."""

@@ -933,10 +933,12 @@ int tier_admit(svf_index* ix, int64_t id0, int64_t n) {
 // order, each query's expanded vertices in order); accesses to cached vectors
 // are hits and set their slot's reference bit; the distinct missed vectors
 // with F_lambda = alpha F_recent + beta log(1 + E_in) above theta, by
-// (F_lambda desc, id asc), at most promote_max of them, are placed into a free
-// slot or by a clock sweep (at most 2C steps) that clears set reference bits
-// and evicts the first clear slot holding a lower F_lambda (a deleted vector
-// counts -1); a candidate without a victim ends the batch's placements.
+// (F_lambda desc, id asc), at most promote_max of them, are placed one after
+// another: into a free slot, else over Alg. 2's clock (WavpSweep): F_min over
+// the residents with a clear reference bit, the hand clearing set bits up to
+// the first clear slot holding F_min, which is replaced, the hand staying on
+// it.  With cache_theta_adapt > 1, theta follows the batch's miss rate and
+// the mean F_lambda of its missed vectors (Sec. 4.4) before the placements.
 int tier_refresh_indegree(svf_index* ix, hipStream_t st) {
   svf::TierState& T = ix->tier;
   const bool recount = !T.e_in_valid;
@@ -1186,17 +1188,21 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
   // separate threads and their candidates are joined in order.
   const int nthr = (int)std::max<int64_t>(1, std::min<int64_t>({16, (total + 65535) / 65536,
                                                                  (int64_t)std::thread::hardware_concurrency()}));
+  // Candidates are taken against theta after the adaptation, which needs the
+  // whole batch: each thread keeps the prediction of every missed alive
+  // vertex of its range, in id order.
   std::vector<std::vector<std::pair<double, int32_t>>> tcand(nthr);
   std::vector<std::vector<int32_t>> tmissed(nthr);
-  std::vector<int64_t> thits(nthr, 0);
+  std::vector<int64_t> thits(nthr, 0), tacc(nthr, 0);
   auto work = [&](int t) {
     const int64_t lo = total * t / nthr, hi = total * (t + 1) / nthr;
-    int64_t h = 0;
+    int64_t h = 0, a = 0;
     for (int64_t i = lo; i < hi; ++i) {
       const int32_t x = tid[i];
       double v = fr_now(T, x);
       const int32_t c = tcnt[i];
       for (int32_t k = 0; k < c; ++k) v += 1.0;
+      a += c;
       T.fr[x] = v;
       T.fr_stamp[x] = T.batch;
       T.freq[x] += c;
@@ -1205,15 +1211,12 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
         h += c;
         T.ref[T.where[x]] = 1;
       } else if (alive(x)) {
-        if (T.policy == 0) {
-          const double f = T.alpha * v + lg(x);
-          if (f > T.theta) tcand[t].emplace_back(f, x);
-        } else {
-          tmissed[t].push_back(x);
-        }
+        if (T.policy == 0) tcand[t].emplace_back(T.alpha * v + lg(x), x);
+        else tmissed[t].push_back(x);
       }
     }
     thits[t] = h;
+    tacc[t] = a;
   };
   if (nthr == 1) {
     work(0);
@@ -1223,16 +1226,40 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
     work(0);
     for (auto& th : pool) th.join();
   }
-  int64_t hits = 0;
+  int64_t hits = 0, acc = 0;
   std::vector<std::pair<double, int32_t>> cand;
   std::vector<int32_t> missed;
   for (int t = 0; t < nthr; ++t) {
     hits += thits[t];
-    cand.insert(cand.end(), tcand[t].begin(), tcand[t].end());
+    acc += tacc[t];
     missed.insert(missed.end(), tmissed[t].begin(), tmissed[t].end());
   }
   T.last_trace_hits = hits;
   if (T.policy != 0) return tier_place_classic(ix, missed, st);
+  if (T.adapt > 1.0 && acc > 0) {
+    // Sec. 4.4: theta rises when the miss rate and the mean prediction of the
+    // missed vectors both rise, and falls back (not below where it started)
+    // when both fall.  The mean is summed in id order.
+    double sum = 0.0;
+    int64_t cnt = 0;
+    for (int t = 0; t < nthr; ++t)
+      for (const auto& c : tcand[t]) { sum += c.first; ++cnt; }
+    const double mean = cnt ? sum / (double)cnt : 0.0;
+    const int64_t miss = acc - hits;
+    if (T.have_prev) {
+      const bool rose = (__int128)miss * T.prev_acc > (__int128)T.prev_miss * acc;
+      const bool fell = (__int128)miss * T.prev_acc < (__int128)T.prev_miss * acc;
+      if (rose && mean > T.prev_mean) T.theta *= T.adapt;
+      else if (fell && mean < T.prev_mean) T.theta = std::max(T.theta0, T.theta / T.adapt);
+    }
+    T.have_prev = true;
+    T.prev_miss = miss;
+    T.prev_acc = acc;
+    T.prev_mean = mean;
+  }
+  for (int t = 0; t < nthr; ++t)
+    for (const auto& c : tcand[t])
+      if (c.first > T.theta) cand.push_back(c);
   auto better = [](const std::pair<double, int32_t>& a, const std::pair<double, int32_t>& b) {
     return a.first > b.first || (a.first == b.first && a.second < b.second);
   };
@@ -1241,8 +1268,8 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
     cand.resize(T.promote_max);
   }
   std::sort(cand.begin(), cand.end(), better);
-  auto flam = [&](int32_t y) -> double { return alive(y) ? T.alpha * fr_now(T, y) + lg(y) : -1.0; };
   std::vector<int32_t> place;
+  svf::WavpSweep& sw = T.sweep;
   for (const auto& c : cand) {
     const int32_t x = c.second;
     const int64_t slot = T.take_slot();
@@ -1253,28 +1280,24 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
       place.insert(place.end(), {(int32_t)slot, x, -1});
       continue;
     }
-    bool placed = false;
-    for (int64_t step = 0; step < 2 * T.C; ++step) {
-      const int64_t s_ = T.clock;
-      T.clock = (T.clock + 1) % T.C;
-      if (T.ref[s_]) {
-        T.ref[s_] = 0;
-        continue;
-      }
-      const int32_t y = T.slot_id[s_];
-      if (flam(y) < c.first) {
-        T.where[y] = -1;
-        T.slot_id[s_] = x;
-        T.where[x] = (int32_t)s_;
-        T.ref[s_] = 0;
-        place.insert(place.end(), {(int32_t)s_, x, y});
-        ++T.evictions;
-        placed = true;
-        break;
-      }
+    if (T.C == 0) break;
+    if (!sw.active()) {     // the cache is full and stays full for the rest of the batch
+      const int nt = (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()));
+      sw.begin(T.C, [&](int64_t s_) {
+        const int32_t y = T.slot_id[s_];
+        return alive(y) ? T.alpha * fr_now(T, y) + lg(y) : -1.0;
+      }, T.ref.data(), nt);
     }
-    if (!placed) break;
+    const int64_t s_ = sw.evict(T.clock, T.ref.data());
+    const int32_t y = T.slot_id[s_];
+    T.where[y] = -1;
+    T.slot_id[s_] = x;
+    T.where[x] = (int32_t)s_;
+    sw.place(s_, c.first);
+    place.insert(place.end(), {(int32_t)s_, x, y});
+    ++T.evictions;
   }
+  sw.end();
   T.promotions += place.size() / 3;
   return tier_apply(ix, place, st);
 }
@@ -1495,6 +1518,12 @@ int svf_set_option(svf_index* ix, const char* key, double v) {
   } else if (k == "cache_theta") {
     if (v < 0) return fail(SVF_E_INVAL, "cache_theta >= 0");
     ix->tier.theta = v;
+    ix->tier.theta0 = v;
+    ix->tier.have_prev = false;
+  } else if (k == "cache_theta_adapt") {
+    if (v != 0 && !(v > 1 && v <= 16)) return fail(SVF_E_INVAL, "cache_theta_adapt 0 or in (1, 16]");
+    ix->tier.adapt = v;
+    ix->tier.have_prev = false;
   } else if (k == "cache_alpha_ratio") {
     if (v < 0 || v > 1) return fail(SVF_E_INVAL, "cache_alpha_ratio in [0, 1]");
     ix->tier.alpha = v;
@@ -1568,6 +1597,7 @@ int svf_get_option(const svf_index* ix, const char* key, double* out) {
   else if (k == "use_model") *out = o.use_model;
   else if (k == "cache_bytes") *out = (double)(ix->tier.C * ix->stride * 4);
   else if (k == "cache_theta") *out = ix->tier.theta;
+  else if (k == "cache_theta_adapt") *out = ix->tier.adapt;
   else if (k == "cache_alpha_ratio") *out = ix->tier.alpha;
   else if (k == "cache_promote_max") *out = ix->tier.promote_max;
   else if (k == "cache_trace_cap") *out = ix->tier.trace_cap;
@@ -1893,6 +1923,95 @@ int svf_export_graph(const svf_index* cix, int32_t* rows, float* edge_d, uint8_t
     std::vector<uint32_t> bits((n + 31) / 32);
     CK(hipMemcpy(bits.data(), ix->alive, bits.size() * 4, hipMemcpyDeviceToHost));
     for (int64_t i = 0; i < n; ++i) alive[i] = (bits[i >> 5] >> (i & 31)) & 1u;
+  }
+  return SVF_OK;
+}
+
+int svf_cache_slots(const svf_index* cix, int32_t* slot_ids, int64_t cap, int64_t* clock) {
+  if (!cix || (!slot_ids && cap > 0)) return fail(SVF_E_INVAL, "null argument");
+  svf_index* ix = const_cast<svf_index*>(cix);
+  std::lock_guard<std::mutex> g(ix->mu);
+  const svf::TierState& T = ix->tier;
+  if (cap < T.C) return fail(SVF_E_INVAL, "cap < cache slots");
+  for (int64_t s = 0; s < T.C; ++s) slot_ids[s] = T.slot_id[s];
+  if (clock) *clock = T.clock;
+  return SVF_OK;
+}
+
+int svf_cache_calibrate(svf_index* ix, double* out) {
+  if (!ix) return fail(SVF_E_INVAL, "null index");
+  if (ix->server) return fail(SVF_E_BUSY, "index is serving: stop serving first");
+  std::lock_guard<std::mutex> g(ix->mu);
+  svf::TierState& T = ix->tier;
+  if (!T.on || ix->n_slots == 0) return fail(SVF_E_INVAL, "no tiered store, or an empty index");
+  std::vector<int32_t> occ;
+  for (int64_t s = 0; s < T.C; ++s)
+    if (T.slot_id[s] >= 0) occ.push_back((int32_t)s);
+  if (occ.empty()) return fail(SVF_E_INVAL, "the cache holds no vector");
+  const int ns = 65536, nx = 2048;
+  std::vector<int32_t> hit(ns), miss(ns), xfer(nx);
+  uint64_t z = 0x5eedULL;
+  auto next = [&]() {                        // SplitMix64 (Steele, Lea and Flood, 2014)
+    uint64_t r = (z += 0x9E3779B97F4A7C15ULL);
+    r = (r ^ (r >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    r = (r ^ (r >> 27)) * 0x94D049BB133111EBULL;
+    return r ^ (r >> 31);
+  };
+  for (int i = 0; i < ns; ++i) hit[i] = occ[next() % occ.size()];
+  for (int i = 0; i < ns; ++i) miss[i] = (int32_t)(next() % (uint64_t)ix->n_slots);
+  for (int i = 0; i < nx; ++i) xfer[i] = (int32_t)(next() % (uint64_t)ix->n_slots);
+  svf::DevBuf ibuf, qbuf, obuf, dbuf;
+  CK(ibuf.ensure((size_t)(2 * ns + nx) * 4));
+  CK(qbuf.ensure((size_t)ix->stride * 4));
+  CK(obuf.ensure((size_t)ns * 4));
+  CK(dbuf.ensure((size_t)nx * ix->stride * 4));
+  int32_t* d_hit = ibuf.as<int32_t>();
+  int32_t* d_miss = d_hit + ns;
+  int32_t* d_xfer = d_miss + ns;
+  hipStream_t st = ix->stream;
+  CK(hipMemcpyAsync(d_hit, hit.data(), ns * 4, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(d_miss, miss.data(), ns * 4, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(d_xfer, xfer.data(), nx * 4, hipMemcpyHostToDevice, st));
+  CK(svf::launch_fill_u32(qbuf.as<uint32_t>(), ix->stride, 0u, st));
+  // each probe: one untimed run, then the median of five timed ones
+  auto timed = [&](auto&& launch, double* ms) -> int {
+    CK(launch());
+    std::vector<double> t;
+    for (int r = 0; r < 5; ++r) {
+      CK(hipEventRecord(ix->ev0, st));
+      CK(launch());
+      CK(hipEventRecord(ix->ev1, st));
+      CK(hipEventSynchronize(ix->ev1));
+      float m = 0.f;
+      CK(hipEventElapsedTime(&m, ix->ev0, ix->ev1));
+      t.push_back(m);
+    }
+    std::sort(t.begin(), t.end());
+    *ms = t[2];
+    return SVF_OK;
+  };
+  double ms_hit = 0, ms_miss = 0, ms_x = 0;
+  int rc;
+  if ((rc = timed([&] { return svf::launch_probe_gather(T.cache, d_hit, ns, ix->stride, ix->dim,
+                                                        qbuf.as<float>(), obuf.as<float>(), st); },
+                  &ms_hit)) ||
+      (rc = timed([&] { return svf::launch_probe_gather(ix->vec32, d_miss, ns, ix->stride, ix->dim,
+                                                        qbuf.as<float>(), obuf.as<float>(), st); },
+                  &ms_miss)) ||
+      (rc = timed([&] { return svf::launch_probe_copy(ix->vec32, d_xfer, nx, ix->stride,
+                                                      dbuf.as<float>(), st); },
+                  &ms_x)))
+    return rc;
+  const double t_hit = ms_hit * 1e6 / ns, t_miss = ms_miss * 1e6 / ns, t_x = ms_x * 1e6 / nx;
+  if (!(t_miss > t_hit)) return fail(SVF_E_INTERNAL, "a host read measured no slower than a cached one");
+  const double theta = t_x / (t_miss - t_hit);
+  T.theta = T.theta0 = theta;
+  T.have_prev = false;
+  if (out) {
+    out[0] = t_hit;
+    out[1] = t_miss;
+    out[2] = t_x;
+    out[3] = theta;
   }
   return SVF_OK;
 }

@@ -11,6 +11,7 @@
 
 #include "../../include/svf.h"
 #include "mlp.hpp"
+#include "wavp.hpp"
 
 namespace svf {
 
@@ -135,6 +136,12 @@ struct TierState {
   std::vector<int64_t> freq;       // LFU: accesses so far per id
   std::vector<int64_t> last;       // LRU: last access, (batch << 40) + position, -1 never
   double alpha = 0.6, beta = 0.4, theta = 1.0;
+  // theta adaptation (Sec. 4.4): factor (0 = off), the starting theta, and
+  // the miss rate and mean missed prediction of the last batch with accesses
+  double adapt = 0.0, theta0 = 1.0, prev_mean = 0.0;
+  bool have_prev = false;
+  int64_t prev_miss = 0, prev_acc = 0;
+  WavpSweep sweep;                 // Alg. 2's victim choice within a batch
   int promote_max = 2048, trace_cap = 512;
   uint64_t gather_hits = 0, gather_misses = 0, promotions = 0, evictions = 0;
   int64_t last_trace_hits = 0, last_placed = 0;

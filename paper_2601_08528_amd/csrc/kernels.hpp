@@ -67,6 +67,10 @@ hipError_t launch_indegree(const int32_t* graph, const uint32_t* alive, int64_t 
 hipError_t launch_place(const int32_t* place, int np, const float* store, float* cache,
                         int64_t stride, int32_t* map, hipStream_t st);
 int64_t touched_blocks(int64_t words);
+hipError_t launch_probe_gather(const float* rows, const int32_t* idx, int n, int64_t stride,
+                               int dim, const float* q, float* out, hipStream_t st);
+hipError_t launch_probe_copy(const float* store, const int32_t* idx, int n, int64_t stride,
+                             float* dst, hipStream_t st);
 hipError_t launch_touched_count(const uint32_t* touched, int64_t words, int32_t* block_tot,
                                 hipStream_t st);
 hipError_t launch_touched_list(const uint32_t* touched, int64_t words, const int32_t* block_off,

@@ -60,6 +60,52 @@ hipError_t launch_place(const int32_t* place, int np, const float* store, float*
   return hipGetLastError();
 }
 
+// Cost probe for the placement threshold (Sec. 4.3): one wave per listed
+// row computes the squared L2 distance between that row of `rows` and q, as
+// a search gather does; `rows` is the HBM cache (a hit) or the host-resident
+// store read over the host link (a miss).
+__global__ __launch_bounds__(256) void probe_gather_kernel(const float* __restrict__ rows,
+                                                           const int32_t* __restrict__ idx, int n,
+                                                           int64_t stride, int dim,
+                                                           const float* __restrict__ q,
+                                                           float* __restrict__ out) {
+  const int w = (int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
+  if (w >= n) return;
+  const float* r = rows + (int64_t)idx[w] * stride;
+  float acc = 0.f;
+  for (int e = lane_id(); e < dim; e += kWave) {
+    const float d = r[e] - q[e];
+    acc += d * d;
+  }
+  for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if (lane_id() == 0) out[w] = acc;
+}
+hipError_t launch_probe_gather(const float* rows, const int32_t* idx, int n, int64_t stride,
+                               int dim, const float* q, float* out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(probe_gather_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, rows, idx,
+                     n, stride, dim, q, out);
+  return hipGetLastError();
+}
+
+// Cost probe of a promotion: listed rows of the host-resident store copied
+// into a device buffer, one workgroup per row, as the placement kernel does.
+__global__ void probe_copy_kernel(const float* __restrict__ store, const int32_t* __restrict__ idx,
+                                  int n, int64_t stride, float* __restrict__ dst) {
+  for (int64_t p = blockIdx.x; p < n; p += gridDim.x) {
+    const float* src = store + (int64_t)idx[p] * stride;
+    float* d = dst + p * stride;
+    for (int64_t e = threadIdx.x; e < stride; e += blockDim.x) d[e] = src[e];
+  }
+}
+hipError_t launch_probe_copy(const float* store, const int32_t* idx, int n, int64_t stride,
+                             float* dst, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(probe_copy_kernel, dim3((unsigned)std::min<int64_t>(n, kMaxBlocks)), dim3(128), 0,
+                     st, store, idx, n, stride, dst);
+  return hipGetLastError();
+}
+
 // Accesses of one batch: per-vertex counts, a bitmap of the vertices touched
 // and (when lastpos is given) each vertex's last position in the traces
 // taken in order (query, step), from nq traces of at most cap entries.

@@ -43,26 +43,37 @@ def test_results_independent_of_cache(state):
     assert st["cache_promotions"] > 0
 
 
-@pytest.mark.parametrize("theta,cap_rows,promote", [(1.0, 300, 2048), (0.5, 120, 64)])
-def test_placement_matches_oracle_replay(state, theta, cap_rows, promote):
+@pytest.mark.parametrize("theta,cap_rows,promote,adapt", [(1.0, 300, 2048, 0.0), (0.5, 120, 64, 0.0),
+                                                          (0.5, 200, 512, 2.0)])
+def test_placement_matches_oracle_replay(state, theta, cap_rows, promote, adapt):
+    """Hits per batch, the theta in force for each batch (with the Sec. 4.4
+    adaptation) and the final slot table (every victim Alg. 2 chose) equal
+    the oracle's replay over the oracle's own traces."""
     oix, base, q = state
     trace_cap = 64
     g = tiered_from_oracle(oix, base, cap_rows, seed=6, cache_theta=theta,
-                           cache_promote_max=promote, cache_trace_cap=trace_cap)
+                           cache_promote_max=promote, cache_trace_cap=trace_cap,
+                           cache_theta_adapt=adapt)
     rows, _, alive = oix.export()
     e_in = np.zeros(len(alive), np.int64)
     src = rows[alive.astype(bool)]
     np.add.at(e_in, src[src >= 0], 1)
-    batches, got = [], []
+    batches, got, th = [], [], []
     for b in range(5):
         qb = q[b * 80:(b + 1) * 80]
         g.search(qb, 10, 40)
         got.append(g.stats()["cache_last_trace_hits"])
+        th.append(g.get_option("cache_theta"))
         tr, cnt = oix.search_expansions(qb, 40, cap=trace_cap)
         batches.append(np.concatenate([tr[i, :min(cnt[i], trace_cap)] for i in range(len(qb))]))
-    hits, slots = O.wavp_replay(len(alive), cap_rows, e_in, alive, batches, 0.6, 0.4, theta, promote)
+    hits, slots, oth = O.wavp_replay(len(alive), cap_rows, e_in, alive, batches, 0.6, 0.4, theta,
+                                     promote, adapt=adapt, with_theta=True)
     assert got == hits.tolist()
+    assert th == oth.tolist()
+    gslots, _ = g.cache_slots()
+    np.testing.assert_array_equal(gslots, slots)
     assert sum(got) > 0
+    assert g.stats()["cache_evictions"] > 0
 
 
 def test_updates_on_tiered_store_bit_exact():
@@ -161,9 +172,10 @@ def test_tiering_a_filled_index_warm_start_matches_replay():
         got.append(g.stats()["cache_last_trace_hits"])
         tr, cnt = oix.search_expansions(qb, 40, cap=trace_cap)
         batches.append(np.concatenate([tr[i, :min(cnt[i], trace_cap)] for i in range(len(qb))]))
-    hits, _ = O.wavp_replay(len(alive), cap_rows, e_in, alive, batches, 0.6, 0.4, theta, 2048,
-                            warm=True)
+    hits, slots = O.wavp_replay(len(alive), cap_rows, e_in, alive, batches, 0.6, 0.4, theta, 2048,
+                                warm=True)
     assert got == hits.tolist()
+    np.testing.assert_array_equal(g.cache_slots()[0], slots)
     assert got[0] > 0
 
 
@@ -198,8 +210,9 @@ def test_reduced_precision_traversal_with_tiered_rescoring(prec):
         got.append(s1["cache_last_trace_hits"])
         tr, cnt = oix.search_expansions(qb, L, cap=trace_cap)
         batches.append(np.concatenate([tr[i, :min(cnt[i], trace_cap)] for i in range(len(qb))]))
-    hits, _ = O.wavp_replay(len(alive), cap_rows, e_in, alive, batches, 0.6, 0.4, 1.0, 2048)
+    hits, slots = O.wavp_replay(len(alive), cap_rows, e_in, alive, batches, 0.6, 0.4, 1.0, 2048)
     assert got == hits.tolist()
+    np.testing.assert_array_equal(g.cache_slots()[0], slots)
     g.set_option("rerank", 0)
     s0 = g.stats()
     g.search(q[:50], 10, L)
@@ -239,9 +252,10 @@ def test_classic_policies_match_oracle_replay(state, policy, warm):
         got.append(g.stats()["cache_last_trace_hits"])
         tr, cnt = oix.search_expansions(qb, 40, cap=trace_cap)
         batches.append(np.concatenate([tr[i, :min(cnt[i], trace_cap)] for i in range(len(qb))]))
-    hits, _ = O.policy_replay(policy, len(alive), cap_rows, e_in, alive, batches, promote_max=100,
-                              warm=warm)
+    hits, slots = O.policy_replay(policy, len(alive), cap_rows, e_in, alive, batches,
+                                  promote_max=100, warm=warm)
     assert got == hits.tolist()
+    np.testing.assert_array_equal(g.cache_slots()[0], slots)
     assert sum(got) > 0
     assert g.stats()["cache_evictions"] > 0
 
@@ -268,3 +282,19 @@ def test_kept_in_degrees_match_a_recount_under_updates():
     g.insert(base[3200:])
     g.search(q[150:], 10, 32)
     assert g.get_option("cache_indegree_verify") == 1
+
+
+def test_theta_from_measured_costs(state):
+    """Sec. 4.3: theta = T_transfer / (T_miss - T_hit) from probes on this
+    GPU; the threshold is set from it and host reads cost more than cached
+    ones."""
+    oix, base, q = state
+    g = tiered_from_oracle(oix, base, 1000, seed=6)
+    g.search(q[:100], 10, 32)
+    c = g.cache_calibrate()
+    assert 0 < c["t_hit_ns"] < c["t_miss_ns"]
+    assert c["t_transfer_ns"] > 0
+    assert c["theta"] == pytest.approx(c["t_transfer_ns"] / (c["t_miss_ns"] - c["t_hit_ns"]))
+    assert g.get_option("cache_theta") == c["theta"]
+    gi, _ = g.search(q[:100], 10, 32)                          # still a working index
+    np.testing.assert_array_equal(gi, oix.search(q[:100], 10, 32)[0])
