@@ -32,6 +32,7 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "queries/sec at recall@10\u22650.95 (batch 10k), plain vs chosen form; p50/p99 mixed"
 DIM, DEGREE, K = 128, 64, 10
 BEAMS = [32, 48, 64, 96, 128, 192, 256, 384, 512]
 
@@ -159,20 +160,24 @@ def sweep(torch, ix, q_t, base_t, kth, bufs, beams, target=0.95, refine=8):
     return chosen, rows
 
 
-def serving_bench(svf, datagen, n_build=5_000_000, rounds=60, rates=(60.0, 240.0, 480.0),
-                  consolidation_rate=240.0, consolidate_frac=0.004):
+def serving_bench(torch, svf, datagen, n_build=5_000_000, rounds=(167, 167, 166),
+                  rates=(60.0, 240.0, 480.0), consolidation_rate=240.0, consolidation_rounds=60,
+                  consolidate_frac=0.004, recall_sample=1000):
     """Streaming mix on the serving loop: an n_build-vector unit-norm 96-d
     mixture (1024 components, inner product, degree 48, BF16 traversal + FP32
-    re-score), then, at each offered load in turn, `rounds` rounds of [one
+    re-score), then, at each offered load in turn, rounds[i] rounds of [one
     10k-vector insert, one 1k-id delete of uniformly chosen live ids, four
     query batches of log-uniform size 1..10k with Zipf(1.1)-skewed
-    components] as open-loop Poisson arrivals.  The index keeps changing
-    from one load to the next.  Then two more phases at one load with a
-    consolidation threshold low enough that consolidations happen inside the
-    phase: synchronous, then in the background on a snapshot."""
-    n_extra = (len(rates) + 2) * rounds * 10_000
+    components] as open-loop Poisson arrivals; 500 rounds take the index from
+    5M to 10M vectors.  The index keeps changing from one load to the next.
+    Then the recall of a query sample on the final index, and two more phases
+    at one load with a consolidation threshold low enough that
+    consolidations happen inside the phase: synchronous, then in the
+    background on a snapshot."""
+    n_extra = (sum(rounds) + 2 * consolidation_rounds) * 10_000
     base, queries = datagen.workload_stream_ip(n_build + n_extra, 20_000)
     ix = svf.Index(96, 48, svf.METRIC_IP, seed=0, precision=svf.PREC_BF16)
+    ix.set_option("capacity", n_build + n_extra)
     t0 = time.perf_counter()
     ix.build(base[:n_build])
     build_s = time.perf_counter() - t0
@@ -181,15 +186,21 @@ def serving_bench(svf, datagen, n_build=5_000_000, rounds=60, rates=(60.0, 240.0
     ix.serve_start(streams=4, max_batch=16384)
     pos_ins, pos_del, pos_q = n_build, 0, 0
     loads = []
-    phases = [(r, None) for r in rates] + [(consolidation_rate, 0), (consolidation_rate, 1)]
-    for rate_hz, async_mode in phases:
+    phases = [(r, n, None) for r, n in zip(rates, rounds)] + \
+             [(consolidation_rate, consolidation_rounds, 0), (consolidation_rate, consolidation_rounds, 1)]
+    rec_after = None
+    for rate_hz, n_rounds, async_mode in phases:
         if async_mode is not None:
             ix.serve_stop()
             ix.consolidate_wait()
+            if rec_after is None:
+                rec_after = stream_recall(torch, ix, base[:pos_ins], queries[:recall_sample])
+                log("serving: recall@10 %.4f on %d queries at %d vectors"
+                    % (rec_after, recall_sample, pos_ins))
             ix.set_option("consolidate_frac", consolidate_frac)
             ix.set_option("consolidate_async", async_mode)
             ix.serve_start(streams=4, max_batch=16384)
-        reqs = datagen.request_stream(rounds, 10_000, 1_000, 4, 10_000, rate_hz)
+        reqs = datagen.request_stream(n_rounds, 10_000, 1_000, 4, 10_000, rate_hz)
         cons0 = ix.stats()["consolidations"]
         tickets = []
         keep = []
@@ -213,7 +224,8 @@ def serving_bench(svf, datagen, n_build=5_000_000, rounds=60, rates=(60.0, 240.0
             tickets.append((t, r.kind, r.size))
         infos = [(kind, size, ix.wait(t, 300.0)) for t, kind, size in tickets]
         wall = time.perf_counter() - t_start
-        out = {"offered_req_per_s": rate_hz, "requests": len(reqs), "wall_s": round(wall, 3)}
+        out = {"offered_req_per_s": rate_hz, "rounds": n_rounds, "requests": len(reqs),
+               "wall_s": round(wall, 3), "vectors_after": pos_ins}
         if async_mode is not None:
             out["consolidation"] = ("background on a snapshot" if async_mode else "synchronous") + \
                 " (consolidate_frac %g)" % consolidate_frac
@@ -227,14 +239,53 @@ def serving_bench(svf, datagen, n_build=5_000_000, rounds=60, rates=(60.0, 240.0
                              "p99_ms": round(float(np.percentile(lat, 99)), 3),
                              "mean_ms": round(float(lat.mean()), 3)}
         out["max_batch_queries"] = int(max(inf["batch_queries"] for _, _, inf in infos))
+        log("serving load %g req/s: %d vectors, %.0f QPS, search p50 %.2f p99 %.2f ms"
+            % (rate_hz, pos_ins, out["qps"], out["search"]["p50_ms"], out["search"]["p99_ms"]))
         loads.append(out)
     ix.serve_stop()
     ix.consolidate_wait()
+    ix.close()
+    del base
+    cols = ["offered_req_per_s", "qps", "search_p50_ms", "search_p99_ms", "insert_p50_ms",
+            "insert_p99_ms", "delete_p50_ms", "delete_p99_ms"]
+    rows = [[L["offered_req_per_s"], L["qps"]] +
+            [L[k][q] if k in L else None for k in ("search", "insert", "delete")
+             for q in ("p50_ms", "p99_ms")] for L in loads[:len(rates)]]
+    headline = {"build": n_build, "after": n_build + sum(rounds) * 10_000,
+                "recall@10": None if rec_after is None else round(rec_after, 4),
+                "cols": cols, "loads": rows}
     return {"workload": "%dM x 96 unit-norm GMM (1024 comps, Zipf(1.1) queries), IP, degree 48, "
-                        "BF16 + FP32 re-score, k=10, beam 64; per load %d rounds of insert 10k / "
-                        "delete 1k / 4 query batches 1..10k, Poisson arrivals"
-                        % (n_build // 1_000_000, rounds),
-            "build_s": round(build_s, 2), "loads": loads}
+                        "BF16 + FP32 re-score, k=10, beam 64; %d rounds of insert 10k / delete 1k / "
+                        "4 query batches 1..10k over %d loads, Poisson arrivals"
+                        % (n_build // 1_000_000, sum(rounds), len(rates)),
+            "build_s": round(build_s, 2), "recall@10_after_stream": rec_after,
+            "headline": headline, "loads": loads}
+
+
+def stream_recall(torch, ix, vecs, q):
+    """Tie-aware recall@10 of a search (k=10, beam 64) over the live vectors
+    of the index, against an exact inner-product top-10."""
+    _, _, alive = ix.export_graph()
+    live = np.flatnonzero(alive[:vecs.shape[0]])
+    ids, _ = ix.search(q, 10, 64)
+    q_t = torch.from_numpy(np.ascontiguousarray(q)).cuda()
+    best = torch.full((q.shape[0], 10), -float("inf"), device="cuda", dtype=torch.float64)
+    chunk = 1 << 18
+    for c0 in range(0, live.size, chunk):
+        sel = live[c0:c0 + chunk]
+        b = torch.from_numpy(np.ascontiguousarray(vecs[sel])).cuda()
+        s = (q_t.double() @ b.double().T)
+        top = torch.topk(s, min(10, s.shape[1]), dim=1).values
+        best = torch.topk(torch.cat([best, top], dim=1), 10, dim=1).values
+        del b, s
+    kth = best[:, 9]                                   # 10th largest product
+    got = np.where(ids >= 0, ids, 0)
+    g_t = torch.from_numpy(np.ascontiguousarray(vecs[got.ravel()].reshape(got.shape + (-1,)))).cuda()
+    prod = (g_t.double() * q_t.double()[:, None, :]).sum(-1)
+    ok = (prod >= kth[:, None]) & torch.from_numpy(ids >= 0).cuda()
+    alive_t = torch.from_numpy(alive[got.ravel()].reshape(got.shape).astype(bool)).cuda()
+    ok &= alive_t
+    return float(ok.double().sum().item() / (10 * q.shape[0]))
 
 
 def small_batch_bench(torch, ix, q_t, base_t, kth, beam, reps=30):
@@ -815,24 +866,44 @@ def policy_bench(torch, svf, datagen, n_total=2_000_000, steps=12, measured=8, b
             "build_s": round(build_s, 2), "settings": out}
 
 
-def cpu_baseline(base, queries, beam):
-    """The FP64 oracle, as it stands, on a bounded sample: it builds its own
-    index over the first 20,000 base vectors (same generator) and searches
-    2,000 of the queries at the chosen beam with all host cores."""
+def cpu_info():
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model
+
+
+def cpu_baseline(ix, base, queries, beam, gpu_ids, n_single=500):
+    """The FP64 oracle, as it stands, on the GPU-built graph of this workload
+    (exported through the C ABI and imported into the oracle): all queries of
+    the batch at the plain form's beam on every host core, and a sample on
+    one core.  Its ids are compared with the GPU's (integer-valued data:
+    every distance is exact on both sides)."""
     import oracle as O
-    ncore = os.cpu_count() or 1
-    n_sample, nq = 20_000, 2_000
-    ix = O.OracleIndex(DIM, DEGREE, O.L2, seed=0)
+    ncore = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    rows, ed, alive = ix.export_graph()
+    oix = O.OracleIndex(DIM, DEGREE, O.L2, seed=0)
+    oix.import_state(base, rows, ed.astype(np.float64), alive)
+    del rows, ed
+    nq = queries.shape[0]
     t0 = time.perf_counter()
-    ix.build(base[:n_sample])
-    tb = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    ix.search(queries[:nq], K, beam, threads=ncore)
+    oi, _, _ = oix.search(queries, K, beam, threads=ncore)
     ts = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oix.search(queries[:n_single], K, beam, threads=1)
+    t1 = time.perf_counter() - t0
+    same = float(np.mean(np.all(oi == gpu_ids, axis=1)))
+    del oix
     return {"value": round(nq / ts, 1), "unit": "queries/s", "cores": ncore, "kind": "oracle",
-            "sample": "FP64 oracle search of %d queries at beam %d over a %d-vector index of the "
-                      "same mixture that the oracle built itself (build took %.1f s, 1 core)"
-                      % (nq, beam, n_sample, tb)}
+            "sample": "FP64 oracle, all %d queries at beam %d on the GPU-built %d-vector graph, "
+                      "%d threads (%s)" % (nq, beam, base.shape[0], ncore, cpu_info() or "cpu"),
+            "single_core_qps": round(n_single / t1, 1), "wall_s": round(ts, 2),
+            "query_ids_equal_gpu": same}
 
 
 def main():
@@ -863,6 +934,9 @@ def main():
                          "hardware counter runs); prints a short JSON line")
     ap.add_argument("--search-precision", choices=("fp32", "bf16", "fp8"), default="fp32",
                     help="traversal precision of --search-only (re-scored in FP32)")
+    ap.add_argument("--detail", default=os.path.join("gpurun_out", "bench_detail.json"),
+                    help="file that receives every leg's figures (sweeps, ablations, serving); "
+                         "stdout's last line is the headline")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device-to-device three times (a reference "
                          "kernel of known traffic for hardware counter runs)")
@@ -925,6 +999,7 @@ def main():
         beam = BEAMS[-1]
     ms, wall = timed_steps(torch, ix, q_t, beam, bufs, args.steps, args.warmup)
     rec = recall(torch, base_t, q_t, bufs[0], kth)
+    gpu_ids = bufs[0].cpu().numpy()
     n_dist_run = int(bufs[2].sum().item())
     n_exp = int(bufs[3].sum().item())
     # algorithmic bytes: count distance evaluations with the largest visited
@@ -939,6 +1014,20 @@ def main():
     ms_step = float(np.mean(ms))
     achieved = alg_bytes / (ms_step / 1e3) / 1e9
     qps = nq / (ms_step / 1e3)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": counted_traffic(beam), "traffic_unit": "bytes/launch",
+            "kernel": "search_kernel<float,1>",
+            "alg_bytes_per_launch": alg_bytes,
+            "n_dist_per_query": round(n_dist / nq, 1),
+            "n_dist_per_query_timed": round(n_dist_run / nq, 1),
+            "n_exp_per_query": round(n_exp / nq, 1)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on the GPU-built graph")
+        cpu = cpu_baseline(ix, base, queries[:nq], beam, gpu_ids)
+        log("oracle %.0f queries/s on %d threads, ids equal to the GPU's for %.4f of queries"
+            % (cpu["value"], cpu["cores"], cpu["query_ids_equal_gpu"]))
     # the same batch through svf_search with host buffers (copies included)
     q_host = queries[:nq]
     ix.search(q_host, K, beam)
@@ -971,47 +1060,68 @@ def main():
     ix.set_option("precision", svf.PREC_FP32)
 
     # chosen form: reduced precision + the learned entry/stop predictor,
-    # trained on the GPU from traces of plain search
+    # trained on the GPU from traces of plain search.  The predictor's head
+    # is 64 entry clusters + 1 stop output; a 256-cluster head is measured
+    # beside it.  Queries whose softmax confidence is below model_conf fall
+    # back to plain search; thresholds 0 and 0.3 are both tried.
     train = datagen.training_queries_uint8(2, 200_000, DIM, 256)
-    t0 = time.perf_counter()
-    fit_loss = ix.model_fit(train, K, 64, n_clusters=256, epochs=12)
-    fit_s = time.perf_counter() - t0
-    ix.set_option("use_model", 1)
-    ix.set_option("model_conf", 0.0)
-    # the visited table's size never changes results, only the balance of
-    # re-evaluations against LDS occupancy (the library's default for reduced
-    # precision is 2048 slots); both sizes are tried
     slots0 = int(ix.get_option("visited_slots"))
-    best = None
-    tried = []
-    for pname, prec in (("bf16", svf.PREC_BF16), ("fp8", svf.PREC_FP8)):
-        ix.set_option("precision", prec)
-        for slots in (4096, 2048):
+
+    def chosen(n_clusters, grid):
+        t0 = time.perf_counter()
+        loss = ix.model_fit(train, K, 64, n_clusters=n_clusters, epochs=12)
+        fit = time.perf_counter() - t0
+        ix.set_option("use_model", 1)
+        best, tried = None, []
+        for pname, prec, slots, width, stop_scale, conf in grid:
+            ix.set_option("precision", prec)
             ix.set_option("visited_slots", slots)
-            for width, stop_scale in ((1, 2.0), (2, 1.0), (2, 1.5), (1, 1e6)):
-                ix.set_option("search_width", width)
-                ix.set_option("model_stop_scale", stop_scale)
-                b, rws = sweep(torch, ix, q_t, base_t, kth, bufs, [32, 48, 64, 96, 128])
-                tried.append({"precision": pname, "visited_slots": slots, "search_width": width,
-                              "stop_scale": stop_scale, "beam": b, "sweep": rws})
-                if b is not None:
-                    ms_c = [r["ms"] for r in rws if r["beam"] == b][0]
-                    if best is None or ms_c < best[0]:
-                        best = (ms_c, pname, prec, width, stop_scale, b, slots)
-    if best is None:
-        best = (None, "bf16", svf.PREC_BF16, 1, 1e6, BEAMS[-1], slots0)
-    _, cpname, cprec, cw, css, beam_c, cslots = best
-    ix.set_option("precision", cprec)
-    ix.set_option("search_width", cw)
-    ix.set_option("model_stop_scale", css)
-    ix.set_option("visited_slots", cslots)
-    ms_c, _ = timed_steps(torch, ix, q_t, beam_c, bufs, args.steps, args.warmup)
-    rec_c = recall(torch, base_t, q_t, bufs[0], kth)
-    maxerr = dist_errors(torch, base_t, q_t, bufs)["max_abs"]
-    ix.set_option("use_model", 0)
-    ix.set_option("search_width", 1)
-    ix.set_option("visited_slots", slots0)
-    ix.set_option("precision", svf.PREC_FP32)
+            ix.set_option("search_width", width)
+            ix.set_option("model_stop_scale", stop_scale)
+            ix.set_option("model_conf", conf)
+            b, rws = sweep(torch, ix, q_t, base_t, kth, bufs, [32, 48, 64, 96, 128])
+            tried.append({"precision": pname, "visited_slots": slots, "search_width": width,
+                          "stop_scale": stop_scale, "model_conf": conf, "beam": b, "sweep": rws})
+            if b is not None:
+                ms_b = [r["ms"] for r in rws if r["beam"] == b][0]
+                if best is None or ms_b < best[0]:
+                    best = (ms_b, pname, prec, slots, width, stop_scale, conf, b)
+        if best is None:
+            best = (None, "bf16", svf.PREC_BF16, slots0, 1, 1e6, 0.0, BEAMS[-1])
+        _, pname, prec, slots, width, stop_scale, conf, b = best
+        for k_, v_ in (("precision", prec), ("visited_slots", slots), ("search_width", width),
+                       ("model_stop_scale", stop_scale), ("model_conf", conf)):
+            ix.set_option(k_, v_)
+        ms_b, _ = timed_steps(torch, ix, q_t, b, bufs, args.steps, args.warmup)
+        fallback = ix.stats()["last_model_fallback"] / nq
+        rec_b = recall(torch, base_t, q_t, bufs[0], kth)
+        err = dist_errors(torch, base_t, q_t, bufs)["max_abs"]
+        ix.set_option("use_model", 0)
+        ix.set_option("search_width", 1)
+        ix.set_option("visited_slots", slots0)
+        ix.set_option("model_conf", 0.5)
+        ix.set_option("precision", svf.PREC_FP32)
+        ms_m = float(np.mean(ms_b))
+        return {"form": "%s traversal + FP32 re-score + learned entry clusters and stop cap "
+                        "(MLP 128-256-256-%d, BF16, trained on the GPU)" % (pname.upper(), n_clusters + 1),
+                "precision": pname, "beam": b, "search_width": width, "model_stop_scale": stop_scale,
+                "model_conf": conf, "fallback_share": round(fallback, 4), "visited_slots": slots,
+                "recall@10": round(rec_b, 5), "value": round(nq / (ms_m / 1e3), 1),
+                "ms_per_step": round(ms_m, 4), "speedup_vs_plain": round(ms_step / ms_m, 3),
+                "max_abs_dist_err_vs_fp64": err, "model_fit_s": round(fit, 2),
+                "model_fit_loss": round(loss, 4), "training_queries": train.shape[0],
+                "n_clusters": n_clusters, "configs_tried": tried}
+
+    grid = [(pn, pr, sl, w, ss, cf)
+            for pn, pr in (("bf16", svf.PREC_BF16), ("fp8", svf.PREC_FP8))
+            for sl in (4096, 2048)
+            for w, ss in ((1, 2.0), (2, 1.0), (2, 1.5), (1, 1e6))
+            for cf in (0.0, 0.3)]
+    chosen64 = chosen(64, grid)
+    c = chosen64
+    grid256 = [(c["precision"], {"bf16": svf.PREC_BF16, "fp8": svf.PREC_FP8}[c["precision"]],
+                c["visited_slots"], c["search_width"], c["model_stop_scale"], cf) for cf in (0.0, 0.3)]
+    chosen256 = chosen(256, grid256)
 
     # update path: delete 1% then insert 10k fresh vectors (one batch each)
     g = np.random.Generator(np.random.Philox(77))
@@ -1063,53 +1173,18 @@ def main():
     serving = None
     if not args.no_serving:
         log("serving mix")
-        serving = serving_bench(svf, datagen)
+        torch.cuda.empty_cache()
+        serving = serving_bench(torch, svf, datagen)
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("timing the CPU oracle")
-        cpu = cpu_baseline(base, queries, beam)
-
-    out = {
-        "metric": "queries/sec at recall@10>=0.95 (batch 10k), plain FP32 search",
-        "value": round(qps, 1),
-        "unit": "queries/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
+    detail = {
         "config": {"workload": "1M x 128 integer-valued GMM (256 comps), L2, degree 64, "
                                "10k-query batch, k=10",
                    "n_base": args.n_base, "n_query": nq, "dim": DIM, "degree": DEGREE, "k": K,
                    "beam": beam, "recall@10": round(rec, 5)},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": counted_traffic(beam), "traffic_unit": "bytes/launch",
-                     "kernel": "search_kernel<float,1>",
-                     "alg_bytes_per_launch": alg_bytes,
-                     "n_dist_per_query": round(n_dist / nq, 1),
-                     "n_dist_per_query_timed": round(n_dist_run / nq, 1),
-                     "n_exp_per_query": round(n_exp / nq, 1)},
+        "roofline": roof,
         "cpu_baseline": cpu,
-        "chosen_form": {"form": "%s traversal + FP32 re-score + learned entry clusters "
-                                "and stop cap (MLP 128-256-256-257, BF16, trained on the GPU)"
-                                % cpname.upper(),
-                        "precision": cpname,
-                        "beam": beam_c, "search_width": cw, "model_stop_scale": css,
-                        "visited_slots": cslots,
-                        "recall@10": round(rec_c, 5),
-                        "value": round(nq / (float(np.mean(ms_c)) / 1e3), 1),
-                        "ms_per_step": round(float(np.mean(ms_c)), 4),
-                        "speedup_vs_plain": round(ms_step / float(np.mean(ms_c)), 3),
-                        "max_abs_dist_err_vs_fp64": maxerr,
-                        "model_fit_s": round(fit_s, 2), "model_fit_loss": round(fit_loss, 4),
-                        "training_queries": 200_000, "n_clusters": 256,
-                        "configs_tried": tried},
+        "chosen_form": chosen64,
+        "chosen_form_256_clusters": chosen256,
         "reduced_precision": lowp,
         "sweep_fp32": rows,
         "update": {"build_s": round(build_s, 3), "build_vectors_per_s": round(args.n_base / build_s, 1),
@@ -1131,7 +1206,40 @@ def main():
         "serving": serving,
         "wall_s_timed": round(wall, 4),
     }
-    print(json.dumps(out), flush=True)
+    os.makedirs(os.path.dirname(args.detail) or ".", exist_ok=True)
+    with open(args.detail, "w") as f:
+        json.dump(detail, f)
+    c = chosen64
+    head = {
+        "metric": METRIC,
+        "value": round(qps, 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "plain FP32 search, 1M x 128 integer-valued GMM (256 comps), L2, "
+                               "degree 64, 10k-query batch, k=10",
+                   "beam": beam, "recall@10": round(rec, 4)},
+        "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic",
+                                          "kernel", "alg_bytes_per_launch")},
+        "cpu_baseline": None if cpu is None else {
+            "value": cpu["value"], "unit": cpu["unit"], "cores": cpu["cores"], "kind": "oracle",
+            "sample": cpu["sample"], "ids_equal_gpu": cpu["query_ids_equal_gpu"]},
+        "chosen_form": {"precision": c["precision"], "n_clusters": c["n_clusters"],
+                        "beam": c["beam"], "search_width": c["search_width"],
+                        "model_conf": c["model_conf"], "fallback_share": c["fallback_share"],
+                        "recall@10": round(c["recall@10"], 4), "value": c["value"],
+                        "speedup_vs_plain": c["speedup_vs_plain"]},
+        "serving": None if serving is None else serving.get("headline"),
+        "detail": args.detail,
+    }
+    print(json.dumps(head, separators=(",", ":")), flush=True)
 
 
 if __name__ == "__main__":

@@ -75,6 +75,8 @@ typedef struct svf_stats {
     int64_t cache_last_placed;      /* last batch: vectors placed in the cache */
     int64_t cache_promotions, cache_evictions;
     int64_t consolidations;         /* global consolidations done (a background one once merged) */
+    int64_t last_model_fallback;    /* last search with use_model: queries below model_conf that
+                                       ran plain search */
 } svf_stats;
 
 /* Create an empty index.  Sec. 2.3: a directed graph with a fixed number of

@@ -57,7 +57,7 @@ class Stats(C.Structure):
         ("cache_gather_misses", C.c_int64), ("cache_last_trace_hits", C.c_int64),
         ("cache_last_placed", C.c_int64), ("cache_promotions", C.c_int64),
         ("cache_evictions", C.c_int64),
-        ("consolidations", C.c_int64),
+        ("consolidations", C.c_int64), ("last_model_fallback", C.c_int64),
     ]
 
     def as_dict(self):

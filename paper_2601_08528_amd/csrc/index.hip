@@ -735,7 +735,7 @@ int search_impl(svf_index* ix, const float* d_q, int64_t nq, int k, int beam, in
   uint64_t* qkey;
   unsigned long long* tot;
   int rc;
-  if ((rc = scratch(ix->s_qkey, nq, &qkey)) || (rc = scratch(ix->s_tot, 2, &tot))) return rc;
+  if ((rc = scratch(ix->s_qkey, nq, &qkey)) || (rc = scratch(ix->s_tot, 3, &tot))) return rc;
   if (ix->n_slots == 0) {
     // nothing indexed: every result is padding
     CK(svf::launch_fill_u32(d_ids, nq * k, 0xffffffffu, st));
@@ -758,7 +758,8 @@ int search_impl(svf_index* ix, const float* d_q, int64_t nq, int k, int beam, in
       return rc;
     CK(ix->model->forward(d_q, nq, z, st));
     CK(svf::launch_model_decide(z, nq, ix->model_nc, (float)ix->opt.model_conf,
-                                (float)ix->opt.model_stop_scale, ix->opt.model_min_iters, qe, qm, st));
+                                (float)ix->opt.model_stop_scale, ix->opt.model_min_iters, qe, qm,
+                                tot + 2, st));
     a.entry_lists = ix->entry_lists.as<int32_t>();
     a.entry_cap = ix->entry_cap;
     a.q_entry = qe;
@@ -779,7 +780,7 @@ int search_impl(svf_index* ix, const float* d_q, int64_t nq, int k, int beam, in
     a.tier_counts = cnt;
     CK(svf::launch_fill_u32(cnt, 4, 0u, st));
   }
-  CK(svf::launch_fill_u32(tot, 4, 0u, st));
+  CK(svf::launch_fill_u32(tot, 6, 0u, st));
   CK(svf::launch_query_keys(d_q, ix->dim, nullptr, ix->dim, a.nq, ix->opt.seed, qkey, st));
   a.qkey = qkey;
   CK(hipEventRecord(ix->ev0, st));
@@ -831,10 +832,11 @@ bool all_finite(const float* p, int64_t n) {
 }
 
 void finish_search_stats(svf_index* ix) {
-  unsigned long long tot[2] = {0, 0};
+  unsigned long long tot[3] = {0, 0, 0};
   if (ix->s_tot.p && hipMemcpy(tot, ix->s_tot.p, sizeof tot, hipMemcpyDeviceToHost) == hipSuccess) {
     ix->st.last_n_dist = (int64_t)tot[0];
     ix->st.last_n_exp = (int64_t)tot[1];
+    ix->st.last_model_fallback = (ix->opt.use_model && ix->model) ? (int64_t)tot[2] : 0;
   }
   ix->st.last_search_ms = elapsed(ix->ev0, ix->ev1);
 }
@@ -1864,7 +1866,7 @@ int svf_model_fit(svf_index* ix, const float* train_queries, int64_t n, int32_t 
         (rc = scratch(ix->s_qmax, n, &qm)))
       return rc;
     CK(ix->model->forward(dq, n, z, st));
-    CK(svf::launch_model_decide(z, n, nc, 0.0f, 1.0f, 1, qe, qm, st));
+    CK(svf::launch_model_decide(z, n, nc, 0.0f, 1.0f, 1, qe, qm, nullptr, st));
     svf::SearchArgs t = base_args(ix);
     set_beam(t, ix, beam);
     t.k = k;

@@ -162,8 +162,14 @@ __global__ void round_params_kernel(float* p, uint16_t* wb, int64_t n) {
   wb[i] = b;
 }
 
+// Gating of the learned form: the first largest cluster logit, its softmax
+// probability p = 1 / sum_j exp(z_j - z_max), and with p >= conf the cluster
+// and an expansion cap max(min_iters, ceil(stop_scale * exp(min(z_stop, 20))))
+// held at or below 2^30; otherwise plain search (cluster -1, no cap), counted
+// in *n_fallback when given.
 __global__ void decide_kernel(const float* z, int64_t n, int nc, float conf, float stop_scale,
-                              int min_iters, int32_t* q_entry, int32_t* q_max) {
+                              int min_iters, int32_t* q_entry, int32_t* q_max,
+                              unsigned long long* n_fallback) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float* zi = z + i * (nc + 1);
@@ -176,21 +182,22 @@ __global__ void decide_kernel(const float* z, int64_t n, int nc, float conf, flo
   const float p = 1.0f / se;                  // softmax of the argmax
   if (p >= conf) {
     q_entry[i] = best;
-    float cap = ceilf(stop_scale * __expf(fminf(zi[nc], 20.f)));
-    int c = (int)cap;
+    const float cap = fminf(ceilf(stop_scale * __expf(fminf(zi[nc], 20.f))), 1073741824.f);
+    const int c = (int)cap;
     q_max[i] = c < min_iters ? min_iters : c;
   } else {
     q_entry[i] = -1;
     q_max[i] = 0;
+    if (n_fallback) atomicAdd(n_fallback, 1ull);
   }
 }
 
 hipError_t launch_model_decide(const float* z, int64_t n, int nc, float conf, float stop_scale,
                                int min_iters, int32_t* q_entry, int32_t* q_max_iters,
-                               hipStream_t st) {
+                               unsigned long long* n_fallback, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(decide_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, z, n, nc,
-                     conf, stop_scale, min_iters, q_entry, q_max_iters);
+                     conf, stop_scale, min_iters, q_entry, q_max_iters, n_fallback);
   return hipGetLastError();
 }
 

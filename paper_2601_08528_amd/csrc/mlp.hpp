@@ -76,7 +76,7 @@ class Mlp {
 // others keep random entries and no cap (plain search).
 hipError_t launch_model_decide(const float* z, int64_t n, int nc, float conf, float stop_scale,
                                int min_iters, int32_t* q_entry, int32_t* q_max_iters,
-                               hipStream_t st);
+                               unsigned long long* n_fallback, hipStream_t st);
 
 // Lloyd k-means of n rows (stride `stride`, first dim used) into nc centroids
 // (device, nc x dim), `iters` iterations, initial centroids given.
