@@ -162,7 +162,7 @@ def sweep(torch, ix, q_t, base_t, kth, bufs, beams, target=0.95, refine=8):
 
 def serving_bench(torch, svf, datagen, n_build=5_000_000, rounds=(167, 167, 166),
                   rates=(60.0, 240.0, 480.0), consolidation_rate=240.0, consolidation_rounds=60,
-                  consolidate_frac=0.004, recall_sample=1000):
+                  consolidate_frac=0.004, recall_sample=1000, beams=(64, 96, 128, 192, 256, 320, 384)):
     """Streaming mix on the serving loop: an n_build-vector unit-norm 96-d
     mixture (1024 components, inner product, degree 48, BF16 traversal + FP32
     re-score), then, at each offered load in turn, rounds[i] rounds of [one
@@ -181,6 +181,19 @@ def serving_bench(torch, svf, datagen, n_build=5_000_000, rounds=(167, 167, 166)
     t0 = time.perf_counter()
     ix.build(base[:n_build])
     build_s = time.perf_counter() - t0
+    # the serving beam: the smallest of a sweep whose recall@10 on a query
+    # sample reaches 0.95 on the built index
+    kth, alive = stream_kth(torch, ix, base[:n_build], queries[:recall_sample])
+    beam, beam_sweep = beams[-1], []
+    for b in beams:
+        ids, _ = ix.search(queries[:recall_sample], 10, b)
+        r = stream_recall_of(torch, ids, base[:n_build], queries[:recall_sample], kth, alive)
+        beam_sweep.append({"beam": b, "recall@10": round(r, 4)})
+        log("serving: beam %d recall@10 %.4f at %d vectors" % (b, r, n_build))
+        if r >= 0.95:
+            beam = b
+            break
+    del kth, alive
     g = np.random.Generator(np.random.Philox(31))
     victims = g.permutation(n_build).astype(np.int32)
     ix.serve_start(streams=4, max_batch=16384)
@@ -194,7 +207,7 @@ def serving_bench(torch, svf, datagen, n_build=5_000_000, rounds=(167, 167, 166)
             ix.serve_stop()
             ix.consolidate_wait()
             if rec_after is None:
-                rec_after = stream_recall(torch, ix, base[:pos_ins], queries[:recall_sample])
+                rec_after = stream_recall(torch, ix, base[:pos_ins], queries[:recall_sample], beam)
                 log("serving: recall@10 %.4f on %d queries at %d vectors"
                     % (rec_after, recall_sample, pos_ins))
             ix.set_option("consolidate_frac", consolidate_frac)
@@ -219,7 +232,7 @@ def serving_bench(torch, svf, datagen, n_build=5_000_000, rounds=(167, 167, 166)
             else:
                 idx = (pos_q + np.arange(r.size)) % queries.shape[0]
                 pos_q += r.size
-                t, ids, d = ix.submit_search(queries[idx], 10, 64)
+                t, ids, d = ix.submit_search(queries[idx], 10, beam)
                 keep.append((ids, d))
             tickets.append((t, r.kind, r.size))
         infos = [(kind, size, ix.wait(t, 300.0)) for t, kind, size in tickets]
@@ -251,23 +264,25 @@ def serving_bench(torch, svf, datagen, n_build=5_000_000, rounds=(167, 167, 166)
     rows = [[L["offered_req_per_s"], L["qps"]] +
             [L[k][q] if k in L else None for k in ("search", "insert", "delete")
              for q in ("p50_ms", "p99_ms")] for L in loads[:len(rates)]]
-    headline = {"build": n_build, "after": n_build + sum(rounds) * 10_000,
+    headline = {"build": n_build, "after": n_build + sum(rounds) * 10_000, "beam": beam,
+                "recall@10_build": beam_sweep[-1]["recall@10"],
                 "recall@10": None if rec_after is None else round(rec_after, 4),
                 "cols": cols, "loads": rows}
     return {"workload": "%dM x 96 unit-norm GMM (1024 comps, Zipf(1.1) queries), IP, degree 48, "
-                        "BF16 + FP32 re-score, k=10, beam 64; %d rounds of insert 10k / delete 1k / "
+                        "BF16 + FP32 re-score, k=10, beam %d (the smallest of a sweep reaching "
+                        "recall@10 0.95 after the build); %d rounds of insert 10k / delete 1k / "
                         "4 query batches 1..10k over %d loads, Poisson arrivals"
-                        % (n_build // 1_000_000, sum(rounds), len(rates)),
-            "build_s": round(build_s, 2), "recall@10_after_stream": rec_after,
+                        % (n_build // 1_000_000, beam, sum(rounds), len(rates)),
+            "build_s": round(build_s, 2), "beam_sweep": beam_sweep,
+            "recall@10_after_stream": rec_after,
             "headline": headline, "loads": loads}
 
 
-def stream_recall(torch, ix, vecs, q):
-    """Tie-aware recall@10 of a search (k=10, beam 64) over the live vectors
-    of the index, against an exact inner-product top-10."""
+def stream_kth(torch, ix, vecs, q):
+    """Exact 10th-largest inner product of each query over the live vectors
+    of the index (FP64), and the alive flags."""
     _, _, alive = ix.export_graph()
     live = np.flatnonzero(alive[:vecs.shape[0]])
-    ids, _ = ix.search(q, 10, 64)
     q_t = torch.from_numpy(np.ascontiguousarray(q)).cuda()
     best = torch.full((q.shape[0], 10), -float("inf"), device="cuda", dtype=torch.float64)
     chunk = 1 << 18
@@ -278,7 +293,12 @@ def stream_recall(torch, ix, vecs, q):
         top = torch.topk(s, min(10, s.shape[1]), dim=1).values
         best = torch.topk(torch.cat([best, top], dim=1), 10, dim=1).values
         del b, s
-    kth = best[:, 9]                                   # 10th largest product
+    return best[:, 9], alive
+
+
+def stream_recall_of(torch, ids, vecs, q, kth, alive):
+    """Tie-aware recall@10 of result ids against the exact 10th product."""
+    q_t = torch.from_numpy(np.ascontiguousarray(q)).cuda()
     got = np.where(ids >= 0, ids, 0)
     g_t = torch.from_numpy(np.ascontiguousarray(vecs[got.ravel()].reshape(got.shape + (-1,)))).cuda()
     prod = (g_t.double() * q_t.double()[:, None, :]).sum(-1)
@@ -286,6 +306,14 @@ def stream_recall(torch, ix, vecs, q):
     alive_t = torch.from_numpy(alive[got.ravel()].reshape(got.shape).astype(bool)).cuda()
     ok &= alive_t
     return float(ok.double().sum().item() / (10 * q.shape[0]))
+
+
+def stream_recall(torch, ix, vecs, q, beam):
+    """Tie-aware recall@10 of a search (k=10) over the live vectors of the
+    index, against an exact inner-product top-10."""
+    kth, alive = stream_kth(torch, ix, vecs, q)
+    ids, _ = ix.search(q, 10, beam)
+    return stream_recall_of(torch, ids, vecs, q, kth, alive)
 
 
 def small_batch_bench(torch, ix, q_t, base_t, kth, beam, reps=30):
@@ -1067,7 +1095,8 @@ def main():
     train = datagen.training_queries_uint8(2, 200_000, DIM, 256)
     slots0 = int(ix.get_option("visited_slots"))
 
-    def chosen(n_clusters, grid):
+    def chosen(n_clusters, grid, entries=1):
+        ix.set_option("model_entries", entries)
         t0 = time.perf_counter()
         loss = ix.model_fit(train, K, 64, n_clusters=n_clusters, epochs=12)
         fit = time.perf_counter() - t0
@@ -1103,7 +1132,10 @@ def main():
         ix.set_option("precision", svf.PREC_FP32)
         ms_m = float(np.mean(ms_b))
         return {"form": "%s traversal + FP32 re-score + learned entry clusters and stop cap "
-                        "(MLP 128-256-256-%d, BF16, trained on the GPU)" % (pname.upper(), n_clusters + 1),
+                        "(MLP 128-256-256-%d, BF16, trained on the GPU; entry lists %s)"
+                        % (pname.upper(), n_clusters + 1,
+                           "spread over each cluster" if entries else "nearest to each centroid"),
+                "model_entries": entries,
                 "precision": pname, "beam": b, "search_width": width, "model_stop_scale": stop_scale,
                 "model_conf": conf, "fallback_share": round(fallback, 4), "visited_slots": slots,
                 "recall@10": round(rec_b, 5), "value": round(nq / (ms_m / 1e3), 1),
@@ -1112,16 +1144,16 @@ def main():
                 "model_fit_loss": round(loss, 4), "training_queries": train.shape[0],
                 "n_clusters": n_clusters, "configs_tried": tried}
 
-    grid = [(pn, pr, sl, w, ss, cf)
+    grid = [(pn, pr, 2048, w, ss, cf)
             for pn, pr in (("bf16", svf.PREC_BF16), ("fp8", svf.PREC_FP8))
-            for sl in (4096, 2048)
-            for w, ss in ((1, 2.0), (2, 1.0), (2, 1.5), (1, 1e6))
+            for w, ss in ((1, 1e6), (2, 1e6), (2, 1.5), (1, 2.0))
             for cf in (0.0, 0.3)]
     chosen64 = chosen(64, grid)
     c = chosen64
-    grid256 = [(c["precision"], {"bf16": svf.PREC_BF16, "fp8": svf.PREC_FP8}[c["precision"]],
-                c["visited_slots"], c["search_width"], c["model_stop_scale"], cf) for cf in (0.0, 0.3)]
-    chosen256 = chosen(256, grid256)
+    small = [(c["precision"], {"bf16": svf.PREC_BF16, "fp8": svf.PREC_FP8}[c["precision"]],
+              c["visited_slots"], c["search_width"], c["model_stop_scale"], cf) for cf in (0.0, 0.3)]
+    chosen64_nearest = chosen(64, small, entries=0)
+    chosen256 = chosen(256, small)
 
     # update path: delete 1% then insert 10k fresh vectors (one batch each)
     g = np.random.Generator(np.random.Philox(77))
@@ -1184,6 +1216,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "chosen_form": chosen64,
+        "chosen_form_64_nearest_entries": chosen64_nearest,
         "chosen_form_256_clusters": chosen256,
         "reduced_precision": lowp,
         "sweep_fp32": rows,
@@ -1235,7 +1268,9 @@ def main():
                         "beam": c["beam"], "search_width": c["search_width"],
                         "model_conf": c["model_conf"], "fallback_share": c["fallback_share"],
                         "recall@10": round(c["recall@10"], 4), "value": c["value"],
-                        "speedup_vs_plain": c["speedup_vs_plain"]},
+                        "speedup_vs_plain": c["speedup_vs_plain"],
+                        "speedup_64_nearest_entries": chosen64_nearest["speedup_vs_plain"],
+                        "speedup_256_clusters": chosen256["speedup_vs_plain"]},
         "serving": None if serving is None else serving.get("headline"),
         "detail": args.detail,
     }

@@ -151,6 +151,10 @@ int svf_destroy(svf_index *ix);
  *   model_conf      softmax confidence below which a query falls back to plain search ([0,1]; 0.5)
  *   model_stop_scale expansion cap = ceil(scale * predicted stop step) (>0; 1.5)
  *   model_min_iters smallest expansion cap of a gated query (>=1; 8)
+ *   model_entries   how svf_model_fit fills a cluster's entry list: 1 = spread over the
+ *                   cluster's members (evenly through its members in the clustered sample,
+ *                   so every part of the cluster holds entries), 0 = the vectors nearest
+ *                   to its centroid (0/1; 1)
  * Unknown key or out-of-range value: SVF_E_INVAL. */
 int svf_set_option(svf_index *ix, const char *key, double value);
 /* Any key above, plus the read-only "dim", "degree", "metric" and
@@ -233,8 +237,9 @@ int svf_search_dev(svf_index *ix, const float *d_queries, int64_t nq, int32_t k,
  *      with k and beam, recording each query's top-1 id and the expansion
  *      count after which its top-k stopped changing;
  *   3. labels: the centroid nearest to the top-1 vector, and log(max(1, step));
- *   4. per cluster, the 64 nearest stored vectors to its centroid become
- *      that cluster's entry list;
+ *   4. per cluster, an entry list of 64 stored vectors: spread over the
+ *      cluster's alive members in the sample (model_entries = 1), or the
+ *      64 nearest stored vectors to its centroid (model_entries = 0);
  *   5. Adam over epochs/2 passes of batches of 1024, loss = cross-entropy +
  *      0.1 * Huber(log step); then the stop labels are re-measured on traces
  *      of the search started from the predicted clusters' entry lists and
@@ -245,6 +250,27 @@ int svf_search_dev(svf_index *ix, const float *d_queries, int64_t nq, int32_t k,
  * *last_loss (may be NULL) receives the mean loss of the last epoch. */
 int svf_model_fit(svf_index *ix, const float *train_queries, int64_t n, int32_t k, int32_t beam,
                   int32_t n_clusters, int32_t epochs, float *last_loss);
+
+/* Plain search (random entry points, no predictor, no cap) that also
+ * reports, per query, the expansion count after which its k nearest last
+ * changed: the stopping-step label that svf_model_fit trains on (step 2
+ * above).  queries: nq x dim FP32, host; out_ids / out_dists: nq x k, host;
+ * out_last_change: nq int32, host (0 when the first pool already held the
+ * final k nearest).  Errors as svf_search; SVF_E_BUSY while serving. */
+int svf_search_trace(svf_index *ix, const float *queries, int64_t nq, int32_t k, int32_t beam,
+                     int32_t *out_ids, float *out_dists, int32_t *out_last_change);
+
+/* The trained predictor as svf_search uses it (so that a replay of the
+ * learned form can be checked outside the library): *n_clusters and
+ * *entry_cap (may be NULL); params (may be NULL; params_cap floats, at least
+ * the count svf_mlp_num_params gives for din = dim, hidden 256, n_clusters)
+ * receives W1 b1 W2 b2 W3 b3 in svf_mlp's flat order with the weights on the
+ * BF16 grid the forward pass multiplies by; entry_lists (may be NULL;
+ * lists_cap ints, at least n_clusters x entry_cap) receives each cluster's
+ * entry ids (-1 padded).  SVF_E_NOTFOUND before svf_model_fit; SVF_E_INVAL
+ * for a short buffer.  Host memory, owned by the caller. */
+int svf_model_get(const svf_index *ix, int32_t *n_clusters, int32_t *entry_cap, float *params,
+                  int64_t params_cap, int32_t *entry_lists, int64_t lists_cap);
 
 /* The predictor on its own (the network svf_model_fit trains), for checks of
  * its forward pass, gradients and training.  Parameters are one flat FP32

@@ -24,7 +24,7 @@ EXPORTED = [
     "svf_create", "svf_destroy", "svf_set_option", "svf_get_option", "svf_insert",
     "svf_insert_dev", "svf_build", "svf_delete", "svf_consolidate", "svf_consolidate_wait", "svf_search",
     "svf_search_dev", "svf_stats_get", "svf_export_graph", "svf_import_graph", "svf_last_error",
-    "svf_search_listed", "svf_model_fit", "svf_mlp_create", "svf_mlp_destroy",
+    "svf_search_listed", "svf_search_trace", "svf_model_get", "svf_model_fit", "svf_mlp_create", "svf_mlp_destroy",
     "svf_mlp_num_params", "svf_mlp_set_params", "svf_mlp_get_params", "svf_mlp_forward",
     "svf_mlp_loss_grad", "svf_mlp_train", "svf_mlp_last_error",
     "svf_serve_start", "svf_serve_stop", "svf_submit_search", "svf_submit_insert",
@@ -95,6 +95,8 @@ def lib():
         L.svf_save.argtypes = [vp, C.c_char_p]
         L.svf_load.argtypes = [C.c_char_p, C.POINTER(vp)]
         L.svf_search_listed.argtypes = [vp, vp, i64, i32, i32, vp, i32, vp, vp, vp]
+        L.svf_search_trace.argtypes = [vp, vp, i64, i32, i32, vp, vp, vp]
+        L.svf_model_get.argtypes = [vp, vp, vp, vp, i64, vp, i64]
         L.svf_model_fit.argtypes = [vp, vp, i64, i32, i32, i32, i32, C.POINTER(C.c_float)]
         L.svf_mlp_create.argtypes = [i32, i32, i32, C.c_uint64, C.POINTER(vp)]
         L.svf_mlp_destroy.argtypes = [vp]
@@ -205,6 +207,27 @@ class Index:
         _check(lib().svf_search_listed(self.h, _p(q), q.shape[0], k, beam, _p(e), e.shape[1],
                                        _p(mi), _p(ids), _p(d)))
         return ids, d
+
+    def search_trace(self, queries, k: int, beam: int):
+        """Plain search plus, per query, the expansion count after which its
+        top-k last changed."""
+        q = np.ascontiguousarray(queries, dtype=np.float32).reshape(-1, self.dim)
+        ids = np.empty((q.shape[0], k), np.int32)
+        d = np.empty((q.shape[0], k), np.float32)
+        lc = np.empty(q.shape[0], np.int32)
+        _check(lib().svf_search_trace(self.h, _p(q), q.shape[0], k, beam, _p(ids), _p(d), _p(lc)))
+        return ids, d, lc
+
+    def model_get(self, hidden: int = 256):
+        """The trained predictor: (flat parameters, entry lists n_clusters x entry_cap)."""
+        nc, ecap = C.c_int32(), C.c_int32()
+        _check(lib().svf_model_get(self.h, C.byref(nc), C.byref(ecap), None, 0, None, 0))
+        din, no = self.dim, nc.value + 1
+        n = din * hidden + hidden + hidden * hidden + hidden + hidden * no + no
+        params = np.empty(n, np.float32)
+        lists = np.empty((nc.value, ecap.value), np.int32)
+        _check(lib().svf_model_get(self.h, None, None, _p(params), n, _p(lists), lists.size))
+        return params, lists
 
     def model_fit(self, train_queries, k: int, beam: int, n_clusters: int = 64, epochs: int = 10):
         q = np.ascontiguousarray(train_queries, dtype=np.float32).reshape(-1, self.dim)

@@ -750,6 +750,9 @@ int search_impl(svf_index* ix, const float* d_q, int64_t nq, int k, int beam, in
   a.queries = d_q;
   a.qstride = ix->dim;
   a.nq = (int)nq;
+  // the totals start at zero before any kernel of this batch counts into them
+  // (the gating below counts its fallbacks)
+  CK(svf::launch_fill_u32(tot, 6, 0u, st));
   if (ix->opt.use_model && ix->model) {
     float* z;
     int32_t *qe, *qm;
@@ -780,7 +783,6 @@ int search_impl(svf_index* ix, const float* d_q, int64_t nq, int k, int beam, in
     a.tier_counts = cnt;
     CK(svf::launch_fill_u32(cnt, 4, 0u, st));
   }
-  CK(svf::launch_fill_u32(tot, 6, 0u, st));
   CK(svf::launch_query_keys(d_q, ix->dim, nullptr, ix->dim, a.nq, ix->opt.seed, qkey, st));
   a.qkey = qkey;
   CK(hipEventRecord(ix->ev0, st));
@@ -1560,6 +1562,9 @@ int svf_set_option(svf_index* ix, const char* key, double v) {
   } else if (k == "model_stop_scale") {
     if (v <= 0 || v > 1e6) return fail(SVF_E_INVAL, "model_stop_scale > 0");
     o.model_stop_scale = v;
+  } else if (k == "model_entries") {
+    if (v != 0 && v != 1) return fail(SVF_E_INVAL, "model_entries 0 or 1");
+    o.model_entries = (int)v;
   } else if (k == "model_min_iters") {
     if (!is_int(v) || v < 1 || v > 1e9) return fail(SVF_E_INVAL, "model_min_iters >= 1");
     o.model_min_iters = (int)v;
@@ -1608,6 +1613,7 @@ int svf_get_option(const svf_index* ix, const char* key, double* out) {
   else if (k == "model_conf") *out = o.model_conf;
   else if (k == "model_stop_scale") *out = o.model_stop_scale;
   else if (k == "model_min_iters") *out = o.model_min_iters;
+  else if (k == "model_entries") *out = o.model_entries;
   else return fail(SVF_E_INVAL, "unknown option " + k);
   return SVF_OK;
 }
@@ -1775,6 +1781,83 @@ int svf_search_listed(svf_index* ix, const float* queries, int64_t nq, int32_t k
   return SVF_OK;
 }
 
+int svf_search_trace(svf_index* ix, const float* queries, int64_t nq, int32_t k, int32_t beam,
+                     int32_t* out_ids, float* out_dists, int32_t* out_last_change) {
+  if (ix && ix->server) return fail(SVF_E_BUSY, "index is serving: stop serving first");
+  int rc = check_search_args(ix, nq, k, beam);
+  if (rc) return rc;
+  if (nq == 0) return SVF_OK;
+  if (!queries || !out_ids || !out_dists || !out_last_change) return fail(SVF_E_INVAL, "null buffer");
+  if (!all_finite(queries, nq * ix->dim)) return fail(SVF_E_INVAL, "non-finite query value");
+  std::lock_guard<std::mutex> g(ix->mu);
+  hipStream_t st = ix->stream;
+  float *dq, *dd;
+  int32_t *di, *dl;
+  uint64_t* qkey;
+  if ((rc = scratch(ix->s_q, (size_t)nq * ix->dim, &dq)) || (rc = scratch(ix->s_ids, (size_t)nq * k, &di)) ||
+      (rc = scratch(ix->s_d, (size_t)nq * k, &dd)) || (rc = scratch(ix->s_misc[1], nq, &dl)) ||
+      (rc = scratch(ix->s_qkey, nq, &qkey)))
+    return rc;
+  CK(hipMemcpyAsync(dq, queries, (size_t)nq * ix->dim * 4, hipMemcpyHostToDevice, st));
+  if (ix->n_slots == 0) {
+    CK(svf::launch_fill_u32(di, nq * k, 0xffffffffu, st));
+    CK(svf::launch_fill_u32(dd, nq * k, 0x7f800000u, st));
+    CK(svf::launch_fill_u32(dl, nq, 0u, st));
+  } else {
+    svf::SearchArgs a = base_args(ix);
+    set_beam(a, ix, beam);
+    a.k = k;
+    a.queries = dq;
+    a.qstride = ix->dim;
+    a.nq = (int)nq;
+    a.out_ids = di;
+    a.out_d = dd;
+    a.last_change = dl;
+    CK(svf::launch_query_keys(dq, ix->dim, nullptr, ix->dim, a.nq, ix->opt.seed, qkey, st));
+    a.qkey = qkey;
+    CK(svf::launch_search(a, ix->veclp_prec, st));
+  }
+  CK(hipMemcpyAsync(out_ids, di, (size_t)nq * k * 4, hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(out_dists, dd, (size_t)nq * k * 4, hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(out_last_change, dl, (size_t)nq * 4, hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  return SVF_OK;
+}
+
+int svf_model_get(const svf_index* cix, int32_t* n_clusters, int32_t* entry_cap, float* params,
+                  int64_t params_cap, int32_t* entry_lists, int64_t lists_cap) {
+  if (!cix) return fail(SVF_E_INVAL, "null index");
+  svf_index* ix = const_cast<svf_index*>(cix);
+  std::lock_guard<std::mutex> g(ix->mu);
+  if (!ix->model) return fail(SVF_E_NOTFOUND, "no trained predictor: call svf_model_fit first");
+  const svf::MlpDims& d = ix->model->dims();
+  if (n_clusters) *n_clusters = ix->model_nc;
+  if (entry_cap) *entry_cap = ix->entry_cap;
+  if (params) {
+    if (params_cap < d.total()) return fail(SVF_E_INVAL, "params_cap below the parameter count");
+    CK(hipStreamSynchronize(ix->stream));
+    CK(ix->model->get_params(params, ix->stream));
+    // the forward pass multiplies by the weights rounded to BF16 (nearest even)
+    auto rnd = [](float& x) {
+      uint32_t u;
+      std::memcpy(&u, &x, 4);
+      u += 0x7fffu + ((u >> 16) & 1u);
+      u &= 0xffff0000u;
+      std::memcpy(&x, &u, 4);
+    };
+    for (int64_t i = d.o_w1(); i < d.o_b1(); ++i) rnd(params[i]);
+    for (int64_t i = d.o_w2(); i < d.o_b2(); ++i) rnd(params[i]);
+    for (int64_t i = d.o_w3(); i < d.o_b3(); ++i) rnd(params[i]);
+  }
+  if (entry_lists) {
+    const int64_t n = (int64_t)ix->model_nc * ix->entry_cap;
+    if (lists_cap < n) return fail(SVF_E_INVAL, "lists_cap below n_clusters * entry_cap");
+    CK(hipStreamSynchronize(ix->stream));
+    CK(hipMemcpy(entry_lists, ix->entry_lists.as<int32_t>(), n * 4, hipMemcpyDeviceToHost));
+  }
+  return SVF_OK;
+}
+
 int svf_model_fit(svf_index* ix, const float* train_queries, int64_t n, int32_t k, int32_t beam,
                   int32_t n_clusters, int32_t epochs, float* last_loss) {
   if (ix && ix->server) return fail(SVF_E_BUSY, "index is serving: stop serving first");
@@ -1826,14 +1909,16 @@ int svf_model_fit(svf_index* ix, const float* train_queries, int64_t n, int32_t 
   CK(svf::assign_rows(ix->vec32, ix->stride, dim, ids, n, k, cent, nc, labels, st));
   CK(svf::launch_log_steps(lcg, n, lstop, st));
   CK(hipStreamSynchronize(st));
-  // 4. per-cluster entry lists: the nearest alive vectors to each centroid
+  // 4. per-cluster entry lists: spread over the cluster, or nearest to its centroid
   int32_t* el;
   float* eld;
   uint64_t* ckey;
   if ((rc = scratch(ix->entry_lists, (size_t)nc * ecap, &el)) ||
       (rc = scratch(ix->s_misc[4], (size_t)nc * ecap, &eld)) || (rc = scratch(ix->s_misc[5], nc, &ckey)))
     return rc;
-  {
+  if (ix->opt.model_entries == 1) {
+    CK(svf::launch_spread_entries(sassign, ns, step, ix->alive, nc, ecap, el, st));
+  } else {
     svf::SearchArgs c = base_args(ix);
     set_beam(c, ix, std::max(2 * ecap, beam));
     c.k = ecap;

@@ -82,6 +82,7 @@ struct Options {
   double model_conf = 0.5;
   double model_stop_scale = 1.5;
   int model_min_iters = 8;
+  int model_entries = 1;        // 1: spread over the cluster, 0: nearest to the centroid
 };
 
 }  // namespace svf

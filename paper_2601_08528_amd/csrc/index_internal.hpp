@@ -43,6 +43,7 @@ int bg_merge(svf_index* ix);
 svf::SearchArgs base_args(const svf_index* ix);
 void set_beam(svf::SearchArgs& a, const svf_index* ix, int L);
 int check_search_args(const svf_index* ix, int64_t nq, int k, int beam);
+
 bool all_finite(const float* p, int64_t n);
 int beam_insert(const svf_index* ix);
 void serve_shutdown(svf_index* ix);

@@ -277,6 +277,55 @@ hipError_t kmeans(const float* x, int64_t n, int64_t stride, int dim, int nc, in
   return e != hipSuccess ? e : e2;
 }
 
+// Entry lists spread over each cluster: one wave per cluster walks the
+// clustered sample (row i of the sample is stored vector i * step) in order,
+// counts the cluster's alive members m, and keeps the members of rank
+// floor(j * m / ecap), j = 0..ecap-1 (all of them, -1 padded, when m < ecap).
+// Sample order is id order, and ids follow no cluster, so the kept members
+// are spread over every part of the cluster in proportion to its size.
+__global__ __launch_bounds__(64) void spread_entries_kernel(const int32_t* __restrict__ assign,
+                                                           int64_t ns, int64_t step,
+                                                           const uint32_t* __restrict__ alive,
+                                                           int ecap, int32_t* __restrict__ lists) {
+  const int c = blockIdx.x;
+  const int lane = threadIdx.x;
+  int32_t* out = lists + (int64_t)c * ecap;
+  int64_t m = 0;
+  for (int64_t i0 = 0; i0 < ns; i0 += 64) {
+    const int64_t i = i0 + lane;
+    const bool mem = i < ns && assign[i] == c && alive_bit(alive, (int32_t)(i * step));
+    m += __popcll(__ballot(mem));
+  }
+  for (int j = lane; j < ecap; j += 64) out[j] = -1;
+  __syncthreads();
+  int64_t r0 = 0;
+  for (int64_t i0 = 0; i0 < ns; i0 += 64) {
+    const int64_t i = i0 + lane;
+    const bool mem = i < ns && assign[i] == c && alive_bit(alive, (int32_t)(i * step));
+    const uint64_t b = __ballot(mem);
+    if (mem) {
+      const int64_t r = r0 + __popcll(b & ((1ull << lane) - 1ull));
+      if (m <= ecap) {
+        out[r] = (int32_t)(i * step);
+      } else {
+        // the j with floor(j * m / ecap) == r, if any
+        const int64_t j = (r * ecap + m - 1) / m;
+        if (j < ecap && (j * m) / ecap == r) out[j] = (int32_t)(i * step);
+      }
+    }
+    r0 += __popcll(b);
+  }
+}
+
+hipError_t launch_spread_entries(const int32_t* assign, int64_t ns, int64_t step,
+                                 const uint32_t* alive, int nc, int ecap, int32_t* lists,
+                                 hipStream_t st) {
+  if (nc <= 0) return hipSuccess;
+  hipLaunchKernelGGL(spread_entries_kernel, dim3(nc), dim3(64), 0, st, assign, ns, step, alive, ecap,
+                     lists);
+  return hipGetLastError();
+}
+
 __global__ void log_steps_kernel(const int32_t* s, int64_t n, float* out) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) out[i] = logf((float)(s[i] > 1 ? s[i] : 1));

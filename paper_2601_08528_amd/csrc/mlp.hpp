@@ -85,6 +85,11 @@ hipError_t kmeans(const float* x, int64_t n, int64_t stride, int dim, int nc, in
 // assign[i] = nearest centroid of row ids[i] of x (stride), ids -1 -> -1
 hipError_t assign_rows(const float* x, int64_t stride, int dim, const int32_t* ids, int64_t n,
                        int id_step, const float* centroids, int nc, int32_t* assign, hipStream_t st);
+// Per cluster, ecap entry ids spread over its alive members in the clustered
+// sample (sample row i = stored vector i * step), -1 padded.
+hipError_t launch_spread_entries(const int32_t* assign, int64_t ns, int64_t step,
+                                 const uint32_t* alive, int nc, int ecap, int32_t* lists,
+                                 hipStream_t st);
 // log(max(1, steps)) as FP32
 hipError_t launch_log_steps(const int32_t* steps, int64_t n, float* out, hipStream_t st);
 

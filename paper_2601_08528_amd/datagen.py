@@ -312,3 +312,42 @@ def request_stream(n_rounds: int, insert_batch: int, delete_batch: int,
                 size = max(1, min(max_query, size))
             reqs.append(Request(kind, size, t))
     return reqs
+
+
+# ----------------------------------------------------------------------------
+# Large imported graphs: integer points along a folded random walk, with rows
+# that mix walk neighbours and uniform long links.
+# ----------------------------------------------------------------------------
+def walk_graph_uint8(workload: int, n: int, dim: int, R: int, n_query: int, step: int = 3,
+                     window: int | None = None):
+    """Points x_i: a random walk in Z^dim with steps uniform in [-step, step],
+    folded into 0..255 (reflection at 0 and 255), so ids close in order lie
+    close in space.  Row i: R/2 ids at offsets +-1, +-2, ... (mod n) and R - R/2
+    distinct uniform ids (no self, no repeats).  Queries: walk points of
+    uniform ids plus integer noise in [-4, 4], clipped to 0..255.  Every value
+    is an integer, stored FP32.  Returns base, rows (n x R int32), queries."""
+    g = rng(workload, ROLE_BASE)
+    walk = np.cumsum(g.integers(-step, step + 1, size=(n, dim), dtype=np.int64), axis=0)
+    walk += 128
+    walk %= 510
+    base = np.where(walk > 255, 510 - walk, walk).astype(np.float32)
+    half = R // 2
+    offs = np.array([s * (j // 2 + 1) for j, s in zip(range(half), [1, -1] * half)], np.int64)
+    ids = np.arange(n, dtype=np.int64)
+    rows = np.empty((n, R), np.int64)
+    rows[:, :half] = (ids[:, None] + offs[None, :]) % n
+    gr = rng(workload, ROLE_SHAPE)
+    far = gr.integers(0, n, size=(n, R - half), dtype=np.int64)
+    while True:
+        rows[:, half:] = far
+        srt = np.sort(rows, axis=1)
+        bad = (np.diff(srt, axis=1) == 0).any(axis=1) | (rows == ids[:, None]).any(axis=1)
+        nb = int(bad.sum())
+        if nb == 0:
+            break
+        far[bad] = gr.integers(0, n, size=(nb, R - half), dtype=np.int64)
+    gq = rng(workload, ROLE_QUERIES)
+    pick = gq.integers(0, n, size=n_query)
+    q = base[pick] + gq.integers(-4, 5, size=(n_query, dim)).astype(np.float32)
+    np.clip(q, 0, 255, out=q)
+    return np.ascontiguousarray(base), rows.astype(np.int32), np.ascontiguousarray(q)

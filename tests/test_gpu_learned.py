@@ -118,3 +118,84 @@ def test_learned_form_gain_over_plain():
     g.set_option("use_model", 0)
     print("recall@10 at beam", beam, "plain", plain, "learned entries", learned)
     assert learned >= plain + 0.02
+
+
+@pytest.mark.parametrize("width", [1, 2])
+def test_search_trace_labels_match_oracle(width):
+    """The stop labels the predictor trains on: per query, the iteration
+    after which the top-k ids last changed, from the GPU's plain search and
+    from the oracle's, on integer-valued data (every distance exact)."""
+    base, q = datagen.gmm_uint8_valued(507, 6000, 150, 128, 24)
+    oix = oracle_index(base, 32, seed=7)
+    oix.set("search_width", width)
+    g = gpu_from_oracle(oix, base, seed=7, search_width=width)
+    for k, beam in ((10, 16), (10, 64), (1, 32)):
+        oi, olc = oix.search_trace(q, k, beam)
+        gi, gd, glc = g.search_trace(q, k, beam)
+        np.testing.assert_array_equal(gi, oi)
+        np.testing.assert_array_equal(glc, olc)
+    assert (olc > 0).mean() > 0.5
+
+
+def _near_integer(x, rel):
+    return np.abs(x - np.rint(x)) <= rel * np.maximum(1.0, np.abs(x))
+
+
+def test_learned_search_replays_through_the_oracle():
+    """use_model = 1 end to end: the GPU-trained predictor is exported, its
+    outputs z (computed by the same kernels) go through the oracle's gating
+    rule (argmax cluster, softmax confidence against the threshold, cap
+    max(min_iters, ceil(scale * exp(z_stop)))), and the oracle's listed-entry
+    search with those entries and caps must return the GPU's ids and
+    distances bit for bit.  Queries whose gating sits within 1e-5 (relative)
+    of a decision boundary, where FP32 and FP64 may round the rule's own
+    arithmetic apart, are set aside; they must be few."""
+    base, q = datagen.gmm_uint8_valued(506, 12_000, 600, 64, 32)
+    train = datagen.training_queries_uint8(506, 4096, 64, 32)
+    oix = oracle_index(base, 24, seed=6)
+    g = gpu_from_oracle(oix, base, seed=6)
+    g.model_fit(train, 10, 32, n_clusters=16, epochs=4)
+    params, lists = g.model_get()
+    assert lists.shape[0] == 16 and (lists >= -1).all() and (lists < 12_000).all()
+    m = svf.Mlp(64, 256, 16)
+    m.set_params(params)
+    z = m.forward(q).astype(np.float64)
+    nc = 16
+    zc = z[:, :nc]
+    zs = np.sort(zc, axis=1)
+    p = 1.0 / np.exp(zc - zs[:, -1:]).sum(axis=1)
+    # the threshold: the middle of the widest gap between consecutive
+    # confidences among the middle 60% of queries, so that between 20% and
+    # 80% of them fall back and none sits next to the threshold
+    ps = np.sort(p)
+    lo, hi = int(0.2 * len(ps)), int(0.8 * len(ps))
+    j = lo + int(np.argmax(np.diff(ps[lo:hi + 1])))
+    conf = float(0.5 * (ps[j] + ps[j + 1]))
+    scale, min_iters = 1.0, 4
+    qe, qm = O.model_decide(z, conf, scale, min_iters)
+    assert 0.2 <= (qe < 0).mean() <= 0.8
+    capv = scale * np.exp(np.minimum(z[:, nc], 20.0))
+    c1 = (zs[:, -1] - zs[:, -2]) > 1e-5 * np.maximum(1.0, np.abs(zs[:, -1]))
+    c2 = np.abs(p - conf) > 1e-5 * conf
+    # the ceiling decides the cap only above min_iters, and a cap above the
+    # number of alive vectors never binds (each expansion takes a new vertex)
+    c3 = ~_near_integer(capv, 1e-5) | (capv < min_iters - 0.5) | (capv > 12_001)
+    safe = c1 & c2 & c3
+    assert safe.mean() > 0.9, (c1.mean(), c2.mean(), c3.mean(), ps[::60], conf)
+    qs = q[safe]
+    ent = np.where(qe[safe, None] >= 0, lists[np.maximum(qe[safe], 0)], -1).astype(np.int32)
+    g.set_option("use_model", 1)
+    g.set_option("model_conf", conf)
+    g.set_option("model_stop_scale", scale)
+    g.set_option("model_min_iters", min_iters)
+    for beam in (16, 48):
+        oi, od, _ = oix.search_listed(qs, 10, beam, ent, qm[safe])
+        gi, gd = g.search(qs, 10, beam)
+        np.testing.assert_array_equal(gi, oi)
+        np.testing.assert_array_equal(gd.astype(np.float64), od)
+        assert g.stats()["last_model_fallback"] == int((qe[safe] < 0).sum())
+    gated = safe & (qe >= 0)
+    assert (qm[gated] > 0).all()                       # gated queries run with a cap
+    print("gated %d, of which capped below 12000 expansions: %d; fallback %d"
+          % (gated.sum(), (qm[gated] <= 12_000).sum(), (safe & (qe < 0)).sum()))
+    g.set_option("use_model", 0)

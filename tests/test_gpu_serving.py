@@ -1,10 +1,12 @@
 """Serving loop: every search in a concurrent mix of searches, inserts and
 deletes returns exactly what the same search returns alone against the
-state of its epoch, replayed one request at a time; reads after a waited-for
+state of its epoch, replayed one request at a time on the GPU and through
+the FP64 oracle; reads after a waited-for
 insert see the insert; admission refuses what can never fit."""
 import numpy as np
 import pytest
 
+import oracle as O
 import paper_2601_08528_amd as svf
 from paper_2601_08528_amd import datagen
 
@@ -54,9 +56,12 @@ def test_mix_equals_alone_replay():
             tickets.append((served.submit_delete(data), kind, data, None, None))
     infos = [served.wait(t[0], 120.0) for t in tickets]
     served.serve_stop()
-    # replay: mutations in arrival order; each search alone at its epoch
+    # replay: mutations in arrival order; each search alone at its epoch, on
+    # the GPU and through the FP64 oracle (integer-valued data: every
+    # distance is exact, so the oracle's results must be equal bit for bit)
     alone = make(build)
-    epoch = 0
+    orc = O.OracleIndex(64, 24, O.L2, seed=3, insert_batch_max=512)
+    orc.build(build, batch_max=512)
     mut = [(i, t) for i, t in enumerate(tickets) if t[1] != "search"]
     srch = [(i, t) for i, t in enumerate(tickets) if t[1] == "search"]
     by_epoch = {}
@@ -68,16 +73,26 @@ def test_mix_equals_alone_replay():
             ids, d = alone.search(t[2], 10, 32)
             np.testing.assert_array_equal(ids, t[3])
             np.testing.assert_array_equal(d, t[4])
+            oi, od, _ = orc.search(t[2], 10, 32)
+            np.testing.assert_array_equal(t[3], oi)
+            np.testing.assert_array_equal(t[4].astype(np.float64), od)
             checked += 1
         if e < len(mut):
             i, t = mut[e]
             assert infos[i]["epoch"] == e + 1
             if t[1] == "insert":
                 np.testing.assert_array_equal(alone.insert(t[2]), t[3])
+                np.testing.assert_array_equal(orc.insert(t[2]), t[3])
             else:
                 alone.delete(t[2])
+                orc.delete(t[2])
     assert checked == len(srch)
     np.testing.assert_array_equal(served.export_graph()[0], alone.export_graph()[0])
+    orows, oed, oal = orc.export()
+    grows, ged, gal = served.export_graph()
+    np.testing.assert_array_equal(gal, oal)
+    np.testing.assert_array_equal(grows, orows)
+    np.testing.assert_array_equal(ged.astype(np.float64), oed)
     assert max(inf["batch_queries"] for inf in infos) > 1
 
 
