@@ -226,6 +226,24 @@ int svf_search_dev(svf_index *ix, const float *d_queries, int64_t nq, int32_t k,
                    int32_t *d_out_ids, float *d_out_dists, int32_t *d_n_dist, int32_t *d_n_exp,
                    void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * search as svf_search_dev, with the same arguments, outputs and stream
+ * semantics, that calls no hipMalloc, hipFree or other allocating routine.
+ * Its only workspace, one 8-byte entry-stream key per query, lives in a
+ * fixed 4 MiB array of device memory that every GPU the library runs on
+ * holds until the process ends, so nq is limited to 524,288 (SVF_E_INVAL
+ * beyond).  All calls on one GPU share that array, across indexes: calls
+ * that overlap on one GPU (on different streams, or from different threads)
+ * race on it and must be ordered by the caller.  Refused with SVF_E_INVAL
+ * when the learned form (use_model) or a tiered store is on, since those
+ * need more workspace; the batch totals that svf_stats_get reports
+ * (last_n_dist, last_n_exp) are not updated by this call (the per-query
+ * counts d_n_dist / d_n_exp are). */
+int svf_search_dev_noalloc(svf_index *ix, const float *d_queries, int64_t nq, int32_t k,
+                           int32_t beam, int32_t *d_out_ids, float *d_out_dists,
+                           int32_t *d_n_dist, int32_t *d_n_exp, void *stream);
+
 /* Learned entry points and stopping step (an extension of the method: the
  * paper starts from random entry points, Sec. 4.2, and notes that entry
  * points may come from a separate algorithm, Sec. 2.3).  Trains, on the GPU,

@@ -29,7 +29,7 @@ EXPORTED = [
     "svf_mlp_loss_grad", "svf_mlp_train", "svf_mlp_last_error",
     "svf_serve_start", "svf_serve_stop", "svf_submit_search", "svf_submit_insert",
     "svf_submit_delete", "svf_wait", "svf_save", "svf_load", "svf_cache_slots",
-    "svf_cache_calibrate",
+    "svf_cache_calibrate", "svf_search_dev_noalloc",
 ]
 
 
@@ -87,6 +87,7 @@ def lib():
         L.svf_consolidate_wait.argtypes = [vp]
         L.svf_search.argtypes = [vp, vp, i64, i32, i32, vp, vp]
         L.svf_search_dev.argtypes = [vp, vp, i64, i32, i32, vp, vp, vp, vp, vp]
+        L.svf_search_dev_noalloc.argtypes = [vp, vp, i64, i32, i32, vp, vp, vp, vp, vp]
         L.svf_stats_get.argtypes = [vp, C.POINTER(Stats)]
         L.svf_export_graph.argtypes = [vp, vp, vp, vp, i64]
         L.svf_import_graph.argtypes = [vp, vp, i64, vp, vp, vp]
@@ -197,6 +198,12 @@ class Index:
                    d_n_dist: int | None = None, d_n_exp: int | None = None, stream: int | None = None):
         _check(lib().svf_search_dev(self.h, d_queries, nq, k, beam, d_ids, d_dists, d_n_dist,
                                     d_n_exp, stream))
+
+    def search_dev_noalloc(self, d_queries: int, nq: int, k: int, beam: int, d_ids: int,
+                           d_dists: int, d_n_dist: int | None = None, d_n_exp: int | None = None,
+                           stream: int | None = None):
+        _check(lib().svf_search_dev_noalloc(self.h, d_queries, nq, k, beam, d_ids, d_dists,
+                                            d_n_dist, d_n_exp, stream))
 
     def search_listed(self, queries, k: int, beam: int, entries, max_iters=None):
         q = np.ascontiguousarray(queries, dtype=np.float32).reshape(-1, self.dim)

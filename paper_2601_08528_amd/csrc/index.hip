@@ -730,12 +730,13 @@ int bg_merge(svf_index* ix) {
 }
 
 int search_impl(svf_index* ix, const float* d_q, int64_t nq, int k, int beam, int32_t* d_ids,
-                float* d_d, int32_t* d_nd, int32_t* d_ne, hipStream_t st) {
+                float* d_d, int32_t* d_nd, int32_t* d_ne, hipStream_t st, uint64_t* ws_qkey) {
   if (nq == 0) return SVF_OK;
-  uint64_t* qkey;
-  unsigned long long* tot;
+  uint64_t* qkey = ws_qkey;
+  unsigned long long* tot = nullptr;   // batch totals are kept only with the index's own buffers
   int rc;
-  if ((rc = scratch(ix->s_qkey, nq, &qkey)) || (rc = scratch(ix->s_tot, 3, &tot))) return rc;
+  if (!ws_qkey && ((rc = scratch(ix->s_qkey, nq, &qkey)) || (rc = scratch(ix->s_tot, 3, &tot))))
+    return rc;
   if (ix->n_slots == 0) {
     // nothing indexed: every result is padding
     CK(svf::launch_fill_u32(d_ids, nq * k, 0xffffffffu, st));
@@ -752,8 +753,9 @@ int search_impl(svf_index* ix, const float* d_q, int64_t nq, int k, int beam, in
   a.nq = (int)nq;
   // the totals start at zero before any kernel of this batch counts into them
   // (the gating below counts its fallbacks)
-  CK(svf::launch_fill_u32(tot, 6, 0u, st));
+  if (tot) CK(svf::launch_fill_u32(tot, 6, 0u, st));
   if (ix->opt.use_model && ix->model) {
+    if (ws_qkey) return fail(SVF_E_INVAL, "the learned form needs the index's own workspace");
     float* z;
     int32_t *qe, *qm;
     if ((rc = scratch(ix->s_z, (size_t)nq * (ix->model_nc + 1), &z)) ||
@@ -774,6 +776,7 @@ int search_impl(svf_index* ix, const float* d_q, int64_t nq, int k, int beam, in
   a.n_exp = d_ne;
   a.totals = tot;
   if (ix->tier.on) {
+    if (ws_qkey) return fail(SVF_E_INVAL, "the tiered store needs the index's own workspace");
     svf::TierState& T = ix->tier;
     unsigned long long* cnt;
     if ((rc = scratch(T.trace, (size_t)nq * T.trace_cap, &a.trace)) ||

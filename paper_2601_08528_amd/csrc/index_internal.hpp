@@ -43,7 +43,13 @@ int bg_merge(svf_index* ix);
 svf::SearchArgs base_args(const svf_index* ix);
 void set_beam(svf::SearchArgs& a, const svf_index* ix, int L);
 int check_search_args(const svf_index* ix, int64_t nq, int k, int beam);
-
+// Search of nq device-resident queries on stream st.  ws_qkey (nq words of
+// device memory) replaces the index's own key buffer when given; the batch
+// totals are then not kept, and the learned form and the tiered store, which
+// need more workspace, are refused.
+int search_impl(svf_index* ix, const float* d_q, int64_t nq, int k, int beam, int32_t* d_ids,
+                float* d_d, int32_t* d_nd, int32_t* d_ne, hipStream_t st,
+                uint64_t* ws_qkey = nullptr);
 bool all_finite(const float* p, int64_t n);
 int beam_insert(const svf_index* ix);
 void serve_shutdown(svf_index* ix);
