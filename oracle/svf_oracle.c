@@ -32,6 +32,7 @@
  * per-query stream key, and SplitMix64 (Steele, Lea, Flood, OOPSLA 2014)
  * whose j-th output from state s is mix(s + (j+1) * golden-gamma).
  */
+#include <limits.h>
 #include <math.h>
 #include <pthread.h>
 #include <stdint.h>
@@ -190,7 +191,7 @@ orc_index *orc_create(int dim, int R, int metric, uint64_t seed)
     ix->max_iters = 0;
     ix->repair_c = 8;
     ix->localized_repair = 1;
-    ix->prune_cap = 0;   /* 0: max(4R, beam_insert) */
+    ix->prune_cap = 0;   /* 0: no cap */
     ix->precision = ORC_P_FP32;
     ix->consolidate_frac = 0.2;
     ix->insert_batch_max = 10000;
@@ -205,11 +206,13 @@ void orc_destroy(orc_index *ix)
     free(ix->log_rows); free(ix->log_d); free(ix);
 }
 
+/* Sec. 5.1 re-prunes a vertex's whole candidate list (its alive neighbours
+ * plus what the update offers it) and bounds no list length, so by default
+ * no candidate is cut.  A positive prune_cap keeps only that many nearest
+ * candidates (an option for experiments, not the method). */
 static int effective_prune_cap(const orc_index *ix)
 {
-    if (ix->prune_cap > 0) return ix->prune_cap;
-    int c = 4 * ix->R;
-    return ix->beam_insert > c ? ix->beam_insert : c;
+    return ix->prune_cap > 0 ? ix->prune_cap : INT_MAX;
 }
 
 int orc_set(orc_index *ix, const char *key, double v)
@@ -682,8 +685,8 @@ static int cmp_cand(const void *a, const void *b) { return cmp_pentry(a, b); }
  * insertion pool size (batch-mates do not see each other); its candidate list
  * is that final pool; its forward row is the pruned list.  Reverse edges: for
  * every old vertex n named by some forward row, the candidates are n's alive
- * neighbours (stored distances) plus the new vertices pointing at it, in
- * (d,id) order and cut to the prune cap; they are pruned with the pre-batch
+ * neighbours (stored distances) plus the new vertices pointing at it, all
+ * of them in (d,id) order; they are pruned with the pre-batch
  * rows of old vertices and the forward rows of new ones.  All rows are
  * committed together at the end of the batch. */
 typedef struct { int32_t v; double d; } incoming;
@@ -857,8 +860,8 @@ int orc_build(orc_index *ix, const float *vecs, int64_t n, int64_t batch_max)
  * (stored distances) and, for each deleted neighbour p in row order, the
  * first c entries of p's row that are alive, not v and not yet candidates.
  * If fewer than R candidates result, the pool of a search for v's own vector
- * (insertion pool size, same snapshot) tops them up.  Candidates are put in
- * (d,id) order, cut to the prune cap and pruned with the pre-repair rows.
+ * (insertion pool size, same snapshot) tops them up.  All candidates are put
+ * in (d,id) order and pruned with the pre-repair rows.
  * Consolidation uses the same routine with "at least one deleted neighbour"
  * and c = R.  It runs when the deleted fraction since the last consolidation
  * reaches consolidate_frac (the paper's example threshold is 20%). */
@@ -961,8 +964,8 @@ static void repair(orc_index *ix, int consolidate)
  * snapshot's in order).  The merge writes the staged rows, then re-prunes
  * every rewritten row that the logged rows name, with the candidates a
  * reverse-edge update uses (its alive entries with their stored distances,
- * then the logged vertices pointing at it, in (d,id) order, cut to the prune
- * cap), against the rows as they stand after the first step; all re-pruned
+ * then the logged vertices pointing at it, all in (d,id) order), against
+ * the rows as they stand after the first step; all re-pruned
  * rows are written at the end.  Other rows keep their live state. */
 static void bg_begin(orc_index *ix)
 {

@@ -290,6 +290,27 @@ def test_repair_and_consolidate_hand_worked():
         assert not set(rows[u].tolist()) & {1, 2}
 
 
+def test_whole_candidate_list_is_pruned_hand_worked():
+    """A consolidation list of 25 candidates (degree 5) whose farthest one
+    has no detour: it is kept because the list is pruned whole; a list cut
+    to its 20 nearest (4R, the experiment option prune_cap) would keep a
+    nearer candidate instead."""
+    g = load("uncut_list_example.json")
+    for cap, key in ((0, "expect_row0"), (g["cut"], "expect_row0_cut")):
+        ix = _import(g)
+        ix.set("localized_repair", 0)
+        ix.set("prune_cap", cap)
+        assert ix.delete(g["delete"]) == 0
+        rows, ed, alive = ix.export()
+        assert rows[0].tolist() == g["rows"][0]       # nothing rewritten yet
+        ix.consolidate()
+        rows, ed, alive = ix.export()
+        assert rows[0].tolist() == g[key]
+        assert ed[0].tolist() == g[key + "_d"]
+        for u in range(6, 31):                         # rows without a deleted neighbour stay
+            assert rows[u].tolist() == g["rows"][u]
+
+
 # --- insert / delete properties ----------------------------------------------------
 def test_insert_properties_and_delete_invariants():
     base, q = datagen.gmm_uint8_valued(96, 900, 30, 16, 6)
