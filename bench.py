@@ -302,7 +302,9 @@ def stream_recall_of(torch, ids, vecs, q, kth, alive):
     got = np.where(ids >= 0, ids, 0)
     g_t = torch.from_numpy(np.ascontiguousarray(vecs[got.ravel()].reshape(got.shape + (-1,)))).cuda()
     prod = (g_t.double() * q_t.double()[:, None, :]).sum(-1)
-    ok = (prod >= kth[:, None]) & torch.from_numpy(ids >= 0).cuda()
+    # kth comes from an FP64 GEMM, prod from an element-wise sum: the two may
+    # round the same product apart in the last bits
+    ok = (prod >= kth[:, None] - 1e-12) & torch.from_numpy(ids >= 0).cuda()
     alive_t = torch.from_numpy(alive[got.ravel()].reshape(got.shape).astype(bool)).cuda()
     ok &= alive_t
     return float(ok.double().sum().item() / (10 * q.shape[0]))

@@ -77,6 +77,8 @@ typedef struct svf_stats {
     int64_t consolidations;         /* global consolidations done (a background one once merged) */
     int64_t last_model_fallback;    /* last search with use_model: queries below model_conf that
                                        ran plain search */
+    int64_t long_lists;             /* candidate lists so far too long for the one-wave LDS
+                                       prune, pruned whole by the long-list kernels */
 } svf_stats;
 
 /* Create an empty index.  Sec. 2.3: a directed graph with a fixed number of
@@ -105,7 +107,9 @@ int svf_destroy(svf_index *ix);
  *   visited_compact exact quotient tags of a scrambled id (12-bit, five per 64-bit set, or
  *                   16-bit, four per set) instead of full 32-bit ids, when the ids fit (0/1; 1)
  *   repair_c        out-neighbours taken from each deleted neighbour (1..min(16, degree); 8)
- *   prune_cap       longest candidate list given to the prune, 0 = max(4*degree, beam_insert)
+ *   prune_cap       0 (the method): every candidate list is pruned whole (Sec. 5.1, 5.2),
+ *                   up to 16384 candidates per list; > 0: an experiment that cuts each list to
+ *                   its prune_cap nearest candidates first (0..; 0)
  *   consolidate_frac deleted fraction that triggers consolidation ([0,1]; 0.2; 0 = never)
  *   localized_repair repair the affected vertices after each deletion (0/1; 1).  With 0
  *                   and consolidate_frac 0 deletion is lazy only (the paper's ablation)

@@ -58,6 +58,7 @@ class Stats(C.Structure):
         ("cache_last_placed", C.c_int64), ("cache_promotions", C.c_int64),
         ("cache_evictions", C.c_int64),
         ("consolidations", C.c_int64), ("last_model_fallback", C.c_int64),
+        ("long_lists", C.c_int64),
     ]
 
     def as_dict(self):

@@ -48,9 +48,121 @@ int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 int beam_insert(const svf_index* ix) {
   return ix->opt.beam_insert > 0 ? ix->opt.beam_insert : std::min(2 * ix->R, kMaxBeam);
 }
+// Candidates one wave prunes in LDS.  Longer lists go to the long-list
+// kernels (no list is cut), unless prune_cap is set: then every list is cut
+// to its prune_cap nearest candidates.  The LDS lists hold a top-up search
+// pool beside fewer than R candidates (R - 1 + beam_insert).
 int prune_cap(const svf_index* ix) {
   if (ix->opt.prune_cap > 0) return ix->opt.prune_cap;
-  return std::max(4 * ix->R, beam_insert(ix));
+  return std::max(4 * ix->R, ix->R + beam_insert(ix));
+}
+bool lists_uncut(const svf_index* ix) { return ix->opt.prune_cap == 0; }
+
+// ---- candidate lists longer than the LDS kernels hold ------------------------------
+constexpr int64_t kLongRoundKeys = (int64_t)1 << 24;   // raw keys per round of the long-list kernels
+
+// Lay out the long-list workspace for n lists of raw lengths len[] (host) and
+// point L at it; d_dst (device, n entries) names each list's output row.
+int long_layout(svf::LongScratch& s, const int32_t* len, int n, const int32_t* d_dst, int skip_m,
+                svf::LongLists* L, int64_t* hash_words, int64_t* cnt_words, int* max_len,
+                hipStream_t st) {
+  std::vector<int64_t> meta(3 * (size_t)n + 2);
+  int64_t* off = meta.data();
+  int64_t* hoff = off + n + 1;
+  int64_t* coff = hoff + n + 1;
+  off[0] = 0;
+  hoff[0] = 0;
+  int64_t c = 0;
+  int mx = 0;
+  for (int l = 0; l < n; ++l) {
+    off[l + 1] = off[l] + len[l];
+    int64_t S = 64;
+    while (S < 2 * (int64_t)len[l]) S <<= 1;
+    hoff[l + 1] = hoff[l] + 2 * S;
+    coff[l] = c;
+    c += 2 * (int64_t)len[l] + 1;
+    mx = std::max(mx, len[l]);
+  }
+  int64_t* dmeta;
+  uint64_t* keys;
+  uint32_t *hash, *cnt;
+  int32_t* m;
+  int rc;
+  if ((rc = scratch(s.meta, meta.size(), &dmeta)) || (rc = scratch(s.keys, (size_t)off[n], &keys)) ||
+      (rc = scratch(s.hash, (size_t)hoff[n], &hash)) || (rc = scratch(s.cnt, (size_t)c, &cnt)) ||
+      (rc = scratch(s.m, (size_t)n, &m)))
+    return rc;
+  CK(hipMemcpyAsync(dmeta, meta.data(), meta.size() * 8, hipMemcpyHostToDevice, st));
+  CK(hipStreamSynchronize(st));       // the host copy of the layout goes out of scope
+  L->n = n;
+  L->off = dmeta;
+  L->hoff = dmeta + n + 1;
+  L->coff = dmeta + 2 * (n + 1);
+  L->dst = d_dst;
+  L->keys = keys;
+  L->m = m;
+  L->hash = hash;
+  L->cnt = cnt;
+  L->skip_m = skip_m;
+  *hash_words = hoff[n];
+  *cnt_words = c;
+  *max_len = mx;
+  return SVF_OK;
+}
+
+// Split n lists of raw lengths len[] into consecutive rounds of at most
+// kLongRoundKeys raw keys; calls run(l0, l1) per round.
+template <class F>
+int long_rounds(const std::vector<int32_t>& len, F run) {
+  const int n = (int)len.size();
+  for (int l0 = 0; l0 < n;) {
+    int l1 = l0;
+    int64_t tot = 0;
+    while (l1 < n && (l1 == l0 || tot + len[l1] <= kLongRoundKeys)) tot += len[l1++];
+    int rc = run(l0, l1);
+    if (rc) return rc;
+    l0 = l1;
+  }
+  return SVF_OK;
+}
+
+// Reverse-edge prune of the n_targets staged targets: the LDS kernel for
+// every target, then the long-list kernels rewrite the targets whose alive
+// row entries plus incoming keys exceed its capacity.
+int reverse_prune_all(svf_index* ix, svf::ReverseArgs& ra, int n_targets, hipStream_t st) {
+  CK(svf::launch_reverse_prune(ra, n_targets, st));
+  if (n_targets <= 0 || !lists_uncut(ix)) return SVF_OK;
+  svf::LongScratch& s = ix->lrev;
+  int32_t* q;
+  int rc;
+  if ((rc = scratch(s.q, 2 * (size_t)n_targets + 1, &q))) return rc;
+  int32_t *qk = q, *qlen = q + n_targets, *nq = q + 2 * n_targets;
+  CK(svf::launch_fill_u32(nq, 1, 0u, st));
+  CK(svf::launch_reverse_long(ra, n_targets, ra.cap, qk, qlen, nq, st));
+  int32_t n_long = 0;
+  CK(hipMemcpyAsync(&n_long, nq, 4, hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  if (n_long == 0) return SVF_OK;
+  s.lists += n_long;
+  std::vector<int32_t> len(n_long);
+  CK(hipMemcpyAsync(len.data(), qlen, (size_t)n_long * 4, hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  for (int32_t x : len)
+    if (x > svf::kLongMaxKeys)
+      return fail(SVF_E_INVAL, "a vertex would take more than 16384 reverse-edge candidates from one "
+                               "insert batch: use smaller batches (insert_batch_max)");
+  svf::LongRows rows{ra.graph, ra.fwd_ids, ra.rows_below ? ra.rows_below : ra.n0, ra.R};
+  return long_rounds(len, [&](int l0, int l1) {
+    svf::LongLists L{};
+    int64_t hw, cw;
+    int mx;
+    int rc2 = long_layout(s, len.data() + l0, l1 - l0, qk + l0, 0, &L, &hw, &cw, &mx, st);
+    if (rc2) return rc2;
+    CK(svf::launch_reverse_gather(ra, qk + l0, L, st));
+    CK(svf::launch_long_sort(L, mx, st));
+    CK(svf::launch_long_prune(L, rows, ra.trow, ra.trow_d, hw, cw, st));
+    return (int)SVF_OK;
+  });
 }
 // Reduced-precision traversal store: FP16/BF16 rows of `stride` 2-byte
 // elements; FP8 rows of round_up(dim, 16) codes followed, after all cap rows,
@@ -318,7 +430,7 @@ int insert_prepare(svf_index* ix, const float* d_vecs, int64_t b, PendingInsert*
   svf::PruneArgs pa{};
   pa.cand = pool;
   pa.cstride = Lins;
-  pa.cap = prune_cap(ix);
+  pa.cap = Lins;                  // the whole insertion pool (prune_cap cuts only update lists)
   pa.graph = ix->graph;
   pa.fwd = nullptr;
   pa.n_old = (int32_t)n0;
@@ -359,7 +471,7 @@ int insert_prepare(svf_index* ix, const float* d_vecs, int64_t b, PendingInsert*
       (rc = scratch(ix->s_misc[8], (size_t)n_targets * R, &ra.trow_d)))
     return rc;
   CK(svf::launch_reverse_scan_scatter(ra, n_targets, st));
-  CK(svf::launch_reverse_prune(ra, n_targets, st));
+  if ((rc = reverse_prune_all(ix, ra, n_targets, st))) return rc;
   CK(hipEventRecord(ix->ev1, st));
   ix->st.ins_reverse_ms = elapsed(ix->ev0, ix->ev1);
   p->n_targets = n_targets;
@@ -429,6 +541,7 @@ struct RepairJob {
   const float* vec32;
   int64_t stride;
   int dim, metric, R, cap, c_local, Lins, prec;
+  bool uncut;                 // lists longer than cap go to the long-list kernels
   uint64_t seed;
   svf::SearchArgs proto;
 };
@@ -445,6 +558,7 @@ RepairJob repair_job(svf_index* ix) {
   j.metric = ix->metric;
   j.R = ix->R;
   j.cap = prune_cap(ix);
+  j.uncut = lists_uncut(ix);
   j.c_local = ix->opt.repair_c;
   j.Lins = beam_insert(ix);
   j.prec = ix->veclp_prec;
@@ -490,7 +604,7 @@ int repair_compute(const RepairJob& j, int consolidate, svf::RepairScratch& s, h
   CK(hipMemcpyAsync(&n_aff, cnt, 4, hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
   if (n_aff == 0) return SVF_OK;
-  int32_t *rows, *mcount, *topup, *topup_v;
+  int32_t *rows, *mcount, *topup, *topup_v, *over;
   float* rows_d;
   uint64_t* cand;
   const int64_t chunk = std::min<int64_t>(n_aff, 131072);
@@ -498,19 +612,54 @@ int repair_compute(const RepairJob& j, int consolidate, svf::RepairScratch& s, h
       (rc = scratch(s.rows_d, (size_t)n_aff * R, &rows_d)) ||
       (rc = scratch(s.cand, (size_t)chunk * cap, &cand)) ||
       (rc = scratch(s.mcount, chunk, &mcount)) || (rc = scratch(s.topup, chunk, &topup)) ||
-      (rc = scratch(s.topup_v, chunk, &topup_v)))
+      (rc = scratch(s.topup_v, chunk, &topup_v)) || (rc = scratch(s.lg.q, 2 * (size_t)chunk, &over)))
     return rc;
   a.cand = cand;
   a.mcount = mcount;
   a.topup = topup;
   a.topup_v = topup_v;
+  a.over_li = j.uncut ? over : nullptr;
+  a.over_len = over + chunk;
+  a.n_over = cnt + 2;
+  const svf::LongRows lrows{j.graph, nullptr, (int32_t)j.n_slots, R};
   for (int64_t first = 0; first < n_aff; first += chunk) {
     const int count = (int)std::min<int64_t>(chunk, n_aff - first);
-    CK(svf::launch_fill_u32(cnt + 1, 1, 0u, st));
+    CK(svf::launch_fill_u32(cnt + 1, 2, 0u, st));
     CK(svf::launch_repair_candidates(a, (int)first, count, st));
-    int32_t ntop = 0;
-    CK(hipMemcpyAsync(&ntop, cnt + 1, 4, hipMemcpyDeviceToHost, st));
+    int32_t hc[2] = {0, 0};
+    CK(hipMemcpyAsync(hc, cnt + 1, 8, hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
+    int32_t ntop = hc[0];
+    const int32_t n_over = hc[1];
+    if (n_over > 0) {
+      // lists that offered more keys than the LDS walk kept: the same walk
+      // again into the long-list staging area, sorted with repeats removed;
+      // those of at most cap candidates go back to the LDS prune (and the
+      // top-up when short), the others are pruned by the long-list kernels
+      s.lg.lists += n_over;
+      std::vector<int32_t> len(n_over);
+      CK(hipMemcpyAsync(len.data(), a.over_len, (size_t)n_over * 4, hipMemcpyDeviceToHost, st));
+      CK(hipStreamSynchronize(st));
+      for (int32_t x : len)
+        if (x > svf::kLongMaxKeys) return fail(SVF_E_INTERNAL, "repair candidate list above 16384");
+      rc = long_rounds(len, [&](int l0, int l1) {
+        svf::LongLists L{};
+        int64_t hw, cw;
+        int mx;
+        int rc2 = long_layout(s.lg, len.data() + l0, l1 - l0, a.over_li + l0, cap, &L, &hw, &cw, &mx, st);
+        if (rc2) return rc2;
+        svf::RepairArgs ar = a;
+        ar.over_li = a.over_li + l0;
+        CK(svf::launch_repair_raw(ar, (int)first, L, st));
+        CK(svf::launch_long_sort(L, mx, st));
+        CK(svf::launch_repair_back(ar, (int)first, L, st));
+        CK(svf::launch_long_prune(L, lrows, rows + first * R, rows_d + first * R, hw, cw, st));
+        return (int)SVF_OK;
+      });
+      if (rc) return rc;
+      CK(hipMemcpyAsync(&ntop, cnt + 1, 4, hipMemcpyDeviceToHost, st));
+      CK(hipStreamSynchronize(st));
+    }
     if (ntop > 0) {
       uint64_t *qkey, *pool;
       if ((rc = scratch(s.qkey, ntop, &qkey)) || (rc = scratch(s.pool, (size_t)ntop * j.Lins, &pool)))
@@ -537,6 +686,7 @@ int repair_compute(const RepairJob& j, int consolidate, svf::RepairScratch& s, h
     pa.out_ids = rows + first * R;
     pa.out_d = rows_d + first * R;
     pa.nlists = count;
+    pa.skip = mcount;                        // -1: pruned by the long-list kernels
     CK(svf::launch_prune_lists(pa, st));
   }
   CK(hipStreamSynchronize(st));
@@ -716,7 +866,7 @@ int bg_merge(svf_index* ix) {
         (rc = scratch(ix->s_misc[8], (size_t)n_targets * R, &ra.trow_d)))
       return rc;
     CK(svf::launch_reverse_scan_scatter(ra, n_targets, st));
-    CK(svf::launch_reverse_prune(ra, n_targets, st));
+    if ((rc = reverse_prune_all(ix, ra, n_targets, st))) return rc;
     if (int32_t* e = kept_indegree(ix))
       CK(svf::launch_indegree_rows_delta(ix->graph, ra.tlist, n_targets, ra.trow, R, e, st));
     svf::ReverseArgs only_targets = ra;
@@ -1596,7 +1746,7 @@ int svf_get_option(const svf_index* ix, const char* key, double* out) {
   else if (k == "visited_slots") *out = o.visited_slots;
   else if (k == "visited_compact") *out = o.visited_compact;
   else if (k == "repair_c") *out = o.repair_c;
-  else if (k == "prune_cap") *out = prune_cap(ix);
+  else if (k == "prune_cap") *out = o.prune_cap;
   else if (k == "consolidate_frac") *out = o.consolidate_frac;
   else if (k == "localized_repair") *out = o.localized_repair;
   else if (k == "consolidate_async") *out = o.consolidate_async;
@@ -1996,6 +2146,7 @@ int svf_stats_get(const svf_index* cix, svf_stats* out) {
   ix->st.cache_last_placed = ix->tier.last_placed;
   ix->st.cache_promotions = (int64_t)ix->tier.promotions;
   ix->st.cache_evictions = (int64_t)ix->tier.evictions;
+  ix->st.long_lists = ix->lrev.lists + ix->rs.lg.lists + ix->bg.rs.lg.lists;
   *out = ix->st;
   return SVF_OK;
 }

@@ -91,8 +91,16 @@ namespace svf {
 struct Server;
 
 // Device buffers of one repair / consolidation pass.
+// Workspace of the long-list kernels (candidate lists longer than the LDS
+// kernels hold): raw keys, per-list offsets, hash tables, detour counts.
+struct LongScratch {
+  DevBuf keys, meta, hash, cnt, m, q;
+  std::atomic<int64_t> lists{0};   // lists pruned here so far
+};
+
 struct RepairScratch {
   DevBuf list, cnt, rows, rows_d, cand, mcount, topup, topup_v, qkey, pool;
+  LongScratch lg;
 };
 
 // A consolidation running in the background on a snapshot (Sec. 5.3): the
@@ -192,6 +200,7 @@ struct svf_index {
   svf::Server* server = nullptr;   // non-null while the serving loop runs
   svf::TierState tier;
   svf::RepairScratch rs;             // foreground repair / consolidation
+  svf::LongScratch lrev;             // long reverse-edge lists (insertion, merge)
   svf::BgConsolidation bg;
   int64_t graph_epoch = 0;         // advances whenever rows are committed
 };

@@ -99,9 +99,39 @@ struct PruneArgs {
   int32_t* out_ids;         // nlists x R
   float* out_d;
   int nlists;
+  const int32_t* skip;      // optional: lists with skip[l] < 0 are left alone
 };
 size_t prune_lds_bytes(int cap);
 hipError_t launch_prune_lists(const PruneArgs& a, hipStream_t st);
+
+// ---- candidate lists longer than the LDS kernels hold (longprune.hip) ----
+// List l's raw keys are keys[off[l], off[l+1]) (any order, repeats allowed,
+// at most kLongMaxKeys).  The host lays out, per list, a hash table of
+// 2 * S_l words at hoff[l] (S_l a power of two >= 2 * its raw length; hoff
+// has n + 1 entries) and 2 * len_l + 1 count words at coff[l].  Row l of the
+// output is written at out + dst[l] * R.
+constexpr int kLongMaxKeys = 16384;
+struct LongLists {
+  int n;
+  const int64_t* off;       // n + 1
+  const int64_t* hoff;      // n + 1, in 32-bit words
+  const int64_t* coff;      // n, in 32-bit words
+  const int32_t* dst;       // n
+  uint64_t* keys;           // raw keys; sorted distinct keys after launch_long_sort
+  int32_t* m;               // distinct candidates per list
+  int skip_m;               // launch_long_prune leaves lists of at most skip_m alone
+  uint32_t* hash;
+  uint32_t* cnt;
+};
+struct LongRows {
+  const int32_t* graph;     // rows of ids < n_old
+  const int32_t* fwd;       // rows of ids >= n_old (staged rows of a batch)
+  int32_t n_old;
+  int R;
+};
+hipError_t launch_long_sort(const LongLists& a, int max_len, hipStream_t st);
+hipError_t launch_long_prune(const LongLists& a, const LongRows& rs, int32_t* out_ids, float* out_d,
+                             int64_t hash_words, int64_t cnt_words, hipStream_t st);
 
 struct ReverseArgs {
   const int32_t* fwd_ids;   // b x R forward rows of the batch
@@ -148,6 +178,9 @@ struct RepairArgs {
   int32_t* topup;           // chunk-local indices needing a search top-up
   int32_t* topup_v;         // their vertex ids
   int32_t* n_topup;
+  int32_t* over_li;         // chunk-local indices of lists that offered more than cap keys
+  int32_t* over_len;        // their offered key counts (null over_li: no queue)
+  int32_t* n_over;
 };
 hipError_t launch_mark_deleted(const int32_t* ids, int64_t n, uint32_t* alive, int32_t* newly,
                                const int32_t* graph, int R, int32_t* e_in, hipStream_t st);
@@ -157,6 +190,14 @@ hipError_t launch_indegree_add(const int32_t* rows, int64_t n, int32_t* e_in, hi
 hipError_t launch_mark_list(const int32_t* list, int n, uint32_t* mask, hipStream_t st);
 hipError_t launch_affected(const RepairArgs& a, hipStream_t st);
 hipError_t launch_repair_candidates(const RepairArgs& a, int first, int count, hipStream_t st);
+// The walk of launch_repair_candidates for the L.n queued lists (a.over_li),
+// writing every offered key to L.keys + L.off[l].
+hipError_t launch_repair_raw(const RepairArgs& a, int first, const LongLists& L, hipStream_t st);
+hipError_t launch_repair_back(const RepairArgs& a, int first, const LongLists& L, hipStream_t st);
+hipError_t launch_reverse_long(const ReverseArgs& a, int n_targets, int cap, int32_t* qk,
+                               int32_t* qlen, int32_t* nq, hipStream_t st);
+hipError_t launch_reverse_gather(const ReverseArgs& a, const int32_t* qk, const LongLists& L,
+                                 hipStream_t st);
 hipError_t launch_topup_merge(const RepairArgs& a, const uint64_t* pool, int L, int first,
                               int ntop, hipStream_t st);
 hipError_t launch_commit_rows(const int32_t* list, int n, const int32_t* rows, const float* rows_d,

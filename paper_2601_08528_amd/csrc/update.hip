@@ -327,6 +327,7 @@ __global__ __launch_bounds__(64) void prune_lists_kernel(PruneArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int li = blockIdx.x;
   if (li >= a.nlists) return;
+  if (a.skip && a.skip[li] < 0) return;
   const int lane = lane_id();
   const int cap = a.cap < a.cstride ? a.cap : a.cstride;
   uint64_t* keys = reinterpret_cast<uint64_t*>(smem);
@@ -491,6 +492,67 @@ hipError_t launch_reverse_prune(const ReverseArgs& a, int n_targets, hipStream_t
   return hipGetLastError();
 }
 
+// Targets whose candidates (alive row entries and incoming keys) outnumber
+// what the LDS kernel holds: their index k and list length are queued for
+// the long-list kernels.  One wave per target, grid-stride.
+__global__ __launch_bounds__(256) void reverse_long_kernel(ReverseArgs a, int n_targets, int cap,
+                                                           int32_t* qk, int32_t* qlen, int32_t* nq) {
+  const int lane = lane_id();
+  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+  for (int64_t k = wave; k < n_targets; k += nwaves) {
+    const int32_t t = a.tlist[k];
+    int na = 0;
+    for (int r0 = 0; r0 < a.R; r0 += kWave) {
+      const int r = r0 + lane;
+      const int32_t u = r < a.R ? a.graph[(int64_t)t * a.R + r] : -1;
+      na += popc64(ballot(u >= 0 && alive_bit(a.alive, u)));
+    }
+    const int len = na + (a.off[k + 1] - a.off[k]);
+    if (len > cap && lane == 0) {
+      const int q = atomicAdd(nq, 1);
+      qk[q] = (int32_t)k;
+      qlen[q] = len;
+    }
+  }
+}
+hipError_t launch_reverse_long(const ReverseArgs& a, int n_targets, int cap, int32_t* qk,
+                               int32_t* qlen, int32_t* nq, hipStream_t st) {
+  if (n_targets <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>(((int64_t)n_targets + 3) / 4, 8192);
+  hipLaunchKernelGGL(reverse_long_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a, n_targets,
+                     cap, qk, qlen, nq);
+  return hipGetLastError();
+}
+
+// Raw keys of the queued targets: alive row entries with their stored
+// distances, then the incoming keys.  One wave per queued target.
+__global__ __launch_bounds__(64) void reverse_gather_kernel(ReverseArgs a, const int32_t* qk,
+                                                           LongLists L) {
+  const int l = blockIdx.x;
+  const int lane = lane_id();
+  const int k = qk[l];
+  const int32_t t = a.tlist[k];
+  uint64_t* out = L.keys + L.off[l];
+  int pos = 0;
+  for (int r0 = 0; r0 < a.R; r0 += kWave) {
+    const int r = r0 + lane;
+    const int32_t u = r < a.R ? a.graph[(int64_t)t * a.R + r] : -1;
+    const bool ok = u >= 0 && alive_bit(a.alive, u);
+    const uint64_t ob = ballot(ok);
+    if (ok) out[pos + lanes_below(ob)] = make_key(a.edge_d[(int64_t)t * a.R + r], u);
+    pos += popc64(ob);
+  }
+  const int lo = a.off[k], hi = a.off[k + 1];
+  for (int i = lo + lane; i < hi; i += kWave) out[pos + (i - lo)] = a.inc[i];
+}
+hipError_t launch_reverse_gather(const ReverseArgs& a, const int32_t* qk, const LongLists& L,
+                                 hipStream_t st) {
+  if (L.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(reverse_gather_kernel, dim3(L.n), dim3(kWave), 0, st, a, qk, L);
+  return hipGetLastError();
+}
+
 // Commit of a batch: target rows, forward rows of the new ids, alive bits,
 // and reset of the per-target counts.
 __global__ void commit_targets_kernel(ReverseArgs a, int n_targets, int32_t* graph, float* edge_d) {
@@ -651,32 +713,47 @@ hipError_t launch_affected(const RepairArgs& a, hipStream_t st) {
 // deleted neighbour p (row order) the first c entries of p's row that are
 // alive, not v and not yet candidates.  All distances are evaluated against
 // v's own vector.  The `cap` smallest keys are kept; a list shorter than R is
-// queued for a search top-up.
-template <int NC>
-__global__ __launch_bounds__(64) void repair_candidates_kernel(RepairArgs a, int first, int count) {
+// queued for a search top-up.  A list that offered more than `cap` keys
+// (repeats included) is queued as overflowing, with that count; RAW = true
+// runs the same walk for the queued lists and writes every offered key to
+// the long-list staging area instead.
+template <int NC, bool RAW>
+__global__ __launch_bounds__(64) void repair_candidates_kernel(RepairArgs a, int first, int count,
+                                                               LongLists L) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int li = blockIdx.x;
-  if (li >= count) return;
+  const int bi = blockIdx.x;
+  if (bi >= count) return;
+  const int li = RAW ? a.over_li[bi] : bi;
   const int lane = lane_id();
   const int cap = a.cap;
   const int32_t v = a.list[first + li];
   WaveCtx w;
   w.ktrack = 0;
   w.pool = reinterpret_cast<uint64_t*>(smem);
-  w.next = w.pool + cap;
-  w.kept = w.next + cap;
-  w.cid = reinterpret_cast<int32_t*>(w.kept + kWave);
+  w.next = w.pool + (RAW ? 0 : cap);
+  w.kept = w.next + (RAW ? 0 : cap);
+  w.cid = reinterpret_cast<int32_t*>(w.kept + (RAW ? 0 : kWave));
   w.vis = reinterpret_cast<uint32_t*>(w.cid + kWave);
   w.L = cap;
+  uint64_t* out = RAW ? L.keys + L.off[bi] : nullptr;
+  int raw = 0;
   const bool exact = a.c < a.R;       // "first c" needs exact membership
   int H = 64;
   if (exact) while (H < 2 * a.R * (1 + a.c)) H <<= 1;
   w.tmask = (uint32_t)H - 1u;
-  for (int i = lane; i < 2 * cap; i += kWave) w.pool[i] = kKeyInf;
+  if (!RAW) for (int i = lane; i < 2 * cap; i += kWave) w.pool[i] = kKeyInf;
   if (exact) for (int i = lane; i < H; i += kWave) w.vis[i] = kEmpty;
   QuerySlice<float, NC> q;
   q.load(a.vec32 + (int64_t)v * a.stride, a.dim, lane % QuerySlice<float, NC>::kLanesPerVec);
   __syncthreads();
+  auto take = [&](uint64_t k, int m) {
+    if constexpr (RAW) {
+      if (lane < m) out[raw + lane] = k;
+    } else {
+      sort_merge(w, k);
+    }
+    raw += m;
+  };
   const int32_t* rowv = a.graph + (int64_t)v * a.R;
   // alive neighbours
   for (int r0 = 0; r0 < a.R; r0 += kWave) {
@@ -688,7 +765,7 @@ __global__ __launch_bounds__(64) void repair_candidates_kernel(RepairArgs a, int
     if (ok) w.cid[lanes_below(ob)] = u;
     __syncthreads();
     uint64_t k = gather_keys<float, NC>(q, a.vec32, a.stride, w.cid, popc64(ob), a.metric);
-    sort_merge(w, k);
+    take(k, popc64(ob));
   }
   // entries of deleted neighbours
   for (int r = 0; r < a.R; ++r) {
@@ -713,17 +790,23 @@ __global__ __launch_bounds__(64) void repair_candidates_kernel(RepairArgs a, int
       __syncthreads();
       if (ob == 0) continue;
       uint64_t k = gather_keys<float, NC>(q, a.vec32, a.stride, w.cid, popc64(ob), a.metric);
-      sort_merge(w, k);
+      take(k, popc64(ob));
     }
   }
-  const int m = count_keys(w.pool, cap);
-  for (int i = lane; i < cap; i += kWave) a.cand[(int64_t)li * cap + i] = w.pool[i];
-  if (lane == 0) {
-    a.mcount[li] = m;
-    if (m < a.R) {
-      const int t = atomicAdd(a.n_topup, 1);
-      a.topup[t] = li;
-      a.topup_v[t] = v;
+  if constexpr (!RAW) {
+    const int m = count_keys(w.pool, cap);
+    for (int i = lane; i < cap; i += kWave) a.cand[(int64_t)li * cap + i] = w.pool[i];
+    if (lane == 0) {
+      a.mcount[li] = m;
+      if (raw > cap && a.over_li) {
+        const int o = atomicAdd(a.n_over, 1);
+        a.over_li[o] = li;
+        a.over_len[o] = raw;
+      } else if (m < a.R) {
+        const int t = atomicAdd(a.n_topup, 1);
+        a.topup[t] = li;
+        a.topup_v[t] = v;
+      }
     }
   }
 }
@@ -734,12 +817,59 @@ hipError_t launch_repair_candidates(const RepairArgs& a, int first, int count, h
   const size_t lds = (size_t)(2 * a.cap + kWave) * 8 + kWave * 4 + (size_t)H * 4;
   const int chunks = (int)((a.stride + 127) / 128);
   dim3 g(count), b(kWave);
+  const LongLists L{};
   switch (chunks <= 1 ? 1 : chunks <= 2 ? 2 : chunks <= 4 ? 4 : 8) {
-    case 1: hipLaunchKernelGGL(repair_candidates_kernel<1>, g, b, lds, st, a, first, count); break;
-    case 2: hipLaunchKernelGGL(repair_candidates_kernel<2>, g, b, lds, st, a, first, count); break;
-    case 4: hipLaunchKernelGGL(repair_candidates_kernel<4>, g, b, lds, st, a, first, count); break;
-    default: hipLaunchKernelGGL(repair_candidates_kernel<8>, g, b, lds, st, a, first, count); break;
+    case 1: hipLaunchKernelGGL((repair_candidates_kernel<1, false>), g, b, lds, st, a, first, count, L); break;
+    case 2: hipLaunchKernelGGL((repair_candidates_kernel<2, false>), g, b, lds, st, a, first, count, L); break;
+    case 4: hipLaunchKernelGGL((repair_candidates_kernel<4, false>), g, b, lds, st, a, first, count, L); break;
+    default: hipLaunchKernelGGL((repair_candidates_kernel<8, false>), g, b, lds, st, a, first, count, L); break;
   }
+  return hipGetLastError();
+}
+hipError_t launch_repair_raw(const RepairArgs& a, int first, const LongLists& L, hipStream_t st) {
+  if (L.n <= 0) return hipSuccess;
+  int H = 64;
+  if (a.c < a.R) while (H < 2 * a.R * (1 + a.c)) H <<= 1;
+  const size_t lds = (size_t)kWave * 4 + (size_t)H * 4;
+  const int chunks = (int)((a.stride + 127) / 128);
+  dim3 g(L.n), b(kWave);
+  switch (chunks <= 1 ? 1 : chunks <= 2 ? 2 : chunks <= 4 ? 4 : 8) {
+    case 1: hipLaunchKernelGGL((repair_candidates_kernel<1, true>), g, b, lds, st, a, first, L.n, L); break;
+    case 2: hipLaunchKernelGGL((repair_candidates_kernel<2, true>), g, b, lds, st, a, first, L.n, L); break;
+    case 4: hipLaunchKernelGGL((repair_candidates_kernel<4, true>), g, b, lds, st, a, first, L.n, L); break;
+    default: hipLaunchKernelGGL((repair_candidates_kernel<8, true>), g, b, lds, st, a, first, L.n, L); break;
+  }
+  return hipGetLastError();
+}
+
+// Overflowing repair lists after the long-list sort: a list of at most cap
+// distinct candidates goes back to its slot of the candidate buffer (and to
+// the top-up queue when it has fewer than R); the others stay with the
+// long-list kernels and are marked (mcount -1) for the LDS prune to skip.
+__global__ __launch_bounds__(64) void repair_back_kernel(RepairArgs a, int first, LongLists L) {
+  const int l = blockIdx.x;
+  const int lane = lane_id();
+  const int li = a.over_li[l];
+  const int m = L.m[l];
+  if (m > a.cap) {
+    // pruned by the long-list kernels; the LDS prune leaves the list alone
+    if (lane == 0) a.mcount[li] = -1;
+    return;
+  }
+  const uint64_t* src = L.keys + L.off[l];
+  for (int i = lane; i < a.cap; i += kWave) a.cand[(int64_t)li * a.cap + i] = i < m ? src[i] : kKeyInf;
+  if (lane == 0) {
+    a.mcount[li] = m;
+    if (m < a.R) {
+      const int t = atomicAdd(a.n_topup, 1);
+      a.topup[t] = li;
+      a.topup_v[t] = a.list[first + li];
+    }
+  }
+}
+hipError_t launch_repair_back(const RepairArgs& a, int first, const LongLists& L, hipStream_t st) {
+  if (L.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(repair_back_kernel, dim3(L.n), dim3(kWave), 0, st, a, first, L);
   return hipGetLastError();
 }
 

@@ -1,0 +1,104 @@
+"""Candidate lists longer than one wave prunes in LDS (Sec. 5.1 re-prunes a
+vertex's whole list; Sec. 5.2's repair and consolidation lists grow with
+the number of deleted neighbours).  The oracle cuts no list, and neither
+does the GPU: lists beyond the LDS kernels' capacity are pruned whole by the
+long-list kernels.  On integer-valued data every distance is exact, so the
+whole graph must equal the oracle's; the statistics show that the long-list
+kernels ran.  With an explicit prune_cap both sides cut every list to that
+many nearest candidates first, and still agree."""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2601_08528_amd as svf
+from paper_2601_08528_amd import datagen
+from gpu_util import gpu_from_oracle, oracle_index
+
+pytestmark = pytest.mark.gpu
+
+
+def same_graph(g, oix):
+    gr, ge, ga = g.export_graph()
+    orows, oe, oa = oix.export()
+    np.testing.assert_array_equal(ga, oa)
+    np.testing.assert_array_equal(gr, orows)
+    np.testing.assert_array_equal(ge.astype(np.float64), oe)
+
+
+@pytest.mark.parametrize("dim,metric", [(32, O.L2), (200, O.IP)])
+def test_long_reverse_lists_bit_exact(dim, metric):
+    """Degree 8 (LDS lists of 32) and one insert batch of 2,400 vectors into
+    600: vertices near the centre of a component take dozens of new
+    neighbours at once."""
+    base, _ = datagen.gmm_uint8_valued(801, 3000, 1, dim, 6)
+    oix = oracle_index(base[:600], 8, metric=metric, seed=3, batch_max=100)
+    oix.set("insert_batch_max", 2400)
+    g = gpu_from_oracle(oix, base[:600], seed=3, insert_batch_max=2400)
+    assert g.insert(base[600:]).tolist() == oix.insert(base[600:]).tolist()
+    same_graph(g, oix)
+    assert g.stats()["long_lists"] > 0
+
+
+@pytest.mark.parametrize("dim,metric", [(64, O.L2), (200, O.IP)])
+def test_long_repair_and_consolidation_lists_bit_exact(dim, metric):
+    """Degree 16: local repair with c = 8 offers up to 16 + 8 * 16 keys and
+    consolidation (c = R) up to 16 * 16, against LDS lists of 64; deletions
+    of 45% of the vertices, then inserts that read the repaired rows."""
+    base, _ = datagen.gmm_uint8_valued(802, 2600, 1, dim, 8)
+    oix = oracle_index(base[:2000], 16, metric=metric, seed=5, batch_max=400, consolidate_frac=0.95)
+    g = gpu_from_oracle(oix, base[:2000], seed=5, insert_batch_max=400, consolidate_frac=0.95)
+    gen = np.random.Generator(np.random.Philox(12))
+    victims = gen.choice(2000, 900, replace=False).astype(np.int32)
+    for part in np.array_split(victims, 3):
+        assert oix.delete(part) == 0
+        g.delete(part)
+        same_graph(g, oix)
+    n_local = g.stats()["long_lists"]
+    assert n_local > 0
+    oix.consolidate()
+    g.consolidate()
+    same_graph(g, oix)
+    assert g.stats()["long_lists"] > n_local
+    oix.insert(base[2000:])
+    g.insert(base[2000:])
+    same_graph(g, oix)
+
+
+def test_explicit_prune_cap_cuts_on_both_sides():
+    base, _ = datagen.gmm_uint8_valued(803, 1800, 1, 48, 6)
+    gen = np.random.Generator(np.random.Philox(13))
+    victims = gen.choice(1200, 500, replace=False).astype(np.int32)
+    graphs = []
+    for cap in (20, 0):
+        oix = oracle_index(base[:1200], 12, seed=8, batch_max=300, prune_cap=cap,
+                           consolidate_frac=0.3)
+        g = gpu_from_oracle(oix, base[:1200], seed=8, insert_batch_max=600, prune_cap=cap,
+                            consolidate_frac=0.3)
+        oix.set("insert_batch_max", 600)
+        oix.delete(victims)
+        g.delete(victims)
+        oix.insert(base[1200:])
+        g.insert(base[1200:])
+        same_graph(g, oix)
+        graphs.append(oix.export()[0])
+    assert (graphs[0] != graphs[1]).any()          # the cut changes the method's result
+
+
+def test_hand_worked_uncut_list_on_the_gpu():
+    """The oracle's hand-worked pin (a 25-candidate consolidation list at
+    degree 5, longer than the 20 the LDS kernels hold) on the GPU."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "uncut_list_example.json")))
+    for cap, key in ((0, "expect_row0"), (g["cut"], "expect_row0_cut")):
+        ix = svf.Index(g["dim"], g["R"], g["metric"], seed=g["seed"], beam_insert=g["beam_insert"],
+                       consolidate_frac=g["consolidate_frac"], localized_repair=0, prune_cap=cap)
+        pts = np.array(g["points"], np.float32).reshape(-1, g["dim"])
+        n = len(pts)
+        ix.import_graph(pts, np.array(g["rows"], np.int32), np.array(g["edge_d"], np.float32),
+                        np.ones(n, np.uint8))
+        ix.delete(np.array(g["delete"], np.int32))
+        ix.consolidate()
+        rows, ed, _ = ix.export_graph()
+        assert rows[0].tolist() == g[key]
+        assert ed[0].astype(np.float64).tolist() == g[key + "_d"]
