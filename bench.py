@@ -962,6 +962,9 @@ def main():
     ap.add_argument("--search-only", type=int, default=0, metavar="BEAM",
                     help="build, then only time the plain FP32 search at this beam (for "
                          "hardware counter runs); prints a short JSON line")
+    ap.add_argument("--insert-only", type=int, default=0, metavar="K",
+                    help="build, then only run K insert batches of 10k vectors and print their "
+                         "median phase times (for kernel traces and hardware counter runs)")
     ap.add_argument("--search-precision", choices=("fp32", "bf16", "fp8"), default="fp32",
                     help="traversal precision of --search-only (re-scored in FP32)")
     ap.add_argument("--detail", default=os.path.join("gpurun_out", "bench_detail.json"),
@@ -1000,6 +1003,22 @@ def main():
     build_s = time.perf_counter() - t0
     log("build %.2f s" % build_s)
 
+    if args.insert_only:
+        extra, _ = datagen.gmm_uint8_valued(2, 10_000 * args.insert_only, 1, DIM, 256)
+        keys = ("ins_search_ms", "ins_prune_ms", "ins_reverse_ms", "ins_commit_ms")
+        ph, wall = {k: [] for k in keys}, []
+        for i in range(args.insert_only):
+            t0 = time.perf_counter()
+            ix.insert(extra[i * 10_000:(i + 1) * 10_000])
+            wall.append((time.perf_counter() - t0) * 1e3)
+            st = ix.stats()
+            for k in keys:
+                ph[k].append(st[k])
+        print(json.dumps({"insert_batches": args.insert_only, "batch": 10_000,
+                          "wall_ms": round(float(np.median(wall)), 3),
+                          **{k: round(float(np.median(v)), 3) for k, v in ph.items()},
+                          "long_lists_total": int(ix.stats()["long_lists"])}), flush=True)
+        return
     base_t = torch.from_numpy(base).cuda()
     q_t = torch.from_numpy(queries).cuda()
     nq = q_t.shape[0]

@@ -57,6 +57,11 @@ int prune_cap(const svf_index* ix) {
   return std::max(4 * ix->R, ix->R + beam_insert(ix));
 }
 bool lists_uncut(const svf_index* ix) { return ix->opt.prune_cap == 0; }
+// Candidates the one-wave reverse-edge prune holds in LDS when lists are not
+// cut: most targets take R alive entries plus a few new neighbours, and the
+// smaller pool leaves room for more waves per compute unit; longer lists go
+// to the long-list kernels.
+int reverse_lds_cap(const svf_index* ix) { return std::max(128, (ix->R + 64 + 63) / 64 * 64); }
 
 // ---- candidate lists longer than the LDS kernels hold ------------------------------
 constexpr int64_t kLongRoundKeys = (int64_t)1 << 24;   // raw keys per round of the long-list kernels
@@ -130,15 +135,23 @@ int long_rounds(const std::vector<int32_t>& len, F run) {
 // every target, then the long-list kernels rewrite the targets whose alive
 // row entries plus incoming keys exceed its capacity.
 int reverse_prune_all(svf_index* ix, svf::ReverseArgs& ra, int n_targets, hipStream_t st) {
-  CK(svf::launch_reverse_prune(ra, n_targets, st));
-  if (n_targets <= 0 || !lists_uncut(ix)) return SVF_OK;
+  if (n_targets <= 0) return SVF_OK;
+  if (!lists_uncut(ix)) {
+    CK(svf::launch_reverse_prune(ra, n_targets, st));
+    return SVF_OK;
+  }
   svf::LongScratch& s = ix->lrev;
   int32_t* q;
   int rc;
   if ((rc = scratch(s.q, 2 * (size_t)n_targets + 1, &q))) return rc;
   int32_t *qk = q, *qlen = q + n_targets, *nq = q + 2 * n_targets;
   CK(svf::launch_fill_u32(nq, 1, 0u, st));
-  CK(svf::launch_reverse_long(ra, n_targets, ra.cap, qk, qlen, nq, st));
+  svf::ReverseArgs rq = ra;
+  rq.cap = reverse_lds_cap(ix);
+  rq.long_q = qk;
+  rq.long_len = qlen;
+  rq.long_n = nq;
+  CK(svf::launch_reverse_prune(rq, n_targets, st));
   int32_t n_long = 0;
   CK(hipMemcpyAsync(&n_long, nq, 4, hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));

@@ -153,6 +153,9 @@ struct ReverseArgs {
   float* trow_d;
   const uint32_t* tmask;    // only targets with their bit set take edges (null: all)
   int32_t rows_below;       // the prune reads rows of ids below this from graph (0: n0)
+  int32_t* long_q;          // optional: targets with more than cap candidates are queued here
+  int32_t* long_len;        // (index k, list length) instead of being pruned
+  int32_t* long_n;
 };
 hipError_t launch_reverse_count(const ReverseArgs& a, hipStream_t st);
 hipError_t launch_reverse_scan_scatter(const ReverseArgs& a, int n_targets, hipStream_t st);
@@ -194,8 +197,6 @@ hipError_t launch_repair_candidates(const RepairArgs& a, int first, int count, h
 // writing every offered key to L.keys + L.off[l].
 hipError_t launch_repair_raw(const RepairArgs& a, int first, const LongLists& L, hipStream_t st);
 hipError_t launch_repair_back(const RepairArgs& a, int first, const LongLists& L, hipStream_t st);
-hipError_t launch_reverse_long(const ReverseArgs& a, int n_targets, int cap, int32_t* qk,
-                               int32_t* qlen, int32_t* nq, hipStream_t st);
 hipError_t launch_reverse_gather(const ReverseArgs& a, const int32_t* qk, const LongLists& L,
                                  hipStream_t st);
 hipError_t launch_topup_merge(const RepairArgs& a, const uint64_t* pool, int L, int first,

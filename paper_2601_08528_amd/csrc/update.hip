@@ -465,6 +465,8 @@ __device__ void reverse_prune_one(ReverseArgs a, int k, unsigned char* smem) {
   for (int i = lane; i < 2 * cap; i += kWave) w.pool[i] = kKeyInf;
   __syncthreads();
   const int32_t t = a.tlist[k];
+  const int lo = a.off[k], hi = a.off[k + 1];
+  int na = 0;
   for (int r0 = 0; r0 < a.R; r0 += kWave) {
     const int r = r0 + lane;
     uint64_t key = kKeyInf;
@@ -472,9 +474,18 @@ __device__ void reverse_prune_one(ReverseArgs a, int k, unsigned char* smem) {
       const int32_t u = a.graph[(int64_t)t * a.R + r];
       if (u >= 0 && alive_bit(a.alive, u)) key = make_key(a.edge_d[(int64_t)t * a.R + r], u);
     }
+    na += popc64(ballot(key != kKeyInf));
     sort_merge(w, key);
   }
-  const int lo = a.off[k], hi = a.off[k + 1];
+  // a list longer than the pool is queued whole for the long-list kernels
+  if (a.long_q && na + (hi - lo) > cap) {
+    if (lane == 0) {
+      const int q = atomicAdd(a.long_n, 1);
+      a.long_q[q] = k;
+      a.long_len[q] = na + (hi - lo);
+    }
+    return;
+  }
   for (int c0 = lo; c0 < hi; c0 += kWave) {
     const int i = c0 + lane;
     uint64_t key = i < hi ? a.inc[i] : kKeyInf;
@@ -489,39 +500,6 @@ hipError_t launch_reverse_prune(const ReverseArgs& a, int n_targets, hipStream_t
   const size_t lds = (size_t)(2 * a.cap + kWave) * 8 + prune_scratch_bytes(a.cap);
   const int blocks = (int)std::min<int64_t>(n_targets, kMaxBlocks);
   hipLaunchKernelGGL(reverse_prune_kernel, dim3(blocks), dim3(kWave), lds, st, a, n_targets);
-  return hipGetLastError();
-}
-
-// Targets whose candidates (alive row entries and incoming keys) outnumber
-// what the LDS kernel holds: their index k and list length are queued for
-// the long-list kernels.  One wave per target, grid-stride.
-__global__ __launch_bounds__(256) void reverse_long_kernel(ReverseArgs a, int n_targets, int cap,
-                                                           int32_t* qk, int32_t* qlen, int32_t* nq) {
-  const int lane = lane_id();
-  const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
-  const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
-  for (int64_t k = wave; k < n_targets; k += nwaves) {
-    const int32_t t = a.tlist[k];
-    int na = 0;
-    for (int r0 = 0; r0 < a.R; r0 += kWave) {
-      const int r = r0 + lane;
-      const int32_t u = r < a.R ? a.graph[(int64_t)t * a.R + r] : -1;
-      na += popc64(ballot(u >= 0 && alive_bit(a.alive, u)));
-    }
-    const int len = na + (a.off[k + 1] - a.off[k]);
-    if (len > cap && lane == 0) {
-      const int q = atomicAdd(nq, 1);
-      qk[q] = (int32_t)k;
-      qlen[q] = len;
-    }
-  }
-}
-hipError_t launch_reverse_long(const ReverseArgs& a, int n_targets, int cap, int32_t* qk,
-                               int32_t* qlen, int32_t* nq, hipStream_t st) {
-  if (n_targets <= 0) return hipSuccess;
-  const int64_t blocks = std::min<int64_t>(((int64_t)n_targets + 3) / 4, 8192);
-  hipLaunchKernelGGL(reverse_long_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a, n_targets,
-                     cap, qk, qlen, nq);
   return hipGetLastError();
 }
 
