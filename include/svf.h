@@ -148,6 +148,14 @@ int svf_destroy(svf_index *ix);
  *   cache_alpha_ratio alpha / (alpha + beta) of F_lambda, alpha + beta = 1 ([0,1]; 0.6)
  *   cache_promote_max placements per query batch (>= 0; 2048)
  *   cache_trace_cap expansions per query recorded for placement (16..8192; 512)
+ *   cache_cpu_miss  Alg. 1's co-processing (0/1; 0): an FP32 traversal of the tiered store
+ *                   computes the distances of uncached neighbours on the host cores (X_CPU)
+ *                   and those of cached ones on the GPU (X_GPU), round by round over the
+ *                   batch; 0 reads uncached rows over the host link inside the search kernel.
+ *                   Results are identical either way (the host follows the GPU's FP32
+ *                   summation order).  Applies to svf_search / svf_search_dev with random
+ *                   entry points and search_width 1; other searches keep the one-kernel form.
+ *                   The read-only key cache_cpu_rounds counts the rounds run so far
  *   cache_policy    placement policy: 0 workload-aware (Alg. 2), or one of the classic
  *                   policies the paper compares it with, in the same batched form:
  *                   1 LRU, 2 LFU, 3 LRFU (0..3; 0)

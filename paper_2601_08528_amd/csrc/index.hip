@@ -952,7 +952,14 @@ int search_impl(svf_index* ix, const float* d_q, int64_t nq, int k, int beam, in
   CK(svf::launch_query_keys(d_q, ix->dim, nullptr, ix->dim, a.nq, ix->opt.seed, qkey, st));
   a.qkey = qkey;
   CK(hipEventRecord(ix->ev0, st));
-  CK(svf::launch_search(a, ix->veclp_prec, st));
+  // Alg. 1's X_CPU: with cache_cpu_miss the misses of an FP32 traversal of
+  // the tiered store are computed on the host cores (random entry points,
+  // one parent per iteration; other forms read misses over the host link)
+  if (ix->tier.on && ix->opt.cache_cpu_miss && ix->veclp_prec == 0 && !a.q_entry && a.width == 1) {
+    if ((rc = co_search(ix, a, d_q, nq, st))) return rc;
+  } else {
+    CK(svf::launch_search(a, ix->veclp_prec, st));
+  }
   CK(hipEventRecord(ix->ev1, st));
   ix->st.last_queries = nq;
   return SVF_OK;
@@ -1728,6 +1735,9 @@ int svf_set_option(svf_index* ix, const char* key, double v) {
   } else if (k == "model_stop_scale") {
     if (v <= 0 || v > 1e6) return fail(SVF_E_INVAL, "model_stop_scale > 0");
     o.model_stop_scale = v;
+  } else if (k == "cache_cpu_miss") {
+    if (v != 0 && v != 1) return fail(SVF_E_INVAL, "cache_cpu_miss 0 or 1");
+    o.cache_cpu_miss = (int)v;
   } else if (k == "model_entries") {
     if (v != 0 && v != 1) return fail(SVF_E_INVAL, "model_entries 0 or 1");
     o.model_entries = (int)v;
@@ -1780,6 +1790,8 @@ int svf_get_option(const svf_index* ix, const char* key, double* out) {
   else if (k == "model_stop_scale") *out = o.model_stop_scale;
   else if (k == "model_min_iters") *out = o.model_min_iters;
   else if (k == "model_entries") *out = o.model_entries;
+  else if (k == "cache_cpu_miss") *out = o.cache_cpu_miss;
+  else if (k == "cache_cpu_rounds") *out = (double)ix->tier.co_rounds;
   else return fail(SVF_E_INVAL, "unknown option " + k);
   return SVF_OK;
 }

@@ -83,6 +83,7 @@ struct Options {
   double model_stop_scale = 1.5;
   int model_min_iters = 8;
   int model_entries = 1;        // 1: spread over the cluster, 0: nearest to the centroid
+  int cache_cpu_miss = 0;       // tiered FP32 search: misses computed on the host cores
 };
 
 }  // namespace svf
@@ -154,6 +155,10 @@ struct TierState {
   int promote_max = 2048, trace_cap = 512;
   uint64_t gather_hits = 0, gather_misses = 0, promotions = 0, evictions = 0;
   int64_t last_trace_hits = 0, last_placed = 0;
+  // co-processed search (misses computed on the host cores): per-batch pools,
+  // round keys, miss lists, and the rounds run so far
+  DevBuf co_pool, co_newk, co_ints, co_missd;
+  int64_t co_rounds = 0;
   DevBuf trace, trace_n, place, counts, e_in_d, acc_cnt, touched, lastpos;
   DevBuf blk, lst_id, lst_cnt, lst_last;   // the batch's touched vertices, in id order
   DevBuf e_in_chk;                         // recount for cache_indegree_verify

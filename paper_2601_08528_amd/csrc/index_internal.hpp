@@ -51,6 +51,10 @@ int search_impl(svf_index* ix, const float* d_q, int64_t nq, int k, int beam, in
                 float* d_d, int32_t* d_nd, int32_t* d_ne, hipStream_t st,
                 uint64_t* ws_qkey = nullptr);
 bool all_finite(const float* p, int64_t n);
+// The search of nq device-resident queries with CPU-GPU co-processing of the
+// tiered store's misses (FP32 traversal, random entry points); `a` is the
+// filled argument block of the one-kernel search.
+int co_search(svf_index* ix, const svf::SearchArgs& a, const float* d_q, int64_t nq, hipStream_t st);
 int beam_insert(const svf_index* ix);
 void serve_shutdown(svf_index* ix);
 

@@ -298,3 +298,75 @@ def test_theta_from_measured_costs(state):
     assert g.get_option("cache_theta") == c["theta"]
     gi, _ = g.search(q[:100], 10, 32)                          # still a working index
     np.testing.assert_array_equal(gi, oix.search(q[:100], 10, 32)[0])
+
+
+@pytest.mark.parametrize("policy", [0, 2])
+def test_cpu_miss_path_matches_oracle_and_placement_replay(state, policy):
+    """Alg. 1's co-processing: uncached neighbours' distances on the host
+    cores, cached ones on the GPU.  Results equal the oracle's bit for bit,
+    expansion counts equal the one-kernel search's, hits plus misses cover
+    every evaluation, and the placement after each batch (WAVP, or LFU)
+    equals the oracle's replay over the oracle's own traces."""
+    oix, base, q = state
+    trace_cap = 64
+    cap_rows = 300
+    g = tiered_from_oracle(oix, base, cap_rows, seed=6, cache_trace_cap=trace_cap,
+                           cache_policy=policy, cache_cpu_miss=1)
+    ref = tiered_from_oracle(oix, base, cap_rows, seed=6, cache_trace_cap=trace_cap,
+                             cache_policy=policy)
+    rows, _, alive = oix.export()
+    e_in = np.zeros(len(alive), np.int64)
+    src = rows[alive.astype(bool)]
+    np.add.at(e_in, src[src >= 0], 1)
+    batches, got = [], []
+    import torch
+    for b in range(4):
+        qb = q[b * 100:(b + 1) * 100]
+        oi, od, ost = oix.search(qb, 10, 40)
+        qt = torch.from_numpy(np.ascontiguousarray(qb)).cuda()
+        n = qb.shape[0]
+        ids = torch.empty((n, 10), dtype=torch.int32, device="cuda")
+        d = torch.empty((n, 10), dtype=torch.float32, device="cuda")
+        nd = torch.empty(n, dtype=torch.int32, device="cuda")
+        ne = torch.empty(n, dtype=torch.int32, device="cuda")
+        g.search_dev(qt.data_ptr(), n, 10, 40, ids.data_ptr(), d.data_ptr(), nd.data_ptr(),
+                     ne.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(ids.cpu().numpy(), oi)
+        np.testing.assert_array_equal(d.cpu().numpy().astype(np.float64), od)
+        np.testing.assert_array_equal(ne.cpu().numpy(), ost["n_exp"])
+        st0 = g.stats()
+        got.append(st0["cache_last_trace_hits"])
+        ri, rd = ref.search(qb, 10, 40)
+        np.testing.assert_array_equal(ri, oi)
+        tr, cnt = oix.search_expansions(qb, 40, cap=trace_cap)
+        batches.append(np.concatenate([tr[i, :min(cnt[i], trace_cap)] for i in range(len(qb))]))
+    if policy == 0:
+        hits, slots = O.wavp_replay(len(alive), cap_rows, e_in, alive, batches, 0.6, 0.4, 1.0, 2048)
+    else:
+        hits, slots = O.policy_replay(policy, len(alive), cap_rows, e_in, alive, batches)
+    assert got == hits.tolist()
+    np.testing.assert_array_equal(g.cache_slots()[0], slots)
+    np.testing.assert_array_equal(ref.cache_slots()[0], slots)
+    st = g.stats()
+    assert st["cache_gather_hits"] > 0 and st["cache_gather_misses"] > 0
+    assert g.get_option("cache_cpu_rounds") > 0
+
+
+def test_cpu_miss_path_float_data_equals_gpu_only():
+    """On float data the host computes each uncached distance with the GPU's
+    FP32 operations in the GPU's order, so the co-processed search returns
+    the one-kernel search's ids and distances bit for bit (L2 at 200
+    dimensions, two chunks; inner product at 96)."""
+    for metric, dim in ((O.L2, 200), (O.IP, 96)):
+        base, q = datagen.gmm_float(703 + dim, 5000, 300, dim, 32, normalise=(metric == O.IP))
+        oix = oracle_index(base, 24, metric=metric, seed=4)
+        a = tiered_from_oracle(oix, base, 800, seed=4, cache_cpu_miss=1)
+        b = tiered_from_oracle(oix, base, 800, seed=4)
+        for s in range(3):
+            qb = q[s * 100:(s + 1) * 100]
+            ai, ad = a.search(qb, 10, 48)
+            bi, bd = b.search(qb, 10, 48)
+            np.testing.assert_array_equal(ai, bi)
+            np.testing.assert_array_equal(ad, bd)
+        np.testing.assert_array_equal(a.cache_slots()[0], b.cache_slots()[0])
