@@ -554,10 +554,22 @@ def tier_bench(torch, svf, datagen, n_base, rounds=20, cache_frac=0.25):
     torch.cuda.synchronize()
     same = bool(torch.equal(bufs[0], ref_ids))
     fp32 = run_rounds(beam, 1)
+    # Alg. 1's co-processing: uncached neighbours' distances on the host
+    # cores, cached ones on the GPU, round by round (results unchanged)
+    ix.set_option("cache_cpu_miss", 1)
+    calib = ix.cache_calibrate()
+    r0 = ix.get_option("cache_cpu_rounds")
+    cpu = run_rounds(beam, 1)
+    cpu["rounds_per_batch"] = round((ix.get_option("cache_cpu_rounds") - r0) / rounds, 1)
+    cpu["theta_from_measured_costs"] = calib
+    ix.set_option("cache_cpu_miss", 0)
+    # the threshold for the miss path in force from here on (GPU reads over the link)
+    calib_gpu = ix.cache_calibrate()
     ix.set_option("precision", svf.PREC_FP8)
     beam8, sweep8 = pick_beam()
     fp8 = run_rounds(beam8, rounds + 1)
     fp8["beam_sweep"] = sweep8
+    fp8["theta_from_measured_costs"] = calib_gpu
     del base_t
     return {"workload": "%dM x 128 GMM (4096 comps, Zipf(1.2) queries), L2, degree 32, "
                         "10k-query batches, k=10; cache of %d%% of the FP32 vectors in HBM, the "
@@ -567,6 +579,7 @@ def tier_bench(torch, svf, datagen, n_base, rounds=20, cache_frac=0.25):
                               "qps": round(nq / (float(np.mean(ms_hbm)) / 1e3), 1)},
             "tiered_same_results_as_untiered": same,
             "tiered_fp32_traversal": fp32,
+            "tiered_fp32_cpu_miss": cpu,
             "tiered_fp8_traversal_fp32_rescore": fp8}
 
 
@@ -827,7 +840,7 @@ def workloads_bench(torch, svf, datagen, n=1_000_000, beam=64, nq=2000, evals=10
 
 
 def policy_bench(torch, svf, datagen, n_total=2_000_000, steps=12, measured=8, beam=64,
-                 ratios=(0.2, 0.4, 0.6, 0.8, 1.0)):
+                 ratios=(0.2, 0.4, 0.6, 0.8, 1.0), cpu_ratios=(0.2, 0.6, 1.0)):
     """Replacement-policy ablation under a sliding window on the tiered store.
     n_total x 128 mixture of 4096 components (L2, degree 32) in 200 equal
     segments; the index starts from the first 100 (built once, then imported
@@ -852,13 +865,15 @@ def policy_bench(torch, svf, datagen, n_total=2_000_000, steps=12, measured=8, b
             torch.empty(nq, dtype=torch.int32, device="cuda"))
     qs = [torch.from_numpy(queries[r * nq:(r + 1) * nq]).cuda() for r in range(steps)]
     out = []
-    for ratio in ratios:
+    settings = [(r, 0) for r in ratios] + [(r, 1) for r in cpu_ratios]
+    for ratio, cpu_miss in settings:
         for name, pol, pmax in (("wavp", 0, 2048), ("lru", 1, 2048), ("lfu", 2, 2048),
                                 ("lrfu", 3, 2048), ("none", 0, 0)):
             g = svf.Index(dim, R, svf.METRIC_L2, seed=0)
             g.import_graph(base[:win * seg], rows, ed, alive)
             g.set_option("cache_policy", pol)
             g.set_option("cache_promote_max", pmax)
+            g.set_option("cache_cpu_miss", cpu_miss)
             g.set_option("cache_bytes", int(ratio * win * seg) * dim * 4)
             res = []
             for st in range(steps):
@@ -880,19 +895,23 @@ def policy_bench(torch, svf, datagen, n_total=2_000_000, steps=12, measured=8, b
             upd = float(np.mean([x[0] for x in st_]))
             srch = float(np.mean([x[1] for x in st_]))
             out.append({"cache_share": ratio, "policy": name,
+                        "miss_path": "host cores (co-processing)" if cpu_miss else "GPU over the host link",
                         "gather_hit_rate": round(float(np.mean([x[3] for x in st_])), 4),
                         "update_ms": round(upd, 3), "search_call_ms": round(srch, 3),
                         "search_kernel_ms": round(float(np.mean([x[2] for x in st_])), 3),
                         "step_ms": round(upd + srch, 3),
                         "updates_per_s": round(2 * seg / (upd / 1e3), 1),
                         "queries_per_s": round(nq / (srch / 1e3), 1)})
-            log("policy %s share %.1f: hit %.3f, update %.1f ms, search %.1f ms"
-                % (name, ratio, out[-1]["gather_hit_rate"], upd, srch))
+            log("policy %s share %.1f%s: hit %.3f, update %.1f ms, search %.1f ms"
+                % (name, ratio, " cpu-miss" if cpu_miss else "", out[-1]["gather_hit_rate"], upd, srch))
     return {"workload": "sliding window over %dM x 128 GMM (4096 comps) in %d segments of %d, "
                         "%d live; per step insert one segment, delete the oldest, search 10k "
                         "queries (Zipf(1.2) comps), L2, degree 32, k=10, beam %d, FP32 traversal "
-                        "through the cache; cache share of the live vectors; %d steps, the last %d "
-                        "averaged" % (n_total // 1_000_000, nseg, seg, win * seg, beam, steps, measured),
+                        "through the cache, misses read by the GPU over the host link or (at "
+                        "shares %s) computed on the host cores; cache share of the live vectors; "
+                        "%d steps, the last %d averaged"
+                        % (n_total // 1_000_000, nseg, seg, win * seg, beam, list(cpu_ratios), steps,
+                           measured),
             "build_s": round(build_s, 2), "settings": out}
 
 

@@ -396,9 +396,11 @@ int svf_cache_slots(const svf_index *ix, int32_t *slot_ids, int64_t cap, int64_t
  * T_hit), the access count from which promoting a vector pays for itself
  * (Eq. 1 with gain = 0).  Measured on this GPU with 65,536 random rows per
  * probe (median of five runs): T_hit, the per-row time of a distance over
- * rows read from the HBM cache; T_miss, the same over rows of the host store
- * read across the host link (the miss path as built, in the place of the
- * paper's CPU-side distance); T_transfer, the per-row time of copying 2048
+ * rows read from the HBM cache; T_miss, the cost of a miss on the path in
+ * force: with cache_cpu_miss the host cores' time per distance (the paper's
+ * T_CPU, on the worker threads of the co-processed search), else the GPU's
+ * time per distance over host rows read across the link; T_transfer, the
+ * per-row time of copying 2048
  * host rows into HBM (one promotion batch).  Sets cache_theta (and the floor
  * of its adaptation) to theta; out (4 doubles, may be NULL) receives T_hit,
  * T_miss, T_transfer in ns per row, and theta.  Needs a tiered store that

@@ -18,6 +18,7 @@
 // earlier may be, which changes no result (the L-th key never grows).
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <condition_variable>
 #include <functional>
@@ -438,6 +439,31 @@ int co_search(svf_index* ix, const svf::SearchArgs& a, const float* d_q, int64_t
   hipLaunchKernelGGL(svf::co_output_kernel, dim3((unsigned)nq), dim3(64), 0, st, c);
   CK(hipGetLastError());
   return SVF_OK;
+}
+
+// Host-core time per distance of the co-processed miss path: the n rows
+// ids[] of the host store against a zero query on the worker threads (one
+// untimed run, then the median of five), in nanoseconds per row.
+double host_distance_ns(svf_index* ix, const int32_t* ids, int n) {
+  const int64_t stride = ix->stride;
+  const int chunks = (int)((stride + 127) / 128);
+  const int nc = chunks <= 1 ? 1 : chunks <= 2 ? 2 : chunks <= 4 ? 4 : 8;
+  const float* host = ix->vec32;
+  std::vector<float> q(stride, 0.0f), out(n);
+  std::function<void(int64_t, int64_t)> job = [&](int64_t i0, int64_t i1) {
+    for (int64_t i = i0; i < i1; ++i)
+      out[i] = svf::host_gather_dist(q.data(), host + (int64_t)ids[i] * stride, ix->dim, stride, nc,
+                                     ix->metric);
+  };
+  svf::cpu_pool().run(n, job);
+  std::vector<double> t;
+  for (int r = 0; r < 5; ++r) {
+    const auto t0 = std::chrono::steady_clock::now();
+    svf::cpu_pool().run(n, job);
+    t.push_back(std::chrono::duration<double, std::nano>(std::chrono::steady_clock::now() - t0).count());
+  }
+  std::sort(t.begin(), t.end());
+  return t[2] / n;
 }
 
 }  // namespace svf_detail

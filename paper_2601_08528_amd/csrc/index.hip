@@ -2268,7 +2268,11 @@ int svf_cache_calibrate(svf_index* ix, double* out) {
                                                       dbuf.as<float>(), st); },
                   &ms_x)))
     return rc;
-  const double t_hit = ms_hit * 1e6 / ns, t_miss = ms_miss * 1e6 / ns, t_x = ms_x * 1e6 / nx;
+  const double t_hit = ms_hit * 1e6 / ns, t_x = ms_x * 1e6 / nx;
+  // the miss path in force: host-core distances (co-processing, the paper's
+  // T_CPU) or reads of the host rows across the link inside the GPU gather
+  const double t_miss = ix->opt.cache_cpu_miss ? host_distance_ns(ix, miss.data(), ns)
+                                               : ms_miss * 1e6 / ns;
   if (!(t_miss > t_hit)) return fail(SVF_E_INTERNAL, "a host read measured no slower than a cached one");
   const double theta = t_x / (t_miss - t_hit);
   T.theta = T.theta0 = theta;

@@ -55,6 +55,8 @@ bool all_finite(const float* p, int64_t n);
 // tiered store's misses (FP32 traversal, random entry points); `a` is the
 // filled argument block of the one-kernel search.
 int co_search(svf_index* ix, const svf::SearchArgs& a, const float* d_q, int64_t nq, hipStream_t st);
+// Host-core nanoseconds per distance of that path over the rows ids[0..n).
+double host_distance_ns(svf_index* ix, const int32_t* ids, int n);
 int beam_insert(const svf_index* ix);
 void serve_shutdown(svf_index* ix);
 

@@ -284,12 +284,14 @@ def test_kept_in_degrees_match_a_recount_under_updates():
     assert g.get_option("cache_indegree_verify") == 1
 
 
-def test_theta_from_measured_costs(state):
+@pytest.mark.parametrize("cpu_miss", [0, 1])
+def test_theta_from_measured_costs(state, cpu_miss):
     """Sec. 4.3: theta = T_transfer / (T_miss - T_hit) from probes on this
-    GPU; the threshold is set from it and host reads cost more than cached
-    ones."""
+    machine (T_miss: a host-core distance with co-processing, else a GPU
+    read across the host link); the threshold is set from it and a miss
+    costs more than a cached distance."""
     oix, base, q = state
-    g = tiered_from_oracle(oix, base, 1000, seed=6)
+    g = tiered_from_oracle(oix, base, 1000, seed=6, cache_cpu_miss=cpu_miss)
     g.search(q[:100], 10, 32)
     c = g.cache_calibrate()
     assert 0 < c["t_hit_ns"] < c["t_miss_ns"]
