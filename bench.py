@@ -1190,10 +1190,11 @@ def main():
             for cf in (0.0, 0.3)]
     chosen64 = chosen(64, grid)
     c = chosen64
-    small = [(c["precision"], {"bf16": svf.PREC_BF16, "fp8": svf.PREC_FP8}[c["precision"]],
-              c["visited_slots"], c["search_width"], c["model_stop_scale"], cf) for cf in (0.0, 0.3)]
-    chosen64_nearest = chosen(64, small, entries=0)
-    chosen256 = chosen(256, small)
+    grid_best = [(c["precision"], {"bf16": svf.PREC_BF16, "fp8": svf.PREC_FP8}[c["precision"]],
+                  c["visited_slots"], c["search_width"], c["model_stop_scale"], cf)
+                 for cf in (0.0, 0.3)]
+    chosen64_nearest = chosen(64, grid_best, entries=0)
+    chosen256 = chosen(256, grid_best)
 
     # update path: delete 1% then insert 10k fresh vectors (one batch each)
     g = np.random.Generator(np.random.Philox(77))
