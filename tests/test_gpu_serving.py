@@ -204,3 +204,79 @@ def test_background_consolidation_while_serving():
     alone.consolidate_wait()
     for a_, b_ in zip(served.export_graph(), alone.export_graph()):
         np.testing.assert_array_equal(a_, b_)
+
+
+def test_streaming_form_served_equals_oracle():
+    """The streaming workload's form: inner product, BF16 traversal with FP32
+    re-scoring, and more than 2^20 ids, so that searches run the 16-bit
+    visited tags of the default 2048-slot table.  Integer values (exact on
+    the BF16 grid; every product exact in FP32) on an imported graph of
+    2^20 + 50,000 vectors; a served stream of searches, inserts and deletes
+    replayed through the FP64 oracle one request at a time must give every
+    search's ids and distances, every insert's ids and the final graph."""
+    n, dim, R = (1 << 20) + 50_000, 8, 16
+    base, rows, pts = datagen.walk_graph_uint8(34, n, dim, R, 2000)
+    q, extra = pts[:500], pts[500:]
+    b = base.astype(np.int64)
+    ed = np.empty(rows.shape, np.float64)
+    for c0 in range(0, n, 1 << 18):
+        c1 = min(n, c0 + (1 << 18))
+        ed[c0:c1] = -(b[rows[c0:c1]] * b[c0:c1, None, :]).sum(axis=2)
+    alive = np.ones(n, np.uint8)
+    orc = O.OracleIndex(dim, R, O.IP, seed=21, insert_batch_max=512)
+    orc.set("precision", O.P_BF16)
+    orc.import_state(base, rows, ed, alive)
+    g = svf.Index(dim, R, svf.METRIC_IP, seed=21, insert_batch_max=512, precision=svf.PREC_BF16)
+    g.import_graph(base, rows, ed.astype(np.float32), alive)
+    assert g.get_option("visited_slots") == 0          # the default: 2048 slots for BF16
+    rng = np.random.Generator(np.random.Philox(34))
+    reqs, pos, live_hi = [], 0, n
+    for step in range(18):
+        kind = ["search", "search", "insert", "search", "delete", "search"][step % 6]
+        if kind == "insert":
+            m = int(rng.integers(100, 500))
+            reqs.append(("insert", extra[pos:pos + m]))
+            pos += m
+            live_hi += m
+        elif kind == "delete":
+            reqs.append(("delete", rng.choice(n, 300, replace=False).astype(np.int32)))
+        else:
+            reqs.append(("search", q[rng.integers(0, q.shape[0], int(rng.integers(1, 120)))]))
+    g.serve_start(streams=4, max_batch=256)
+    tickets = []
+    for kind, data in reqs:
+        if kind == "search":
+            t, ids, d = g.submit_search(data, 10, 32)
+            tickets.append((t, kind, data, ids, d))
+        elif kind == "insert":
+            t, ids = g.submit_insert(data)
+            tickets.append((t, kind, data, ids, None))
+        else:
+            tickets.append((g.submit_delete(data), kind, data, None, None))
+    infos = [g.wait(t[0], 120.0) for t in tickets]
+    g.serve_stop()
+    mut = [(i, t) for i, t in enumerate(tickets) if t[1] != "search"]
+    by_epoch = {}
+    for i, t in enumerate(tickets):
+        if t[1] == "search":
+            by_epoch.setdefault(infos[i]["epoch"], []).append(t)
+    checked = 0
+    for e in range(len(mut) + 1):
+        for t in by_epoch.get(e, []):
+            oi, od, _ = orc.search(t[2], 10, 32)
+            np.testing.assert_array_equal(t[3], oi)
+            np.testing.assert_array_equal(t[4].astype(np.float64), od)
+            checked += 1
+        if e < len(mut):
+            i, t = mut[e]
+            assert infos[i]["epoch"] == e + 1
+            if t[1] == "insert":
+                np.testing.assert_array_equal(orc.insert(t[2]), t[3])
+            else:
+                orc.delete(t[2])
+    assert checked == sum(1 for t in tickets if t[1] == "search")
+    orows, oed, oal = orc.export()
+    grows, ged, gal = g.export_graph()
+    np.testing.assert_array_equal(gal, oal)
+    np.testing.assert_array_equal(grows, orows)
+    np.testing.assert_array_equal(ged.astype(np.float64), oed)
