@@ -552,3 +552,26 @@ def test_fp8_search_recall_and_rescore():
     ex = ((base[ids].astype(np.float64) - q[:, None, :].astype(np.float64)) ** 2).sum(-1)
     np.testing.assert_allclose(d, ex, rtol=1e-12)
     ix.set("precision", O.P_FP32)
+
+
+def test_decision_margin_hand_worked():
+    """The margin that decides which float queries are compared by id: the
+    smallest relative gap among the comparisons that set the search's course.
+    Three points on a line, every row naming the other two, a pool of three
+    (all points are entries, so no entry cut): the parent choices compare
+    d0 with d1, then d1 with d2; no merge cuts the pool.  Query 2 against
+    x = 0, 5, 9: squared distances 4, 9, 49; gaps |4 - 9| / 9 = 5/9 and
+    |9 - 49| / 49 = 40/49, so the margin is 5/9.  For the inner product the
+    gap is taken relative to |q| * max|x| (= 2 * 9): distances -0, -10, -18
+    order as 2 (-18), 1 (-10), 0 (0); gaps 8/18 and 10/18, margin 4/9."""
+    pts = np.array([[0.0], [5.0], [9.0]], np.float32)
+    rows = np.array([[1, 2], [0, 2], [0, 1]], np.int32)
+    for metric, edge, want_ids, want in (
+            (O.L2, [[25.0, 81.0], [25.0, 16.0], [81.0, 16.0]], [0, 1, 2], 5.0 / 9.0),
+            (O.IP, [[0.0, 0.0], [0.0, -45.0], [0.0, -45.0]], [2, 1, 0], 4.0 / 9.0)):
+        ix = O.OracleIndex(1, 2, metric, seed=0)
+        ix.import_state(pts, rows, np.array(edge), np.ones(3, np.uint8))
+        ids, d, st = ix.search(np.array([[2.0]], np.float32), 3, 3)
+        assert ids[0].tolist() == want_ids
+        assert st["n_exp"][0] == 3
+        assert st["margin"][0] == pytest.approx(want, rel=1e-12)
