@@ -201,3 +201,24 @@ def test_background_consolidation_bit_exact(tmp_path):
         oi, od, _ = oix.search(q, 10, 48)
         gi, gd = g.search(q, 10, 48)
         np.testing.assert_array_equal(gi, oi)
+
+
+def test_hand_worked_merge_on_the_gpu():
+    """The oracle's hand-worked pin of a background consolidation merged
+    after an insertion in its window, on the GPU."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "merge_example.json")))
+    ix = svf.Index(g["dim"], g["R"], g["metric"], seed=g["seed"], beam_insert=g["beam_insert"],
+                   consolidate_frac=g["consolidate_frac"], consolidate_async=1)
+    pts = np.array(g["points"], np.float32).reshape(-1, g["dim"])
+    ix.import_graph(pts, np.array(g["rows"], np.int32), np.array(g["edge_d"], np.float32),
+                    np.ones(len(pts), np.uint8))
+    ix.delete(np.array(g["delete"], np.int32))
+    assert ix.get_option("consolidate_pending") == 1
+    assert ix.insert(np.array(g["insert"], np.float32).reshape(-1, g["dim"])).tolist() == [5]
+    ix.consolidate_wait()
+    rows, ed, alive = ix.export_graph()
+    assert rows.tolist() == g["expect_rows"]
+    assert ed.astype(np.float64).tolist() == g["expect_edge_d"]
+    assert alive.tolist() == g["expect_alive"]

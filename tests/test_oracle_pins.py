@@ -575,3 +575,20 @@ def test_decision_margin_hand_worked():
         assert ids[0].tolist() == want_ids
         assert st["n_exp"][0] == 3
         assert st["margin"][0] == pytest.approx(want, rel=1e-12)
+
+
+def test_background_consolidation_merge_hand_worked():
+    """A consolidation on a snapshot, an insertion during its window, then the
+    merge: consolidated rows written, then the rewritten rows that the logged
+    forward rows name re-pruned with the logged vertices (hand-worked)."""
+    g = load("merge_example.json")
+    ix = _import(g)
+    ix.set("consolidate_async", 1)
+    assert ix.delete(g["delete"]) == 0
+    new = ix.insert(np.array(g["insert"], np.float32).reshape(-1, g["dim"]))
+    assert new.tolist() == [5]
+    ix.consolidate_wait()
+    rows, ed, alive = ix.export()
+    assert rows.tolist() == g["expect_rows"]
+    assert ed.tolist() == g["expect_edge_d"]
+    assert alive.tolist() == g["expect_alive"]
