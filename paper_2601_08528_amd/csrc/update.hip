@@ -15,6 +15,7 @@
 // copies them into the graph afterwards, so the result never depends on the
 // order in which waves run.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -44,18 +45,69 @@ struct RowSource {
   }
 };
 
+// Candidate id -> position table of the prune: S slots (a power of two) of
+// (position << 32) | id with linear probing, followed by a copy of the first
+// kProbeMax slots so that a lookup reads consecutive slots without wrapping.
+// dmax is the largest distance of an inserted id from its home slot; a lookup
+// that reads the dmax + 1 slots from the home slot finds any inserted id.
+constexpr int kProbeMax = 8;
+constexpr uint64_t kTabEmpty = ~0ull;
 struct PruneLds {
-  uint32_t* mkey;   // S slots
-  uint32_t* mval;   // S slots
+  uint64_t* tab;    // S + kProbeMax slots
   uint32_t* cnt;    // cap
   uint32_t* hist;   // cap + 1
+  uint32_t* dmax;   // 1
   int S;
 };
+
+// Position of candidate id e (-1 if e is not a candidate) when the table's
+// largest displacement is below N: a fixed read of the N slots from the home
+// slot, with no data-dependent branch.
+template <int N>
+__device__ __forceinline__ int tab_find(const PruneLds& s, uint32_t home, int32_t e) {
+  uint64_t w[N];
+#pragma unroll
+  for (int d = 0; d < N; ++d) w[d] = s.tab[home + d];
+  int pos = -1;
+#pragma unroll
+  for (int d = 0; d < N; ++d)
+    if ((uint32_t)w[d] == (uint32_t)e) pos = (int)(w[d] >> 32);
+  return e >= 0 ? pos : -1;
+}
+// The same with any displacement (a probe loop that stops at an empty slot).
+__device__ __forceinline__ int tab_find_loop(const PruneLds& s, uint32_t home, int32_t e,
+                                             uint32_t mask) {
+  if (e < 0) return -1;
+  uint32_t sl = home;
+  for (;;) {
+    const uint64_t w = s.tab[sl];
+    if ((uint32_t)w == (uint32_t)e) return (int)(w >> 32);
+    if (w == kTabEmpty) return -1;
+    sl = (sl + 1) & mask;
+  }
+}
 
 __device__ __forceinline__ int pow2_at_least(int x, int lo) {
   int p = lo;
   while (p < x) p <<= 1;
   return p;
+}
+
+// Calls f with the number of slots a lookup reads as a compile-time constant
+// (1 .. kProbeMax), or 0 for the probe loop when the displacement is larger.
+template <class F>
+__device__ __forceinline__ void probe_by_slots(int nd, F&& f) {
+  switch (nd) {
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 5: f(std::integral_constant<int, 5>{}); break;
+    case 6: f(std::integral_constant<int, 6>{}); break;
+    case 7: f(std::integral_constant<int, 7>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    default: f(std::integral_constant<int, 0>{}); break;
+  }
 }
 
 // Rank-based reordering of the m sorted candidate keys in LDS; writes R ids
@@ -66,55 +118,95 @@ __device__ void prune_core(const uint64_t* keys, int m, const RowSource& rs, int
   int tau = 0, need = 0;
   const bool full = m > R;
   if (full) {
-    for (int i = lane; i < s.S; i += kWave) s.mkey[i] = kEmpty;
+    for (int i = lane; i < s.S; i += kWave) s.tab[i] = kTabEmpty;
     for (int i = lane; i <= m; i += kWave) { s.hist[i] = 0; if (i < m) s.cnt[i] = 0; }
+    if (lane == 0) *s.dmax = 0;
     __syncthreads();
     const uint32_t mask = (uint32_t)s.S - 1u;
     for (int i = lane; i < m; i += kWave) {
       const uint32_t id = (uint32_t)key_id(keys[i]);
-      uint32_t sl = slot_hash(id, mask);
-      for (;;) {
-        uint32_t old = atomicCAS(&s.mkey[sl], kEmpty, id);
-        if (old == kEmpty) { s.mval[sl] = (uint32_t)i; break; }
+      const uint64_t v = ((uint64_t)(uint32_t)i << 32) | id;
+      uint32_t sl = slot_hash(id, mask), d = 0;
+      while (atomicCAS((unsigned long long*)&s.tab[sl], (unsigned long long)kTabEmpty,
+                       (unsigned long long)v) != kTabEmpty) {
         sl = (sl + 1) & mask;
+        ++d;
       }
+      atomicMax(s.dmax, d);
     }
     __syncthreads();
-    // detour counts: entry r of row(c_j) naming c_i with i > j.  Entry
-    // t = j * R + r goes to lane t % 64; each lane loads kRowSteps entries
-    // (rows of different candidates) before it probes any, so that many row
-    // reads are in flight per wave.  The counts are sums, so the order in
-    // which entries are probed does not matter.
-    constexpr int kRowSteps = 8;
-    const int total = m * R;
-    int j0 = lane / R, r0 = lane - (lane / R) * R;   // (j, r) of entry t0 + lane
-    for (int t0 = 0; t0 < total; t0 += kWave * kRowSteps) {
-      int32_t e[kRowSteps];
-      int jj[kRowSteps];
-      int j = j0, r = r0;
-#pragma unroll
-      for (int u = 0; u < kRowSteps; ++u) {
-        jj[u] = j;
-        e[u] = t0 + u * kWave + lane < total ? rs.row(key_id(keys[j]))[r] : -1;
-        r += kWave;
-        while (r >= R) { r -= R; ++j; }
-      }
-      j0 = j;
-      r0 = r;
-#pragma unroll
-      for (int u = 0; u < kRowSteps; ++u) {
-        if (e[u] < 0) continue;
-        uint32_t sl = slot_hash((uint32_t)e[u], mask);
-        for (;;) {
-          const uint32_t k = s.mkey[sl];
-          if (k == (uint32_t)e[u]) {
-            const int i = (int)s.mval[sl];
-            if (i > jj[u]) atomicAdd(&s.cnt[i], 1u);
-            break;
-          }
-          if (k == kEmpty) break;
-          sl = (sl + 1) & mask;
+    for (int i = lane; i < kProbeMax; i += kWave) s.tab[s.S + i] = s.tab[i];
+    const int nd = uniform((int)*s.dmax) + 1;   // slots a lookup reads
+    __syncthreads();
+    // detour counts: entry r of row(c_j) naming c_i with i > j.  The counts
+    // are sums, so the order in which entries are probed does not matter.
+    if (R > 32 && R <= kWave) {
+      // One whole row per step: lane r reads entry r of row j.  The offsets
+      // of a pass's 8 rows from the graph base are computed once, one row
+      // per lane, and read out lane by lane, so a row's address is a scalar;
+      // each lane has 8 row reads in flight before it probes any.
+      constexpr int kRowSteps = 8;
+      const int64_t fwd_off = rs.fwd ? (int64_t)(rs.fwd - rs.graph) : 0;
+      for (int j0 = 0; j0 < m; j0 += kRowSteps) {
+        int64_t ro = -1;
+        if (lane < kRowSteps && j0 + lane < m) {
+          const int32_t id = (int32_t)(((uint32_t)keys[j0 + lane]) >> 1);
+          ro = id < rs.n_old ? (int64_t)id * R : fwd_off + (int64_t)(id - rs.n_old) * R;
         }
+        const uint32_t ro_lo = (uint32_t)ro, ro_hi = (uint32_t)((uint64_t)ro >> 32);
+        int32_t e[kRowSteps];
+#pragma unroll
+        for (int u = 0; u < kRowSteps; ++u) {
+          const int64_t b =
+              (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(ro_hi, u) << 32) |
+                        (uint32_t)__builtin_amdgcn_readlane(ro_lo, u));
+          e[u] = j0 + u < m && lane < R ? rs.graph[b + lane] : -1;
+        }
+        auto count = [&](auto nslots) {
+#pragma unroll
+          for (int u = 0; u < kRowSteps; ++u) {
+            constexpr int N = decltype(nslots)::value;
+            const uint32_t h = slot_hash((uint32_t)e[u], mask);
+            int i;
+            if constexpr (N > 0) i = tab_find<N>(s, h, e[u]);
+            else i = tab_find_loop(s, h, e[u], mask);
+            if (i > j0 + u) atomicAdd(&s.cnt[i], 1u);
+          }
+        };
+        probe_by_slots(nd, count);
+      }
+    } else {
+      // Any degree: entry t = j * R + r goes to lane t % 64; each lane loads
+      // kRowSteps entries (rows of different candidates) before it probes
+      // any, so that many row reads are in flight per wave.
+      constexpr int kRowSteps = 8;
+      const int total = m * R;
+      int j0 = lane / R, r0 = lane - (lane / R) * R;   // (j, r) of entry t0 + lane
+      for (int t0 = 0; t0 < total; t0 += kWave * kRowSteps) {
+        int32_t e[kRowSteps];
+        int jj[kRowSteps];
+        int j = j0, r = r0;
+#pragma unroll
+        for (int u = 0; u < kRowSteps; ++u) {
+          jj[u] = j;
+          e[u] = t0 + u * kWave + lane < total ? rs.row(key_id(keys[j]))[r] : -1;
+          r += kWave;
+          while (r >= R) { r -= R; ++j; }
+        }
+        j0 = j;
+        r0 = r;
+        auto count = [&](auto nslots) {
+#pragma unroll
+          for (int u = 0; u < kRowSteps; ++u) {
+            constexpr int N = decltype(nslots)::value;
+            const uint32_t h = slot_hash((uint32_t)e[u], mask);
+            int i;
+            if constexpr (N > 0) i = tab_find<N>(s, h, e[u]);
+            else i = tab_find_loop(s, h, e[u], mask);
+            if (i > jj[u]) atomicAdd(&s.cnt[i], 1u);
+          }
+        };
+        probe_by_slots(nd, count);
       }
     }
     __syncthreads();
@@ -166,16 +258,16 @@ __device__ void prune_core(const uint64_t* keys, int m, const RowSource& rs, int
 __device__ __forceinline__ PruneLds carve_prune_lds(unsigned char* p, int cap) {
   PruneLds s;
   s.S = pow2_at_least(2 * cap, 64);
-  s.mkey = reinterpret_cast<uint32_t*>(p);
-  s.mval = s.mkey + s.S;
-  s.cnt = s.mval + s.S;
+  s.tab = reinterpret_cast<uint64_t*>(p);
+  s.cnt = reinterpret_cast<uint32_t*>(s.tab + s.S + kProbeMax);
   s.hist = s.cnt + cap;
+  s.dmax = s.hist + cap + 1;
   return s;
 }
 size_t prune_scratch_bytes(int cap) {
   int S = 64;
   while (S < 2 * cap) S <<= 1;
-  return (size_t)S * 8 + (size_t)cap * 4 + (size_t)(cap + 1) * 4 + 16;
+  return (size_t)(S + kProbeMax) * 8 + (size_t)cap * 4 + (size_t)(cap + 1) * 4 + 16;
 }
 
 // Number of non-padding keys in a sorted LDS list of n keys.
@@ -467,7 +559,30 @@ __device__ void reverse_prune_one(ReverseArgs a, int k, unsigned char* smem) {
   const int32_t t = a.tlist[k];
   const int lo = a.off[k], hi = a.off[k + 1];
   int na = 0;
-  for (int r0 = 0; r0 < a.R; r0 += kWave) {
+  bool placed = false;
+  if (a.R <= kWave) {
+    // Rows are stored in (d, id) order, so the alive entries fill the empty
+    // pool as they stand; a row out of order is merged key by key instead.
+    uint64_t key = kKeyInf;
+    if (lane < a.R) {
+      const int32_t u = a.graph[(int64_t)t * a.R + lane];
+      const float d = a.edge_d[(int64_t)t * a.R + lane];
+      if (u >= 0 && alive_bit(a.alive, u)) key = make_key(d, u);
+    }
+    const uint64_t ab = ballot(key != kKeyInf);
+    na = popc64(ab);
+    if (key != kKeyInf) w.pool[lanes_below(ab)] = key;
+    __syncthreads();
+    const bool bad = lane + 1 < na && key_ord(w.pool[lane]) >= key_ord(w.pool[lane + 1]);
+    placed = ballot(bad) == 0;
+    __syncthreads();
+    if (!placed) {
+      if (lane < na) w.pool[lane] = kKeyInf;
+      na = 0;
+      __syncthreads();
+    }
+  }
+  for (int r0 = 0; !placed && r0 < a.R; r0 += kWave) {
     const int r = r0 + lane;
     uint64_t key = kKeyInf;
     if (r < a.R) {
