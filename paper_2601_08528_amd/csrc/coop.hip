@@ -157,6 +157,7 @@ __global__ __launch_bounds__(64 * W) void search_coop_kernel(SearchArgs a) {
   int lcur = meta[2 * W + 1];
   const int cap_iters = (a.q_max_iters && a.q_max_iters[qi] > 0) ? a.q_max_iters[qi] : a.max_iters;
   int last_change = 0, n_iter = 0, n_exp = 0;
+  const bool any_deleted = a.n_alive < a.n_slots;
   for (;;) {
     if (cap_iters > 0 && n_iter >= cap_iters) break;
     int ppos[W];
@@ -187,18 +188,19 @@ __global__ __launch_bounds__(64 * W) void search_coop_kernel(SearchArgs a) {
     if (active) {
       const int32_t nb = lane < a.R ? a.graph[(int64_t)parent * a.R + lane] : -1;
       bool ok = nb >= 0 && nb < a.n_slots;
+      // deleted vertices are never evaluated (no bit is read without deletions)
+      uint32_t aword = ~0u;
+      if (ok && any_deleted) aword = a.alive[(uint32_t)nb >> 5];
       if (ok) ok = !vis.test_and_set(nb);
+      if (ok && any_deleted) ok = (aword >> (nb & 31)) & 1u;
       const uint64_t ob = ballot(ok);
       if (ok) mycid[lanes_below(ob)] = nb;
       const int m = popc64(ob);
       WaveSync::sync();
       uint64_t k = kKeyInf;
       if (m > 0) {
-        const int32_t mine = lane < m ? mycid[lane] : 0;
-        const uint32_t aword = a.alive[(uint32_t)mine >> 5];
         k = gather_keys<VT, NC, false>(qs, base, a.vstride, mycid, m, a.metric, nullptr, nullptr,
                                        a.vscale);
-        if (lane < m && !((aword >> (mine & 31)) & 1u)) k = kKeyInf;
         n_dist += m;
       }
       // keys that can enter a full pool, sorted; then those the pool lacks

@@ -152,6 +152,7 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
   // which equals one merge of all new keys (the top-L of a union).
   const int cap_iters = (a.q_max_iters && a.q_max_iters[qi] > 0) ? a.q_max_iters[qi] : a.max_iters;
   int last_change = 0, n_iter = 0;
+  const bool any_deleted = a.n_alive < a.n_slots;
   for (;;) {
     if (cap_iters > 0 && n_iter >= cap_iters) break;
     int ppos[4];
@@ -184,8 +185,14 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
         const int rr = r0 + lane;
         const int32_t nb = rr < a.R ? row[rr] : -1;
         bool ok = nb >= 0 && nb < a.n_slots;
+        // Deleted vertices are never evaluated.  With deletions in the
+        // snapshot their bits load while the visited table is probed; with
+        // none, no bit is read.
+        uint32_t aword = ~0u;
+        if (ok && any_deleted) aword = a.alive[(uint32_t)nb >> 5];
         __syncthreads();
         if (ok) ok = !vis.test_and_set(nb);
+        if (ok && any_deleted) ok = (aword >> (nb & 31)) & 1u;
         const uint64_t ob = ballot(ok);
         if (ok) {
           w.cid[lanes_below(ob)] = nb;
@@ -199,12 +206,9 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
           t_hit += popc64(ballot(h));
           t_miss += m - popc64(ballot(h));
         }
-        // the deletion bits load while the vectors are gathered
-        const int32_t mine = lane < m ? w.cid[lane] : 0;
-        const uint32_t aword = a.alive[(uint32_t)mine >> 5];
-        uint64_t k = gather_keys<VT, NC, tier, form>(qs, base, a.vstride, w.cid, m, a.metric, slot,
-                                               reinterpret_cast<const VT*>(a.tcache), a.vscale);
-        if (lane < m && !((aword >> (mine & 31)) & 1u)) k = kKeyInf;
+        const uint64_t k = gather_keys<VT, NC, tier, form>(qs, base, a.vstride, w.cid, m, a.metric,
+                                                     slot, reinterpret_cast<const VT*>(a.tcache),
+                                                     a.vscale);
         n_dist += m;
         if (sort_merge(w, k)) last_change = n_iter;
       }
