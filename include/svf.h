@@ -137,7 +137,15 @@ int svf_destroy(svf_index *ix);
  *                   svf_build warms it with the highest in-degree vectors (Sec. 4.4).
  *                   A deleted vector leaves the cache at once; inserted vectors take
  *                   free slots in id order.  While the serving loop runs the cache
- *                   does not change.
+ *                   does not change.  The host store is a set of pinned segments of
+ *                   host_segment_rows rows each (one allocation per segment), so it
+ *                   grows segment by segment up to what pinned memory holds in all.
+ *                   svf_model_fit is refused once the store is tiered
+ *   host_segment_rows rows per pinned host segment of the tiered store, set before
+ *                   cache_bytes: 0 = the most rows whose segment stays within 4 GiB
+ *                   (at least 4096), else a power of two in [1024, 2^30] (0).  Reading it
+ *                   back once tiered gives the size in force; "host_segments" (read-only)
+ *                   is the number of segments
  *   cache_theta     placement threshold on F_lambda (>= 0; 1.0); also the floor of the
  *                   adaptation below.  svf_cache_calibrate sets it from measured costs
  *   cache_theta_adapt Sec. 4.4's adaptation of theta, by this factor, 0 = off (0 or (1, 16];

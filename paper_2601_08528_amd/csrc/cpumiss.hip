@@ -98,7 +98,7 @@ __global__ __launch_bounds__(64) void co_round_kernel(CoArgs c, int round) {
     }
     __syncthreads();
     const uint64_t k = gather_keys<float, NC, true, 0>(qs, host, a.stride, cid, nh, a.metric, slot,
-                                                      a.tcache);
+                                                      a.tcache, nullptr, a.hsegs);
     if (lane < nh) out[n + lane] = k;
     n += nh + nm;
     hits += nh;
@@ -393,7 +393,6 @@ int co_search(svf_index* ix, const svf::SearchArgs& a, const float* d_q, int64_t
   CK(hipStreamSynchronize(st));
   const size_t lds_round = (size_t)Lp * 8 + 2 * svf::kWave * 4 + (size_t)std::max(a.E, 2 * Lp) * 4;
   const size_t lds_merge = (size_t)(2 * Lp + svf::kWave) * 8;
-  const float* host = static_cast<const float*>(a.vec);
   std::vector<int32_t> mpos, mid;
   std::vector<float> md;
   for (int round = 0;; ++round) {
@@ -421,8 +420,8 @@ int co_search(svf_index* ix, const svf::SearchArgs& a, const float* d_q, int64_t
       std::function<void(int64_t, int64_t)> job = [&](int64_t i0, int64_t i1) {
         for (int64_t i = i0; i < i1; ++i) {
           const int64_t q = mpos[i] / C;
-          md[i] = svf::host_gather_dist(qh.data() + q * dim, host + (int64_t)mid[i] * stride, dim,
-                                        stride, nc, metric);
+          md[i] = svf::host_gather_dist(qh.data() + q * dim, T.hrow(mid[i], stride), dim, stride,
+                                        nc, metric);
         }
       };
       svf::cpu_pool().run(nmiss, job);
@@ -448,11 +447,11 @@ double host_distance_ns(svf_index* ix, const int32_t* ids, int n) {
   const int64_t stride = ix->stride;
   const int chunks = (int)((stride + 127) / 128);
   const int nc = chunks <= 1 ? 1 : chunks <= 2 ? 2 : chunks <= 4 ? 4 : 8;
-  const float* host = ix->vec32;
+  const svf::TierState& T = ix->tier;
   std::vector<float> q(stride, 0.0f), out(n);
   std::function<void(int64_t, int64_t)> job = [&](int64_t i0, int64_t i1) {
     for (int64_t i = i0; i < i1; ++i)
-      out[i] = svf::host_gather_dist(q.data(), host + (int64_t)ids[i] * stride, ix->dim, stride, nc,
+      out[i] = svf::host_gather_dist(q.data(), T.hrow(ids[i], stride), ix->dim, stride, nc,
                                      ix->metric);
   };
   svf::cpu_pool().run(n, job);

@@ -208,6 +208,55 @@ int visited_slots(const svf_index* ix, int E) {
 
 
 // Grow the device arrays to hold `need` id slots, keeping the contents.
+// One pinned host allocation is kept below this size: larger ones have failed
+// well below what pinned memory holds in all.
+constexpr int64_t kHostSegBytes = int64_t(4) << 30;
+
+// Rows per host segment, as a power of two: the host_segment_rows option, or
+// the most rows whose segment stays within kHostSegBytes (at least 4096).
+int host_seg_shift(const svf_index* ix) {
+  int s = 10;
+  if (ix->tier.seg_rows_opt > 0) {
+    while ((int64_t(1) << s) < ix->tier.seg_rows_opt) ++s;
+    return s;
+  }
+  s = 12;
+  while ((int64_t(2) << s) * ix->stride * 4 <= kHostSegBytes) ++s;
+  return s;
+}
+
+// Make the tiered store's host segments hold rows [0, cap).  Rows already
+// stored stay where they are, except in a last segment that grows (its rows
+// are copied into the larger allocation); new rows are zero.  On failure the
+// store keeps its previous rows and capacity.
+int tier_grow_host(svf_index* ix, int64_t cap) {
+  svf::TierState& T = ix->tier;
+  const int64_t S = int64_t(1) << T.seg_shift;
+  const int64_t rb = ix->stride * 4;
+  const int64_t nseg = (cap + S - 1) / S;
+  for (int64_t i = 0; i < nseg; ++i) {
+    const int64_t want = (i + 1 < nseg) ? S : cap - i * S;
+    const int64_t have = i < (int64_t)T.seg.size() ? T.seg_alloc[i] : 0;
+    if (have >= want) continue;
+    float* p = nullptr;
+    const hipError_t e = hipHostMalloc((void**)&p, (size_t)(want * rb), 0);
+    if (e != hipSuccess) return hip_fail(e, "pinned host segment of the tiered store");
+    if (have > 0) std::memcpy(p, T.seg[i], (size_t)(have * rb));
+    std::memset(reinterpret_cast<char*>(p) + have * rb, 0, (size_t)((want - have) * rb));
+    if (i < (int64_t)T.seg.size()) {
+      (void)hipHostFree(T.seg[i]);
+      T.seg[i] = p;
+      T.seg_alloc[i] = want;
+    } else {
+      T.seg.push_back(p);
+      T.seg_alloc.push_back(want);
+    }
+  }
+  CK(T.seg_d.ensure(T.seg.size() * sizeof(float*)));
+  CK(hipMemcpy(T.seg_d.p, T.seg.data(), T.seg.size() * sizeof(float*), hipMemcpyHostToDevice));
+  return SVF_OK;
+}
+
 int reserve(svf_index* ix, int64_t need) {
   if (need <= ix->cap) return SVF_OK;
   bg_join(ix);                              // it reads the vector stores that move below
@@ -220,7 +269,7 @@ int reserve(svf_index* ix, int64_t need) {
   int32_t *g = nullptr, *tc = nullptr, *ti = nullptr;
   uint32_t* al = nullptr;
   auto cleanup = [&]() {
-    if (v32) (void)(ix->tier.on ? hipHostFree(v32) : hipFree(v32));
+    if (v32) (void)hipFree(v32);
     if (vlp) (void)hipFree(vlp);
     if (g) (void)hipFree(g);
     if (ed) (void)hipFree(ed);
@@ -231,9 +280,13 @@ int reserve(svf_index* ix, int64_t need) {
   hipError_t e = hipSuccess;
   const bool tier = ix->tier.on;
   int32_t* tmap = nullptr;
-  if (tier && (e = hipMalloc(&tmap, cap * 4)) != hipSuccess) return hip_fail(e, "index allocation");
-  if ((e = tier ? hipHostMalloc((void**)&v32, cap * ix->stride * 4, 0)
-                : hipMalloc(&v32, cap * ix->stride * 4)) != hipSuccess ||
+  if (tier) {
+    // the host store grows by segments in place (rows already stored stay put)
+    const int rc = tier_grow_host(ix, cap);
+    if (rc) return rc;
+    if ((e = hipMalloc(&tmap, cap * 4)) != hipSuccess) return hip_fail(e, "index allocation");
+  }
+  if ((!tier && (e = hipMalloc(&v32, cap * ix->stride * 4)) != hipSuccess) ||
       (ix->veclp_prec && (e = hipMalloc(&vlp, lp_bytes(ix, ix->veclp_prec, cap))) != hipSuccess) ||
       (e = hipMalloc(&g, cap * ix->R * 4)) != hipSuccess ||
       (e = hipMalloc(&ed, cap * ix->R * 4)) != hipSuccess ||
@@ -247,8 +300,6 @@ int reserve(svf_index* ix, int64_t need) {
   const int64_t n = ix->n_slots;
   ix->tier.e_in_valid = false;             // sized by capacity: counted again when next needed
   if (tier) {
-    std::memset(v32, 0, cap * ix->stride * 4);
-    if (n > 0) std::memcpy(v32, ix->vec32, n * ix->stride * 4);
     CK(svf::launch_fill_u32(tmap, cap, 0xffffffffu, st));
     if (n > 0 && ix->tier.map) CK(hipMemcpyAsync(tmap, ix->tier.map, n * 4, hipMemcpyDeviceToDevice, st));
     ix->tier.where.resize(cap, -1);
@@ -278,16 +329,17 @@ int reserve(svf_index* ix, int64_t need) {
     CK(hipMemcpyAsync(al, ix->alive, ((n + 31) / 32) * 4, hipMemcpyDeviceToDevice, st));
   }
   CK(hipStreamSynchronize(st));
-  if (ix->vec32) (void)(tier ? hipHostFree(ix->vec32) : hipFree(ix->vec32));
   if (tier) {
     if (ix->tier.map) (void)hipFree(ix->tier.map);
     ix->tier.map = tmap;
+  } else {
+    if (ix->vec32) (void)hipFree(ix->vec32);
+    ix->vec32 = v32;
   }
   if (ix->veclp) (void)hipFree(ix->veclp);
   if (ix->graph) (void)hipFree(ix->graph);
   if (ix->edge_d) (void)hipFree(ix->edge_d);
   if (ix->alive) (void)hipFree(ix->alive);
-  ix->vec32 = v32;
   ix->veclp = vlp;
   ix->graph = g;
   ix->edge_d = ed;
@@ -305,6 +357,8 @@ int reserve(svf_index* ix, int64_t need) {
 int32_t* tcount(svf_index* ix) { return ix->s_misc[10].as<int32_t>(); }
 int32_t* tidx(svf_index* ix) { return ix->s_misc[11].as<int32_t>(); }
 
+int store_lowp_rows(svf_index* ix, int64_t row0, int64_t n, hipStream_t st);
+
 // Make the reduced-precision copy match the chosen precision.
 int sync_lowp(svf_index* ix) {
   const int prec = ix->opt.precision;
@@ -316,23 +370,56 @@ int sync_lowp(svf_index* ix) {
   if (prec == 0 || ix->cap == 0) return SVF_OK;
   CK(hipMalloc(&ix->veclp, lp_bytes(ix, prec, ix->cap)));
   CK(svf::launch_fill_u32(ix->veclp, lp_bytes(ix, prec, ix->cap) / 4, 0u, ix->stream));
-  CK(svf::launch_store_lowp(ix->vec32, ix->stride, ix->dim, ix->veclp, lp_stride(ix, prec),
-                            lp_scale(ix->veclp, ix, prec, ix->cap), 0, ix->n_slots, prec,
-                            ix->stream));
+  const int rc = store_lowp_rows(ix, 0, ix->n_slots, ix->stream);
+  if (rc) return rc;
   CK(hipStreamSynchronize(ix->stream));
   return SVF_OK;
+}
+
+// Calls f(row0, nrows, src) for the runs of rows [at, at + n) that are
+// contiguous in the FP32 store (one run in HBM, one per segment when tiered);
+// src is the address of row row0.
+template <class F>
+int for_store_runs(svf_index* ix, int64_t at, int64_t n, F&& f) {
+  while (n > 0) {
+    int64_t len = n;
+    float* src = nullptr;
+    if (ix->tier.on) {
+      const int64_t S = int64_t(1) << ix->tier.seg_shift;
+      len = std::min<int64_t>(n, S - (at & (S - 1)));
+      src = ix->tier.hrow(at, ix->stride);
+    } else {
+      src = ix->vec32 + at * ix->stride;
+    }
+    const int rc = f(at, len, src);
+    if (rc) return rc;
+    at += len;
+    n -= len;
+  }
+  return SVF_OK;
+}
+
+// Reduced-precision rows [row0, row0 + n) from the FP32 store.
+int store_lowp_rows(svf_index* ix, int64_t row0, int64_t n, hipStream_t st) {
+  const int p = ix->veclp_prec;
+  if (!p || n <= 0) return SVF_OK;
+  return for_store_runs(ix, row0, n, [&](int64_t r0, int64_t len, float* src) -> int {
+    CK(svf::launch_store_lowp(src, ix->stride, ix->dim, ix->veclp, lp_stride(ix, p),
+                              lp_scale(ix->veclp, ix, p, ix->cap), r0, len, p, st));
+    return SVF_OK;
+  });
 }
 
 // Copy n rows (pitch dim floats, device memory) into slots [at, at + n).
 int store_rows(svf_index* ix, const float* d_src, int64_t n, int64_t at, hipStream_t st) {
   if (n <= 0) return SVF_OK;
-  CK(hipMemcpy2DAsync(ix->vec32 + at * ix->stride, ix->stride * 4, d_src, ix->dim * 4,
-                      ix->dim * 4, n, hipMemcpyDefault, st));
-  const int p = ix->veclp_prec;
-  if (p)
-    CK(svf::launch_store_lowp(ix->vec32, ix->stride, ix->dim, ix->veclp, lp_stride(ix, p),
-                              lp_scale(ix->veclp, ix, p, ix->cap), at, n, p, st));
-  return SVF_OK;
+  const int rc = for_store_runs(ix, at, n, [&](int64_t r0, int64_t len, float* dst) -> int {
+    CK(hipMemcpy2DAsync(dst, ix->stride * 4, d_src + (r0 - at) * ix->dim, ix->dim * 4,
+                        ix->dim * 4, len, hipMemcpyDefault, st));
+    return SVF_OK;
+  });
+  if (rc) return rc;
+  return store_lowp_rows(ix, at, n, st);
 }
 
 const void* traversal_store(const svf_index* ix) {
@@ -355,6 +442,7 @@ svf::SearchArgs base_args(const svf_index* ix) {
   a.metric = ix->metric;
   a.max_iters = ix->opt.max_iters;
   if (ix->tier.on) {
+    a.hsegs = ix->tier.segs();
     a.tmap = ix->tier.map;
     a.tcache = ix->tier.cache;
   }
@@ -407,8 +495,10 @@ int insert_prepare(svf_index* ix, const float* d_vecs, int64_t b, PendingInsert*
     if (b > 4 * R) return fail(SVF_E_INTERNAL, "seed batch larger than 4 * degree");
     rc = store_rows(ix, d_vecs, b, 0, st);
     if (rc) return rc;
-    CK(svf::launch_seed(ix->vec32, ix->stride, ix->dim, ix->metric, (int)b, R, ix->graph,
-                        ix->edge_d, st));
+    // the seed rows sit in the first host segment when tiered (it holds at
+    // least 1024 rows)
+    const float* v0 = ix->tier.on ? ix->tier.seg[0] : ix->vec32;
+    CK(svf::launch_seed(v0, ix->stride, ix->dim, ix->metric, (int)b, R, ix->graph, ix->edge_d, st));
     CK(hipStreamSynchronize(st));
     return SVF_OK;
   }
@@ -428,7 +518,16 @@ int insert_prepare(svf_index* ix, const float* d_vecs, int64_t b, PendingInsert*
   set_beam(a, ix, Lins);
   a.max_iters = 0;
   a.k = 0;
-  a.queries = ix->vec32 + n0 * ix->stride;
+  if (ix->tier.on) {
+    // the batch's rows, read from HBM rather than across the host link
+    float* qrows;
+    if ((rc = scratch(ix->s_rows, (size_t)b * ix->stride, &qrows))) return rc;
+    CK(hipMemcpy2DAsync(qrows, ix->stride * 4, d_vecs, ix->dim * 4, ix->dim * 4, b,
+                        hipMemcpyDefault, st));
+    a.queries = qrows;
+  } else {
+    a.queries = ix->vec32 + n0 * ix->stride;
+  }
   a.qstride = ix->stride;
   a.nq = (int)b;
   a.out_pool = pool;
@@ -552,6 +651,7 @@ struct RepairJob {
   const uint32_t* alive;
   int64_t n_slots;
   const float* vec32;
+  svf::HostSegs hsegs;        // tiered store: the FP32 rows (vec32 unused)
   int64_t stride;
   int dim, metric, R, cap, c_local, Lins, prec;
   bool uncut;                 // lists longer than cap go to the long-list kernels
@@ -566,6 +666,7 @@ RepairJob repair_job(svf_index* ix) {
   j.alive = ix->alive;
   j.n_slots = ix->n_slots;
   j.vec32 = ix->vec32;
+  j.hsegs = ix->tier.on ? ix->tier.segs() : svf::HostSegs{nullptr, 0};
   j.stride = ix->stride;
   j.dim = ix->dim;
   j.metric = ix->metric;
@@ -597,6 +698,7 @@ int repair_compute(const RepairJob& j, int consolidate, svf::RepairScratch& s, h
     return rc;
   svf::RepairArgs a{};
   a.vec32 = j.vec32;
+  a.hsegs = j.hsegs;
   a.stride = j.stride;
   a.dim = j.dim;
   a.metric = j.metric;
@@ -681,9 +783,17 @@ int repair_compute(const RepairJob& j, int consolidate, svf::RepairScratch& s, h
       q.queries = j.vec32;
       q.qstride = j.stride;
       q.qids = topup_v;
+      if (j.hsegs.seg) {
+        // tiered: the vertices' own rows are staged in HBM first
+        float* qrows;
+        if ((rc = scratch(s.qrows, (size_t)ntop * j.stride, &qrows))) return rc;
+        CK(svf::launch_gather_rows(j.hsegs, topup_v, ntop, j.stride, qrows, st));
+        q.queries = qrows;
+        q.qids = nullptr;
+      }
       q.nq = ntop;
       q.out_pool = pool;
-      CK(svf::launch_query_keys(j.vec32, j.stride, topup_v, j.dim, ntop, j.seed, qkey, st));
+      CK(svf::launch_query_keys(q.queries, j.stride, q.qids, j.dim, ntop, j.seed, qkey, st));
       q.qkey = qkey;
       CK(svf::launch_search(q, j.prec, st));
       CK(svf::launch_topup_merge(a, pool, j.Lins, (int)first, ntop, st));
@@ -1181,7 +1291,7 @@ int tier_apply(svf_index* ix, const std::vector<int32_t>& place, hipStream_t st)
   int rc = scratch(T.place, net.size(), &d);
   if (rc) return rc;
   CK(hipMemcpyAsync(d, net.data(), net.size() * 4, hipMemcpyHostToDevice, st));
-  CK(svf::launch_place(d, nn, ix->vec32, T.cache, ix->stride, T.map, st));
+  CK(svf::launch_place(d, nn, T.segs(), T.cache, ix->stride, T.map, st));
   CK(hipStreamSynchronize(st));
   return SVF_OK;
 }
@@ -1527,6 +1637,7 @@ int tier_enable(svf_index* ix, double bytes) {
   T.e_in_valid = false;
   T.used = 0;
   T.clock = 0;
+  T.seg_shift = host_seg_shift(ix);
   if (ix->n_slots == 0) {
     if (ix->vec32) (void)hipFree(ix->vec32);
     ix->vec32 = nullptr;
@@ -1535,26 +1646,35 @@ int tier_enable(svf_index* ix, double bytes) {
     ix->cap = 0;                      // re-create the stores in their tiered form
     return reserve(ix, std::max<int64_t>(cap, 1024));
   }
-  // a filled index: its FP32 store moves to pinned host memory, then the
+  // a filled index: its FP32 store moves to pinned host segments, then the
   // cache is warmed with the highest in-degree vectors
-  const size_t vbytes = (size_t)ix->cap * ix->stride * 4;
-  float* host = nullptr;
   int32_t* map = nullptr;
-  hipError_t e;
-  if ((e = hipHostMalloc((void**)&host, vbytes, 0)) != hipSuccess ||
-      (e = hipMalloc(&map, ix->cap * 4)) != hipSuccess ||
-      (e = hipMemcpyAsync(host, ix->vec32, vbytes, hipMemcpyDeviceToHost, ix->stream)) != hipSuccess ||
-      (e = svf::launch_fill_u32(map, ix->cap, 0xffffffffu, ix->stream)) != hipSuccess ||
-      (e = hipStreamSynchronize(ix->stream)) != hipSuccess) {
-    if (host) (void)hipHostFree(host);
+  hipError_t e = hipSuccess;
+  int rc = tier_grow_host(ix, ix->cap);
+  if (rc == SVF_OK) {
+    const int64_t S = int64_t(1) << T.seg_shift;
+    for (size_t i = 0; i < T.seg.size() && e == hipSuccess; ++i) {
+      const int64_t rows = std::min<int64_t>(T.seg_alloc[i], ix->cap - (int64_t)i * S);
+      e = hipMemcpyAsync(T.seg[i], ix->vec32 + (int64_t)i * S * ix->stride,
+                         (size_t)(rows * ix->stride * 4), hipMemcpyDeviceToHost, ix->stream);
+    }
+    if (e == hipSuccess && (e = hipMalloc(&map, ix->cap * 4)) == hipSuccess &&
+        (e = svf::launch_fill_u32(map, ix->cap, 0xffffffffu, ix->stream)) == hipSuccess)
+      e = hipStreamSynchronize(ix->stream);
+    if (e != hipSuccess) rc = hip_fail(e, "tiered store setup");
+  }
+  if (rc) {
+    for (float* p : T.seg) (void)hipHostFree(p);
+    T.seg.clear();
+    T.seg_alloc.clear();
     if (map) (void)hipFree(map);
     (void)hipFree(T.cache);
     T.cache = nullptr;
     T.C = 0;
-    return hip_fail(e, "tiered store setup");
+    return rc;
   }
   (void)hipFree(ix->vec32);
-  ix->vec32 = host;
+  ix->vec32 = nullptr;
   T.map = map;
   T.where.assign(ix->cap, -1);
   T.fr.assign(ix->cap, 0.0);
@@ -1614,7 +1734,8 @@ int svf_destroy(svf_index* ix) {
     if (ix->bg.st) (void)hipStreamDestroy(ix->bg.st);
     ix->bg.st = nullptr;
     if (ix->stream) (void)hipStreamSynchronize(ix->stream);
-    if (ix->vec32) (void)(ix->tier.on ? hipHostFree(ix->vec32) : hipFree(ix->vec32));
+    if (ix->vec32) (void)hipFree(ix->vec32);
+    for (float* p : ix->tier.seg) (void)hipHostFree(p);
     if (ix->veclp) (void)hipFree(ix->veclp);
     if (ix->graph) (void)hipFree(ix->graph);
     if (ix->edge_d) (void)hipFree(ix->edge_d);
@@ -1717,6 +1838,13 @@ int svf_set_option(svf_index* ix, const char* key, double v) {
   } else if (k == "cache_trace_cap") {
     if (!is_int(v) || v < 16 || v > 8192) return fail(SVF_E_INVAL, "cache_trace_cap in [16, 8192]");
     ix->tier.trace_cap = (int)v;
+  } else if (k == "host_segment_rows") {
+    if (ix->tier.on) return fail(SVF_E_BUSY, "host_segment_rows is set before cache_bytes");
+    // (the seed rows, at most 4 * degree <= 512, sit in the first segment)
+    if (v != 0 && (!is_int(v) || v < 1024 || v > (double)(1 << 30) ||
+                   ((int64_t)v & ((int64_t)v - 1)) != 0))
+      return fail(SVF_E_INVAL, "host_segment_rows 0 or a power of two in [1024, 2^30]");
+    ix->tier.seg_rows_opt = (int64_t)v;
   } else if (k == "precision") {
     if (v != 0 && v != 1 && v != 2 && v != 3)
       return fail(SVF_E_INVAL, "precision 0 (FP32), 1 (FP16), 2 (BF16) or 3 (FP8)");
@@ -1786,6 +1914,9 @@ int svf_get_option(const svf_index* ix, const char* key, double* out) {
   else if (k == "cache_trace_cap") *out = ix->tier.trace_cap;
   else if (k == "cache_policy") *out = ix->tier.policy;
   else if (k == "cache_indegree_verify") *out = ix->tier.verify_indegree;
+  else if (k == "host_segment_rows")
+    *out = ix->tier.on ? (double)(int64_t(1) << ix->tier.seg_shift) : (double)ix->tier.seg_rows_opt;
+  else if (k == "host_segments") *out = (double)ix->tier.seg.size();
   else if (k == "model_conf") *out = o.model_conf;
   else if (k == "model_stop_scale") *out = o.model_stop_scale;
   else if (k == "model_min_iters") *out = o.model_min_iters;
@@ -2046,6 +2177,9 @@ int svf_model_fit(svf_index* ix, const float* train_queries, int64_t n, int32_t 
   if (epochs < 1 || epochs > 1000) return fail(SVF_E_INVAL, "epochs in [1, 1000]");
   if (!all_finite(train_queries, n * ix->dim)) return fail(SVF_E_INVAL, "non-finite query value");
   std::lock_guard<std::mutex> g(ix->mu);
+  if (ix->tier.on)
+    return fail(SVF_E_INVAL, "the predictor is fitted on an index whose FP32 store is in HBM "
+                             "(not with cache_bytes)");
   if (ix->n_alive < 2 * n_clusters) return fail(SVF_E_INVAL, "index too small for the clusters");
   hipStream_t st = ix->stream;
   const int dim = ix->dim, nc = n_clusters, ecap = 64;
@@ -2258,14 +2392,16 @@ int svf_cache_calibrate(svf_index* ix, double* out) {
   };
   double ms_hit = 0, ms_miss = 0, ms_x = 0;
   int rc;
-  if ((rc = timed([&] { return svf::launch_probe_gather(T.cache, d_hit, ns, ix->stride, ix->dim,
-                                                        qbuf.as<float>(), obuf.as<float>(), st); },
+  if ((rc = timed([&] { return svf::launch_probe_gather(T.cache, svf::HostSegs{nullptr, 0}, d_hit,
+                                                        ns, ix->stride, ix->dim, qbuf.as<float>(),
+                                                        obuf.as<float>(), st); },
                   &ms_hit)) ||
-      (rc = timed([&] { return svf::launch_probe_gather(ix->vec32, d_miss, ns, ix->stride, ix->dim,
-                                                        qbuf.as<float>(), obuf.as<float>(), st); },
+      (rc = timed([&] { return svf::launch_probe_gather(nullptr, T.segs(), d_miss, ns, ix->stride,
+                                                        ix->dim, qbuf.as<float>(), obuf.as<float>(),
+                                                        st); },
                   &ms_miss)) ||
-      (rc = timed([&] { return svf::launch_probe_copy(ix->vec32, d_xfer, nx, ix->stride,
-                                                      dbuf.as<float>(), st); },
+      (rc = timed([&] { return svf::launch_gather_rows(T.segs(), d_xfer, nx, ix->stride,
+                                                       dbuf.as<float>(), st); },
                   &ms_x)))
     return rc;
   const double t_hit = ms_hit * 1e6 / ns, t_x = ms_x * 1e6 / nx;

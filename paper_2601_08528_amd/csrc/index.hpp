@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/svf.h"
+#include "kernels.hpp"
 #include "mlp.hpp"
 #include "wavp.hpp"
 
@@ -100,7 +101,7 @@ struct LongScratch {
 };
 
 struct RepairScratch {
-  DevBuf list, cnt, rows, rows_d, cand, mcount, topup, topup_v, qkey, pool;
+  DevBuf list, cnt, rows, rows_d, cand, mcount, topup, topup_v, qkey, pool, qrows;
   LongScratch lg;
 };
 
@@ -125,8 +126,16 @@ struct BgConsolidation {
 
 // Tiered vector store: every vector lives in pinned host memory; an HBM cache
 // of C rows, a device mapping table id -> slot, and the placement state.
+// The host store is a list of pinned segments of 2^seg_shift rows (each one
+// allocation, below the size one pinned allocation may take), so that it can
+// grow segment by segment up to what pinned memory holds in all.
 struct TierState {
   bool on = false;
+  std::vector<float*> seg;         // host segments; the last may hold fewer rows
+  std::vector<int64_t> seg_alloc;  // rows allocated per segment
+  int seg_shift = 0;
+  int64_t seg_rows_opt = 0;        // host_segment_rows option (0: by size)
+  DevBuf seg_d;                    // device copy of seg (the kernels' table)
   int64_t C = 0;
   float* cache = nullptr;          // device, C x stride
   int32_t* map = nullptr;          // device, cap entries (-1 = not cached)
@@ -173,6 +182,11 @@ struct TierState {
     return used < C ? used++ : -1;
   }
   int64_t free_count() const { return (int64_t)free_slots.size() + (C - used); }
+  // host address of row id of the segmented store
+  float* hrow(int64_t id, int64_t stride) const {
+    return seg[(size_t)(id >> seg_shift)] + (id & ((int64_t(1) << seg_shift) - 1)) * stride;
+  }
+  HostSegs segs() const { return HostSegs{seg_d.as<const float* const>(), seg_shift}; }
   int32_t in_degree(int32_t x) const { return e_in.as<int32_t>()[x]; }
 };
 }  // namespace svf
@@ -197,6 +211,7 @@ struct svf_index {
   std::mutex mu;
   // scratch
   svf::DevBuf s_q, s_qkey, s_ids, s_d, s_pool, s_tot, s_misc[12];
+  svf::DevBuf s_rows;                // FP32 rows staged in HBM for a tiered store's kernels
   // learned form
   svf::Mlp* model = nullptr;
   int model_nc = 0, entry_cap = 0;

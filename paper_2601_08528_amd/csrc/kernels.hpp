@@ -5,6 +5,18 @@
 
 namespace svf {
 
+// Rows of the tiered FP32 store: pinned host memory in segments of 2^shift
+// rows, segment i holding rows [i << shift, (i + 1) << shift).  seg is a
+// device-readable table of the segment bases (null: no segments).
+struct HostSegs {
+  const float* const* seg;
+  int shift;
+  __device__ __forceinline__ const float* row(int32_t id, int64_t stride) const {
+    const uint32_t u = (uint32_t)id;
+    return seg[u >> shift] + (int64_t)(u & ((1u << shift) - 1u)) * stride;
+  }
+};
+
 struct SearchArgs {
   // index snapshot
   const void* vec;          // traversal store: FP32 / FP16 / BF16 / FP8, n x vstride
@@ -44,7 +56,9 @@ struct SearchArgs {
   const int32_t* q_entry;      // per query: list index, or -1 for random entries
   const int32_t* q_max_iters;  // per query iteration cap (0: none)
   int32_t* last_change;        // per query: iterations done when the top-k last changed
-  // tiered vector store (FP32 traversal only): vec is the host-resident store
+  // tiered vector store: the FP32 rows sit in host segments (hsegs; vec and
+  // vec32 are then unused), an FP32 traversal reads through the cache
+  HostSegs hsegs;
   const int32_t* tmap;         // id -> HBM cache slot, -1 when not cached
   const float* tcache;         // cache rows, stride apart
   int32_t* trace;              // per query: expanded vertices in order (trace_cap each)
@@ -64,13 +78,15 @@ hipError_t launch_query_keys(const float* q, int64_t qstride, const int32_t* qid
 // ---- tiered store (tier.hip) ----
 hipError_t launch_indegree(const int32_t* graph, const uint32_t* alive, int64_t n, int R,
                            int32_t* e_in, hipStream_t st);
-hipError_t launch_place(const int32_t* place, int np, const float* store, float* cache,
+hipError_t launch_place(const int32_t* place, int np, HostSegs store, float* cache,
                         int64_t stride, int32_t* map, hipStream_t st);
 int64_t touched_blocks(int64_t words);
-hipError_t launch_probe_gather(const float* rows, const int32_t* idx, int n, int64_t stride,
-                               int dim, const float* q, float* out, hipStream_t st);
-hipError_t launch_probe_copy(const float* store, const int32_t* idx, int n, int64_t stride,
-                             float* dst, hipStream_t st);
+// rows: an HBM array (hs.seg null) or the host segments
+hipError_t launch_probe_gather(const float* rows, HostSegs hs, const int32_t* idx, int n,
+                               int64_t stride, int dim, const float* q, float* out, hipStream_t st);
+// Listed rows of the host segments copied into dst (n rows, stride apart).
+hipError_t launch_gather_rows(HostSegs store, const int32_t* idx, int n, int64_t stride,
+                              float* dst, hipStream_t st);
 hipError_t launch_touched_count(const uint32_t* touched, int64_t words, int32_t* block_tot,
                                 hipStream_t st);
 hipError_t launch_touched_list(const uint32_t* touched, int64_t words, const int32_t* block_off,
@@ -81,7 +97,9 @@ hipError_t launch_trace_count(const int32_t* trace, const int32_t* trace_n, int 
 
 // ---- index maintenance (update.hip) ----
 hipError_t launch_fill_u32(void* p, int64_t n, uint32_t v, hipStream_t st);
-hipError_t launch_store_lowp(const float* vec32, int64_t stride, int dim, void* veclp,
+// Reduced-precision rows [row0, row0 + nrows) of the traversal store from the
+// FP32 rows at src (row row0 first, stride apart).
+hipError_t launch_store_lowp(const float* src, int64_t stride, int dim, void* veclp,
                              int64_t lp_stride, float* vscale, int64_t row0, int64_t nrows,
                              int precision, hipStream_t st);
 hipError_t launch_seed(const float* vec32, int64_t stride, int dim, int metric, int s0, int R,
@@ -165,6 +183,7 @@ hipError_t launch_commit_batch(const ReverseArgs& a, int n_targets, int32_t* gra
 
 struct RepairArgs {
   const float* vec32;
+  HostSegs hsegs;           // tiered store: the FP32 rows (vec32 unused)
   int64_t stride;
   int dim, metric, R;
   const int32_t* graph;

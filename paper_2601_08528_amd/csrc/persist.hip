@@ -95,7 +95,11 @@ int svf_save(const svf_index* cix, const char* path) {
   {
     std::lock_guard<std::mutex> g(ix->mu);
     CK(hipStreamSynchronize(ix->stream));
-    if (n > 0) {
+    if (n > 0 && ix->tier.on) {
+      // pinned host segments: copied row by row on the host
+      for (int64_t i = 0; i < n; ++i)
+        std::memcpy(vecs.data() + i * ix->dim, ix->tier.hrow(i, ix->stride), (size_t)ix->dim * 4);
+    } else if (n > 0) {
       CK(hipMemcpy2D(vecs.data(), ix->dim * 4, ix->vec32, ix->stride * 4, ix->dim * 4, n,
                      hipMemcpyDefault));
     }

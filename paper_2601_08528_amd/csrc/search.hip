@@ -45,9 +45,10 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
   w.cid = reinterpret_cast<int32_t*>(w.kept + kWave);
   int32_t* slot = w.cid + kWave;                 // tier slots of the survivors
   void* vis_mem = reinterpret_cast<void*>(slot + kWave);
-  // With a tier the FP32 store sits in host memory behind an HBM cache.  An
-  // FP32 traversal reads through the cache; a reduced-precision traversal
-  // store stays in HBM and only the exact re-scoring reads go through it.
+  // With a tier the FP32 store sits in host memory (segments a.hsegs) behind
+  // an HBM cache.  An FP32 traversal reads through the cache; a
+  // reduced-precision traversal store stays in HBM and only the exact
+  // re-scoring reads go through it.
   constexpr bool tier = TIER && sizeof(VT) == 4;
   // the traversal's gather: branch-free rounds for unscaled rows in HBM,
   // without any per-lane test when the rows fill their chunks (FULL)
@@ -105,7 +106,8 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
         t_miss += nt - popc64(ballot(h));
       }
       uint64_t k = gather_keys<VT, NC, tier, form>(qs, base, a.vstride, w.cid, nt, a.metric, slot,
-                                             reinterpret_cast<const VT*>(a.tcache), a.vscale);
+                                             reinterpret_cast<const VT*>(a.tcache), a.vscale,
+                                             a.hsegs);
       n_dist += nt;
       sort_merge(w, k);
     };
@@ -208,7 +210,7 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
         }
         const uint64_t k = gather_keys<VT, NC, tier, form>(qs, base, a.vstride, w.cid, m, a.metric,
                                                      slot, reinterpret_cast<const VT*>(a.tcache),
-                                                     a.vscale);
+                                                     a.vscale, a.hsegs);
         n_dist += m;
         if (sort_merge(w, k)) last_change = n_iter;
       }
@@ -240,7 +242,7 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
         t_miss += m - popc64(ballot(h));
       }
       const uint64_t k = gather_keys<float, NC, TIER>(q32, a.vec32, a.stride, w.cid, m, a.metric,
-                                                      slot, a.tcache);
+                                                      slot, a.tcache, nullptr, a.hsegs);
       if (lane < m) buf[c0 + lane] = k;
       else if (c0 + lane < Lp) buf[c0 + lane] = kKeyInf;
       __syncthreads();

@@ -34,13 +34,12 @@ hipError_t launch_indegree(const int32_t* graph, const uint32_t* alive, int64_t 
 // the cache slot, then the mapping entries of both ids are updated (a new id
 // of -1 only releases the slot).  No two placements of one batch share a slot
 // or an id.
-__global__ void place_kernel(const int32_t* __restrict__ place, int64_t np,
-                             const float* __restrict__ store, float* __restrict__ cache,
-                             int64_t stride, int32_t* __restrict__ map) {
+__global__ void place_kernel(const int32_t* __restrict__ place, int64_t np, HostSegs store,
+                             float* __restrict__ cache, int64_t stride, int32_t* __restrict__ map) {
   for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
     const int32_t slot = place[3 * p], nid = place[3 * p + 1], oid = place[3 * p + 2];
     if (nid >= 0) {
-      const float* src = store + (int64_t)nid * stride;
+      const float* src = store.row(nid, stride);
       float* dst = cache + (int64_t)slot * stride;
       for (int64_t e = threadIdx.x; e < stride; e += blockDim.x) dst[e] = src[e];
     }
@@ -52,7 +51,7 @@ __global__ void place_kernel(const int32_t* __restrict__ place, int64_t np,
     }
   }
 }
-hipError_t launch_place(const int32_t* place, int np, const float* store, float* cache,
+hipError_t launch_place(const int32_t* place, int np, HostSegs store, float* cache,
                         int64_t stride, int32_t* map, hipStream_t st) {
   if (np <= 0) return hipSuccess;
   hipLaunchKernelGGL(place_kernel, dim3((unsigned)std::min<int64_t>(np, kMaxBlocks)), dim3(128), 0, st,
@@ -61,17 +60,18 @@ hipError_t launch_place(const int32_t* place, int np, const float* store, float*
 }
 
 // Cost probe for the placement threshold (Sec. 4.3): one wave per listed
-// row computes the squared L2 distance between that row of `rows` and q, as
-// a search gather does; `rows` is the HBM cache (a hit) or the host-resident
-// store read over the host link (a miss).
+// row computes the squared L2 distance between that row and q, as a search
+// gather does; the rows are the HBM cache (a hit, hs.seg null) or the host
+// segments read over the host link (a miss).
 __global__ __launch_bounds__(256) void probe_gather_kernel(const float* __restrict__ rows,
+                                                           HostSegs hs,
                                                            const int32_t* __restrict__ idx, int n,
                                                            int64_t stride, int dim,
                                                            const float* __restrict__ q,
                                                            float* __restrict__ out) {
   const int w = (int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
   if (w >= n) return;
-  const float* r = rows + (int64_t)idx[w] * stride;
+  const float* r = hs.seg ? hs.row(idx[w], stride) : rows + (int64_t)idx[w] * stride;
   float acc = 0.f;
   for (int e = lane_id(); e < dim; e += kWave) {
     const float d = r[e] - q[e];
@@ -80,29 +80,30 @@ __global__ __launch_bounds__(256) void probe_gather_kernel(const float* __restri
   for (int o = kWave / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
   if (lane_id() == 0) out[w] = acc;
 }
-hipError_t launch_probe_gather(const float* rows, const int32_t* idx, int n, int64_t stride,
-                               int dim, const float* q, float* out, hipStream_t st) {
+hipError_t launch_probe_gather(const float* rows, HostSegs hs, const int32_t* idx, int n,
+                               int64_t stride, int dim, const float* q, float* out, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(probe_gather_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, rows, idx,
-                     n, stride, dim, q, out);
+  hipLaunchKernelGGL(probe_gather_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, rows, hs,
+                     idx, n, stride, dim, q, out);
   return hipGetLastError();
 }
 
-// Cost probe of a promotion: listed rows of the host-resident store copied
-// into a device buffer, one workgroup per row, as the placement kernel does.
-__global__ void probe_copy_kernel(const float* __restrict__ store, const int32_t* __restrict__ idx,
-                                  int n, int64_t stride, float* __restrict__ dst) {
+// Listed rows of the host segments copied into a device buffer, one
+// workgroup per row, as the placement kernel copies them (also the cost
+// probe of a promotion).
+__global__ void gather_rows_kernel(HostSegs store, const int32_t* __restrict__ idx, int n,
+                                   int64_t stride, float* __restrict__ dst) {
   for (int64_t p = blockIdx.x; p < n; p += gridDim.x) {
-    const float* src = store + (int64_t)idx[p] * stride;
+    const float* src = store.row(idx[p], stride);
     float* d = dst + p * stride;
     for (int64_t e = threadIdx.x; e < stride; e += blockDim.x) d[e] = src[e];
   }
 }
-hipError_t launch_probe_copy(const float* store, const int32_t* idx, int n, int64_t stride,
-                             float* dst, hipStream_t st) {
+hipError_t launch_gather_rows(HostSegs store, const int32_t* idx, int n, int64_t stride, float* dst,
+                              hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(probe_copy_kernel, dim3((unsigned)std::min<int64_t>(n, kMaxBlocks)), dim3(128), 0,
-                     st, store, idx, n, stride, dst);
+  hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)std::min<int64_t>(n, kMaxBlocks)), dim3(128),
+                     0, st, store, idx, n, stride, dst);
   return hipGetLastError();
 }
 

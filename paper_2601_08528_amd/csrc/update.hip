@@ -331,14 +331,13 @@ __global__ __launch_bounds__(256) void store_fp8_kernel(const float* __restrict_
   }
 }
 
-hipError_t launch_store_lowp(const float* vec32, int64_t stride, int dim, void* veclp,
+hipError_t launch_store_lowp(const float* src, int64_t stride, int dim, void* veclp,
                              int64_t lp_stride, float* vscale, int64_t row0, int64_t nrows,
                              int precision, hipStream_t st) {
   if (nrows <= 0 || precision == 0) return hipSuccess;
   if (precision == 3) {
     const int64_t blocks = std::min<int64_t>((nrows + 3) / 4, kMaxBlocks);
-    hipLaunchKernelGGL(store_fp8_kernel, dim3((unsigned)blocks), dim3(256), 0, st,
-                       vec32 + row0 * stride, stride, dim,
+    hipLaunchKernelGGL(store_fp8_kernel, dim3((unsigned)blocks), dim3(256), 0, st, src, stride, dim,
                        static_cast<uint8_t*>(veclp) + row0 * lp_stride, lp_stride, vscale + row0,
                        nrows);
     return hipGetLastError();
@@ -346,9 +345,8 @@ hipError_t launch_store_lowp(const float* vec32, int64_t stride, int dim, void* 
   const int64_t n = nrows * stride;
   int64_t blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(store_lowp_kernel, dim3((unsigned)blocks), dim3(256), 0, st,
-                     vec32 + row0 * stride, static_cast<uint16_t*>(veclp) + row0 * stride, n,
-                     precision);
+  hipLaunchKernelGGL(store_lowp_kernel, dim3((unsigned)blocks), dim3(256), 0, st, src,
+                     static_cast<uint16_t*>(veclp) + row0 * stride, n, precision);
   return hipGetLastError();
 }
 
@@ -810,7 +808,7 @@ hipError_t launch_affected(const RepairArgs& a, hipStream_t st) {
 // (repeats included) is queued as overflowing, with that count; RAW = true
 // runs the same walk for the queued lists and writes every offered key to
 // the long-list staging area instead.
-template <int NC, bool RAW>
+template <int NC, bool RAW, bool SEG>
 __global__ __launch_bounds__(64) void repair_candidates_kernel(RepairArgs a, int first, int count,
                                                                LongLists L) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -836,8 +834,14 @@ __global__ __launch_bounds__(64) void repair_candidates_kernel(RepairArgs a, int
   w.tmask = (uint32_t)H - 1u;
   if (!RAW) for (int i = lane; i < 2 * cap; i += kWave) w.pool[i] = kKeyInf;
   if (exact) for (int i = lane; i < H; i += kWave) w.vis[i] = kEmpty;
+  // vectors: the FP32 store in HBM, or the tiered store's host segments (SEG)
+  const float* xv = SEG ? a.hsegs.row(v, a.stride) : a.vec32 + (int64_t)v * a.stride;
+  auto gather = [&](const QuerySlice<float, NC>& qs, int m) {
+    return gather_keys<float, NC, SEG>(qs, a.vec32, a.stride, w.cid, m, a.metric, nullptr, nullptr,
+                                       nullptr, a.hsegs);
+  };
   QuerySlice<float, NC> q;
-  q.load(a.vec32 + (int64_t)v * a.stride, a.dim, lane % QuerySlice<float, NC>::kLanesPerVec);
+  q.load(xv, a.dim, lane % QuerySlice<float, NC>::kLanesPerVec);
   __syncthreads();
   auto take = [&](uint64_t k, int m) {
     if constexpr (RAW) {
@@ -857,7 +861,7 @@ __global__ __launch_bounds__(64) void repair_candidates_kernel(RepairArgs a, int
     const uint64_t ob = ballot(ok);
     if (ok) w.cid[lanes_below(ob)] = u;
     __syncthreads();
-    uint64_t k = gather_keys<float, NC>(q, a.vec32, a.stride, w.cid, popc64(ob), a.metric);
+    uint64_t k = gather(q, popc64(ob));
     take(k, popc64(ob));
   }
   // entries of deleted neighbours
@@ -882,7 +886,7 @@ __global__ __launch_bounds__(64) void repair_candidates_kernel(RepairArgs a, int
       taken += popc64(ob);
       __syncthreads();
       if (ob == 0) continue;
-      uint64_t k = gather_keys<float, NC>(q, a.vec32, a.stride, w.cid, popc64(ob), a.metric);
+      uint64_t k = gather(q, popc64(ob));
       take(k, popc64(ob));
     }
   }
@@ -903,20 +907,26 @@ __global__ __launch_bounds__(64) void repair_candidates_kernel(RepairArgs a, int
     }
   }
 }
+template <bool RAW, bool SEG>
+static void launch_repair_nc(const RepairArgs& a, int first, int count, const LongLists& L,
+                             size_t lds, hipStream_t st) {
+  const int chunks = (int)((a.stride + 127) / 128);
+  dim3 g(count), b(kWave);
+  switch (chunks <= 1 ? 1 : chunks <= 2 ? 2 : chunks <= 4 ? 4 : 8) {
+    case 1: hipLaunchKernelGGL((repair_candidates_kernel<1, RAW, SEG>), g, b, lds, st, a, first, count, L); break;
+    case 2: hipLaunchKernelGGL((repair_candidates_kernel<2, RAW, SEG>), g, b, lds, st, a, first, count, L); break;
+    case 4: hipLaunchKernelGGL((repair_candidates_kernel<4, RAW, SEG>), g, b, lds, st, a, first, count, L); break;
+    default: hipLaunchKernelGGL((repair_candidates_kernel<8, RAW, SEG>), g, b, lds, st, a, first, count, L); break;
+  }
+}
 hipError_t launch_repair_candidates(const RepairArgs& a, int first, int count, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   int H = 64;
   if (a.c < a.R) while (H < 2 * a.R * (1 + a.c)) H <<= 1;
   const size_t lds = (size_t)(2 * a.cap + kWave) * 8 + kWave * 4 + (size_t)H * 4;
-  const int chunks = (int)((a.stride + 127) / 128);
-  dim3 g(count), b(kWave);
   const LongLists L{};
-  switch (chunks <= 1 ? 1 : chunks <= 2 ? 2 : chunks <= 4 ? 4 : 8) {
-    case 1: hipLaunchKernelGGL((repair_candidates_kernel<1, false>), g, b, lds, st, a, first, count, L); break;
-    case 2: hipLaunchKernelGGL((repair_candidates_kernel<2, false>), g, b, lds, st, a, first, count, L); break;
-    case 4: hipLaunchKernelGGL((repair_candidates_kernel<4, false>), g, b, lds, st, a, first, count, L); break;
-    default: hipLaunchKernelGGL((repair_candidates_kernel<8, false>), g, b, lds, st, a, first, count, L); break;
-  }
+  if (a.hsegs.seg) launch_repair_nc<false, true>(a, first, count, L, lds, st);
+  else launch_repair_nc<false, false>(a, first, count, L, lds, st);
   return hipGetLastError();
 }
 hipError_t launch_repair_raw(const RepairArgs& a, int first, const LongLists& L, hipStream_t st) {
@@ -924,14 +934,8 @@ hipError_t launch_repair_raw(const RepairArgs& a, int first, const LongLists& L,
   int H = 64;
   if (a.c < a.R) while (H < 2 * a.R * (1 + a.c)) H <<= 1;
   const size_t lds = (size_t)kWave * 4 + (size_t)H * 4;
-  const int chunks = (int)((a.stride + 127) / 128);
-  dim3 g(L.n), b(kWave);
-  switch (chunks <= 1 ? 1 : chunks <= 2 ? 2 : chunks <= 4 ? 4 : 8) {
-    case 1: hipLaunchKernelGGL((repair_candidates_kernel<1, true>), g, b, lds, st, a, first, L.n, L); break;
-    case 2: hipLaunchKernelGGL((repair_candidates_kernel<2, true>), g, b, lds, st, a, first, L.n, L); break;
-    case 4: hipLaunchKernelGGL((repair_candidates_kernel<4, true>), g, b, lds, st, a, first, L.n, L); break;
-    default: hipLaunchKernelGGL((repair_candidates_kernel<8, true>), g, b, lds, st, a, first, L.n, L); break;
-  }
+  if (a.hsegs.seg) launch_repair_nc<true, true>(a, first, L.n, L, lds, st);
+  else launch_repair_nc<true, false>(a, first, L.n, L, lds, st);
   return hipGetLastError();
 }
 

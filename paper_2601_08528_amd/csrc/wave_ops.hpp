@@ -3,6 +3,7 @@
 // and the rank-based (merge path) update of a sorted key list.
 #pragma once
 #include "common.hpp"
+#include "kernels.hpp"
 
 namespace svf {
 
@@ -275,7 +276,7 @@ template <typename VT, int NC, bool TIER, int FORM>
 __device__ inline float gather_rounds(const QuerySlice<VT, NC>& qs, const VT* __restrict__ base,
                                       int64_t stride, const int32_t* cid, int m, int metric,
                                       const int32_t* slot, const VT* __restrict__ tcache,
-                                      const float* __restrict__ vscale) {
+                                      const float* __restrict__ vscale, HostSegs hs) {
   constexpr bool kScaled = Elem<VT>::kScaled;
   using QS = QuerySlice<VT, NC>;
   constexpr int E = QS::E;
@@ -303,10 +304,11 @@ __device__ inline float gather_rounds(const QuerySlice<VT, NC>& qs, const VT* __
       const bool on = j < m;
       if constexpr (TIER) {
         const int32_t id = on ? cid[j] : 0;
-        const VT* row = base + (uint64_t)(uint32_t)id * ustride;
+        const VT* row = hs.seg ? reinterpret_cast<const VT*>(hs.row(id, stride))
+                               : base + (uint64_t)(uint32_t)id * ustride;
         if constexpr (kScaled) xs[u] = on ? vscale[id] : 0.0f;
         else xs[u] = 1.0f;
-        const int32_t sl_ = on ? slot[j] : -1;
+        const int32_t sl_ = on && slot ? slot[j] : -1;
         if (sl_ >= 0) row = tcache + (uint64_t)(uint32_t)sl_ * ustride;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
@@ -368,19 +370,21 @@ __device__ inline float gather_rounds(const QuerySlice<VT, NC>& qs, const VT* __
 // A kernel inlines one form only: with two, the compiler keeps the step arrays
 // in scratch memory.
 // With a tier (TIER), vector j is read from tcache row slot[j] when that slot
-// is >= 0 and from base row cid[j] otherwise.  A scaled (FP8) store reads the
+// is >= 0 (slot may be null: no cache) and otherwise from row cid[j] of the
+// host segments hs, or of base when hs has none.  A scaled (FP8) store reads the
 // vector's scale from vscale[id] with its row.
 template <typename VT, int NC, bool TIER = false, int FORM = 0>
 __device__ inline uint64_t gather_keys(const QuerySlice<VT, NC>& qs, const VT* __restrict__ base,
                                        int64_t stride, const int32_t* cid, int m, int metric,
                                        const int32_t* slot = nullptr,
                                        const VT* __restrict__ tcache = nullptr,
-                                       const float* __restrict__ vscale = nullptr) {
+                                       const float* __restrict__ vscale = nullptr,
+                                       HostSegs hs = HostSegs{nullptr, 0}) {
   constexpr bool kScaled = Elem<VT>::kScaled;
   static_assert(FORM == 0 || (!TIER && !kScaled), "gather form");
   const int lane = lane_id();
   const float mine =
-      gather_rounds<VT, NC, TIER, FORM>(qs, base, stride, cid, m, metric, slot, tcache, vscale);
+      gather_rounds<VT, NC, TIER, FORM>(qs, base, stride, cid, m, metric, slot, tcache, vscale, hs);
   if (lane >= m) return kKeyInf;
   float x = mine;
   if (kScaled && metric != 0) x *= vscale[cid[lane]];

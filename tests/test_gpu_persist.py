@@ -49,6 +49,28 @@ def test_round_trip_and_continued_updates(tmp_path):
         np.testing.assert_array_equal(a, b)
 
 
+def test_tiered_segmented_store_round_trip(tmp_path):
+    """A tiered index whose host store spans four 1024-row segments saves the
+    vectors of every segment: the loaded (untiered) index has the same graph
+    and answers searches identically."""
+    base, q = datagen.gmm_uint8_valued(802, 3600, 60, 48, 10)
+    g = svf.Index(48, 16, svf.METRIC_L2, seed=3, insert_batch_max=400)
+    g.set_option("host_segment_rows", 1024)
+    g.set_option("cache_bytes", 600 * 48 * 4)
+    g.build(base[:3300])
+    g.delete(np.arange(0, 3300, 13, dtype=np.int32))
+    assert g.get_option("host_segments") == 4
+    path = str(tmp_path / "tiered.svf")
+    g.save(path)
+    h = svf.Index.load(path)
+    for a, b in zip(g.export_graph(), h.export_graph()):
+        np.testing.assert_array_equal(a, b)
+    gi, gd = g.search(q, 10, 40)
+    hi, hd = h.search(q, 10, 40)
+    np.testing.assert_array_equal(gi, hi)
+    np.testing.assert_array_equal(gd, hd)
+
+
 def test_damaged_files_are_refused(tmp_path):
     g, _, _ = make_index()
     path = str(tmp_path / "index.svf")

@@ -16,6 +16,7 @@ pytestmark = pytest.mark.gpu
 def tiered_from_oracle(oix, base, cache_rows, **opts):
     rows, ed, alive = oix.export()
     g = svf.Index(base.shape[1], oix.R, oix.metric, seed=opts.pop("seed", 0))
+    g.set_option("host_segment_rows", opts.pop("host_segment_rows", 0))
     g.set_option("cache_bytes", cache_rows * 4 * ((base.shape[1] + 7) // 8 * 8))
     for k, v in opts.items():
         g.set_option(k, v)
@@ -29,10 +30,14 @@ def state():
     return oracle_index(base, 24, seed=6), base, q
 
 
-def test_results_independent_of_cache(state):
+@pytest.mark.parametrize("seg_rows", [0, 1024])
+def test_results_independent_of_cache(state, seg_rows):
+    """With one host segment or with 1024-row segments (6000 vectors span six
+    of them), every search equals the oracle."""
     oix, base, q = state
     ref_i, ref_d, _ = oix.search(q, 10, 48)
-    g = tiered_from_oracle(oix, base, 600, seed=6)
+    g = tiered_from_oracle(oix, base, 600, seed=6, host_segment_rows=seg_rows)
+    assert g.get_option("host_segments") == (1 if seg_rows == 0 else 6)
     for b in range(4):
         gi, gd = g.search(q[b * 100:(b + 1) * 100], 10, 48)
         np.testing.assert_array_equal(gi, ref_i[b * 100:(b + 1) * 100])
@@ -76,10 +81,15 @@ def test_placement_matches_oracle_replay(state, theta, cap_rows, promote, adapt)
     assert g.stats()["cache_evictions"] > 0
 
 
-def test_updates_on_tiered_store_bit_exact():
+@pytest.mark.parametrize("seg_rows", [0, 1024])
+def test_updates_on_tiered_store_bit_exact(seg_rows):
+    """Build, insert and delete (with repair and consolidation) on a tiered
+    store give the untiered graph; with 1024-row host segments insertion
+    batches and repair candidate lists cross segment boundaries."""
     base, q = datagen.gmm_uint8_valued(702, 3500, 60, 32, 8)
     plain = svf.Index(32, 12, svf.METRIC_L2, seed=2, insert_batch_max=400)
     tier = svf.Index(32, 12, svf.METRIC_L2, seed=2, insert_batch_max=400)
+    tier.set_option("host_segment_rows", seg_rows)
     tier.set_option("cache_bytes", 500 * 32 * 4)
     for g in (plain, tier):
         g.build(base[:3000])
@@ -89,6 +99,8 @@ def test_updates_on_tiered_store_bit_exact():
         np.testing.assert_array_equal(a, b)
     np.testing.assert_array_equal(plain.search(q, 10, 32)[0], tier.search(q, 10, 32)[0])
     assert tier.stats()["cache_slots"] == 500
+    if seg_rows:
+        assert tier.get_option("host_segments") >= 4
 
 
 def _warm_set(rows, alive, c):
@@ -142,11 +154,13 @@ def test_cache_slots_follow_updates(cap_rows):
     np.testing.assert_array_equal(plain.search(q, 10, 32)[0], tier.search(q, 10, 32)[0])
 
 
-def test_tiering_a_filled_index_warm_start_matches_replay():
+@pytest.mark.parametrize("seg_rows", [0, 1024])
+def test_tiering_a_filled_index_warm_start_matches_replay(seg_rows):
     """cache_bytes on a filled index (with deleted vectors): the FP32 store moves
-    to host memory, the cache is warmed with the highest in-degree alive
-    vectors, results stay those of the untiered index, and the placements of
-    the following batches equal the oracle's replay from the same warm start."""
+    to host memory (one segment, or four of 1024 rows), the cache is warmed
+    with the highest in-degree alive vectors, results stay those of the
+    untiered index, and the placements of the following batches equal the
+    oracle's replay from the same warm start."""
     base, q = datagen.gmm_uint8_valued(703, 4000, 400, 48, 16)
     oix = oracle_index(base, 16, seed=8)
     oix.delete(np.arange(0, 4000, 11, dtype=np.int32))
@@ -157,8 +171,10 @@ def test_tiering_a_filled_index_warm_start_matches_replay():
     cap_rows, trace_cap, theta = 250, 64, 1.0
     g.set_option("cache_trace_cap", trace_cap)
     g.set_option("cache_theta", theta)
+    g.set_option("host_segment_rows", seg_rows)
     g.set_option("cache_bytes", cap_rows * 4 * 48)
     assert g.stats()["cache_promotions"] == cap_rows          # warm-up filled every slot
+    assert g.get_option("host_segments") == (1 if seg_rows == 0 else 4)
     e_in = np.zeros(len(alive), np.int64)
     src = rows[alive.astype(bool)]
     np.add.at(e_in, src[src >= 0], 1)
@@ -179,8 +195,9 @@ def test_tiering_a_filled_index_warm_start_matches_replay():
     assert got[0] > 0
 
 
-@pytest.mark.parametrize("prec", [svf.PREC_FP8, svf.PREC_BF16])
-def test_reduced_precision_traversal_with_tiered_rescoring(prec):
+@pytest.mark.parametrize("prec,seg_rows", [(svf.PREC_FP8, 0), (svf.PREC_BF16, 0),
+                                           (svf.PREC_FP8, 1024)])
+def test_reduced_precision_traversal_with_tiered_rescoring(prec, seg_rows):
     """A reduced-precision traversal store stays in HBM; only the exact FP32
     re-scoring goes through the cache.  Results equal the oracle's bit for
     bit (the data is exact on both grids), every re-scoring read is either a
@@ -190,7 +207,7 @@ def test_reduced_precision_traversal_with_tiered_rescoring(prec):
     oix.set("precision", O.P_FP8 if prec == svf.PREC_FP8 else O.P_BF16)
     L, cap_rows, trace_cap = 32, 400, 64
     g = tiered_from_oracle(oix, base, cap_rows, seed=9, precision=prec,
-                           cache_trace_cap=trace_cap)
+                           cache_trace_cap=trace_cap, host_segment_rows=seg_rows)
     rows, _, alive = oix.export()
     e_in = np.zeros(len(alive), np.int64)
     src = rows[alive.astype(bool)]
@@ -284,14 +301,15 @@ def test_kept_in_degrees_match_a_recount_under_updates():
     assert g.get_option("cache_indegree_verify") == 1
 
 
-@pytest.mark.parametrize("cpu_miss", [0, 1])
-def test_theta_from_measured_costs(state, cpu_miss):
+@pytest.mark.parametrize("cpu_miss,seg_rows", [(0, 0), (1, 0), (0, 1024), (1, 1024)])
+def test_theta_from_measured_costs(state, cpu_miss, seg_rows):
     """Sec. 4.3: theta = T_transfer / (T_miss - T_hit) from probes on this
     machine (T_miss: a host-core distance with co-processing, else a GPU
     read across the host link); the threshold is set from it and a miss
     costs more than a cached distance."""
     oix, base, q = state
-    g = tiered_from_oracle(oix, base, 1000, seed=6, cache_cpu_miss=cpu_miss)
+    g = tiered_from_oracle(oix, base, 1000, seed=6, cache_cpu_miss=cpu_miss,
+                           host_segment_rows=seg_rows)
     g.search(q[:100], 10, 32)
     c = g.cache_calibrate()
     assert 0 < c["t_hit_ns"] < c["t_miss_ns"]
@@ -302,8 +320,8 @@ def test_theta_from_measured_costs(state, cpu_miss):
     np.testing.assert_array_equal(gi, oix.search(q[:100], 10, 32)[0])
 
 
-@pytest.mark.parametrize("policy", [0, 2])
-def test_cpu_miss_path_matches_oracle_and_placement_replay(state, policy):
+@pytest.mark.parametrize("policy,seg_rows", [(0, 0), (2, 0), (0, 1024)])
+def test_cpu_miss_path_matches_oracle_and_placement_replay(state, policy, seg_rows):
     """Alg. 1's co-processing: uncached neighbours' distances on the host
     cores, cached ones on the GPU.  Results equal the oracle's bit for bit,
     expansion counts equal the one-kernel search's, hits plus misses cover
@@ -313,7 +331,7 @@ def test_cpu_miss_path_matches_oracle_and_placement_replay(state, policy):
     trace_cap = 64
     cap_rows = 300
     g = tiered_from_oracle(oix, base, cap_rows, seed=6, cache_trace_cap=trace_cap,
-                           cache_policy=policy, cache_cpu_miss=1)
+                           cache_policy=policy, cache_cpu_miss=1, host_segment_rows=seg_rows)
     ref = tiered_from_oracle(oix, base, cap_rows, seed=6, cache_trace_cap=trace_cap,
                              cache_policy=policy)
     rows, _, alive = oix.export()
