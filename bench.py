@@ -688,7 +688,7 @@ def full_tier_bench(torch, svf, datagen, n_base, cache_gb=None, steps=8, sample=
     try:
         ix.set_option("cache_bytes", cache_gb * 1e9)
     except svf.SvfError as e:
-        # the FP32 store goes to one pinned host allocation; hosts cap its size
+        # the FP32 store goes to pinned host segments; hosts cap pinned memory in all
         out["tiered"] = "not set up: %s" % e
         log("full tier: %s" % e)
         ix.close()

@@ -46,14 +46,16 @@ struct RowSource {
 };
 
 // Candidate id -> position table of the prune: S slots (a power of two) of
-// (position << 32) | id with linear probing, followed by a copy of the first
-// kProbeMax slots so that a lookup reads consecutive slots without wrapping.
-// dmax is the largest distance of an inserted id from its home slot; a lookup
-// that reads the dmax + 1 slots from the home slot finds any inserted id.
+// ids with linear probing, each with its candidate's position in a second
+// array, followed by a copy of the first kProbeMax slots of both so that a
+// lookup reads consecutive slots without wrapping.  dmax is the largest
+// distance of an inserted id from its home slot; a lookup that reads the
+// dmax + 1 slots from the home slot finds any inserted id.  A lookup reads
+// 4-byte ids and fetches a position only on a hit.
 constexpr int kProbeMax = 8;
-constexpr uint64_t kTabEmpty = ~0ull;
 struct PruneLds {
-  uint64_t* tab;    // S + kProbeMax slots
+  uint32_t* mkey;   // S + kProbeMax slots (kEmpty when free)
+  uint32_t* mval;   // S + kProbeMax positions
   uint32_t* cnt;    // cap
   uint32_t* hist;   // cap + 1
   uint32_t* dmax;   // 1
@@ -65,14 +67,14 @@ struct PruneLds {
 // slot, with no data-dependent branch.
 template <int N>
 __device__ __forceinline__ int tab_find(const PruneLds& s, uint32_t home, int32_t e) {
-  uint64_t w[N];
+  uint32_t w[N];
 #pragma unroll
-  for (int d = 0; d < N; ++d) w[d] = s.tab[home + d];
-  int pos = -1;
+  for (int d = 0; d < N; ++d) w[d] = s.mkey[home + d];
+  int hit = -1;
 #pragma unroll
   for (int d = 0; d < N; ++d)
-    if ((uint32_t)w[d] == (uint32_t)e) pos = (int)(w[d] >> 32);
-  return e >= 0 ? pos : -1;
+    if (w[d] == (uint32_t)e) hit = (int)home + d;
+  return (e >= 0 && hit >= 0) ? (int)s.mval[hit] : -1;
 }
 // The same with any displacement (a probe loop that stops at an empty slot).
 __device__ __forceinline__ int tab_find_loop(const PruneLds& s, uint32_t home, int32_t e,
@@ -80,9 +82,9 @@ __device__ __forceinline__ int tab_find_loop(const PruneLds& s, uint32_t home, i
   if (e < 0) return -1;
   uint32_t sl = home;
   for (;;) {
-    const uint64_t w = s.tab[sl];
-    if ((uint32_t)w == (uint32_t)e) return (int)(w >> 32);
-    if (w == kTabEmpty) return -1;
+    const uint32_t k = s.mkey[sl];
+    if (k == (uint32_t)e) return (int)s.mval[sl];
+    if (k == kEmpty) return -1;
     sl = (sl + 1) & mask;
   }
 }
@@ -118,24 +120,26 @@ __device__ void prune_core(const uint64_t* keys, int m, const RowSource& rs, int
   int tau = 0, need = 0;
   const bool full = m > R;
   if (full) {
-    for (int i = lane; i < s.S; i += kWave) s.tab[i] = kTabEmpty;
+    for (int i = lane; i < s.S; i += kWave) s.mkey[i] = kEmpty;
     for (int i = lane; i <= m; i += kWave) { s.hist[i] = 0; if (i < m) s.cnt[i] = 0; }
     if (lane == 0) *s.dmax = 0;
     __syncthreads();
     const uint32_t mask = (uint32_t)s.S - 1u;
     for (int i = lane; i < m; i += kWave) {
       const uint32_t id = (uint32_t)key_id(keys[i]);
-      const uint64_t v = ((uint64_t)(uint32_t)i << 32) | id;
       uint32_t sl = slot_hash(id, mask), d = 0;
-      while (atomicCAS((unsigned long long*)&s.tab[sl], (unsigned long long)kTabEmpty,
-                       (unsigned long long)v) != kTabEmpty) {
+      while (atomicCAS(&s.mkey[sl], kEmpty, id) != kEmpty) {
         sl = (sl + 1) & mask;
         ++d;
       }
+      s.mval[sl] = (uint32_t)i;
       atomicMax(s.dmax, d);
     }
     __syncthreads();
-    for (int i = lane; i < kProbeMax; i += kWave) s.tab[s.S + i] = s.tab[i];
+    for (int i = lane; i < kProbeMax; i += kWave) {
+      s.mkey[s.S + i] = s.mkey[i];
+      s.mval[s.S + i] = s.mval[i];
+    }
     const int nd = uniform((int)*s.dmax) + 1;   // slots a lookup reads
     __syncthreads();
     // detour counts: entry r of row(c_j) naming c_i with i > j.  The counts
@@ -258,8 +262,9 @@ __device__ void prune_core(const uint64_t* keys, int m, const RowSource& rs, int
 __device__ __forceinline__ PruneLds carve_prune_lds(unsigned char* p, int cap) {
   PruneLds s;
   s.S = pow2_at_least(2 * cap, 64);
-  s.tab = reinterpret_cast<uint64_t*>(p);
-  s.cnt = reinterpret_cast<uint32_t*>(s.tab + s.S + kProbeMax);
+  s.mkey = reinterpret_cast<uint32_t*>(p);
+  s.mval = s.mkey + s.S + kProbeMax;
+  s.cnt = s.mval + s.S + kProbeMax;
   s.hist = s.cnt + cap;
   s.dmax = s.hist + cap + 1;
   return s;
