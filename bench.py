@@ -986,6 +986,9 @@ def main():
                          "median phase times (for kernel traces and hardware counter runs)")
     ap.add_argument("--search-precision", choices=("fp32", "bf16", "fp8"), default="fp32",
                     help="traversal precision of --search-only (re-scored in FP32)")
+    ap.add_argument("--fp8-row-scales", type=int, choices=(-1, 0, 1), default=-1,
+                    help="FP8 scales beside the graph rows for --search-only (-1: the library's "
+                         "choice by size)")
     ap.add_argument("--detail", default=os.path.join("gpurun_out", "bench_detail.json"),
                     help="file that receives every leg's figures (sweeps, ablations, serving); "
                          "stdout's last line is the headline")
@@ -1048,12 +1051,14 @@ def main():
     if args.search_only:
         prec = {"fp32": svf.PREC_FP32, "bf16": svf.PREC_BF16, "fp8": svf.PREC_FP8}[args.search_precision]
         ix.set_option("precision", prec)
+        ix.set_option("fp8_row_scales", args.fp8_row_scales)
         ms, _ = timed_steps(torch, ix, q_t, args.search_only, bufs, args.steps, args.warmup)
         n_dist = int(bufs[2].sum().item())
         n_exp = int(bufs[3].sum().item())
         per = {"fp32": DIM * 4, "bf16": DIM * 2, "fp8": DIM + 4}[args.search_precision]
         rescore = 0 if prec == svf.PREC_FP32 else nq * args.search_only * DIM * 4
         print(json.dumps({"beam": args.search_only, "precision": args.search_precision,
+                          "fp8_row_scales": int(ix.get_option("fp8_row_scales_on")),
                           "ms_per_step": round(float(np.mean(ms)), 4),
                           "n_dist": n_dist, "n_exp": n_exp,
                           "alg_bytes": n_dist * per + n_exp * DEGREE * 4 + rescore}), flush=True)

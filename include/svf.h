@@ -122,6 +122,12 @@ int svf_destroy(svf_index *ix);
  *                   scale s = max|x| / 448 per vector (the query quantised the same way);
  *                   distances accumulate in FP32
  *   rerank          exact FP32 re-scoring of the final pool under reduced precision (0/1; 1)
+ *   fp8_row_scales  FP8 traversal: keep, beside every graph row, the scales of the vectors it
+ *                   names (capacity x degree floats in HBM, refreshed for every row written),
+ *                   so the search reads a row's scales with its ids instead of one scattered
+ *                   4-byte scale per distance; results are identical.  -1 = when the index
+ *                   holds 2^24 vectors or more, 0 = off, 1 = on (-1, 0, 1; -1).  Read-only
+ *                   "fp8_row_scales_on" tells whether the scales are kept now
  *   capacity        reserve id slots for this many vectors now (never shrinks); otherwise
  *                   the stores grow by reallocation to twice their size when full, which
  *                   briefly holds both copies (1..2^31-65)

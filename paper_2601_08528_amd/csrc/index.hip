@@ -240,7 +240,16 @@ int tier_grow_host(svf_index* ix, int64_t cap) {
     if (have >= want) continue;
     float* p = nullptr;
     const hipError_t e = hipHostMalloc((void**)&p, (size_t)(want * rb), 0);
-    if (e != hipSuccess) return hip_fail(e, "pinned host segment of the tiered store");
+    if (e != hipSuccess) {
+      int64_t held = 0;
+      for (int64_t r : T.seg_alloc) held += r * rb;
+      char what[160];
+      std::snprintf(what, sizeof what,
+                    "pinned host segment of the tiered store (%.2f GiB already pinned in %zu "
+                    "segments of at most %.2f GiB)",
+                    (double)held / (1 << 30), T.seg.size(), (double)(S * rb) / (1 << 30));
+      return hip_fail(e, what);
+    }
     if (have > 0) std::memcpy(p, T.seg[i], (size_t)(have * rb));
     std::memset(reinterpret_cast<char*>(p) + have * rb, 0, (size_t)((want - have) * rb));
     if (i < (int64_t)T.seg.size()) {
@@ -256,6 +265,8 @@ int tier_grow_host(svf_index* ix, int64_t cap) {
   CK(hipMemcpy(T.seg_d.p, T.seg.data(), T.seg.size() * sizeof(float*), hipMemcpyHostToDevice));
   return SVF_OK;
 }
+
+int row_scales_sync(svf_index* ix, hipStream_t st);
 
 int reserve(svf_index* ix, int64_t need) {
   if (need <= ix->cap) return SVF_OK;
@@ -351,6 +362,9 @@ int reserve(svf_index* ix, int64_t need) {
   ix->s_misc[11].release();
   ix->s_misc[10].p = tc; ix->s_misc[10].bytes = cap * 4;
   ix->s_misc[11].p = ti; ix->s_misc[11].bytes = cap * 4;
+  const int rc = row_scales_sync(ix, st);     // sized by capacity: filled again
+  if (rc) return rc;
+  CK(hipStreamSynchronize(st));
   return SVF_OK;
 }
 
@@ -359,19 +373,49 @@ int32_t* tidx(svf_index* ix) { return ix->s_misc[11].as<int32_t>(); }
 
 int store_lowp_rows(svf_index* ix, int64_t row0, int64_t n, hipStream_t st);
 
+// FP8 traversal keeps each row's vector scales beside it (nscale) when asked,
+// or by size once the per-vector scales (4 B each) are past what the caches
+// hold: then a scale read costs a cache line per distance.
+bool row_scales_wanted(const svf_index* ix) {
+  if (ix->veclp_prec != 3 || ix->cap == 0) return false;
+  if (ix->opt.fp8_row_scales >= 0) return ix->opt.fp8_row_scales == 1;
+  return ix->cap >= (int64_t(1) << 24);
+}
+
+// Allocate (capacity rows) and fill, or free, the row scales to match
+// row_scales_wanted.
+int row_scales_sync(svf_index* ix, hipStream_t st) {
+  if (ix->nscale) (void)hipFree(ix->nscale);
+  ix->nscale = nullptr;
+  if (!row_scales_wanted(ix)) return SVF_OK;
+  CK(hipMalloc(&ix->nscale, (size_t)ix->cap * ix->R * 4));
+  CK(svf::launch_row_scales(ix->graph, ix->R, nullptr, 0, ix->n_slots,
+                            lp_scale(ix->veclp, ix, 3, ix->cap), ix->nscale, st));
+  return SVF_OK;
+}
+
+// Row scales of rows just written: the n rows of list, or rows [lo, lo + n).
+int row_scales_rows(svf_index* ix, const int32_t* list, int64_t lo, int64_t n, hipStream_t st) {
+  if (!ix->nscale || n <= 0) return SVF_OK;
+  CK(svf::launch_row_scales(ix->graph, ix->R, list, lo, n, lp_scale(ix->veclp, ix, 3, ix->cap),
+                            ix->nscale, st));
+  return SVF_OK;
+}
+
 // Make the reduced-precision copy match the chosen precision.
 int sync_lowp(svf_index* ix) {
   const int prec = ix->opt.precision;
-  if (prec == ix->veclp_prec) return SVF_OK;
+  if (prec == ix->veclp_prec) return row_scales_wanted(ix) == (ix->nscale != nullptr)
+                                        ? SVF_OK : row_scales_sync(ix, ix->stream);
   bg_join(ix);                              // it may be reading the store freed below
   if (ix->veclp) (void)hipFree(ix->veclp);
   ix->veclp = nullptr;
   ix->veclp_prec = prec;
-  if (prec == 0 || ix->cap == 0) return SVF_OK;
+  if (prec == 0 || ix->cap == 0) return row_scales_sync(ix, ix->stream);
   CK(hipMalloc(&ix->veclp, lp_bytes(ix, prec, ix->cap)));
   CK(svf::launch_fill_u32(ix->veclp, lp_bytes(ix, prec, ix->cap) / 4, 0u, ix->stream));
-  const int rc = store_lowp_rows(ix, 0, ix->n_slots, ix->stream);
-  if (rc) return rc;
+  int rc = store_lowp_rows(ix, 0, ix->n_slots, ix->stream);
+  if (rc || (rc = row_scales_sync(ix, ix->stream))) return rc;
   CK(hipStreamSynchronize(ix->stream));
   return SVF_OK;
 }
@@ -433,6 +477,7 @@ svf::SearchArgs base_args(const svf_index* ix) {
   a.stride = ix->stride;
   a.vstride = ix->veclp_prec ? lp_stride(ix, ix->veclp_prec) : ix->stride;
   a.vscale = lp_scale(ix->veclp, ix, ix->veclp_prec, ix->cap);
+  a.nscale = ix->veclp_prec == 3 ? ix->nscale : nullptr;
   a.dim = ix->dim;
   a.graph = ix->graph;
   a.R = ix->R;
@@ -596,6 +641,8 @@ int insert_commit(svf_index* ix, PendingInsert* p) {
   if (p->seed) {
     ix->tier.e_in_valid = false;
     CK(svf::launch_set_alive(ix->alive, 0, p->b, st));
+    const int rc = row_scales_rows(ix, nullptr, 0, p->b, st);
+    if (rc) return rc;
     CK(hipStreamSynchronize(st));
     ix->n_slots = p->b;
     ix->n_alive = p->b;
@@ -613,6 +660,8 @@ int insert_commit(svf_index* ix, PendingInsert* p) {
     CK(svf::launch_indegree_add(p->ra.fwd_ids, p->b * ix->R, e, st));
   }
   CK(svf::launch_commit_batch(p->ra, p->n_targets, ix->graph, ix->edge_d, ix->alive, st));
+  int rc = row_scales_rows(ix, p->ra.tlist, 0, p->n_targets, st);
+  if (rc || (rc = row_scales_rows(ix, nullptr, p->n0, p->b, st))) return rc;
   CK(hipEventRecord(ix->ev1, st));
   CK(hipStreamSynchronize(st));
   ix->st.ins_commit_ms = elapsed(ix->ev0, ix->ev1);
@@ -825,7 +874,7 @@ int commit_repaired(svf_index* ix, const int32_t* list, int n, const int32_t* ro
     CK(svf::launch_indegree_rows_delta(ix->graph, list, n, rows, ix->R, e, st));
   CK(svf::launch_commit_rows(list, n, rows, rows_d, ix->R, ix->graph, ix->edge_d, st));
   ++ix->graph_epoch;
-  return SVF_OK;
+  return row_scales_rows(ix, list, 0, n, st);
 }
 
 // Repair (consolidate = 0) or consolidation (1) of the live graph.
@@ -888,6 +937,7 @@ int bg_begin(svf_index* ix) {
   j.alive = al;
   j.proto.graph = g;
   j.proto.alive = al;
+  j.proto.nscale = nullptr;                 // the live rows' scales, not the snapshot's
   B.n0 = n;
   B.log_n = 0;
   B.n_aff = 0;
@@ -996,6 +1046,7 @@ int bg_merge(svf_index* ix) {
     only_targets.b = 0;                       // the logged rows are live already
     CK(svf::launch_commit_batch(only_targets, n_targets, ix->graph, ix->edge_d, ix->alive, st));
     ++ix->graph_epoch;
+    if ((rc = row_scales_rows(ix, ra.tlist, 0, n_targets, st))) return rc;
   }
   CK(hipStreamSynchronize(st));
   B.log_n = 0;
@@ -1738,6 +1789,7 @@ int svf_destroy(svf_index* ix) {
     for (float* p : ix->tier.seg) (void)hipHostFree(p);
     if (ix->veclp) (void)hipFree(ix->veclp);
     if (ix->graph) (void)hipFree(ix->graph);
+    if (ix->nscale) (void)hipFree(ix->nscale);
     if (ix->edge_d) (void)hipFree(ix->edge_d);
     if (ix->alive) (void)hipFree(ix->alive);
     if (ix->tier.cache) (void)hipFree(ix->tier.cache);
@@ -1838,6 +1890,13 @@ int svf_set_option(svf_index* ix, const char* key, double v) {
   } else if (k == "cache_trace_cap") {
     if (!is_int(v) || v < 16 || v > 8192) return fail(SVF_E_INVAL, "cache_trace_cap in [16, 8192]");
     ix->tier.trace_cap = (int)v;
+  } else if (k == "fp8_row_scales") {
+    if (v != -1 && v != 0 && v != 1) return fail(SVF_E_INVAL, "fp8_row_scales -1, 0 or 1");
+    bg_join(ix);                              // its searches may read the scales freed below
+    o.fp8_row_scales = (int)v;
+    const int rc = row_scales_sync(ix, ix->stream);
+    if (rc) return rc;
+    CK(hipStreamSynchronize(ix->stream));
   } else if (k == "host_segment_rows") {
     if (ix->tier.on) return fail(SVF_E_BUSY, "host_segment_rows is set before cache_bytes");
     // (the seed rows, at most 4 * degree <= 512, sit in the first segment)
@@ -1917,6 +1976,8 @@ int svf_get_option(const svf_index* ix, const char* key, double* out) {
   else if (k == "host_segment_rows")
     *out = ix->tier.on ? (double)(int64_t(1) << ix->tier.seg_shift) : (double)ix->tier.seg_rows_opt;
   else if (k == "host_segments") *out = (double)ix->tier.seg.size();
+  else if (k == "fp8_row_scales") *out = o.fp8_row_scales;
+  else if (k == "fp8_row_scales_on") *out = ix->nscale ? 1.0 : 0.0;
   else if (k == "model_conf") *out = o.model_conf;
   else if (k == "model_stop_scale") *out = o.model_stop_scale;
   else if (k == "model_min_iters") *out = o.model_min_iters;
@@ -2451,6 +2512,8 @@ int svf_import_graph(svf_index* ix, const float* vecs, int64_t n, const int32_t*
   CK(hipStreamSynchronize(st));
   ix->n_slots = n;
   ix->n_alive = na;
+  if ((rc = row_scales_sync(ix, st))) return rc;
+  CK(hipStreamSynchronize(st));
   return SVF_OK;
 }
 

@@ -85,6 +85,7 @@ struct Options {
   int model_min_iters = 8;
   int model_entries = 1;        // 1: spread over the cluster, 0: nearest to the centroid
   int cache_cpu_miss = 0;       // tiered FP32 search: misses computed on the host cores
+  int fp8_row_scales = -1;      // FP8 scales beside the rows: -1 by size, 0 off, 1 on
 };
 
 }  // namespace svf
@@ -202,6 +203,7 @@ struct svf_index {
                                      // rows then per-vector scales)
   int veclp_prec = 0;
   int32_t* graph = nullptr;          // cap x R
+  float* nscale = nullptr;           // FP8: cap x R scales of the vectors the rows name (or null)
   float* edge_d = nullptr;           // cap x R
   uint32_t* alive = nullptr;         // ceil(cap/32) words
   svf::Options opt;

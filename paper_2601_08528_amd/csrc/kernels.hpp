@@ -24,6 +24,8 @@ struct SearchArgs {
   int64_t stride;           // elements per FP32 row (multiple of 8)
   int64_t vstride;          // elements per traversal row (0: stride; FP8: multiple of 16)
   const float* vscale;      // FP8: per-vector scales
+  const float* nscale;      // FP8 (optional): per row entry, the scale of the vector it names,
+                            // n x R beside graph; the search then reads no per-vector scale
   int dim;
   const int32_t* graph;     // n x R ids
   int R;
@@ -105,6 +107,10 @@ hipError_t launch_store_lowp(const float* src, int64_t stride, int dim, void* ve
 hipError_t launch_seed(const float* vec32, int64_t stride, int dim, int metric, int s0, int R,
                        int32_t* graph, float* edge_d, hipStream_t st);
 hipError_t launch_set_alive(uint32_t* alive, int64_t lo, int64_t hi, hipStream_t st);
+// nscale[v * R + r] = vscale[graph[v * R + r]] (0 for an empty entry) for the
+// rows v of list[0, n), or, with list null, for rows [lo, lo + n).
+hipError_t launch_row_scales(const int32_t* graph, int R, const int32_t* list, int64_t lo, int64_t n,
+                             const float* vscale, float* nscale, hipStream_t st);
 
 struct PruneArgs {
   const uint64_t* cand;     // lists of sorted keys, cstride apart (kKeyInf padded)

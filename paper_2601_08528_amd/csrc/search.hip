@@ -155,6 +155,11 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
   const int cap_iters = (a.q_max_iters && a.q_max_iters[qi] > 0) ? a.q_max_iters[qi] : a.max_iters;
   int last_change = 0, n_iter = 0;
   const bool any_deleted = a.n_alive < a.n_slots;
+  // FP8 rows whose vector scales sit beside the ids (a.nscale): each
+  // survivor's scale goes to LDS with its id (in the slot array, which an
+  // untiered traversal does not use) and no per-vector scale is read
+  const bool rowsc = Elem<VT>::kScaled && !tier && a.nscale != nullptr;
+  float* cscale = reinterpret_cast<float*>(slot);
   for (;;) {
     if (cap_iters > 0 && n_iter >= cap_iters) break;
     int ppos[4];
@@ -183,9 +188,11 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
     ++n_iter;
     for (int t = 0; t < np; ++t) {
       const int32_t* row = a.graph + (int64_t)parents[t] * a.R;
+      const float* rsc = a.nscale + (int64_t)parents[t] * a.R;
       for (int r0 = 0; r0 < a.R; r0 += kWave) {
         const int rr = r0 + lane;
         const int32_t nb = rr < a.R ? row[rr] : -1;
+        const float nsc = rowsc && rr < a.R ? rsc[rr] : 0.0f;
         bool ok = nb >= 0 && nb < a.n_slots;
         // Deleted vertices are never evaluated.  With deletions in the
         // snapshot their bits load while the visited table is probed; with
@@ -199,6 +206,7 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
         if (ok) {
           w.cid[lanes_below(ob)] = nb;
           if (tier) slot[lanes_below(ob)] = a.tmap[nb];
+          else if (rowsc) cscale[lanes_below(ob)] = nsc;
         }
         const int m = popc64(ob);
         __syncthreads();
@@ -210,7 +218,7 @@ __global__ __launch_bounds__(64) void search_kernel(SearchArgs a) {
         }
         const uint64_t k = gather_keys<VT, NC, tier, form>(qs, base, a.vstride, w.cid, m, a.metric,
                                                      slot, reinterpret_cast<const VT*>(a.tcache),
-                                                     a.vscale, a.hsegs);
+                                                     a.vscale, a.hsegs, rowsc ? cscale : nullptr);
         n_dist += m;
         if (sort_merge(w, k)) last_change = n_iter;
       }

@@ -355,6 +355,29 @@ hipError_t launch_store_lowp(const float* src, int64_t stride, int dim, void* ve
   return hipGetLastError();
 }
 
+// Scales of the vectors a row names, stored beside the row (FP8 traversal):
+// one thread per row entry, over listed rows or a range of rows.
+__global__ void row_scales_kernel(const int32_t* __restrict__ graph, int R,
+                                  const int32_t* __restrict__ list, int64_t lo, int64_t n,
+                                  const float* __restrict__ vscale, float* __restrict__ nscale) {
+  const int64_t total = n * R;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = i / R, r = i - k * R;
+    const int64_t v = list ? (int64_t)list[k] : lo + k;
+    const int32_t u = graph[v * R + r];
+    nscale[v * R + r] = u >= 0 ? vscale[u] : 0.0f;
+  }
+}
+hipError_t launch_row_scales(const int32_t* graph, int R, const int32_t* list, int64_t lo, int64_t n,
+                             const float* vscale, float* nscale, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n * R + 255) / 256, kMaxBlocks);
+  hipLaunchKernelGGL(row_scales_kernel, dim3((unsigned)blocks), dim3(256), 0, st, graph, R, list, lo,
+                     n, vscale, nscale);
+  return hipGetLastError();
+}
+
 __global__ void set_alive_kernel(uint32_t* alive, int64_t lo, int64_t hi) {
   const int64_t i = lo + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < hi) atomicOr(&alive[i >> 5], 1u << (i & 31));

@@ -276,7 +276,8 @@ template <typename VT, int NC, bool TIER, int FORM>
 __device__ inline float gather_rounds(const QuerySlice<VT, NC>& qs, const VT* __restrict__ base,
                                       int64_t stride, const int32_t* cid, int m, int metric,
                                       const int32_t* slot, const VT* __restrict__ tcache,
-                                      const float* __restrict__ vscale, HostSegs hs) {
+                                      const float* __restrict__ vscale, HostSegs hs,
+                                      const float* vj) {
   constexpr bool kScaled = Elem<VT>::kScaled;
   using QS = QuerySlice<VT, NC>;
   constexpr int E = QS::E;
@@ -336,7 +337,7 @@ __device__ inline float gather_rounds(const QuerySlice<VT, NC>& qs, const VT* __
       } else {
         const int32_t id = on ? cid[j] : 0;
         const VT* row = base + (uint64_t)(uint32_t)id * ustride;
-        if constexpr (kScaled) xs[u] = on ? vscale[id] : 0.0f;
+        if constexpr (kScaled) xs[u] = on ? (vj ? vj[j] : vscale[id]) : 0.0f;
         else xs[u] = 1.0f;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
@@ -372,22 +373,24 @@ __device__ inline float gather_rounds(const QuerySlice<VT, NC>& qs, const VT* __
 // With a tier (TIER), vector j is read from tcache row slot[j] when that slot
 // is >= 0 (slot may be null: no cache) and otherwise from row cid[j] of the
 // host segments hs, or of base when hs has none.  A scaled (FP8) store reads the
-// vector's scale from vscale[id] with its row.
+// vector's scale from vscale[id] with its row, or, when vj is given, takes
+// candidate j's scale from vj[j] (the scales a row carries beside its ids).
 template <typename VT, int NC, bool TIER = false, int FORM = 0>
 __device__ inline uint64_t gather_keys(const QuerySlice<VT, NC>& qs, const VT* __restrict__ base,
                                        int64_t stride, const int32_t* cid, int m, int metric,
                                        const int32_t* slot = nullptr,
                                        const VT* __restrict__ tcache = nullptr,
                                        const float* __restrict__ vscale = nullptr,
-                                       HostSegs hs = HostSegs{nullptr, 0}) {
+                                       HostSegs hs = HostSegs{nullptr, 0},
+                                       const float* vj = nullptr) {
   constexpr bool kScaled = Elem<VT>::kScaled;
   static_assert(FORM == 0 || (!TIER && !kScaled), "gather form");
   const int lane = lane_id();
-  const float mine =
-      gather_rounds<VT, NC, TIER, FORM>(qs, base, stride, cid, m, metric, slot, tcache, vscale, hs);
+  const float mine = gather_rounds<VT, NC, TIER, FORM>(qs, base, stride, cid, m, metric, slot,
+                                                       tcache, vscale, hs, vj);
   if (lane >= m) return kKeyInf;
   float x = mine;
-  if (kScaled && metric != 0) x *= vscale[cid[lane]];
+  if (kScaled && metric != 0) x *= vj ? vj[lane] : vscale[cid[lane]];
   const float d = metric == 0 ? x : -x;
   return make_key(d, cid[lane]);
 }

@@ -30,15 +30,19 @@ def dev_counts(g, q, k, beam):
     return ids.cpu().numpy(), d.cpu().numpy(), ne.cpu().numpy()
 
 
-@pytest.mark.parametrize("dim,metric", [(128, O.L2), (72, O.L2), (200, O.IP)])
+@pytest.mark.parametrize("dim,metric,row_scales", [(128, O.L2, 0), (72, O.L2, 0), (200, O.IP, 0),
+                                                    (128, O.L2, 1), (200, O.IP, 1)])
 @pytest.mark.parametrize("rerank", [0, 1])
-def test_fp8_search_bit_exact_on_exact_levels(dim, metric, rerank):
+def test_fp8_search_bit_exact_on_exact_levels(dim, metric, row_scales, rerank):
     """dim 72: a 16-byte-ragged FP8 row; dim 200: two 128-element chunks with
-    the inner product (a scale of 1/8 keeps s * sum exact)."""
+    the inner product (a scale of 1/8 keeps s * sum exact).  row_scales: the
+    scales read beside the graph rows instead of per vector."""
     base, q = datagen.gmm_fp8_exact_valued(401, 5000, 131, dim, 16)
     oix = oracle_index(base, 24, metric=metric, seed=3)
     oix.set("precision", O.P_FP8)
-    g = gpu_from_oracle(oix, base, seed=3, precision=svf.PREC_FP8, rerank=rerank)
+    g = gpu_from_oracle(oix, base, seed=3, precision=svf.PREC_FP8, rerank=rerank,
+                        fp8_row_scales=row_scales)
+    assert g.get_option("fp8_row_scales_on") == row_scales
     for beam in (16, 96):
         oi, od, ost = oix.search(q, 10, beam, rerank=bool(rerank))
         gi, gd, gne = dev_counts(g, q, 10, beam)
@@ -109,3 +113,60 @@ def test_fp8_switch_and_growth_keep_results():
     # exact levels: FP8 traversal equals FP32 traversal, so both graphs agree
     np.testing.assert_array_equal(ia, ib)
     np.testing.assert_array_equal(da, db)
+
+
+def test_fp8_row_scales_follow_every_row_write():
+    """With the scales kept beside the graph rows, every search equals the
+    per-vector-scale search bit for bit (ids, distances, expansion counts)
+    after a build, an insertion, deletions with localized repair, a
+    synchronous and a background consolidation (with insertions in its
+    window) and an import: every kind of row write refreshes the row scales.
+    Integer data gives each vector its own scale, so a stale one would show."""
+    base, q = datagen.gmm_uint8_valued(405, 4200, 80, 64, 12)
+    opts = dict(seed=5, insert_batch_max=300, consolidate_frac=0.0, precision=svf.PREC_FP8)
+    a = svf.Index(64, 16, svf.METRIC_L2, fp8_row_scales=1, **opts)
+    b = svf.Index(64, 16, svf.METRIC_L2, fp8_row_scales=0, **opts)
+
+    def same():
+        for beam in (16, 64):
+            ia, da, na = dev_counts(a, q, 10, beam)
+            ib, db, nb = dev_counts(b, q, 10, beam)
+            np.testing.assert_array_equal(ia, ib)
+            np.testing.assert_array_equal(da, db)
+            np.testing.assert_array_equal(na, nb)
+
+    g = np.random.Generator(np.random.Philox(405))
+    for x in (a, b):
+        x.build(base[:2500])
+    assert a.get_option("fp8_row_scales_on") == 1 and b.get_option("fp8_row_scales_on") == 0
+    same()
+    for x in (a, b):
+        x.insert(base[2500:3100])
+    same()
+    gone = g.choice(3100, 600, replace=False).astype(np.int32)
+    for x in (a, b):
+        x.delete(gone)                                    # localized repair
+    same()
+    for x in (a, b):
+        x.consolidate()
+    same()
+    more = np.setdiff1d(g.choice(3100, 700, replace=False), gone).astype(np.int32)
+    for x in (a, b):
+        x.set_option("consolidate_async", 1)
+        x.set_option("consolidate_frac", 0.05)
+        x.delete(more)                                    # starts a background consolidation
+        x.insert(base[3100:3700])                         # rows logged for the merge
+        x.consolidate_wait()
+    same()
+    for x in (a, b):
+        x.insert(base[3700:])                             # growth past the capacity
+    same()
+    rows, ed, alive = a.export_graph()
+    c = svf.Index(64, 16, svf.METRIC_L2, fp8_row_scales=1, **opts)
+    n = len(alive)
+    c.import_graph(np.ascontiguousarray(base[:n]), rows, ed, alive)
+    ia, da, na = dev_counts(a, q, 10, 48)
+    ic, dc, nc = dev_counts(c, q, 10, 48)
+    np.testing.assert_array_equal(ia, ic)
+    np.testing.assert_array_equal(da, dc)
+    assert svf.Index(64, 16, svf.METRIC_L2, **opts).get_option("fp8_row_scales") == -1
