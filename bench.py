@@ -43,8 +43,8 @@ BEAMS = [32, 48, 64, 96, 128, 192, 256, 384, 512]
 # WRITE_SIZE 1,048,576).  The figure describes the kernel built from the sources
 # whose hash is recorded; any edit to them makes it stale and it is reported as null.
 COUNTED = {"sources": ("common.hpp", "wave_ops.hpp", "search.hip"),
-           "sha256_16": "d5016c9e60dd18a3", "beam": 88,
-           "fetch_kib": 9004432.7, "fetch_scale": 1048576.0 / 524300.0,
+           "sha256_16": "2edd73c46cd52efd", "beam": 88,
+           "fetch_kib": 9004520.1, "fetch_scale": 1048576.0 / 524300.0,
            "write_kib": 2516.0, "write_scale": 1.0}
 
 
