@@ -79,6 +79,12 @@ typedef struct svf_stats {
                                        ran plain search */
     int64_t long_lists;             /* candidate lists so far too long for the one-wave LDS
                                        prune, pruned whole by the long-list kernels */
+    /* tiered store: host-clock time of the last batch's placement (ms), by phase */
+    double place_count_ms;   /* access counts and touched list on the GPU, copied back   */
+    double place_indeg_ms;   /* in-degrees brought up to date (after the graph changed)  */
+    double place_walk_ms;    /* F_recent, hits and candidates over the touched vertices */
+    double place_evict_ms;   /* Alg. 2's victims, scoring the residents included        */
+    double place_apply_ms;   /* rows copied into the cache and the map rewritten         */
 } svf_stats;
 
 /* Create an empty index.  Sec. 2.3: a directed graph with a fixed number of

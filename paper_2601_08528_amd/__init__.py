@@ -59,6 +59,9 @@ class Stats(C.Structure):
         ("cache_evictions", C.c_int64),
         ("consolidations", C.c_int64), ("last_model_fallback", C.c_int64),
         ("long_lists", C.c_int64),
+        ("place_count_ms", C.c_double), ("place_indeg_ms", C.c_double),
+        ("place_walk_ms", C.c_double), ("place_evict_ms", C.c_double),
+        ("place_apply_ms", C.c_double),
     ]
 
     def as_dict(self):

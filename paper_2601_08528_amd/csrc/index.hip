@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1460,6 +1461,12 @@ int tier_place_classic(svf_index* ix, std::vector<int32_t>& order, hipStream_t s
 
 int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
   svf::TierState& T = ix->tier;
+  using clk = std::chrono::steady_clock;
+  auto ms_since = [](clk::time_point t0) {
+    return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+  };
+  auto tp = clk::now();
+  ix->st.place_indeg_ms = ix->st.place_walk_ms = ix->st.place_evict_ms = ix->st.place_apply_ms = 0;
   const int cap = T.trace_cap;
   const int64_t n = ix->n_slots;
   const int64_t words = (n + 31) / 32;
@@ -1512,19 +1519,24 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
   CK(hipMemcpyAsync(T.lst_cnt_h.p, lcnt, total * 4, hipMemcpyDeviceToHost, st));
   if (lru) CK(hipMemcpyAsync(T.lst_last_h.p, llast, total * 4, hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
+  ix->st.place_count_ms = ms_since(tp);
+  tp = clk::now();
   rc = tier_refresh_indegree(ix, st);
   if (rc) return rc;
+  ix->st.place_indeg_ms = ms_since(tp);
+  tp = clk::now();
   T.gather_hits += gcnt[0];
   T.gather_misses += gcnt[1];
   auto alive = [&](int32_t x) { return ((bits[x >> 5] >> (x & 31)) & 1u) != 0; };
-  auto lg = [&](int32_t x) { return T.beta * std::log(1.0 + (double)T.in_degree(x)); };
+  (void)T.log1p_deg(0);                     // the table is filled before the threads read it
+  auto lg = [&](int32_t x) { return T.beta * T.log1p_deg(T.in_degree(x)); };
   ++T.batch;
   // every touched vertex in id order: F_recent halves, then gains one per
   // access; accesses of cached vertices are hits and set their slot's
   // reference bit; uncached vertices above theta become candidates.  The
   // vertices are independent, so contiguous ranges of the list run on
   // separate threads and their candidates are joined in order.
-  const int nthr = (int)std::max<int64_t>(1, std::min<int64_t>({16, (total + 65535) / 65536,
+  const int nthr = (int)std::max<int64_t>(1, std::min<int64_t>({16, (total + 16383) / 16384,
                                                                  (int64_t)std::thread::hardware_concurrency()}));
   // Candidates are taken against theta after the adaptation, which needs the
   // whole batch: each thread keeps the prediction of every missed alive
@@ -1573,7 +1585,10 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
     missed.insert(missed.end(), tmissed[t].begin(), tmissed[t].end());
   }
   T.last_trace_hits = hits;
-  if (T.policy != 0) return tier_place_classic(ix, missed, st);
+  if (T.policy != 0) {
+    ix->st.place_walk_ms = ms_since(tp);
+    return tier_place_classic(ix, missed, st);
+  }
   if (T.adapt > 1.0 && acc > 0) {
     // Sec. 4.4: theta rises when the miss rate and the mean prediction of the
     // missed vectors both rise, and falls back (not below where it started)
@@ -1606,6 +1621,8 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
     cand.resize(T.promote_max);
   }
   std::sort(cand.begin(), cand.end(), better);
+  ix->st.place_walk_ms = ms_since(tp);
+  tp = clk::now();
   std::vector<int32_t> place;
   svf::WavpSweep& sw = T.sweep;
   for (const auto& c : cand) {
@@ -1637,7 +1654,11 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
   }
   sw.end();
   T.promotions += place.size() / 3;
-  return tier_apply(ix, place, st);
+  ix->st.place_evict_ms = ms_since(tp);
+  tp = clk::now();
+  rc = tier_apply(ix, place, st);
+  ix->st.place_apply_ms = ms_since(tp);
+  return rc;
 }
 
 // Cold start (Sec. 4.4): fill the cache with the highest in-degree alive
@@ -2358,7 +2379,7 @@ int svf_stats_get(const svf_index* cix, svf_stats* out) {
   ix->st.capacity = ix->cap;
   ix->st.device_bytes = ix->cap * ((ix->tier.on ? 0 : ix->stride * 4) + ix->R * 8 + 8) + ix->cap / 8 +
                         (ix->veclp_prec ? (int64_t)lp_bytes(ix, ix->veclp_prec, ix->cap) : 0) +
-                        ix->tier.C * ix->stride * 4;
+                        ix->tier.C * ix->stride * 4 + (ix->nscale ? ix->cap * ix->R * 4 : 0);
   ix->st.cache_slots = ix->tier.C;
   ix->st.cache_gather_hits = (int64_t)ix->tier.gather_hits;
   ix->st.cache_gather_misses = (int64_t)ix->tier.gather_misses;

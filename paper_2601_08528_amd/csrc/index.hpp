@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include <atomic>
+#include <cmath>
 #include <mutex>
 #include <thread>
 #include <string>
@@ -189,6 +190,15 @@ struct TierState {
   }
   HostSegs segs() const { return HostSegs{seg_d.as<const float* const>(), seg_shift}; }
   int32_t in_degree(int32_t x) const { return e_in.as<int32_t>()[x]; }
+  // log(1 + e) for in-degree e, from a table of the same values for small e
+  std::vector<double> log1p_tab;
+  double log1p_deg(int32_t e) {
+    if (log1p_tab.empty()) {
+      log1p_tab.resize(1 << 16);
+      for (int i = 0; i < (1 << 16); ++i) log1p_tab[i] = std::log(1.0 + (double)i);
+    }
+    return (uint32_t)e < log1p_tab.size() ? log1p_tab[e] : std::log(1.0 + (double)e);
+  }
 };
 }  // namespace svf
 

@@ -38,7 +38,7 @@ class WavpSweep {
     bmin_.resize(nb_);
     nw_ = (nb_ + 63) / 64;
     busy_.assign(nw_, 0);
-    const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(threads, nb_ / 4096));
+    const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(threads, nb_ / 512));
     auto work = [&](int t) {
       const int64_t b0 = nb_ * t / nt, b1 = nb_ * (t + 1) / nt;
       for (int64_t b = b0; b < b1; ++b) {
