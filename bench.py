@@ -666,10 +666,10 @@ def full_tier_bench(torch, svf, datagen, n_base, cache_gb=None, steps=8, sample=
                 return b, rows
         return beams[-1], rows
 
-    beam32, sweep32 = pick((64, 96, 128, 192, 256, 384, 512))
+    beam32, sweep32 = pick((64, 96, 128, 192, 256, 384, 512, 768, 1024))
     fp32_row = sweep32[-1]
     ix.set_option("precision", svf.PREC_FP8)
-    beam8, sweep8 = pick((64, 96, 128, 192, 256, 384, 512))
+    beam8, sweep8 = pick((64, 96, 128, 192, 256, 384, 512, 768, 1024))
     run_search(torch, ix, q0, beam8, bufs)
     torch.cuda.synchronize()
     ref_ids = bufs[0].clone()

@@ -239,7 +239,7 @@ int svf_consolidate_wait(svf_index *ix);
 
 /* Batched search (Sec. 4.2, Algorithm 1): for each of nq queries (nq x dim
  * FP32, host memory) a best-first search with a candidate pool of `beam`
- * entries (k <= beam <= 512) from random entry points, stopping when every
+ * entries (k <= beam <= 1024) from random entry points, stopping when every
  * pool entry is expanded; the k nearest found are written to out_ids and
  * out_dists (nq x k each, ascending).  Fewer than k alive vectors: the rest
  * is padded with id -1 and distance +inf.  nq <= 2^25 per call (SVF_E_INVAL

@@ -31,7 +31,8 @@ int hip_fail(hipError_t e, const char* what) {
   return e == hipErrorOutOfMemory ? SVF_E_NOMEM : SVF_E_DEVICE;
 }
 
-constexpr int kMaxBeam = 512;
+constexpr int kMaxBeam = 512;          // insertion pool (beam_insert)
+constexpr int kMaxSearchBeam = 1024;   // search pool: 2 x 1024 keys of LDS per wave
 constexpr int kMaxEntries = 1024;
 
 int tier_release(svf_index* ix, const int32_t* ids, int64_t n);
@@ -1158,7 +1159,7 @@ int check_search_args(const svf_index* ix, int64_t nq, int k, int beam) {
   if (nq < 0 || nq > (1 << 25)) return fail(SVF_E_INVAL, "nq must be in [0, 2^25]");
   if (k < 1) return fail(SVF_E_INVAL, "k must be >= 1");
   if (beam < k) return fail(SVF_E_INVAL, "beam must be >= k");
-  if (beam > kMaxBeam) return fail(SVF_E_INVAL, "beam must be <= 512");
+  if (beam > kMaxSearchBeam) return fail(SVF_E_INVAL, "beam must be <= 1024");
   return SVF_OK;
 }
 

@@ -36,7 +36,7 @@ def int_l2():
     return oix, base, q
 
 
-@pytest.mark.parametrize("beam", [10, 64, 256])
+@pytest.mark.parametrize("beam", [10, 64, 256, 1024])
 def test_search_bit_exact_integer_l2(int_l2, beam):
     oix, base, q = int_l2
     g = gpu_from_oracle(oix, base, seed=11)
@@ -65,6 +65,28 @@ def test_search_width_bit_exact(int_l2, width, coop):
     finally:
         oix.set("search_width", 1)
     gi, gd, gnd, gne = dev_search(g, q, 10, 64)
+    np.testing.assert_array_equal(gi, oi)
+    np.testing.assert_array_equal(gd.astype(np.float64), od)
+    np.testing.assert_array_equal(gne, ost["n_exp"])
+
+
+@pytest.mark.parametrize("prec,width,coop", [(0, 4, 1024), (2, 1, 0), (2, 2, 1024)])
+def test_largest_beam_every_form(int_l2, prec, width, coop):
+    """The largest pool (beam 1024, 16 KB of keys per query in LDS): several
+    parents per iteration with one wave per parent, and BF16 traversal with
+    its FP32 re-score of all 1024 entries (integer data is exact on the BF16
+    grid), against the oracle."""
+    oix, base, q = int_l2
+    g = gpu_from_oracle(oix, base, seed=11, precision=prec, search_width=width,
+                        coop_max_batch=coop)
+    oix.set("search_width", width)
+    oix.set("precision", O.P_BF16 if prec == 2 else O.P_FP32)
+    try:
+        oi, od, ost = oix.search(q[:60], 10, 1024)
+    finally:
+        oix.set("search_width", 1)
+        oix.set("precision", O.P_FP32)
+    gi, gd, gnd, gne = dev_search(g, q[:60], 10, 1024)
     np.testing.assert_array_equal(gi, oi)
     np.testing.assert_array_equal(gd.astype(np.float64), od)
     np.testing.assert_array_equal(gne, ost["n_exp"])
@@ -137,14 +159,14 @@ def test_edge_cases_padding_and_limits():
     gi, gd = g.search(q, 1, 1)
     oi, od, _ = oix.search(q, 1, 1)
     np.testing.assert_array_equal(gi, oi)
-    gi, gd = g.search(q, 10, 512)                 # maximum beam
+    gi, gd = g.search(q, 10, 1024)                # maximum beam
     assert gi.shape == (3, 10)
     e, _ = g.search(np.zeros((0, 16), np.float32), 5, 5)
     assert e.shape == (0, 5)
     with pytest.raises(svf.SvfError):
         g.search(q, 5, 4)                         # beam < k
     with pytest.raises(svf.SvfError):
-        g.search(q, 5, 513)
+        g.search(q, 5, 1025)
     bad = q.copy()
     bad[0, 0] = np.nan
     with pytest.raises(svf.SvfError):
