@@ -45,17 +45,18 @@ struct RowSource {
   }
 };
 
-// Candidate id -> position table of the prune: S slots (a power of two) of
-// ids with linear probing, each with its candidate's position in a second
-// array, followed by a copy of the first kProbeMax slots of both so that a
-// lookup reads consecutive slots without wrapping.  dmax is the largest
+// Candidate id -> position table of the prune: S slots (a power of two, at
+// least four per candidate, so that ids sit close to their home slots) of
+// ids with linear probing, each with its candidate's 16-bit position in a
+// second array, followed by a copy of the first kProbeMax slots of both so
+// that a lookup reads consecutive slots without wrapping.  dmax is the largest
 // distance of an inserted id from its home slot; a lookup that reads the
 // dmax + 1 slots from the home slot finds any inserted id.  A lookup reads
 // 4-byte ids and fetches a position only on a hit.
 constexpr int kProbeMax = 8;
 struct PruneLds {
   uint32_t* mkey;   // S + kProbeMax slots (kEmpty when free)
-  uint32_t* mval;   // S + kProbeMax positions
+  uint16_t* mval;   // S + kProbeMax positions
   uint32_t* cnt;    // cap
   uint32_t* hist;   // cap + 1
   uint32_t* dmax;   // 1
@@ -132,7 +133,7 @@ __device__ void prune_core(const uint64_t* keys, int m, const RowSource& rs, int
         sl = (sl + 1) & mask;
         ++d;
       }
-      s.mval[sl] = (uint32_t)i;
+      s.mval[sl] = (uint16_t)i;
       atomicMax(s.dmax, d);
     }
     __syncthreads();
@@ -261,18 +262,18 @@ __device__ void prune_core(const uint64_t* keys, int m, const RowSource& rs, int
 
 __device__ __forceinline__ PruneLds carve_prune_lds(unsigned char* p, int cap) {
   PruneLds s;
-  s.S = pow2_at_least(2 * cap, 64);
+  s.S = pow2_at_least(4 * cap, 64);
   s.mkey = reinterpret_cast<uint32_t*>(p);
-  s.mval = s.mkey + s.S + kProbeMax;
-  s.cnt = s.mval + s.S + kProbeMax;
+  s.mval = reinterpret_cast<uint16_t*>(s.mkey + s.S + kProbeMax);
+  s.cnt = reinterpret_cast<uint32_t*>(s.mkey + s.S + kProbeMax) + (s.S + kProbeMax) / 2;
   s.hist = s.cnt + cap;
   s.dmax = s.hist + cap + 1;
   return s;
 }
 size_t prune_scratch_bytes(int cap) {
   int S = 64;
-  while (S < 2 * cap) S <<= 1;
-  return (size_t)(S + kProbeMax) * 8 + (size_t)cap * 4 + (size_t)(cap + 1) * 4 + 16;
+  while (S < 4 * cap) S <<= 1;
+  return (size_t)(S + kProbeMax) * 6 + (size_t)cap * 4 + (size_t)(cap + 1) * 4 + 16;
 }
 
 // Number of non-padding keys in a sorted LDS list of n keys.
