@@ -52,30 +52,41 @@ struct RowSource {
 // that a lookup reads consecutive slots without wrapping.  dmax is the largest
 // distance of an inserted id from its home slot; a lookup that reads the
 // dmax + 1 slots from the home slot finds any inserted id.  A lookup reads
-// 4-byte ids and fetches a position only on a hit.
+// 4-byte ids and fetches a position only on a hit.  A free slot holds
+// kFree, which is neither an id nor the -1 that pads rows, so an entry read
+// from a row never matches a free slot.
 constexpr int kProbeMax = 8;
+constexpr uint32_t kFree = 0xfffffffeu;
+// The positions come first, at the start of the kernel's LDS, so that the
+// address of a hit's position is one shift-and-add of its slot.
 struct PruneLds {
-  uint32_t* mkey;   // S + kProbeMax slots (kEmpty when free)
   uint16_t* mval;   // S + kProbeMax positions
+  uint32_t* mkey;   // S + kProbeMax slots (kFree when free)
   uint32_t* cnt;    // cap
   uint32_t* hist;   // cap + 1
   uint32_t* dmax;   // 1
   int S;
 };
 
-// Position of candidate id e (-1 if e is not a candidate) when the table's
-// largest displacement is below N: a fixed read of the N slots from the home
-// slot, with no data-dependent branch.
+// Byte offset from the home slot's position to the position of candidate id
+// e (-1 if e is not a candidate, -1 included) when the table's largest
+// displacement is below N: a fixed read of the N slots from the home slot,
+// with no data-dependent branch.  The offsets are constants of the unrolled
+// compare chain.
 template <int N>
-__device__ __forceinline__ int tab_find(const PruneLds& s, uint32_t home, int32_t e) {
+__device__ __forceinline__ int tab_off(const PruneLds& s, uint32_t home, int32_t e) {
   uint32_t w[N];
 #pragma unroll
   for (int d = 0; d < N; ++d) w[d] = s.mkey[home + d];
-  int hit = -1;
+  int off = -1;
 #pragma unroll
   for (int d = 0; d < N; ++d)
-    if (w[d] == (uint32_t)e) hit = (int)home + d;
-  return (e >= 0 && hit >= 0) ? (int)s.mval[hit] : -1;
+    if (w[d] == (uint32_t)e) off = 2 * d;
+  return off;
+}
+__device__ __forceinline__ int tab_pos(const PruneLds& s, uint32_t home, int off) {
+  return *reinterpret_cast<const uint16_t*>(reinterpret_cast<const unsigned char*>(s.mval + home) +
+                                            off);
 }
 // The same with any displacement (a probe loop that stops at an empty slot).
 __device__ __forceinline__ int tab_find_loop(const PruneLds& s, uint32_t home, int32_t e,
@@ -85,10 +96,25 @@ __device__ __forceinline__ int tab_find_loop(const PruneLds& s, uint32_t home, i
   for (;;) {
     const uint32_t k = s.mkey[sl];
     if (k == (uint32_t)e) return (int)s.mval[sl];
-    if (k == kEmpty) return -1;
+    if (k == kFree) return -1;
     sl = (sl + 1) & mask;
   }
 }
+
+// Home slot of an id in the prune's table (S = 2^sbits slots): bits 7 and up
+// of a multiplicative hash of the id's low 24 bits, on the full-rate 24-bit
+// multiplier (a 32-bit multiply issues at a quarter of the rate).  Ids equal
+// in their low 24 bits share a home slot; that only lengthens probes.
+__device__ __forceinline__ uint32_t prune_hash(uint32_t id, uint32_t sbits) {
+  return __builtin_amdgcn_ubfe(__umul24(id, 0x9E3779u), 7u, sbits);
+}
+
+// Fourth word of a raw (unformatted, unswizzled) buffer resource on gfx9
+// targets: 32-bit data format, so that a dword load returns the dword.  A row
+// read through a resource takes its base from two scalar registers and the
+// lane's byte offset from a vector register, with no address arithmetic per
+// row; offsets past the resource's size return 0 instead of reading memory.
+constexpr int kRawBufferWord3 = 0x00020000;
 
 __device__ __forceinline__ int pow2_at_least(int x, int lo) {
   int p = lo;
@@ -121,15 +147,16 @@ __device__ void prune_core(const uint64_t* keys, int m, const RowSource& rs, int
   int tau = 0, need = 0;
   const bool full = m > R;
   if (full) {
-    for (int i = lane; i < s.S; i += kWave) s.mkey[i] = kEmpty;
+    for (int i = lane; i < s.S; i += kWave) s.mkey[i] = kFree;
     for (int i = lane; i <= m; i += kWave) { s.hist[i] = 0; if (i < m) s.cnt[i] = 0; }
     if (lane == 0) *s.dmax = 0;
     __syncthreads();
     const uint32_t mask = (uint32_t)s.S - 1u;
+    const uint32_t sbits = (uint32_t)__builtin_ctz((uint32_t)s.S);
     for (int i = lane; i < m; i += kWave) {
       const uint32_t id = (uint32_t)key_id(keys[i]);
-      uint32_t sl = slot_hash(id, mask), d = 0;
-      while (atomicCAS(&s.mkey[sl], kEmpty, id) != kEmpty) {
+      uint32_t sl = prune_hash(id, sbits), d = 0;
+      while (atomicCAS(&s.mkey[sl], kFree, id) != kFree) {
         sl = (sl + 1) & mask;
         ++d;
       }
@@ -146,39 +173,67 @@ __device__ void prune_core(const uint64_t* keys, int m, const RowSource& rs, int
     // detour counts: entry r of row(c_j) naming c_i with i > j.  The counts
     // are sums, so the order in which entries are probed does not matter.
     if (R > 32 && R <= kWave) {
-      // One whole row per step: lane r reads entry r of row j.  The offsets
-      // of a pass's 8 rows from the graph base are computed once, one row
-      // per lane, and read out lane by lane, so a row's address is a scalar;
-      // each lane has 8 row reads in flight before it probes any.
+      // One whole row per step: lane r reads entry r of row j.  The byte
+      // addresses of a pass's 8 rows are computed once, one row per lane, and
+      // read out lane by lane into a buffer resource per row, so each load is
+      // a scalar base plus the lane's byte offset.  Every load is issued, with
+      // no branch: lanes past the row re-read its last entry and rows past m
+      // re-read row 0; the first do not probe and the second count nothing.
+      // The rows of the next pass are requested before the entries of this
+      // one are probed (after the last pass, 8 reads of row 0 that are never
+      // used), so that the probes run while those reads are in flight.  Row
+      // addresses are computed 64 rows at a time, lane l holding row g + l.
       constexpr int kRowSteps = 8;
-      const int64_t fwd_off = rs.fwd ? (int64_t)(rs.fwd - rs.graph) : 0;
-      for (int j0 = 0; j0 < m; j0 += kRowSteps) {
-        int64_t ro = -1;
-        if (lane < kRowSteps && j0 + lane < m) {
-          const int32_t id = (int32_t)(((uint32_t)keys[j0 + lane]) >> 1);
-          ro = id < rs.n_old ? (int64_t)id * R : fwd_off + (int64_t)(id - rs.n_old) * R;
-        }
-        const uint32_t ro_lo = (uint32_t)ro, ro_hi = (uint32_t)((uint64_t)ro >> 32);
-        int32_t e[kRowSteps];
+      const bool lane_on = lane < R;
+      const uint32_t lbyte = 4u * (uint32_t)(lane_on ? lane : R - 1);
+      uint32_t ra_lo = 0, ra_hi = 0;
+      auto address_rows = [&](int g) {
+        const int j = g + lane < m ? g + lane : 0;
+        const uint64_t ra = (uint64_t)(uintptr_t)rs.row(key_id(keys[j]));
+        ra_lo = (uint32_t)ra;
+        ra_hi = (uint32_t)(ra >> 32);
+      };
+      auto load_pass = [&](int j0, int32_t (&e)[kRowSteps]) {
+        const int l0 = j0 & (kWave - 1);
 #pragma unroll
         for (int u = 0; u < kRowSteps; ++u) {
-          const int64_t b =
-              (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(ro_hi, u) << 32) |
-                        (uint32_t)__builtin_amdgcn_readlane(ro_lo, u));
-          e[u] = j0 + u < m && lane < R ? rs.graph[b + lane] : -1;
+          const uint64_t b =
+              ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(ra_hi, l0 + u) << 32) |
+              (uint32_t)__builtin_amdgcn_readlane(ra_lo, l0 + u);
+          const __amdgpu_buffer_rsrc_t row = __builtin_amdgcn_make_buffer_rsrc(
+              reinterpret_cast<void*>(b), (short)0, 4 * R, kRawBufferWord3);
+          e[u] = __builtin_amdgcn_raw_buffer_load_b32(row, lbyte, 0, 0);
         }
+      };
+      int32_t e[kRowSteps], en[kRowSteps];
+      address_rows(0);
+      load_pass(0, e);
+      for (int j0 = 0; j0 < m; j0 += kRowSteps) {
+        const int jn = j0 + kRowSteps;
+        if ((jn & (kWave - 1)) == 0) address_rows(jn);
+        load_pass(jn, en);
         auto count = [&](auto nslots) {
 #pragma unroll
           for (int u = 0; u < kRowSteps; ++u) {
             constexpr int N = decltype(nslots)::value;
-            const uint32_t h = slot_hash((uint32_t)e[u], mask);
-            int i;
-            if constexpr (N > 0) i = tab_find<N>(s, h, e[u]);
-            else i = tab_find_loop(s, h, e[u], mask);
-            if (i > j0 + u) atomicAdd(&s.cnt[i], 1u);
+            const uint32_t h = prune_hash((uint32_t)e[u], sbits);
+            // a row past m counts nothing (its threshold exceeds any position)
+            const int jt = j0 + u < m ? j0 + u : 0x7fffffff;
+            if constexpr (N > 0) {
+              const int off = tab_off<N>(s, h, e[u]);
+              if (off >= 0) {
+                const int i = tab_pos(s, h, off);
+                if (i > jt) atomicAdd(&s.cnt[i], 1u);
+              }
+            } else {
+              const int i = tab_find_loop(s, h, e[u], mask);
+              if (i > jt) atomicAdd(&s.cnt[i], 1u);
+            }
           }
         };
-        probe_by_slots(nd, count);
+        if (lane_on) probe_by_slots(nd, count);
+#pragma unroll
+        for (int u = 0; u < kRowSteps; ++u) e[u] = en[u];
       }
     } else {
       // Any degree: entry t = j * R + r goes to lane t % 64; each lane loads
@@ -204,11 +259,17 @@ __device__ void prune_core(const uint64_t* keys, int m, const RowSource& rs, int
 #pragma unroll
           for (int u = 0; u < kRowSteps; ++u) {
             constexpr int N = decltype(nslots)::value;
-            const uint32_t h = slot_hash((uint32_t)e[u], mask);
-            int i;
-            if constexpr (N > 0) i = tab_find<N>(s, h, e[u]);
-            else i = tab_find_loop(s, h, e[u], mask);
-            if (i > jj[u]) atomicAdd(&s.cnt[i], 1u);
+            const uint32_t h = prune_hash((uint32_t)e[u], sbits);
+            if constexpr (N > 0) {
+              const int off = tab_off<N>(s, h, e[u]);
+              if (off >= 0) {
+                const int i = tab_pos(s, h, off);
+                if (i > jj[u]) atomicAdd(&s.cnt[i], 1u);
+              }
+            } else {
+              const int i = tab_find_loop(s, h, e[u], mask);
+              if (i > jj[u]) atomicAdd(&s.cnt[i], 1u);
+            }
           }
         };
         probe_by_slots(nd, count);
@@ -260,20 +321,34 @@ __device__ void prune_core(const uint64_t* keys, int m, const RowSource& rs, int
   __syncthreads();
 }
 
-__device__ __forceinline__ PruneLds carve_prune_lds(unsigned char* p, int cap) {
+// LDS of the prune for lists of up to cap candidates, at the start of the
+// kernel's LDS: positions, slots, counts, histogram, displacement; its size is
+// a multiple of 16 bytes so that what follows stays aligned.
+__host__ __device__ inline int prune_table_slots(int cap) {
+  int S = 64;
+  while (S < 4 * cap) S <<= 1;
+  return S;
+}
+__host__ __device__ inline int prune_scratch_bytes_of(int cap) {
+  const int S = prune_table_slots(cap);
+  return ((S + kProbeMax) * 6 + cap * 4 + (cap + 1) * 4 + 4 + 15) / 16 * 16;
+}
+__device__ __forceinline__ PruneLds carve_prune_lds(unsigned char* smem, int cap) {
   PruneLds s;
-  s.S = pow2_at_least(4 * cap, 64);
-  s.mkey = reinterpret_cast<uint32_t*>(p);
-  s.mval = reinterpret_cast<uint16_t*>(s.mkey + s.S + kProbeMax);
-  s.cnt = reinterpret_cast<uint32_t*>(s.mkey + s.S + kProbeMax) + (s.S + kProbeMax) / 2;
+  s.S = prune_table_slots(cap);
+  s.mval = reinterpret_cast<uint16_t*>(smem);
+  s.mkey = reinterpret_cast<uint32_t*>(smem + 2 * (s.S + kProbeMax));
+  s.cnt = s.mkey + s.S + kProbeMax;
   s.hist = s.cnt + cap;
   s.dmax = s.hist + cap + 1;
   return s;
 }
-size_t prune_scratch_bytes(int cap) {
-  int S = 64;
-  while (S < 4 * cap) S <<= 1;
-  return (size_t)(S + kProbeMax) * 6 + (size_t)cap * 4 + (size_t)(cap + 1) * 4 + 16;
+size_t prune_scratch_bytes(int cap) { return (size_t)prune_scratch_bytes_of(cap); }
+// LDS in front of the reverse-edge pool: the prune table, or while the pool is
+// merged, the merge buffers (cap + one wave of keys).
+__host__ __device__ inline int reverse_table_bytes(int cap) {
+  const int t = prune_scratch_bytes_of(cap), mb = (cap + kWave) * 8;
+  return t > mb ? t : (mb + 15) / 16 * 16;
 }
 
 // Number of non-padding keys in a sorted LDS list of n keys.
@@ -449,8 +524,8 @@ __global__ __launch_bounds__(64) void prune_lists_kernel(PruneArgs a) {
   if (a.skip && a.skip[li] < 0) return;
   const int lane = lane_id();
   const int cap = a.cap < a.cstride ? a.cap : a.cstride;
-  uint64_t* keys = reinterpret_cast<uint64_t*>(smem);
-  PruneLds s = carve_prune_lds(reinterpret_cast<unsigned char*>(keys + cap), cap);
+  PruneLds s = carve_prune_lds(smem, cap);
+  uint64_t* keys = reinterpret_cast<uint64_t*>(smem + prune_scratch_bytes_of(cap));
   const uint64_t* src = a.cand + (int64_t)li * a.cstride;
   for (int i = lane; i < cap; i += kWave) keys[i] = src[i];
   __syncthreads();
@@ -576,12 +651,15 @@ __device__ void reverse_prune_one(ReverseArgs a, int k, unsigned char* smem) {
   const int cap = a.cap;
   WaveCtx w;
   w.ktrack = 0;
-  w.pool = reinterpret_cast<uint64_t*>(smem);
-  w.next = w.pool + cap;
+  // The merge buffers (next, kept) share the prune table's LDS: the table is
+  // built only once the pool is complete, and the pool is then moved back to
+  // its own region if the last merge left it in the shared one.
+  uint64_t* pool = reinterpret_cast<uint64_t*>(smem + reverse_table_bytes(cap));
+  w.pool = pool;
+  w.next = reinterpret_cast<uint64_t*>(smem);
   w.kept = w.next + cap;
   w.L = cap;
-  PruneLds s = carve_prune_lds(reinterpret_cast<unsigned char*>(w.kept + kWave), cap);
-  for (int i = lane; i < 2 * cap; i += kWave) w.pool[i] = kKeyInf;
+  for (int i = lane; i < cap; i += kWave) { w.pool[i] = kKeyInf; w.next[i] = kKeyInf; }
   __syncthreads();
   const int32_t t = a.tlist[k];
   const int lo = a.off[k], hi = a.off[k + 1];
@@ -633,13 +711,18 @@ __device__ void reverse_prune_one(ReverseArgs a, int k, unsigned char* smem) {
     uint64_t key = i < hi ? a.inc[i] : kKeyInf;
     sort_merge(w, key);
   }
-  const int m = count_keys(w.pool, cap);
+  if (w.pool != pool) {
+    for (int i = lane; i < cap; i += kWave) pool[i] = w.pool[i];
+    __syncthreads();
+  }
+  const int m = count_keys(pool, cap);
+  PruneLds s = carve_prune_lds(smem, cap);
   RowSource rs{a.graph, a.fwd_ids, a.rows_below ? a.rows_below : a.n0, a.R};
-  prune_core(w.pool, m, rs, a.R, s, a.trow + (int64_t)k * a.R, a.trow_d + (int64_t)k * a.R);
+  prune_core(pool, m, rs, a.R, s, a.trow + (int64_t)k * a.R, a.trow_d + (int64_t)k * a.R);
 }
 hipError_t launch_reverse_prune(const ReverseArgs& a, int n_targets, hipStream_t st) {
   if (n_targets <= 0) return hipSuccess;
-  const size_t lds = (size_t)(2 * a.cap + kWave) * 8 + prune_scratch_bytes(a.cap);
+  const size_t lds = (size_t)reverse_table_bytes(a.cap) + (size_t)a.cap * 8;
   const int blocks = (int)std::min<int64_t>(n_targets, kMaxBlocks);
   hipLaunchKernelGGL(reverse_prune_kernel, dim3(blocks), dim3(kWave), lds, st, a, n_targets);
   return hipGetLastError();
