@@ -373,10 +373,10 @@ int co_search(svf_index* ix, const svf::SearchArgs& a, const float* d_q, int64_t
   int rc;
   int32_t* ints;
   float* missd;
-  if ((rc = scratch(T.co_pool, (size_t)nq * Lp, &c.pool)) ||
-      (rc = scratch(T.co_newk, (size_t)nq * C, &c.newk)) ||
-      (rc = scratch(T.co_ints, (size_t)nq * (4 + 2 * (size_t)C) + 2, &ints)) ||
-      (rc = scratch(T.co_missd, (size_t)nq * C, &missd)))
+  if ((rc = scratch_grow(T.co_pool, (size_t)nq * Lp, &c.pool)) ||
+      (rc = scratch_grow(T.co_newk, (size_t)nq * C, &c.newk)) ||
+      (rc = scratch_grow(T.co_ints, (size_t)nq * (4 + 2 * (size_t)C) + 2, &ints)) ||
+      (rc = scratch_grow(T.co_missd, (size_t)nq * C, &missd)))
     return rc;
   c.state = ints;
   c.iters = ints + nq;

@@ -95,9 +95,9 @@ int long_layout(svf::LongScratch& s, const int32_t* len, int n, const int32_t* d
   uint32_t *hash, *cnt;
   int32_t* m;
   int rc;
-  if ((rc = scratch(s.meta, meta.size(), &dmeta)) || (rc = scratch(s.keys, (size_t)off[n], &keys)) ||
-      (rc = scratch(s.hash, (size_t)hoff[n], &hash)) || (rc = scratch(s.cnt, (size_t)c, &cnt)) ||
-      (rc = scratch(s.m, (size_t)n, &m)))
+  if ((rc = scratch_grow(s.meta, meta.size(), &dmeta)) || (rc = scratch_grow(s.keys, (size_t)off[n], &keys)) ||
+      (rc = scratch_grow(s.hash, (size_t)hoff[n], &hash)) || (rc = scratch_grow(s.cnt, (size_t)c, &cnt)) ||
+      (rc = scratch_grow(s.m, (size_t)n, &m)))
     return rc;
   CK(hipMemcpyAsync(dmeta, meta.data(), meta.size() * 8, hipMemcpyHostToDevice, st));
   CK(hipStreamSynchronize(st));       // the host copy of the layout goes out of scope
@@ -145,7 +145,7 @@ int reverse_prune_all(svf_index* ix, svf::ReverseArgs& ra, int n_targets, hipStr
   svf::LongScratch& s = ix->lrev;
   int32_t* q;
   int rc;
-  if ((rc = scratch(s.q, 2 * (size_t)n_targets + 1, &q))) return rc;
+  if ((rc = scratch_grow(s.q, 2 * (size_t)n_targets + 1, &q))) return rc;
   int32_t *qk = q, *qlen = q + n_targets, *nq = q + 2 * n_targets;
   CK(svf::launch_fill_u32(nq, 1, 0u, st));
   svf::ReverseArgs rq = ra;
@@ -623,11 +623,12 @@ int insert_prepare(svf_index* ix, const float* d_vecs, int64_t b, PendingInsert*
   int32_t n_targets = 0;
   CK(hipMemcpyAsync(&n_targets, cnt, 4, hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
-  if ((rc = scratch(ix->s_misc[4], n_targets + 1, &ra.off)) ||
-      (rc = scratch(ix->s_misc[5], (size_t)n_targets + 2 + n_targets / 1024 + 2, &ra.cursor)) ||
+  const size_t nt = (size_t)n_targets;
+  if ((rc = scratch_grow(ix->s_misc[4], nt + 1, &ra.off)) ||
+      (rc = scratch_grow(ix->s_misc[5], nt + 2 + nt / 1024 + 2, &ra.cursor)) ||
       (rc = scratch(ix->s_misc[6], npairs, &ra.inc)) ||
-      (rc = scratch(ix->s_misc[7], (size_t)n_targets * R, &ra.trow)) ||
-      (rc = scratch(ix->s_misc[8], (size_t)n_targets * R, &ra.trow_d)))
+      (rc = scratch_grow(ix->s_misc[7], nt * R, &ra.trow)) ||
+      (rc = scratch_grow(ix->s_misc[8], nt * R, &ra.trow_d)))
     return rc;
   CK(svf::launch_reverse_scan_scatter(ra, n_targets, st));
   if ((rc = reverse_prune_all(ix, ra, n_targets, st))) return rc;
@@ -745,7 +746,7 @@ int repair_compute(const RepairJob& j, int consolidate, svf::RepairScratch& s, h
   int32_t *list, *cnt;
   int rc;
   *n_aff_out = 0;
-  if ((rc = scratch(s.list, std::max<int64_t>(j.n_slots, 1), &list)) || (rc = scratch(s.cnt, 8, &cnt)))
+  if ((rc = scratch_grow(s.list, std::max<int64_t>(j.n_slots, 1), &list)) || (rc = scratch_grow(s.cnt, 8, &cnt)))
     return rc;
   svf::RepairArgs a{};
   a.vec32 = j.vec32;
@@ -774,11 +775,11 @@ int repair_compute(const RepairJob& j, int consolidate, svf::RepairScratch& s, h
   float* rows_d;
   uint64_t* cand;
   const int64_t chunk = std::min<int64_t>(n_aff, 131072);
-  if ((rc = scratch(s.rows, (size_t)n_aff * R, &rows)) ||
-      (rc = scratch(s.rows_d, (size_t)n_aff * R, &rows_d)) ||
-      (rc = scratch(s.cand, (size_t)chunk * cap, &cand)) ||
-      (rc = scratch(s.mcount, chunk, &mcount)) || (rc = scratch(s.topup, chunk, &topup)) ||
-      (rc = scratch(s.topup_v, chunk, &topup_v)) || (rc = scratch(s.lg.q, 2 * (size_t)chunk, &over)))
+  if ((rc = scratch_grow(s.rows, (size_t)n_aff * R, &rows)) ||
+      (rc = scratch_grow(s.rows_d, (size_t)n_aff * R, &rows_d)) ||
+      (rc = scratch_grow(s.cand, (size_t)chunk * cap, &cand)) ||
+      (rc = scratch_grow(s.mcount, chunk, &mcount)) || (rc = scratch_grow(s.topup, chunk, &topup)) ||
+      (rc = scratch_grow(s.topup_v, chunk, &topup_v)) || (rc = scratch_grow(s.lg.q, 2 * (size_t)chunk, &over)))
     return rc;
   a.cand = cand;
   a.mcount = mcount;
@@ -828,7 +829,7 @@ int repair_compute(const RepairJob& j, int consolidate, svf::RepairScratch& s, h
     }
     if (ntop > 0) {
       uint64_t *qkey, *pool;
-      if ((rc = scratch(s.qkey, ntop, &qkey)) || (rc = scratch(s.pool, (size_t)ntop * j.Lins, &pool)))
+      if ((rc = scratch_grow(s.qkey, ntop, &qkey)) || (rc = scratch_grow(s.pool, (size_t)ntop * j.Lins, &pool)))
         return rc;
       svf::SearchArgs q = j.proto;
       q.queries = j.vec32;
@@ -837,7 +838,7 @@ int repair_compute(const RepairJob& j, int consolidate, svf::RepairScratch& s, h
       if (j.hsegs.seg) {
         // tiered: the vertices' own rows are staged in HBM first
         float* qrows;
-        if ((rc = scratch(s.qrows, (size_t)ntop * j.stride, &qrows))) return rc;
+        if ((rc = scratch_grow(s.qrows, (size_t)ntop * j.stride, &qrows))) return rc;
         CK(svf::launch_gather_rows(j.hsegs, topup_v, ntop, j.stride, qrows, st));
         q.queries = qrows;
         q.qids = nullptr;
@@ -1009,7 +1010,7 @@ int bg_merge(svf_index* ix) {
     const int64_t words = (ix->n_slots + 31) / 32;
     uint32_t* mask;
     int32_t* cnt;
-    if ((rc = scratch(B.mask, words, &mask)) || (rc = scratch(ix->s_misc[2], 8, &cnt))) return rc;
+    if ((rc = scratch_grow(B.mask, words, &mask)) || (rc = scratch_grow(ix->s_misc[2], 8, &cnt))) return rc;
     CK(svf::launch_fill_u32(mask, words, 0u, st));
     CK(svf::launch_mark_list(B.rs.list.as<int32_t>(), n_aff, mask, st));
     svf::ReverseArgs ra{};
@@ -1034,11 +1035,12 @@ int bg_merge(svf_index* ix) {
     int32_t n_targets = 0;
     CK(hipMemcpyAsync(&n_targets, cnt, 4, hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
-    if ((rc = scratch(ix->s_misc[4], n_targets + 1, &ra.off)) ||
-        (rc = scratch(ix->s_misc[5], (size_t)n_targets + 2 + n_targets / 1024 + 2, &ra.cursor)) ||
+    const size_t nt = (size_t)n_targets;
+    if ((rc = scratch_grow(ix->s_misc[4], nt + 1, &ra.off)) ||
+        (rc = scratch_grow(ix->s_misc[5], nt + 2 + nt / 1024 + 2, &ra.cursor)) ||
         (rc = scratch(ix->s_misc[6], npairs, &ra.inc)) ||
-        (rc = scratch(ix->s_misc[7], (size_t)n_targets * R, &ra.trow)) ||
-        (rc = scratch(ix->s_misc[8], (size_t)n_targets * R, &ra.trow_d)))
+        (rc = scratch_grow(ix->s_misc[7], nt * R, &ra.trow)) ||
+        (rc = scratch_grow(ix->s_misc[8], nt * R, &ra.trow_d)))
       return rc;
     CK(svf::launch_reverse_scan_scatter(ra, n_targets, st));
     if ((rc = reverse_prune_all(ix, ra, n_targets, st))) return rc;
@@ -1163,9 +1165,21 @@ int check_search_args(const svf_index* ix, int64_t nq, int k, int beam) {
   return SVF_OK;
 }
 
+// A float is finite unless its exponent bits are all ones (inf or NaN).  The
+// test runs over blocks of 4096 values with a branch-free OR of the exponent
+// tests, which the compiler vectorizes, and stops at the first bad block.
 bool all_finite(const float* p, int64_t n) {
-  for (int64_t i = 0; i < n; ++i)
-    if (!std::isfinite(p[i])) return false;
+  constexpr int64_t kBlock = 4096;
+  for (int64_t i0 = 0; i0 < n; i0 += kBlock) {
+    const int64_t i1 = i0 + kBlock < n ? i0 + kBlock : n;
+    uint32_t bad = 0;
+    for (int64_t i = i0; i < i1; ++i) {
+      uint32_t u;
+      std::memcpy(&u, p + i, 4);
+      bad |= (uint32_t)((u & 0x7f800000u) == 0x7f800000u);
+    }
+    if (bad) return false;
+  }
   return true;
 }
 
@@ -1188,7 +1202,7 @@ int delete_ids(svf_index* ix, const int32_t* ids, int64_t n) {
   hipStream_t st = ix->stream;
   int32_t *d, *cnt;
   int rc;
-  if ((rc = scratch(ix->s_misc[9], n, &d)) || (rc = scratch(ix->s_tot, 2, &cnt))) return rc;
+  if ((rc = scratch_grow(ix->s_misc[9], n, &d)) || (rc = scratch_grow(ix->s_tot, 2, &cnt))) return rc;
   CK(hipEventRecord(ix->ev0, st));
   CK(hipMemcpyAsync(d, ids, n * 4, hipMemcpyHostToDevice, st));
   CK(svf::launch_fill_u32(cnt, 1, 0u, st));
@@ -1479,8 +1493,8 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
   uint32_t* touched_d;
   const int64_t nb = svf::touched_blocks(words);
   int rc;
-  if ((rc = scratch(T.acc_cnt, n, &cnt_d)) || (rc = scratch(T.touched, words, &touched_d)) ||
-      (lru && (rc = scratch(T.lastpos, n, &lastpos_d))) || (rc = scratch(T.blk, 2 * nb + 2, &blk_d)))
+  if ((rc = scratch_grow(T.acc_cnt, n, &cnt_d)) || (rc = scratch_grow(T.touched, words, &touched_d)) ||
+      (lru && (rc = scratch_grow(T.lastpos, n, &lastpos_d))) || (rc = scratch_grow(T.blk, 2 * nb + 2, &blk_d)))
     return rc;
   CK(T.blk_h.ensure((nb + 1) * 8));
   CK(T.alive_h.ensure((words + 1) * 4));
@@ -1505,8 +1519,8 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
     total += btot[b];
   }
   int32_t *lid, *lcnt, *llast = nullptr;
-  if ((rc = scratch(T.lst_id, total + 1, &lid)) || (rc = scratch(T.lst_cnt, total + 1, &lcnt)) ||
-      (lru && (rc = scratch(T.lst_last, total + 1, &llast))))
+  if ((rc = scratch_grow(T.lst_id, total + 1, &lid)) || (rc = scratch_grow(T.lst_cnt, total + 1, &lcnt)) ||
+      (lru && (rc = scratch_grow(T.lst_last, total + 1, &llast))))
     return rc;
   CK(T.lst_id_h.ensure((total + 1) * 4));
   CK(T.lst_cnt_h.ensure((total + 1) * 4));
@@ -2027,7 +2041,7 @@ int svf_insert(svf_index* ix, const float* vecs, int64_t n, int32_t* out_ids) {
   if (!all_finite(vecs, n * ix->dim)) return fail(SVF_E_INVAL, "non-finite vector value");
   std::lock_guard<std::mutex> g(ix->mu);
   float* d;
-  int rc = scratch(ix->s_q, (size_t)n * ix->dim, &d);
+  int rc = scratch_grow(ix->s_q, (size_t)n * ix->dim, &d);
   if (rc) return rc;
   CK(hipMemcpyAsync(d, vecs, (size_t)n * ix->dim * 4, hipMemcpyHostToDevice, ix->stream));
   return insert_stream(ix, d, n, nullptr, out_ids);
@@ -2043,7 +2057,7 @@ int svf_build(svf_index* ix, const float* vecs, int64_t n) {
   int rc = reserve(ix, n);
   if (rc) return rc;
   float* d;
-  if ((rc = scratch(ix->s_q, (size_t)n * ix->dim, &d))) return rc;
+  if ((rc = scratch_grow(ix->s_q, (size_t)n * ix->dim, &d))) return rc;
   CK(hipMemcpyAsync(d, vecs, (size_t)n * ix->dim * 4, hipMemcpyHostToDevice, ix->stream));
   ix->tier.building = true;
   rc = insert_stream(ix, d, n, nullptr, nullptr);
@@ -2105,8 +2119,8 @@ int svf_search(svf_index* ix, const float* queries, int64_t nq, int32_t k, int32
   hipStream_t st = ix->stream;
   float *dq, *dd;
   int32_t* di;
-  if ((rc = scratch(ix->s_q, (size_t)nq * ix->dim, &dq)) || (rc = scratch(ix->s_ids, (size_t)nq * k, &di)) ||
-      (rc = scratch(ix->s_d, (size_t)nq * k, &dd)))
+  if ((rc = scratch_grow(ix->s_q, (size_t)nq * ix->dim, &dq)) || (rc = scratch_grow(ix->s_ids, (size_t)nq * k, &di)) ||
+      (rc = scratch_grow(ix->s_d, (size_t)nq * k, &dd)))
     return rc;
   CK(hipMemcpyAsync(dq, queries, (size_t)nq * ix->dim * 4, hipMemcpyHostToDevice, st));
   rc = search_impl(ix, dq, nq, k, beam, di, dd, nullptr, nullptr, st);
@@ -2133,10 +2147,10 @@ int svf_search_listed(svf_index* ix, const float* queries, int64_t nq, int32_t k
   float *dq, *dd;
   int32_t *di, *de, *dqe, *dqm;
   uint64_t* qkey;
-  if ((rc = scratch(ix->s_q, (size_t)nq * ix->dim, &dq)) || (rc = scratch(ix->s_ids, (size_t)nq * k, &di)) ||
-      (rc = scratch(ix->s_d, (size_t)nq * k, &dd)) || (rc = scratch(ix->s_misc[0], (size_t)nq * ecap, &de)) ||
-      (rc = scratch(ix->s_misc[1], nq, &dqe)) || (rc = scratch(ix->s_misc[2], nq, &dqm)) ||
-      (rc = scratch(ix->s_qkey, nq, &qkey)))
+  if ((rc = scratch_grow(ix->s_q, (size_t)nq * ix->dim, &dq)) || (rc = scratch_grow(ix->s_ids, (size_t)nq * k, &di)) ||
+      (rc = scratch_grow(ix->s_d, (size_t)nq * k, &dd)) || (rc = scratch_grow(ix->s_misc[0], (size_t)nq * ecap, &de)) ||
+      (rc = scratch_grow(ix->s_misc[1], nq, &dqe)) || (rc = scratch_grow(ix->s_misc[2], nq, &dqm)) ||
+      (rc = scratch_grow(ix->s_qkey, nq, &qkey)))
     return rc;
   std::vector<int32_t> qe(nq), qm(nq, 0);
   for (int64_t i = 0; i < nq; ++i) {
@@ -2186,9 +2200,9 @@ int svf_search_trace(svf_index* ix, const float* queries, int64_t nq, int32_t k,
   float *dq, *dd;
   int32_t *di, *dl;
   uint64_t* qkey;
-  if ((rc = scratch(ix->s_q, (size_t)nq * ix->dim, &dq)) || (rc = scratch(ix->s_ids, (size_t)nq * k, &di)) ||
-      (rc = scratch(ix->s_d, (size_t)nq * k, &dd)) || (rc = scratch(ix->s_misc[1], nq, &dl)) ||
-      (rc = scratch(ix->s_qkey, nq, &qkey)))
+  if ((rc = scratch_grow(ix->s_q, (size_t)nq * ix->dim, &dq)) || (rc = scratch_grow(ix->s_ids, (size_t)nq * k, &di)) ||
+      (rc = scratch_grow(ix->s_d, (size_t)nq * k, &dd)) || (rc = scratch_grow(ix->s_misc[1], nq, &dl)) ||
+      (rc = scratch_grow(ix->s_qkey, nq, &qkey)))
     return rc;
   CK(hipMemcpyAsync(dq, queries, (size_t)nq * ix->dim * 4, hipMemcpyHostToDevice, st));
   if (ix->n_slots == 0) {
@@ -2520,7 +2534,7 @@ int svf_import_graph(svf_index* ix, const float* vecs, int64_t n, const int32_t*
   if (rc) return rc;
   hipStream_t st = ix->stream;
   float* d;
-  if ((rc = scratch(ix->s_q, (size_t)std::max<int64_t>(n, 1) * ix->dim, &d))) return rc;
+  if ((rc = scratch_grow(ix->s_q, (size_t)std::max<int64_t>(n, 1) * ix->dim, &d))) return rc;
   CK(hipMemcpyAsync(d, vecs, n * ix->dim * 4, hipMemcpyHostToDevice, st));
   rc = store_rows(ix, d, n, 0, st);
   if (rc) return rc;

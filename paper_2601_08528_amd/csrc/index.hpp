@@ -27,11 +27,13 @@ struct DevBuf {
     p = nullptr;
     bytes = 0;
   }
-  // Make at least `need` bytes available; old contents are not kept.
-  hipError_t ensure(size_t need) {
+  // Make at least `need` bytes available; old contents are not kept.  A
+  // reallocation takes `grow` bytes when that is more (room for later growth).
+  hipError_t ensure(size_t need, size_t grow = 0) {
     if (need <= bytes && p) return hipSuccess;
     release();
     size_t b = need < 256 ? 256 : need;
+    if (grow > b) b = grow;
     hipError_t e = hipMalloc(&p, b);
     if (e != hipSuccess) { p = nullptr; return e; }
     bytes = b;

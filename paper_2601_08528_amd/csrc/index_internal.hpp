@@ -26,6 +26,17 @@ int scratch(svf::DevBuf& b, size_t count, T** out) {
   *out = b.as<T>();
   return SVF_OK;
 }
+// The same for buffers sized by counts that vary from call to call: a
+// reallocation leaves an eighth more room, so that slowly growing counts do
+// not reallocate (and synchronize the device) on every call.
+template <class T>
+int scratch_grow(svf::DevBuf& b, size_t count, T** out) {
+  const size_t need = count * sizeof(T) + 16;
+  hipError_t e = b.ensure(need, need + need / 8);
+  if (e != hipSuccess) return hip_fail(e, "scratch allocation");
+  *out = b.as<T>();
+  return SVF_OK;
+}
 
 struct PendingInsert {
   bool seed = false;
