@@ -1559,10 +1559,20 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
   std::vector<std::vector<std::pair<double, int32_t>>> tcand(nthr);
   std::vector<std::vector<int32_t>> tmissed(nthr);
   std::vector<int64_t> thits(nthr, 0), tacc(nthr, 0);
+  const int32_t* indeg_h = T.e_in.as<int32_t>();
   auto work = [&](int t) {
     const int64_t lo = total * t / nthr, hi = total * (t + 1) / nthr;
     int64_t h = 0, a = 0;
     for (int64_t i = lo; i < hi; ++i) {
+      if (i + 32 < hi) {               // the touched ids are sparse: request ahead
+        const int32_t xa = tid[i + 32];
+        __builtin_prefetch(&T.fr[xa]);
+        __builtin_prefetch(&T.fr_stamp[xa]);
+        __builtin_prefetch(&T.freq[xa]);
+        __builtin_prefetch(&T.where[xa]);
+        __builtin_prefetch(&bits[xa >> 5]);
+        __builtin_prefetch(&indeg_h[xa]);
+      }
       const int32_t x = tid[i];
       double v = fr_now(T, x);
       const int32_t c = tcnt[i];
@@ -1625,15 +1635,36 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
     T.prev_acc = acc;
     T.prev_mean = mean;
   }
-  for (int t = 0; t < nthr; ++t)
-    for (const auto& c : tcand[t])
-      if (c.first > T.theta) cand.push_back(c);
   auto better = [](const std::pair<double, int32_t>& a, const std::pair<double, int32_t>& b) {
     return a.first > b.first || (a.first == b.first && a.second < b.second);
   };
-  if ((int64_t)cand.size() > T.promote_max) {
-    std::nth_element(cand.begin(), cand.begin() + T.promote_max, cand.end(), better);
-    cand.resize(T.promote_max);
+  // The placements are the promote_max best candidates above theta in the
+  // (F_lambda desc, id asc) order, a strict order: each thread keeps the best
+  // promote_max of its own range, and the best of those are the best of all.
+  const double theta = T.theta;
+  const int64_t pmax = T.promote_max;
+  auto keep_best = [&](int t) {
+    auto& v = tcand[t];
+    v.erase(std::remove_if(v.begin(), v.end(),
+                           [&](const std::pair<double, int32_t>& c) { return !(c.first > theta); }),
+            v.end());
+    if ((int64_t)v.size() > pmax) {
+      std::nth_element(v.begin(), v.begin() + pmax, v.end(), better);
+      v.resize(pmax);
+    }
+  };
+  if (nthr == 1) {
+    keep_best(0);
+  } else {
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nthr; ++t) pool.emplace_back(keep_best, t);
+    keep_best(0);
+    for (auto& th : pool) th.join();
+  }
+  for (int t = 0; t < nthr; ++t) cand.insert(cand.end(), tcand[t].begin(), tcand[t].end());
+  if ((int64_t)cand.size() > pmax) {
+    std::nth_element(cand.begin(), cand.begin() + pmax, cand.end(), better);
+    cand.resize(pmax);
   }
   std::sort(cand.begin(), cand.end(), better);
   ix->st.place_walk_ms = ms_since(tp);
@@ -1653,9 +1684,16 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
     if (T.C == 0) break;
     if (!sw.active()) {     // the cache is full and stays full for the rest of the batch
       const int nt = (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()));
+      const int32_t* indeg = T.e_in.as<int32_t>();
       sw.begin(T.C, [&](int64_t s_) {
         const int32_t y = T.slot_id[s_];
         return alive(y) ? T.alpha * fr_now(T, y) + lg(y) : -1.0;
+      }, [&](int64_t s_) {
+        const int32_t y = T.slot_id[s_];
+        __builtin_prefetch(&bits[y >> 5]);
+        __builtin_prefetch(&T.fr[y]);
+        __builtin_prefetch(&T.fr_stamp[y]);
+        __builtin_prefetch(&indeg[y]);
       }, T.ref.data(), nt);
     }
     const int64_t s_ = sw.evict(T.clock, T.ref.data());

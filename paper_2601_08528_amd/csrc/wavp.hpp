@@ -28,9 +28,11 @@ class WavpSweep {
  public:
   // Score all C slots: f_of(s) gives F_lambda of slot s's vector (every slot
   // is occupied), ref[s] its reference bit.  Runs on up to `threads` host
-  // threads.
-  template <class F>
-  void begin(int64_t C, F f_of, const uint8_t* ref, int threads) {
+  // threads.  prefetch(s) is called kAhead slots before f_of(s), to request
+  // the per-vector data f_of(s) will read (scattered over all vectors, it
+  // would otherwise be one cache miss after another).
+  template <class F, class P>
+  void begin(int64_t C, F f_of, P prefetch, const uint8_t* ref, int threads) {
     C_ = C;
     nb_ = (C + 63) / 64;
     f_.resize(C);
@@ -45,7 +47,9 @@ class WavpSweep {
         uint64_t m = 0;
         double mn = kInf;
         const int64_t s1 = std::min(C, (b + 1) * 64);
+        const int64_t pf_end = std::min(C, b1 * 64);
         for (int64_t s = b * 64; s < s1; ++s) {
+          if (s + kAhead < pf_end) prefetch(s + kAhead);
           const double v = f_of(s);
           f_[s] = v;
           if (ref[s]) m |= 1ull << (s - b * 64);
@@ -109,6 +113,7 @@ class WavpSweep {
 
  private:
   static constexpr double kInf = std::numeric_limits<double>::infinity();
+  static constexpr int64_t kAhead = 32;
   int64_t C_ = 0, nb_ = 0, nw_ = 0, P_ = 1;
   bool active_ = false;
   std::vector<double> f_, bmin_, tree_;
