@@ -316,8 +316,7 @@ int reserve(svf_index* ix, int64_t need) {
     CK(svf::launch_fill_u32(tmap, cap, 0xffffffffu, st));
     if (n > 0 && ix->tier.map) CK(hipMemcpyAsync(tmap, ix->tier.map, n * 4, hipMemcpyDeviceToDevice, st));
     ix->tier.where.resize(cap, -1);
-    ix->tier.fr.resize(cap, 0.0);
-    ix->tier.fr_stamp.resize(cap, 0);
+    ix->tier.fr.resize(cap);
     ix->tier.freq.resize(cap, 0);
     ix->tier.last.resize(cap, -1);
   } else {
@@ -1394,7 +1393,7 @@ double halve_times(double v, int64_t k) {
   return v;
 }
 double fr_now(const svf::TierState& T, int32_t x) {
-  return halve_times(T.fr[x], T.batch - T.fr_stamp[x]);
+  return halve_times(T.fr[x].v, T.batch - T.fr[x].stamp);
 }
 
 // The classic replacement policies (LRU, LFU, LRFU) in the batched form: the
@@ -1567,7 +1566,6 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
       if (i + 32 < hi) {               // the touched ids are sparse: request ahead
         const int32_t xa = tid[i + 32];
         __builtin_prefetch(&T.fr[xa]);
-        __builtin_prefetch(&T.fr_stamp[xa]);
         __builtin_prefetch(&T.freq[xa]);
         __builtin_prefetch(&T.where[xa]);
         __builtin_prefetch(&bits[xa >> 5]);
@@ -1578,8 +1576,8 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
       const int32_t c = tcnt[i];
       for (int32_t k = 0; k < c; ++k) v += 1.0;
       a += c;
-      T.fr[x] = v;
-      T.fr_stamp[x] = T.batch;
+      T.fr[x].v = v;
+      T.fr[x].stamp = T.batch;
       T.freq[x] += c;
       if (lru) T.last[x] = ((T.batch - 1) << 40) + tlast[i];
       if (T.where[x] >= 0) {
@@ -1692,7 +1690,6 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
         const int32_t y = T.slot_id[s_];
         __builtin_prefetch(&bits[y >> 5]);
         __builtin_prefetch(&T.fr[y]);
-        __builtin_prefetch(&T.fr_stamp[y]);
         __builtin_prefetch(&indeg[y]);
       }, T.ref.data(), nt);
     }
@@ -1802,8 +1799,7 @@ int tier_enable(svf_index* ix, double bytes) {
   ix->vec32 = nullptr;
   T.map = map;
   T.where.assign(ix->cap, -1);
-  T.fr.assign(ix->cap, 0.0);
-  T.fr_stamp.assign(ix->cap, 0);
+  T.fr.assign(ix->cap, svf::TierState::FRec{});
   T.freq.assign(ix->cap, 0);
   T.last.assign(ix->cap, -1);
   T.on = true;

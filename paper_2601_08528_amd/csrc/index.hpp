@@ -147,8 +147,13 @@ struct TierState {
   std::vector<int32_t> free_slots; // slots below `used` released by deletions (a stack)
   std::vector<int32_t> where;      // id -> slot (host mirror of map)
   std::vector<uint8_t> ref;        // reference bits per slot
-  std::vector<double> fr;          // F_recent per id, as of batch fr_stamp[id]
-  std::vector<int64_t> fr_stamp;   // (the halvings of later batches are applied on use)
+  // F_recent per id as of batch `stamp` (the halvings of later batches are
+  // applied on use); the two share a 16-byte record, one cache line fetch.
+  struct FRec {
+    double v = 0.0;
+    int64_t stamp = 0;
+  };
+  std::vector<FRec> fr;
   PinnedBuf e_in;                  // host copy: int32 in-degree per id, e_in_n of them
   int64_t e_in_n = 0;
   bool e_in_valid = false;         // e_in_d (cap entries) is kept current under updates
