@@ -39,6 +39,19 @@ def test_long_reverse_lists_bit_exact(dim, metric):
     assert g.stats()["long_lists"] > 0
 
 
+def test_long_reverse_lists_whole_rows_bit_exact():
+    """Degree 48, whose prunes read whole rows per step: one insert batch of
+    2,700 vectors into 300 gives every old vertex hundreds of reverse-edge
+    candidates, beyond the one-wave list of 128."""
+    base, _ = datagen.gmm_uint8_valued(803, 3000, 1, 64, 6)
+    oix = oracle_index(base[:300], 48, seed=6, batch_max=100)
+    oix.set("insert_batch_max", 2700)
+    g = gpu_from_oracle(oix, base[:300], seed=6, insert_batch_max=2700)
+    assert g.insert(base[300:]).tolist() == oix.insert(base[300:]).tolist()
+    same_graph(g, oix)
+    assert g.stats()["long_lists"] > 0
+
+
 @pytest.mark.parametrize("dim,metric", [(64, O.L2), (200, O.IP)])
 def test_long_repair_and_consolidation_lists_bit_exact(dim, metric):
     """Degree 16: local repair with c = 8 offers up to 16 + 8 * 16 keys and

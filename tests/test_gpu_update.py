@@ -21,8 +21,11 @@ def assert_same_graph(g, oix, check_dist=True):
         np.testing.assert_array_equal(ge.astype(np.float64), oe)
 
 
-@pytest.mark.parametrize("dim,R,metric,n", [(128, 16, O.L2, 3000), (72, 24, O.IP, 2000)])
+@pytest.mark.parametrize("dim,R,metric,n", [(128, 16, O.L2, 3000), (72, 24, O.IP, 2000),
+                                            (64, 48, O.L2, 2500), (48, 64, O.IP, 2000)])
 def test_build_bit_exact_integer(dim, R, metric, n):
+    """Degrees up to 32 take the prune's lane-per-entry row walk; degrees 33-64
+    read whole rows per step (48: lanes past the row re-read its last entry)."""
     base, _ = datagen.gmm_uint8_valued(301, n, 1, dim, 12)
     oix = oracle_index(base, R, metric=metric, seed=7, batch_max=400)
     g = svf.Index(dim, R, metric, seed=7, insert_batch_max=400)
@@ -60,6 +63,35 @@ def test_insert_and_delete_sequence_bit_exact():
     for v in np.nonzero(ga)[0]:
         r = gr[v][gr[v] >= 0]
         assert ga[r].all() and v not in r and len(set(r.tolist())) == len(r)
+
+
+def test_insert_delete_sequence_whole_row_prune_bit_exact():
+    """Degree 40, so every prune (forward rows, reverse edges, repair and
+    consolidation lists) reads whole rows per step with lanes 40..63 idle:
+    inserts, deletions with local repair, then consolidation, the graph equal
+    to the oracle's after each step."""
+    base, q = datagen.gmm_uint8_valued(305, 3300, 30, 48, 10)
+    R = 40
+    oix = oracle_index(base[:2400], R, seed=13, batch_max=300)
+    g = gpu_from_oracle(oix, base[:2400], seed=13, insert_batch_max=300)
+    rng = np.random.Generator(np.random.Philox(14))
+    pos = 2400
+    for step in range(3):
+        new = base[pos:pos + 300]
+        pos += 300
+        assert g.insert(new).tolist() == oix.insert(new).tolist()
+        assert_same_graph(g, oix)
+        _, _, alive = oix.export()
+        victims = rng.choice(np.nonzero(alive)[0], 150, replace=False).astype(np.int32)
+        g.delete(victims)
+        assert oix.delete(victims) == 0
+        assert_same_graph(g, oix)
+    g.consolidate()
+    oix.consolidate()
+    assert_same_graph(g, oix)
+    oi, od, _ = oix.search(q, 10, 64)
+    gi, gd = g.search(q, 10, 64)
+    np.testing.assert_array_equal(gi, oi)
 
 
 def test_repair_topup_path_bit_exact():
