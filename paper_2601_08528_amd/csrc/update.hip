@@ -178,7 +178,7 @@ __device__ void prune_core(const uint64_t* keys, int m, const RowSource& rs, int
       // read out lane by lane into a buffer resource per row, so each load is
       // a scalar base plus the lane's byte offset.  Every load is issued, with
       // no branch: lanes past the row re-read its last entry and rows past m
-      // re-read row 0; the first do not probe and the second count nothing.
+      // re-read row 0; neither is probed.
       // The rows of the next pass are requested before the entries of this
       // one are probed (after the last pass, 8 reads of row 0 that are never
       // used), so that the probes run while those reads are in flight.  Row
@@ -216,9 +216,9 @@ __device__ void prune_core(const uint64_t* keys, int m, const RowSource& rs, int
 #pragma unroll
           for (int u = 0; u < kRowSteps; ++u) {
             constexpr int N = decltype(nslots)::value;
+            if (j0 + u >= m) break;          // rows past the list (last pass only)
             const uint32_t h = prune_hash((uint32_t)e[u], sbits);
-            // a row past m counts nothing (its threshold exceeds any position)
-            const int jt = j0 + u < m ? j0 + u : 0x7fffffff;
+            const int jt = j0 + u;
             if constexpr (N > 0) {
               const int off = tab_off<N>(s, h, e[u]);
               if (off >= 0) {
