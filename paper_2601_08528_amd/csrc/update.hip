@@ -665,16 +665,17 @@ __device__ void reverse_prune_one(ReverseArgs a, int k, unsigned char* smem) {
   const int lo = a.off[k], hi = a.off[k + 1];
   int na = 0;
   bool placed = false;
+  uint64_t key = kKeyInf;       // lane r: alive entry r of the row (R <= 64)
+  uint64_t ab = 0;              // lanes holding one
   if (a.R <= kWave) {
     // Rows are stored in (d, id) order, so the alive entries fill the empty
     // pool as they stand; a row out of order is merged key by key instead.
-    uint64_t key = kKeyInf;
     if (lane < a.R) {
       const int32_t u = a.graph[(int64_t)t * a.R + lane];
       const float d = a.edge_d[(int64_t)t * a.R + lane];
       if (u >= 0 && alive_bit(a.alive, u)) key = make_key(d, u);
     }
-    const uint64_t ab = ballot(key != kKeyInf);
+    ab = ballot(key != kKeyInf);
     na = popc64(ab);
     if (key != kKeyInf) w.pool[lanes_below(ab)] = key;
     __syncthreads();
@@ -706,7 +707,38 @@ __device__ void reverse_prune_one(ReverseArgs a, int k, unsigned char* smem) {
     }
     return;
   }
-  for (int c0 = lo; c0 < hi; c0 += kWave) {
+  // With the row in place and at most one wave of incoming keys that all fit,
+  // every key's final position is its rank: an alive entry moves up by the
+  // incoming keys below it, an incoming key lands after the alive entries and
+  // the incoming keys below it.  Equal keys (never produced by one batch) take
+  // the merge below, which drops repeats.
+  const int c = hi - lo;
+  bool merged = false;
+  if (placed && c <= kWave && na + c <= cap) {
+    const uint64_t q = lane < c ? a.inc[lo + lane] : kKeyInf;
+    const bool has_a = key != kKeyInf, has_q = lane < c;
+    const uint64_t ko = key_ord(key), qo = key_ord(q);
+    const uint32_t q_lo = (uint32_t)q, q_hi = (uint32_t)(q >> 32);
+    int up = 0, qpos = 0;
+    bool tie = false;
+    for (int j = 0; j < c; ++j) {
+      const uint64_t qj = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(q_hi, j) << 32) |
+                          (uint32_t)__builtin_amdgcn_readlane(q_lo, j);
+      const uint64_t qjo = key_ord(qj);
+      if (has_a && qjo < ko) ++up;
+      const int pa = popc64(ballot(has_a && ko < qjo));
+      const int pq = popc64(ballot(has_q && qo < qjo));
+      tie = tie || ballot((has_a && ko == qjo) || (has_q && lane != j && qo == qjo)) != 0;
+      if (lane == j) qpos = pa + pq;
+    }
+    if (!tie) {
+      if (has_a) pool[lanes_below(ab) + up] = key;
+      if (has_q) pool[qpos] = q;
+      __syncthreads();
+      merged = true;
+    }
+  }
+  for (int c0 = lo; !merged && c0 < hi; c0 += kWave) {
     const int i = c0 + lane;
     uint64_t key = i < hi ? a.inc[i] : kKeyInf;
     sort_merge(w, key);
