@@ -173,16 +173,16 @@ __device__ void prune_core(const uint64_t* keys, int m, const RowSource& rs, int
     // detour counts: entry r of row(c_j) naming c_i with i > j.  The counts
     // are sums, so the order in which entries are probed does not matter.
     if (R > 32 && R <= kWave) {
-      // One whole row per step: lane r reads entry r of row j.  The byte
-      // addresses of a pass's 8 rows are computed once, one row per lane, and
-      // read out lane by lane into a buffer resource per row, so each load is
-      // a scalar base plus the lane's byte offset.  Every load is issued, with
-      // no branch: lanes past the row re-read its last entry and rows past m
-      // re-read row 0; neither is probed.
-      // The rows of the next pass are requested before the entries of this
-      // one are probed (after the last pass, 8 reads of row 0 that are never
-      // used), so that the probes run while those reads are in flight.  Row
-      // addresses are computed 64 rows at a time, lane l holding row g + l.
+      // One whole row per step, 8 rows per pass: lane r reads entry r of row
+      // j.  Row addresses are computed 64 rows at a time (lane l holds the
+      // byte address of row g + l) and read out lane by lane into a buffer
+      // resource per row, so each load is a scalar base plus the lane's byte
+      // offset.  Every load is issued, with no branch: lanes past the row
+      // re-read its last entry and rows past m re-read row 0; neither is
+      // probed.  The rows of the next pass are requested before the entries
+      // of this one are probed (after the last pass, 8 reads of row 0 that
+      // are never used), so that the probes run while those reads are in
+      // flight.
       constexpr int kRowSteps = 8;
       const bool lane_on = lane < R;
       const uint32_t lbyte = 4u * (uint32_t)(lane_on ? lane : R - 1);
