@@ -721,7 +721,11 @@ def full_tier_bench(torch, svf, datagen, n_base, cache_gb=None, steps=8, sample=
         rows.append({"step": r, "insert_100k_ms": round((tb - ta) * 1e3, 1),
                      "search_kernel_ms": round(kms, 3), "search_call_ms": round((td - tc) * 1e3, 2),
                      "gather_hit_rate": round(h / max(h + m, 1), 4),
-                     "host_link_gbs": round(m * dim * 4 / (kms / 1e3) / 1e9, 1)})
+                     "host_link_gbs": round(m * dim * 4 / (kms / 1e3) / 1e9, 1),
+                     # the placement's phases on the host (count waits for the kernel)
+                     **{k: round(s1[k], 2) for k in ("place_count_ms", "place_indeg_ms",
+                                                     "place_walk_ms", "place_evict_ms",
+                                                     "place_apply_ms")}})
         log("full tier: step", rows[-1])
     st = rows[steps // 2:]
     kms = float(np.mean([x["search_kernel_ms"] for x in st]))

@@ -1268,9 +1268,7 @@ int tier_admit(svf_index* ix, int64_t id0, int64_t n) {
   for (int64_t x = id0; x < id0 + n; ++x) {
     const int64_t slot = T.take_slot();
     if (slot < 0) break;
-    T.slot_id[slot] = (int32_t)x;
-    T.where[x] = (int32_t)slot;
-    T.ref[slot] = 0;
+    T.occupy(slot, (int32_t)x);
     place.insert(place.end(), {(int32_t)slot, (int32_t)x, -1});
   }
   T.promotions += place.size() / 3;
@@ -1438,9 +1436,7 @@ int place_classic(svf_index* ix, std::vector<int32_t>& order, Key key, hipStream
     const int32_t x = c.second;
     const int64_t slot = T.take_slot();
     if (slot >= 0) {
-      T.slot_id[slot] = x;
-      T.where[x] = (int32_t)slot;
-      T.ref[slot] = 0;
+      T.occupy(slot, x);
       place.insert(place.end(), {(int32_t)slot, x, -1});
       if (evicting) {
         heap.push_back(c);
@@ -1454,9 +1450,7 @@ int place_classic(svf_index* ix, std::vector<int32_t>& order, Key key, hipStream
     heap.pop_back();
     const int32_t s_ = T.where[y];
     T.where[y] = -1;
-    T.slot_id[s_] = x;
-    T.where[x] = s_;
-    T.ref[s_] = 0;
+    T.occupy(s_, x);
     place.insert(place.end(), {s_, x, y});
     ++T.evictions;
     heap.push_back(c);
@@ -1583,6 +1577,7 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
       if (T.where[x] >= 0) {
         h += c;
         T.ref[T.where[x]] = 1;
+        T.sfr[T.where[x]] = T.fr[x];
       } else if (alive(x)) {
         if (T.policy == 0) tcand[t].emplace_back(T.alpha * v + lg(x), x);
         else tmissed[t].push_back(x);
@@ -1673,9 +1668,7 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
     const int32_t x = c.second;
     const int64_t slot = T.take_slot();
     if (slot >= 0) {
-      T.slot_id[slot] = x;
-      T.where[x] = (int32_t)slot;
-      T.ref[slot] = 0;
+      T.occupy(slot, x);
       place.insert(place.end(), {(int32_t)slot, x, -1});
       continue;
     }
@@ -1685,19 +1678,18 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
       const int32_t* indeg = T.e_in.as<int32_t>();
       sw.begin(T.C, [&](int64_t s_) {
         const int32_t y = T.slot_id[s_];
-        return alive(y) ? T.alpha * fr_now(T, y) + lg(y) : -1.0;
+        const svf::TierState::FRec& f = T.sfr[s_];   // equals T.fr[y]
+        return alive(y) ? T.alpha * halve_times(f.v, T.batch - f.stamp) + lg(y) : -1.0;
       }, [&](int64_t s_) {
         const int32_t y = T.slot_id[s_];
         __builtin_prefetch(&bits[y >> 5]);
-        __builtin_prefetch(&T.fr[y]);
         __builtin_prefetch(&indeg[y]);
       }, T.ref.data(), nt);
     }
     const int64_t s_ = sw.evict(T.clock, T.ref.data());
     const int32_t y = T.slot_id[s_];
     T.where[y] = -1;
-    T.slot_id[s_] = x;
-    T.where[x] = (int32_t)s_;
+    T.occupy(s_, x);                        // the victim's bit was clear
     sw.place(s_, c.first);
     place.insert(place.end(), {(int32_t)s_, x, y});
     ++T.evictions;
@@ -1736,9 +1728,7 @@ int tier_warmup(svf_index* ix, hipStream_t st) {
     const int32_t x = order[i];
     if (T.where[x] >= 0) continue;
     const int64_t slot = T.take_slot();
-    T.slot_id[slot] = x;
-    T.where[x] = (int32_t)slot;
-    T.ref[slot] = 0;
+    T.occupy(slot, x);
     place.insert(place.end(), {(int32_t)slot, x, -1});
   }
   T.promotions += place.size() / 3;
@@ -1754,6 +1744,7 @@ int tier_enable(svf_index* ix, double bytes) {
   CK(hipMalloc(&T.cache, C * ix->stride * 4));
   T.C = C;
   T.slot_id.assign(C, -1);
+  T.sfr.assign(C, svf::TierState::FRec{});
   T.ref.assign(C, 0);
   T.free_slots.clear();
   T.e_in_valid = false;

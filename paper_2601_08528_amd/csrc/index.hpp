@@ -154,6 +154,11 @@ struct TierState {
     int64_t stamp = 0;
   };
   std::vector<FRec> fr;
+  // Per slot, a copy of fr of the slot's vector, kept in step with it (every
+  // slot assignment goes through occupy(), and the per-batch update of a
+  // cached vector writes both), so that the victim sweep reads it in slot
+  // order instead of one scattered record per slot.
+  std::vector<FRec> sfr;
   PinnedBuf e_in;                  // host copy: int32 in-degree per id, e_in_n of them
   int64_t e_in_n = 0;
   bool e_in_valid = false;         // e_in_d (cap entries) is kept current under updates
@@ -182,6 +187,13 @@ struct TierState {
   DevBuf e_in_chk;                         // recount for cache_indegree_verify
   PinnedBuf blk_h, lst_id_h, lst_cnt_h, lst_last_h, alive_h;
   // A free slot (released ones first, then the untouched tail), -1 when full.
+  // Slot `slot` now holds vector x, with a clear reference bit.
+  void occupy(int64_t slot, int32_t x) {
+    slot_id[slot] = x;
+    where[x] = (int32_t)slot;
+    ref[slot] = 0;
+    sfr[slot] = fr[x];
+  }
   int64_t take_slot() {
     if (!free_slots.empty()) {
       const int64_t s = free_slots.back();
