@@ -1306,6 +1306,13 @@ int tier_refresh_indegree(svf_index* ix, hipStream_t st) {
     T.e_in_valid = true;
   }
   CK(hipMemcpyAsync(T.e_in.p, d, ix->n_slots * 4, hipMemcpyDeviceToHost, st));
+  if (T.C > 0 && T.sdeg) {                  // the slots' in-degrees, in slot order
+    int32_t* sd;
+    if ((rc = scratch(T.sdeg_d, (size_t)T.C, &sd))) return rc;
+    CK(svf::launch_fill_u32(reinterpret_cast<uint32_t*>(sd), T.C, 0u, st));
+    CK(svf::launch_slot_indegree(T.map, d, ix->n_slots, sd, st));
+    CK(hipMemcpyAsync(T.sdeg, sd, T.C * 4, hipMemcpyDeviceToHost, st));
+  }
   if (!recount && T.verify_indegree) {
     int32_t* chk;
     if ((rc = scratch(T.e_in_chk, cap, &chk))) return rc;
@@ -1675,15 +1682,14 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
     if (T.C == 0) break;
     if (!sw.active()) {     // the cache is full and stays full for the rest of the batch
       const int nt = (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()));
-      const int32_t* indeg = T.e_in.as<int32_t>();
       sw.begin(T.C, [&](int64_t s_) {
         const int32_t y = T.slot_id[s_];
-        const svf::TierState::FRec& f = T.sfr[s_];   // equals T.fr[y]
-        return alive(y) ? T.alpha * halve_times(f.v, T.batch - f.stamp) + lg(y) : -1.0;
+        const svf::TierState::FRec& f = T.sfr[s_];   // sfr, sdeg: T.fr[y], in_degree(y)
+        return alive(y) ? T.alpha * halve_times(f.v, T.batch - f.stamp) +
+                              T.beta * T.log1p_deg(T.sdeg[s_])
+                        : -1.0;
       }, [&](int64_t s_) {
-        const int32_t y = T.slot_id[s_];
-        __builtin_prefetch(&bits[y >> 5]);
-        __builtin_prefetch(&indeg[y]);
+        __builtin_prefetch(&bits[T.slot_id[s_] >> 5]);
       }, T.ref.data(), nt);
     }
     const int64_t s_ = sw.evict(T.clock, T.ref.data());
@@ -1745,6 +1751,14 @@ int tier_enable(svf_index* ix, double bytes) {
   T.C = C;
   T.slot_id.assign(C, -1);
   T.sfr.assign(C, svf::TierState::FRec{});
+  if (T.sdeg_h.ensure(C * 4) == hipSuccess) {
+    T.sdeg = T.sdeg_h.as<int32_t>();
+  } else {                                  // past the host's pinning limit
+    (void)hipGetLastError();
+    T.sdeg_v.assign(C, 0);
+    T.sdeg = T.sdeg_v.data();
+  }
+  std::fill(T.sdeg, T.sdeg + C, 0);
   T.ref.assign(C, 0);
   T.free_slots.clear();
   T.e_in_valid = false;

@@ -159,6 +159,13 @@ struct TierState {
   // cached vector writes both), so that the victim sweep reads it in slot
   // order instead of one scattered record per slot.
   std::vector<FRec> sfr;
+  // Per slot, the in-degree of the slot's vector, likewise for the sweep:
+  // rewritten from the device whenever the host copy of the in-degrees is,
+  // and by occupy() in between.  Pinned when the host allows (sdeg_h), else
+  // in ordinary memory (sdeg_v); sdeg points at the one in use.
+  PinnedBuf sdeg_h;
+  std::vector<int32_t> sdeg_v;
+  int32_t* sdeg = nullptr;
   PinnedBuf e_in;                  // host copy: int32 in-degree per id, e_in_n of them
   int64_t e_in_n = 0;
   bool e_in_valid = false;         // e_in_d (cap entries) is kept current under updates
@@ -182,7 +189,7 @@ struct TierState {
   // round keys, miss lists, and the rounds run so far
   DevBuf co_pool, co_newk, co_ints, co_missd;
   int64_t co_rounds = 0;
-  DevBuf trace, trace_n, place, counts, e_in_d, acc_cnt, touched, lastpos;
+  DevBuf trace, trace_n, place, counts, e_in_d, acc_cnt, touched, lastpos, sdeg_d;
   DevBuf blk, lst_id, lst_cnt, lst_last;   // the batch's touched vertices, in id order
   DevBuf e_in_chk;                         // recount for cache_indegree_verify
   PinnedBuf blk_h, lst_id_h, lst_cnt_h, lst_last_h, alive_h;
@@ -193,6 +200,7 @@ struct TierState {
     where[x] = (int32_t)slot;
     ref[slot] = 0;
     sfr[slot] = fr[x];
+    sdeg[slot] = x < e_in_n ? in_degree(x) : 0;   // refreshed with the in-degrees
   }
   int64_t take_slot() {
     if (!free_slots.empty()) {

@@ -82,6 +82,9 @@ hipError_t launch_indegree(const int32_t* graph, const uint32_t* alive, int64_t 
                            int32_t* e_in, hipStream_t st);
 hipError_t launch_place(const int32_t* place, int np, HostSegs store, float* cache,
                         int64_t stride, int32_t* map, hipStream_t st);
+// sdeg[map[i]] = e_in[i] for every id i < n that holds a slot
+hipError_t launch_slot_indegree(const int32_t* map, const int32_t* e_in, int64_t n, int32_t* sdeg,
+                                hipStream_t st);
 int64_t touched_blocks(int64_t words);
 // rows: an HBM array (hs.seg null) or the host segments
 hipError_t launch_probe_gather(const float* rows, HostSegs hs, const int32_t* idx, int n,

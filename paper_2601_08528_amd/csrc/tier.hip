@@ -59,6 +59,25 @@ hipError_t launch_place(const int32_t* place, int np, HostSegs store, float* cac
   return hipGetLastError();
 }
 
+// In-degree of each cache slot's vector, in slot order: every id holding a
+// slot (map[id] >= 0) writes its in-degree at that slot.  Slots no id holds
+// keep what they had.
+__global__ void slot_indegree_kernel(const int32_t* __restrict__ map, const int32_t* __restrict__ e_in,
+                                     int64_t n, int32_t* __restrict__ sdeg) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t s = map[i];
+    if (s >= 0) sdeg[s] = e_in[i];
+  }
+}
+hipError_t launch_slot_indegree(const int32_t* map, const int32_t* e_in, int64_t n, int32_t* sdeg,
+                                hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, kMaxBlocks);
+  hipLaunchKernelGGL(slot_indegree_kernel, dim3((unsigned)blocks), dim3(256), 0, st, map, e_in, n, sdeg);
+  return hipGetLastError();
+}
+
 // Cost probe for the placement threshold (Sec. 4.3): one wave per listed
 // row computes the squared L2 distance between that row and q, as a search
 // gather does; the rows are the HBM cache (a hit, hs.seg null) or the host
