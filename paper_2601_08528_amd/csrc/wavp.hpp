@@ -11,8 +11,9 @@
 // are scored once when the batch first needs a victim: f[s], the reference
 // bits as one 64-bit mask per block of 64 slots, and per block the least f
 // over its clear-bit slots, with a min tree over the blocks and a bitmap of
-// the blocks that hold set bits.  An eviction then costs O(log C) plus the
-// set bits its walk clears, instead of a pass over every slot.
+// the blocks that hold set bits (and over it, a bitmap of its nonzero words).
+// An eviction then costs O(log C) plus the set bits its walk clears, instead
+// of a pass over every slot.
 #pragma once
 #include <stdint.h>
 
@@ -40,6 +41,7 @@ class WavpSweep {
     bmin_.resize(nb_);
     nw_ = (nb_ + 63) / 64;
     busy_.assign(nw_, 0);
+    busy2_.assign((nw_ + 63) / 64, 0);
     const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(threads, nb_ / 512));
     auto work = [&](int t) {
       const int64_t b0 = nb_ * t / nt, b1 = nb_ * (t + 1) / nt;
@@ -69,6 +71,8 @@ class WavpSweep {
     }
     for (int64_t b = 0; b < nb_; ++b)
       if (mask_[b]) busy_[b >> 6] |= 1ull << (b & 63);
+    for (int64_t w = 0; w < nw_; ++w)
+      if (busy_[w]) busy2_[w >> 6] |= 1ull << (w & 63);
     P_ = 1;
     while (P_ < nb_) P_ <<= 1;
     tree_.assign(2 * P_, kInf);
@@ -96,6 +100,7 @@ class WavpSweep {
         tree_[P_ + b] = mn;
       }
       std::fill(busy_.begin(), busy_.end(), 0ull);
+      std::fill(busy2_.begin(), busy2_.end(), 0ull);
       for (int64_t i = P_ - 1; i >= 1; --i) tree_[i] = std::min(tree_[2 * i], tree_[2 * i + 1]);
       fmin = tree_[1];
     }
@@ -117,7 +122,7 @@ class WavpSweep {
   int64_t C_ = 0, nb_ = 0, nw_ = 0, P_ = 1;
   bool active_ = false;
   std::vector<double> f_, bmin_, tree_;
-  std::vector<uint64_t> mask_, busy_;
+  std::vector<uint64_t> mask_, busy_, busy2_;
 
   void set_leaf(int64_t b, double v) {
     bmin_[b] = v;
@@ -172,15 +177,27 @@ class WavpSweep {
       clear_linear(0, to, ref);
     }
   }
+  // First word index >= w0 of busy_ that is nonzero, or nw_.
+  int64_t next_busy_word(int64_t w0) const {
+    int64_t i = w0 >> 6;
+    if (i >= (int64_t)busy2_.size()) return nw_;
+    uint64_t m = busy2_[i] & (~0ull << (w0 & 63));
+    while (m == 0) {
+      if (++i >= (int64_t)busy2_.size()) return nw_;
+      m = busy2_[i];
+    }
+    return i * 64 + __builtin_ctzll(m);
+  }
   void clear_linear(int64_t from, int64_t to, uint8_t* ref) {
     if (from >= to) return;
     const int64_t bl = from >> 6, bh = (to - 1) >> 6;
     int64_t b = bl;
     while (b <= bh) {
-      // skip blocks without set bits, a bitmap word at a time
+      // skip blocks without set bits, a bitmap word at a time, and runs of
+      // empty words through the bitmap over the words
       const uint64_t w = busy_[b >> 6] >> (b & 63);
       if (w == 0) {
-        b = ((b >> 6) + 1) << 6;
+        b = next_busy_word((b >> 6) + 1) << 6;
         continue;
       }
       b += __builtin_ctzll(w);
@@ -198,7 +215,10 @@ class WavpSweep {
           mn = std::min(mn, f_[s]);
         }
         mask_[b] &= ~sel;
-        if (!mask_[b]) busy_[b >> 6] &= ~(1ull << (b & 63));
+        if (!mask_[b]) {
+          busy_[b >> 6] &= ~(1ull << (b & 63));
+          if (!busy_[b >> 6]) busy2_[b >> 12] &= ~(1ull << ((b >> 6) & 63));
+        }
         set_leaf(b, mn);
       }
       ++b;
