@@ -462,9 +462,29 @@ def large_bench(torch, svf, datagen, n_base, steps, warmup):
     alg = n_dist * dim * 4 + n_exp * R * 4
     ms_step = float(np.mean(ms))
     achieved = alg / (ms_step / 1e3) / 1e9
+    # The same search expanding four parents per iteration: each iteration
+    # then gathers four rows' unvisited neighbours at once, where one parent
+    # leaves about 18 new vectors per iteration to carry its fixed costs.
+    ix.set_option("search_width", 4)
+    rows4, beam4 = [], None
+    for b in BEAMS:
+        run_search(torch, ix, q_t, b, bufs)
+        torch.cuda.synchronize()
+        r = rec_ip()
+        rows4.append({"beam": b, "recall@10": round(r, 5)})
+        if r >= 0.95:
+            beam4 = b
+            break
+    beam4 = beam4 or BEAMS[-1]
+    ms4, _ = timed_steps(torch, ix, q_t, beam4, bufs, steps, warmup)
+    ms4 = float(np.mean(ms4))
+    ix.set_option("search_width", 1)
     del base_t
     return {"workload": "%dM x 96 unit-norm GMM (1024 comps, Zipf(1.1) queries), IP, degree 48, "
                         "10k-query batch, k=10, plain FP32" % (n_base // 1_000_000),
+            "width4": {"beam": beam4, "recall@10": rows4[-1]["recall@10"], "sweep": rows4,
+                       "ms_per_step": round(ms4, 4), "qps": round(nq / (ms4 / 1e3), 1),
+                       "speedup_vs_width1": round(ms_step / ms4, 3)},
             "vector_bytes": n_base * dim * 4, "build_s": round(build_s, 2),
             "beam": beam, "recall@10": rows[-1]["recall@10"], "sweep": rows,
             "ms_per_step": round(ms_step, 4), "qps": round(nq / (ms_step / 1e3), 1),
