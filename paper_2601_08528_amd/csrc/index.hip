@@ -1243,6 +1243,7 @@ int delete_ids(svf_index* ix, const int32_t* ids, int64_t n) {
 // reading it).
 int tier_release(svf_index* ix, const int32_t* ids, int64_t n) {
   svf::TierState& T = ix->tier;
+  if (T.on && ix->server && n > 0) T.dead_residents = true;   // kept until evicted
   if (!T.on || ix->server || n == 0) return SVF_OK;
   std::vector<int32_t> place;
   for (int64_t i = 0; i < n; ++i) {
@@ -1682,14 +1683,18 @@ int tier_after_batch(svf_index* ix, int64_t nq, hipStream_t st) {
     if (T.C == 0) break;
     if (!sw.active()) {     // the cache is full and stays full for the rest of the batch
       const int nt = (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()));
+      // A deletion releases the vertex's slot at once, except while serving,
+      // where deleted residents stay until evicted: until then every
+      // resident is alive and the scattered alive bits need not be read.
+      const bool check_alive = T.dead_residents;
       sw.begin(T.C, [&](int64_t s_) {
         const int32_t y = T.slot_id[s_];
         const svf::TierState::FRec& f = T.sfr[s_];   // sfr, sdeg: T.fr[y], in_degree(y)
-        return alive(y) ? T.alpha * halve_times(f.v, T.batch - f.stamp) +
-                              T.beta * T.log1p_deg(T.sdeg[s_])
-                        : -1.0;
+        return !check_alive || alive(y) ? T.alpha * halve_times(f.v, T.batch - f.stamp) +
+                                              T.beta * T.log1p_deg(T.sdeg[s_])
+                                        : -1.0;
       }, [&](int64_t s_) {
-        __builtin_prefetch(&bits[T.slot_id[s_] >> 5]);
+        if (check_alive) __builtin_prefetch(&bits[T.slot_id[s_] >> 5]);
       }, T.ref.data(), nt);
     }
     const int64_t s_ = sw.evict(T.clock, T.ref.data());
@@ -1751,6 +1756,7 @@ int tier_enable(svf_index* ix, double bytes) {
   T.C = C;
   T.slot_id.assign(C, -1);
   T.sfr.assign(C, svf::TierState::FRec{});
+  T.dead_residents = false;
   if (T.sdeg_h.ensure(C * 4) == hipSuccess) {
     T.sdeg = T.sdeg_h.as<int32_t>();
   } else {                                  // past the host's pinning limit

@@ -159,6 +159,7 @@ struct TierState {
   // cached vector writes both), so that the victim sweep reads it in slot
   // order instead of one scattered record per slot.
   std::vector<FRec> sfr;
+  bool dead_residents = false;     // a deleted vector may hold a slot (deleted while serving)
   // Per slot, the in-degree of the slot's vector, likewise for the sweep:
   // rewritten from the device whenever the host copy of the in-degrees is,
   // and by occupy() in between.  Pinned when the host allows (sdeg_h), else
