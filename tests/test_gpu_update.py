@@ -22,10 +22,13 @@ def assert_same_graph(g, oix, check_dist=True):
 
 
 @pytest.mark.parametrize("dim,R,metric,n", [(128, 16, O.L2, 3000), (72, 24, O.IP, 2000),
-                                            (64, 48, O.L2, 2500), (48, 64, O.IP, 2000)])
+                                            (64, 48, O.L2, 2500), (48, 64, O.IP, 2000),
+                                            (32, 80, O.L2, 1500)])
 def test_build_bit_exact_integer(dim, R, metric, n):
     """Degrees up to 32 take the prune's lane-per-entry row walk; degrees 33-64
-    read whole rows per step (48: lanes past the row re-read its last entry)."""
+    read whole rows per step (48: lanes past the row re-read its last entry);
+    degree 80 walks entries again, and its rows, wider than a wave, are
+    merged into the reverse-edge pool key by key."""
     base, _ = datagen.gmm_uint8_valued(301, n, 1, dim, 12)
     oix = oracle_index(base, R, metric=metric, seed=7, batch_max=400)
     g = svf.Index(dim, R, metric, seed=7, insert_batch_max=400)
