@@ -147,7 +147,9 @@ __device__ void prune_core(const uint64_t* keys, int m, const RowSource& rs, int
   int tau = 0, need = 0;
   const bool full = m > R;
   if (full) {
-    for (int i = lane; i < s.S; i += kWave) s.mkey[i] = kFree;
+    // S is a power of two >= 64 and the slots start 16-byte aligned
+    for (int i = 4 * lane; i < s.S; i += 4 * kWave)
+      *reinterpret_cast<uint4*>(s.mkey + i) = make_uint4(kFree, kFree, kFree, kFree);
     for (int i = lane; i <= m; i += kWave) { s.hist[i] = 0; if (i < m) s.cnt[i] = 0; }
     if (lane == 0) *s.dmax = 0;
     __syncthreads();
@@ -747,7 +749,7 @@ __device__ void reverse_prune_one(ReverseArgs a, int k, unsigned char* smem) {
     for (int i = lane; i < cap; i += kWave) pool[i] = w.pool[i];
     __syncthreads();
   }
-  const int m = count_keys(pool, cap);
+  const int m = merged ? na + c : count_keys(pool, cap);
   PruneLds s = carve_prune_lds(smem, cap);
   RowSource rs{a.graph, a.fwd_ids, a.rows_below ? a.rows_below : a.n0, a.R};
   prune_core(pool, m, rs, a.R, s, a.trow + (int64_t)k * a.R, a.trow_d + (int64_t)k * a.R);
